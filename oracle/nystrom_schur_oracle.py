@@ -1,0 +1,503 @@
+"""FP64 CPU oracle: DBBD split, Schur operator, block PCG, Nystrom, M_2, PCG.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Every routine is the
+plain definition or the paper's algorithm step by step, in float64, with
+NumPy / SciPy dense and sparse primitives as the only building blocks.  There
+is no blocking, fusion or reordering beyond what the definitions state.
+
+Readings taken where the paper is silent (each is repeated in the design
+notes of the repository):
+
+* inner solve: block PCG on the shifted system S_Gamma D = W Omega with
+  W = A_GammaI A_I^{-1} A_IGamma, preconditioned by A_Gamma^{-1}; then
+  Y = A_Gamma D.  By eq. (S-1) this Y equals A_GammaI S_I^{-1} A_IGamma Omega,
+  the product of Algorithm alg:prec1 steps 2-4 (``inner='formA'`` runs
+  those steps literally).
+* block stopping rule: max over columns of ||R_j|| / ||F_j|| <= eps_SI.
+* breakdown-free orthonormalisation: thin SVD, keep sigma_i > delta*sigma_max.
+* Nystrom threshold: eigenvalues of sym(Omega^T Y) >= eps_rel * max eigenvalue.
+* Algorithm alg:prec1 step 10 reads U = Q W(:, 1:k) (Q from the QR of Y, as in
+  Algorithm alg:nystrom); eigenvalues of T sorted descending; k' = min(k, r).
+* outer PCG: recurrence residual ||r_j|| / ||f|| <= tol, w_0 = 0 for M_2 and
+  w_0 = Z E^{-1} Z^T f for the adapted-deflation form.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, Optional
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+# ----------------------------------------------------------------------------
+# doubly bordered block diagonal split  (eq. perm_A)
+
+
+class DBBD:
+    """Index sets and blocks of P^T A P = [[A_I, A_IG], [A_GI, A_G]] (eq. perm_A).
+
+    Interior nodes (part >= 0) are ordered by (subdomain, original index);
+    interface nodes (part < 0) by original index.  A_I must be block diagonal
+    (no coupling between distinct subdomains) and A symmetric.
+    """
+
+    def __init__(self, n, row_ptr, col, val, part):
+        A = sp.csr_matrix((np.asarray(val, dtype=np.float64), np.asarray(col), np.asarray(row_ptr)), shape=(n, n))
+        part = np.asarray(part).astype(np.int64)
+        if part.shape != (n,):
+            raise ValueError("part must have length n")
+        asym = A - A.T
+        if asym.nnz and np.max(np.abs(asym.data)) != 0.0:
+            raise ValueError("A is not symmetric")
+        interior = np.nonzero(part >= 0)[0]
+        order = np.lexsort((interior, part[interior]))
+        self.I = interior[order]
+        self.G = np.nonzero(part < 0)[0]
+        coo = A.tocoo()
+        pi, pj = part[coo.row], part[coo.col]
+        cross = (pi >= 0) & (pj >= 0) & (pi != pj) & (coo.data != 0)
+        if np.any(cross):
+            raise ValueError("A couples interior nodes of different subdomains: not DBBD")
+        self.A = A.tocsr()
+        self.part = part
+        nsub = int(part.max()) + 1 if interior.size else 0
+        counts = np.bincount(part[interior], minlength=nsub) if nsub else np.zeros(0, dtype=np.int64)
+        self.block_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        AI = self.A[self.I]
+        AG = self.A[self.G]
+        self.A_I = AI[:, self.I].tocsr()
+        self.A_IG = AI[:, self.G].tocsr()
+        self.A_GI = AG[:, self.I].tocsr()
+        self.A_G = AG[:, self.G].tocsr()
+
+    @property
+    def n(self):
+        return self.A.shape[0]
+
+    @property
+    def n_gamma(self):
+        return self.G.size
+
+    @property
+    def n_sub(self):
+        return self.block_ptr.size - 1
+
+    def block(self, j):
+        a, b = self.block_ptr[j], self.block_ptr[j + 1]
+        return self.A_I[a:b, a:b]
+
+
+# ----------------------------------------------------------------------------
+# exact solves with A_I (block diagonal) and A_Gamma
+
+
+class Operators:
+    """A_I^{-1}, A_Gamma^{-1}, the Schur operator S_Gamma and W.
+
+    A_I^{-1}: one Cholesky factor per diagonal block (the blocks are factorised
+    independently, "cheaply in parallel" in the paper's words).  A_Gamma^{-1}:
+    exact, assumed available by eq. (S1).  ``factor='dense'`` uses LAPACK
+    Cholesky on dense blocks; ``'sparse'`` uses SuperLU (same result up to
+    rounding, for sizes where dense copies do not fit in host memory).
+    """
+
+    def __init__(self, dbbd: DBBD, factor: str = "dense", gamma_factor: Optional[str] = None):
+        self.d = dbbd
+        self.factor = factor
+        self._blk = []
+        for j in range(dbbd.n_sub):
+            Aj = dbbd.block(j)
+            if factor == "dense":
+                L = sla.cholesky(Aj.toarray(), lower=True)
+                self._blk.append(("dense", L))
+            else:
+                self._blk.append(("sparse", spla.splu(Aj.tocsc())))
+        gf = gamma_factor or ("dense" if dbbd.n_gamma <= 6000 else "sparse")
+        if dbbd.n_gamma == 0:
+            self._g = ("none", None)
+        elif gf == "dense":
+            self._g = ("dense", sla.cholesky(dbbd.A_G.toarray(), lower=True))
+        else:
+            self._g = ("sparse", spla.splu(dbbd.A_G.tocsc()))
+
+    def block_factor(self, j):
+        kind, F = self._blk[j]
+        if kind != "dense":
+            raise ValueError("dense factor not available")
+        return F
+
+    def solve_I(self, X):
+        """A_I^{-1} X, block by block."""
+        X = np.asarray(X, dtype=np.float64)
+        out = np.empty_like(X)
+        bp = self.d.block_ptr
+        for j, (kind, F) in enumerate(self._blk):
+            a, b = bp[j], bp[j + 1]
+            if kind == "dense":
+                out[a:b] = sla.cho_solve((F, True), X[a:b])
+            else:
+                out[a:b] = F.solve(np.ascontiguousarray(X[a:b]))
+        return out
+
+    def solve_G(self, X):
+        """A_Gamma^{-1} X (the first-level preconditioner of eq. S1)."""
+        X = np.asarray(X, dtype=np.float64)
+        kind, F = self._g
+        if kind == "none":
+            return X.copy()
+        if kind == "dense":
+            return sla.cho_solve((F, True), X)
+        return F.solve(np.ascontiguousarray(X))
+
+    def S(self, X):
+        """S_Gamma X = A_Gamma X - A_GammaI A_I^{-1} A_IGamma X  (eq. schur_complement)."""
+        d = self.d
+        return d.A_G @ X - d.A_GI @ self.solve_I(d.A_IG @ X)
+
+    def W(self, X):
+        """W X = A_GammaI A_I^{-1} A_IGamma X = (A_Gamma - S_Gamma) X."""
+        d = self.d
+        return d.A_GI @ self.solve_I(d.A_IG @ X)
+
+    def S_I(self, X):
+        """S_I X = A_I X - A_IGamma A_Gamma^{-1} A_GammaI X  (eq. SI)."""
+        d = self.d
+        return d.A_I @ X - d.A_IG @ self.solve_G(d.A_GI @ X)
+
+
+# ----------------------------------------------------------------------------
+# breakdown-free block PCG  (block CG of O'Leary with the rank-revealing
+# orthonormalisation of Ji & Li, the inner solver of the numerical section)
+
+
+def orth(V, delta):
+    """Orthonormal basis of range(V): thin SVD, keep sigma_i > delta * sigma_1."""
+    V = np.asarray(V, dtype=np.float64)
+    if V.shape[1] == 0:
+        return V.copy()
+    U, s, _ = np.linalg.svd(V, full_matrices=False)
+    if s.size == 0 or not s[0] > 0.0:
+        return V[:, :0].copy()
+    r = int(np.count_nonzero(s > delta * s[0]))
+    return U[:, :r]
+
+
+@dataclasses.dataclass
+class BCGResult:
+    X: np.ndarray
+    iters: int
+    converged: bool
+    relres: float
+    widths: list
+
+
+def _col_relres(R, nF):
+    nr = np.linalg.norm(R, axis=0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel = np.where(nF > 0, nr / np.where(nF > 0, nF, 1.0), 0.0)
+    return float(rel.max()) if rel.size else 0.0
+
+
+def bf_bpcg(Sop: Callable, Mop: Callable, F, tol: float, maxit: int, delta: float = 1e-8) -> BCGResult:
+    """Block PCG for S X = F with preconditioner M, from X_0 = 0.
+
+    P_0 = orth(M R_0); per iteration Q = S P, Delta = P^T Q,
+    alpha = Delta^{-1} P^T R, X += P alpha, R -= Q alpha, stop when the largest
+    column relative residual is <= tol, then Z = M R,
+    beta = -Delta^{-1} Q^T Z, P = orth(Z + P beta).
+    """
+    F = np.asarray(F, dtype=np.float64)
+    X = np.zeros_like(F)
+    R = F.copy()
+    nF = np.linalg.norm(F, axis=0)
+    rel = _col_relres(R, nF)
+    widths = []
+    if rel <= tol:
+        return BCGResult(X, 0, True, rel, widths)
+    P = orth(Mop(R), delta)
+    for it in range(1, maxit + 1):
+        widths.append(P.shape[1])
+        if P.shape[1] == 0:
+            return BCGResult(X, it - 1, False, rel, widths)
+        Q = Sop(P)
+        Delta = P.T @ Q
+        Delta = 0.5 * (Delta + Delta.T)
+        cf = sla.cho_factor(Delta, lower=True)
+        alpha = sla.cho_solve(cf, P.T @ R)
+        X += P @ alpha
+        R -= Q @ alpha
+        rel = _col_relres(R, nF)
+        if rel <= tol:
+            return BCGResult(X, it, True, rel, widths)
+        Z = Mop(R)
+        beta = -sla.cho_solve(cf, Q.T @ Z)
+        P = orth(Z + P @ beta, delta)
+    return BCGResult(X, maxit, False, rel, widths)
+
+
+# ----------------------------------------------------------------------------
+# Nystrom core: Algorithm alg:nystrom steps 3-8 / Algorithm alg:prec1 steps 5-10
+
+
+def nystrom_core(Y, Omega, k, eps_rel=1e-10):
+    """Rank-k' Nystrom factors (U, Sigma) of B from Y = B Omega.
+
+    QR of Y; C = Omega^T Y (symmetrised); EVD of C, keep eigenvalues
+    >= eps_rel * max (V_1, D_1, rank r); T = (R V_1) D_1^{-1} (R V_1)^T; EVD of
+    T sorted descending; U = Q W(:, 1:k'), Sigma = E(1:k'), k' = min(k, r).
+    """
+    Y = np.asarray(Y, dtype=np.float64)
+    Q, R = np.linalg.qr(Y)
+    C = Omega.T @ Y
+    C = 0.5 * (C + C.T)
+    d, V = np.linalg.eigh(C)
+    if d.size == 0 or not d.max() > 0.0:
+        return Q[:, :0], np.zeros(0), 0
+    keep = d >= eps_rel * d.max()
+    V1, D1 = V[:, keep], d[keep]
+    r = int(D1.size)
+    RV1 = R @ V1
+    T = (RV1 / D1) @ RV1.T
+    T = 0.5 * (T + T.T)
+    e, Wm = np.linalg.eigh(T)
+    order = np.argsort(-e, kind="stable")
+    kk = min(int(k), r)
+    U = Q @ Wm[:, order[:kk]]
+    return U, e[order[:kk]], r
+
+
+# ----------------------------------------------------------------------------
+# PCG on S_Gamma w = f  (eq. Sx=b)
+
+
+@dataclasses.dataclass
+class PCGResult:
+    w: np.ndarray
+    iters: int
+    converged: bool
+    hist: list
+
+
+def pcg(Sop: Callable, Mop: Callable, f, tol: float, maxit: int, w0=None, callback=None) -> PCGResult:
+    """Preconditioned CG (Hestenes-Stiefel); stops on ||r_j|| / ||f|| <= tol.
+
+    ``iters`` counts applications of S inside the loop; ``callback(w)`` sees
+    every iterate.
+    """
+    f = np.asarray(f, dtype=np.float64)
+    nf = float(np.linalg.norm(f))
+    if w0 is None:
+        w = np.zeros_like(f)
+        r = f.copy()
+    else:
+        w = np.array(w0, dtype=np.float64)
+        r = f - Sop(w)
+    if nf == 0.0:
+        return PCGResult(np.zeros_like(f), 0, True, [0.0])
+    hist = [float(np.linalg.norm(r)) / nf]
+    if hist[0] <= tol:
+        return PCGResult(w, 0, True, hist)
+    z = Mop(r)
+    p = z.copy()
+    rho = float(r @ z)
+    for it in range(1, maxit + 1):
+        q = Sop(p)
+        alpha = rho / float(p @ q)
+        w = w + alpha * p
+        r = r - alpha * q
+        if callback is not None:
+            callback(w)
+        hist.append(float(np.linalg.norm(r)) / nf)
+        if hist[-1] <= tol:
+            return PCGResult(w, it, True, hist)
+        z = Mop(r)
+        rho_new = float(r @ z)
+        beta = rho_new / rho
+        rho = rho_new
+        p = z + beta * p
+    return PCGResult(w, maxit, False, hist)
+
+
+# ----------------------------------------------------------------------------
+# the whole method
+
+
+@dataclasses.dataclass
+class SetupResult:
+    it_inner: int
+    inner_converged: bool
+    k_eff: int
+    rank_C: int
+    U: np.ndarray
+    Sigma: np.ndarray
+    Z: np.ndarray
+    Y: np.ndarray
+
+
+@dataclasses.dataclass
+class SolveResult:
+    x: np.ndarray
+    w: np.ndarray
+    it_pcg: int
+    converged: bool
+    relres_schur: float
+    relres_schur_true: float
+    relres_true: float
+    hist: list
+
+
+class NystromSchurOracle:
+    """Algorithm alg:prec1 plus the block LDL^T solve of eq. A_LDLT.
+
+    ``apply_mode``: 'M2' (eq. left_prec_mat, the preconditioner of the
+    experiments) or 'ADEF2' (adapted deflation built from Z, eqs.
+    adapted_deflation_prec and deflation_comp_from_low_rank).
+    ``inner``: 'shifted' (S_Gamma D = W Omega, preconditioned by A_Gamma^{-1})
+    or 'formA' (S_I X = A_IGamma Omega, preconditioned by A_I^{-1}, the
+    literal step 3).  ``k = 0`` gives the first-level preconditioner S_1.
+    """
+
+    def __init__(self, n, row_ptr, col, val, part, *, k, p, omega, tol_inner=0.1, eps_rel=1e-10, delta=1e-8,
+                 maxit_inner=500, factor="dense", apply_mode="M2", inner="shifted", gamma_factor=None):
+        self.dbbd = DBBD(n, row_ptr, col, val, part)
+        self.ops = Operators(self.dbbd, factor=factor, gamma_factor=gamma_factor)
+        self.k, self.p = int(k), int(p)
+        self.omega = np.asarray(omega, dtype=np.float64) if omega is not None else None
+        self.tol_inner = tol_inner
+        self.eps_rel = eps_rel
+        self.delta = delta
+        self.maxit_inner = maxit_inner
+        self.apply_mode = apply_mode
+        self.inner = inner
+        self.setup_result: Optional[SetupResult] = None
+
+    # -- Algorithm alg:prec1 ------------------------------------------------
+    def setup(self) -> SetupResult:
+        ops, d = self.ops, self.dbbd
+        if self.k == 0:
+            ng = d.n_gamma
+            self.Z = np.zeros((ng, 0))
+            self.Sigma = np.zeros(0)
+            self.setup_result = SetupResult(0, True, 0, 0, np.zeros((ng, 0)), self.Sigma, self.Z, np.zeros((ng, 0)))
+            self._post_setup()
+            return self.setup_result
+        Om = self.omega
+        if self.inner == "shifted":
+            F = ops.W(Om)
+            res = bf_bpcg(ops.S, ops.solve_G, F, self.tol_inner, self.maxit_inner, self.delta)
+            Y = d.A_G @ res.X
+        elif self.inner == "formA":
+            F = d.A_IG @ Om
+            res = bf_bpcg(ops.S_I, ops.solve_I, F, self.tol_inner, self.maxit_inner, self.delta)
+            Y = d.A_GI @ res.X
+        else:
+            raise ValueError(self.inner)
+        U, Sig, r = nystrom_core(Y, Om, self.k, self.eps_rel)
+        self.Z = ops.solve_G(U)
+        self.Sigma = Sig
+        self.setup_result = SetupResult(res.iters, res.converged, U.shape[1], r, U, Sig, self.Z, Y)
+        self._post_setup()
+        return self.setup_result
+
+    def _post_setup(self):
+        if self.apply_mode == "ADEF2" and self.Z.shape[1] > 0:
+            self.SZ = self.ops.S(self.Z)
+            E = self.Z.T @ self.SZ
+            self.E_cf = sla.cho_factor(0.5 * (E + E.T), lower=True)
+
+    # -- preconditioner application (Algorithm alg:prec1 step 12) ------------
+    def apply(self, r):
+        """z = M r for one vector or a block of columns."""
+        ops = self.ops
+        t = ops.solve_G(r)
+        Z = self.Z
+        if Z.shape[1] == 0:
+            return t
+        if self.apply_mode == "M2":
+            c = Z.T @ r
+            c = (self.Sigma * c.T).T if c.ndim == 2 else self.Sigma * c
+            return t + Z @ c
+        # adapted deflation: t + Z E^{-1} (Z^T r - (S Z)^T t)
+        return t + Z @ sla.cho_solve(self.E_cf, Z.T @ r - self.SZ.T @ t)
+
+    def initial_guess(self, f):
+        if self.apply_mode == "ADEF2" and self.Z.shape[1] > 0:
+            return self.Z @ sla.cho_solve(self.E_cf, self.Z.T @ f)
+        return None
+
+    # -- block LDL^T solve of A x = b (eq. A_LDLT, eq. Sx=b) -----------------
+    def reduce_rhs(self, b):
+        """f = b_Gamma - A_GammaI A_I^{-1} b_I."""
+        d = self.dbbd
+        return b[d.G] - d.A_GI @ self.ops.solve_I(b[d.I])
+
+    def solve(self, b, tol=1e-8, maxit=1000) -> SolveResult:
+        if self.setup_result is None:
+            self.setup()
+        d, ops = self.dbbd, self.ops
+        b = np.asarray(b, dtype=np.float64)
+        f = self.reduce_rhs(b)
+        res = pcg(ops.S, self.apply, f, tol, maxit, w0=self.initial_guess(f))
+        w = res.w
+        xI = ops.solve_I(b[d.I] - d.A_IG @ w)
+        x = np.empty(d.n)
+        x[d.I] = xI
+        x[d.G] = w
+        nb = float(np.linalg.norm(b))
+        nf = float(np.linalg.norm(f))
+        rt = float(np.linalg.norm(b - d.A @ x)) / nb if nb > 0 else 0.0
+        rs = float(np.linalg.norm(f - ops.S(w))) / nf if nf > 0 else 0.0
+        return SolveResult(x, w, res.iters, res.converged, res.hist[-1], rs, rt, res.hist)
+
+
+# ----------------------------------------------------------------------------
+# dense references for tiny inputs
+
+
+def dense_schur(d: DBBD):
+    """Explicit S_Gamma = A_Gamma - A_GammaI A_I^{-1} A_IGamma (dense)."""
+    AI = d.A_I.toarray()
+    return d.A_G.toarray() - d.A_GI.toarray() @ np.linalg.solve(AI, d.A_IG.toarray())
+
+
+def ideal_s2(d: DBBD, k: int):
+    """Ideal second-level preconditioner of eq. S2 from the exact GEVP S z = lambda A_Gamma z.
+
+    Returns (apply, lam) with apply(r) = A_Gamma^{-1} r + Z_k (Lambda_k^{-1} - I) Z_k^T r,
+    Z_k the A_Gamma-orthonormal eigenvectors of the k smallest eigenvalues.
+    """
+    S = dense_schur(d)
+    AG = d.A_G.toarray()
+    lam, Zf = sla.eigh(S, AG)
+    Zk, lk = Zf[:, :k], lam[:k]
+    cf = sla.cho_factor(AG, lower=True)
+
+    def apply(r):
+        c = Zk.T @ r
+        c = ((1.0 / lk - 1.0) * c.T).T if c.ndim == 2 else (1.0 / lk - 1.0) * c
+        return sla.cho_solve(cf, r) + Zk @ c
+
+    return apply, lam
+
+
+def full_system_pcg(orc: NystromSchurOracle, b, tol=1e-8, maxit=1000) -> PCGResult:
+    """PCG on A x = b (DBBD order) with the block LDL^T preconditioner built
+    from S~^{-1} = the oracle's apply (the approximate block factorisation
+    M^{-1} of the Schur-complement section; spectrum Lambda(S~^{-1} S) u {1})."""
+    d, ops = orc.dbbd, orc.ops
+    nI = d.I.size
+    Aperm = d.A[np.concatenate([d.I, d.G])][:, np.concatenate([d.I, d.G])].tocsr()
+
+    def Minv(r):
+        rI, rG = r[:nI], r[nI:]
+        uI = ops.solve_I(rI)
+        yG = orc.apply(rG - d.A_GI @ uI)
+        yI = uI - ops.solve_I(d.A_IG @ yG)
+        return np.concatenate([yI, yG])
+
+    bp = np.asarray(b)[np.concatenate([d.I, d.G])]
+    return pcg(lambda v: Aperm @ v, Minv, bp, tol, maxit)

@@ -1,0 +1,119 @@
+"""Plant plausible mistakes in a copy of the oracle and check that the pins catch them.
+
+Each mutation edits the oracle's source text (a sign, a dropped term, a
+transposed operand, a wrong index) and loads it as a fresh module on the CPU;
+the pin checks below must then fail.  The unmodified source must pass them.
+"""
+
+import importlib.util
+import os
+import sys
+import types
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "nystrom_schur_oracle.py")
+
+from workloads import make_problem, random_dbbd  # noqa: E402
+
+
+def load_variant(old, new):
+    text = open(SRC).read()
+    if old is not None:
+        assert text.count(old) >= 1, old
+        text = text.replace(old, new, 1)
+    mod = types.ModuleType("oracle_variant")
+    mod.__dict__["__name__"] = "oracle_variant"
+    sys.modules["oracle_variant"] = mod
+    exec(compile(text, "oracle_variant", "exec"), mod.__dict__)
+    return mod
+
+
+def pins_pass(m):
+    """A compact subset of the oracle pins, run against module ``m``."""
+    ok = []
+    # 1. Schur operator vs ((A^{-1})_GG)^{-1}
+    P = random_dbbd(5, sizes=(8, 6, 11), n_gamma=7)
+    d = m.DBBD(P.n, P.row_ptr, P.col, P.val, P.part)
+    ops = m.Operators(d)
+    Ainv = np.linalg.inv(P.csr().toarray())
+    S_ref = np.linalg.inv(Ainv[np.ix_(d.G, d.G)])
+    ok.append(np.allclose(ops.S(np.eye(d.n_gamma)), S_ref, rtol=1e-10, atol=1e-10))
+    # 2. block PCG with one column is textbook PCG
+    Q = make_problem((14, 14), (2, 2), sigma=1.5, ell=3.0, k=4, p=3)
+    d2 = m.DBBD(Q.n, Q.row_ptr, Q.col, Q.val, Q.part)
+    ops2 = m.Operators(d2)
+    S = ops2.S(np.eye(d2.n_gamma))
+    AGi = np.linalg.inv(d2.A_G.toarray())
+    f = np.random.default_rng(3).standard_normal((d2.n_gamma, 1))
+    res = m.bf_bpcg(ops2.S, ops2.solve_G, f, 0.0, 4, 1e-8)
+    x_ref, _ = spla.cg(S, f[:, 0], M=AGi, maxiter=4, rtol=1e-300, atol=0.0)
+    ok.append(np.allclose(res.X[:, 0], x_ref, rtol=1e-9, atol=1e-11))
+    # 3. Nystrom closed form / exactness for low rank
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((30, 5))
+    B = X @ X.T
+    Om = rng.standard_normal((30, 8))
+    U, Sig, r = m.nystrom_core(B @ Om, Om, 10, 1e-10)
+    ok.append(U.shape[1] == 5 and np.allclose(U @ np.diag(Sig) @ U.T, B, atol=1e-9 * np.abs(B).max()))
+    # 4. outer PCG vs textbook, with M_2
+    o = m.NystromSchurOracle(Q.n, Q.row_ptr, Q.col, Q.val, Q.part, k=4, p=3, omega=Q.omega())
+    o.setup()
+    M = o.apply(np.eye(d2.n_gamma))
+    g = np.random.default_rng(9).standard_normal(d2.n_gamma)
+    pr = m.pcg(o.ops.S, o.apply, g, 0.0, 3)
+    x2, _ = spla.cg(S, g, M=M, maxiter=3, rtol=1e-300, atol=0.0)
+    ok.append(np.allclose(pr.w, x2, rtol=1e-9, atol=1e-12))
+    # 5. exact inverse in one iteration (Nystrom of the whole space)
+    ng = d2.n_gamma
+    Om2 = np.random.default_rng(5).standard_normal((ng, ng))
+    o2 = m.NystromSchurOracle(Q.n, Q.row_ptr, Q.col, Q.val, Q.part, k=ng, p=0, omega=Om2, tol_inner=1e-14,
+                              eps_rel=1e-14)
+    o2.setup()
+    ok.append(np.allclose(o2.apply(np.eye(ng)) @ S, np.eye(ng), atol=1e-8))
+    # 6. full solve reaches the true residual
+    sr = o.solve(Q.b(), tol=1e-8)
+    ok.append(sr.relres_true <= 1e-8 and sr.relres_schur_true <= 2e-8)
+    return all(ok), ok
+
+
+MUTATIONS = {
+    "schur_sign": ("return d.A_G @ X - d.A_GI @ self.solve_I(d.A_IG @ X)",
+                   "return d.A_G @ X + d.A_GI @ self.solve_I(d.A_IG @ X)"),
+    "schur_drop_AG": ("return d.A_G @ X - d.A_GI @ self.solve_I(d.A_IG @ X)",
+                      "return - d.A_GI @ self.solve_I(d.A_IG @ X)"),
+    "bcg_beta_sign": ("beta = -sla.cho_solve(cf, Q.T @ Z)", "beta = sla.cho_solve(cf, Q.T @ Z)"),
+    "bcg_alpha_transposed": ("alpha = sla.cho_solve(cf, P.T @ R)", "alpha = sla.cho_solve(cf, Q.T @ R)"),
+    "bcg_residual_update": ("R -= Q @ alpha", "R -= P @ alpha"),
+    "nystrom_U_from_Y": ("U = Q @ Wm[:, order[:kk]]", "U = Y @ Wm[:, order[:kk]]"),
+    "nystrom_T_no_inverse": ("T = (RV1 / D1) @ RV1.T", "T = (RV1 * D1) @ RV1.T"),
+    "nystrom_ascending": ("order = np.argsort(-e, kind=\"stable\")", "order = np.argsort(e, kind=\"stable\")"),
+    "nystrom_C_uses_Q": ("C = Omega.T @ Y", "C = Omega.T @ Q"),
+    "pcg_beta": ("beta = rho_new / rho", "beta = rho / rho_new"),
+    "pcg_alpha": ("alpha = rho / float(p @ q)", "alpha = rho / float(q @ q)"),
+    "m2_drop_sigma": ("c = (self.Sigma * c.T).T if c.ndim == 2 else self.Sigma * c", "pass"),
+    "reduce_sign": ("return b[d.G] - d.A_GI @ self.ops.solve_I(b[d.I])",
+                    "return b[d.G] + d.A_GI @ self.ops.solve_I(b[d.I])"),
+    "backsub_drop": ("xI = ops.solve_I(b[d.I] - d.A_IG @ w)", "xI = ops.solve_I(b[d.I])"),
+    "interior_order": ("order = np.lexsort((interior, part[interior]))", "order = np.lexsort((part[interior], interior))"),
+}
+
+
+def test_unmodified_oracle_passes_pins():
+    m = load_variant(None, None)
+    passed, detail = pins_pass(m)
+    assert passed, detail
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(name):
+    old, new = MUTATIONS[name]
+    m = load_variant(old, new)
+    try:
+        passed, detail = pins_pass(m)
+    except Exception:
+        passed = False
+    assert not passed, f"mutation {name} was not detected"
