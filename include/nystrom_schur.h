@@ -1,0 +1,202 @@
+/*
+ * nystrom_schur.h -- C ABI of the MI355X (gfx950) Nystrom-Schur solver library.
+ *
+ * Method: H. Al Daas, T. Rees, J. Scott, "Two-level Nystrom-Schur
+ * Preconditioner for Sparse Symmetric Positive Definite Matrices",
+ * arXiv:2101.12164.  The library takes a sparse SPD matrix A in CSR form and a
+ * partition of its nodes into subdomains (interior nodes) and an interface,
+ * i.e. the doubly bordered block diagonal (DBBD) form of eq. (perm_A).  It
+ * builds the two-level preconditioner M_2 = A_Gamma^{-1} + Z Sigma Z^T of
+ * eq. (left_prec_mat) with Algorithm alg:prec1 and solves A x = b through the
+ * block LDL^T factorisation of eq. (A_LDLT): PCG on the Schur complement
+ * system S_Gamma w = f of eq. (Sx=b), then back-substitution.
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - Every array argument is a DEVICE pointer (memory of the current HIP
+ *    device, e.g. a torch CUDA tensor's data_ptr()), except the info structs
+ *    and the options struct, which live in HOST memory.
+ *  - Sizes are element counts.  Floating point data is IEEE double.
+ *  - Dense blocks of vectors are ROW-MAJOR: element (i, c) of an m x ncols
+ *    block is at [i * ncols + c].
+ *  - "Interface order": the interface nodes (part[i] < 0) sorted by ascending
+ *    original node index.  Vectors on the interface (length n_gamma) and the
+ *    sketch Omega use this order.
+ *  - "Interior order": interior nodes sorted by (subdomain id, original node
+ *    index).
+ *  - The caller owns every buffer it passes.  setup() copies what it needs, so
+ *    A, part and omega may be freed after it returns.  The handle owns all
+ *    internal device memory (factors, low-rank term, workspaces) and releases it
+ *    in nystrom_schur_destroy().
+ *  - Work is ordered on opt->stream (a hipStream_t; NULL = the null stream).
+ *    Entry points synchronise that stream before returning status; they never
+ *    synchronise the whole device.  A handle must not be used from two threads
+ *    at once.
+ *  - Errors are reported through the returned status only.  On failure of
+ *    setup(), *out is set to NULL and nothing leaks.  nystrom_schur_last_error()
+ *    returns a human-readable message for the last failure on a handle (or on
+ *    the calling thread when the handle is NULL).
+ */
+#ifndef NYSTROM_SCHUR_H
+#define NYSTROM_SCHUR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ns_handle_s* ns_handle;
+
+typedef enum {
+  NS_OK = 0,
+  NS_ERR_INVALID_ARG = 1,   /* bad sizes, NaN input, A not symmetric, partition not DBBD      */
+  NS_ERR_NOT_SPD = 2,       /* a Cholesky pivot was <= 0: info->bad_block / bad_col say where */
+  NS_ERR_OOM = 3,           /* device allocation failed                                       */
+  NS_ERR_HIP = 4,           /* a HIP runtime call failed                                      */
+  NS_ERR_NOT_CONVERGED = 5, /* maxit reached; the last iterate is still written               */
+  NS_ERR_BREAKDOWN = 6      /* block CG lost every search direction / zero curvature          */
+} ns_status;
+
+typedef enum { NS_FP64 = 0, NS_FP32 = 1 } ns_prec;
+
+typedef enum {
+  NS_APPLY_M2 = 0,    /* z = A_Gamma^{-1} r + Z (Sigma o Z^T r)            eq. (left_prec_mat)  */
+  NS_APPLY_ADEF2 = 1  /* z = t + Z E^{-1} (Z^T r - (S Z)^T t), t = A_G^{-1} r, E = Z^T S Z;
+                         adapted deflation, eqs. (adapted_deflation_prec),
+                         (deflation_comp_from_low_rank); PCG starts at w_0 = Z E^{-1} Z^T f */
+} ns_apply_mode;
+
+/*
+ * Options of setup().  Zero-initialise and set what you need; a value of 0 in
+ * tol_inner, eig_thresh_rel, orth_drop_rel or max_inner_iters selects the
+ * default given in brackets.
+ */
+typedef struct {
+  int32_t k;                 /* rank of the low-rank term, 0 <= k; k = 0 gives M = A_Gamma^{-1}  */
+  int32_t p;                 /* oversampling, 0 <= p, k + p <= n_gamma                            */
+  double tol_inner;          /* eps_SI: block-CG relative tolerance (max over columns) [0.1]     */
+  double eig_thresh_rel;     /* Nystrom threshold on eig(C) relative to its largest [1e-10]      */
+  double orth_drop_rel;      /* block-CG drop tolerance on singular values rel. to the largest
+                                [1e-8 with FP64 inner work, 1e-3 with FP32]                      */
+  int32_t max_inner_iters;   /* block-CG iteration cap [500]                                      */
+  int32_t prec_inner;        /* ns_prec of the inner block CG (factors, block vectors) [NS_FP64] */
+  int32_t apply_mode;        /* ns_apply_mode [NS_APPLY_M2]                                       */
+  int32_t trsm_cols;         /* columns per workgroup in the batched triangular solves, 16/32/64;
+                                0 = automatic (autotuned table)                                   */
+  const double* omega;       /* DEVICE, n_gamma x (k+p) row-major Gaussian sketch in interface
+                                order (Algorithm alg:prec1 step 1).  Required when k > 0.         */
+  const double* proposal;    /* DEVICE, optional n_gamma x k starting subspace (learned); NULL =
+                                plain Nystrom.  Accepted subspaces run in NS_APPLY_ADEF2 mode.   */
+  double accept_tol;         /* eigen-residual threshold for accepting `proposal` [0.2]          */
+  void* stream;              /* hipStream_t for all work; NULL = null stream                      */
+} ns_options;
+
+/* Outputs of setup(), HOST memory. Times are seconds measured with hipEvents. */
+typedef struct {
+  int64_t n, n_interior, n_gamma, n_junction;
+  int32_t n_sub, n_level2_blocks;
+  int32_t k_eff;             /* rank actually kept: min(k, rank of thresholded C)                 */
+  int32_t it_inner;          /* block-CG iterations (it_SI)                                       */
+  int32_t inner_converged;   /* 1 if eps_SI was reached                                           */
+  int32_t proposal_accepted; /* 1 if the learned subspace was accepted                            */
+  int32_t bad_block, bad_col;/* location of a non-positive pivot (NS_ERR_NOT_SPD), else -1        */
+  double inner_relres;       /* final max column relative residual of block CG                    */
+  double t_extract, t_factor, t_inner, t_nystrom, t_total;
+} ns_setup_info;
+
+/* Outputs of pcg_solve(), HOST memory. */
+typedef struct {
+  int32_t it_pcg;            /* outer PCG iterations (applications of S_Gamma in the loop)        */
+  int32_t converged;
+  double relres_schur;       /* recurrence residual ||r|| / ||f|| at exit                         */
+  double relres_true;        /* ||b - A x|| / ||b|| of the returned x                             */
+  double t_solve;            /* seconds, hipEvents                                                */
+  double* res_hist;          /* optional HOST array receiving ||r_j|| / ||f||, j = 0..it_pcg      */
+  int32_t res_hist_cap;      /* capacity of res_hist (0 = do not record)                          */
+} ns_solve_info;
+
+/*
+ * Build the preconditioner (Algorithm alg:prec1) for the n x n SPD matrix A.
+ *   row_ptr [n+1] int64, col_idx [nnz] int32, val [nnz] double: CSR of A with
+ *     both triangles stored; A must be exactly symmetric.
+ *   part [n] int32: partition labels.  part[i] >= 0: interior node of
+ *     subdomain part[i] (ids 0..n_sub-1, every id used); part[i] == -1:
+ *     interface node that is a junction of the interface split; part[i] <= -2:
+ *     interface node of interface block (-2 - part[i]).  Interior nodes of
+ *     distinct subdomains must not be coupled (eq. perm_A), and interface nodes
+ *     of distinct interface blocks must not be coupled (the same form applied to
+ *     A_Gamma, which the library uses for its exact A_Gamma solves).  Labelling
+ *     every interface node -1 is always valid (A_Gamma is then factorised as
+ *     one dense block).
+ *   opt: options (HOST).  info: HOST, may be NULL.
+ * Steps on the device: DBBD extraction; batched dense Cholesky of the interior
+ * blocks and of the interface blocks; the junction Schur complement and its
+ * Cholesky; block PCG on S_Gamma D = W Omega with W = A_Gamma - S_Gamma,
+ * preconditioned by A_Gamma^{-1}, to tol_inner; Y = A_Gamma D (which equals
+ * A_GammaI S_I^{-1} A_IGamma Omega by eq. S-1); the Nystrom core (QR of Y,
+ * EVDs of C = Omega^T Y and T); Z = A_Gamma^{-1} U.
+ * Errors: NS_ERR_INVALID_ARG (sizes, labels, asymmetry, DBBD violation, NaN),
+ * NS_ERR_NOT_SPD (info->bad_block, bad_col: subdomain block -- or, for
+ * bad_block <= -2, interface block -2-bad_block, or -1 for the junction
+ * complement -- and its column), NS_ERR_OOM, NS_ERR_HIP, NS_ERR_BREAKDOWN.
+ * A block CG that reaches max_inner_iters is not an error (info says so).
+ */
+ns_status nystrom_schur_setup(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                              const double* val, const int32_t* part, const ns_options* opt, ns_handle* out,
+                              ns_setup_info* info);
+
+/*
+ * z = M r for ncols vectors (Algorithm alg:prec1 step 12, or the adapted
+ * deflation form).  r_gamma, z_gamma: DEVICE, n_gamma x ncols row-major in
+ * interface order; they must not overlap.  1 <= ncols <= 1024.
+ */
+ns_status nystrom_schur_apply(ns_handle h, const double* r_gamma, double* z_gamma, int32_t ncols);
+
+/*
+ * Solve A x = b (eq. A_LDLT): f = b_Gamma - A_GammaI A_I^{-1} b_I; PCG with M on
+ * S_Gamma w = f until ||r_j|| / ||f|| <= rtol (eq. Sx=b); x_I = A_I^{-1}(b_I -
+ * A_IGamma w), x_Gamma = w.  b, x: DEVICE, length n, ORIGINAL node order; they
+ * must not overlap.  Returns NS_ERR_NOT_CONVERGED (x still written) when maxit
+ * iterations do not reach rtol; NS_ERR_INVALID_ARG for NaN/Inf in b.
+ */
+ns_status nystrom_schur_pcg_solve(ns_handle h, const double* b, double* x, double rtol, int32_t maxit,
+                                  ns_solve_info* info);
+
+/* Operator access (the building blocks of the two calls above), for testing and
+ * composition.  All blocks are DEVICE, row-major, ncols columns (1..1024).    */
+
+/* Y = S_Gamma X = A_Gamma X - A_GammaI A_I^{-1} A_IGamma X (eq. schur_complement);
+ * X, Y: n_gamma x ncols, interface order.  prec selects the FP64 operator or
+ * the FP32 one used inside the inner block CG (inputs/outputs stay double). */
+ns_status nystrom_schur_schur_apply(ns_handle h, const double* X, double* Y, int32_t ncols, int32_t prec);
+
+/* Y = A_Gamma^{-1} X (the first-level preconditioner of eq. S1); interface order. */
+ns_status nystrom_schur_interface_solve(ns_handle h, const double* X, double* Y, int32_t ncols, int32_t prec);
+
+/* Y = A_I^{-1} X; X, Y: n_interior x ncols in interior order. */
+ns_status nystrom_schur_interior_solve(ns_handle h, const double* X, double* Y, int32_t ncols, int32_t prec);
+
+/* Copy the dense lower Cholesky factor of interior block `block` (FP64) into
+ * L (DEVICE, nb x nb column-major, nb = size of the block; upper part zeroed). */
+ns_status nystrom_schur_export_factor(ns_handle h, int32_t block, double* L);
+
+/* Sizes: out[0..7] = n, n_interior, n_gamma, n_sub, n_junction,
+ * n_level2_blocks, k_eff, block size of interior block 0.  HOST array.      */
+ns_status nystrom_schur_get_sizes(ns_handle h, int64_t* out);
+
+/* Copy the low-rank term: Z (DEVICE, n_gamma x k_eff row-major, interface
+ * order) and Sigma (DEVICE, k_eff).  Either pointer may be NULL. */
+ns_status nystrom_schur_get_lowrank(ns_handle h, double* Z, double* Sigma);
+
+/* Release everything the handle owns.  Idempotent on NULL. */
+void nystrom_schur_destroy(ns_handle h);
+
+/* Message of the last failure on h (thread-local when h == NULL).  Never NULL. */
+const char* nystrom_schur_last_error(ns_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NYSTROM_SCHUR_H */

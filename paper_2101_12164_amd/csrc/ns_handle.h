@@ -1,0 +1,89 @@
+// The solver handle and the host-side operator entry points that the C ABI uses.
+#pragma once
+
+#include "../../include/nystrom_schur.h"
+#include "ns_internal.h"
+
+struct ns_handle_s {
+  hipStream_t stream = nullptr;
+  std::string last_error;
+
+  // sizes
+  int64_t n = 0, nnz = 0, nI = 0, nG = 0, nJ = 0;
+  int nsub = 0, nl2 = 0;
+  int k = 0, p = 0, s = 0, k_eff = 0;
+  int prec_inner = 0, apply_mode = 0, trsm_cols = 0;
+  double tol_inner = 0.1, eig_rel = 1e-10, drop_rel = 1e-6;
+  int max_inner = 500;
+
+  // original matrix (for the true residual)
+  ns::Csr Aorig;
+
+  // index maps
+  ns::DBuf<int32_t> iperm;  // padded interior row -> original node, -1 on padding
+  ns::DBuf<int32_t> icomp;  // padded interior row -> compact interior index, -1 on padding
+  ns::DBuf<int32_t> gperm;  // interface index -> original node
+  ns::DBuf<int32_t> l2src;  // padded level-2 row -> interface index, -1 on padding
+  ns::DBuf<int32_t> jsrc;   // padded junction row -> interface index, -1 on padding
+
+  // level-1 couplings and blocks
+  ns::Csr AIG;  // rows: padded interior rows; cols: interface index
+  ns::Csr AGI;  // rows: interface index;      cols: padded interior rows
+  ns::Csr AGG;  // rows: interface index;      cols: interface index
+  ns::TileLevel L1;
+  // level-2 (exact A_Gamma solve)
+  ns::Csr AsJ;  // rows: padded level-2 rows;  cols: junction rows
+  ns::Csr AJs;  // rows: padded junction rows; cols: padded level-2 rows
+  ns::TileLevel L2, LJ;
+
+  // low-rank term (FP64): Z n_G x k_eff (ld = k), Sigma k_eff
+  ns::DBuf<double> Z, Sigma;
+  // adapted deflation: SZ = S Z, chol(E) (k x k lower, ld = k)
+  ns::DBuf<double> SZ, Echol;
+
+  // error flags written by kernels (pinned host-visible copy in hflags)
+  ns::DBuf<int> dflags;
+  int* hflags = nullptr;  // pinned
+  double* hscal = nullptr;  // pinned scalars for readbacks
+
+  // workspaces (sized at setup)
+  ns::DBuf<double> wsT64, wsB64, wsJ64, wsG64, wsG64b;  // interior rhs, level-2 rhs, junction rhs, gathered copies
+  ns::DBuf<float> wsT32, wsB32, wsJ32, wsG32, wsG32b;
+  ns::DBuf<double> red;     // reduction partials
+  ns::DBuf<double> small;   // small dense scratch
+  int64_t ws_cols = 0;      // column capacity of the workspaces
+
+  ~ns_handle_s();
+};
+
+namespace ns {
+
+using Handle = ns_handle_s;
+
+// Workspace management: make sure every per-apply buffer holds ncols columns.
+void ensure_workspace(Handle& h, int64_t ncols);
+
+// Operators on FP64 or FP32 data (blocks row-major, ld = leading dimension).
+template <class T>
+void op_schur(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, bool w_only);
+template <class T>
+void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int ncols);
+template <class T>
+void op_interior_solve(Handle& h, const T* X, T* Y, int ncols);  // X, Y: n_I x ncols interior order
+
+// Setup pieces.
+void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
+                  const double* val, const int32_t* part);
+void assemble_junction(Handle& h);
+
+// Generic row gather / scatter and CSR products (row-major blocks).
+template <class T>
+void gather_rows(int64_t nrows, const int32_t* src, const T* R, int64_t ldr, T* Out, int64_t ldo, int ncols,
+                 hipStream_t st);
+template <class T, class U>
+void scatter_rows(int64_t nrows, const int32_t* dst, const T* B, int64_t ldb, U* Out, int64_t ldo, int ncols,
+                  hipStream_t st);
+template <class T>
+void csr_mult(const Csr& A, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, hipStream_t st);
+
+}  // namespace ns

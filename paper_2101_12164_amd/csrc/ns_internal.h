@@ -1,0 +1,103 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ns {
+
+// Dense blocks are stored as TILE x TILE tiles.
+constexpr int TILE = 64;
+constexpr int TILE2 = TILE * TILE;
+
+// Status codes (mirror ns_status of the public header).
+enum Status { OK = 0, INVALID_ARG = 1, NOT_SPD = 2, OOM = 3, HIP = 4, NOT_CONVERGED = 5, BREAKDOWN = 6 };
+
+struct Error {
+  int status;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int status, const std::string& msg);
+void hip_check(hipError_t e, const char* what, const char* file, int line);
+#define NS_HIP(call) ::ns::hip_check((call), #call, __FILE__, __LINE__)
+#define NS_LAUNCH_CHECK() ::ns::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+// Owning device buffer.
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      fail(OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  operator T*() const { return p; }
+};
+
+// A batch of dense SPD blocks in tile storage.
+//   Block b has nb[b] rows, padded to nt[b] * TILE; padding rows carry an
+//   identity diagonal so the padded block stays SPD and leaves padded
+//   right-hand-side rows at zero.
+//   Factor tiles: the lower tile triangle, tile columns in order, column j
+//   holding tiles (j, j), (j+1, j), ..., (nt-1, j); each tile TILE x TILE
+//   column-major.  Block b's first tile is at element foff[b].
+//   Inverse diagonal tiles: nt[b] tiles from element ioff[b].
+//   Padded rows of block b start at row roff[b] of a padded right-hand side.
+struct TileLevel {
+  int nblk = 0;
+  int max_nt = 0;
+  std::vector<int> h_nb, h_nt;
+  std::vector<int64_t> h_foff, h_ioff, h_roff;
+  int64_t nrows_pad = 0, f_elems = 0, i_elems = 0;
+  DBuf<int> nt, nb;
+  DBuf<int64_t> foff, ioff, roff;
+  DBuf<double> L64, Linv64;
+  DBuf<float> L32, Linv32;
+  void layout(const std::vector<int>& sizes);  // host: fills h_*, allocates index arrays + FP64 storage
+};
+
+inline int64_t tri_tiles(int nt) { return int64_t(nt) * (nt + 1) / 2; }
+
+// ---------------------------------------------------------------- dense tiles
+// Batched Cholesky of all blocks of a level (FP64, in place), with inverted
+// diagonal tiles.  err[0..2] = (flag, block, column) of the first pivot <= 0.
+void tile_cholesky(TileLevel& lv, int* d_err, hipStream_t st);
+// Convert the FP64 factor of a level to FP32 (allocates L32/Linv32).
+void tile_make_fp32(TileLevel& lv, hipStream_t st);
+// In-place solve (L L^T) X = B on a padded right-hand side (rows lv.nrows_pad,
+// row-major with leading dimension ldb, ncols columns).
+template <class T>
+void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st);
+// Expand the factor of one block to a dense nb x nb column-major lower matrix.
+void tile_export(const TileLevel& lv, int block, double* out, hipStream_t st);
+
+// ---------------------------------------------------------------- sparse
+struct Csr {
+  int64_t nrows = 0, nnz = 0;
+  DBuf<int64_t> ptr;
+  DBuf<int32_t> col;
+  DBuf<double> val64;
+  DBuf<float> val32;
+};
+
+}  // namespace ns

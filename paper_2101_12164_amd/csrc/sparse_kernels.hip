@@ -1,0 +1,754 @@
+// Sparse and index kernels: the DBBD extraction of eq. (perm_A) on the device,
+// the CSR products A_IGamma X, A_GammaI T, A_Gamma X, and the operators built
+// from them: the Schur complement S_Gamma (eq. schur_complement), the exact
+// A_Gamma solve through the interface split, and the interior solve A_I^{-1}.
+#include "ns_handle.h"
+
+namespace ns {
+namespace {
+
+constexpr int F_STRUCT = 0, F_NAN = 1, F_ASYM = 2, F_DBBD1 = 3, F_DBBD2 = 4;
+
+// ----------------------------------------------------------------- products
+// Threads per row (TPR) cover the columns of a row-major block.
+
+template <class T, int TPR>
+__global__ __launch_bounds__(256) void k_spmm(int64_t nrows, const int64_t* __restrict__ ptr,
+                                              const int32_t* __restrict__ col, const T* __restrict__ val,
+                                              const T* __restrict__ X, int64_t ldx, T* __restrict__ Y, int64_t ldy,
+                                              int ncols) {
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
+  const int lane = threadIdx.x % TPR;
+  if (row >= nrows) return;
+  const int64_t e0 = ptr[row], e1 = ptr[row + 1];
+  for (int c = lane; c < ncols; c += TPR) {
+    T acc = T(0);
+    for (int64_t e = e0; e < e1; ++e) acc += val[e] * X[int64_t(col[e]) * ldx + c];
+    Y[row * ldy + c] = acc;
+  }
+}
+
+// Y = A_Gamma X - A_GammaI Tb   (or Y = A_GammaI Tb when w_only)
+template <class T, int TPR>
+__global__ __launch_bounds__(256) void k_schur_epi(int64_t nrows, const int64_t* __restrict__ pG,
+                                                   const int32_t* __restrict__ cG, const T* __restrict__ vG,
+                                                   const T* __restrict__ X, int64_t ldx,
+                                                   const int64_t* __restrict__ pI, const int32_t* __restrict__ cI,
+                                                   const T* __restrict__ vI, const T* __restrict__ Tb, int64_t ldt,
+                                                   T* __restrict__ Y, int64_t ldy, int ncols, int w_only) {
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
+  const int lane = threadIdx.x % TPR;
+  if (row >= nrows) return;
+  for (int c = lane; c < ncols; c += TPR) {
+    T a = T(0), w = T(0);
+    if (!w_only)
+      for (int64_t e = pG[row]; e < pG[row + 1]; ++e) a += vG[e] * X[int64_t(cG[e]) * ldx + c];
+    for (int64_t e = pI[row]; e < pI[row + 1]; ++e) w += vI[e] * Tb[int64_t(cI[e]) * ldt + c];
+    Y[row * ldy + c] = w_only ? w : a - w;
+  }
+}
+
+// Out[r] = (src[r] >= 0 ? R[src[r]] : 0) - sum_e val[e] X[col[e]]   (CSR optional)
+template <class T, int TPR>
+__global__ __launch_bounds__(256) void k_gather_sub(int64_t nrows, const int32_t* __restrict__ src,
+                                                    const T* __restrict__ R, int64_t ldr,
+                                                    const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                    const T* __restrict__ val, const T* __restrict__ X, int64_t ldx,
+                                                    T* __restrict__ Out, int64_t ldo, int ncols) {
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
+  const int lane = threadIdx.x % TPR;
+  if (row >= nrows) return;
+  const int s = src ? src[row] : int(row);
+  for (int c = lane; c < ncols; c += TPR) {
+    T acc = s >= 0 ? R[int64_t(s) * ldr + c] : T(0);
+    if (ptr)
+      for (int64_t e = ptr[row]; e < ptr[row + 1]; ++e) acc -= val[e] * X[int64_t(col[e]) * ldx + c];
+    Out[row * ldo + c] = acc;
+  }
+}
+
+// Out[dst[r]] = B[r] for dst[r] >= 0
+template <class T, class U, int TPR>
+__global__ __launch_bounds__(256) void k_scatter(int64_t nrows, const int32_t* __restrict__ dst,
+                                                 const T* __restrict__ B, int64_t ldb, U* __restrict__ Out,
+                                                 int64_t ldo, int ncols) {
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
+  const int lane = threadIdx.x % TPR;
+  if (row >= nrows) return;
+  const int d = dst[row];
+  if (d < 0) return;
+  for (int c = lane; c < ncols; c += TPR) Out[int64_t(d) * ldo + c] = U(B[row * ldb + c]);
+}
+
+template <int TPR>
+inline int grid_rows(int64_t nrows) {
+  return int((nrows * TPR + 255) / 256);
+}
+
+#define NS_TPR_DISPATCH(ncols, BODY)      \
+  do {                                    \
+    if ((ncols) == 1) {                   \
+      constexpr int TPR = 1;              \
+      BODY;                               \
+    } else if ((ncols) <= 4) {            \
+      constexpr int TPR = 4;              \
+      BODY;                               \
+    } else if ((ncols) <= 16) {           \
+      constexpr int TPR = 16;             \
+      BODY;                               \
+    } else {                              \
+      constexpr int TPR = 64;             \
+      BODY;                               \
+    }                                     \
+  } while (0)
+
+template <class T>
+const T* csr_vals(const Csr& A) {
+  if constexpr (sizeof(T) == 8)
+    return A.val64.p;
+  else
+    return A.val32.p;
+}
+
+template <class T>
+void spmm(const Csr& A, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, hipStream_t st) {
+  if (A.nrows == 0 || ncols == 0) return;
+  NS_TPR_DISPATCH(ncols, (k_spmm<T, TPR><<<grid_rows<TPR>(A.nrows), 256, 0, st>>>(
+                              A.nrows, A.ptr, A.col, csr_vals<T>(A), X, ldx, Y, ldy, ncols)));
+  NS_LAUNCH_CHECK();
+}
+
+template <class T>
+void gather_sub(int64_t nrows, const int32_t* src, const T* R, int64_t ldr, const Csr* A, const T* X, int64_t ldx,
+                T* Out, int64_t ldo, int ncols, hipStream_t st) {
+  if (nrows == 0 || ncols == 0) return;
+  const int64_t* p = A && A->nnz ? A->ptr.p : nullptr;
+  const int32_t* c = A ? A->col.p : nullptr;
+  const T* v = A ? csr_vals<T>(*A) : nullptr;
+  NS_TPR_DISPATCH(ncols, (k_gather_sub<T, TPR><<<grid_rows<TPR>(nrows), 256, 0, st>>>(nrows, src, R, ldr, p, c, v,
+                                                                                          X, ldx, Out, ldo, ncols)));
+  NS_LAUNCH_CHECK();
+}
+
+template <class T, class U>
+void scatter(int64_t nrows, const int32_t* dst, const T* B, int64_t ldb, U* Out, int64_t ldo, int ncols,
+             hipStream_t st) {
+  if (nrows == 0 || ncols == 0) return;
+  NS_TPR_DISPATCH(ncols, (k_scatter<T, U, TPR><<<grid_rows<TPR>(nrows), 256, 0, st>>>(nrows, dst, B, ldb, Out, ldo,
+                                                                                          ncols)));
+  NS_LAUNCH_CHECK();
+}
+
+// ----------------------------------------------------------------- scan
+// In-place inclusive scan of a[0..m) (int64), 4096 elements per workgroup.
+__global__ __launch_bounds__(1024) void k_scan_local(int64_t* a, int64_t m, int64_t* bsum) {
+  __shared__ int64_t s[1024];
+  const int64_t base = int64_t(blockIdx.x) * 4096 + int64_t(threadIdx.x) * 4;
+  int64_t v[4];
+  int64_t run = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t idx = base + q;
+    run += idx < m ? a[idx] : 0;
+    v[q] = run;
+  }
+  s[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  const int64_t excl = threadIdx.x ? s[threadIdx.x - 1] : 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t idx = base + q;
+    if (idx < m) a[idx] = v[q] + excl;
+  }
+  if (threadIdx.x == 1023 && bsum) bsum[blockIdx.x] = s[1023];
+}
+
+__global__ void k_scan_add(int64_t* a, int64_t m, const int64_t* bsum) {
+  const int64_t idx = int64_t(blockIdx.x + 1) * 4096 + int64_t(threadIdx.x) * 4;  // blocks 1..
+  const int64_t off = bsum[blockIdx.x];                                            // inclusive sum of blocks < this
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (idx + q < m) a[idx + q] += off;
+}
+
+void scan_inclusive(int64_t* a, int64_t m, hipStream_t st) {
+  if (m <= 0) return;
+  const int64_t nb = (m + 4095) / 4096;
+  DBuf<int64_t> bsum;
+  bsum.alloc(nb);
+  k_scan_local<<<int(nb), 1024, 0, st>>>(a, m, bsum);
+  NS_LAUNCH_CHECK();
+  if (nb > 1) {
+    scan_inclusive(bsum.p, nb, st);
+    k_scan_add<<<int(nb - 1), 1024, 0, st>>>(a, m, bsum);
+    NS_LAUNCH_CHECK();
+  }
+  NS_HIP(hipStreamSynchronize(st));  // bsum is freed on return
+}
+
+// ----------------------------------------------------------------- extraction
+
+__global__ void k_validate(int64_t n, int64_t nnz, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                           const double* __restrict__ val, const int32_t* __restrict__ part, int* flags,
+                           int* minmax) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (i == 0 && (ptr[0] != 0 || ptr[n] != nnz)) flags[F_STRUCT] = 1;
+  const int64_t e0 = ptr[i], e1 = ptr[i + 1];
+  if (e1 < e0 || e0 < 0 || e1 > nnz) {
+    flags[F_STRUCT] = 1;
+    return;
+  }
+  for (int64_t e = e0; e < e1; ++e) {
+    const int32_t j = col[e];
+    if (j < 0 || j >= n) flags[F_STRUCT] = 1;
+    const double v = val[e];
+    if (!(v == v) || v - v != 0.0) flags[F_NAN] = 1;
+  }
+  atomicMax(&minmax[0], part[i]);
+  atomicMin(&minmax[1], part[i]);
+}
+
+// Every stored (i, j, v) must have its mirror (j, i, v).
+__global__ void k_symcheck(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                           const double* __restrict__ val, int* flags) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+    const int32_t j = col[e];
+    bool ok = false;
+    for (int64_t f = ptr[j]; f < ptr[j + 1]; ++f)
+      if (col[f] == i) {
+        ok = val[f] == val[e];
+        break;
+      }
+    if (!ok) flags[F_ASYM] = 1;
+  }
+}
+
+__global__ void k_group(int64_t n, const int32_t* __restrict__ part, int nsub, int nl2, int32_t* __restrict__ grp,
+                        int32_t* __restrict__ grp2) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = part[i];
+  grp[i] = p >= 0 ? p : (p <= -2 ? nsub + (-2 - p) : nsub + nl2);
+  grp2[i] = p < 0 ? 1 : 0;
+}
+
+// Stable rank of each node inside its group: rank[i] = #{j < i : grp[j] == grp[i]}.
+__global__ __launch_bounds__(1024) void k_chunk_hist(int64_t n, const int32_t* __restrict__ grp, int G,
+                                                     int32_t* __restrict__ cnt) {
+  extern __shared__ int hist[];
+  for (int g = threadIdx.x; g < G; g += blockDim.x) hist[g] = 0;
+  __syncthreads();
+  const int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  if (i < n) atomicAdd(&hist[grp[i]], 1);
+  __syncthreads();
+  for (int g = threadIdx.x; g < G; g += blockDim.x) cnt[int64_t(blockIdx.x) * G + g] = hist[g];
+}
+
+__global__ void k_chunk_offsets(int nchunk, int G, int32_t* __restrict__ cnt, int32_t* __restrict__ total) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  int run = 0;
+  for (int c = 0; c < nchunk; ++c) {
+    const int v = cnt[int64_t(c) * G + g];
+    cnt[int64_t(c) * G + g] = run;
+    run += v;
+  }
+  total[g] = run;
+}
+
+__global__ __launch_bounds__(1024) void k_chunk_rank(int64_t n, const int32_t* __restrict__ grp, int G,
+                                                     const int32_t* __restrict__ cnt, int32_t* __restrict__ rank) {
+  __shared__ int sg[1024];
+  const int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  sg[threadIdx.x] = i < n ? grp[i] : -1;
+  __syncthreads();
+  if (i >= n) return;
+  const int my = sg[threadIdx.x];
+  int c = 0;
+  for (int u = 0; u < int(threadIdx.x); ++u) c += sg[u] == my;
+  rank[i] = cnt[int64_t(blockIdx.x) * G + my] + c;
+}
+
+struct NodeMaps {
+  const int32_t* part;
+  const int32_t* rank;   // rank inside (subdomain | level-2 block | junction set)
+  const int32_t* gidx;   // rank among interface nodes
+  const int64_t* roff1;  // padded row offset of each subdomain block
+  const int64_t* roff2;  // padded row offset of each level-2 block
+  const int64_t* coff1;  // compact interior offset of each subdomain
+};
+
+__global__ void k_maps(int64_t n, NodeMaps m, int32_t* iperm, int32_t* icomp, int32_t* gperm, int32_t* l2src,
+                       int32_t* jsrc) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = m.part[i];
+  const int r = m.rank[i];
+  if (p >= 0) {
+    const int64_t pos = m.roff1[p] + r;
+    iperm[pos] = int32_t(i);
+    icomp[pos] = int32_t(m.coff1[p] + r);
+  } else {
+    const int g = m.gidx[i];
+    gperm[g] = int32_t(i);
+    if (p <= -2)
+      l2src[m.roff2[-2 - p] + r] = g;
+    else
+      jsrc[r] = g;
+  }
+}
+
+__device__ __forceinline__ int64_t tile_elem(int nt, int r, int c) {  // element (r, c), r >= c, of a tile block
+  const int i = r >> 6, j = c >> 6;
+  return (int64_t(j) * nt - int64_t(j) * (j - 1) / 2 + (i - j)) * TILE2 + (c & 63) * TILE + (r & 63);
+}
+
+struct Outs {
+  int64_t *pIG, *pGI, *pGG, *psJ, *pJs;  // row pointers (counting pass: counts at [row+1])
+  int32_t *cIG, *cGI, *cGG, *csJ, *cJs;
+  double *vIG, *vGI, *vGG, *vsJ, *vJs;
+  float *fIG, *fGI, *fGG, *fsJ, *fJs;
+  double *L1, *L2, *LJ;
+  const int *nt1, *nt2;
+  const int64_t *foff1, *foff2;
+  int ntJ;
+};
+
+// One thread per row.  FILL = false: count entries per CSR row; FILL = true:
+// write CSR entries and the lower triangles of the dense diagonal blocks.
+template <bool FILL>
+__global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                          const double* __restrict__ val, NodeMaps m, Outs o, int* flags) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int pi = m.part[i];
+  const int ri = m.rank[i];
+  int64_t nIG = 0, nGI = 0, nGG = 0, nsJ = 0, nJs = 0;
+  int64_t rowIG = 0, rowG = 0, rowsJ = 0, rowJs = 0;
+  if (pi >= 0) {
+    rowIG = m.roff1[pi] + ri;
+  } else {
+    rowG = m.gidx[i];
+    if (pi <= -2) rowsJ = m.roff2[-2 - pi] + ri;
+    if (pi == -1) rowJs = ri;
+  }
+  for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+    const int j = col[e];
+    const int pj = m.part[j];
+    const double v = val[e];
+    const int rj = m.rank[j];
+    if (pi >= 0) {
+      if (pj >= 0) {
+        if (pj != pi) {
+          flags[F_DBBD1] = 1;
+        } else if (FILL && ri >= rj) {
+          o.L1[o.foff1[pi] + tile_elem(o.nt1[pi], ri, rj)] = v;
+        }
+      } else {
+        if (FILL) {
+          const int64_t q = o.pIG[rowIG] + nIG;
+          o.cIG[q] = m.gidx[j];
+          o.vIG[q] = v;
+          o.fIG[q] = float(v);
+        }
+        ++nIG;
+      }
+    } else {
+      if (pj >= 0) {
+        if (FILL) {
+          const int64_t q = o.pGI[rowG] + nGI;
+          o.cGI[q] = int32_t(m.roff1[pj] + rj);
+          o.vGI[q] = v;
+          o.fGI[q] = float(v);
+        }
+        ++nGI;
+      } else {
+        if (FILL) {
+          const int64_t q = o.pGG[rowG] + nGG;
+          o.cGG[q] = m.gidx[j];
+          o.vGG[q] = v;
+          o.fGG[q] = float(v);
+        }
+        ++nGG;
+        if (pi <= -2) {
+          if (pj <= -2) {
+            if (pj != pi)
+              flags[F_DBBD2] = 1;
+            else if (FILL && ri >= rj)
+              o.L2[o.foff2[-2 - pi] + tile_elem(o.nt2[-2 - pi], ri, rj)] = v;
+          } else {  // junction column
+            if (FILL) {
+              const int64_t q = o.psJ[rowsJ] + nsJ;
+              o.csJ[q] = rj;
+              o.vsJ[q] = v;
+              o.fsJ[q] = float(v);
+            }
+            ++nsJ;
+          }
+        } else {  // junction row
+          if (pj <= -2) {
+            if (FILL) {
+              const int64_t q = o.pJs[rowJs] + nJs;
+              o.cJs[q] = int32_t(m.roff2[-2 - pj] + rj);
+              o.vJs[q] = v;
+              o.fJs[q] = float(v);
+            }
+            ++nJs;
+          } else if (FILL && ri >= rj) {
+            o.LJ[tile_elem(o.ntJ, ri, rj)] = v;
+          }
+        }
+      }
+    }
+  }
+  if (!FILL) {
+    if (pi >= 0) {
+      o.pIG[rowIG + 1] = nIG;
+    } else {
+      o.pGI[rowG + 1] = nGI;
+      o.pGG[rowG + 1] = nGG;
+      if (pi <= -2) o.psJ[rowsJ + 1] = nsJ;
+      if (pi == -1) o.pJs[rowJs + 1] = nJs;
+    }
+  }
+}
+
+// Identity on the padded diagonal of every block.
+__global__ void k_pad_identity(const int* __restrict__ nt_arr, const int* __restrict__ nb_arr,
+                               const int64_t* __restrict__ foff, double* __restrict__ L) {
+  const int b = blockIdx.y;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nt = nt_arr[b], nb = nb_arr[b];
+  if (r < nb || r >= nt * TILE) return;
+  L[foff[b] + tile_elem(nt, r, r)] = 1.0;
+}
+
+__global__ void k_csr_to_dense(int64_t nrows, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                               const double* __restrict__ val, double* __restrict__ E, int64_t lde) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) E[r * lde + col[e]] = val[e];
+}
+
+// S_J(ji, jj) -= sum_e A_Js(ji, e) * E(col_e, jj) on the lower triangle.
+__global__ void k_junction_update(int nJ, int ntJ, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                  const double* __restrict__ val, const double* __restrict__ E, double* __restrict__ LJ) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(nJ) * nJ) return;
+  const int ji = int(idx / nJ), jj = int(idx % nJ);
+  if (jj > ji) return;
+  double acc = 0.0;
+  for (int64_t e = ptr[ji]; e < ptr[ji + 1]; ++e) acc += val[e] * E[int64_t(col[e]) * nJ + jj];
+  LJ[tile_elem(ntJ, ji, jj)] -= acc;
+}
+
+void pad_identity(TileLevel& lv, hipStream_t st) {
+  if (lv.nblk == 0) return;
+  dim3 g((lv.max_nt * TILE + 255) / 256, lv.nblk);
+  k_pad_identity<<<g, 256, 0, st>>>(lv.nt, lv.nb, lv.foff, lv.L64);
+  NS_LAUNCH_CHECK();
+}
+
+void alloc_csr(Csr& A, int64_t nrows) {
+  A.nrows = nrows;
+  A.ptr.alloc(nrows + 1);
+  NS_HIP(hipMemset(A.ptr.p, 0, (nrows + 1) * sizeof(int64_t)));
+}
+
+void finish_csr(Csr& A, hipStream_t st) {
+  if (A.nrows == 0) return;
+  scan_inclusive(A.ptr.p + 1, A.nrows, st);
+  NS_HIP(hipMemcpyAsync(&A.nnz, A.ptr.p + A.nrows, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipStreamSynchronize(st));
+  A.col.alloc(A.nnz > 0 ? A.nnz : 1);
+  A.val64.alloc(A.nnz > 0 ? A.nnz : 1);
+  A.val32.alloc(A.nnz > 0 ? A.nnz : 1);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------ API
+
+void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col, const double* val,
+                  const int32_t* part) {
+  hipStream_t st = h.stream;
+  h.n = n;
+  h.nnz = nnz;
+  int* flags = h.dflags.p;
+  DBuf<int> minmax;
+  minmax.alloc(2);
+  const int hm[2] = {INT32_MIN, INT32_MAX};
+  NS_HIP(hipMemcpy(minmax.p, hm, sizeof(hm), hipMemcpyHostToDevice));
+  const int gn = int((n + 255) / 256);
+  k_validate<<<gn, 256, 0, st>>>(n, nnz, row_ptr, col, val, part, flags, minmax);
+  NS_LAUNCH_CHECK();
+  int mm[2];
+  NS_HIP(hipMemcpyAsync(mm, minmax.p, sizeof(mm), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipMemcpyAsync(h.hflags, flags, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipStreamSynchronize(st));
+  if (h.hflags[F_STRUCT]) fail(INVALID_ARG, "CSR structure invalid (row_ptr/col_idx out of range)");
+  if (h.hflags[F_NAN]) fail(INVALID_ARG, "matrix values contain NaN or Inf");
+  k_symcheck<<<gn, 256, 0, st>>>(n, row_ptr, col, val, flags);
+  NS_LAUNCH_CHECK();
+  h.nsub = mm[0] >= 0 ? mm[0] + 1 : 0;
+  h.nl2 = mm[1] <= -2 ? -mm[1] - 1 : 0;
+  const int G = h.nsub + h.nl2 + 1;
+  if (G > 32768) fail(INVALID_ARG, "too many subdomains + interface blocks (limit 32767)");
+
+  // groups and stable ranks
+  DBuf<int32_t> grp, grp2, rank, gidx, cnt, total, total2;
+  grp.alloc(n);
+  grp2.alloc(n);
+  rank.alloc(n);
+  gidx.alloc(n);
+  const int nchunk = int((n + 1023) / 1024);
+  k_group<<<gn, 256, 0, st>>>(n, part, h.nsub, h.nl2, grp, grp2);
+  NS_LAUNCH_CHECK();
+  auto ranks = [&](const int32_t* g, int GG, int32_t* out, DBuf<int32_t>& tot) {
+    cnt.alloc(int64_t(nchunk) * GG);
+    tot.alloc(GG);
+    k_chunk_hist<<<nchunk, 1024, GG * sizeof(int), st>>>(n, g, GG, cnt);
+    NS_LAUNCH_CHECK();
+    k_chunk_offsets<<<(GG + 255) / 256, 256, 0, st>>>(nchunk, GG, cnt, tot);
+    NS_LAUNCH_CHECK();
+    k_chunk_rank<<<nchunk, 1024, 0, st>>>(n, g, GG, cnt, out);
+    NS_LAUNCH_CHECK();
+  };
+  ranks(grp, G, rank, total);
+  ranks(grp2, 2, gidx, total2);
+  std::vector<int> tot(G);
+  NS_HIP(hipMemcpyAsync(tot.data(), total.p, G * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipMemcpyAsync(h.hflags, flags, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipStreamSynchronize(st));
+  if (h.hflags[F_ASYM]) fail(INVALID_ARG, "A is not symmetric (pattern or values)");
+
+  std::vector<int> nb1(tot.begin(), tot.begin() + h.nsub), nb2(tot.begin() + h.nsub, tot.begin() + h.nsub + h.nl2);
+  h.nJ = tot[G - 1];
+  h.nI = 0;
+  std::vector<int64_t> coff(h.nsub + 1, 0);
+  for (int b = 0; b < h.nsub; ++b) {
+    coff[b + 1] = coff[b] + nb1[b];
+  }
+  h.nI = coff[h.nsub];
+  h.nG = n - h.nI;
+  if (h.nG <= 0) fail(INVALID_ARG, "partition has no interface nodes");
+  if (h.nI <= 0) fail(INVALID_ARG, "partition has no interior nodes");
+  h.L1.layout(nb1);
+  h.L2.layout(nb2);
+  h.LJ.layout(h.nJ > 0 ? std::vector<int>{int(h.nJ)} : std::vector<int>{});
+  DBuf<int64_t> coff1;
+  coff1.alloc(h.nsub > 0 ? h.nsub : 1);
+  if (h.nsub) NS_HIP(hipMemcpy(coff1.p, coff.data(), h.nsub * sizeof(int64_t), hipMemcpyHostToDevice));
+
+  // maps
+  const int64_t nIpad = h.L1.nrows_pad, n2pad = h.L2.nrows_pad, nJpad = h.LJ.nrows_pad;
+  h.iperm.alloc(nIpad > 0 ? nIpad : 1);
+  h.icomp.alloc(nIpad > 0 ? nIpad : 1);
+  h.gperm.alloc(h.nG);
+  h.l2src.alloc(n2pad > 0 ? n2pad : 1);
+  h.jsrc.alloc(nJpad > 0 ? nJpad : 1);
+  NS_HIP(hipMemsetAsync(h.iperm.p, 0xFF, h.iperm.n * sizeof(int32_t), st));
+  NS_HIP(hipMemsetAsync(h.icomp.p, 0xFF, h.icomp.n * sizeof(int32_t), st));
+  NS_HIP(hipMemsetAsync(h.l2src.p, 0xFF, h.l2src.n * sizeof(int32_t), st));
+  NS_HIP(hipMemsetAsync(h.jsrc.p, 0xFF, h.jsrc.n * sizeof(int32_t), st));
+  NodeMaps m{part, rank, gidx, h.L1.roff.p, h.L2.roff.p, coff1.p};
+  k_maps<<<gn, 256, 0, st>>>(n, m, h.iperm, h.icomp, h.gperm, h.l2src, h.jsrc);
+  NS_LAUNCH_CHECK();
+
+  // counting pass
+  alloc_csr(h.AIG, nIpad);
+  alloc_csr(h.AGI, h.nG);
+  alloc_csr(h.AGG, h.nG);
+  alloc_csr(h.AsJ, n2pad);
+  alloc_csr(h.AJs, nJpad);
+  Outs o{};
+  o.pIG = h.AIG.ptr;
+  o.pGI = h.AGI.ptr;
+  o.pGG = h.AGG.ptr;
+  o.psJ = h.AsJ.ptr;
+  o.pJs = h.AJs.ptr;
+  o.nt1 = h.L1.nt;
+  o.nt2 = h.L2.nt;
+  o.foff1 = h.L1.foff;
+  o.foff2 = h.L2.foff;
+  o.ntJ = h.LJ.nblk ? h.LJ.h_nt[0] : 0;
+  k_extract<false><<<gn, 256, 0, st>>>(n, row_ptr, col, val, m, o, flags);
+  NS_LAUNCH_CHECK();
+  NS_HIP(hipMemcpyAsync(h.hflags, flags, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipStreamSynchronize(st));
+  if (h.hflags[F_DBBD1]) fail(INVALID_ARG, "partition is not DBBD: interior nodes of different subdomains are coupled");
+  if (h.hflags[F_DBBD2]) fail(INVALID_ARG, "interface split invalid: nodes of different interface blocks are coupled");
+  finish_csr(h.AIG, st);
+  finish_csr(h.AGI, st);
+  finish_csr(h.AGG, st);
+  finish_csr(h.AsJ, st);
+  finish_csr(h.AJs, st);
+  // fill pass
+  if (h.L1.f_elems) NS_HIP(hipMemsetAsync(h.L1.L64.p, 0, h.L1.f_elems * sizeof(double), st));
+  if (h.L2.f_elems) NS_HIP(hipMemsetAsync(h.L2.L64.p, 0, h.L2.f_elems * sizeof(double), st));
+  if (h.LJ.f_elems) NS_HIP(hipMemsetAsync(h.LJ.L64.p, 0, h.LJ.f_elems * sizeof(double), st));
+  o.cIG = h.AIG.col;
+  o.vIG = h.AIG.val64;
+  o.fIG = h.AIG.val32;
+  o.cGI = h.AGI.col;
+  o.vGI = h.AGI.val64;
+  o.fGI = h.AGI.val32;
+  o.cGG = h.AGG.col;
+  o.vGG = h.AGG.val64;
+  o.fGG = h.AGG.val32;
+  o.csJ = h.AsJ.col;
+  o.vsJ = h.AsJ.val64;
+  o.fsJ = h.AsJ.val32;
+  o.cJs = h.AJs.col;
+  o.vJs = h.AJs.val64;
+  o.fJs = h.AJs.val32;
+  o.L1 = h.L1.L64;
+  o.L2 = h.L2.L64;
+  o.LJ = h.LJ.L64;
+  k_extract<true><<<gn, 256, 0, st>>>(n, row_ptr, col, val, m, o, flags);
+  NS_LAUNCH_CHECK();
+  pad_identity(h.L1, st);
+  pad_identity(h.L2, st);
+  pad_identity(h.LJ, st);
+  // keep the original matrix for the true residual
+  h.Aorig.nrows = n;
+  h.Aorig.nnz = nnz;
+  h.Aorig.ptr.alloc(n + 1);
+  h.Aorig.col.alloc(nnz > 0 ? nnz : 1);
+  h.Aorig.val64.alloc(nnz > 0 ? nnz : 1);
+  NS_HIP(hipMemcpyAsync(h.Aorig.ptr.p, row_ptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+  if (nnz) {
+    NS_HIP(hipMemcpyAsync(h.Aorig.col.p, col, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    NS_HIP(hipMemcpyAsync(h.Aorig.val64.p, val, nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  NS_HIP(hipStreamSynchronize(st));
+}
+
+void assemble_junction(Handle& h) {
+  hipStream_t st = h.stream;
+  if (h.nJ == 0 || h.L2.nblk == 0) return;
+  const int64_t nJ = h.nJ, n2pad = h.L2.nrows_pad;
+  DBuf<double> E;
+  E.alloc(n2pad * nJ);
+  NS_HIP(hipMemsetAsync(E.p, 0, n2pad * nJ * sizeof(double), st));
+  k_csr_to_dense<<<int((n2pad + 255) / 256), 256, 0, st>>>(n2pad, h.AsJ.ptr, h.AsJ.col, h.AsJ.val64, E, nJ);
+  NS_LAUNCH_CHECK();
+  tile_solve<double>(h.L2, E.p, nJ, int(nJ), 64, st);
+  k_junction_update<<<int((nJ * nJ + 255) / 256), 256, 0, st>>>(int(nJ), h.LJ.h_nt[0], h.AJs.ptr, h.AJs.col,
+                                                                 h.AJs.val64, E, h.LJ.L64);
+  NS_LAUNCH_CHECK();
+  NS_HIP(hipStreamSynchronize(st));
+}
+
+template <class T>
+static T* ws_ptr(DBuf<double>& a, DBuf<float>& b) {
+  if constexpr (sizeof(T) == 8)
+    return a.p;
+  else
+    return b.p;
+}
+
+void ensure_workspace(Handle& h, int64_t ncols) {
+  if (ncols <= h.ws_cols) return;
+  const int64_t c = ncols;
+  auto grow = [&](auto& buf, int64_t rows) { buf.alloc(rows > 0 ? rows * c : 1); };
+  grow(h.wsT64, h.L1.nrows_pad);
+  grow(h.wsB64, h.L2.nrows_pad);
+  grow(h.wsJ64, h.LJ.nrows_pad);
+  grow(h.wsG64, h.nG);
+  grow(h.wsG64b, h.nG);
+  grow(h.wsT32, h.L1.nrows_pad);
+  grow(h.wsB32, h.L2.nrows_pad);
+  grow(h.wsJ32, h.LJ.nrows_pad);
+  grow(h.wsG32, h.nG);
+  grow(h.wsG32b, h.nG);
+  h.ws_cols = c;
+}
+
+template <class T>
+void op_schur(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, bool w_only) {
+  hipStream_t st = h.stream;
+  ensure_workspace(h, ncols);
+  T* Tb = ws_ptr<T>(h.wsT64, h.wsT32);
+  spmm<T>(h.AIG, X, ldx, Tb, ncols, ncols, st);
+  tile_solve<T>(h.L1, Tb, ncols, ncols, h.trsm_cols, st);
+  if (h.nG == 0) return;
+  NS_TPR_DISPATCH(ncols, (k_schur_epi<T, TPR><<<grid_rows<TPR>(h.nG), 256, 0, st>>>(
+                              h.nG, h.AGG.ptr, h.AGG.col, csr_vals<T>(h.AGG), X, ldx, h.AGI.ptr, h.AGI.col,
+                              csr_vals<T>(h.AGI), Tb, ncols, Y, ldy, ncols, w_only ? 1 : 0)));
+  NS_LAUNCH_CHECK();
+}
+
+template <class T>
+void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int ncols) {
+  hipStream_t st = h.stream;
+  ensure_workspace(h, ncols);
+  T* Bp = ws_ptr<T>(h.wsB64, h.wsB32);
+  T* Gj = ws_ptr<T>(h.wsJ64, h.wsJ32);
+  const int64_t n2pad = h.L2.nrows_pad, nJpad = h.LJ.nrows_pad;
+  if (n2pad) {
+    gather_sub<T>(n2pad, h.l2src, R, ldr, nullptr, static_cast<const T*>(nullptr), 0, Bp, ncols, ncols, st);
+    tile_solve<T>(h.L2, Bp, ncols, ncols, h.trsm_cols, st);
+  }
+  if (nJpad) {
+    gather_sub<T>(nJpad, h.jsrc, R, ldr, n2pad ? &h.AJs : nullptr, Bp, ncols, Gj, ncols, ncols, st);
+    tile_solve<T>(h.LJ, Gj, ncols, ncols, h.trsm_cols, st);
+    if (n2pad) {
+      gather_sub<T>(n2pad, h.l2src, R, ldr, &h.AsJ, Gj, ncols, Bp, ncols, ncols, st);
+      tile_solve<T>(h.L2, Bp, ncols, ncols, h.trsm_cols, st);
+    }
+    scatter<T, T>(nJpad, h.jsrc, Gj, ncols, Out, ldo, ncols, st);
+  }
+  if (n2pad) scatter<T, T>(n2pad, h.l2src, Bp, ncols, Out, ldo, ncols, st);
+}
+
+template <class T>
+void op_interior_solve(Handle& h, const T* X, T* Y, int ncols) {
+  hipStream_t st = h.stream;
+  ensure_workspace(h, ncols);
+  T* Tb = ws_ptr<T>(h.wsT64, h.wsT32);
+  gather_sub<T>(h.L1.nrows_pad, h.icomp, X, ncols, nullptr, static_cast<const T*>(nullptr), 0, Tb, ncols, ncols, st);
+  tile_solve<T>(h.L1, Tb, ncols, ncols, h.trsm_cols, st);
+  scatter<T, T>(h.L1.nrows_pad, h.icomp, Tb, ncols, Y, ncols, ncols, st);
+}
+
+// explicit instantiations
+template void op_schur<double>(Handle&, const double*, int64_t, double*, int64_t, int, bool);
+template void op_schur<float>(Handle&, const float*, int64_t, float*, int64_t, int, bool);
+template void op_gamma_solve<double>(Handle&, const double*, int64_t, double*, int64_t, int);
+template void op_gamma_solve<float>(Handle&, const float*, int64_t, float*, int64_t, int);
+template void op_interior_solve<double>(Handle&, const double*, double*, int);
+template void op_interior_solve<float>(Handle&, const float*, float*, int);
+
+// generic helpers used by the solver
+template <class T>
+void gather_rows(int64_t nrows, const int32_t* src, const T* R, int64_t ldr, T* Out, int64_t ldo, int ncols,
+                 hipStream_t st) {
+  gather_sub<T>(nrows, src, R, ldr, nullptr, static_cast<const T*>(nullptr), 0, Out, ldo, ncols, st);
+}
+template <class T, class U>
+void scatter_rows(int64_t nrows, const int32_t* dst, const T* B, int64_t ldb, U* Out, int64_t ldo, int ncols,
+                  hipStream_t st) {
+  scatter<T, U>(nrows, dst, B, ldb, Out, ldo, ncols, st);
+}
+template <class T>
+void csr_mult(const Csr& A, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, hipStream_t st) {
+  spmm<T>(A, X, ldx, Y, ldy, ncols, st);
+}
+template void gather_rows<double>(int64_t, const int32_t*, const double*, int64_t, double*, int64_t, int, hipStream_t);
+template void gather_rows<float>(int64_t, const int32_t*, const float*, int64_t, float*, int64_t, int, hipStream_t);
+template void scatter_rows<double, double>(int64_t, const int32_t*, const double*, int64_t, double*, int64_t, int,
+                                           hipStream_t);
+template void csr_mult<double>(const Csr&, const double*, int64_t, double*, int64_t, int, hipStream_t);
+template void csr_mult<float>(const Csr&, const float*, int64_t, float*, int64_t, int, hipStream_t);
+
+}  // namespace ns

@@ -1,0 +1,420 @@
+// Dense tile kernels for gfx950: batched left-looking Cholesky of the subdomain
+// blocks (diagonal tile factor + triangular inverse in LDS, off-diagonal
+// updates and panels on MFMA) and the batched forward/backward triangular
+// solves with many right-hand sides used by every Schur-operator application.
+//
+// The paper factorises the diagonal blocks of A_I "cheaply in parallel" with
+// a direct method (section on Schur complement preconditioners); here every
+// block of every size is factorised in the same sequence of launches.
+#include "ns_internal.h"
+
+namespace ns {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct MF;
+// MFMA 16x16x4 operand layout on gfx950 (lane l of a 64-wide wave):
+//   A fragment: A[l % 16][l / 16]   (16 rows x 4 k)
+//   B fragment: B[l / 16][l % 16]   (4 k x 16 cols)
+//   D, FP32: element v of lane l is D[4 * (l / 16) + v][l % 16]
+//   D, FP64: element v of lane l is D[4 * v + l / 16][l % 16]
+// (measured on the device; row(q, v) below gives the D row for q = l / 16).
+template <>
+struct MF<double> {
+  using acc_t = v4d;
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int q, int v) { return 4 * v + q; }
+};
+template <>
+struct MF<float> {
+  using acc_t = v4f;
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int q, int v) { return 4 * q + v; }
+};
+
+constexpr int LDT = TILE + 1;  // LDS row stride of a staged tile (bank spread)
+
+__device__ __forceinline__ int64_t tile_index(int nt, int i, int j) {  // tile (i, j), i >= j
+  return int64_t(j) * nt - int64_t(j) * (j - 1) / 2 + (i - j);
+}
+
+template <class T>
+__device__ __forceinline__ void load_tile_lds(T* s, const T* __restrict__ g) {
+  for (int e = threadIdx.x; e < TILE2; e += blockDim.x) s[(e >> 6) * LDT + (e & 63)] = g[e];
+}
+template <class T>
+__device__ __forceinline__ void store_tile_lds(T* __restrict__ g, const T* s) {
+  for (int e = threadIdx.x; e < TILE2; e += blockDim.x) g[e] = s[(e >> 6) * LDT + (e & 63)];
+}
+
+// Cholesky of the TILE x TILE lower triangle held in LDS (column-major, LDT).
+__device__ void potrf_lds(double* s, int blk, int jt, int* err) {
+  for (int c = 0; c < TILE; ++c) {
+    if (threadIdx.x == 0) {
+      double d = s[c * LDT + c];
+      if (!(d > 0.0)) {
+        if (atomicCAS(err, 0, 1) == 0) {
+          err[1] = blk;
+          err[2] = jt * TILE + c;
+        }
+        d = 1.0;
+      }
+      s[c * LDT + c] = sqrt(d);
+    }
+    __syncthreads();
+    const double dinv = 1.0 / s[c * LDT + c];
+    for (int r = c + 1 + threadIdx.x; r < TILE; r += blockDim.x) s[c * LDT + r] *= dinv;
+    __syncthreads();
+    const int m = TILE - 1 - c;
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      const int q = c + 1 + idx / m, r = c + 1 + idx % m;
+      if (r >= q) s[q * LDT + r] -= s[c * LDT + r] * s[c * LDT + q];
+    }
+    __syncthreads();
+  }
+}
+
+// x = inverse of the lower triangular tile s (both LDS, column-major, LDT).
+__device__ void trtri_lds(const double* s, double* x) {
+  const int c = threadIdx.x;
+  if (c < TILE) {
+    for (int r = 0; r < c; ++r) x[c * LDT + r] = 0.0;
+    x[c * LDT + c] = 1.0 / s[c * LDT + c];
+    for (int r = c + 1; r < TILE; ++r) {
+      double acc = 0.0;
+      for (int m = c; m < r; ++m) acc += s[m * LDT + r] * x[c * LDT + m];
+      x[c * LDT + r] = -acc / s[r * LDT + r];
+    }
+  }
+  __syncthreads();
+}
+
+// Left-looking update of tile column j: C_ij = A_ij - sum_{l<j} L_il L_jl^T for
+// i >= j; the diagonal workgroup then factorises C_jj and inverts L_jj.
+__global__ __launch_bounds__(256) void k_chol_update(int j, const int* __restrict__ nt_arr,
+                                                     const int64_t* __restrict__ foff,
+                                                     const int64_t* __restrict__ ioff, double* __restrict__ L,
+                                                     double* __restrict__ Linv, int* err) {
+  __shared__ double sA[TILE * LDT];
+  __shared__ double sB[TILE * LDT];
+  const int b = blockIdx.y;
+  const int nt = nt_arr[b];
+  const int i = j + blockIdx.x;
+  if (j >= nt || i >= nt) return;
+  double* Lb = L + foff[b];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+  v4d acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  for (int l = 0; l < j; ++l) {
+    __syncthreads();
+    load_tile_lds(sA, Lb + tile_index(nt, i, l) * TILE2);
+    load_tile_lds(sB, Lb + tile_index(nt, j, l) * TILE2);
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < TILE; kk += 4) {
+      const int kr = (kk + (lane >> 4)) * LDT + (lane & 15);
+      const double a0 = sA[kr + r0], a1 = sA[kr + r0 + 16];
+      const double b0 = sB[kr + c0], b1 = sB[kr + c0 + 16];
+      acc00 = MF<double>::mma(a0, b0, acc00);
+      acc01 = MF<double>::mma(a0, b1, acc01);
+      acc10 = MF<double>::mma(a1, b0, acc10);
+      acc11 = MF<double>::mma(a1, b1, acc11);
+    }
+  }
+  __syncthreads();
+  double* Tij = Lb + tile_index(nt, i, j) * TILE2;
+  load_tile_lds(sA, Tij);
+  __syncthreads();
+  {
+    const int cb = c0 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rb = r0 + MF<double>::row(lane >> 4, v);
+      sA[(cb)*LDT + rb] -= acc00[v];
+      sA[(cb + 16) * LDT + rb] -= acc01[v];
+      sA[(cb)*LDT + rb + 16] -= acc10[v];
+      sA[(cb + 16) * LDT + rb + 16] -= acc11[v];
+    }
+  }
+  __syncthreads();
+  if (i != j) {
+    store_tile_lds(Tij, sA);
+    return;
+  }
+  potrf_lds(sA, b, j, err);
+  trtri_lds(sA, sB);
+  for (int e = threadIdx.x; e < TILE2; e += blockDim.x) {
+    const int c = e >> 6, r = e & 63;
+    Tij[e] = r >= c ? sA[c * LDT + r] : 0.0;
+  }
+  store_tile_lds(Linv + ioff[b] + int64_t(j) * TILE2, sB);
+}
+
+// Panel: L_ij = C_ij L_jj^{-T} = C_ij * (L_jj^{-1})^T for i > j.
+__global__ __launch_bounds__(256) void k_chol_panel(int j, const int* __restrict__ nt_arr,
+                                                    const int64_t* __restrict__ foff,
+                                                    const int64_t* __restrict__ ioff, double* __restrict__ L,
+                                                    const double* __restrict__ Linv) {
+  __shared__ double sA[TILE * LDT];
+  __shared__ double sB[TILE * LDT];
+  const int b = blockIdx.y;
+  const int nt = nt_arr[b];
+  const int i = j + 1 + blockIdx.x;
+  if (i >= nt) return;
+  double* Tij = L + foff[b] + tile_index(nt, i, j) * TILE2;
+  load_tile_lds(sA, Tij);
+  load_tile_lds(sB, Linv + ioff[b] + int64_t(j) * TILE2);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+  v4d acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+#pragma unroll 4
+  for (int kk = 0; kk < TILE; kk += 4) {
+    const int kr = (kk + (lane >> 4)) * LDT + (lane & 15);
+    const double a0 = sA[kr + r0], a1 = sA[kr + r0 + 16];
+    const double b0 = sB[kr + c0], b1 = sB[kr + c0 + 16];
+    acc00 = MF<double>::mma(a0, b0, acc00);
+    acc01 = MF<double>::mma(a0, b1, acc01);
+    acc10 = MF<double>::mma(a1, b0, acc10);
+    acc11 = MF<double>::mma(a1, b1, acc11);
+  }
+  __syncthreads();
+  {
+    const int cb = c0 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rb = r0 + MF<double>::row(lane >> 4, v);
+      sA[(cb)*LDT + rb] = acc00[v];
+      sA[(cb + 16) * LDT + rb] = acc01[v];
+      sA[(cb)*LDT + rb + 16] = acc10[v];
+      sA[(cb + 16) * LDT + rb + 16] = acc11[v];
+    }
+  }
+  __syncthreads();
+  store_tile_lds(Tij, sA);
+}
+
+// --------------------------------------------------------------------------
+// Batched triangular solves with many right-hand sides.
+//
+// One workgroup owns CW columns of one block's padded right-hand side and
+// walks its tile rows; wave w computes rows [16w, 16w+16) of each 64-row tile
+// with CW/16 MFMA column blocks.  Workgroup ids are mapped so that all column
+// chunks of a block run on the same XCD (ids are dispatched round-robin over
+// the 8 XCDs) and share that XCD's L2 while they stream the block's factor.
+
+__device__ __forceinline__ void map_block_chunk(int nblk, int& b, int& chunk) {
+  const int nbp8 = (nblk + 7) >> 3;  // blocks per XCD
+  const int g = blockIdx.x;
+  const int xcd = g & 7, slot = g >> 3;
+  b = xcd + 8 * (slot % nbp8);
+  chunk = slot / nbp8;
+}
+
+template <class T, int CW>
+__device__ __forceinline__ void load_rows(T* sY, const T* __restrict__ g, int64_t ldb, int c0, int ncols) {
+  for (int e = threadIdx.x; e < TILE * CW; e += blockDim.x) {
+    const int r = e / CW, c = e % CW;
+    sY[r * (CW + 1) + c] = (c0 + c < ncols) ? g[int64_t(r) * ldb + c0 + c] : T(0);
+  }
+}
+
+template <class T, int CW, bool FWD>
+__global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ nt_arr,
+                                              const int64_t* __restrict__ foff, const int64_t* __restrict__ ioff,
+                                              const int64_t* __restrict__ roff, const T* __restrict__ L,
+                                              const T* __restrict__ Linv, T* __restrict__ B, int64_t ldb,
+                                              int ncols) {
+  using acc_t = typename MF<T>::acc_t;
+  constexpr int NB = CW / 16;
+  constexpr int YP = CW + 1;
+  __shared__ T sL[TILE * LDT];
+  __shared__ T sY[TILE * YP];
+  int b, chunk;
+  map_block_chunk(nblk, b, chunk);
+  if (b >= nblk) return;
+  const int c0 = chunk * CW;
+  if (c0 >= ncols) return;
+  const int nt = nt_arr[b];
+  T* Bb = B + roff[b] * ldb;
+  const T* Lb = L + foff[b];
+  const T* Ib = Linv + ioff[b];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rl = lane & 15, kq = lane >> 4;
+  for (int step = 0; step < nt; ++step) {
+    const int i = FWD ? step : nt - 1 - step;
+    acc_t acc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc[q] = acc_t{0, 0, 0, 0};
+    const int l0 = FWD ? 0 : i + 1, l1 = FWD ? i : nt;
+    for (int l = l0; l < l1; ++l) {
+      __syncthreads();
+      load_tile_lds(sL, Lb + (FWD ? tile_index(nt, i, l) : tile_index(nt, l, i)) * TILE2);
+      load_rows<T, CW>(sY, Bb + int64_t(l) * TILE * ldb, ldb, c0, ncols);
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < TILE; kk += 4) {
+        // FWD: A = L_il (row 16w+rl, col kk+kq); BWD: A = L_li^T
+        const T a = FWD ? sL[(kk + kq) * LDT + 16 * w + rl] : sL[(16 * w + rl) * LDT + kk + kq];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[q] = MF<T>::mma(a, sY[(kk + kq) * YP + 16 * q + rl], acc[q]);
+      }
+    }
+    __syncthreads();
+    load_tile_lds(sL, Ib + int64_t(i) * TILE2);
+    load_rows<T, CW>(sY, Bb + int64_t(i) * TILE * ldb, ldb, c0, ncols);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sY[(16 * w + MF<T>::row(kq, v)) * YP + 16 * q + rl] -= acc[q][v];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc[q] = acc_t{0, 0, 0, 0};
+#pragma unroll 4
+    for (int kk = 0; kk < TILE; kk += 4) {
+      const T a = FWD ? sL[(kk + kq) * LDT + 16 * w + rl] : sL[(16 * w + rl) * LDT + kk + kq];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) acc[q] = MF<T>::mma(a, sY[(kk + kq) * YP + 16 * q + rl], acc[q]);
+    }
+    T* Bi = Bb + int64_t(i) * TILE * ldb;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int col = c0 + 16 * q + rl;
+      if (col < ncols) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Bi[int64_t(16 * w + MF<T>::row(kq, v)) * ldb + col] = acc[q][v];
+      }
+    }
+  }
+}
+
+__global__ void k_tile_export(int nt, int nb, const double* __restrict__ Lb, double* __restrict__ out) {
+  const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= int64_t(nb) * nb) return;
+  const int c = int(idx / nb), r = int(idx % nb);
+  double v = 0.0;
+  if (r >= c) v = Lb[tile_index(nt, r >> 6, c >> 6) * TILE2 + (c & 63) * TILE + (r & 63)];
+  out[idx] = v;
+}
+
+__global__ void k_to_fp32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = float(a[i]);
+}
+
+template <class T, int CW>
+void launch_trsm(const TileLevel& lv, T* B, int64_t ldb, int ncols, const T* L, const T* Linv, hipStream_t st) {
+  const int nchunk = (ncols + CW - 1) / CW;
+  const int nbp8 = (lv.nblk + 7) / 8;
+  const int grid = nbp8 * 8 * nchunk;
+  k_trsm<T, CW, true><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L, Linv, B, ldb, ncols);
+  NS_LAUNCH_CHECK();
+  k_trsm<T, CW, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L, Linv, B, ldb, ncols);
+  NS_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void tile_cholesky(TileLevel& lv, int* d_err, hipStream_t st) {
+  if (lv.nblk == 0) return;
+  for (int j = 0; j < lv.max_nt; ++j) {
+    dim3 g1(lv.max_nt - j, lv.nblk);
+    k_chol_update<<<g1, 256, 0, st>>>(j, lv.nt, lv.foff, lv.ioff, lv.L64, lv.Linv64, d_err);
+    NS_LAUNCH_CHECK();
+    if (lv.max_nt - j - 1 > 0) {
+      dim3 g2(lv.max_nt - j - 1, lv.nblk);
+      k_chol_panel<<<g2, 256, 0, st>>>(j, lv.nt, lv.foff, lv.ioff, lv.L64, lv.Linv64);
+      NS_LAUNCH_CHECK();
+    }
+  }
+}
+
+void tile_make_fp32(TileLevel& lv, hipStream_t st) {
+  if (lv.nblk == 0) return;
+  lv.L32.alloc(lv.f_elems);
+  lv.Linv32.alloc(lv.i_elems);
+  k_to_fp32<<<2048, 256, 0, st>>>(lv.L64, lv.L32, lv.f_elems);
+  NS_LAUNCH_CHECK();
+  k_to_fp32<<<1024, 256, 0, st>>>(lv.Linv64, lv.Linv32, lv.i_elems);
+  NS_LAUNCH_CHECK();
+}
+
+template <class T>
+void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st) {
+  if (lv.nblk == 0 || ncols == 0) return;
+  const T* L;
+  const T* Li;
+  if constexpr (sizeof(T) == 8) {
+    L = lv.L64.p;
+    Li = lv.Linv64.p;
+  } else {
+    L = lv.L32.p;
+    Li = lv.Linv32.p;
+  }
+  if (cw <= 0) cw = ncols <= 16 ? 16 : 32;
+  if (cw == 16)
+    launch_trsm<T, 16>(lv, B, ldb, ncols, L, Li, st);
+  else if (cw == 32)
+    launch_trsm<T, 32>(lv, B, ldb, ncols, L, Li, st);
+  else
+    launch_trsm<T, 64>(lv, B, ldb, ncols, L, Li, st);
+}
+
+template void tile_solve<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t);
+template void tile_solve<float>(const TileLevel&, float*, int64_t, int, int, hipStream_t);
+
+void tile_export(const TileLevel& lv, int block, double* out, hipStream_t st) {
+  const int nb = lv.h_nb[block];
+  const int64_t n2 = int64_t(nb) * nb;
+  const int grid = int((n2 + 255) / 256);
+  k_tile_export<<<grid, 256, 0, st>>>(lv.h_nt[block], nb, lv.L64.p + lv.h_foff[block], out);
+  NS_LAUNCH_CHECK();
+}
+
+void TileLevel::layout(const std::vector<int>& sizes) {
+  nblk = int(sizes.size());
+  h_nb = sizes;
+  h_nt.resize(nblk);
+  h_foff.resize(nblk);
+  h_ioff.resize(nblk);
+  h_roff.resize(nblk);
+  int64_t f = 0, iv = 0, r = 0;
+  max_nt = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int t = (sizes[b] + TILE - 1) / TILE;
+    h_nt[b] = t;
+    h_foff[b] = f;
+    h_ioff[b] = iv;
+    h_roff[b] = r;
+    f += tri_tiles(t) * TILE2;
+    iv += int64_t(t) * TILE2;
+    r += int64_t(t) * TILE;
+    if (t > max_nt) max_nt = t;
+  }
+  f_elems = f;
+  i_elems = iv;
+  nrows_pad = r;
+  if (nblk == 0) return;
+  nt.alloc(nblk);
+  nb.alloc(nblk);
+  foff.alloc(nblk);
+  ioff.alloc(nblk);
+  roff.alloc(nblk);
+  NS_HIP(hipMemcpy(nt.p, h_nt.data(), nblk * sizeof(int), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(nb.p, h_nb.data(), nblk * sizeof(int), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(foff.p, h_foff.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(ioff.p, h_ioff.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(roff.p, h_roff.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice));
+  L64.alloc(f_elems);
+  Linv64.alloc(i_elems);
+}
+
+}  // namespace ns

@@ -1,0 +1,316 @@
+"""ctypes binding of libnystrom_schur.so (the C ABI in include/nystrom_schur.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  Functions carry the C names; device arrays are torch CUDA tensors
+(their data_ptr() is passed), work is ordered on torch's current stream.
+There is no CPU fallback: a missing library raises at load time.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnystrom_schur.so")
+_lib = None
+
+NS_OK, NS_ERR_INVALID_ARG, NS_ERR_NOT_SPD, NS_ERR_OOM, NS_ERR_HIP, NS_ERR_NOT_CONVERGED, NS_ERR_BREAKDOWN = range(7)
+NS_FP64, NS_FP32 = 0, 1
+NS_APPLY_M2, NS_APPLY_ADEF2 = 0, 1
+
+STATUS_NAMES = {
+    0: "NS_OK",
+    1: "NS_ERR_INVALID_ARG",
+    2: "NS_ERR_NOT_SPD",
+    3: "NS_ERR_OOM",
+    4: "NS_ERR_HIP",
+    5: "NS_ERR_NOT_CONVERGED",
+    6: "NS_ERR_BREAKDOWN",
+}
+
+EXPORTED = [
+    "nystrom_schur_setup",
+    "nystrom_schur_apply",
+    "nystrom_schur_pcg_solve",
+    "nystrom_schur_schur_apply",
+    "nystrom_schur_interface_solve",
+    "nystrom_schur_interior_solve",
+    "nystrom_schur_export_factor",
+    "nystrom_schur_get_sizes",
+    "nystrom_schur_get_lowrank",
+    "nystrom_schur_destroy",
+    "nystrom_schur_last_error",
+]
+
+
+class NsOptions(ctypes.Structure):
+    _fields_ = [
+        ("k", c_int32),
+        ("p", c_int32),
+        ("tol_inner", c_double),
+        ("eig_thresh_rel", c_double),
+        ("orth_drop_rel", c_double),
+        ("max_inner_iters", c_int32),
+        ("prec_inner", c_int32),
+        ("apply_mode", c_int32),
+        ("trsm_cols", c_int32),
+        ("omega", c_void_p),
+        ("proposal", c_void_p),
+        ("accept_tol", c_double),
+        ("stream", c_void_p),
+    ]
+
+
+class NsSetupInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int64),
+        ("n_interior", c_int64),
+        ("n_gamma", c_int64),
+        ("n_junction", c_int64),
+        ("n_sub", c_int32),
+        ("n_level2_blocks", c_int32),
+        ("k_eff", c_int32),
+        ("it_inner", c_int32),
+        ("inner_converged", c_int32),
+        ("proposal_accepted", c_int32),
+        ("bad_block", c_int32),
+        ("bad_col", c_int32),
+        ("inner_relres", c_double),
+        ("t_extract", c_double),
+        ("t_factor", c_double),
+        ("t_inner", c_double),
+        ("t_nystrom", c_double),
+        ("t_total", c_double),
+    ]
+
+
+class NsSolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("it_pcg", c_int32),
+        ("converged", c_int32),
+        ("relres_schur", c_double),
+        ("relres_true", c_double),
+        ("t_solve", c_double),
+        ("res_hist", POINTER(c_double)),
+        ("res_hist_cap", c_int32),
+    ]
+
+
+class NsError(RuntimeError):
+    def __init__(self, status, message, info=None):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.info = info
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the in-tree HIP library (build it with paper_2101_12164_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {_LIB_PATH} is missing (run paper_2101_12164_amd.build)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    H = c_void_p
+    lib.nystrom_schur_setup.argtypes = [c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(NsOptions),
+                                        POINTER(H), POINTER(NsSetupInfo)]
+    lib.nystrom_schur_setup.restype = c_int32
+    lib.nystrom_schur_apply.argtypes = [H, c_void_p, c_void_p, c_int32]
+    lib.nystrom_schur_apply.restype = c_int32
+    lib.nystrom_schur_pcg_solve.argtypes = [H, c_void_p, c_void_p, c_double, c_int32, POINTER(NsSolveInfo)]
+    lib.nystrom_schur_pcg_solve.restype = c_int32
+    for name in ("nystrom_schur_schur_apply", "nystrom_schur_interface_solve", "nystrom_schur_interior_solve"):
+        f = getattr(lib, name)
+        f.argtypes = [H, c_void_p, c_void_p, c_int32, c_int32]
+        f.restype = c_int32
+    lib.nystrom_schur_export_factor.argtypes = [H, c_int32, c_void_p]
+    lib.nystrom_schur_export_factor.restype = c_int32
+    lib.nystrom_schur_get_sizes.argtypes = [H, POINTER(c_int64)]
+    lib.nystrom_schur_get_sizes.restype = c_int32
+    lib.nystrom_schur_get_lowrank.argtypes = [H, c_void_p, c_void_p]
+    lib.nystrom_schur_get_lowrank.restype = c_int32
+    lib.nystrom_schur_destroy.argtypes = [H]
+    lib.nystrom_schur_destroy.restype = None
+    lib.nystrom_schur_last_error.argtypes = [H]
+    lib.nystrom_schur_last_error.restype = c_char_p
+    _lib = lib
+    return lib
+
+
+def _dev(t: torch.Tensor, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(status, handle, info=None):
+    if status != NS_OK:
+        msg = load_library().nystrom_schur_last_error(handle).decode()
+        raise NsError(status, msg, info)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _setup_info_dict(si: NsSetupInfo) -> dict:
+    return {f: getattr(si, f) for f, _ in NsSetupInfo._fields_}
+
+
+def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_inner=0.1, eig_thresh_rel=1e-10,
+                        orth_drop_rel=0.0, max_inner_iters=500, prec_inner=NS_FP64, apply_mode=NS_APPLY_M2,
+                        trsm_cols=0, proposal=None, accept_tol=0.2):
+    """Returns (handle, info dict).  row_ptr int64, col_idx int32, val float64, part int32, omega float64
+    (n_gamma x (k+p), row-major), all CUDA tensors."""
+    lib = load_library()
+    n = row_ptr.numel() - 1
+    nnz = val.numel()
+    opt = NsOptions()
+    opt.k, opt.p = int(k), int(p)
+    opt.tol_inner = tol_inner
+    opt.eig_thresh_rel = eig_thresh_rel
+    opt.orth_drop_rel = orth_drop_rel
+    opt.max_inner_iters = max_inner_iters
+    opt.prec_inner = prec_inner
+    opt.apply_mode = apply_mode
+    opt.trsm_cols = trsm_cols
+    opt.omega = _dev(omega, torch.float64, "omega") if omega is not None else None
+    opt.proposal = _dev(proposal, torch.float64, "proposal") if proposal is not None else None
+    opt.accept_tol = accept_tol
+    opt.stream = _stream()
+    h = c_void_p()
+    info = NsSetupInfo()
+    st = lib.nystrom_schur_setup(n, nnz, _dev(row_ptr, torch.int64, "row_ptr"), _dev(col_idx, torch.int32, "col_idx"),
+                                 _dev(val, torch.float64, "val"), _dev(part, torch.int32, "part"), ctypes.byref(opt),
+                                 ctypes.byref(h), ctypes.byref(info))
+    _check(st, None, _setup_info_dict(info))
+    return h, _setup_info_dict(info)
+
+
+def nystrom_schur_apply(handle, r: torch.Tensor, z: torch.Tensor = None):
+    lib = load_library()
+    ncols = 1 if r.dim() == 1 else r.shape[1]
+    if z is None:
+        z = torch.empty_like(r)
+    _check(lib.nystrom_schur_apply(handle, _dev(r, torch.float64, "r"), _dev(z, torch.float64, "z"), ncols), handle)
+    return z
+
+
+def nystrom_schur_pcg_solve(handle, b: torch.Tensor, x: torch.Tensor = None, rtol=1e-8, maxit=1000,
+                            hist_cap=0, raise_on_not_converged=True):
+    lib = load_library()
+    if x is None:
+        x = torch.empty_like(b)
+    info = NsSolveInfo()
+    hist = (c_double * max(hist_cap, 1))()
+    info.res_hist = ctypes.cast(hist, POINTER(c_double))
+    info.res_hist_cap = hist_cap
+    st = lib.nystrom_schur_pcg_solve(handle, _dev(b, torch.float64, "b"), _dev(x, torch.float64, "x"), rtol, maxit,
+                                     ctypes.byref(info))
+    out = dict(it_pcg=info.it_pcg, converged=info.converged, relres_schur=info.relres_schur,
+               relres_true=info.relres_true, t_solve=info.t_solve, status=st)
+    if hist_cap:
+        out["res_hist"] = [hist[i] for i in range(min(hist_cap, info.it_pcg + 1))]
+    if st == NS_ERR_NOT_CONVERGED and not raise_on_not_converged:
+        return x, out
+    _check(st, handle, out)
+    return x, out
+
+
+def _op(name, handle, X, prec, out_rows=None):
+    lib = load_library()
+    ncols = 1 if X.dim() == 1 else X.shape[1]
+    Y = torch.empty_like(X)
+    _check(getattr(lib, name)(handle, _dev(X, torch.float64, "X"), _dev(Y, torch.float64, "Y"), ncols, prec), handle)
+    return Y
+
+
+def nystrom_schur_schur_apply(handle, X, prec=NS_FP64):
+    return _op("nystrom_schur_schur_apply", handle, X, prec)
+
+
+def nystrom_schur_interface_solve(handle, X, prec=NS_FP64):
+    return _op("nystrom_schur_interface_solve", handle, X, prec)
+
+
+def nystrom_schur_interior_solve(handle, X, prec=NS_FP64):
+    return _op("nystrom_schur_interior_solve", handle, X, prec)
+
+
+def nystrom_schur_get_sizes(handle) -> dict:
+    lib = load_library()
+    out = (c_int64 * 8)()
+    _check(lib.nystrom_schur_get_sizes(handle, out), handle)
+    keys = ["n", "n_interior", "n_gamma", "n_sub", "n_junction", "n_level2_blocks", "k_eff", "nb0"]
+    return dict(zip(keys, list(out)))
+
+
+def nystrom_schur_export_factor(handle, block: int, nb: int, device="cuda"):
+    lib = load_library()
+    L = torch.empty((nb, nb), dtype=torch.float64, device=device)
+    _check(lib.nystrom_schur_export_factor(handle, block, _dev(L, torch.float64, "L")), handle)
+    return L.t()  # stored column-major
+
+
+def nystrom_schur_get_lowrank(handle, device="cuda"):
+    lib = load_library()
+    sz = nystrom_schur_get_sizes(handle)
+    ke, ng = sz["k_eff"], sz["n_gamma"]
+    Z = torch.empty((ng, max(ke, 1)), dtype=torch.float64, device=device)
+    S = torch.empty(max(ke, 1), dtype=torch.float64, device=device)
+    _check(lib.nystrom_schur_get_lowrank(handle, _dev(Z, torch.float64, "Z"), _dev(S, torch.float64, "Sigma")),
+           handle)
+    return Z[:, :ke], S[:ke]
+
+
+def nystrom_schur_destroy(handle):
+    load_library().nystrom_schur_destroy(handle)
+
+
+def nystrom_schur_last_error(handle=None) -> str:
+    return load_library().nystrom_schur_last_error(handle).decode()
+
+
+class NystromSchur:
+    """Owning wrapper: builds the preconditioner on construction, frees it on close()."""
+
+    def __init__(self, row_ptr, col_idx, val, part, **kw):
+        self.handle, self.setup_info = nystrom_schur_setup(row_ptr, col_idx, val, part, **kw)
+
+    def apply(self, r):
+        return nystrom_schur_apply(self.handle, r)
+
+    def solve(self, b, rtol=1e-8, maxit=1000, hist_cap=0, raise_on_not_converged=True):
+        return nystrom_schur_pcg_solve(self.handle, b, rtol=rtol, maxit=maxit, hist_cap=hist_cap,
+                                       raise_on_not_converged=raise_on_not_converged)
+
+    def sizes(self):
+        return nystrom_schur_get_sizes(self.handle)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            nystrom_schur_destroy(self.handle)
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
