@@ -14,7 +14,8 @@ notes of the repository):
   the product of Algorithm alg:prec1 steps 2-4 (``inner='formA'`` runs
   those steps literally).
 * block stopping rule: max over columns of ||R_j|| / ||F_j|| <= eps_SI.
-* breakdown-free orthonormalisation: thin SVD, keep sigma_i > delta*sigma_max.
+* breakdown-free orthonormalisation: thin SVD, keep sigma_i > delta*sigma_max
+  with delta = 1e-6 (the drop tolerance of Ji & Li's method is not given).
 * Nystrom threshold: eigenvalues of sym(Omega^T Y) >= eps_rel * max eigenvalue.
 * Algorithm alg:prec1 step 10 reads U = Q W(:, 1:k) (Q from the QR of Y, as in
   Algorithm alg:nystrom); eigenvalues of T sorted descending; k' = min(k, r).
@@ -361,7 +362,7 @@ class NystromSchurOracle:
     literal step 3).  ``k = 0`` gives the first-level preconditioner S_1.
     """
 
-    def __init__(self, n, row_ptr, col, val, part, *, k, p, omega, tol_inner=0.1, eps_rel=1e-10, delta=1e-8,
+    def __init__(self, n, row_ptr, col, val, part, *, k, p, omega, tol_inner=0.1, eps_rel=1e-10, delta=1e-6,
                  maxit_inner=500, factor="dense", apply_mode="M2", inner="shifted", gamma_factor=None):
         self.dbbd = DBBD(n, row_ptr, col, val, part)
         self.ops = Operators(self.dbbd, factor=factor, gamma_factor=gamma_factor)
