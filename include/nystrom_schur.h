@@ -78,12 +78,18 @@ typedef struct {
   double tol_inner;          /* eps_SI: block-CG relative tolerance (max over columns) [0.1]     */
   double eig_thresh_rel;     /* Nystrom threshold on eig(C) relative to its largest [1e-10]      */
   double orth_drop_rel;      /* block-CG drop tolerance on singular values rel. to the largest
-                                [1e-8 with FP64 inner work, 1e-3 with FP32]                      */
+                                [1e-6 with FP64 inner work, 1e-5 with FP32]                      */
   int32_t max_inner_iters;   /* block-CG iteration cap [500]                                      */
   int32_t prec_inner;        /* ns_prec of the inner block CG (factors, block vectors) [NS_FP64] */
   int32_t apply_mode;        /* ns_apply_mode [NS_APPLY_M2]                                       */
   int32_t trsm_cols;         /* columns per workgroup in the batched triangular solves, 16/32/64;
-                                0 = automatic (autotuned table)                                   */
+                                0 = automatic                                                     */
+  int32_t schur_mode;        /* how S_Gamma X is applied: 0 = automatic (local blocks), 1 =
+                                A_Gamma X - A_GammaI (L L^T)^{-1} A_IGamma X with the interior
+                                Cholesky factors (two triangular sweeps per apply), 2 = explicit
+                                local Schur blocks S_j = (L_j^{-1} B_j)^T (L_j^{-1} B_j), one dense
+                                block per subdomain over the interface nodes it touches, applied
+                                as one batched GEMM                                              */
   const double* omega;       /* DEVICE, n_gamma x (k+p) row-major Gaussian sketch in interface
                                 order (Algorithm alg:prec1 step 1).  Required when k > 0.         */
   const double* proposal;    /* DEVICE, optional n_gamma x k starting subspace (learned); NULL =
@@ -188,6 +194,23 @@ ns_status nystrom_schur_get_sizes(ns_handle h, int64_t* out);
 /* Copy the low-rank term: Z (DEVICE, n_gamma x k_eff row-major, interface
  * order) and Sigma (DEVICE, k_eff).  Either pointer may be NULL. */
 ns_status nystrom_schur_get_lowrank(ns_handle h, double* Z, double* Sigma);
+
+/* Opt-in kernel timing for performance measurement (callers: benchmarks).
+ * enable != 0 brackets every launch of the main kernel families with HIP
+ * events on the launching stream (adds a few microseconds per launch);
+ * calling it also resets the accumulated totals.  Process-wide. */
+void nystrom_schur_kernel_timing(int32_t enable);
+
+/* Accumulated device time (milliseconds, from the events), launch count and
+ * algorithmic work (bytes the method must move, flops it must compute: the
+ * unpadded dense factor once per sweep, no re-reads) of one kernel family
+ * since timing was enabled.  family: "chol_update", "chol_panel",
+ * "trsm_interior_f64", "trsm_interior_f32", "trsm_interface_f64",
+ * "trsm_interface_f32" (forward and backward sweeps), "schur_epi", "spmm".
+ * Waits for the recorded events.  All outputs are HOST pointers (may be NULL).
+ * NS_ERR_INVALID_ARG for an unknown family. */
+ns_status nystrom_schur_kernel_stats(const char* family, double* total_ms, int64_t* launches, double* bytes,
+                                     double* flops);
 
 /* Release everything the handle owns.  Idempotent on NULL. */
 void nystrom_schur_destroy(ns_handle h);

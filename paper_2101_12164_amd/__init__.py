@@ -6,10 +6,14 @@ bordered block diagonal form (Al Daas, Rees & Scott, arXiv:2101.12164).
 
 from .nystrom_schur import (  # noqa: F401
     EXPORTED,
+    KERNEL_FAMILIES,
     NS_APPLY_ADEF2,
     NS_APPLY_M2,
     NS_FP32,
     NS_FP64,
+    NS_SCHUR_AUTO,
+    NS_SCHUR_LOCAL,
+    NS_SCHUR_TRIANGULAR,
     NsError,
     NystromSchur,
     library_path,
@@ -21,6 +25,8 @@ from .nystrom_schur import (  # noqa: F401
     nystrom_schur_get_sizes,
     nystrom_schur_interface_solve,
     nystrom_schur_interior_solve,
+    nystrom_schur_kernel_stats,
+    nystrom_schur_kernel_timing,
     nystrom_schur_last_error,
     nystrom_schur_pcg_solve,
     nystrom_schur_schur_apply,

@@ -14,7 +14,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnystrom_schur.so")
-SOURCES = ["tile_kernels.hip", "sparse_kernels.hip", "vec_kernels.hip", "small_kernels.hip", "ns_solver.hip"]
+SOURCES = [
+    "tile_kernels.hip", "sparse_kernels.hip", "vec_kernels.hip", "small_kernels.hip", "ns_solver.hip", "ktimer.hip",
+    "local_schur.hip"
+]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [

@@ -1,0 +1,124 @@
+// Opt-in per-kernel timing with HIP events (for live roofline measurement).
+// When enabled, every launch of a timed kernel family is bracketed by two
+// events on its stream; totals are resolved lazily when statistics are read.
+#include <cstring>
+#include <mutex>
+
+#include "../../include/nystrom_schur.h"
+#include "ns_internal.h"
+
+namespace ns {
+namespace {
+
+const char* kFamilyNames[KF_COUNT] = {"chol_update",        "chol_panel",         "trsm_interior_f64",
+                                      "trsm_interior_f32",  "trsm_interface_f64", "trsm_interface_f32",
+                                      "schur_epi",          "spmm",               "local_schur_form",
+                                      "local_schur_apply_f64", "local_schur_apply_f32"};
+
+struct Rec {
+  hipEvent_t a, b;
+  int fam;
+  double bytes, flops;
+};
+
+struct KTimer {
+  std::mutex mu;
+  bool on = false;
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double total_ms[KF_COUNT] = {};
+  int64_t count[KF_COUNT] = {};
+  double bytes[KF_COUNT] = {};
+  double flops[KF_COUNT] = {};
+};
+
+KTimer& timer() {
+  static KTimer* t = new KTimer();  // process lifetime
+  return *t;
+}
+
+hipEvent_t get_event(KTimer& t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  NS_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void resolve(KTimer& t) {
+  for (Rec& r : t.pending) {
+    NS_HIP(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    NS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    t.total_ms[r.fam] += ms;
+    t.count[r.fam] += 1;
+    t.bytes[r.fam] += r.bytes;
+    t.flops[r.fam] += r.flops;
+    t.pool.push_back(r.a);
+    t.pool.push_back(r.b);
+  }
+  t.pending.clear();
+}
+
+}  // namespace
+
+KScope::KScope(int fam_, hipStream_t st_, double bytes_, double flops_)
+    : fam(fam_), st(st_), bytes(bytes_), flops(flops_) {
+  KTimer& t = timer();
+  on = t.on;
+  if (!on) return;
+  std::lock_guard<std::mutex> g(t.mu);
+  a = get_event(t);
+  b = get_event(t);
+  NS_HIP(hipEventRecord(a, st));
+}
+
+KScope::~KScope() {
+  if (!on) return;
+  KTimer& t = timer();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (hipEventRecord(b, st) == hipSuccess) t.pending.push_back(Rec{a, b, fam, bytes, flops});
+}
+
+}  // namespace ns
+
+extern "C" {
+
+void nystrom_schur_kernel_timing(int32_t enable) {
+  ns::KTimer& t = ns::timer();
+  std::lock_guard<std::mutex> g(t.mu);
+  try {
+    ns::resolve(t);
+  } catch (...) {
+  }
+  std::memset(t.total_ms, 0, sizeof(t.total_ms));
+  std::memset(t.count, 0, sizeof(t.count));
+  std::memset(t.bytes, 0, sizeof(t.bytes));
+  std::memset(t.flops, 0, sizeof(t.flops));
+  t.on = enable != 0;
+}
+
+ns_status nystrom_schur_kernel_stats(const char* family, double* total_ms, int64_t* launches, double* bytes,
+                                     double* flops) {
+  ns::KTimer& t = ns::timer();
+  std::lock_guard<std::mutex> g(t.mu);
+  try {
+    ns::resolve(t);
+  } catch (const ns::Error& e) {
+    return ns_status(e.status);
+  }
+  for (int f = 0; f < ns::KF_COUNT; ++f)
+    if (family && std::strcmp(family, ns::kFamilyNames[f]) == 0) {
+      if (total_ms) *total_ms = t.total_ms[f];
+      if (launches) *launches = t.count[f];
+      if (bytes) *bytes = t.bytes[f];
+      if (flops) *flops = t.flops[f];
+      return NS_OK;
+    }
+  return NS_ERR_INVALID_ARG;
+}
+
+}  // extern "C"

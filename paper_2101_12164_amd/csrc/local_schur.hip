@@ -1,0 +1,495 @@
+// Explicit local Schur complements.  For every subdomain j let Gamma_j be the
+// interface nodes coupled to block j and B_j = A_{I_j, Gamma_j}.  Then
+//   A_GammaI A_I^{-1} A_IGamma = sum_j E_j^T S_j E_j,   S_j = W_j^T W_j,
+//   W_j = L_j^{-1} B_j,
+// with E_j selecting the rows Gamma_j (the Schur complement of eq.
+// schur_complement assembled block by block, never as one global matrix).
+// Each application of S_Gamma is then a gather, one batched GEMM S_j X_j on
+// MFMA, and a deterministic gather-reduce into A_Gamma X - sum_j E_j^T (...).
+#include <algorithm>
+
+#include "ns_handle.h"
+#include "ns_vec.h"
+
+namespace ns {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct MFL;
+template <>
+struct MFL<double> {
+  using acc_t = v4d;
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int q, int v) { return 4 * v + q; }
+};
+template <>
+struct MFL<float> {
+  using acc_t = v4f;
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int q, int v) { return 4 * q + v; }
+};
+
+// Mark the interface columns touched by each block: flag[j * nG + g] = 1.
+__global__ void k_mark(int64_t nrows, const int32_t* __restrict__ rblk, const int64_t* __restrict__ ptr,
+                       const int32_t* __restrict__ col, int64_t nG, int* __restrict__ flag) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int j = rblk[r];
+  if (j < 0) return;
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) flag[int64_t(j) * nG + col[e]] = 1;
+}
+
+__global__ void k_row_block(const int* __restrict__ nt, const int64_t* __restrict__ roff, int32_t* __restrict__ rblk) {
+  const int j = blockIdx.y;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nt[j] * TILE) rblk[roff[j] + r] = j;
+}
+
+// One workgroup per block: count (mode 0) or compact (mode 1) the flags in
+// ascending interface order: cidx[j nG + g] = local index, glist[off_j + c] = g.
+__global__ __launch_bounds__(1024) void k_compact(int64_t nG, const int* __restrict__ flag, int* __restrict__ cnt,
+                                                  const int64_t* __restrict__ goff, int32_t* __restrict__ cidx,
+                                                  int32_t* __restrict__ glist, int mode) {
+  __shared__ int s[1024];
+  __shared__ int base;
+  const int j = blockIdx.x;
+  const int* f = flag + int64_t(j) * nG;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int64_t g0 = 0; g0 < nG; g0 += 1024) {
+    const int64_t g = g0 + threadIdx.x;
+    const int v = g < nG ? f[g] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int t = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    const int incl = s[threadIdx.x];
+    if (mode == 1 && g < nG) {
+      const int c = base + incl - v;
+      cidx[int64_t(j) * nG + g] = v ? c : -1;
+      if (v) glist[goff[j] + c] = int32_t(g);
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) base += s[1023];
+    __syncthreads();
+  }
+  if (mode == 0 && threadIdx.x == 0) cnt[j] = base;
+}
+
+// B (padded interior rows x ldb) = A_IGamma restricted to each block's Gamma_j columns.
+__global__ void k_fill_B(int64_t nrows, const int32_t* __restrict__ rblk, const int64_t* __restrict__ ptr,
+                         const int32_t* __restrict__ col, const double* __restrict__ val, int64_t nG,
+                         const int32_t* __restrict__ cidx, double* __restrict__ B, int64_t ldb) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int j = rblk[r];
+  if (j < 0) return;
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) B[r * ldb + cidx[int64_t(j) * nG + col[e]]] = val[e];
+}
+
+// Batched C_j = A_j^T B_j on MFMA.  A_j: K_j x M_j, B_j: K_j x N (row-major,
+// leading dimensions lda_j / ldb_j), C_j: M_j x N (ld ldc_j).  Output tile
+// 64 x NC per workgroup; K in chunks of 32 rows staged through LDS with a
+// one-deep register prefetch.  With sym != 0 (A = B, square C) only tiles on
+// or below the diagonal are computed and each is also written transposed.
+struct GemmBatch {
+  const int* M;         // rows of C per block
+  const int* K;         // reduction length per block
+  const int64_t* aoff;  // element offset of A_j
+  const int64_t* lda;   // leading dimension of A_j
+  const int64_t* boff;  // offset of B_j = boff[j] * bscale
+  int64_t bscale;
+  int64_t ldb;          // leading dimension of every B_j
+  const int64_t* coff;  // offset of C_j = coff[j] * cscale
+  int64_t cscale;
+  const int64_t* ldc;   // per block, or NULL: ldc_s
+  int64_t ldc_s;
+};
+
+template <class T, int NC>
+__global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restrict__ A, const T* __restrict__ B,
+                                                 T* __restrict__ C, int N, int sym) {
+  using acc_t = typename MFL<T>::acc_t;
+  constexpr int KC = 32;
+  constexpr int AP = 64 + 1, BP = NC + 1;
+  constexpr int MW = NC == 64 ? 2 : 1;  // MFMA row blocks per wave
+  __shared__ T sA[KC * AP];
+  __shared__ T sB[KC * BP];
+  const int j = blockIdx.z;
+  const int M = g.M[j], K = g.K[j];
+  const int tm = blockIdx.y, tn = blockIdx.x;
+  const int m0 = tm * 64, n0 = tn * NC;
+  if (m0 >= M || n0 >= (sym ? M : N)) return;
+  if (sym && tn * NC > tm * 64 + 63) return;  // strictly above the diagonal
+  const T* Aj = A + g.aoff[j];
+  const T* Bj = B + g.boff[j] * g.bscale;
+  const int64_t lda = g.lda[j], ldb = g.ldb;
+  const int Nj = sym ? M : N;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rl = lane & 15, kq = lane >> 4;
+  // wave layout: NC == 64: wave w owns rows [32*(w>>1), +32) x cols [32*(w&1), +32)
+  //              NC == 16: wave w owns rows [16 w, +16) x cols [0, 16)
+  const int wr = NC == 64 ? 32 * (w >> 1) : 16 * w;
+  const int wc = NC == 64 ? 32 * (w & 1) : 0;
+  acc_t acc[MW][MW];
+#pragma unroll
+  for (int a = 0; a < MW; ++a)
+#pragma unroll
+    for (int b = 0; b < MW; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  constexpr int PA = KC * 64 / 256, PB = KC * NC / 256;
+  T ra[PA], rb[PB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      const int e = threadIdx.x + 256 * q, kk = e / 64, m = e % 64;
+      ra[q] = (k0 + kk < K && m0 + m < M) ? Aj[int64_t(k0 + kk) * lda + m0 + m] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int e = threadIdx.x + 256 * q, kk = e / NC, n = e % NC;
+      rb[q] = (k0 + kk < K && n0 + n < Nj) ? Bj[int64_t(k0 + kk) * ldb + n0 + n] : T(0);
+    }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PA; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      sA[(e / 64) * AP + e % 64] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < PB; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      sB[(e / NC) * BP + e % NC] = rb[q];
+    }
+    if (k0 + KC < K) gload(k0 + KC);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      T a[MW], b[MW];
+#pragma unroll
+      for (int q = 0; q < MW; ++q) {
+        a[q] = sA[(kk + kq) * AP + wr + 16 * q + rl];
+        b[q] = sB[(kk + kq) * BP + wc + 16 * q + rl];
+      }
+#pragma unroll
+      for (int x = 0; x < MW; ++x)
+#pragma unroll
+        for (int y = 0; y < MW; ++y) acc[x][y] = MFL<T>::mma(a[x], b[y], acc[x][y]);
+    }
+  }
+  T* Cj = C + g.coff[j] * g.cscale;
+  const int64_t ldc = g.ldc ? g.ldc[j] : g.ldc_s;
+#pragma unroll
+  for (int x = 0; x < MW; ++x)
+#pragma unroll
+    for (int y = 0; y < MW; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + wr + 16 * x + MFL<T>::row(kq, v);
+        const int c = n0 + wc + 16 * y + rl;
+        if (r < M && c < Nj) {
+          Cj[int64_t(r) * ldc + c] = acc[x][y][v];
+          if (sym && tm != tn) Cj[int64_t(c) * ldc + r] = acc[x][y][v];
+        }
+      }
+}
+
+// Contributor lists: for each interface row g the stacked positions p with
+// glist[p] == g, in ascending p (deterministic summation order).
+__global__ void k_contrib_count(int64_t npos, const int32_t* __restrict__ glist, int64_t* __restrict__ ptr1) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= npos) return;
+  const int g = glist[p];
+  if (g >= 0) atomicAdd(reinterpret_cast<unsigned long long*>(&ptr1[g + 1]), 1ull);
+}
+
+__global__ void k_contrib_fill(int64_t npos, const int32_t* __restrict__ glist, const int64_t* __restrict__ ptr,
+                               int* __restrict__ fillc, int32_t* __restrict__ col) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= npos) return;
+  const int g = glist[p];
+  if (g < 0) return;
+  const int slot = atomicAdd(&fillc[g], 1);
+  col[ptr[g] + slot] = int32_t(p);
+}
+
+__global__ void k_contrib_sort(int64_t nG, const int64_t* __restrict__ ptr, int32_t* __restrict__ col,
+                               double* __restrict__ v64, float* __restrict__ v32) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= nG) return;
+  const int64_t a = ptr[g], b = ptr[g + 1];
+  for (int64_t i = a + 1; i < b; ++i) {  // insertion sort (a handful of entries per row)
+    const int32_t x = col[i];
+    int64_t k = i - 1;
+    while (k >= a && col[k] > x) {
+      col[k + 1] = col[k];
+      --k;
+    }
+    col[k + 1] = x;
+  }
+  for (int64_t i = a; i < b; ++i) {
+    v64[i] = 1.0;
+    v32[i] = 1.0f;
+  }
+}
+
+__global__ void k_to_fp32_ls(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = float(a[i]);
+}
+
+template <class T, int TPR>
+__global__ __launch_bounds__(256) void k_schur_epi_local(int64_t nrows, const int64_t* __restrict__ pG,
+                                                         const int32_t* __restrict__ cG, const T* __restrict__ vG,
+                                                         const T* __restrict__ X, int64_t ldx,
+                                                         const int64_t* __restrict__ pC, const int32_t* __restrict__ cC,
+                                                         const T* __restrict__ Yg, int64_t ldy_g, T* __restrict__ Y,
+                                                         int64_t ldy, int ncols, int w_only) {
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
+  const int lane = threadIdx.x % TPR;
+  if (row >= nrows) return;
+  for (int c = lane; c < ncols; c += TPR) {
+    T a = T(0), w = T(0);
+    if (!w_only)
+      for (int64_t e = pG[row]; e < pG[row + 1]; ++e) a += vG[e] * X[int64_t(cG[e]) * ldx + c];
+    for (int64_t e = pC[row]; e < pC[row + 1]; ++e) w += Yg[int64_t(cC[e]) * ldy_g + c];
+    Y[row * ldy + c] = w_only ? w : a - w;
+  }
+}
+
+template <class T, int TPR>
+__global__ __launch_bounds__(256) void k_gather_ls(int64_t nrows, const int32_t* __restrict__ src,
+                                                   const T* __restrict__ R, int64_t ldr, T* __restrict__ Out,
+                                                   int64_t ldo, int ncols) {
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
+  const int lane = threadIdx.x % TPR;
+  if (row >= nrows) return;
+  const int s = src[row];
+  for (int c = lane; c < ncols; c += TPR) Out[row * ldo + c] = s >= 0 ? R[int64_t(s) * ldr + c] : T(0);
+}
+
+template <class T>
+void launch_gemm(const LocalSchur& ls, const T* A, const T* B, T* C, int N, hipStream_t st, bool sym,
+                 const GemmBatch& g, int maxM) {
+  if (maxM == 0) return;
+  const int tilesM = (maxM + 63) / 64;
+  if (N <= 16 && !sym) {
+    dim3 grid(1, tilesM, ls.nblk);
+    k_gemm_tn<T, 16><<<grid, 256, 0, st>>>(g, A, B, C, N, 0);
+  } else {
+    const int tilesN = sym ? tilesM : (N + 63) / 64;
+    dim3 grid(tilesN, tilesM, ls.nblk);
+    k_gemm_tn<T, 64><<<grid, 256, 0, st>>>(g, A, B, C, N, sym ? 1 : 0);
+  }
+  NS_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void local_schur_build(Handle& h) {
+  hipStream_t st = h.stream;
+  LocalSchur& ls = h.LS;
+  const TileLevel& lv = h.L1;
+  const int nb = lv.nblk;
+  const int64_t nG = h.nG, nIp = lv.nrows_pad;
+  ls.nblk = nb;
+  // row -> block map of the padded interior rows
+  DBuf<int32_t> rblk;
+  rblk.alloc(nIp);
+  NS_HIP(hipMemsetAsync(rblk.p, 0xFF, nIp * sizeof(int32_t), st));
+  k_row_block<<<dim3((lv.max_nt * TILE + 255) / 256, nb), 256, 0, st>>>(lv.nt, lv.roff, rblk);
+  NS_LAUNCH_CHECK();
+  DBuf<int> flag, cnt;
+  DBuf<int32_t> cidx;
+  flag.alloc(int64_t(nb) * nG);
+  cnt.alloc(nb);
+  cidx.alloc(int64_t(nb) * nG);
+  NS_HIP(hipMemsetAsync(flag.p, 0, int64_t(nb) * nG * sizeof(int), st));
+  k_mark<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, h.AIG.ptr, h.AIG.col, nG, flag);
+  NS_LAUNCH_CHECK();
+  k_compact<<<nb, 1024, 0, st>>>(nG, flag, cnt, nullptr, nullptr, nullptr, 0);
+  NS_LAUNCH_CHECK();
+  ls.h_m.resize(nb);
+  NS_HIP(hipMemcpyAsync(ls.h_m.data(), cnt.p, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipStreamSynchronize(st));
+  // stacked layouts: Gamma_j lists padded to 64 rows; S_j with ld = padded m_j
+  std::vector<int64_t> goff(nb), soff(nb), sld(nb), woff(nb), wld(nb), xld(nb), yld(nb);
+  std::vector<int> Kv(nb);
+  int64_t gp = 0, sp = 0;
+  ls.max_m = 0;
+  for (int j = 0; j < nb; ++j) {
+    const int m = ls.h_m[j], mp = (m + 63) / 64 * 64;
+    goff[j] = gp;
+    soff[j] = sp;
+    sld[j] = mp > 0 ? mp : 1;
+    gp += mp;
+    sp += int64_t(mp) * mp;
+    ls.max_m = std::max(ls.max_m, m);
+    Kv[j] = lv.h_nt[j] * TILE;
+  }
+  ls.npos = gp;
+  ls.s_elems = sp;
+  const int64_t ldw = std::max(ls.max_m, 1);
+  for (int j = 0; j < nb; ++j) {
+    woff[j] = lv.h_roff[j] * ldw;
+    wld[j] = ldw;
+  }
+  ls.goff.alloc(nb);
+  NS_HIP(hipMemcpy(ls.goff.p, goff.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+  ls.glist.alloc(gp > 0 ? gp : 1);
+  NS_HIP(hipMemsetAsync(ls.glist.p, 0xFF, ls.glist.n * sizeof(int32_t), st));
+  k_compact<<<nb, 1024, 0, st>>>(nG, flag, cnt, ls.goff, cidx, ls.glist, 1);
+  NS_LAUNCH_CHECK();
+  // W = L^{-1} B_j for all blocks (forward sweep only), then S_j = W_j^T W_j
+  DBuf<double> W;
+  W.alloc(nIp * ldw);
+  NS_HIP(hipMemsetAsync(W.p, 0, nIp * ldw * sizeof(double), st));
+  k_fill_B<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, h.AIG.ptr, h.AIG.col, h.AIG.val64, nG, cidx, W,
+                                                        ldw);
+  NS_LAUNCH_CHECK();
+  tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st);
+  // per-block metadata for the batched GEMMs
+  auto up = [&](DBuf<int64_t>& d, const std::vector<int64_t>& v) {
+    d.alloc(nb);
+    NS_HIP(hipMemcpy(d.p, v.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+  };
+  ls.M.alloc(nb);
+  ls.K.alloc(nb);
+  ls.Kg.alloc(nb);
+  (void)xld;
+  (void)yld;
+  NS_HIP(hipMemcpy(ls.M.p, ls.h_m.data(), nb * sizeof(int), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(ls.K.p, Kv.data(), nb * sizeof(int), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(ls.Kg.p, ls.h_m.data(), nb * sizeof(int), hipMemcpyHostToDevice));
+  up(ls.soff, soff);
+  up(ls.sld, sld);
+  up(ls.woff, woff);
+  up(ls.wld, wld);
+  ls.S64.alloc(sp > 0 ? sp : 1);
+  NS_HIP(hipMemsetAsync(ls.S64.p, 0, ls.S64.n * sizeof(double), st));
+  {
+    // B_j = W_j: offset woff[j], common leading dimension ldw
+    GemmBatch g{ls.M, ls.K, ls.woff, ls.wld, ls.woff, 1, ldw, ls.soff, 1, ls.sld, 0};
+    double fl = 0;
+    for (int j = 0; j < nb; ++j) fl += 2.0 * Kv[j] * ls.h_m[j] * (ls.h_m[j] + 1) / 2;
+    KScope ks(KF_LS_FORM, st, double(nIp) * ldw * 8.0, fl);
+    launch_gemm<double>(ls, W.p, W.p, ls.S64.p, 0, st, true, g, ls.max_m);
+  }
+  if (h.prec_inner) {
+    ls.S32.alloc(ls.S64.n);
+    k_to_fp32_ls<<<2048, 256, 0, st>>>(ls.S64, ls.S32, ls.S64.n);
+    NS_LAUNCH_CHECK();
+  }
+  // contributor CSR (interface row -> stacked positions), values 1
+  Csr& C = ls.contrib;
+  C.nrows = nG;
+  C.ptr.alloc(nG + 1);
+  NS_HIP(hipMemsetAsync(C.ptr.p, 0, (nG + 1) * sizeof(int64_t), st));
+  k_contrib_count<<<unsigned((gp + 255) / 256), 256, 0, st>>>(gp, ls.glist, C.ptr);
+  NS_LAUNCH_CHECK();
+  scan_inclusive(C.ptr.p + 1, nG, st);
+  NS_HIP(hipMemcpyAsync(&C.nnz, C.ptr.p + nG, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipStreamSynchronize(st));
+  C.col.alloc(C.nnz > 0 ? C.nnz : 1);
+  C.val64.alloc(C.nnz > 0 ? C.nnz : 1);
+  C.val32.alloc(C.nnz > 0 ? C.nnz : 1);
+  DBuf<int> fillc;
+  fillc.alloc(nG);
+  NS_HIP(hipMemsetAsync(fillc.p, 0, nG * sizeof(int), st));
+  k_contrib_fill<<<unsigned((gp + 255) / 256), 256, 0, st>>>(gp, ls.glist, C.ptr, fillc, C.col);
+  NS_LAUNCH_CHECK();
+  k_contrib_sort<<<unsigned((nG + 255) / 256), 256, 0, st>>>(nG, C.ptr, C.col, C.val64, C.val32);
+  NS_LAUNCH_CHECK();
+  // algorithmic work of one apply (per column): S_j read once, 2 m_j^2 flops
+  ls.alg_bytes = 0;
+  ls.alg_flops = 0;
+  for (int j = 0; j < nb; ++j) {
+    ls.alg_bytes += double(ls.h_m[j]) * ls.h_m[j];
+    ls.alg_flops += 2.0 * ls.h_m[j] * ls.h_m[j];
+  }
+  NS_HIP(hipStreamSynchronize(st));
+  ls.built = true;
+}
+
+template <class T>
+void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, bool w_only) {
+  hipStream_t st = h.stream;
+  LocalSchur& ls = h.LS;
+  ensure_local_workspace(h, ncols);
+  T *Xg, *Yg;
+  const T* S;
+  if constexpr (sizeof(T) == 8) {
+    Xg = ls.wsX64.p;
+    Yg = ls.wsY64.p;
+    S = ls.S64.p;
+  } else {
+    Xg = ls.wsX32.p;
+    Yg = ls.wsY32.p;
+    S = ls.S32.p;
+  }
+  const int64_t np = ls.npos;
+#define NS_TPR_DISPATCH_LS(ncols, BODY) \
+  do {                                  \
+    if ((ncols) == 1) {                 \
+      constexpr int TPR = 1;            \
+      BODY;                             \
+    } else if ((ncols) <= 16) {         \
+      constexpr int TPR = 16;           \
+      BODY;                             \
+    } else {                            \
+      constexpr int TPR = 64;           \
+      BODY;                             \
+    }                                   \
+  } while (0)
+  NS_TPR_DISPATCH_LS(ncols, (k_gather_ls<T, TPR><<<unsigned((np * TPR + 255) / 256), 256, 0, st>>>(
+                                 np, ls.glist, X, ldx, Xg, ncols, ncols)));
+  NS_LAUNCH_CHECK();
+  {
+    // X_j / Y_j: stacked rows goff[j], leading dimension ncols
+    GemmBatch g{ls.M, ls.Kg, ls.soff, ls.sld, ls.goff, ncols, ncols, ls.goff, ncols, nullptr, ncols};
+    KScope ks(sizeof(T) == 8 ? KF_LS_APPLY64 : KF_LS_APPLY32, st,
+              ls.alg_bytes * sizeof(T) + 2.0 * np * ncols * sizeof(T), ls.alg_flops * ncols);
+    launch_gemm<T>(ls, S, Xg, Yg, ncols, st, false, g, ls.max_m);
+  }
+  const T* vG;
+  if constexpr (sizeof(T) == 8)
+    vG = h.AGG.val64.p;
+  else
+    vG = h.AGG.val32.p;
+  NS_TPR_DISPATCH_LS(ncols, (k_schur_epi_local<T, TPR><<<unsigned((h.nG * TPR + 255) / 256), 256, 0, st>>>(
+                                 h.nG, h.AGG.ptr, h.AGG.col, vG, X, ldx, ls.contrib.ptr, ls.contrib.col, Yg, ncols,
+                                 Y, ldy, ncols, w_only ? 1 : 0)));
+  NS_LAUNCH_CHECK();
+#undef NS_TPR_DISPATCH_LS
+}
+
+void ensure_local_workspace(Handle& h, int64_t ncols) {
+  LocalSchur& ls = h.LS;
+  if (ncols <= ls.ws_cols) return;
+  const int64_t n = ls.npos > 0 ? ls.npos * ncols : 1;
+  if (h.prec_inner) {
+    ls.wsX32.alloc(n);
+    ls.wsY32.alloc(n);
+  }
+  ls.wsX64.alloc(n);
+  ls.wsY64.alloc(n);
+  ls.ws_cols = ncols;
+}
+
+template void op_schur_local<double>(Handle&, const double*, int64_t, double*, int64_t, int, bool);
+template void op_schur_local<float>(Handle&, const float*, int64_t, float*, int64_t, int, bool);
+
+}  // namespace ns

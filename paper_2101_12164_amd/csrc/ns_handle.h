@@ -4,6 +4,29 @@
 #include "../../include/nystrom_schur.h"
 #include "ns_internal.h"
 
+namespace ns {
+
+// Explicit local Schur complements S_j = (L_j^{-1} B_j)^T (L_j^{-1} B_j), one
+// dense m_j x m_j block per subdomain (m_j = interface nodes coupled to it).
+struct LocalSchur {
+  bool built = false;
+  int nblk = 0, max_m = 0;
+  int64_t npos = 0, s_elems = 0;  // stacked (padded) interface rows, S elements
+  std::vector<int> h_m;
+  DBuf<int> M, K, Kg;                          // per block: m_j, padded rows, m_j
+  DBuf<int64_t> goff, soff, sld, woff, wld;    // stacked offsets / leading dimensions
+  DBuf<int32_t> glist;                         // stacked position -> interface index (-1 pad)
+  DBuf<double> S64;
+  DBuf<float> S32;
+  Csr contrib;  // interface row -> stacked positions (values 1)
+  DBuf<double> wsX64, wsY64;
+  DBuf<float> wsX32, wsY32;
+  int64_t ws_cols = 0;
+  double alg_bytes = 0, alg_flops = 0;  // per apply and column: sum m_j^2 entries, 2 sum m_j^2 flops
+};
+
+}  // namespace ns
+
 struct ns_handle_s {
   hipStream_t stream = nullptr;
   std::string last_error;
@@ -12,7 +35,7 @@ struct ns_handle_s {
   int64_t n = 0, nnz = 0, nI = 0, nG = 0, nJ = 0;
   int nsub = 0, nl2 = 0;
   int k = 0, p = 0, s = 0, k_eff = 0;
-  int prec_inner = 0, apply_mode = 0, trsm_cols = 0;
+  int prec_inner = 0, apply_mode = 0, trsm_cols = 0, schur_mode = 0;
   double tol_inner = 0.1, eig_rel = 1e-10, drop_rel = 1e-6;
   int max_inner = 500;
 
@@ -31,6 +54,7 @@ struct ns_handle_s {
   ns::Csr AGI;  // rows: interface index;      cols: padded interior rows
   ns::Csr AGG;  // rows: interface index;      cols: interface index
   ns::TileLevel L1;
+  ns::LocalSchur LS;
   // level-2 (exact A_Gamma solve)
   ns::Csr AsJ;  // rows: padded level-2 rows;  cols: junction rows
   ns::Csr AJs;  // rows: padded junction rows; cols: padded level-2 rows
@@ -43,15 +67,15 @@ struct ns_handle_s {
 
   // error flags written by kernels (pinned host-visible copy in hflags)
   ns::DBuf<int> dflags;
-  int* hflags = nullptr;  // pinned
+  int* hflags = nullptr;    // pinned
   double* hscal = nullptr;  // pinned scalars for readbacks
 
   // workspaces (sized at setup)
   ns::DBuf<double> wsT64, wsB64, wsJ64, wsG64, wsG64b;  // interior rhs, level-2 rhs, junction rhs, gathered copies
   ns::DBuf<float> wsT32, wsB32, wsJ32, wsG32, wsG32b;
-  ns::DBuf<double> red;     // reduction partials
-  ns::DBuf<double> small;   // small dense scratch
-  int64_t ws_cols = 0;      // column capacity of the workspaces
+  ns::DBuf<double> red;    // reduction partials
+  ns::DBuf<double> small;  // small dense scratch
+  int64_t ws_cols = 0;     // column capacity of the workspaces
 
   ~ns_handle_s();
 };
@@ -60,12 +84,21 @@ namespace ns {
 
 using Handle = ns_handle_s;
 
+enum SchurMode { SCHUR_AUTO = 0, SCHUR_TRIANGULAR = 1, SCHUR_LOCAL = 2 };
+
 // Workspace management: make sure every per-apply buffer holds ncols columns.
 void ensure_workspace(Handle& h, int64_t ncols);
+void ensure_local_workspace(Handle& h, int64_t ncols);
 
 // Operators on FP64 or FP32 data (blocks row-major, ld = leading dimension).
+// op_schur uses the local Schur blocks when they were built, else the
+// triangular solves with the interior factors (op_schur_tri).
 template <class T>
 void op_schur(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, bool w_only);
+template <class T>
+void op_schur_tri(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, bool w_only);
+template <class T>
+void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, bool w_only);
 template <class T>
 void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int ncols);
 template <class T>
@@ -75,6 +108,7 @@ void op_interior_solve(Handle& h, const T* X, T* Y, int ncols);  // X, Y: n_I x 
 void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
                   const double* val, const int32_t* part);
 void assemble_junction(Handle& h);
+void local_schur_build(Handle& h);
 
 // Generic row gather / scatter and CSR products (row-major blocks).
 template <class T>

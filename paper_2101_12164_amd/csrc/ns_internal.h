@@ -64,6 +64,7 @@ struct DBuf {
 //   Inverse diagonal tiles: nt[b] tiles from element ioff[b].
 //   Padded rows of block b start at row roff[b] of a padded right-hand side.
 struct TileLevel {
+  int role = 0;  // 0: interior blocks, 1: interface blocks (timing family)
   int nblk = 0;
   int max_nt = 0;
   std::vector<int> h_nb, h_nt;
@@ -73,10 +74,43 @@ struct TileLevel {
   DBuf<int64_t> foff, ioff, roff;
   DBuf<double> L64, Linv64;
   DBuf<float> L32, Linv32;
+  // algorithmic work: sum of nb(nb+1)/2, sum of nb^2, sum of nb; per tile column
+  // of the factorisation: update flops, panel flops, bytes
+  double alg_tri = 0, alg_sq = 0, alg_rows = 0;
+  std::vector<double> chol_upd_flops, chol_pan_flops, chol_bytes;
   void layout(const std::vector<int>& sizes);  // host: fills h_*, allocates index arrays + FP64 storage
 };
 
 inline int64_t tri_tiles(int nt) { return int64_t(nt) * (nt + 1) / 2; }
+
+// ---------------------------------------------------------------- kernel timing
+// Families of launches that can be timed with HIP events (opt-in, ABI
+// nystrom_schur_kernel_timing / nystrom_schur_kernel_stats).
+enum KFamily {
+  KF_CHOL_UPDATE = 0,
+  KF_CHOL_PANEL,
+  KF_TRSM_I64,  // interior blocks, FP64
+  KF_TRSM_I32,  // interior blocks, FP32
+  KF_TRSM_G64,  // interface blocks (level 2 and junction), FP64
+  KF_TRSM_G32,
+  KF_SCHUR_EPI,
+  KF_SPMM,
+  KF_LS_FORM,     // local Schur blocks: S_j = W_j^T W_j
+  KF_LS_APPLY64,  // local Schur blocks applied (batched GEMM), FP64
+  KF_LS_APPLY32,
+  KF_COUNT
+};
+// Brackets one launch when timing is on; bytes / flops are the algorithmic
+// work of the launch (what the method must move / compute, no padding).
+struct KScope {
+  int fam;
+  hipStream_t st;
+  double bytes, flops;
+  hipEvent_t a = nullptr, b = nullptr;
+  bool on = false;
+  KScope(int fam, hipStream_t st, double bytes = 0.0, double flops = 0.0);
+  ~KScope();
+};
 
 // ---------------------------------------------------------------- dense tiles
 // Batched Cholesky of all blocks of a level (FP64, in place), with inverted
@@ -88,10 +122,16 @@ void tile_make_fp32(TileLevel& lv, hipStream_t st);
 // row-major with leading dimension ldb, ncols columns).
 template <class T>
 void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st);
+// Forward sweep only: B <- L^{-1} B.
+template <class T>
+void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st);
 // Expand the factor of one block to a dense nb x nb column-major lower matrix.
 void tile_export(const TileLevel& lv, int block, double* out, hipStream_t st);
 
 // ---------------------------------------------------------------- sparse
+// In-place inclusive scan of a[0..m) (int64).  Synchronises st.
+void scan_inclusive(int64_t* a, int64_t m, hipStream_t st);
+
 struct Csr {
   int64_t nrows = 0, nnz = 0;
   DBuf<int64_t> ptr;

@@ -312,6 +312,8 @@ ns_status nystrom_schur_setup(int64_t n, int64_t nnz, const int64_t* row_ptr, co
     h->max_inner = opt->max_inner_iters > 0 ? opt->max_inner_iters : 500;
     h->apply_mode = opt->apply_mode == NS_APPLY_ADEF2 ? 1 : 0;
     h->trsm_cols = opt->trsm_cols;
+    h->schur_mode = opt->schur_mode;
+    if (h->schur_mode < 0 || h->schur_mode > 2) fail(INVALID_ARG, "schur_mode must be 0, 1 or 2");
     if (h->trsm_cols != 0 && h->trsm_cols != 16 && h->trsm_cols != 32 && h->trsm_cols != 64)
       fail(INVALID_ARG, "trsm_cols must be 0, 16, 32 or 64");
     h->dflags.alloc(16);
@@ -326,13 +328,14 @@ ns_status nystrom_schur_setup(int64_t n, int64_t nnz, const int64_t* row_ptr, co
     ev.rec(1);
     tile_cholesky(h->L1, h->dflags.p + 8, h->stream);
     check_chol(*h, 1, info);
+    if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_build(*h);
     tile_cholesky(h->L2, h->dflags.p + 8, h->stream);
     check_chol(*h, 2, info);
     assemble_junction(*h);
     tile_cholesky(h->LJ, h->dflags.p + 8, h->stream);
     check_chol(*h, 3, info);
     if (h->prec_inner) {
-      tile_make_fp32(h->L1, h->stream);
+      if (!h->LS.built) tile_make_fp32(h->L1, h->stream);
       tile_make_fp32(h->L2, h->stream);
       tile_make_fp32(h->LJ, h->stream);
     }

@@ -113,6 +113,7 @@ const T* csr_vals(const Csr& A) {
 template <class T>
 void spmm(const Csr& A, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, hipStream_t st) {
   if (A.nrows == 0 || ncols == 0) return;
+  KScope ks(KF_SPMM, st);
   NS_TPR_DISPATCH(ncols, (k_spmm<T, TPR><<<grid_rows<TPR>(A.nrows), 256, 0, st>>>(
                               A.nrows, A.ptr, A.col, csr_vals<T>(A), X, ldx, Y, ldy, ncols)));
   NS_LAUNCH_CHECK();
@@ -177,6 +178,8 @@ __global__ void k_scan_add(int64_t* a, int64_t m, const int64_t* bsum) {
     if (idx + q < m) a[idx + q] += off;
 }
 
+}  // namespace
+
 void scan_inclusive(int64_t* a, int64_t m, hipStream_t st) {
   if (m <= 0) return;
   const int64_t nb = (m + 4095) / 4096;
@@ -191,6 +194,8 @@ void scan_inclusive(int64_t* a, int64_t m, hipStream_t st) {
   }
   NS_HIP(hipStreamSynchronize(st));  // bsum is freed on return
 }
+
+namespace {
 
 // ----------------------------------------------------------------- extraction
 
@@ -544,6 +549,8 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
   if (h.nI <= 0) fail(INVALID_ARG, "partition has no interior nodes");
   h.L1.layout(nb1);
   h.L2.layout(nb2);
+  h.L2.role = 1;
+  h.LJ.role = 1;
   h.LJ.layout(h.nJ > 0 ? std::vector<int>{int(h.nJ)} : std::vector<int>{});
   DBuf<int64_t> coff1;
   coff1.alloc(h.nsub > 0 ? h.nsub : 1);
@@ -676,12 +683,30 @@ void ensure_workspace(Handle& h, int64_t ncols) {
 
 template <class T>
 void op_schur(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, bool w_only) {
+  if (h.LS.built)
+    op_schur_local<T>(h, X, ldx, Y, ldy, ncols, w_only);
+  else
+    op_schur_tri<T>(h, X, ldx, Y, ldy, ncols, w_only);
+}
+
+// FP32 interior factors are made on first use when the local Schur blocks
+// replaced them inside the inner solve.
+template <class T>
+static void need_l1(Handle& h) {
+  if constexpr (sizeof(T) == 4)
+    if (!h.L1.L32.p) tile_make_fp32(h.L1, h.stream);
+}
+
+template <class T>
+void op_schur_tri(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int ncols, bool w_only) {
   hipStream_t st = h.stream;
+  need_l1<T>(h);
   ensure_workspace(h, ncols);
   T* Tb = ws_ptr<T>(h.wsT64, h.wsT32);
   spmm<T>(h.AIG, X, ldx, Tb, ncols, ncols, st);
   tile_solve<T>(h.L1, Tb, ncols, ncols, h.trsm_cols, st);
   if (h.nG == 0) return;
+  KScope ks(KF_SCHUR_EPI, st);
   NS_TPR_DISPATCH(ncols, (k_schur_epi<T, TPR><<<grid_rows<TPR>(h.nG), 256, 0, st>>>(
                               h.nG, h.AGG.ptr, h.AGG.col, csr_vals<T>(h.AGG), X, ldx, h.AGI.ptr, h.AGI.col,
                               csr_vals<T>(h.AGI), Tb, ncols, Y, ldy, ncols, w_only ? 1 : 0)));
@@ -714,6 +739,7 @@ void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int
 template <class T>
 void op_interior_solve(Handle& h, const T* X, T* Y, int ncols) {
   hipStream_t st = h.stream;
+  need_l1<T>(h);
   ensure_workspace(h, ncols);
   T* Tb = ws_ptr<T>(h.wsT64, h.wsT32);
   gather_sub<T>(h.L1.nrows_pad, h.icomp, X, ncols, nullptr, static_cast<const T*>(nullptr), 0, Tb, ncols, ncols, st);
@@ -724,6 +750,8 @@ void op_interior_solve(Handle& h, const T* X, T* Y, int ncols) {
 // explicit instantiations
 template void op_schur<double>(Handle&, const double*, int64_t, double*, int64_t, int, bool);
 template void op_schur<float>(Handle&, const float*, int64_t, float*, int64_t, int, bool);
+template void op_schur_tri<double>(Handle&, const double*, int64_t, double*, int64_t, int, bool);
+template void op_schur_tri<float>(Handle&, const float*, int64_t, float*, int64_t, int, bool);
 template void op_gamma_solve<double>(Handle&, const double*, int64_t, double*, int64_t, int);
 template void op_gamma_solve<float>(Handle&, const float*, int64_t, float*, int64_t, int);
 template void op_interior_solve<double>(Handle&, const double*, double*, int);

@@ -6,6 +6,8 @@
 // The paper factorises the diagonal blocks of A_I "cheaply in parallel" with
 // a direct method (section on Schur complement preconditioners); here every
 // block of every size is factorised in the same sequence of launches.
+#include <algorithm>
+
 #include "ns_internal.h"
 
 namespace ns {
@@ -226,6 +228,39 @@ __device__ __forceinline__ void load_rows(T* sY, const T* __restrict__ g, int64_
   }
 }
 
+// Register pipeline: each thread holds its share of the next two (tile, rhs
+// rows) pairs while the MFMAs run on the pair staged in LDS, so two global
+// loads per thread stream are always in flight.
+template <class T, int CW>
+struct TrsmStage {
+  static constexpr int PT = TILE2 / 256;      // tile elements per thread
+  static constexpr int PY = TILE * CW / 256;  // rhs elements per thread
+  T t[PT];
+  T y[PY];
+  __device__ __forceinline__ void load(const T* __restrict__ gt, const T* __restrict__ gy, int64_t ldb, int c0,
+                                       int ncols) {
+#pragma unroll
+    for (int q = 0; q < PT; ++q) t[q] = gt[threadIdx.x + 256 * q];
+#pragma unroll
+    for (int q = 0; q < PY; ++q) {
+      const int e = threadIdx.x + 256 * q, r = e / CW, c = e % CW;
+      y[q] = (c0 + c < ncols) ? gy[int64_t(r) * ldb + c0 + c] : T(0);
+    }
+  }
+  __device__ __forceinline__ void store(T* sL, T* sY) const {
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      sL[(e >> 6) * LDT + (e & 63)] = t[q];
+    }
+#pragma unroll
+    for (int q = 0; q < PY; ++q) {
+      const int e = threadIdx.x + 256 * q, r = e / CW, c = e % CW;
+      sY[r * (CW + 1) + c] = y[q];
+    }
+  }
+};
+
 template <class T, int CW, bool FWD>
 __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ nt_arr,
                                               const int64_t* __restrict__ foff, const int64_t* __restrict__ ioff,
@@ -248,23 +283,39 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
   const T* Ib = Linv + ioff[b];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rl = lane & 15, kq = lane >> 4;
+  TrsmStage<T, CW> s0, s1;
   for (int step = 0; step < nt; ++step) {
     const int i = FWD ? step : nt - 1 - step;
     acc_t acc[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) acc[q] = acc_t{0, 0, 0, 0};
-    const int l0 = FWD ? 0 : i + 1, l1 = FWD ? i : nt;
-    for (int l = l0; l < l1; ++l) {
-      __syncthreads();
-      load_tile_lds(sL, Lb + (FWD ? tile_index(nt, i, l) : tile_index(nt, l, i)) * TILE2);
-      load_rows<T, CW>(sY, Bb + int64_t(l) * TILE * ldb, ldb, c0, ncols);
-      __syncthreads();
+    const int l0 = FWD ? 0 : i + 1, nl = FWD ? i : nt - 1 - i;
+    auto tile = [&](int t) { return Lb + (FWD ? tile_index(nt, i, l0 + t) : tile_index(nt, l0 + t, i)) * TILE2; };
+    auto rows = [&](int t) { return Bb + int64_t(l0 + t) * TILE * ldb; };
+    auto mma_stage = [&]() {
 #pragma unroll 4
       for (int kk = 0; kk < TILE; kk += 4) {
         // FWD: A = L_il (row 16w+rl, col kk+kq); BWD: A = L_li^T
         const T a = FWD ? sL[(kk + kq) * LDT + 16 * w + rl] : sL[(16 * w + rl) * LDT + kk + kq];
 #pragma unroll
         for (int q = 0; q < NB; ++q) acc[q] = MF<T>::mma(a, sY[(kk + kq) * YP + 16 * q + rl], acc[q]);
+      }
+    };
+    __syncthreads();  // rows written at the previous step are visible to every thread
+    if (nl > 0) s0.load(tile(0), rows(0), ldb, c0, ncols);
+    if (nl > 1) s1.load(tile(1), rows(1), ldb, c0, ncols);
+    for (int t = 0; t < nl; t += 2) {
+      __syncthreads();
+      s0.store(sL, sY);
+      if (t + 2 < nl) s0.load(tile(t + 2), rows(t + 2), ldb, c0, ncols);
+      __syncthreads();
+      mma_stage();
+      if (t + 1 < nl) {
+        __syncthreads();
+        s1.store(sL, sY);
+        if (t + 3 < nl) s1.load(tile(t + 3), rows(t + 3), ldb, c0, ncols);
+        __syncthreads();
+        mma_stage();
       }
     }
     __syncthreads();
@@ -315,10 +366,21 @@ void launch_trsm(const TileLevel& lv, T* B, int64_t ldb, int ncols, const T* L, 
   const int nchunk = (ncols + CW - 1) / CW;
   const int nbp8 = (lv.nblk + 7) / 8;
   const int grid = nbp8 * 8 * nchunk;
-  k_trsm<T, CW, true><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L, Linv, B, ldb, ncols);
-  NS_LAUNCH_CHECK();
-  k_trsm<T, CW, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L, Linv, B, ldb, ncols);
-  NS_LAUNCH_CHECK();
+  constexpr bool f64 = sizeof(T) == 8;
+  const int fam = lv.role == 0 ? (f64 ? KF_TRSM_I64 : KF_TRSM_I32) : (f64 ? KF_TRSM_G64 : KF_TRSM_G32);
+  // algorithmic work of one triangular sweep: the factor once, the rhs read + written
+  const double bytes = (lv.alg_tri + 2.0 * lv.alg_rows * ncols) * sizeof(T);
+  const double flops = lv.alg_sq * ncols;
+  {
+    KScope ks(fam, st, bytes, flops);
+    k_trsm<T, CW, true><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L, Linv, B, ldb, ncols);
+    NS_LAUNCH_CHECK();
+  }
+  {
+    KScope ks(fam, st, bytes, flops);
+    k_trsm<T, CW, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L, Linv, B, ldb, ncols);
+    NS_LAUNCH_CHECK();
+  }
 }
 
 }  // namespace
@@ -326,10 +388,14 @@ void launch_trsm(const TileLevel& lv, T* B, int64_t ldb, int ncols, const T* L, 
 void tile_cholesky(TileLevel& lv, int* d_err, hipStream_t st) {
   if (lv.nblk == 0) return;
   for (int j = 0; j < lv.max_nt; ++j) {
-    dim3 g1(lv.max_nt - j, lv.nblk);
-    k_chol_update<<<g1, 256, 0, st>>>(j, lv.nt, lv.foff, lv.ioff, lv.L64, lv.Linv64, d_err);
-    NS_LAUNCH_CHECK();
+    {
+      KScope ks(KF_CHOL_UPDATE, st, lv.chol_bytes[j], lv.chol_upd_flops[j]);
+      dim3 g1(lv.max_nt - j, lv.nblk);
+      k_chol_update<<<g1, 256, 0, st>>>(j, lv.nt, lv.foff, lv.ioff, lv.L64, lv.Linv64, d_err);
+      NS_LAUNCH_CHECK();
+    }
     if (lv.max_nt - j - 1 > 0) {
+      KScope ks(KF_CHOL_PANEL, st, 0.0, lv.chol_pan_flops[j]);
       dim3 g2(lv.max_nt - j - 1, lv.nblk);
       k_chol_panel<<<g2, 256, 0, st>>>(j, lv.nt, lv.foff, lv.ioff, lv.L64, lv.Linv64);
       NS_LAUNCH_CHECK();
@@ -368,6 +434,38 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
     launch_trsm<T, 64>(lv, B, ldb, ncols, L, Li, st);
 }
 
+template <class T>
+void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st) {
+  if (lv.nblk == 0 || ncols == 0) return;
+  const T* L;
+  const T* Li;
+  if constexpr (sizeof(T) == 8) {
+    L = lv.L64.p;
+    Li = lv.Linv64.p;
+  } else {
+    L = lv.L32.p;
+    Li = lv.Linv32.p;
+  }
+  if (cw != 16 && cw != 32) cw = 64;
+  const int nbp8 = (lv.nblk + 7) / 8;
+  const double bytes = (lv.alg_tri + 2.0 * lv.alg_rows * ncols) * sizeof(T);
+  const double flops = lv.alg_sq * ncols;
+  KScope ks(lv.role == 0 ? (sizeof(T) == 8 ? KF_TRSM_I64 : KF_TRSM_I32) : (sizeof(T) == 8 ? KF_TRSM_G64 : KF_TRSM_G32),
+            st, bytes, flops);
+  if (cw == 16) {
+    k_trsm<T, 16, true><<<nbp8 * 8 * ((ncols + 15) / 16), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
+                                                                         Li, B, ldb, ncols);
+  } else if (cw == 32) {
+    k_trsm<T, 32, true><<<nbp8 * 8 * ((ncols + 31) / 32), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
+                                                                         Li, B, ldb, ncols);
+  } else {
+    k_trsm<T, 64, true><<<nbp8 * 8 * ((ncols + 63) / 64), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
+                                                                         Li, B, ldb, ncols);
+  }
+  NS_LAUNCH_CHECK();
+}
+
+template void tile_solve_fwd<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t);
 template void tile_solve<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t);
 template void tile_solve<float>(const TileLevel&, float*, int64_t, int, int, hipStream_t);
 
@@ -402,6 +500,33 @@ void TileLevel::layout(const std::vector<int>& sizes) {
   f_elems = f;
   i_elems = iv;
   nrows_pad = r;
+  // algorithmic work (unpadded dense Cholesky of each block)
+  alg_tri = alg_sq = alg_rows = 0;
+  chol_upd_flops.assign(max_nt, 0.0);
+  chol_pan_flops.assign(max_nt, 0.0);
+  chol_bytes.assign(max_nt, 0.0);
+  for (int b = 0; b < nblk; ++b) {
+    const double n = sizes[b];
+    alg_tri += n * (n + 1) / 2;
+    alg_sq += n * n;
+    alg_rows += n;
+    for (int j = 0; j < h_nt[b]; ++j) {
+      const int c0 = j * TILE, c1 = std::min(sizes[b], c0 + TILE);
+      double pairs = 0, diag = 0;
+      for (int c = c0; c < c1; ++c) {
+        pairs += n - c;        // entries (r >= c) of this tile column
+        diag += double(c1 - c);  // entries inside the diagonal tile
+      }
+      const double below = pairs - diag;
+      // columns < c0 update every entry of the tile column: 2 * c0 flops each;
+      // the diagonal tile's own factorisation: sum over its columns of (c1-c)^2
+      double dflops = 0;
+      for (int c = c0; c < c1; ++c) dflops += double(c1 - c) * (c1 - c);
+      chol_upd_flops[j] += 2.0 * c0 * pairs + dflops;
+      chol_pan_flops[j] += below * double(c1 - c0);  // triangular solve of the panel
+      chol_bytes[j] += 2.0 * pairs * sizeof(double);  // each entry read and written once
+    }
+  }
   if (nblk == 0) return;
   nt.alloc(nblk);
   nb.alloc(nblk);

@@ -20,6 +20,7 @@ _lib = None
 NS_OK, NS_ERR_INVALID_ARG, NS_ERR_NOT_SPD, NS_ERR_OOM, NS_ERR_HIP, NS_ERR_NOT_CONVERGED, NS_ERR_BREAKDOWN = range(7)
 NS_FP64, NS_FP32 = 0, 1
 NS_APPLY_M2, NS_APPLY_ADEF2 = 0, 1
+NS_SCHUR_AUTO, NS_SCHUR_TRIANGULAR, NS_SCHUR_LOCAL = 0, 1, 2
 
 STATUS_NAMES = {
     0: "NS_OK",
@@ -41,9 +42,15 @@ EXPORTED = [
     "nystrom_schur_export_factor",
     "nystrom_schur_get_sizes",
     "nystrom_schur_get_lowrank",
+    "nystrom_schur_kernel_timing",
+    "nystrom_schur_kernel_stats",
     "nystrom_schur_destroy",
     "nystrom_schur_last_error",
 ]
+
+KERNEL_FAMILIES = ["chol_update", "chol_panel", "trsm_interior_f64", "trsm_interior_f32", "trsm_interface_f64",
+                   "trsm_interface_f32", "schur_epi", "spmm", "local_schur_form", "local_schur_apply_f64",
+                   "local_schur_apply_f32"]
 
 
 class NsOptions(ctypes.Structure):
@@ -57,6 +64,7 @@ class NsOptions(ctypes.Structure):
         ("prec_inner", c_int32),
         ("apply_mode", c_int32),
         ("trsm_cols", c_int32),
+        ("schur_mode", c_int32),
         ("omega", c_void_p),
         ("proposal", c_void_p),
         ("accept_tol", c_double),
@@ -136,6 +144,11 @@ def load_library() -> ctypes.CDLL:
     lib.nystrom_schur_get_sizes.restype = c_int32
     lib.nystrom_schur_get_lowrank.argtypes = [H, c_void_p, c_void_p]
     lib.nystrom_schur_get_lowrank.restype = c_int32
+    lib.nystrom_schur_kernel_timing.argtypes = [c_int32]
+    lib.nystrom_schur_kernel_timing.restype = None
+    lib.nystrom_schur_kernel_stats.argtypes = [c_char_p, POINTER(c_double), POINTER(c_int64), POINTER(c_double),
+                                               POINTER(c_double)]
+    lib.nystrom_schur_kernel_stats.restype = c_int32
     lib.nystrom_schur_destroy.argtypes = [H]
     lib.nystrom_schur_destroy.restype = None
     lib.nystrom_schur_last_error.argtypes = [H]
@@ -170,7 +183,7 @@ def _setup_info_dict(si: NsSetupInfo) -> dict:
 
 def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_inner=0.1, eig_thresh_rel=1e-10,
                         orth_drop_rel=0.0, max_inner_iters=500, prec_inner=NS_FP64, apply_mode=NS_APPLY_M2,
-                        trsm_cols=0, proposal=None, accept_tol=0.2):
+                        trsm_cols=0, schur_mode=0, proposal=None, accept_tol=0.2):
     """Returns (handle, info dict).  row_ptr int64, col_idx int32, val float64, part int32, omega float64
     (n_gamma x (k+p), row-major), all CUDA tensors."""
     lib = load_library()
@@ -185,6 +198,7 @@ def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_in
     opt.prec_inner = prec_inner
     opt.apply_mode = apply_mode
     opt.trsm_cols = trsm_cols
+    opt.schur_mode = schur_mode
     opt.omega = _dev(omega, torch.float64, "omega") if omega is not None else None
     opt.proposal = _dev(proposal, torch.float64, "proposal") if proposal is not None else None
     opt.accept_tol = accept_tol
@@ -272,6 +286,21 @@ def nystrom_schur_get_lowrank(handle, device="cuda"):
     _check(lib.nystrom_schur_get_lowrank(handle, _dev(Z, torch.float64, "Z"), _dev(S, torch.float64, "Sigma")),
            handle)
     return Z[:, :ke], S[:ke]
+
+
+def nystrom_schur_kernel_timing(enable: bool):
+    """Turn per-kernel HIP-event timing on/off (and reset the totals)."""
+    load_library().nystrom_schur_kernel_timing(1 if enable else 0)
+
+
+def nystrom_schur_kernel_stats(family: str):
+    """dict(ms, launches, bytes, flops) of one kernel family since timing was enabled."""
+    ms, cnt, by, fl = c_double(), c_int64(), c_double(), c_double()
+    st = load_library().nystrom_schur_kernel_stats(family.encode(), ctypes.byref(ms), ctypes.byref(cnt),
+                                                   ctypes.byref(by), ctypes.byref(fl))
+    if st != NS_OK:
+        raise NsError(st, f"unknown kernel family {family}")
+    return dict(ms=ms.value, launches=cnt.value, bytes=by.value, flops=fl.value)
 
 
 def nystrom_schur_destroy(handle):

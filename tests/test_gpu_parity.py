@@ -39,13 +39,21 @@ PROBLEMS = {
 }
 
 
-@pytest.fixture(scope="module", params=sorted(PROBLEMS))
+CASES = [(p, m) for p in sorted(PROBLEMS) for m in ("tri", "local")]
+MODES = {"tri": ns.NS_SCHUR_TRIANGULAR, "local": ns.NS_SCHUR_LOCAL}
+_oracles = {}
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[f"{p}-{m}" for p, m in CASES])
 def case(request):
-    P = PROBLEMS[request.param]()
-    g = gpu_setup(P)
-    o = oracle(P)
-    o.setup()
-    yield request.param, P, g, o
+    pname, mode = request.param
+    P = PROBLEMS[pname]()
+    g = gpu_setup(P, schur_mode=MODES[mode])
+    if pname not in _oracles:
+        o = oracle(P)
+        o.setup()
+        _oracles[pname] = o
+    yield f"{pname}-{mode}", P, g, _oracles[pname]
     g.close()
 
 
