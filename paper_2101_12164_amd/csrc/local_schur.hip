@@ -299,6 +299,32 @@ void launch_gemm(const LocalSchur& ls, const T* A, const T* B, T* C, int N, hipS
 
 }  // namespace
 
+template <class T>
+void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStream_t st) {
+  if (lv.nblk == 0 || ncols == 0) return;
+  const T* A;
+  if constexpr (sizeof(T) == 8)
+    A = lv.Ainv64.p;
+  else
+    A = lv.Ainv32.p;
+  GemmBatch g{lv.npad_d, lv.npad_d, lv.inv_off, lv.inv_lda, lv.roff, ncols, ncols, lv.roff, ncols, nullptr, ncols};
+  double sq = 0;
+  for (int b = 0; b < lv.nblk; ++b) sq += double(lv.h_nb[b]) * lv.h_nb[b];
+  KScope ks(sizeof(T) == 8 ? KF_INV64 : KF_INV32, st, (sq + 2.0 * lv.alg_rows * ncols) * sizeof(T), 2.0 * sq * ncols);
+  const int tilesM = lv.max_nt;
+  if (ncols <= 16) {
+    dim3 grid(1, tilesM, lv.nblk);
+    k_gemm_tn<T, 16><<<grid, 256, 0, st>>>(g, A, B, C, ncols, 0);
+  } else {
+    dim3 grid((ncols + 63) / 64, tilesM, lv.nblk);
+    k_gemm_tn<T, 64><<<grid, 256, 0, st>>>(g, A, B, C, ncols, 0);
+  }
+  NS_LAUNCH_CHECK();
+}
+
+template void tile_apply_inverse<double>(const TileLevel&, const double*, double*, int, hipStream_t);
+template void tile_apply_inverse<float>(const TileLevel&, const float*, float*, int, hipStream_t);
+
 void local_schur_build(Handle& h) {
   hipStream_t st = h.stream;
   LocalSchur& ls = h.LS;

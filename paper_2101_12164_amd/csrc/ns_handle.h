@@ -71,8 +71,8 @@ struct ns_handle_s {
   double* hscal = nullptr;  // pinned scalars for readbacks
 
   // workspaces (sized at setup)
-  ns::DBuf<double> wsT64, wsB64, wsJ64, wsG64, wsG64b;  // interior rhs, level-2 rhs, junction rhs, gathered copies
-  ns::DBuf<float> wsT32, wsB32, wsJ32, wsG32, wsG32b;
+  ns::DBuf<double> wsT64, wsB64, wsJ64, wsB64b, wsJ64b;  // interior rhs, level-2 rhs, junction rhs, outputs
+  ns::DBuf<float> wsT32, wsB32, wsJ32, wsB32b, wsJ32b;
   ns::DBuf<double> red;    // reduction partials
   ns::DBuf<double> small;  // small dense scratch
   int64_t ws_cols = 0;     // column capacity of the workspaces

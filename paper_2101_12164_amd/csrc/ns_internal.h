@@ -74,6 +74,13 @@ struct TileLevel {
   DBuf<int64_t> foff, ioff, roff;
   DBuf<double> L64, Linv64;
   DBuf<float> L32, Linv32;
+  DBuf<double> LT64;  // tile-wise transposed factor (single-column backward sweeps)
+  // explicit inverses of the (small) blocks: rows nrows_pad x inv_ld, block b at row roff_b
+  DBuf<double> Ainv64;
+  DBuf<float> Ainv32;
+  DBuf<int64_t> inv_off, inv_lda;
+  DBuf<int> npad_d;
+  int64_t inv_ld = 0;
   // algorithmic work: sum of nb(nb+1)/2, sum of nb^2, sum of nb; per tile column
   // of the factorisation: update flops, panel flops, bytes
   double alg_tri = 0, alg_sq = 0, alg_rows = 0;
@@ -98,6 +105,8 @@ enum KFamily {
   KF_LS_FORM,     // local Schur blocks: S_j = W_j^T W_j
   KF_LS_APPLY64,  // local Schur blocks applied (batched GEMM), FP64
   KF_LS_APPLY32,
+  KF_INV64,  // explicit interface-block inverses applied, FP64
+  KF_INV32,
   KF_COUNT
 };
 // Brackets one launch when timing is on; bytes / flops are the algorithmic
@@ -125,6 +134,15 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
 // Forward sweep only: B <- L^{-1} B.
 template <class T>
 void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st);
+// Single right-hand side sweeps (FP64) with 16-wave workgroups; need LT64.
+bool trsv1_supported(const TileLevel& lv);
+void tile_make_transposed(TileLevel& lv, hipStream_t st);
+void tile_solve1(const TileLevel& lv, double* B, int64_t ldb, hipStream_t st);
+// Explicit inverses (L L^T)^{-1} of every block of a level (FP64, optional FP32 copy).
+void tile_make_inverse(TileLevel& lv, bool fp32, hipStream_t st);
+// C = A^{-1} B for every block with the explicit inverses; B, C padded rhs (ld ncols).
+template <class T>
+void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStream_t st);
 // Expand the factor of one block to a dense nb x nb column-major lower matrix.
 void tile_export(const TileLevel& lv, int block, double* out, hipStream_t st);
 

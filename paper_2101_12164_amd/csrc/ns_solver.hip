@@ -154,7 +154,7 @@ int block_pcg(Handle& h, SmallMats& sm, const double* Omega, double* D, double& 
       op_schur<T>(h, P, s, Q, s, r, false);                                   // Q = S P
       gram<T, T>(nG, P, s, r, Q, s, r, sm.Delta, 1.0, 0.0, work, st);       // Delta = P^T Q
       gram<T, T>(nG, P, s, r, R.p, s, s, sm.G1, 1.0, 0.0, work, st);        // P^T R
-      small_chol_solve(r, sm.Delta, sm.G1, s, sm.alpha, s, s, 1.0, sm.flag, st);  // alpha
+      small_chol_solve(r, sm.Delta, sm.G1, s, sm.alpha, s, s, 1.0, sm.flag, h.small.p, st);  // alpha
       ts_update<T>(nG, s, X.p, s, 1.0, 1.0, P, s, r, sm.alpha, s, nullptr, 0, 0, nullptr, 0, st);
       ts_update<T>(nG, s, R.p, s, 1.0, -1.0, Q, s, r, sm.alpha, s, nullptr, 0, 0, nullptr, 0, st);
       col_sumsq<T>(nG, s, R.p, s, sm.colsq, work, st);
@@ -169,7 +169,7 @@ int block_pcg(Handle& h, SmallMats& sm, const double* Omega, double* D, double& 
       }
       op_gamma_solve<T>(h, R.p, s, Z.p, s, s);                            // Z = A_G^{-1} R
       gram<T, T>(nG, Q, s, r, Z.p, s, s, sm.G2, 1.0, 0.0, work, st);       // Q^T Z
-      small_chol_apply(r, sm.Delta, sm.G2, s, sm.beta, s, s, -1.0, st);    // beta
+      small_chol_apply(r, sm.Delta, sm.G2, s, sm.beta, s, s, -1.0, h.small.p, st);    // beta
       ts_update<T>(nG, s, Z.p, s, 1.0, 1.0, P, s, r, sm.beta, s, nullptr, 0, 0, nullptr, 0, st);  // Z + P beta
       r = orth<T>(h, sm, work, Z.p, P, Q, s);
     }
@@ -229,7 +229,7 @@ void setup_adef2(Handle& h) {
   DBuf<double> work;
   work.alloc(gram_work_elems(k));
   gram<double, double>(nG, h.Z.p, k, ke, h.SZ.p, k, ke, h.Echol.p, 1.0, 0.0, work, st);
-  small_chol_solve(ke, h.Echol.p, nullptr, 0, nullptr, 0, 0, 1.0, h.dflags.p + 12, st);
+  small_chol_solve(ke, h.Echol.p, nullptr, 0, nullptr, 0, 0, 1.0, h.dflags.p + 12, h.small.p, st);
   int fl = 0;
   read_back(h, &fl, h.dflags.p + 12, 1);
   if (fl) fail(BREAKDOWN, "Z^T S Z is not positive definite");
@@ -250,7 +250,7 @@ void apply_prec(Handle& h, const double* r, int64_t ldr, double* z, int64_t ldz,
   } else {
     gram<double, double>(nG, h.Z.p, k, ke, r, ldr, ncols, c1, 1.0, 0.0, work, st);   // Z^T r
     gram<double, double>(nG, h.SZ.p, k, ke, z, ldz, ncols, c1, -1.0, 1.0, work, st);  // - (SZ)^T t
-    small_chol_apply(ke, h.Echol.p, c1, ncols, c2, ncols, ncols, 1.0, st);           // E^{-1} (...)
+    small_chol_apply(ke, h.Echol.p, c1, ncols, c2, ncols, ncols, 1.0, h.small.p, st);           // E^{-1} (...)
     ts_update<double>(nG, ncols, z, ldz, 1.0, 1.0, h.Z.p, k, ke, c2, ncols, nullptr, 0, 0, nullptr, 0, st);
   }
 }
@@ -334,6 +334,10 @@ ns_status nystrom_schur_setup(int64_t n, int64_t nnz, const int64_t* row_ptr, co
     assemble_junction(*h);
     tile_cholesky(h->LJ, h->dflags.p + 8, h->stream);
     check_chol(*h, 3, info);
+    tile_make_transposed(h->L1, h->stream);
+    for (ns::TileLevel* lv : {&h->L2, &h->LJ})
+      if (lv->nblk && lv->max_nt * TILE <= 4096 && lv->nrows_pad * lv->max_nt * TILE <= (int64_t(1) << 28))
+        tile_make_inverse(*lv, h->prec_inner != 0, h->stream);
     if (h->prec_inner) {
       if (!h->LS.built) tile_make_fp32(h->L1, h->stream);
       tile_make_fp32(h->L2, h->stream);
@@ -450,7 +454,7 @@ ns_status nystrom_schur_pcg_solve(ns_handle h, const double* b, double* x, doubl
       // w0 = Z E^{-1} Z^T f ; r = f - S w0
       const int k = h->k, ke = h->k_eff;
       gram<double, double>(nG, h->Z.p, k, ke, f.p, 1, 1, c1.p, 1.0, 0.0, work, st);
-      small_chol_apply(ke, h->Echol.p, c1.p, 1, c2.p, 1, 1, 1.0, st);
+      small_chol_apply(ke, h->Echol.p, c1.p, 1, c2.p, 1, 1, 1.0, h->small.p, st);
       ts_update<double>(nG, 1, w.p, 1, 0.0, 1.0, h->Z.p, k, ke, c2.p, 1, nullptr, 0, 0, nullptr, 0, st);
       op_schur<double>(*h, w.p, 1, q.p, 1, 1, false);
       axpby(nG, 1.0, f.p, -1.0, q.p, st);

@@ -32,15 +32,16 @@ void pcg_update_p(int64_t n, const double* sc, int it, const double* z, double* 
 void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
 
 // ---------------------------------------------------------------- small dense (one workgroup)
-// All matrices row-major FP64 in device memory.
+// All matrices row-major FP64 in device memory; gw: global scratch of
+// small_scratch_elems() doubles, used when a matrix does not fit in LDS.
 
 // L (in place of D, lower) = chol(D) for an r x r SPD D; X = alpha * D^{-1} B (B: r x s, ld ldb; X ld ldx).
 // flag[0] is set to 1 when D is not numerically SPD.
 void small_chol_solve(int r, double* D, const double* B, int64_t ldb, double* X, int64_t ldx, int s, double alpha,
-                      int* flag, hipStream_t st);
+                      int* flag, double* gw, hipStream_t st);
 // X = alpha * (L L^T)^{-1} B with L from small_chol_solve.
 void small_chol_apply(int r, const double* L, const double* B, int64_t ldb, double* X, int64_t ldx, int s,
-                      double alpha, hipStream_t st);
+                      double alpha, double* gw, hipStream_t st);
 // Orthonormalising transform of a block with Gram matrix G (s x s): T[:, c] = u_c / sqrt(lambda_c)
 // for the eigenpairs with lambda_c > drop2 * lambda_max, descending; out[0] = number kept.
 void small_svqb(int s, const double* G, double drop2, double* T, int* out, double* gw, hipStream_t st);

@@ -4,6 +4,8 @@
 // Algorithm alg:nystrom (EVD of C, threshold, T, EVD of T).  Symmetric
 // eigen-decompositions use the cyclic two-sided Jacobi method with a
 // round-robin ordering, so all rotations of a round are independent.
+// Matrices staged in LDS use a row stride of n + 1 doubles so that column
+// accesses spread over the LDS banks.
 #include "ns_vec.h"
 
 namespace ns {
@@ -11,6 +13,7 @@ namespace {
 
 constexpr int NT = 1024;                  // threads per workgroup
 constexpr size_t LDS_LIMIT = 136 * 1024;  // dynamic LDS used when the matrices fit
+constexpr int SMAX = 256;                 // largest s supported by the small kernels
 
 __device__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
@@ -24,11 +27,15 @@ __device__ double block_sum(double v, double* red) {
   return r;
 }
 
-// Cyclic Jacobi: A (n x n, row-major, symmetric) is diagonalised in place; V
-// receives the eigenvectors in its columns.  cs: 2*n doubles, pr: n ints.
-__device__ void jacobi(double* A, double* V, int n, double* cs, int* pr, double* red) {
+// Cyclic Jacobi: A (n x n, row stride ld, symmetric) is diagonalised in place;
+// V (stride ld) receives the eigenvectors in its columns.  cs: 2n doubles,
+// pr: n+1 ints.
+__device__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr, double* red) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += NT) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+  for (int e = tid; e < n * n; e += NT) {
+    const int i = e / n, j = e % n;
+    V[i * ld + j] = i == j ? 1.0 : 0.0;
+  }
   __syncthreads();
   if (n < 2) return;
   const int m = n + (n & 1);
@@ -36,9 +43,10 @@ __device__ void jacobi(double* A, double* V, int n, double* cs, int* pr, double*
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < n * n; e += NT) {
-      const double v = A[e] * A[e];
+      const int i = e / n, j = e % n;
+      const double v = A[i * ld + j] * A[i * ld + j];
       tot += v;
-      if (e / n != e % n) off += v;
+      if (i != j) off += v;
     }
     off = block_sum(off, red);
     tot = block_sum(tot, red);
@@ -54,9 +62,9 @@ __device__ void jacobi(double* A, double* V, int n, double* cs, int* pr, double*
         }
         double c = 1.0, s = 0.0;
         if (q < n) {
-          const double apq = A[p * n + q];
+          const double apq = A[p * ld + q];
           if (fabs(apq) > 1e-300) {
-            const double tau = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+            const double tau = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
@@ -76,23 +84,23 @@ __device__ void jacobi(double* A, double* V, int n, double* cs, int* pr, double*
         if (p < 0) continue;
         const int q = pr[2 * k + 1];
         const double c = cs[2 * k], s = cs[2 * k + 1];
-        const double ap = A[p * n + j], aq = A[q * n + j];
-        A[p * n + j] = c * ap - s * aq;
-        A[q * n + j] = s * ap + c * aq;
+        const double ap = A[p * ld + j], aq = A[q * ld + j];
+        A[p * ld + j] = c * ap - s * aq;
+        A[q * ld + j] = s * ap + c * aq;
       }
       __syncthreads();
       for (int t = tid; t < half * n; t += NT) {  // columns: A <- A J, V <- V J
-        const int k = t / n, i = t % n;
+        const int k = t % half, i = t / half;
         const int p = pr[2 * k];
         if (p < 0) continue;
         const int q = pr[2 * k + 1];
         const double c = cs[2 * k], s = cs[2 * k + 1];
-        const double ap = A[i * n + p], aq = A[i * n + q];
-        A[i * n + p] = c * ap - s * aq;
-        A[i * n + q] = s * ap + c * aq;
-        const double vp = V[i * n + p], vq = V[i * n + q];
-        V[i * n + p] = c * vp - s * vq;
-        V[i * n + q] = s * vp + c * vq;
+        const double ap = A[i * ld + p], aq = A[i * ld + q];
+        A[i * ld + p] = c * ap - s * aq;
+        A[i * ld + q] = s * ap + c * aq;
+        const double vp = V[i * ld + p], vq = V[i * ld + q];
+        V[i * ld + p] = c * vp - s * vq;
+        V[i * ld + q] = s * vp + c * vq;
       }
       __syncthreads();
     }
@@ -110,8 +118,8 @@ __device__ void sort_desc(const double* d, int n, int* order) {
   __syncthreads();
 }
 
-// In-place lower Cholesky of A (n x n, row-major, lda).  Returns 0 or the
-// 1-based index of the first non-positive pivot (the pivot is then set to 1).
+// In-place lower Cholesky of A (n x n, stride lda).  Returns 0 or the 1-based
+// index of the first non-positive pivot (the pivot is then taken as 1).
 __device__ int chol_dev(double* A, int n, int lda, int* sinfo) {
   if (threadIdx.x == 0) *sinfo = 0;
   __syncthreads();
@@ -140,76 +148,82 @@ __device__ int chol_dev(double* A, int n, int lda, int* sinfo) {
   return info;
 }
 
-// X (r x s) = alpha * (L L^T)^{-1} B; one thread per column.
-__device__ void chol_solve_dev(const double* L, int r, int ldl, const double* B, int64_t ldb, double* X, int64_t ldx,
-                               int s, double alpha) {
-  for (int j = threadIdx.x; j < s; j += NT) {
-    for (int i = 0; i < r; ++i) {  // forward: L y = b
-      double acc = B[i * ldb + j];
-      for (int m = 0; m < i; ++m) acc -= L[i * ldl + m] * X[m * ldx + j];
-      X[i * ldx + j] = acc / L[i * ldl + i];
+// X (r x s, stride ldx) <- (L L^T)^{-1} X, right-looking row sweeps, all
+// columns and rows of a step in parallel.
+__device__ void chol_solve_inplace(const double* L, int r, int ldl, double* X, int ldx, int s) {
+  for (int m = 0; m < r; ++m) {  // forward: L y = x
+    const double inv = 1.0 / L[m * ldl + m];
+    for (int j = threadIdx.x; j < s; j += NT) X[m * ldx + j] *= inv;
+    __syncthreads();
+    const int rows = r - 1 - m;
+    for (int t = threadIdx.x; t < rows * s; t += NT) {
+      const int i = m + 1 + t / s, j = t % s;
+      X[i * ldx + j] -= L[i * ldl + m] * X[m * ldx + j];
     }
-    for (int i = r - 1; i >= 0; --i) {  // backward: L^T x = y
-      double acc = X[i * ldx + j];
-      for (int m = i + 1; m < r; ++m) acc -= L[m * ldl + i] * X[m * ldx + j];
-      X[i * ldx + j] = acc / L[i * ldl + i];
-    }
-    for (int i = 0; i < r; ++i) X[i * ldx + j] *= alpha;
+    __syncthreads();
   }
-  __syncthreads();
+  for (int m = r - 1; m >= 0; --m) {  // backward: L^T x = y
+    const double inv = 1.0 / L[m * ldl + m];
+    for (int j = threadIdx.x; j < s; j += NT) X[m * ldx + j] *= inv;
+    __syncthreads();
+    for (int t = threadIdx.x; t < m * s; t += NT) {
+      const int i = t / s, j = t % s;
+      X[i * ldx + j] -= L[m * ldl + i] * X[m * ldx + j];
+    }
+    __syncthreads();
+  }
+}
+
+// Dynamic LDS layout of the Cholesky-solve kernels: L (r x (r+1)) and X (r x (s+1)).
+__host__ __device__ inline size_t cs_lds(int r, int s) {
+  return (size_t(r) * (r + 1) + size_t(r) * (s + 1)) * sizeof(double);
 }
 
 __global__ __launch_bounds__(NT) void k_small_chol_solve(int r, double* D, const double* B, int64_t ldb, double* X,
-                                                         int64_t ldx, int s, double alpha, int* flag) {
+                                                         int64_t ldx, int s, double alpha, int* flag, int factor,
+                                                         double* gw) {
   extern __shared__ double sm[];
   __shared__ int sinfo;
-  const bool lds = size_t(r) * r * sizeof(double) <= LDS_LIMIT;
-  double* A = lds ? sm : D;
-  if (lds)
-    for (int e = threadIdx.x; e < r * r; e += NT) A[e] = D[e];
+  const bool lds = cs_lds(r, s) <= LDS_LIMIT;
+  double* Ls = lds ? sm : gw;
+  const int ldl = r + 1, lx = s + 1;
+  double* Xs = Ls + size_t(r) * ldl;
+  for (int e = threadIdx.x; e < r * r; e += NT) Ls[(e / r) * ldl + e % r] = D[e];
+  for (int e = threadIdx.x; e < r * s; e += NT) Xs[(e / s) * lx + e % s] = B[(e / s) * ldb + e % s];
   __syncthreads();
-  const int info = chol_dev(A, r, r, &sinfo);
-  if (info && threadIdx.x == 0) flag[0] = 1;
-  if (lds)
-    for (int e = threadIdx.x; e < r * r; e += NT) D[e] = A[e];
-  __syncthreads();
-  chol_solve_dev(A, r, r, B, ldb, X, ldx, s, alpha);
-}
-
-__global__ __launch_bounds__(NT) void k_small_chol_apply(int r, const double* Lg, const double* B, int64_t ldb,
-                                                         double* X, int64_t ldx, int s, double alpha) {
-  extern __shared__ double sm[];
-  const bool lds = size_t(r) * r * sizeof(double) <= LDS_LIMIT;
-  const double* L = Lg;
-  if (lds) {
-    for (int e = threadIdx.x; e < r * r; e += NT) sm[e] = Lg[e];
-    L = sm;
+  if (factor) {
+    const int info = chol_dev(Ls, r, ldl, &sinfo);
+    if (info && threadIdx.x == 0) flag[0] = 1;
+    for (int e = threadIdx.x; e < r * r; e += NT) D[e] = Ls[(e / r) * ldl + e % r];
+    __syncthreads();
   }
-  __syncthreads();
-  chol_solve_dev(L, r, r, B, ldb, X, ldx, s, alpha);
+  chol_solve_inplace(Ls, r, ldl, Xs, lx, s);
+  for (int e = threadIdx.x; e < r * s; e += NT) X[(e / s) * ldx + e % s] = alpha * Xs[(e / s) * lx + e % s];
 }
 
-// Workspace for the Jacobi kernels: two n x n matrices + small arrays, in LDS
-// when they fit, else in the caller's global scratch `gw` (2 n^2 doubles).
+// Workspace for the Jacobi kernels: two n x (n+1) matrices + small arrays, in
+// LDS when they fit, else in the caller's global scratch `gw`.
 struct EvdSpace {
   double *A, *V, *cs, *d;
   int *pr, *ord;
+  int ld;
 };
+
+__host__ __device__ inline size_t evd_bytes(int n) { return size_t(2) * n * (n + 1) * sizeof(double); }
 
 __device__ EvdSpace evd_space(int n, double* sm, double* gw, double* small_d, int* small_i) {
   EvdSpace e;
-  const bool lds = size_t(2) * n * n * sizeof(double) <= LDS_LIMIT;
+  const bool lds = evd_bytes(n) <= LDS_LIMIT;
   double* base = lds ? sm : gw;
+  e.ld = n + 1;
   e.A = base;
-  e.V = base + size_t(n) * n;
+  e.V = base + size_t(n) * e.ld;
   e.cs = small_d;
   e.d = small_d + 2 * n;
   e.pr = small_i;
   e.ord = small_i + 2 * n;
   return e;
 }
-
-constexpr int SMAX = 256;  // largest s supported by the small kernels
 
 __global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, double drop2, double* T, int* out,
                                                    double* gw) {
@@ -218,25 +232,28 @@ __global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, doubl
   __shared__ double sd[3 * SMAX];
   __shared__ int si[3 * SMAX];
   EvdSpace w = evd_space(s, sm, gw, sd, si);
+  const int ld = w.ld;
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
-    w.A[e] = 0.5 * (G[i * s + j] + G[j * s + i]);
+    w.A[i * ld + j] = 0.5 * (G[i * s + j] + G[j * s + i]);
   }
   __syncthreads();
-  jacobi(w.A, w.V, s, w.cs, w.pr, red);
-  for (int i = threadIdx.x; i < s; i += NT) w.d[i] = w.A[i * s + i];
+  jacobi(w.A, w.V, s, ld, w.cs, w.pr, red);
+  for (int i = threadIdx.x; i < s; i += NT) w.d[i] = w.A[i * ld + i];
   __syncthreads();
   sort_desc(w.d, s, w.ord);
   const double lmax = w.d[w.ord[0]];
   int kept = 0;
   for (int c = 0; c < s; ++c) {
     const double l = w.d[w.ord[c]];
-    if (l > 0.0 && l > drop2 * lmax) ++kept;
-    else break;
+    if (l > 0.0 && l > drop2 * lmax)
+      ++kept;
+    else
+      break;
   }
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, c = e % s;
-    T[e] = c < kept ? w.V[i * s + w.ord[c]] / sqrt(w.d[w.ord[c]]) : 0.0;
+    T[e] = c < kept ? w.V[i * ld + w.ord[c]] / sqrt(w.d[w.ord[c]]) : 0.0;
   }
   if (threadIdx.x == 0) out[0] = kept;
 }
@@ -253,45 +270,48 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const double* G, dou
   }
   __syncthreads();
   const double shift = sshift;
-  const bool lds = size_t(2) * s * s * sizeof(double) <= LDS_LIMIT;
+  const bool lds = evd_bytes(s) <= LDS_LIMIT;
+  const int ld = s + 1;
   double* A = lds ? sm : gw;
-  double* X = A + size_t(s) * s;
+  double* X = A + size_t(s) * ld;
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
-    A[e] = 0.5 * (G[i * s + j] + G[j * s + i]) + (i == j ? shift : 0.0);
+    A[i * ld + j] = 0.5 * (G[i * s + j] + G[j * s + i]) + (i == j ? shift : 0.0);
+    X[i * ld + j] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (chol_dev(A, s, s, &sinfo) && threadIdx.x == 0) flag[0] = 1;
-  // X = L^{-1} (lower), one thread per column
-  for (int c = threadIdx.x; c < s; c += NT) {
-    for (int r = 0; r < c; ++r) X[r * s + c] = 0.0;
-    X[c * s + c] = 1.0 / A[c * s + c];
-    for (int r = c + 1; r < s; ++r) {
-      double acc = 0.0;
-      for (int m = c; m < r; ++m) acc += A[r * s + m] * X[m * s + c];
-      X[r * s + c] = -acc / A[r * s + r];
+  if (chol_dev(A, s, ld, &sinfo) && threadIdx.x == 0) flag[0] = 1;
+  // X = L^{-1}: forward sweep on the identity
+  for (int m = 0; m < s; ++m) {
+    const double inv = 1.0 / A[m * ld + m];
+    for (int j = threadIdx.x; j <= m; j += NT) X[m * ld + j] *= inv;
+    __syncthreads();
+    const int rows = s - 1 - m;
+    for (int t = threadIdx.x; t < rows * (m + 1); t += NT) {
+      const int i = m + 1 + t / (m + 1), j = t % (m + 1);
+      X[i * ld + j] -= A[i * ld + m] * X[m * ld + j];
     }
+    __syncthreads();
   }
-  __syncthreads();
   // Rinv = (L^{-1})^T (upper); R = L^T
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
-    Rinv[e] = X[j * s + i];
+    Rinv[e] = X[j * ld + i];
   }
   __syncthreads();
-  // Racc <- R * Racc ; reuse X for the product
+  // Racc <- R * Racc ; X reused for the product
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
     double acc = 0.0;
     if (init) {
-      acc = j >= i ? A[j * s + i] : 0.0;
+      acc = j >= i ? A[j * ld + i] : 0.0;
     } else {
-      for (int m = i; m <= j; ++m) acc += A[m * s + i] * Racc[m * s + j];
+      for (int m = i; m <= j; ++m) acc += A[m * ld + i] * Racc[m * s + j];
     }
-    X[e] = acc;
+    X[i * ld + j] = acc;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < s * s; e += NT) Racc[e] = X[e];
+  for (int e = threadIdx.x; e < s * s; e += NT) Racc[e] = X[(e / s) * ld + e % s];
 }
 
 __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double* C, const double* R, double eps_rel,
@@ -304,13 +324,14 @@ __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double
   __shared__ int ikeep[SMAX];
   __shared__ int nkeep;
   EvdSpace w = evd_space(s, sm, gw, sd, si);
-  for (int e = threadIdx.x; e < s * s; e += NT) {  // symmetrised C (step: EVD of C)
+  const int ld = w.ld;
+  for (int e = threadIdx.x; e < s * s; e += NT) {  // symmetrised C
     const int i = e / s, j = e % s;
-    w.A[e] = 0.5 * (C[i * s + j] + C[j * s + i]);
+    w.A[i * ld + j] = 0.5 * (C[i * s + j] + C[j * s + i]);
   }
   __syncthreads();
-  jacobi(w.A, w.V, s, w.cs, w.pr, red);
-  for (int i = threadIdx.x; i < s; i += NT) w.d[i] = w.A[i * s + i];
+  jacobi(w.A, w.V, s, ld, w.cs, w.pr, red);
+  for (int i = threadIdx.x; i < s; i += NT) w.d[i] = w.A[i * ld + i];
   __syncthreads();
   if (threadIdx.x == 0) {
     double dmax = w.d[0];
@@ -327,39 +348,32 @@ __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double
   }
   __syncthreads();
   const int r = nkeep;
-  // M = R V_1 (s x r) into A
+  // M = R V_1 (s x r) into A (stride ld >= r)
   for (int e = threadIdx.x; e < s * r; e += NT) {
     const int i = e / r, c = e % r;
     double acc = 0.0;
-    for (int m = i; m < s; ++m) acc += R[i * s + m] * w.V[m * s + ikeep[c]];
-    w.A[i * r + c] = acc;
+    for (int m = i; m < s; ++m) acc += R[i * s + m] * w.V[m * ld + ikeep[c]];
+    w.A[i * ld + c] = acc;
   }
   __syncthreads();
-  // T = M D_1^{-1} M^T into V
+  // T = M D_1^{-1} M^T into V, symmetric by construction of the sum
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
+    if (j > i) continue;
     double acc = 0.0;
-    for (int c = 0; c < r; ++c) acc += w.A[i * r + c] * w.A[j * r + c] / dkeep[c];
-    w.V[e] = acc;
+    for (int c = 0; c < r; ++c) acc += w.A[i * ld + c] * w.A[j * ld + c] / dkeep[c];
+    w.V[i * ld + j] = acc;
+    w.V[j * ld + i] = acc;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < s * s; e += NT) {  // symmetrise T
-    const int i = e / s, j = e % s;
-    if (j > i) {
-      const double a = 0.5 * (w.V[i * s + j] + w.V[j * s + i]);
-      w.V[i * s + j] = a;
-      w.V[j * s + i] = a;
-    }
-  }
-  __syncthreads();
-  jacobi(w.V, w.A, s, w.cs, w.pr, red);  // EVD of T: eigenvectors in A
-  for (int i = threadIdx.x; i < s; i += NT) w.d[i] = w.V[i * s + i];
+  jacobi(w.V, w.A, s, ld, w.cs, w.pr, red);  // EVD of T: eigenvectors in A
+  for (int i = threadIdx.x; i < s; i += NT) w.d[i] = w.V[i * ld + i];
   __syncthreads();
   sort_desc(w.d, s, w.ord);
   const int kk = k < r ? k : r;
   for (int e = threadIdx.x; e < s * k; e += NT) {
     const int i = e / k, c = e % k;
-    Wk[e] = c < kk ? w.A[i * s + w.ord[c]] : 0.0;
+    Wk[e] = c < kk ? w.A[i * ld + w.ord[c]] : 0.0;
   }
   for (int c = threadIdx.x; c < k; c += NT) Ek[c] = c < kk ? w.d[w.ord[c]] : 0.0;
   if (threadIdx.x == 0) {
@@ -381,46 +395,53 @@ __global__ __launch_bounds__(NT) void k_small_sym_evd(int m, const double* Ain, 
   __shared__ double sd[3 * SMAX];
   __shared__ int si[3 * SMAX];
   EvdSpace w = evd_space(m, sm, gw, sd, si);
+  const int ld = w.ld;
   for (int e = threadIdx.x; e < m * m; e += NT) {
     const int i = e / m, j = e % m;
-    w.A[e] = 0.5 * (Ain[i * m + j] + Ain[j * m + i]);
+    w.A[i * ld + j] = 0.5 * (Ain[i * m + j] + Ain[j * m + i]);
   }
   __syncthreads();
-  jacobi(w.A, w.V, m, w.cs, w.pr, red);
-  for (int i = threadIdx.x; i < m; i += NT) w.d[i] = w.A[i * m + i];
+  jacobi(w.A, w.V, m, ld, w.cs, w.pr, red);
+  for (int i = threadIdx.x; i < m; i += NT) w.d[i] = w.A[i * ld + i];
   __syncthreads();
   sort_desc(w.d, m, w.ord);
   for (int e = threadIdx.x; e < m * m; e += NT) {
     const int i = e / m, c = e % m;
-    W[e] = w.V[i * m + w.ord[c]];
+    W[e] = w.V[i * ld + w.ord[c]];
   }
   for (int c = threadIdx.x; c < m; c += NT) E[c] = w.d[w.ord[c]];
 }
 
 size_t evd_lds(int n) {
-  const size_t b = size_t(2) * n * n * sizeof(double);
+  const size_t b = evd_bytes(n);
   return b <= LDS_LIMIT ? b : 0;
 }
 
 }  // namespace
 
+size_t small_scratch_elems() {
+  const size_t evd = size_t(2) * SMAX * (SMAX + 1), cs = size_t(SMAX) * (SMAX + 1) + size_t(SMAX) * (4 * SMAX + 1);
+  return evd > cs ? evd : cs;
+}
+
 void small_chol_solve(int r, double* D, const double* B, int64_t ldb, double* X, int64_t ldx, int s, double alpha,
-                      int* flag, hipStream_t st) {
+                      int* flag, double* gw, hipStream_t st) {
   if (r <= 0) return;
-  const size_t b = size_t(r) * r * sizeof(double);
-  k_small_chol_solve<<<1, NT, b <= LDS_LIMIT ? b : 0, st>>>(r, D, B, ldb, X, ldx, s, alpha, flag);
+  if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
+  const size_t b = cs_lds(r, s);
+  k_small_chol_solve<<<1, NT, b <= LDS_LIMIT ? b : 0, st>>>(r, D, B, ldb, X, ldx, s, alpha, flag, 1, gw);
   NS_LAUNCH_CHECK();
 }
 
 void small_chol_apply(int r, const double* L, const double* B, int64_t ldb, double* X, int64_t ldx, int s,
-                      double alpha, hipStream_t st) {
-  if (r <= 0) return;
-  const size_t b = size_t(r) * r * sizeof(double);
-  k_small_chol_apply<<<1, NT, b <= LDS_LIMIT ? b : 0, st>>>(r, L, B, ldb, X, ldx, s, alpha);
+                      double alpha, double* gw, hipStream_t st) {
+  if (r <= 0 || s <= 0) return;
+  if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
+  const size_t b = cs_lds(r, s);
+  k_small_chol_solve<<<1, NT, b <= LDS_LIMIT ? b : 0, st>>>(r, const_cast<double*>(L), B, ldb, X, ldx, s, alpha,
+                                                            nullptr, 0, gw);
   NS_LAUNCH_CHECK();
 }
-
-size_t small_scratch_elems() { return size_t(2) * SMAX * SMAX; }
 
 void small_svqb(int s, const double* G, double drop2, double* T, int* out, double* gw, hipStream_t st) {
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");

@@ -671,13 +671,15 @@ void ensure_workspace(Handle& h, int64_t ncols) {
   grow(h.wsT64, h.L1.nrows_pad);
   grow(h.wsB64, h.L2.nrows_pad);
   grow(h.wsJ64, h.LJ.nrows_pad);
-  grow(h.wsG64, h.nG);
-  grow(h.wsG64b, h.nG);
-  grow(h.wsT32, h.L1.nrows_pad);
-  grow(h.wsB32, h.L2.nrows_pad);
-  grow(h.wsJ32, h.LJ.nrows_pad);
-  grow(h.wsG32, h.nG);
-  grow(h.wsG32b, h.nG);
+  grow(h.wsB64b, h.L2.nrows_pad);
+  grow(h.wsJ64b, h.LJ.nrows_pad);
+  if (h.prec_inner) {
+    grow(h.wsT32, h.L1.nrows_pad);
+    grow(h.wsB32, h.L2.nrows_pad);
+    grow(h.wsJ32, h.LJ.nrows_pad);
+    grow(h.wsB32b, h.L2.nrows_pad);
+    grow(h.wsJ32b, h.LJ.nrows_pad);
+  }
   h.ws_cols = c;
 }
 
@@ -718,22 +720,34 @@ void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int
   hipStream_t st = h.stream;
   ensure_workspace(h, ncols);
   T* Bp = ws_ptr<T>(h.wsB64, h.wsB32);
+  T* Bq = ws_ptr<T>(h.wsB64b, h.wsB32b);
   T* Gj = ws_ptr<T>(h.wsJ64, h.wsJ32);
+  T* Gk = ws_ptr<T>(h.wsJ64b, h.wsJ32b);
   const int64_t n2pad = h.L2.nrows_pad, nJpad = h.LJ.nrows_pad;
+  // interface blocks: explicit inverses when built, else the two triangular sweeps (in place)
+  auto solve = [&](const TileLevel& lv, T* in, T* out) -> T* {
+    if (lv.Ainv64.p && (sizeof(T) == 8 || lv.Ainv32.p)) {
+      tile_apply_inverse<T>(lv, in, out, ncols, st);
+      return out;
+    }
+    tile_solve<T>(lv, in, ncols, ncols, h.trsm_cols, st);
+    return in;
+  };
+  T* xs = nullptr;
   if (n2pad) {
     gather_sub<T>(n2pad, h.l2src, R, ldr, nullptr, static_cast<const T*>(nullptr), 0, Bp, ncols, ncols, st);
-    tile_solve<T>(h.L2, Bp, ncols, ncols, h.trsm_cols, st);
+    xs = solve(h.L2, Bp, Bq);
   }
   if (nJpad) {
-    gather_sub<T>(nJpad, h.jsrc, R, ldr, n2pad ? &h.AJs : nullptr, Bp, ncols, Gj, ncols, ncols, st);
-    tile_solve<T>(h.LJ, Gj, ncols, ncols, h.trsm_cols, st);
+    gather_sub<T>(nJpad, h.jsrc, R, ldr, n2pad ? &h.AJs : nullptr, xs, ncols, Gj, ncols, ncols, st);
+    T* xj = solve(h.LJ, Gj, Gk);
     if (n2pad) {
-      gather_sub<T>(n2pad, h.l2src, R, ldr, &h.AsJ, Gj, ncols, Bp, ncols, ncols, st);
-      tile_solve<T>(h.L2, Bp, ncols, ncols, h.trsm_cols, st);
+      gather_sub<T>(n2pad, h.l2src, R, ldr, &h.AsJ, xj, ncols, Bp, ncols, ncols, st);
+      xs = solve(h.L2, Bp, Bq);
     }
-    scatter<T, T>(nJpad, h.jsrc, Gj, ncols, Out, ldo, ncols, st);
+    scatter<T, T>(nJpad, h.jsrc, xj, ncols, Out, ldo, ncols, st);
   }
-  if (n2pad) scatter<T, T>(n2pad, h.l2src, Bp, ncols, Out, ldo, ncols, st);
+  if (n2pad) scatter<T, T>(n2pad, h.l2src, xs, ncols, Out, ldo, ncols, st);
 }
 
 template <class T>

@@ -1,0 +1,210 @@
+// Single right-hand-side triangular solves with the interior Cholesky factors
+// (the solves of the block LDL^T reduction and back-substitution, eq. A_LDLT)
+// and explicit inverses of the small interface blocks used by the exact
+// A_Gamma solve.
+//
+// The single-column sweeps are bandwidth bound: one 1024-thread workgroup per
+// block keeps the block's solution in LDS and its 16 waves stream the factor
+// tiles of the current tile column in parallel.  The forward sweep updates the
+// rows below (tile (l, i) read column-major: lane r, coalesced); the backward
+// sweep forms the dot products with a transposed copy of the same tiles so that
+// its loads are coalesced as well.
+#include "ns_internal.h"
+
+namespace ns {
+namespace {
+
+constexpr int NW = 16;  // waves per workgroup
+constexpr int NTH = NW * 64;
+constexpr int LDT = TILE + 1;
+
+__device__ __forceinline__ int64_t tile_index(int nt, int i, int j) {
+  return int64_t(j) * nt - int64_t(j) * (j - 1) / 2 + (i - j);
+}
+
+// Forward: y = L^{-1} b (b, y in B with stride ldb, one column).
+__global__ __launch_bounds__(NTH) void k_trsv_fwd(const int* __restrict__ nt_arr, const int64_t* __restrict__ foff,
+                                                  const int64_t* __restrict__ ioff, const int64_t* __restrict__ roff,
+                                                  const double* __restrict__ L, const double* __restrict__ Linv,
+                                                  double* __restrict__ B, int64_t ldb) {
+  extern __shared__ double yv[];  // npad values of this block
+  __shared__ double red[NW * 64];
+  const int b = blockIdx.x;
+  const int nt = nt_arr[b];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* Bb = B + roff[b] * ldb;
+  const double* Lb = L + foff[b];
+  const double* Ib = Linv + ioff[b];
+  for (int e = threadIdx.x; e < nt * TILE; e += NTH) yv[e] = Bb[int64_t(e) * ldb];
+  __syncthreads();
+  for (int i = 0; i < nt; ++i) {
+    // y_i = Linv_ii * acc_i: wave w sums columns [4w, 4w + 4)
+    const double* Li = Ib + int64_t(i) * TILE2;
+    double p = 0.0;
+#pragma unroll
+    for (int c = 4 * w; c < 4 * w + 4; ++c) p += Li[c * TILE + lane] * yv[i * TILE + c];
+    red[w * 64 + lane] = p;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      double y = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) y += red[q * 64 + threadIdx.x];
+      yv[i * TILE + threadIdx.x] = y;
+    }
+    __syncthreads();
+    // acc_l -= L_li y_i for l > i (tiles of column i are contiguous)
+    const double* col = Lb + tile_index(nt, i, i) * TILE2;
+    for (int l = i + 1 + w; l < nt; l += NW) {
+      const double* T = col + int64_t(l - i) * TILE2;
+      double s = 0.0;
+#pragma unroll 16
+      for (int c = 0; c < TILE; ++c) s += T[c * TILE + lane] * yv[i * TILE + c];
+      yv[l * TILE + lane] -= s;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nt * TILE; e += NTH) Bb[int64_t(e) * ldb] = yv[e];
+}
+
+// Backward: x = L^{-T} y, dot products with the transposed tiles LT.
+__global__ __launch_bounds__(NTH) void k_trsv_bwd(const int* __restrict__ nt_arr, const int64_t* __restrict__ foff,
+                                                  const int64_t* __restrict__ ioff, const int64_t* __restrict__ roff,
+                                                  const double* __restrict__ LT, const double* __restrict__ Linv,
+                                                  double* __restrict__ B, int64_t ldb) {
+  extern __shared__ double yv[];
+  __shared__ double red[NW * 64];
+  __shared__ double sI[TILE * LDT];
+  __shared__ double tv[TILE];
+  const int b = blockIdx.x;
+  const int nt = nt_arr[b];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* Bb = B + roff[b] * ldb;
+  const double* Lb = LT + foff[b];
+  const double* Ib = Linv + ioff[b];
+  for (int e = threadIdx.x; e < nt * TILE; e += NTH) yv[e] = Bb[int64_t(e) * ldb];
+  __syncthreads();
+  for (int i = nt - 1; i >= 0; --i) {
+    // t = y_i - sum_{l>i} L_li^T x_l : lane c of wave w over tiles l = i+1+w, ...
+    const double* col = Lb + tile_index(nt, i, i) * TILE2;
+    double s = 0.0;
+    for (int l = i + 1 + w; l < nt; l += NW) {
+      const double* T = col + int64_t(l - i) * TILE2;  // row-major copy: element (r, c) at r * TILE + c
+#pragma unroll 16
+      for (int r = 0; r < TILE; ++r) s += T[r * TILE + lane] * yv[l * TILE + r];
+    }
+    red[w * 64 + lane] = s;
+    const double* Li = Ib + int64_t(i) * TILE2;
+    for (int e = threadIdx.x; e < TILE2; e += NTH) sI[(e >> 6) * LDT + (e & 63)] = Li[e];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      double t = yv[i * TILE + threadIdx.x];
+#pragma unroll
+      for (int q = 0; q < NW; ++q) t -= red[q * 64 + threadIdx.x];
+      tv[threadIdx.x] = t;
+    }
+    __syncthreads();
+    // x_i = Linv_ii^T t : out[c] = sum_r Linv[r][c] t[r], wave w sums rows [4w, 4w+4)
+    double p = 0.0;
+#pragma unroll
+    for (int r = 4 * w; r < 4 * w + 4; ++r) p += sI[lane * LDT + r] * tv[r];
+    red[w * 64 + lane] = p;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      double x = 0.0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) x += red[q * 64 + threadIdx.x];
+      yv[i * TILE + threadIdx.x] = x;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nt * TILE; e += NTH) Bb[int64_t(e) * ldb] = yv[e];
+}
+
+// LT = tile-wise transpose of L (every tile of the level).
+__global__ __launch_bounds__(256) void k_transpose_tiles(int64_t ntiles, const double* __restrict__ L,
+                                                         double* __restrict__ LT) {
+  __shared__ double s[TILE * LDT];
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const double* src = L + t * TILE2;
+    double* dst = LT + t * TILE2;
+    for (int e = threadIdx.x; e < TILE2; e += 256) s[(e >> 6) * LDT + (e & 63)] = src[e];  // (r = e&63, c = e>>6)
+    __syncthreads();
+    for (int e = threadIdx.x; e < TILE2; e += 256) dst[e] = s[(e & 63) * LDT + (e >> 6)];  // row-major (r = e>>6)
+    __syncthreads();
+  }
+}
+
+// Identity right-hand side for explicit inverses: E (rows x ld), block b rows
+// roff_b .. + npad_b get e_{row - roff_b}.
+__global__ void k_identity_blocks(const int* __restrict__ nt_arr, const int64_t* __restrict__ roff,
+                                  double* __restrict__ E, int64_t ld) {
+  const int b = blockIdx.y;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nt_arr[b] * TILE) E[(roff[b] + r) * ld + r] = 1.0;
+}
+
+__global__ void k_to_fp32_g(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    b[i] = float(a[i]);
+}
+
+}  // namespace
+
+bool trsv1_supported(const TileLevel& lv) {
+  return lv.LT64.p != nullptr && size_t(lv.max_nt) * TILE * sizeof(double) <= 96 * 1024;
+}
+
+void tile_make_transposed(TileLevel& lv, hipStream_t st) {
+  if (lv.nblk == 0) return;
+  lv.LT64.alloc(lv.f_elems);
+  const int64_t ntiles = lv.f_elems / TILE2;
+  k_transpose_tiles<<<unsigned(std::min<int64_t>(ntiles, 8192)), 256, 0, st>>>(ntiles, lv.L64, lv.LT64);
+  NS_LAUNCH_CHECK();
+}
+
+void tile_solve1(const TileLevel& lv, double* B, int64_t ldb, hipStream_t st) {
+  const size_t lds = size_t(lv.max_nt) * TILE * sizeof(double);
+  const double bytes = (lv.alg_tri + 2.0 * lv.alg_rows) * sizeof(double);
+  const int fam = lv.role == 0 ? KF_TRSM_I64 : KF_TRSM_G64;
+  {
+    KScope ks(fam, st, bytes, lv.alg_sq);
+    k_trsv_fwd<<<lv.nblk, NTH, lds, st>>>(lv.nt, lv.foff, lv.ioff, lv.roff, lv.L64, lv.Linv64, B, ldb);
+    NS_LAUNCH_CHECK();
+  }
+  {
+    KScope ks(fam, st, bytes, lv.alg_sq);
+    k_trsv_bwd<<<lv.nblk, NTH, lds, st>>>(lv.nt, lv.foff, lv.ioff, lv.roff, lv.LT64, lv.Linv64, B, ldb);
+    NS_LAUNCH_CHECK();
+  }
+}
+
+void tile_make_inverse(TileLevel& lv, bool fp32, hipStream_t st) {
+  if (lv.nblk == 0) return;
+  int maxpad = lv.max_nt * TILE;
+  lv.inv_ld = maxpad;
+  lv.Ainv64.alloc(lv.nrows_pad * maxpad);
+  NS_HIP(hipMemsetAsync(lv.Ainv64.p, 0, lv.nrows_pad * maxpad * sizeof(double), st));
+  k_identity_blocks<<<dim3((maxpad + 255) / 256, lv.nblk), 256, 0, st>>>(lv.nt, lv.roff, lv.Ainv64, maxpad);
+  NS_LAUNCH_CHECK();
+  tile_solve<double>(lv, lv.Ainv64.p, maxpad, maxpad, 64, st);
+  std::vector<int64_t> aoff(lv.nblk), lda(lv.nblk, maxpad);
+  std::vector<int> np(lv.nblk);
+  for (int b = 0; b < lv.nblk; ++b) {
+    aoff[b] = lv.h_roff[b] * maxpad;
+    np[b] = lv.h_nt[b] * TILE;
+  }
+  lv.inv_off.alloc(lv.nblk);
+  lv.inv_lda.alloc(lv.nblk);
+  lv.npad_d.alloc(lv.nblk);
+  NS_HIP(hipMemcpy(lv.inv_off.p, aoff.data(), lv.nblk * sizeof(int64_t), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(lv.inv_lda.p, lda.data(), lv.nblk * sizeof(int64_t), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(lv.npad_d.p, np.data(), lv.nblk * sizeof(int), hipMemcpyHostToDevice));
+  if (fp32) {
+    lv.Ainv32.alloc(lv.Ainv64.n);
+    k_to_fp32_g<<<2048, 256, 0, st>>>(lv.Ainv64, lv.Ainv32, lv.Ainv64.n);
+    NS_LAUNCH_CHECK();
+  }
+  NS_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace ns

@@ -416,6 +416,12 @@ void tile_make_fp32(TileLevel& lv, hipStream_t st) {
 template <class T>
 void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st) {
   if (lv.nblk == 0 || ncols == 0) return;
+  if constexpr (sizeof(T) == 8) {
+    if (ncols == 1 && trsv1_supported(lv)) {
+      tile_solve1(lv, B, ldb, st);
+      return;
+    }
+  }
   const T* L;
   const T* Li;
   if constexpr (sizeof(T) == 8) {
