@@ -386,7 +386,6 @@ void local_schur_build(Handle& h) {
   k_fill_B<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, h.AIG.ptr, h.AIG.col, h.AIG.val64, nG, cidx, W,
                                                         ldw);
   NS_LAUNCH_CHECK();
-  tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st);
   // per-block metadata for the batched GEMMs
   auto up = [&](DBuf<int64_t>& d, const std::vector<int64_t>& v) {
     d.alloc(nb);
@@ -400,6 +399,7 @@ void local_schur_build(Handle& h) {
   NS_HIP(hipMemcpy(ls.M.p, ls.h_m.data(), nb * sizeof(int), hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(ls.K.p, Kv.data(), nb * sizeof(int), hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(ls.Kg.p, ls.h_m.data(), nb * sizeof(int), hipMemcpyHostToDevice));
+  tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p);  // W_j = L_j^{-1} B_j
   up(ls.soff, soff);
   up(ls.sld, sld);
   up(ls.woff, woff);

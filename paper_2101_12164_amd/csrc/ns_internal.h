@@ -133,7 +133,8 @@ template <class T>
 void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st);
 // Forward sweep only: B <- L^{-1} B.
 template <class T>
-void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st);
+void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st,
+                    const int* ncols_blk = nullptr);
 // Single right-hand side sweeps (FP64) with 16-wave workgroups; need LT64.
 bool trsv1_supported(const TileLevel& lv);
 void tile_make_transposed(TileLevel& lv, hipStream_t st);

@@ -29,7 +29,9 @@ __device__ double block_sum(double v, double* red) {
 
 // Cyclic Jacobi: A (n x n, row stride ld, symmetric) is diagonalised in place;
 // V (stride ld) receives the eigenvectors in its columns.  cs: 2n doubles,
-// pr: n+1 ints.
+// pr: n+2 ints.  Each round applies the n/2 disjoint rotations of a
+// round-robin ordering at once: every 2x2 block (pair P rows, pair Q columns)
+// of A becomes J_P^T B J_Q, and V's column pairs become V J_Q.
 __device__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr, double* red) {
   const int tid = threadIdx.x;
   for (int e = tid; e < n * n; e += NT) {
@@ -40,6 +42,7 @@ __device__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr,
   if (n < 2) return;
   const int m = n + (n & 1);
   const int half = m / 2;
+  const float inv_half = 1.0f / float(half);
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < n * n; e += NT) {
@@ -50,7 +53,8 @@ __device__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr,
     }
     off = block_sum(off, red);
     tot = block_sum(tot, red);
-    if (!(off > 1e-30 * tot)) break;
+    // stop at the rounding floor: off-diagonal Frobenius norm <= 2 n eps ||A||_F
+    if (!(off > 2e-31 * double(n) * double(n) * tot)) break;
     for (int round = 0; round < m - 1; ++round) {
       if (tid < half) {
         auto pos = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + round) % (m - 1); };
@@ -63,44 +67,45 @@ __device__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr,
         double c = 1.0, s = 0.0;
         if (q < n) {
           const double apq = A[p * ld + q];
-          if (fabs(apq) > 1e-300) {
+          if (fabs(apq) > 1e-18 * sqrt(fabs(A[p * ld + p] * A[q * ld + q])) && fabs(apq) > 1e-300) {
             const double tau = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
           }
-        } else {
-          p = -1;
         }
         pr[2 * tid] = p;
-        pr[2 * tid + 1] = q;
+        pr[2 * tid + 1] = q;  // q == n marks the dummy partner of an odd n
         cs[2 * tid] = c;
         cs[2 * tid + 1] = s;
       }
       __syncthreads();
-      for (int t = tid; t < half * n; t += NT) {  // rows: A <- J^T A
-        const int k = t / n, j = t % n;
-        const int p = pr[2 * k];
-        if (p < 0) continue;
-        const int q = pr[2 * k + 1];
-        const double c = cs[2 * k], s = cs[2 * k + 1];
-        const double ap = A[p * ld + j], aq = A[q * ld + j];
-        A[p * ld + j] = c * ap - s * aq;
-        A[q * ld + j] = s * ap + c * aq;
+      // A <- J^T A J on all 2x2 pair blocks
+      for (int t = tid; t < half * half; t += NT) {
+        const int P = int((float(t) + 0.5f) * inv_half), Q = t - P * half;
+        const int p0 = pr[2 * P], q0 = pr[2 * P + 1], p1 = pr[2 * Q], q1 = pr[2 * Q + 1];
+        const double cP = cs[2 * P], sP = cs[2 * P + 1], cQ = cs[2 * Q], sQ = cs[2 * Q + 1];
+        const bool hq0 = q0 < n, hq1 = q1 < n;
+        const double b00 = A[p0 * ld + p1];
+        const double b01 = hq1 ? A[p0 * ld + q1] : 0.0;
+        const double b10 = hq0 ? A[q0 * ld + p1] : 0.0;
+        const double b11 = (hq0 && hq1) ? A[q0 * ld + q1] : 0.0;
+        const double x00 = cP * b00 - sP * b10, x01 = cP * b01 - sP * b11;  // J_P^T B
+        const double x10 = sP * b00 + cP * b10, x11 = sP * b01 + cP * b11;
+        A[p0 * ld + p1] = x00 * cQ - x01 * sQ;
+        if (hq1) A[p0 * ld + q1] = x00 * sQ + x01 * cQ;
+        if (hq0) A[q0 * ld + p1] = x10 * cQ - x11 * sQ;
+        if (hq0 && hq1) A[q0 * ld + q1] = x10 * sQ + x11 * cQ;
       }
-      __syncthreads();
-      for (int t = tid; t < half * n; t += NT) {  // columns: A <- A J, V <- V J
-        const int k = t % half, i = t / half;
-        const int p = pr[2 * k];
-        if (p < 0) continue;
-        const int q = pr[2 * k + 1];
-        const double c = cs[2 * k], s = cs[2 * k + 1];
-        const double ap = A[i * ld + p], aq = A[i * ld + q];
-        A[i * ld + p] = c * ap - s * aq;
-        A[i * ld + q] = s * ap + c * aq;
-        const double vp = V[i * ld + p], vq = V[i * ld + q];
-        V[i * ld + p] = c * vp - s * vq;
-        V[i * ld + q] = s * vp + c * vq;
+      // V <- V J
+      for (int t = tid; t < n * half; t += NT) {
+        const int i = int((float(t) + 0.5f) * inv_half), Q = t - i * half;
+        const int p1 = pr[2 * Q], q1 = pr[2 * Q + 1];
+        if (q1 >= n) continue;
+        const double cQ = cs[2 * Q], sQ = cs[2 * Q + 1];
+        const double vp = V[i * ld + p1], vq = V[i * ld + q1];
+        V[i * ld + p1] = cQ * vp - sQ * vq;
+        V[i * ld + q1] = sQ * vp + cQ * vq;
       }
       __syncthreads();
     }

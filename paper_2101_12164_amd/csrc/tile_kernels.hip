@@ -100,24 +100,49 @@ __device__ void trtri_lds(const double* s, double* x) {
 
 // Left-looking update of tile column j: C_ij = A_ij - sum_{l<j} L_il L_jl^T for
 // i >= j; the diagonal workgroup then factorises C_jj and inverts L_jj.
-__global__ __launch_bounds__(256) void k_chol_update(int j, const int* __restrict__ nt_arr,
+// Workgroup ids map all tiles of one block to one XCD (ids are dispatched
+// round-robin over the 8 XCDs), so the shared row j tiles L_jl hit that L2.
+// The next (L_il, L_jl) pair is held in registers while the MFMAs consume the
+// pair staged in LDS.
+__global__ __launch_bounds__(256) void k_chol_update(int j, int nblk, const int* __restrict__ nt_arr,
                                                      const int64_t* __restrict__ foff,
                                                      const int64_t* __restrict__ ioff, double* __restrict__ L,
                                                      double* __restrict__ Linv, int* err) {
   __shared__ double sA[TILE * LDT];
   __shared__ double sB[TILE * LDT];
-  const int b = blockIdx.y;
+  const int nbp8 = (nblk + 7) >> 3;
+  const int g = blockIdx.x;
+  const int slot = g >> 3;
+  const int b = (g & 7) + 8 * (slot % nbp8);
+  const int i = j + slot / nbp8;
+  if (b >= nblk) return;
   const int nt = nt_arr[b];
-  const int i = j + blockIdx.x;
   if (j >= nt || i >= nt) return;
   double* Lb = L + foff[b];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
   v4d acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  constexpr int PT = TILE2 / 256;
+  double ra[PT], rb[PT];
+  auto gload = [&](int l) {
+    const double* ga = Lb + tile_index(nt, i, l) * TILE2;
+    const double* gb = Lb + tile_index(nt, j, l) * TILE2;
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      ra[q] = ga[threadIdx.x + 256 * q];
+      rb[q] = gb[threadIdx.x + 256 * q];
+    }
+  };
+  if (j > 0) gload(0);
   for (int l = 0; l < j; ++l) {
     __syncthreads();
-    load_tile_lds(sA, Lb + tile_index(nt, i, l) * TILE2);
-    load_tile_lds(sB, Lb + tile_index(nt, j, l) * TILE2);
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      sA[(e >> 6) * LDT + (e & 63)] = ra[q];
+      sB[(e >> 6) * LDT + (e & 63)] = rb[q];
+    }
+    if (l + 1 < j) gload(l + 1);
     __syncthreads();
 #pragma unroll 4
     for (int kk = 0; kk < TILE; kk += 4) {
@@ -266,7 +291,7 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
                                               const int64_t* __restrict__ foff, const int64_t* __restrict__ ioff,
                                               const int64_t* __restrict__ roff, const T* __restrict__ L,
                                               const T* __restrict__ Linv, T* __restrict__ B, int64_t ldb,
-                                              int ncols) {
+                                              int ncols, const int* __restrict__ ncols_blk = nullptr) {
   using acc_t = typename MF<T>::acc_t;
   constexpr int NB = CW / 16;
   constexpr int YP = CW + 1;
@@ -277,6 +302,7 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
   if (b >= nblk) return;
   const int c0 = chunk * CW;
   if (c0 >= ncols) return;
+  if (ncols_blk && c0 >= ncols_blk[b]) return;  // this block's columns beyond its count are zero
   const int nt = nt_arr[b];
   T* Bb = B + roff[b] * ldb;
   const T* Lb = L + foff[b];
@@ -390,8 +416,9 @@ void tile_cholesky(TileLevel& lv, int* d_err, hipStream_t st) {
   for (int j = 0; j < lv.max_nt; ++j) {
     {
       KScope ks(KF_CHOL_UPDATE, st, lv.chol_bytes[j], lv.chol_upd_flops[j]);
-      dim3 g1(lv.max_nt - j, lv.nblk);
-      k_chol_update<<<g1, 256, 0, st>>>(j, lv.nt, lv.foff, lv.ioff, lv.L64, lv.Linv64, d_err);
+      const int nbp8 = (lv.nblk + 7) / 8;
+      k_chol_update<<<(lv.max_nt - j) * nbp8 * 8, 256, 0, st>>>(j, lv.nblk, lv.nt, lv.foff, lv.ioff, lv.L64,
+                                                                 lv.Linv64, d_err);
       NS_LAUNCH_CHECK();
     }
     if (lv.max_nt - j - 1 > 0) {
@@ -441,7 +468,8 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
 }
 
 template <class T>
-void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st) {
+void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st,
+                    const int* ncols_blk) {
   if (lv.nblk == 0 || ncols == 0) return;
   const T* L;
   const T* Li;
@@ -460,18 +488,18 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
             st, bytes, flops);
   if (cw == 16) {
     k_trsm<T, 16, true><<<nbp8 * 8 * ((ncols + 15) / 16), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
-                                                                         Li, B, ldb, ncols);
+                                                                         Li, B, ldb, ncols, ncols_blk);
   } else if (cw == 32) {
     k_trsm<T, 32, true><<<nbp8 * 8 * ((ncols + 31) / 32), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
-                                                                         Li, B, ldb, ncols);
+                                                                         Li, B, ldb, ncols, ncols_blk);
   } else {
     k_trsm<T, 64, true><<<nbp8 * 8 * ((ncols + 63) / 64), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
-                                                                         Li, B, ldb, ncols);
+                                                                         Li, B, ldb, ncols, ncols_blk);
   }
   NS_LAUNCH_CHECK();
 }
 
-template void tile_solve_fwd<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t);
+template void tile_solve_fwd<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t, const int*);
 template void tile_solve<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t);
 template void tile_solve<float>(const TileLevel&, float*, int64_t, int, int, hipStream_t);
 

@@ -58,9 +58,14 @@ __global__ void k_gram_final(int nchunk, int nout, const double* __restrict__ pa
                              double alpha, double beta) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= nout) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * nout + o];
-  G[o] = alpha * s + (beta != 0.0 ? beta * G[o] : 0.0);
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int c = 0;
+  for (; c + 8 <= nchunk; c += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += part[int64_t(c + u) * nout + o];
+  for (; c < nchunk; ++c) s[0] += part[int64_t(c) * nout + o];
+  const double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  G[o] = alpha * t + (beta != 0.0 ? beta * G[o] : 0.0);
 }
 
 // Out[r, c] = beta * Out[r, c] + sum_m X[r, m] M[m, c] + sum_m X2[r, m] M2[m, c]
