@@ -87,15 +87,32 @@ __global__ __launch_bounds__(1024) void k_compact(int64_t nG, const int* __restr
   if (mode == 0 && threadIdx.x == 0) cnt[j] = base;
 }
 
-// B (padded interior rows x ldb) = A_IGamma restricted to each block's Gamma_j columns.
-__global__ void k_fill_B(int64_t nrows, const int32_t* __restrict__ rblk, const int64_t* __restrict__ ptr,
-                         const int32_t* __restrict__ col, const double* __restrict__ val, int64_t nG,
-                         const int32_t* __restrict__ cidx, double* __restrict__ B, int64_t ldb) {
+// B (padded interior rows x ldb) = A_IGamma restricted to each block's Gamma_j
+// columns; first[j * ldb + c] = first block-local row with a nonzero in column c.
+__global__ void k_fill_B(int64_t nrows, const int32_t* __restrict__ rblk, const int64_t* __restrict__ roff,
+                         const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                         const double* __restrict__ val, int64_t nG, const int32_t* __restrict__ cidx,
+                         double* __restrict__ B, int64_t ldb, int* __restrict__ first) {
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   const int j = rblk[r];
   if (j < 0) return;
-  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) B[r * ldb + cidx[int64_t(j) * nG + col[e]]] = val[e];
+  const int lr = int(r - roff[j]);
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) {
+    const int c = cidx[int64_t(j) * nG + col[e]];
+    B[r * ldb + c] = val[e];
+    atomicMin(&first[int64_t(j) * ldb + c], lr);
+  }
+}
+
+// per (block, 64-column tile): first tile row holding a nonzero of any column
+__global__ void k_first_tiles(int nb, int ldb, int ntiles, const int* __restrict__ first, int* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nb * ntiles) return;
+  const int j = idx / ntiles, t = idx % ntiles;
+  int m = INT32_MAX;
+  for (int c = t * 64; c < min(ldb, t * 64 + 64); ++c) m = min(m, first[int64_t(j) * ldb + c]);
+  out[idx] = m == INT32_MAX ? INT32_MAX / 128 : m / TILE;
 }
 
 // Batched C_j = A_j^T B_j on MFMA.  A_j: K_j x M_j, B_j: K_j x N (row-major,
@@ -104,6 +121,8 @@ __global__ void k_fill_B(int64_t nrows, const int32_t* __restrict__ rblk, const 
 // one-deep register prefetch.  With sym != 0 (A = B, square C) only tiles on
 // or below the diagonal are computed and each is also written transposed.
 struct GemmBatch {
+  const int* kstart;    // optional [j * kstride + tile]: first 64-row tile of nonzeros of A/B column tile
+  int kstride;
   const int* M;         // rows of C per block
   const int* K;         // reduction length per block
   const int64_t* aoff;  // element offset of A_j
@@ -142,6 +161,13 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restric
   //              NC == 16: wave w owns rows [16 w, +16) x cols [0, 16)
   const int wr = NC == 64 ? 32 * (w >> 1) : 16 * w;
   const int wc = NC == 64 ? 32 * (w & 1) : 0;
+  // columns of A and B are zero above their first nonzero tile row: start K there
+  int kbeg = 0;
+  if (g.kstart) {
+    const int ka = g.kstart[j * g.kstride + tm];
+    const int kb = g.kstart[j * g.kstride + (n0 >> 6)];
+    kbeg = min(max(ka, kb) * 64, K);
+  }
   acc_t acc[MW][MW];
 #pragma unroll
   for (int a = 0; a < MW; ++a)
@@ -161,8 +187,8 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restric
       rb[q] = (k0 + kk < K && n0 + n < Nj) ? Bj[int64_t(k0 + kk) * ldb + n0 + n] : T(0);
     }
   };
-  gload(0);
-  for (int k0 = 0; k0 < K; k0 += KC) {
+  if (kbeg < K) gload(kbeg);
+  for (int k0 = kbeg; k0 < K; k0 += KC) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PA; ++q) {
@@ -307,7 +333,8 @@ void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStr
     A = lv.Ainv64.p;
   else
     A = lv.Ainv32.p;
-  GemmBatch g{lv.npad_d, lv.npad_d, lv.inv_off, lv.inv_lda, lv.roff, ncols, ncols, lv.roff, ncols, nullptr, ncols};
+  GemmBatch g{nullptr, 0, lv.npad_d, lv.npad_d, lv.inv_off, lv.inv_lda, lv.roff, ncols, ncols, lv.roff, ncols, nullptr,
+              ncols};
   double sq = 0;
   for (int b = 0; b < lv.nblk; ++b) sq += double(lv.h_nb[b]) * lv.h_nb[b];
   KScope ks(sizeof(T) == 8 ? KF_INV64 : KF_INV32, st, (sq + 2.0 * lv.alg_rows * ncols) * sizeof(T), 2.0 * sq * ncols);
@@ -383,8 +410,15 @@ void local_schur_build(Handle& h) {
   DBuf<double> W;
   W.alloc(nIp * ldw);
   NS_HIP(hipMemsetAsync(W.p, 0, nIp * ldw * sizeof(double), st));
-  k_fill_B<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, h.AIG.ptr, h.AIG.col, h.AIG.val64, nG, cidx, W,
-                                                        ldw);
+  DBuf<int> first, ftile;
+  first.alloc(int64_t(nb) * ldw);
+  NS_HIP(hipMemsetAsync(first.p, 0x7F, int64_t(nb) * ldw * sizeof(int), st));  // ~INT_MAX
+  k_fill_B<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, lv.roff, h.AIG.ptr, h.AIG.col, h.AIG.val64, nG,
+                                                        cidx, W, ldw, first);
+  NS_LAUNCH_CHECK();
+  const int ctiles = int((ldw + 63) / 64);
+  ftile.alloc(int64_t(nb) * ctiles);
+  k_first_tiles<<<(nb * ctiles + 255) / 256, 256, 0, st>>>(nb, int(ldw), ctiles, first, ftile);
   NS_LAUNCH_CHECK();
   // per-block metadata for the batched GEMMs
   auto up = [&](DBuf<int64_t>& d, const std::vector<int64_t>& v) {
@@ -399,7 +433,20 @@ void local_schur_build(Handle& h) {
   NS_HIP(hipMemcpy(ls.M.p, ls.h_m.data(), nb * sizeof(int), hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(ls.K.p, Kv.data(), nb * sizeof(int), hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(ls.Kg.p, ls.h_m.data(), nb * sizeof(int), hipMemcpyHostToDevice));
-  tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p);  // W_j = L_j^{-1} B_j
+  {
+    // algorithmic flops: each column c costs (n_b - r_c)^2 below its first nonzero row r_c (approximated
+    // per 64-column tile by the tile's first row)
+    std::vector<int> hf(size_t(nb) * ctiles);
+    NS_HIP(hipMemcpy(hf.data(), ftile.p, hf.size() * sizeof(int), hipMemcpyDeviceToHost));
+    double fl = 0.0;
+    for (int j = 0; j < nb; ++j)
+      for (int t = 0; t < ctiles; ++t) {
+        const int cols = std::max(0, std::min(64, ls.h_m[j] - 64 * t));
+        const double rem = std::max(0.0, double(lv.h_nb[j]) - 64.0 * std::min(hf[size_t(j) * ctiles + t], 1 << 20));
+        fl += rem * rem * cols;
+      }
+    tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p, ftile.p, fl);  // W_j = L_j^{-1} B_j
+  }
   up(ls.soff, soff);
   up(ls.sld, sld);
   up(ls.woff, woff);
@@ -408,7 +455,7 @@ void local_schur_build(Handle& h) {
   NS_HIP(hipMemsetAsync(ls.S64.p, 0, ls.S64.n * sizeof(double), st));
   {
     // B_j = W_j: offset woff[j], common leading dimension ldw
-    GemmBatch g{ls.M, ls.K, ls.woff, ls.wld, ls.woff, 1, ldw, ls.soff, 1, ls.sld, 0};
+    GemmBatch g{ftile.p, ctiles, ls.M, ls.K, ls.woff, ls.wld, ls.woff, 1, ldw, ls.soff, 1, ls.sld, 0};
     double fl = 0;
     for (int j = 0; j < nb; ++j) fl += 2.0 * Kv[j] * ls.h_m[j] * (ls.h_m[j] + 1) / 2;
     KScope ks(KF_LS_FORM, st, double(nIp) * ldw * 8.0, fl);
@@ -485,7 +532,7 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
   NS_LAUNCH_CHECK();
   {
     // X_j / Y_j: stacked rows goff[j], leading dimension ncols
-    GemmBatch g{ls.M, ls.Kg, ls.soff, ls.sld, ls.goff, ncols, ncols, ls.goff, ncols, nullptr, ncols};
+    GemmBatch g{nullptr, 0, ls.M, ls.Kg, ls.soff, ls.sld, ls.goff, ncols, ncols, ls.goff, ncols, nullptr, ncols};
     KScope ks(sizeof(T) == 8 ? KF_LS_APPLY64 : KF_LS_APPLY32, st,
               ls.alg_bytes * sizeof(T) + 2.0 * np * ncols * sizeof(T), ls.alg_flops * ncols);
     launch_gemm<T>(ls, S, Xg, Yg, ncols, st, false, g, ls.max_m);

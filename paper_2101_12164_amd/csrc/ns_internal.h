@@ -132,9 +132,12 @@ void tile_make_fp32(TileLevel& lv, hipStream_t st);
 template <class T>
 void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st);
 // Forward sweep only: B <- L^{-1} B.
+// ncols_blk: optional per-block column count (chunks beyond it are skipped);
+// first_tile: optional [block * nchunks + chunk] first tile row with a nonzero
+// right-hand side (rows above stay zero); alg_flops overrides the timing work.
 template <class T>
 void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st,
-                    const int* ncols_blk = nullptr);
+                    const int* ncols_blk = nullptr, const int* first_tile = nullptr, double alg_flops = 0.0);
 // Single right-hand side sweeps (FP64) with 16-wave workgroups; need LT64.
 bool trsv1_supported(const TileLevel& lv);
 void tile_make_transposed(TileLevel& lv, hipStream_t st);

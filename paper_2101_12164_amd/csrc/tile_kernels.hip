@@ -291,7 +291,8 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
                                               const int64_t* __restrict__ foff, const int64_t* __restrict__ ioff,
                                               const int64_t* __restrict__ roff, const T* __restrict__ L,
                                               const T* __restrict__ Linv, T* __restrict__ B, int64_t ldb,
-                                              int ncols, const int* __restrict__ ncols_blk = nullptr) {
+                                              int ncols, const int* __restrict__ ncols_blk = nullptr,
+                                              const int* __restrict__ first_tile = nullptr, int nchunk_all = 0) {
   using acc_t = typename MF<T>::acc_t;
   constexpr int NB = CW / 16;
   constexpr int YP = CW + 1;
@@ -310,12 +311,14 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rl = lane & 15, kq = lane >> 4;
   TrsmStage<T, CW> s0, s1;
-  for (int step = 0; step < nt; ++step) {
+  // forward sweeps whose right-hand side is zero above tile row `first` start there
+  const int first = (FWD && first_tile) ? min(first_tile[b * nchunk_all + chunk], nt) : 0;
+  for (int step = first; step < nt; ++step) {
     const int i = FWD ? step : nt - 1 - step;
     acc_t acc[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) acc[q] = acc_t{0, 0, 0, 0};
-    const int l0 = FWD ? 0 : i + 1, nl = FWD ? i : nt - 1 - i;
+    const int l0 = FWD ? first : i + 1, nl = FWD ? i - first : nt - 1 - i;
     auto tile = [&](int t) { return Lb + (FWD ? tile_index(nt, i, l0 + t) : tile_index(nt, l0 + t, i)) * TILE2; };
     auto rows = [&](int t) { return Bb + int64_t(l0 + t) * TILE * ldb; };
     auto mma_stage = [&]() {
@@ -469,7 +472,7 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
 
 template <class T>
 void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st,
-                    const int* ncols_blk) {
+                    const int* ncols_blk, const int* first_tile, double alg_flops) {
   if (lv.nblk == 0 || ncols == 0) return;
   const T* L;
   const T* Li;
@@ -483,23 +486,25 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
   if (cw != 16 && cw != 32) cw = 64;
   const int nbp8 = (lv.nblk + 7) / 8;
   const double bytes = (lv.alg_tri + 2.0 * lv.alg_rows * ncols) * sizeof(T);
-  const double flops = lv.alg_sq * ncols;
+  const double flops = alg_flops > 0 ? alg_flops : lv.alg_sq * ncols;
   KScope ks(lv.role == 0 ? (sizeof(T) == 8 ? KF_TRSM_I64 : KF_TRSM_I32) : (sizeof(T) == 8 ? KF_TRSM_G64 : KF_TRSM_G32),
             st, bytes, flops);
+  const int nchunk_all = (ncols + cw - 1) / cw;
   if (cw == 16) {
     k_trsm<T, 16, true><<<nbp8 * 8 * ((ncols + 15) / 16), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
-                                                                         Li, B, ldb, ncols, ncols_blk);
+                                                                         Li, B, ldb, ncols, ncols_blk, first_tile, nchunk_all);
   } else if (cw == 32) {
     k_trsm<T, 32, true><<<nbp8 * 8 * ((ncols + 31) / 32), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
-                                                                         Li, B, ldb, ncols, ncols_blk);
+                                                                         Li, B, ldb, ncols, ncols_blk, first_tile, nchunk_all);
   } else {
     k_trsm<T, 64, true><<<nbp8 * 8 * ((ncols + 63) / 64), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
-                                                                         Li, B, ldb, ncols, ncols_blk);
+                                                                         Li, B, ldb, ncols, ncols_blk, first_tile, nchunk_all);
   }
   NS_LAUNCH_CHECK();
 }
 
-template void tile_solve_fwd<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t, const int*);
+template void tile_solve_fwd<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t, const int*, const int*,
+                                     double);
 template void tile_solve<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t);
 template void tile_solve<float>(const TileLevel&, float*, int64_t, int, int, hipStream_t);
 
