@@ -89,19 +89,30 @@ void check_chol(Handle& h, int level, ns_setup_info* info) {
 }
 
 // Orthonormal basis of the columns of V (n_G x s, ld s) into P, dropping
-// directions with singular value <= drop * sigma_max: eigen-decomposition of
-// the Gram matrix, then one Cholesky-QR pass to restore orthogonality.
+// directions with singular value <= drop * sigma_max.  When a Cholesky of the
+// Gram matrix certifies that every singular value ratio exceeds the drop
+// tolerance, nothing is dropped and Cholesky-QR2 yields a basis of the same
+// span; otherwise the Gram matrix is eigen-decomposed (SVQB: keep the
+// eigenpairs above drop^2 * lambda_max) followed by one Cholesky-QR pass.
 // Returns the number of columns kept.  Q is used as scratch.
 template <class T>
 int orth(Handle& h, SmallMats& sm, DBuf<double>& work, const T* V, T*& P, T*& Q, int s) {
   hipStream_t st = h.stream;
   const int64_t nG = h.nG;
+  const double drop2 = h.drop_rel * h.drop_rel;
   gram<T, T>(nG, V, s, s, V, s, s, sm.Gorth, 1.0, 0.0, work, st);
-  small_svqb(s, sm.Gorth, h.drop_rel * h.drop_rel, sm.Torth, sm.rank, h.small.p, st);
-  int r = 0;
-  read_back(h, &r, sm.rank, 1);
-  if (r == 0) return 0;
-  ts_update<T>(nG, r, P, s, 0.0, 1.0, V, s, s, sm.Torth, s, nullptr, 0, 0, nullptr, 0, st);
+  small_cholqr(s, sm.Gorth, 0.0, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.small.p, st, drop2, sm.rank + 2);
+  int okv = 0;
+  read_back(h, &okv, sm.rank + 2, 1);
+  int r = s;
+  if (okv) {
+    ts_update<T>(nG, s, P, s, 0.0, 1.0, V, s, s, sm.Rinv, s, nullptr, 0, 0, nullptr, 0, st);
+  } else {
+    small_svqb(s, sm.Gorth, drop2, sm.Torth, sm.rank, h.small.p, st);
+    read_back(h, &r, sm.rank, 1);
+    if (r == 0) return 0;
+    ts_update<T>(nG, r, P, s, 0.0, 1.0, V, s, s, sm.Torth, s, nullptr, 0, 0, nullptr, 0, st);
+  }
   gram<T, T>(nG, P, s, r, P, s, r, sm.Gorth, 1.0, 0.0, work, st);
   small_cholqr(r, sm.Gorth, 0.0, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.small.p, st);
   ts_update<T>(nG, r, Q, s, 0.0, 1.0, P, s, r, sm.Rinv, r, nullptr, 0, 0, nullptr, 0, st);

@@ -46,8 +46,10 @@ void small_chol_apply(int r, const double* L, const double* B, int64_t ldb, doub
 // for the eigenpairs with lambda_c > drop2 * lambda_max, descending; out[0] = number kept.
 void small_svqb(int s, const double* G, double drop2, double* T, int* out, double* gw, hipStream_t st);
 // R = chol(G + shift_coef * trace(G) * I)^T (upper); Rinv = R^{-1}; Racc <- R * Racc (or R when init).
+// With ok != NULL: ok[0] = 1 when the Cholesky succeeded and 1/||R^{-1}||_F^2 > certify * trace(G), which
+// proves lambda_min(G) / lambda_max(G) > certify (so no direction falls below that ratio).
 void small_cholqr(int s, const double* G, double shift_coef, double* Rinv, double* Racc, int init, int* flag,
-                  double* gw, hipStream_t st);
+                  double* gw, hipStream_t st, double certify = 0.0, int* ok = nullptr);
 // Nystrom core: EVD of sym(C), keep eigenvalues >= eps_rel * max; T = (R V1) D1^{-1} (R V1)^T;
 // EVD of T descending; Wk = first k' eigenvectors (s x k, ld k), Ek = eigenvalues; out = {r, k'}.
 void small_nystrom(int s, int k, const double* C, const double* R, double eps_rel, double* Wk, double* Ek, int* out,

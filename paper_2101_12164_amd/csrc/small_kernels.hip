@@ -264,14 +264,16 @@ __global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, doubl
 }
 
 __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const double* G, double shift_coef, double* Rinv,
-                                                     double* Racc, int init, int* flag, double* gw) {
+                                                     double* Racc, int init, int* flag, double* gw, double certify,
+                                                     int* ok) {
   extern __shared__ double sm[];
   __shared__ int sinfo;
-  __shared__ double sshift;
+  __shared__ double sshift, strace;
   if (threadIdx.x == 0) {
     double tr = 0.0;
     for (int i = 0; i < s; ++i) tr += G[i * s + i];
     sshift = shift_coef * tr;
+    strace = tr;
   }
   __syncthreads();
   const double shift = sshift;
@@ -299,9 +301,27 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const double* G, dou
     __syncthreads();
   }
   // Rinv = (L^{-1})^T (upper); R = L^T
+  double fro = 0.0;
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
-    Rinv[e] = X[j * ld + i];
+    const double x = X[j * ld + i];
+    Rinv[e] = x;
+    fro += x * x;
+  }
+  if (ok) {
+    // lambda_min(G) >= 1 / ||L^{-1}||_F^2 and lambda_max(G) <= trace(G): certify that no
+    // singular value ratio of the block is at or below the drop tolerance
+    __shared__ double red[NT];
+    red[threadIdx.x] = fro;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const double lmin_lb = 1.0 / red[0];
+      ok[0] = (sinfo == 0 && lmin_lb > certify * strace) ? 1 : 0;
+    }
   }
   __syncthreads();
   // Racc <- R * Racc ; X reused for the product
@@ -455,9 +475,9 @@ void small_svqb(int s, const double* G, double drop2, double* T, int* out, doubl
 }
 
 void small_cholqr(int s, const double* G, double shift_coef, double* Rinv, double* Racc, int init, int* flag,
-                  double* gw, hipStream_t st) {
+                  double* gw, hipStream_t st, double certify, int* ok) {
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
-  k_small_cholqr<<<1, NT, evd_lds(s), st>>>(s, G, shift_coef, Rinv, Racc, init, flag, gw);
+  k_small_cholqr<<<1, NT, evd_lds(s), st>>>(s, G, shift_coef, Rinv, Racc, init, flag, gw, certify, ok);
   NS_LAUNCH_CHECK();
 }
 
