@@ -434,8 +434,9 @@ void local_schur_build(Handle& h) {
   NS_HIP(hipMemcpy(ls.K.p, Kv.data(), nb * sizeof(int), hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(ls.Kg.p, ls.h_m.data(), nb * sizeof(int), hipMemcpyHostToDevice));
   {
-    // algorithmic flops: each column c costs (n_b - r_c)^2 below its first nonzero row r_c (approximated
-    // per 64-column tile by the tile's first row)
+    // algorithmic flops: a column with first nonzero row r_c costs, over the rows below r_c, two flops per
+    // factor entry within the half-bandwidth bw_j, i.e. t(t-1) + 2 (rem - t) bw_j + rem with rem = n_b - r_c
+    // and t = min(rem, bw_j) (r_c approximated per 64-column tile by the tile's first row)
     std::vector<int> hf(size_t(nb) * ctiles);
     NS_HIP(hipMemcpy(hf.data(), ftile.p, hf.size() * sizeof(int), hipMemcpyDeviceToHost));
     double fl = 0.0;
@@ -443,7 +444,8 @@ void local_schur_build(Handle& h) {
       for (int t = 0; t < ctiles; ++t) {
         const int cols = std::max(0, std::min(64, ls.h_m[j] - 64 * t));
         const double rem = std::max(0.0, double(lv.h_nb[j]) - 64.0 * std::min(hf[size_t(j) * ctiles + t], 1 << 20));
-        fl += rem * rem * cols;
+        const double tb = std::min(rem, double(lv.h_bw[j]));
+        fl += (tb * (tb - 1.0) + 2.0 * (rem - tb) * lv.h_bw[j] + rem) * cols;
       }
     tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p, ftile.p, fl);  // W_j = L_j^{-1} B_j
   }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -54,23 +55,47 @@ struct DBuf {
   operator T*() const { return p; }
 };
 
-// A batch of dense SPD blocks in tile storage.
+// Tile band storage.  A block of nt tile rows whose nonzeros lie within nbt
+// tile diagonals below the main one (0 <= nbt <= nt - 1; nbt = nt - 1 is the
+// full lower tile triangle) stores, tile column by tile column, the tiles
+// (j, j), (j + 1, j), ..., (min(nt - 1, j + nbt), j).  The Cholesky factor of
+// a band matrix keeps the band, so the factor lives in the same storage.
+__host__ __device__ inline int64_t band_col_off(int nt, int nbt, int j) {
+  const int a = nt - nbt;  // tile columns that hold nbt + 1 tiles
+  if (j <= a) return int64_t(j) * (nbt + 1);
+  const int64_t m = j - a;
+  return int64_t(a) * (nbt + 1) + m * nt - m * (a + j - 1) / 2;
+}
+__host__ __device__ inline int64_t band_tile_index(int nt, int nbt, int i, int j) {  // tile (i, j), 0 <= i - j <= nbt
+  return band_col_off(nt, nbt, j) + (i - j);
+}
+// Element (r, c), r >= c, of a band tile block (tiles TILE x TILE column-major).
+__host__ __device__ inline int64_t band_elem(int nt, int nbt, int r, int c) {
+  return band_tile_index(nt, nbt, r >> 6, c >> 6) * TILE2 + (c & 63) * TILE + (r & 63);
+}
+// Tile half-bandwidth that holds an element half-bandwidth bw of an n-row block.
+inline int band_tiles_for(int n, int bw) {
+  const int nt = (n + TILE - 1) / TILE;
+  return nt == 0 ? 0 : std::min(nt - 1, (bw + TILE - 1) / TILE);
+}
+
+// A batch of SPD blocks in band tile storage.
 //   Block b has nb[b] rows, padded to nt[b] * TILE; padding rows carry an
 //   identity diagonal so the padded block stays SPD and leaves padded
-//   right-hand-side rows at zero.
-//   Factor tiles: the lower tile triangle, tile columns in order, column j
-//   holding tiles (j, j), (j+1, j), ..., (nt-1, j); each tile TILE x TILE
-//   column-major.  Block b's first tile is at element foff[b].
+//   right-hand-side rows at zero.  bw[b] is the element half-bandwidth of the
+//   block (largest r - c of a nonzero) and nbt[b] the tile half-bandwidth.
+//   Factor tiles: band storage above, block b's first tile at element foff[b].
 //   Inverse diagonal tiles: nt[b] tiles from element ioff[b].
 //   Padded rows of block b start at row roff[b] of a padded right-hand side.
+// layout() sets the row layout; layout_band() the band and the factor storage.
 struct TileLevel {
   int role = 0;  // 0: interior blocks, 1: interface blocks (timing family)
   int nblk = 0;
-  int max_nt = 0;
-  std::vector<int> h_nb, h_nt;
+  int max_nt = 0, max_nbt = 0;
+  std::vector<int> h_nb, h_nt, h_bw, h_nbt;
   std::vector<int64_t> h_foff, h_ioff, h_roff;
   int64_t nrows_pad = 0, f_elems = 0, i_elems = 0;
-  DBuf<int> nt, nb;
+  DBuf<int> nt, nb, nbt;
   DBuf<int64_t> foff, ioff, roff;
   DBuf<double> L64, Linv64;
   DBuf<float> L32, Linv32;
@@ -81,14 +106,14 @@ struct TileLevel {
   DBuf<int64_t> inv_off, inv_lda;
   DBuf<int> npad_d;
   int64_t inv_ld = 0;
-  // algorithmic work: sum of nb(nb+1)/2, sum of nb^2, sum of nb; per tile column
-  // of the factorisation: update flops, panel flops, bytes
+  // algorithmic work: factor entries (band lower triangle), flops of one
+  // triangular sweep per right-hand side, rows; per tile column of the
+  // factorisation: update flops, panel flops, bytes
   double alg_tri = 0, alg_sq = 0, alg_rows = 0;
   std::vector<double> chol_upd_flops, chol_pan_flops, chol_bytes;
-  void layout(const std::vector<int>& sizes);  // host: fills h_*, allocates index arrays + FP64 storage
+  void layout(const std::vector<int>& sizes);   // host: row layout + index arrays
+  void layout_band(const std::vector<int>& bw);  // host: band, factor storage (allocates L64, Linv64)
 };
-
-inline int64_t tri_tiles(int nt) { return int64_t(nt) * (nt + 1) / 2; }
 
 // ---------------------------------------------------------------- kernel timing
 // Families of launches that can be timed with HIP events (opt-in, ABI

@@ -312,10 +312,6 @@ __global__ void k_maps(int64_t n, NodeMaps m, int32_t* iperm, int32_t* icomp, in
   }
 }
 
-__device__ __forceinline__ int64_t tile_elem(int nt, int r, int c) {  // element (r, c), r >= c, of a tile block
-  const int i = r >> 6, j = c >> 6;
-  return (int64_t(j) * nt - int64_t(j) * (j - 1) / 2 + (i - j)) * TILE2 + (c & 63) * TILE + (r & 63);
-}
 
 struct Outs {
   int64_t *pIG, *pGI, *pGG, *psJ, *pJs;  // row pointers (counting pass: counts at [row+1])
@@ -323,13 +319,15 @@ struct Outs {
   double *vIG, *vGI, *vGG, *vsJ, *vJs;
   float *fIG, *fGI, *fGG, *fsJ, *fJs;
   double *L1, *L2, *LJ;
-  const int *nt1, *nt2;
+  const int *nt1, *nt2, *nbt1, *nbt2;
   const int64_t *foff1, *foff2;
   int ntJ;
+  int *bw1, *bw2;  // counting pass: element half-bandwidth of every diagonal block
 };
 
-// One thread per row.  FILL = false: count entries per CSR row; FILL = true:
-// write CSR entries and the lower triangles of the dense diagonal blocks.
+// One thread per row.  FILL = false: count entries per CSR row and find the
+// half-bandwidth of every diagonal block; FILL = true: write CSR entries and
+// the lower triangles of the diagonal blocks (band tile storage).
 template <bool FILL>
 __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
                           const double* __restrict__ val, NodeMaps m, Outs o, int* flags) {
@@ -339,6 +337,7 @@ __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int3
   const int ri = m.rank[i];
   int64_t nIG = 0, nGI = 0, nGG = 0, nsJ = 0, nJs = 0;
   int64_t rowIG = 0, rowG = 0, rowsJ = 0, rowJs = 0;
+  int bw = 0;
   if (pi >= 0) {
     rowIG = m.roff1[pi] + ri;
   } else {
@@ -355,8 +354,10 @@ __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int3
       if (pj >= 0) {
         if (pj != pi) {
           flags[F_DBBD1] = 1;
-        } else if (FILL && ri >= rj) {
-          o.L1[o.foff1[pi] + tile_elem(o.nt1[pi], ri, rj)] = v;
+        } else if (!FILL) {
+          bw = max(bw, ri - rj);
+        } else if (ri >= rj) {
+          o.L1[o.foff1[pi] + band_elem(o.nt1[pi], o.nbt1[pi], ri, rj)] = v;
         }
       } else {
         if (FILL) {
@@ -388,8 +389,10 @@ __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int3
           if (pj <= -2) {
             if (pj != pi)
               flags[F_DBBD2] = 1;
-            else if (FILL && ri >= rj)
-              o.L2[o.foff2[-2 - pi] + tile_elem(o.nt2[-2 - pi], ri, rj)] = v;
+            else if (!FILL)
+              bw = max(bw, ri - rj);
+            else if (ri >= rj)
+              o.L2[o.foff2[-2 - pi] + band_elem(o.nt2[-2 - pi], o.nbt2[-2 - pi], ri, rj)] = v;
           } else {  // junction column
             if (FILL) {
               const int64_t q = o.psJ[rowsJ] + nsJ;
@@ -409,13 +412,17 @@ __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int3
             }
             ++nJs;
           } else if (FILL && ri >= rj) {
-            o.LJ[tile_elem(o.ntJ, ri, rj)] = v;
+            o.LJ[band_elem(o.ntJ, o.ntJ - 1, ri, rj)] = v;
           }
         }
       }
     }
   }
   if (!FILL) {
+    if (bw > 0) {
+      if (pi >= 0) atomicMax(o.bw1 + pi, bw);
+      if (pi <= -2) atomicMax(o.bw2 + (-2 - pi), bw);
+    }
     if (pi >= 0) {
       o.pIG[rowIG + 1] = nIG;
     } else {
@@ -428,13 +435,14 @@ __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int3
 }
 
 // Identity on the padded diagonal of every block.
-__global__ void k_pad_identity(const int* __restrict__ nt_arr, const int* __restrict__ nb_arr,
-                               const int64_t* __restrict__ foff, double* __restrict__ L) {
+__global__ void k_pad_identity(const int* __restrict__ nt_arr, const int* __restrict__ nbt_arr,
+                               const int* __restrict__ nb_arr, const int64_t* __restrict__ foff,
+                               double* __restrict__ L) {
   const int b = blockIdx.y;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int nt = nt_arr[b], nb = nb_arr[b];
   if (r < nb || r >= nt * TILE) return;
-  L[foff[b] + tile_elem(nt, r, r)] = 1.0;
+  L[foff[b] + band_elem(nt, nbt_arr[b], r, r)] = 1.0;
 }
 
 __global__ void k_csr_to_dense(int64_t nrows, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
@@ -453,13 +461,13 @@ __global__ void k_junction_update(int nJ, int ntJ, const int64_t* __restrict__ p
   if (jj > ji) return;
   double acc = 0.0;
   for (int64_t e = ptr[ji]; e < ptr[ji + 1]; ++e) acc += val[e] * E[int64_t(col[e]) * nJ + jj];
-  LJ[tile_elem(ntJ, ji, jj)] -= acc;
+  LJ[band_elem(ntJ, ntJ - 1, ji, jj)] -= acc;
 }
 
 void pad_identity(TileLevel& lv, hipStream_t st) {
   if (lv.nblk == 0) return;
   dim3 g((lv.max_nt * TILE + 255) / 256, lv.nblk);
-  k_pad_identity<<<g, 256, 0, st>>>(lv.nt, lv.nb, lv.foff, lv.L64);
+  k_pad_identity<<<g, 256, 0, st>>>(lv.nt, lv.nbt, lv.nb, lv.foff, lv.L64);
   NS_LAUNCH_CHECK();
 }
 
@@ -583,17 +591,30 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
   o.pGG = h.AGG.ptr;
   o.psJ = h.AsJ.ptr;
   o.pJs = h.AJs.ptr;
-  o.nt1 = h.L1.nt;
-  o.nt2 = h.L2.nt;
-  o.foff1 = h.L1.foff;
-  o.foff2 = h.L2.foff;
-  o.ntJ = h.LJ.nblk ? h.LJ.h_nt[0] : 0;
+  DBuf<int> bwd;
+  bwd.alloc(h.nsub + h.nl2 + 1);
+  NS_HIP(hipMemsetAsync(bwd.p, 0, bwd.n * sizeof(int), st));
+  o.bw1 = bwd.p;
+  o.bw2 = bwd.p + h.nsub;
   k_extract<false><<<gn, 256, 0, st>>>(n, row_ptr, col, val, m, o, flags);
   NS_LAUNCH_CHECK();
+  std::vector<int> bwh(bwd.n);
+  NS_HIP(hipMemcpyAsync(bwh.data(), bwd.p, bwd.n * sizeof(int), hipMemcpyDeviceToHost, st));
   NS_HIP(hipMemcpyAsync(h.hflags, flags, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
   NS_HIP(hipStreamSynchronize(st));
   if (h.hflags[F_DBBD1]) fail(INVALID_ARG, "partition is not DBBD: interior nodes of different subdomains are coupled");
   if (h.hflags[F_DBBD2]) fail(INVALID_ARG, "interface split invalid: nodes of different interface blocks are coupled");
+  // band storage of the diagonal blocks (the junction block is dense)
+  h.L1.layout_band(std::vector<int>(bwh.begin(), bwh.begin() + h.nsub));
+  h.L2.layout_band(std::vector<int>(bwh.begin() + h.nsub, bwh.begin() + h.nsub + h.nl2));
+  h.LJ.layout_band(h.nJ > 0 ? std::vector<int>{int(h.nJ) - 1} : std::vector<int>{});
+  o.nt1 = h.L1.nt;
+  o.nt2 = h.L2.nt;
+  o.nbt1 = h.L1.nbt;
+  o.nbt2 = h.L2.nbt;
+  o.foff1 = h.L1.foff;
+  o.foff2 = h.L2.foff;
+  o.ntJ = h.LJ.nblk ? h.LJ.h_nt[0] : 0;
   finish_csr(h.AIG, st);
   finish_csr(h.AGI, st);
   finish_csr(h.AGG, st);

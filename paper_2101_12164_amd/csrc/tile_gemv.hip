@@ -18,19 +18,16 @@ constexpr int NW = 16;  // waves per workgroup
 constexpr int NTH = NW * 64;
 constexpr int LDT = TILE + 1;
 
-__device__ __forceinline__ int64_t tile_index(int nt, int i, int j) {
-  return int64_t(j) * nt - int64_t(j) * (j - 1) / 2 + (i - j);
-}
-
 // Forward: y = L^{-1} b (b, y in B with stride ldb, one column).
-__global__ __launch_bounds__(NTH) void k_trsv_fwd(const int* __restrict__ nt_arr, const int64_t* __restrict__ foff,
+__global__ __launch_bounds__(NTH) void k_trsv_fwd(const int* __restrict__ nt_arr, const int* __restrict__ nbt_arr,
+                                                  const int64_t* __restrict__ foff,
                                                   const int64_t* __restrict__ ioff, const int64_t* __restrict__ roff,
                                                   const double* __restrict__ L, const double* __restrict__ Linv,
                                                   double* __restrict__ B, int64_t ldb) {
   extern __shared__ double yv[];  // npad values of this block
   __shared__ double red[NW * 64];
   const int b = blockIdx.x;
-  const int nt = nt_arr[b];
+  const int nt = nt_arr[b], nbt = nbt_arr[b];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double* Bb = B + roff[b] * ldb;
   const double* Lb = L + foff[b];
@@ -52,9 +49,10 @@ __global__ __launch_bounds__(NTH) void k_trsv_fwd(const int* __restrict__ nt_arr
       yv[i * TILE + threadIdx.x] = y;
     }
     __syncthreads();
-    // acc_l -= L_li y_i for l > i (tiles of column i are contiguous)
-    const double* col = Lb + tile_index(nt, i, i) * TILE2;
-    for (int l = i + 1 + w; l < nt; l += NW) {
+    // acc_l -= L_li y_i for i < l <= i + nbt (tiles of column i are contiguous)
+    const double* col = Lb + band_tile_index(nt, nbt, i, i) * TILE2;
+    const int lend = min(nt, i + nbt + 1);
+    for (int l = i + 1 + w; l < lend; l += NW) {
       const double* T = col + int64_t(l - i) * TILE2;
       double s = 0.0;
 #pragma unroll 16
@@ -67,7 +65,8 @@ __global__ __launch_bounds__(NTH) void k_trsv_fwd(const int* __restrict__ nt_arr
 }
 
 // Backward: x = L^{-T} y, dot products with the transposed tiles LT.
-__global__ __launch_bounds__(NTH) void k_trsv_bwd(const int* __restrict__ nt_arr, const int64_t* __restrict__ foff,
+__global__ __launch_bounds__(NTH) void k_trsv_bwd(const int* __restrict__ nt_arr, const int* __restrict__ nbt_arr,
+                                                  const int64_t* __restrict__ foff,
                                                   const int64_t* __restrict__ ioff, const int64_t* __restrict__ roff,
                                                   const double* __restrict__ LT, const double* __restrict__ Linv,
                                                   double* __restrict__ B, int64_t ldb) {
@@ -76,7 +75,7 @@ __global__ __launch_bounds__(NTH) void k_trsv_bwd(const int* __restrict__ nt_arr
   __shared__ double sI[TILE * LDT];
   __shared__ double tv[TILE];
   const int b = blockIdx.x;
-  const int nt = nt_arr[b];
+  const int nt = nt_arr[b], nbt = nbt_arr[b];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double* Bb = B + roff[b] * ldb;
   const double* Lb = LT + foff[b];
@@ -85,9 +84,10 @@ __global__ __launch_bounds__(NTH) void k_trsv_bwd(const int* __restrict__ nt_arr
   __syncthreads();
   for (int i = nt - 1; i >= 0; --i) {
     // t = y_i - sum_{l>i} L_li^T x_l : lane c of wave w over tiles l = i+1+w, ...
-    const double* col = Lb + tile_index(nt, i, i) * TILE2;
+    const double* col = Lb + band_tile_index(nt, nbt, i, i) * TILE2;
+    const int lend = min(nt, i + nbt + 1);
     double s = 0.0;
-    for (int l = i + 1 + w; l < nt; l += NW) {
+    for (int l = i + 1 + w; l < lend; l += NW) {
       const double* T = col + int64_t(l - i) * TILE2;  // row-major copy: element (r, c) at r * TILE + c
 #pragma unroll 16
       for (int r = 0; r < TILE; ++r) s += T[r * TILE + lane] * yv[l * TILE + r];
@@ -168,12 +168,12 @@ void tile_solve1(const TileLevel& lv, double* B, int64_t ldb, hipStream_t st) {
   const int fam = lv.role == 0 ? KF_TRSM_I64 : KF_TRSM_G64;
   {
     KScope ks(fam, st, bytes, lv.alg_sq);
-    k_trsv_fwd<<<lv.nblk, NTH, lds, st>>>(lv.nt, lv.foff, lv.ioff, lv.roff, lv.L64, lv.Linv64, B, ldb);
+    k_trsv_fwd<<<lv.nblk, NTH, lds, st>>>(lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, lv.L64, lv.Linv64, B, ldb);
     NS_LAUNCH_CHECK();
   }
   {
     KScope ks(fam, st, bytes, lv.alg_sq);
-    k_trsv_bwd<<<lv.nblk, NTH, lds, st>>>(lv.nt, lv.foff, lv.ioff, lv.roff, lv.LT64, lv.Linv64, B, ldb);
+    k_trsv_bwd<<<lv.nblk, NTH, lds, st>>>(lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, lv.LT64, lv.Linv64, B, ldb);
     NS_LAUNCH_CHECK();
   }
 }

@@ -43,59 +43,97 @@ struct MF<float> {
 
 constexpr int LDT = TILE + 1;  // LDS row stride of a staged tile (bank spread)
 
-__device__ __forceinline__ int64_t tile_index(int nt, int i, int j) {  // tile (i, j), i >= j
-  return int64_t(j) * nt - int64_t(j) * (j - 1) / 2 + (i - j);
-}
 
+// Tile <-> LDS copies by a 256-thread workgroup: every thread issues its 16
+// global loads before the LDS stores, so the loads are in flight together.
+constexpr int WG = 256;
 template <class T>
 __device__ __forceinline__ void load_tile_lds(T* s, const T* __restrict__ g) {
-  for (int e = threadIdx.x; e < TILE2; e += blockDim.x) s[(e >> 6) * LDT + (e & 63)] = g[e];
+  T r[TILE2 / WG];
+#pragma unroll
+  for (int q = 0; q < TILE2 / WG; ++q) r[q] = g[threadIdx.x + WG * q];
+#pragma unroll
+  for (int q = 0; q < TILE2 / WG; ++q) {
+    const int e = threadIdx.x + WG * q;
+    s[(e >> 6) * LDT + (e & 63)] = r[q];
+  }
 }
 template <class T>
 __device__ __forceinline__ void store_tile_lds(T* __restrict__ g, const T* s) {
-  for (int e = threadIdx.x; e < TILE2; e += blockDim.x) g[e] = s[(e >> 6) * LDT + (e & 63)];
+#pragma unroll
+  for (int q = 0; q < TILE2 / WG; ++q) {
+    const int e = threadIdx.x + WG * q;
+    g[e] = s[(e >> 6) * LDT + (e & 63)];
+  }
 }
 
-// Cholesky of the TILE x TILE lower triangle held in LDS (column-major, LDT).
-__device__ void potrf_lds(double* s, int blk, int jt, int* err) {
+// Cholesky factor and its inverse of the TILE x TILE SPD tile in s (LDS,
+// column-major, stride LDT; lower triangle used), computed by wave 0 alone:
+// lane r keeps row r in registers; each pivot is read from its lane, the
+// scaled column and (for the inverse) the factor's columns are LDS broadcasts,
+// so no workgroup barrier is needed between columns.  On return s holds L
+// (zeros above the diagonal) and x holds L^{-1}.  A pivot <= 0 records
+// (block, column) in err once and is replaced by 1 so the sweep finishes.
+__device__ __forceinline__ double lane_value(double v, int lane) {  // v of `lane` (lane uniform)
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// 1 / sqrt(d) for d > 0: hardware estimate refined by two Newton steps
+// (y <- y (3 - d y^2) / 2), each doubling the number of correct bits.
+__device__ __forceinline__ double rsqrt_refined(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  return y;
+}
+
+__device__ void potrf_trtri_wave(double* s, double* x, double* colbuf, int blk, int jt, int* err) {
+  if (threadIdx.x >= 64) return;
+  const int r = threadIdx.x;
+  double a[TILE];
+#pragma unroll
+  for (int q = 0; q < TILE; ++q) a[q] = s[q * LDT + r];
+  int badc = -1;
+  // right-looking: column c is scaled by its pivot, then updates the columns to its right
+#pragma unroll
   for (int c = 0; c < TILE; ++c) {
-    if (threadIdx.x == 0) {
-      double d = s[c * LDT + c];
-      if (!(d > 0.0)) {
-        if (atomicCAS(err, 0, 1) == 0) {
-          err[1] = blk;
-          err[2] = jt * TILE + c;
-        }
-        d = 1.0;
-      }
-      s[c * LDT + c] = sqrt(d);
+    double d = lane_value(a[c], c);
+    if (!(d > 0.0)) {
+      if (badc < 0) badc = c;
+      d = 1.0;
     }
-    __syncthreads();
-    const double dinv = 1.0 / s[c * LDT + c];
-    for (int r = c + 1 + threadIdx.x; r < TILE; r += blockDim.x) s[c * LDT + r] *= dinv;
-    __syncthreads();
-    const int m = TILE - 1 - c;
-    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-      const int q = c + 1 + idx / m, r = c + 1 + idx % m;
-      if (r >= q) s[q * LDT + r] -= s[c * LDT + r] * s[c * LDT + q];
-    }
-    __syncthreads();
+    const double inv = rsqrt_refined(d);
+    const double l = a[c] * inv;
+    a[c] = (r == c) ? d * inv : l;
+    colbuf[TILE + c] = inv;  // 1 / l_cc for the inverse below
+    colbuf[r] = l;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the lanes' stores before the reads below
+#pragma unroll
+    for (int q = c + 1; q < TILE; ++q) a[q] = fma(-l, colbuf[q], a[q]);  // a_rq -= l_rc l_qc
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
-}
-
-// x = inverse of the lower triangular tile s (both LDS, column-major, LDT).
-__device__ void trtri_lds(const double* s, double* x) {
-  const int c = threadIdx.x;
-  if (c < TILE) {
-    for (int r = 0; r < c; ++r) x[c * LDT + r] = 0.0;
-    x[c * LDT + c] = 1.0 / s[c * LDT + c];
-    for (int r = c + 1; r < TILE; ++r) {
-      double acc = 0.0;
-      for (int m = c; m < r; ++m) acc += s[m * LDT + r] * x[c * LDT + m];
-      x[c * LDT + r] = -acc / s[r * LDT + r];
+  if (badc >= 0 && r == 0) {
+    if (atomicCAS(err, 0, 1) == 0) {
+      err[1] = blk;
+      err[2] = jt * TILE + badc;
     }
   }
-  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < TILE; ++q) s[q * LDT + r] = (r >= q) ? a[q] : 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  // row r of X = L^{-1} from X L = I, columns right to left:
+  // x_rc = (delta_rc - sum_{m>c} x_rm l_mc) / l_cc, the sum split over four chains
+#pragma unroll
+  for (int c = TILE - 1; c >= 0; --c) {
+    double acc[4] = {(r == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = c + 1; m < TILE; ++m) acc[m & 3] = fma(-a[m], s[c * LDT + m], acc[m & 3]);
+    a[c] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * colbuf[TILE + c];
+  }
+#pragma unroll
+  for (int q = 0; q < TILE; ++q) x[q * LDT + r] = a[q];
 }
 
 // Left-looking update of tile column j: C_ij = A_ij - sum_{l<j} L_il L_jl^T for
@@ -105,6 +143,7 @@ __device__ void trtri_lds(const double* s, double* x) {
 // The next (L_il, L_jl) pair is held in registers while the MFMAs consume the
 // pair staged in LDS.
 __global__ __launch_bounds__(256) void k_chol_update(int j, int nblk, const int* __restrict__ nt_arr,
+                                                     const int* __restrict__ nbt_arr,
                                                      const int64_t* __restrict__ foff,
                                                      const int64_t* __restrict__ ioff, double* __restrict__ L,
                                                      double* __restrict__ Linv, int* err) {
@@ -116,25 +155,26 @@ __global__ __launch_bounds__(256) void k_chol_update(int j, int nblk, const int*
   const int b = (g & 7) + 8 * (slot % nbp8);
   const int i = j + slot / nbp8;
   if (b >= nblk) return;
-  const int nt = nt_arr[b];
-  if (j >= nt || i >= nt) return;
+  const int nt = nt_arr[b], nbt = nbt_arr[b];
+  if (j >= nt || i >= nt || i - j > nbt) return;
   double* Lb = L + foff[b];
+  const int lbeg = max(0, i - nbt);  // L_il = 0 outside the band
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
   v4d acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
   constexpr int PT = TILE2 / 256;
   double ra[PT], rb[PT];
   auto gload = [&](int l) {
-    const double* ga = Lb + tile_index(nt, i, l) * TILE2;
-    const double* gb = Lb + tile_index(nt, j, l) * TILE2;
+    const double* ga = Lb + band_tile_index(nt, nbt, i, l) * TILE2;
+    const double* gb = Lb + band_tile_index(nt, nbt, j, l) * TILE2;
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
       ra[q] = ga[threadIdx.x + 256 * q];
       rb[q] = gb[threadIdx.x + 256 * q];
     }
   };
-  if (j > 0) gload(0);
-  for (int l = 0; l < j; ++l) {
+  if (lbeg < j) gload(lbeg);
+  for (int l = lbeg; l < j; ++l) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
@@ -156,7 +196,7 @@ __global__ __launch_bounds__(256) void k_chol_update(int j, int nblk, const int*
     }
   }
   __syncthreads();
-  double* Tij = Lb + tile_index(nt, i, j) * TILE2;
+  double* Tij = Lb + band_tile_index(nt, nbt, i, j) * TILE2;
   load_tile_lds(sA, Tij);
   __syncthreads();
   {
@@ -175,27 +215,26 @@ __global__ __launch_bounds__(256) void k_chol_update(int j, int nblk, const int*
     store_tile_lds(Tij, sA);
     return;
   }
-  potrf_lds(sA, b, j, err);
-  trtri_lds(sA, sB);
-  for (int e = threadIdx.x; e < TILE2; e += blockDim.x) {
-    const int c = e >> 6, r = e & 63;
-    Tij[e] = r >= c ? sA[c * LDT + r] : 0.0;
-  }
+  __shared__ double colbuf[2 * TILE];
+  potrf_trtri_wave(sA, sB, colbuf, b, j, err);
+  __syncthreads();
+  store_tile_lds(Tij, sA);
   store_tile_lds(Linv + ioff[b] + int64_t(j) * TILE2, sB);
 }
 
 // Panel: L_ij = C_ij L_jj^{-T} = C_ij * (L_jj^{-1})^T for i > j.
 __global__ __launch_bounds__(256) void k_chol_panel(int j, const int* __restrict__ nt_arr,
+                                                    const int* __restrict__ nbt_arr,
                                                     const int64_t* __restrict__ foff,
                                                     const int64_t* __restrict__ ioff, double* __restrict__ L,
                                                     const double* __restrict__ Linv) {
   __shared__ double sA[TILE * LDT];
   __shared__ double sB[TILE * LDT];
   const int b = blockIdx.y;
-  const int nt = nt_arr[b];
+  const int nt = nt_arr[b], nbt = nbt_arr[b];
   const int i = j + 1 + blockIdx.x;
-  if (i >= nt) return;
-  double* Tij = L + foff[b] + tile_index(nt, i, j) * TILE2;
+  if (i >= nt || i - j > nbt) return;
+  double* Tij = L + foff[b] + band_tile_index(nt, nbt, i, j) * TILE2;
   load_tile_lds(sA, Tij);
   load_tile_lds(sB, Linv + ioff[b] + int64_t(j) * TILE2);
   __syncthreads();
@@ -247,9 +286,17 @@ __device__ __forceinline__ void map_block_chunk(int nblk, int& b, int& chunk) {
 
 template <class T, int CW>
 __device__ __forceinline__ void load_rows(T* sY, const T* __restrict__ g, int64_t ldb, int c0, int ncols) {
-  for (int e = threadIdx.x; e < TILE * CW; e += blockDim.x) {
-    const int r = e / CW, c = e % CW;
-    sY[r * (CW + 1) + c] = (c0 + c < ncols) ? g[int64_t(r) * ldb + c0 + c] : T(0);
+  constexpr int PY = TILE * CW / WG;
+  T v[PY];
+#pragma unroll
+  for (int q = 0; q < PY; ++q) {
+    const int e = threadIdx.x + WG * q, r = e / CW, c = e % CW;
+    v[q] = (c0 + c < ncols) ? g[int64_t(r) * ldb + c0 + c] : T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < PY; ++q) {
+    const int e = threadIdx.x + WG * q, r = e / CW, c = e % CW;
+    sY[r * (CW + 1) + c] = v[q];
   }
 }
 
@@ -288,7 +335,7 @@ struct TrsmStage {
 
 template <class T, int CW, bool FWD>
 __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ nt_arr,
-                                              const int64_t* __restrict__ foff, const int64_t* __restrict__ ioff,
+                                              const int* __restrict__ nbt_arr, const int64_t* __restrict__ foff, const int64_t* __restrict__ ioff,
                                               const int64_t* __restrict__ roff, const T* __restrict__ L,
                                               const T* __restrict__ Linv, T* __restrict__ B, int64_t ldb,
                                               int ncols, const int* __restrict__ ncols_blk = nullptr,
@@ -304,7 +351,7 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
   const int c0 = chunk * CW;
   if (c0 >= ncols) return;
   if (ncols_blk && c0 >= ncols_blk[b]) return;  // this block's columns beyond its count are zero
-  const int nt = nt_arr[b];
+  const int nt = nt_arr[b], nbt = nbt_arr[b];
   T* Bb = B + roff[b] * ldb;
   const T* Lb = L + foff[b];
   const T* Ib = Linv + ioff[b];
@@ -318,8 +365,11 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
     acc_t acc[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) acc[q] = acc_t{0, 0, 0, 0};
-    const int l0 = FWD ? first : i + 1, nl = FWD ? i - first : nt - 1 - i;
-    auto tile = [&](int t) { return Lb + (FWD ? tile_index(nt, i, l0 + t) : tile_index(nt, l0 + t, i)) * TILE2; };
+    // FWD: L_il for l in [max(first, i - nbt), i); BWD: L_li for l in (i, min(nt - 1, i + nbt)]
+    const int l0 = FWD ? max(first, i - nbt) : i + 1, nl = FWD ? i - l0 : min(nt - 1, i + nbt) - i;
+    auto tile = [&](int t) {
+      return Lb + (FWD ? band_tile_index(nt, nbt, i, l0 + t) : band_tile_index(nt, nbt, l0 + t, i)) * TILE2;
+    };
     auto rows = [&](int t) { return Bb + int64_t(l0 + t) * TILE * ldb; };
     auto mma_stage = [&]() {
 #pragma unroll 4
@@ -376,12 +426,12 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
   }
 }
 
-__global__ void k_tile_export(int nt, int nb, const double* __restrict__ Lb, double* __restrict__ out) {
+__global__ void k_tile_export(int nt, int nbt, int nb, const double* __restrict__ Lb, double* __restrict__ out) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(nb) * nb) return;
   const int c = int(idx / nb), r = int(idx % nb);
   double v = 0.0;
-  if (r >= c) v = Lb[tile_index(nt, r >> 6, c >> 6) * TILE2 + (c & 63) * TILE + (r & 63)];
+  if (r >= c && (r >> 6) - (c >> 6) <= nbt) v = Lb[band_elem(nt, nbt, r, c)];
   out[idx] = v;
 }
 
@@ -402,12 +452,12 @@ void launch_trsm(const TileLevel& lv, T* B, int64_t ldb, int ncols, const T* L, 
   const double flops = lv.alg_sq * ncols;
   {
     KScope ks(fam, st, bytes, flops);
-    k_trsm<T, CW, true><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L, Linv, B, ldb, ncols);
+    k_trsm<T, CW, true><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L, Linv, B, ldb, ncols);
     NS_LAUNCH_CHECK();
   }
   {
     KScope ks(fam, st, bytes, flops);
-    k_trsm<T, CW, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L, Linv, B, ldb, ncols);
+    k_trsm<T, CW, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L, Linv, B, ldb, ncols);
     NS_LAUNCH_CHECK();
   }
 }
@@ -417,17 +467,19 @@ void launch_trsm(const TileLevel& lv, T* B, int64_t ldb, int ncols, const T* L, 
 void tile_cholesky(TileLevel& lv, int* d_err, hipStream_t st) {
   if (lv.nblk == 0) return;
   for (int j = 0; j < lv.max_nt; ++j) {
+    // tile rows j .. j + max_nbt of every block (rows outside a block's band exit at once)
+    const int rows = std::min(lv.max_nt - j, lv.max_nbt + 1);
     {
       KScope ks(KF_CHOL_UPDATE, st, lv.chol_bytes[j], lv.chol_upd_flops[j]);
       const int nbp8 = (lv.nblk + 7) / 8;
-      k_chol_update<<<(lv.max_nt - j) * nbp8 * 8, 256, 0, st>>>(j, lv.nblk, lv.nt, lv.foff, lv.ioff, lv.L64,
-                                                                 lv.Linv64, d_err);
+      k_chol_update<<<rows * nbp8 * 8, 256, 0, st>>>(j, lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.L64, lv.Linv64,
+                                                     d_err);
       NS_LAUNCH_CHECK();
     }
-    if (lv.max_nt - j - 1 > 0) {
+    if (rows > 1) {
       KScope ks(KF_CHOL_PANEL, st, 0.0, lv.chol_pan_flops[j]);
-      dim3 g2(lv.max_nt - j - 1, lv.nblk);
-      k_chol_panel<<<g2, 256, 0, st>>>(j, lv.nt, lv.foff, lv.ioff, lv.L64, lv.Linv64);
+      dim3 g2(rows - 1, lv.nblk);
+      k_chol_panel<<<g2, 256, 0, st>>>(j, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.L64, lv.Linv64);
       NS_LAUNCH_CHECK();
     }
   }
@@ -491,13 +543,13 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
             st, bytes, flops);
   const int nchunk_all = (ncols + cw - 1) / cw;
   if (cw == 16) {
-    k_trsm<T, 16, true><<<nbp8 * 8 * ((ncols + 15) / 16), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
+    k_trsm<T, 16, true><<<nbp8 * 8 * ((ncols + 15) / 16), 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L,
                                                                          Li, B, ldb, ncols, ncols_blk, first_tile, nchunk_all);
   } else if (cw == 32) {
-    k_trsm<T, 32, true><<<nbp8 * 8 * ((ncols + 31) / 32), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
+    k_trsm<T, 32, true><<<nbp8 * 8 * ((ncols + 31) / 32), 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L,
                                                                          Li, B, ldb, ncols, ncols_blk, first_tile, nchunk_all);
   } else {
-    k_trsm<T, 64, true><<<nbp8 * 8 * ((ncols + 63) / 64), 256, 0, st>>>(lv.nblk, lv.nt, lv.foff, lv.ioff, lv.roff, L,
+    k_trsm<T, 64, true><<<nbp8 * 8 * ((ncols + 63) / 64), 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L,
                                                                          Li, B, ldb, ncols, ncols_blk, first_tile, nchunk_all);
   }
   NS_LAUNCH_CHECK();
@@ -512,7 +564,7 @@ void tile_export(const TileLevel& lv, int block, double* out, hipStream_t st) {
   const int nb = lv.h_nb[block];
   const int64_t n2 = int64_t(nb) * nb;
   const int grid = int((n2 + 255) / 256);
-  k_tile_export<<<grid, 256, 0, st>>>(lv.h_nt[block], nb, lv.L64.p + lv.h_foff[block], out);
+  k_tile_export<<<grid, 256, 0, st>>>(lv.h_nt[block], lv.h_nbt[block], nb, lv.L64.p + lv.h_foff[block], out);
   NS_LAUNCH_CHECK();
 }
 
@@ -520,63 +572,124 @@ void TileLevel::layout(const std::vector<int>& sizes) {
   nblk = int(sizes.size());
   h_nb = sizes;
   h_nt.resize(nblk);
-  h_foff.resize(nblk);
   h_ioff.resize(nblk);
   h_roff.resize(nblk);
-  int64_t f = 0, iv = 0, r = 0;
+  int64_t iv = 0, r = 0;
   max_nt = 0;
+  alg_rows = 0;
   for (int b = 0; b < nblk; ++b) {
     const int t = (sizes[b] + TILE - 1) / TILE;
     h_nt[b] = t;
-    h_foff[b] = f;
     h_ioff[b] = iv;
     h_roff[b] = r;
-    f += tri_tiles(t) * TILE2;
     iv += int64_t(t) * TILE2;
     r += int64_t(t) * TILE;
     if (t > max_nt) max_nt = t;
+    alg_rows += sizes[b];
   }
-  f_elems = f;
   i_elems = iv;
   nrows_pad = r;
-  // algorithmic work (unpadded dense Cholesky of each block)
-  alg_tri = alg_sq = alg_rows = 0;
-  chol_upd_flops.assign(max_nt, 0.0);
-  chol_pan_flops.assign(max_nt, 0.0);
-  chol_bytes.assign(max_nt, 0.0);
-  for (int b = 0; b < nblk; ++b) {
-    const double n = sizes[b];
-    alg_tri += n * (n + 1) / 2;
-    alg_sq += n * n;
-    alg_rows += n;
-    for (int j = 0; j < h_nt[b]; ++j) {
-      const int c0 = j * TILE, c1 = std::min(sizes[b], c0 + TILE);
-      double pairs = 0, diag = 0;
-      for (int c = c0; c < c1; ++c) {
-        pairs += n - c;        // entries (r >= c) of this tile column
-        diag += double(c1 - c);  // entries inside the diagonal tile
-      }
-      const double below = pairs - diag;
-      // columns < c0 update every entry of the tile column: 2 * c0 flops each;
-      // the diagonal tile's own factorisation: sum over its columns of (c1-c)^2
-      double dflops = 0;
-      for (int c = c0; c < c1; ++c) dflops += double(c1 - c) * (c1 - c);
-      chol_upd_flops[j] += 2.0 * c0 * pairs + dflops;
-      chol_pan_flops[j] += below * double(c1 - c0);  // triangular solve of the panel
-      chol_bytes[j] += 2.0 * pairs * sizeof(double);  // each entry read and written once
-    }
-  }
   if (nblk == 0) return;
   nt.alloc(nblk);
   nb.alloc(nblk);
-  foff.alloc(nblk);
   ioff.alloc(nblk);
   roff.alloc(nblk);
   NS_HIP(hipMemcpy(nt.p, h_nt.data(), nblk * sizeof(int), hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(nb.p, h_nb.data(), nblk * sizeof(int), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(foff.p, h_foff.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(ioff.p, h_ioff.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(roff.p, h_roff.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice));
+}
+
+namespace {
+
+// sum over l in [A, B] of the number of rows r in [r0, min(U, l + bw)] (each term >= 0)
+double band_rows(int64_t A, int64_t B, int64_t U, int64_t r0, int64_t bw) {
+  A = std::max(A, r0 - bw);
+  if (B < A || U < r0) return 0.0;
+  const int64_t ls = U - bw;  // l <= ls: the column reaches row l + bw
+  double s = 0.0;
+  const int64_t b1 = std::min(B, ls);
+  if (b1 >= A) {
+    const double cnt = double(b1 - A + 1);
+    s += cnt * double(A + b1) / 2.0 + cnt * double(bw - r0 + 1);
+  }
+  const int64_t a2 = std::max(A, ls + 1);
+  if (B >= a2) s += double(B - a2 + 1) * double(U - r0 + 1);
+  return s;
+}
+
+struct BandWork {
+  std::vector<double> upd, pan, bytes;
+  double tri = 0;
+};
+
+// Algorithmic work of the band Cholesky of an n-row block with element
+// half-bandwidth bw, per tile column: updates from earlier tile columns and the
+// diagonal tile's own factorisation, the panel solve below the diagonal tile,
+// and every factor entry read and written once.
+BandWork band_work(int n, int bw) {
+  BandWork w;
+  const int nt = (n + TILE - 1) / TILE;
+  w.upd.assign(nt, 0.0);
+  w.pan.assign(nt, 0.0);
+  w.bytes.assign(nt, 0.0);
+  for (int j = 0; j < nt; ++j) {
+    const int64_t c0 = int64_t(j) * TILE, c1 = std::min<int64_t>(n, c0 + TILE);
+    for (int64_t c = c0; c < c1; ++c) {
+      const int64_t e = std::min<int64_t>(bw, n - 1 - c) + 1;  // entries of column c
+      const int64_t lo = std::max<int64_t>(0, c - bw);
+      w.upd[j] += 2.0 * band_rows(lo, c0 - 1, n - 1, c, bw);
+      w.upd[j] += 2.0 * band_rows(std::max(c0, lo), c - 1, c1 - 1, c, bw);
+      w.pan[j] += 2.0 * band_rows(std::max(c0, lo), c - 1, n - 1, c1, bw);
+      w.bytes[j] += 2.0 * e * sizeof(double);
+      w.tri += double(e);
+    }
+  }
+  return w;
+}
+
+}  // namespace
+
+void TileLevel::layout_band(const std::vector<int>& bw) {
+  h_bw.assign(nblk, 0);
+  h_nbt.assign(nblk, 0);
+  h_foff.assign(nblk, 0);
+  int64_t f = 0;
+  max_nbt = 0;
+  alg_tri = alg_sq = 0;
+  chol_upd_flops.assign(max_nt, 0.0);
+  chol_pan_flops.assign(max_nt, 0.0);
+  chol_bytes.assign(max_nt, 0.0);
+  std::vector<std::pair<std::pair<int, int>, BandWork>> memo;  // work per distinct (rows, bandwidth)
+  for (int b = 0; b < nblk; ++b) {
+    const int n = h_nb[b];
+    const int w = std::max(0, std::min(bw[b], n - 1));
+    h_bw[b] = w;
+    h_nbt[b] = band_tiles_for(n, w);
+    h_foff[b] = f;
+    f += band_col_off(h_nt[b], h_nbt[b], h_nt[b]) * TILE2;
+    max_nbt = std::max(max_nbt, h_nbt[b]);
+    const BandWork* bwk = nullptr;
+    for (auto& m : memo)
+      if (m.first.first == n && m.first.second == w) bwk = &m.second;
+    if (!bwk) {
+      memo.push_back({{n, w}, band_work(n, w)});
+      bwk = &memo.back().second;
+    }
+    alg_tri += bwk->tri;
+    for (int j = 0; j < h_nt[b]; ++j) {
+      chol_upd_flops[j] += bwk->upd[j];
+      chol_pan_flops[j] += bwk->pan[j];
+      chol_bytes[j] += bwk->bytes[j];
+    }
+  }
+  alg_sq = 2.0 * alg_tri - alg_rows;  // one triangular sweep per right-hand side
+  f_elems = f;
+  if (nblk == 0) return;
+  nbt.alloc(nblk);
+  foff.alloc(nblk);
+  NS_HIP(hipMemcpy(nbt.p, h_nbt.data(), nblk * sizeof(int), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(foff.p, h_foff.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice));
   L64.alloc(f_elems);
   Linv64.alloc(i_elems);
 }
