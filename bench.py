@@ -44,7 +44,130 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trsm-cols", type=int, default=0)
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
+                    help="c2: the 64^3 lognormal system (default line); c3: the batched anisotropic set")
+    ap.add_argument("--nprob", type=int, default=256, help="problems of the batched workload")
     return ap.parse_args()
+
+
+def roofline(stats, steps):
+    """Roofline of the dominant kernel family from the live HIP-event totals."""
+    dom = max(stats, key=lambda f: stats[f]["ms"])
+    d = stats[dom]
+    avg_ms = d["ms"] / max(d["launches"], 1)
+    if dom.startswith("chol"):
+        # factorisation: both kernel families together, flop bound (FP64 MFMA)
+        fl = stats["chol_update"]["flops"] + stats["chol_panel"]["flops"]
+        ms = stats["chol_update"]["ms"] + stats["chol_panel"]["ms"]
+        ach = fl / (ms * 1e-3) / 1e12
+        roof = {"kernel": "chol_update+chol_panel", "bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["f64"],
+                "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS["f64"], "traffic": None}
+    else:
+        by_per = d["bytes"] / max(d["launches"], 1)
+        fl_per = d["flops"] / max(d["launches"], 1)
+        intensity = fl_per / by_per if by_per else 0.0
+        prec = "f32" if dom.endswith("f32") else "f64"
+        ridge = PEAK_TFLOPS[prec] * 1e3 / HBM_PEAK_GBS
+        if intensity >= ridge:
+            ach = fl_per / (avg_ms * 1e-3) / 1e12
+            roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                    "frac": ach / PEAK_TFLOPS[prec], "traffic": None}
+        else:
+            ach = by_per / (avg_ms * 1e-3) / 1e9
+            roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    roof["avg_launch_ms"] = avg_ms
+    roof["launches_per_step"] = d["launches"] / steps
+    return roof
+
+
+def _c3_problem(i):
+    from workloads import config_c3_problem
+
+    return config_c3_problem(i)
+
+
+def bench_c3(args):
+    """Batched workload: nprob 2D anisotropic Q1 problems (L ~ U{128..512}, 4x4 boxes, k=32, p=8), one
+    batched setup + one batched PCG solve per step."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1), mp_context=mp.get_context("spawn")) as ex:
+        Ps = list(ex.map(_c3_problem, range(args.nprob)))
+    print(f"generated {len(Ps)} problems in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    import numpy as np
+    import torch
+
+    import paper_2101_12164_amd as ns
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    def T(a, dt):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+    probs = [(T(P.row_ptr, torch.int64), T(P.col, torch.int32), T(P.val, torch.float64), T(P.part, torch.int32))
+             for P in Ps]
+    oms = [T(P.omega(), torch.float64) for P in Ps]
+    bs = [T(P.b(), torch.float64) for P in Ps]
+    torch.cuda.synchronize()
+    k, p = Ps[0].k, Ps[0].p
+    prec = ns.NS_FP32 if args.prec == "fp32" else ns.NS_FP64
+
+    def step():
+        h, infos = ns.nystrom_schur_setup_batched(probs, k=k, p=p, omegas=oms, tol_inner=0.1, prec_inner=prec)
+        try:
+            xs, outs = ns.nystrom_schur_pcg_solve_batched(h, bs, rtol=1e-8, maxit=2000)
+        finally:
+            ns.nystrom_schur_destroy(h)
+        return infos, outs
+
+    for _ in range(args.warmup):
+        step()
+        print("warmup step done", file=sys.stderr, flush=True)
+    ns.nystrom_schur_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        infos, outs = step()
+        print(f"step {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    stats = {f: ns.nystrom_schur_kernel_stats(f) for f in ns.KERNEL_FAMILIES}
+    ns.nystrom_schur_kernel_timing(False)
+    its = np.array([o["it_pcg"] for o in outs])
+    isi = np.array([i["it_inner"] for i in infos])
+    line = {
+        "metric": METRIC,
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (inner block CG f32)" if prec == ns.NS_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(Ps)} 2D anisotropic Q1 problems (eps 1e-3, random angle), L ~ U{{128..512}}, "
+                               f"4x4 box subdomains, k={k} p={p}, eps_SI=0.1, rtol 1e-8, one batched setup + "
+                               "batched PCG per step",
+                   "n_total": int(sum(P.n for P in Ps)), "n_gamma_total": int(sum(P.n_gamma for P in Ps)),
+                   "inner_prec": args.prec},
+        "problems_per_s": len(Ps) / sec,
+        "it_SI": {"min": int(isi.min()), "mean": float(isi.mean()), "max": int(isi.max())},
+        "it_PCG": {"min": int(its.min()), "mean": float(its.mean()), "max": int(its.max())},
+        "relres_true_max": max(o["relres_true"] for o in outs),
+        "t_setup_s": infos[0]["t_total"],
+        "t_solve_s": outs[0]["t_solve"],
+        "t_phases_s": {kk: infos[0][kk] for kk in ("t_extract", "t_factor", "t_inner", "t_nystrom")},
+        "roofline": roofline(stats, args.steps),
+        "kernels": {f: {"ms_total": v["ms"], "launches": v["launches"]} for f, v in stats.items() if v["launches"]},
+    }
+    print(json.dumps(line))
 
 
 def main():
@@ -54,6 +177,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only "
                                    "(see DESIGN.md)", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload == "c3":
+        bench_c3(args)
+        return
 
     import numpy as np
     import torch
@@ -138,32 +265,7 @@ def main():
 
     # dominant kernel family in the timed region -> roofline
     kern = {f: {"ms_total": v["ms"], "launches": v["launches"]} for f, v in stats.items() if v["launches"]}
-    dom = max(stats, key=lambda f: stats[f]["ms"])
-    d = stats[dom]
-    avg_ms = d["ms"] / max(d["launches"], 1)
-    if dom.startswith("chol"):
-        # factorisation: both kernel families together, flop bound (FP64 MFMA)
-        fl = stats["chol_update"]["flops"] + stats["chol_panel"]["flops"]
-        ms = stats["chol_update"]["ms"] + stats["chol_panel"]["ms"]
-        ach = fl / (ms * 1e-3) / 1e12
-        roof = {"kernel": "chol_update+chol_panel", "bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["f64"],
-                "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS["f64"], "traffic": None}
-    else:
-        by_per = d["bytes"] / max(d["launches"], 1)
-        fl_per = d["flops"] / max(d["launches"], 1)
-        intensity = fl_per / by_per if by_per else 0.0
-        prec = "f32" if dom.endswith("f32") else "f64"
-        ridge = PEAK_TFLOPS[prec] * 1e3 / HBM_PEAK_GBS
-        if intensity >= ridge:
-            ach = fl_per / (avg_ms * 1e-3) / 1e12
-            roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                    "frac": ach / PEAK_TFLOPS[prec], "traffic": None}
-        else:
-            ach = by_per / (avg_ms * 1e-3) / 1e9
-            roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS, "traffic": None}
-    roof["avg_launch_ms"] = avg_ms
-    roof["launches_per_step"] = d["launches"] / args.steps
+    roof = roofline(stats, args.steps)
 
     line = {
         "metric": METRIC,

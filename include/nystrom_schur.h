@@ -96,6 +96,10 @@ typedef struct {
                                 plain Nystrom.  Accepted subspaces run in NS_APPLY_ADEF2 mode.   */
   double accept_tol;         /* eigen-residual threshold for accepting `proposal` [0.2]          */
   void* stream;              /* hipStream_t for all work; NULL = null stream                      */
+  int32_t pcg_graph_iters;   /* PCG iterations recorded per HIP graph and replayed between the
+                                host's stopping checks: 0 = automatic (1 for one problem, 4 for
+                                a batch), -1 = plain launches, m > 0 = m iterations per graph.
+                                Results are the same in every mode.                              */
 } ns_options;
 
 /* Outputs of setup(), HOST memory. Times are seconds measured with hipEvents. */
@@ -169,6 +173,44 @@ ns_status nystrom_schur_apply(ns_handle h, const double* r_gamma, double* z_gamm
 ns_status nystrom_schur_pcg_solve(ns_handle h, const double* b, double* x, double rtol, int32_t maxit,
                                   ns_solve_info* info);
 
+/*
+ * Batched setup: nprob independent problems set up together, as the diagonal
+ * blocks of one block-diagonal matrix (Algorithm alg:prec1 for each of them).
+ * Every launch of the extraction, the factorisations, the Schur operator and
+ * the A_Gamma solves covers the subdomain and interface blocks of all problems;
+ * block CG, the Nystrom core and PCG keep separate scalars, Gram matrices,
+ * ranks and stopping tests per problem, and every reduction is taken per
+ * problem over a fixed number of row chunks that depends only on that
+ * problem's size, so each problem's results equal those of the problem set up
+ * alone with nystrom_schur_setup (same options).
+ *   n[q], nnz[q]: HOST arrays; row_ptr[q], col_idx[q], val[q], part[q]: HOST
+ *     arrays of DEVICE pointers, each problem as in nystrom_schur_setup (labels
+ *     local to the problem); omega[q]: DEVICE n_gamma(q) x (k+p) sketch of
+ *     problem q (HOST array of pointers; may be NULL when k == 0).
+ *   opt: shared options (opt->omega is ignored).  info: HOST array of nprob
+ *     entries (times are those of the whole batch), may be NULL.
+ * The handle serves nystrom_schur_pcg_solve_batched and nystrom_schur_apply
+ * (on the problems' interface vectors stacked in problem order).
+ * Errors as nystrom_schur_setup; a failure in any problem fails the batch.
+ */
+ns_status nystrom_schur_setup_batched(int32_t nprob, const int64_t* n, const int64_t* nnz,
+                                      const int64_t* const* row_ptr, const int32_t* const* col_idx,
+                                      const double* const* val, const int32_t* const* part,
+                                      const double* const* omega, const ns_options* opt, ns_handle* out,
+                                      ns_setup_info* info);
+
+/*
+ * Solve A_q x_q = b_q for every problem of a batched handle (eqs. A_LDLT and
+ * Sx=b): one PCG over all problems with per-problem scalars; a problem that
+ * meets rtol is frozen (its iterate no longer changes) while the others go on,
+ * so each problem stops at the same iteration as alone.  b[q], x[q]: HOST
+ * arrays of DEVICE pointers (length n[q], the problem's own node order).
+ * info: HOST array of nprob entries (t_solve: the whole batch), may be NULL.
+ * NS_ERR_NOT_CONVERGED when some problem does not reach rtol (all x written).
+ */
+ns_status nystrom_schur_pcg_solve_batched(ns_handle h, const double* const* b, double* const* x, double rtol,
+                                          int32_t maxit, ns_solve_info* info);
+
 /* Operator access (the building blocks of the two calls above), for testing and
  * composition.  All blocks are DEVICE, row-major, ncols columns (1..1024).    */
 
@@ -188,11 +230,13 @@ ns_status nystrom_schur_interior_solve(ns_handle h, const double* X, double* Y, 
 ns_status nystrom_schur_export_factor(ns_handle h, int32_t block, double* L);
 
 /* Sizes: out[0..7] = n, n_interior, n_gamma, n_sub, n_junction,
- * n_level2_blocks, k_eff, block size of interior block 0.  HOST array.      */
+ * n_level2_blocks, k_eff, number of problems (totals over the problems of a
+ * batched handle; k_eff is then the largest).  HOST array.                  */
 ns_status nystrom_schur_get_sizes(ns_handle h, int64_t* out);
 
 /* Copy the low-rank term: Z (DEVICE, n_gamma x k_eff row-major, interface
- * order) and Sigma (DEVICE, k_eff).  Either pointer may be NULL. */
+ * order) and Sigma (DEVICE, k_eff).  Either pointer may be NULL.
+ * NS_ERR_INVALID_ARG for a batched handle. */
 ns_status nystrom_schur_get_lowrank(ns_handle h, double* Z, double* Sigma);
 
 /* Opt-in kernel timing for performance measurement (callers: benchmarks).

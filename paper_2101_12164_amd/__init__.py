@@ -9,6 +9,9 @@ from .nystrom_schur import (  # noqa: F401
     KERNEL_FAMILIES,
     NS_APPLY_ADEF2,
     NS_APPLY_M2,
+    NS_ERR_INVALID_ARG,
+    NS_ERR_NOT_CONVERGED,
+    NS_ERR_NOT_SPD,
     NS_FP32,
     NS_FP64,
     NS_SCHUR_AUTO,
@@ -29,6 +32,8 @@ from .nystrom_schur import (  # noqa: F401
     nystrom_schur_kernel_timing,
     nystrom_schur_last_error,
     nystrom_schur_pcg_solve,
+    nystrom_schur_pcg_solve_batched,
     nystrom_schur_schur_apply,
     nystrom_schur_setup,
+    nystrom_schur_setup_batched,
 )

@@ -71,6 +71,11 @@ KScope::KScope(int fam_, hipStream_t st_, double bytes_, double flops_)
   KTimer& t = timer();
   on = t.on;
   if (!on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+    on = false;  // launches recorded into a graph are not timed one by one
+    return;
+  }
   std::lock_guard<std::mutex> g(t.mu);
   a = get_event(t);
   b = get_event(t);

@@ -36,14 +36,16 @@ struct MFL<float> {
   __device__ static inline int row(int q, int v) { return 4 * q + v; }
 };
 
-// Mark the interface columns touched by each block: flag[j * nG + g] = 1.
+// Mark the interface columns touched by each block: flag[j * ldf + g - gbase_j] = 1, where block j's
+// interface columns lie in [gbase_j, gbase_j + ldf) (its problem's interface rows).
 __global__ void k_mark(int64_t nrows, const int32_t* __restrict__ rblk, const int64_t* __restrict__ ptr,
-                       const int32_t* __restrict__ col, int64_t nG, int* __restrict__ flag) {
+                       const int32_t* __restrict__ col, const int64_t* __restrict__ gbase, int64_t ldf,
+                       int* __restrict__ flag) {
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   const int j = rblk[r];
   if (j < 0) return;
-  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) flag[int64_t(j) * nG + col[e]] = 1;
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) flag[int64_t(j) * ldf + (col[e] - gbase[j])] = 1;
 }
 
 __global__ void k_row_block(const int* __restrict__ nt, const int64_t* __restrict__ roff, int32_t* __restrict__ rblk) {
@@ -53,14 +55,16 @@ __global__ void k_row_block(const int* __restrict__ nt, const int64_t* __restric
 }
 
 // One workgroup per block: count (mode 0) or compact (mode 1) the flags in
-// ascending interface order: cidx[j nG + g] = local index, glist[off_j + c] = g.
-__global__ __launch_bounds__(1024) void k_compact(int64_t nG, const int* __restrict__ flag, int* __restrict__ cnt,
+// ascending interface order: cidx[j ldf + g] = local index, glist[off_j + c] = gbase_j + g.
+__global__ __launch_bounds__(1024) void k_compact(const int64_t* __restrict__ gcnt, const int64_t* __restrict__ gbase,
+                                                  int64_t ldf, const int* __restrict__ flag, int* __restrict__ cnt,
                                                   const int64_t* __restrict__ goff, int32_t* __restrict__ cidx,
                                                   int32_t* __restrict__ glist, int mode) {
   __shared__ int s[1024];
   __shared__ int base;
   const int j = blockIdx.x;
-  const int* f = flag + int64_t(j) * nG;
+  const int64_t nG = gcnt[j];
+  const int* f = flag + int64_t(j) * ldf;
   if (threadIdx.x == 0) base = 0;
   __syncthreads();
   for (int64_t g0 = 0; g0 < nG; g0 += 1024) {
@@ -77,8 +81,8 @@ __global__ __launch_bounds__(1024) void k_compact(int64_t nG, const int* __restr
     const int incl = s[threadIdx.x];
     if (mode == 1 && g < nG) {
       const int c = base + incl - v;
-      cidx[int64_t(j) * nG + g] = v ? c : -1;
-      if (v) glist[goff[j] + c] = int32_t(g);
+      cidx[int64_t(j) * ldf + g] = v ? c : -1;
+      if (v) glist[goff[j] + c] = int32_t(gbase[j] + g);
     }
     __syncthreads();
     if (threadIdx.x == 1023) base += s[1023];
@@ -87,20 +91,22 @@ __global__ __launch_bounds__(1024) void k_compact(int64_t nG, const int* __restr
   if (mode == 0 && threadIdx.x == 0) cnt[j] = base;
 }
 
-// B (padded interior rows x ldb) = A_IGamma restricted to each block's Gamma_j
-// columns; first[j * ldb + c] = first block-local row with a nonzero in column c.
-__global__ void k_fill_B(int64_t nrows, const int32_t* __restrict__ rblk, const int64_t* __restrict__ roff,
-                         const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                         const double* __restrict__ val, int64_t nG, const int32_t* __restrict__ cidx,
+// B (rows row0 .. row0 + nrows of the padded interior rows, x ldb) = A_IGamma restricted to each block's
+// Gamma_j columns; first[j * ldb + c] = first block-local row with a nonzero in column c.
+__global__ void k_fill_B(int64_t nrows, int64_t row0, const int32_t* __restrict__ rblk,
+                         const int64_t* __restrict__ roff, const int64_t* __restrict__ ptr,
+                         const int32_t* __restrict__ col, const double* __restrict__ val,
+                         const int64_t* __restrict__ gbase, int64_t ldf, const int32_t* __restrict__ cidx,
                          double* __restrict__ B, int64_t ldb, int* __restrict__ first) {
-  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= nrows) return;
+  const int64_t rr = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (rr >= nrows) return;
+  const int64_t r = row0 + rr;
   const int j = rblk[r];
   if (j < 0) return;
   const int lr = int(r - roff[j]);
   for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) {
-    const int c = cidx[int64_t(j) * nG + col[e]];
-    B[r * ldb + c] = val[e];
+    const int c = cidx[int64_t(j) * ldf + (col[e] - gbase[j])];
+    B[rr * ldb + c] = val[e];
     atomicMin(&first[int64_t(j) * ldb + c], lr);
   }
 }
@@ -309,15 +315,17 @@ __global__ __launch_bounds__(256) void k_gather_ls(int64_t nrows, const int32_t*
 
 template <class T>
 void launch_gemm(const LocalSchur& ls, const T* A, const T* B, T* C, int N, hipStream_t st, bool sym,
-                 const GemmBatch& g, int maxM) {
+                 const GemmBatch& g, int maxM, int nblk = -1) {
   if (maxM == 0) return;
+  if (nblk < 0) nblk = ls.nblk;
+  if (nblk == 0) return;
   const int tilesM = (maxM + 63) / 64;
   if (N <= 16 && !sym) {
-    dim3 grid(1, tilesM, ls.nblk);
+    dim3 grid(1, tilesM, nblk);
     k_gemm_tn<T, 16><<<grid, 256, 0, st>>>(g, A, B, C, N, 0);
   } else {
     const int tilesN = sym ? tilesM : (N + 63) / 64;
-    dim3 grid(tilesN, tilesM, ls.nblk);
+    dim3 grid(tilesN, tilesM, nblk);
     k_gemm_tn<T, 64><<<grid, 256, 0, st>>>(g, A, B, C, N, sym ? 1 : 0);
   }
   NS_LAUNCH_CHECK();
@@ -365,21 +373,37 @@ void local_schur_build(Handle& h) {
   NS_HIP(hipMemsetAsync(rblk.p, 0xFF, nIp * sizeof(int32_t), st));
   k_row_block<<<dim3((lv.max_nt * TILE + 255) / 256, nb), 256, 0, st>>>(lv.nt, lv.roff, rblk);
   NS_LAUNCH_CHECK();
+  // interface range of every block: its problem's interface rows
+  std::vector<int64_t> gbase(nb), gcnt(nb);
+  int64_t ldf = 1;
+  for (int q = 0; q < h.nprob; ++q) {
+    const int64_t g0 = h.h_goff[q], g1 = h.h_goff[q + 1];
+    ldf = std::max(ldf, g1 - g0);
+    for (int j = h.h_sub[q]; j < h.h_sub[q + 1]; ++j) {
+      gbase[j] = g0;
+      gcnt[j] = g1 - g0;
+    }
+  }
+  DBuf<int64_t> gbase_d, gcnt_d;
+  gbase_d.alloc(nb);
+  gcnt_d.alloc(nb);
+  NS_HIP(hipMemcpy(gbase_d.p, gbase.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(gcnt_d.p, gcnt.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
   DBuf<int> flag, cnt;
   DBuf<int32_t> cidx;
-  flag.alloc(int64_t(nb) * nG);
+  flag.alloc(int64_t(nb) * ldf);
   cnt.alloc(nb);
-  cidx.alloc(int64_t(nb) * nG);
-  NS_HIP(hipMemsetAsync(flag.p, 0, int64_t(nb) * nG * sizeof(int), st));
-  k_mark<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, h.AIG.ptr, h.AIG.col, nG, flag);
+  cidx.alloc(int64_t(nb) * ldf);
+  NS_HIP(hipMemsetAsync(flag.p, 0, int64_t(nb) * ldf * sizeof(int), st));
+  k_mark<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, h.AIG.ptr, h.AIG.col, gbase_d, ldf, flag);
   NS_LAUNCH_CHECK();
-  k_compact<<<nb, 1024, 0, st>>>(nG, flag, cnt, nullptr, nullptr, nullptr, 0);
+  k_compact<<<nb, 1024, 0, st>>>(gcnt_d, gbase_d, ldf, flag, cnt, nullptr, nullptr, nullptr, 0);
   NS_LAUNCH_CHECK();
   ls.h_m.resize(nb);
   NS_HIP(hipMemcpyAsync(ls.h_m.data(), cnt.p, nb * sizeof(int), hipMemcpyDeviceToHost, st));
   NS_HIP(hipStreamSynchronize(st));
   // stacked layouts: Gamma_j lists padded to 64 rows; S_j with ld = padded m_j
-  std::vector<int64_t> goff(nb), soff(nb), sld(nb), woff(nb), wld(nb), xld(nb), yld(nb);
+  std::vector<int64_t> goff(nb), soff(nb), sld(nb), wld(nb);
   std::vector<int> Kv(nb);
   int64_t gp = 0, sp = 0;
   ls.max_m = 0;
@@ -396,29 +420,12 @@ void local_schur_build(Handle& h) {
   ls.npos = gp;
   ls.s_elems = sp;
   const int64_t ldw = std::max(ls.max_m, 1);
-  for (int j = 0; j < nb; ++j) {
-    woff[j] = lv.h_roff[j] * ldw;
-    wld[j] = ldw;
-  }
+  for (int j = 0; j < nb; ++j) wld[j] = ldw;
   ls.goff.alloc(nb);
   NS_HIP(hipMemcpy(ls.goff.p, goff.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
   ls.glist.alloc(gp > 0 ? gp : 1);
   NS_HIP(hipMemsetAsync(ls.glist.p, 0xFF, ls.glist.n * sizeof(int32_t), st));
-  k_compact<<<nb, 1024, 0, st>>>(nG, flag, cnt, ls.goff, cidx, ls.glist, 1);
-  NS_LAUNCH_CHECK();
-  // W = L^{-1} B_j for all blocks (forward sweep only), then S_j = W_j^T W_j
-  DBuf<double> W;
-  W.alloc(nIp * ldw);
-  NS_HIP(hipMemsetAsync(W.p, 0, nIp * ldw * sizeof(double), st));
-  DBuf<int> first, ftile;
-  first.alloc(int64_t(nb) * ldw);
-  NS_HIP(hipMemsetAsync(first.p, 0x7F, int64_t(nb) * ldw * sizeof(int), st));  // ~INT_MAX
-  k_fill_B<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, lv.roff, h.AIG.ptr, h.AIG.col, h.AIG.val64, nG,
-                                                        cidx, W, ldw, first);
-  NS_LAUNCH_CHECK();
-  const int ctiles = int((ldw + 63) / 64);
-  ftile.alloc(int64_t(nb) * ctiles);
-  k_first_tiles<<<(nb * ctiles + 255) / 256, 256, 0, st>>>(nb, int(ldw), ctiles, first, ftile);
+  k_compact<<<nb, 1024, 0, st>>>(gcnt_d, gbase_d, ldf, flag, cnt, ls.goff, cidx, ls.glist, 1);
   NS_LAUNCH_CHECK();
   // per-block metadata for the batched GEMMs
   auto up = [&](DBuf<int64_t>& d, const std::vector<int64_t>& v) {
@@ -428,40 +435,72 @@ void local_schur_build(Handle& h) {
   ls.M.alloc(nb);
   ls.K.alloc(nb);
   ls.Kg.alloc(nb);
-  (void)xld;
-  (void)yld;
   NS_HIP(hipMemcpy(ls.M.p, ls.h_m.data(), nb * sizeof(int), hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(ls.K.p, Kv.data(), nb * sizeof(int), hipMemcpyHostToDevice));
   NS_HIP(hipMemcpy(ls.Kg.p, ls.h_m.data(), nb * sizeof(int), hipMemcpyHostToDevice));
-  {
-    // algorithmic flops: a column with first nonzero row r_c costs, over the rows below r_c, two flops per
-    // factor entry within the half-bandwidth bw_j, i.e. t(t-1) + 2 (rem - t) bw_j + rem with rem = n_b - r_c
-    // and t = min(rem, bw_j) (r_c approximated per 64-column tile by the tile's first row)
-    std::vector<int> hf(size_t(nb) * ctiles);
-    NS_HIP(hipMemcpy(hf.data(), ftile.p, hf.size() * sizeof(int), hipMemcpyDeviceToHost));
-    double fl = 0.0;
-    for (int j = 0; j < nb; ++j)
-      for (int t = 0; t < ctiles; ++t) {
-        const int cols = std::max(0, std::min(64, ls.h_m[j] - 64 * t));
-        const double rem = std::max(0.0, double(lv.h_nb[j]) - 64.0 * std::min(hf[size_t(j) * ctiles + t], 1 << 20));
-        const double tb = std::min(rem, double(lv.h_bw[j]));
-        fl += (tb * (tb - 1.0) + 2.0 * (rem - tb) * lv.h_bw[j] + rem) * cols;
-      }
-    tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p, ftile.p, fl);  // W_j = L_j^{-1} B_j
-  }
   up(ls.soff, soff);
   up(ls.sld, sld);
-  up(ls.woff, woff);
   up(ls.wld, wld);
   ls.S64.alloc(sp > 0 ? sp : 1);
   NS_HIP(hipMemsetAsync(ls.S64.p, 0, ls.S64.n * sizeof(double), st));
-  {
-    // B_j = W_j: offset woff[j], common leading dimension ldw
-    GemmBatch g{ftile.p, ctiles, ls.M, ls.K, ls.woff, ls.wld, ls.woff, 1, ldw, ls.soff, 1, ls.sld, 0};
-    double fl = 0;
-    for (int j = 0; j < nb; ++j) fl += 2.0 * Kv[j] * ls.h_m[j] * (ls.h_m[j] + 1) / 2;
-    KScope ks(KF_LS_FORM, st, double(nIp) * ldw * 8.0, fl);
-    launch_gemm<double>(ls, W.p, W.p, ls.S64.p, 0, st, true, g, ls.max_m);
+  // W_j = L_j^{-1} B_j (forward sweep only), then S_j = W_j^T W_j, for groups of consecutive blocks whose
+  // W fits a fixed budget (the groups only bound memory: every block is computed the same way)
+  const int64_t budget = std::max<int64_t>(int64_t(1) << 30, int64_t(lv.max_nt) * TILE * ldw);
+  const int ctiles = int((ldw + 63) / 64);
+  DBuf<int> first, ftile;
+  first.alloc(int64_t(nb) * ldw);
+  NS_HIP(hipMemsetAsync(first.p, 0x7F, int64_t(nb) * ldw * sizeof(int), st));  // ~INT_MAX
+  ftile.alloc(int64_t(nb) * ctiles);
+  int64_t wmax = 0;
+  std::vector<std::pair<int, int>> groups;
+  for (int b0 = 0; b0 < nb;) {
+    int b1 = b0 + 1;
+    while (b1 < nb && (lv.h_roff[b1] + int64_t(lv.h_nt[b1]) * TILE - lv.h_roff[b0]) * ldw <= budget) ++b1;
+    groups.push_back({b0, b1});
+    wmax = std::max(wmax, (lv.h_roff[b1 - 1] + int64_t(lv.h_nt[b1 - 1]) * TILE - lv.h_roff[b0]) * ldw);
+    b0 = b1;
+  }
+  DBuf<double> W;
+  W.alloc(wmax > 0 ? wmax : 1);
+  DBuf<int64_t> woffg;
+  woffg.alloc(nb);
+  std::vector<int64_t> hwo(nb);
+  for (const auto& gr : groups) {
+    const int b0 = gr.first, b1 = gr.second, nbs = b1 - b0;
+    const int64_t row0 = lv.h_roff[b0];
+    const int64_t rows = lv.h_roff[b1 - 1] + int64_t(lv.h_nt[b1 - 1]) * TILE - row0;
+    NS_HIP(hipMemsetAsync(W.p, 0, rows * ldw * sizeof(double), st));
+    k_fill_B<<<unsigned((rows + 255) / 256), 256, 0, st>>>(rows, row0, rblk, lv.roff, h.AIG.ptr, h.AIG.col,
+                                                           h.AIG.val64, gbase_d, ldf, cidx, W, ldw, first);
+    NS_LAUNCH_CHECK();
+    k_first_tiles<<<(nbs * ctiles + 255) / 256, 256, 0, st>>>(nbs, int(ldw), ctiles, first.p + int64_t(b0) * ldw,
+                                                               ftile.p + int64_t(b0) * ctiles);
+    NS_LAUNCH_CHECK();
+    // algorithmic flops: a column with first nonzero row r_c costs, over the rows below r_c, two flops per
+    // factor entry within the half-bandwidth bw_j, i.e. t(t-1) + 2 (rem - t) bw_j + rem with rem = n_b - r_c
+    // and t = min(rem, bw_j) (r_c approximated per 64-column tile by the tile's first row)
+    std::vector<int> hf(size_t(nbs) * ctiles);
+    NS_HIP(hipMemcpy(hf.data(), ftile.p + int64_t(b0) * ctiles, hf.size() * sizeof(int), hipMemcpyDeviceToHost));
+    double fl = 0.0;
+    for (int j = b0; j < b1; ++j)
+      for (int t = 0; t < ctiles; ++t) {
+        const int cols = std::max(0, std::min(64, ls.h_m[j] - 64 * t));
+        const double rem =
+            std::max(0.0, double(lv.h_nb[j]) - 64.0 * std::min(hf[size_t(j - b0) * ctiles + t], 1 << 20));
+        const double tb = std::min(rem, double(lv.h_bw[j]));
+        fl += (tb * (tb - 1.0) + 2.0 * (rem - tb) * lv.h_bw[j] + rem) * cols;
+      }
+    tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p, ftile.p, fl, b0, b1, row0);  // W_j = L_j^{-1} B_j
+    for (int j = b0; j < b1; ++j) hwo[j] = (lv.h_roff[j] - row0) * ldw;
+    NS_HIP(hipMemcpyAsync(woffg.p + b0, hwo.data() + b0, nbs * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    // B_j = W_j: offset woff[j] inside the group, common leading dimension ldw
+    GemmBatch g{ftile.p + int64_t(b0) * ctiles, ctiles, ls.M.p + b0, ls.K.p + b0, woffg.p + b0, ls.wld.p + b0,
+                woffg.p + b0, 1, ldw, ls.soff.p + b0, 1, ls.sld.p + b0, 0};
+    double flg = 0;
+    for (int j = b0; j < b1; ++j) flg += 2.0 * Kv[j] * ls.h_m[j] * (ls.h_m[j] + 1) / 2;
+    KScope ks(KF_LS_FORM, st, double(rows) * ldw * 8.0, flg);
+    launch_gemm<double>(ls, W.p, W.p, ls.S64.p, 0, st, true, g, ls.max_m, nbs);
+    NS_HIP(hipStreamSynchronize(st));  // W and hwo are reused by the next group
   }
   if (h.prec_inner) {
     ls.S32.alloc(ls.S64.n);

@@ -3,6 +3,7 @@
 
 #include "../../include/nystrom_schur.h"
 #include "ns_internal.h"
+#include "ns_vec.h"
 
 namespace ns {
 
@@ -14,7 +15,7 @@ struct LocalSchur {
   int64_t npos = 0, s_elems = 0;  // stacked (padded) interface rows, S elements
   std::vector<int> h_m;
   DBuf<int> M, K, Kg;                          // per block: m_j, padded rows, m_j
-  DBuf<int64_t> goff, soff, sld, woff, wld;    // stacked offsets / leading dimensions
+  DBuf<int64_t> goff, soff, sld, wld;          // stacked offsets / leading dimensions
   DBuf<int32_t> glist;                         // stacked position -> interface index (-1 pad)
   DBuf<double> S64;
   DBuf<float> S32;
@@ -31,11 +32,23 @@ struct ns_handle_s {
   hipStream_t stream = nullptr;
   std::string last_error;
 
-  // sizes
+  // sizes (a batch of problems is one block-diagonal matrix: totals over the problems)
   int64_t n = 0, nnz = 0, nI = 0, nG = 0, nJ = 0;
   int nsub = 0, nl2 = 0;
-  int k = 0, p = 0, s = 0, k_eff = 0;
-  int prec_inner = 0, apply_mode = 0, trsm_cols = 0, schur_mode = 0;
+  int k = 0, p = 0, s = 0, k_eff = 0;  // k_eff: largest over the problems
+  // problems: original rows [h_noff[q], h_noff[q + 1]), interface rows [h_goff[q], h_goff[q + 1])
+  int nprob = 1;
+  std::vector<int64_t> h_noff, h_goff;
+  std::vector<int> h_sub;   // first subdomain of each problem
+  ns::DBuf<int64_t> pnode;  // device copy of h_noff
+  ns::DBuf<int> l2first;    // first level-2 block of each problem
+  ns::SegBuf segG, segN;    // interface rows / original rows by problem
+  std::vector<int> h_keff;  // k_eff of each problem
+  ns::DBuf<int> keff_d;
+  // per-problem inner solve results
+  std::vector<int> it_inner, conv_inner;
+  std::vector<double> relres_inner;
+  int prec_inner = 0, apply_mode = 0, trsm_cols = 0, schur_mode = 0, pcg_graph = 0;
   double tol_inner = 0.1, eig_rel = 1e-10, drop_rel = 1e-6;
   int max_inner = 500;
 
@@ -60,9 +73,9 @@ struct ns_handle_s {
   ns::Csr AJs;  // rows: padded junction rows; cols: padded level-2 rows
   ns::TileLevel L2, LJ;
 
-  // low-rank term (FP64): Z n_G x k_eff (ld = k), Sigma k_eff
+  // low-rank term (FP64): Z n_G x k (ld = k; columns >= k_eff of a problem are zero), Sigma k per problem
   ns::DBuf<double> Z, Sigma;
-  // adapted deflation: SZ = S Z, chol(E) (k x k lower, ld = k)
+  // adapted deflation: SZ = S Z, chol(E) (k x k lower, ld = k, per problem)
   ns::DBuf<double> SZ, Echol;
 
   // error flags written by kernels (pinned host-visible copy in hflags)
@@ -74,8 +87,9 @@ struct ns_handle_s {
   ns::DBuf<double> wsT64, wsB64, wsJ64, wsB64b, wsJ64b;  // interior rhs, level-2 rhs, junction rhs, outputs
   ns::DBuf<float> wsT32, wsB32, wsJ32, wsB32b, wsJ32b;
   ns::DBuf<double> red;    // reduction partials
-  ns::DBuf<double> small;  // small dense scratch
+  ns::DBuf<double> small;  // small dense scratch (per problem)
   int64_t ws_cols = 0;     // column capacity of the workspaces
+  int64_t wsT64_cols = 0, wsT32_cols = 0;  // column capacity of the interior workspaces
 
   ~ns_handle_s();
 };
@@ -105,8 +119,15 @@ template <class T>
 void op_interior_solve(Handle& h, const T* X, T* Y, int ncols);  // X, Y: n_I x ncols interior order
 
 // Setup pieces.
+// Problems of a batch laid side by side in one matrix: piece q owns nodes [node[q], node[q + 1]),
+// subdomain labels [sub[q], sub[q + 1]) and level-2 labels [l2[q], l2[q + 1]); its junction nodes form
+// junction block q.  pieces == nullptr: one problem, labels as given.
+struct Pieces {
+  std::vector<int64_t> node;
+  std::vector<int> sub, l2;
+};
 void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
-                  const double* val, const int32_t* part);
+                  const double* val, const int32_t* part, const Pieces* pieces = nullptr);
 void assemble_junction(Handle& h);
 void local_schur_build(Handle& h);
 

@@ -160,11 +160,14 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
 // ncols_blk: optional per-block column count (chunks beyond it are skipped);
 // first_tile: optional [block * nchunks + chunk] first tile row with a nonzero
 // right-hand side (rows above stay zero); alg_flops overrides the timing work.
+// Blocks b0 .. b1-1 only (b1 < 0: all), with B holding the padded rows from row0 on.
 template <class T>
 void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st,
-                    const int* ncols_blk = nullptr, const int* first_tile = nullptr, double alg_flops = 0.0);
+                    const int* ncols_blk = nullptr, const int* first_tile = nullptr, double alg_flops = 0.0,
+                    int b0 = 0, int b1 = -1, int64_t row0 = 0);
 // Single right-hand side sweeps (FP64) with 16-wave workgroups; need LT64.
 bool trsv1_supported(const TileLevel& lv);
+bool trsv1_supported_size(const TileLevel& lv);  // the block size allows the single-column sweeps
 void tile_make_transposed(TileLevel& lv, hipStream_t st);
 void tile_solve1(const TileLevel& lv, double* B, int64_t ldb, hipStream_t st);
 // Explicit inverses (L L^T)^{-1} of every block of a level (FP64, optional FP32 copy).

@@ -42,29 +42,46 @@ struct Events {
   }
 };
 
-// Small FP64 matrices of one setup, carved from a single allocation.
+// Small FP64 matrices of one setup, stacked per problem (s x s each unless noted).
 struct SmallMats {
   DBuf<double> buf;
-  double *Delta, *G1, *alpha, *G2, *beta, *Gorth, *Torth, *Rinv, *Racc, *C, *Wk, *Ek, *colsq, *nF2;
+  double *Delta, *G1, *alpha, *G2, *beta, *Gorth, *Torth, *Rinv, *Racc, *C;
+  double *Wk, *Ek, *colsq, *nF2, *coef, *relres;  // Wk s x k, Ek k, colsq / nF2 s, coef / relres 1
   DBuf<int> ibuf;
-  int *flag, *rank;
-  void init(int s) {
-    const size_t m = size_t(s) * s;
-    buf.alloc(12 * m + 3 * s + 8);
+  int* flag;   // [4] breakdown / factorisation flags
+  int* ctr;    // [4] ctr[0]: problems no longer active in the inner solve
+  int *active, *rank, *ok, *skip, *svr, *dimA, *itp, *conv, *nys;  // per problem (nys: 2 per problem)
+  int np = 0;
+  void init(int nprob, int s, int k) {
+    np = nprob;
+    const size_t m = size_t(s) * s * np;
+    buf.alloc(10 * m + size_t(s) * std::max(k, 1) * np + size_t(std::max(k, 1)) * np + 2 * size_t(s) * np + 2 * np);
     double* p = buf.p;
-    for (double** q : {&Delta, &G1, &alpha, &G2, &beta, &Gorth, &Torth, &Rinv, &Racc, &C, &Wk}) {
+    for (double** q : {&Delta, &G1, &alpha, &G2, &beta, &Gorth, &Torth, &Rinv, &Racc, &C}) {
       *q = p;
       p += m;
     }
+    Wk = p;
+    p += size_t(s) * std::max(k, 1) * np;
     Ek = p;
-    p += s;
+    p += size_t(std::max(k, 1)) * np;
     colsq = p;
-    p += s;
+    p += size_t(s) * np;
     nF2 = p;
-    ibuf.alloc(8);
-    NS_HIP(hipMemset(ibuf.p, 0, 8 * sizeof(int)));
+    p += size_t(s) * np;
+    coef = p;
+    p += np;
+    relres = p;
+    ibuf.alloc(8 + 10 * size_t(np));
+    NS_HIP(hipMemset(ibuf.p, 0, ibuf.n * sizeof(int)));
     flag = ibuf.p;
-    rank = ibuf.p + 4;
+    ctr = ibuf.p + 4;
+    int* q = ibuf.p + 8;
+    for (int** d : {&active, &rank, &ok, &skip, &svr, &dimA, &itp, &conv}) {
+      *d = q;
+      q += np;
+    }
+    nys = q;
   }
 };
 
@@ -88,51 +105,103 @@ void check_chol(Handle& h, int level, ns_setup_info* info) {
   fail(NOT_SPD, "Cholesky pivot <= 0 in block " + std::to_string(blk) + ", column " + std::to_string(e[2]));
 }
 
-// Orthonormal basis of the columns of V (n_G x s, ld s) into P, dropping
-// directions with singular value <= drop * sigma_max.  When a Cholesky of the
-// Gram matrix certifies that every singular value ratio exceeds the drop
-// tolerance, nothing is dropped and Cholesky-QR2 yields a basis of the same
-// span; otherwise the Gram matrix is eigen-decomposed (SVQB: keep the
-// eigenpairs above drop^2 * lambda_max) followed by one Cholesky-QR pass.
-// Returns the number of columns kept.  Q is used as scratch.
-template <class T>
-int orth(Handle& h, SmallMats& sm, DBuf<double>& work, const T* V, T*& P, T*& Q, int s) {
-  hipStream_t st = h.stream;
-  const int64_t nG = h.nG;
-  const double drop2 = h.drop_rel * h.drop_rel;
-  gram<T, T>(nG, V, s, s, V, s, s, sm.Gorth, 1.0, 0.0, work, st);
-  small_cholqr(s, sm.Gorth, 0.0, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.small.p, st, drop2, sm.rank + 2);
-  int okv = 0;
-  read_back(h, &okv, sm.rank + 2, 1);
-  int r = s;
-  if (okv) {
-    ts_update<T>(nG, s, P, s, 0.0, 1.0, V, s, s, sm.Rinv, s, nullptr, 0, 0, nullptr, 0, st);
-  } else {
-    small_svqb(s, sm.Gorth, drop2, sm.Torth, sm.rank, h.small.p, st);
-    read_back(h, &r, sm.rank, 1);
-    if (r == 0) return 0;
-    ts_update<T>(nG, r, P, s, 0.0, 1.0, V, s, s, sm.Torth, s, nullptr, 0, 0, nullptr, 0, st);
+// ------------------------------------------------------------------ inner-solve control (per problem)
+// Stopping test of block CG: rel_p = max_j ||R_p(:, j)|| / ||F_p(:, j)||; an active problem with
+// rel_p <= tol stops (converged) at iteration it.
+__global__ void k_bcg_check(int np, int s, const double* __restrict__ colsq, const double* __restrict__ nF2,
+                            double tol, int it, int* active, int* itp, int* conv, double* relres, int* ndone) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np || !active[p]) return;
+  double m = 0.0;
+  for (int j = 0; j < s; ++j) {
+    const double f = nF2[p * s + j];
+    if (f > 0.0) m = fmax(m, sqrt(colsq[p * s + j] / f));
   }
-  gram<T, T>(nG, P, s, r, P, s, r, sm.Gorth, 1.0, 0.0, work, st);
-  small_cholqr(r, sm.Gorth, 0.0, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.small.p, st);
-  ts_update<T>(nG, r, Q, s, 0.0, 1.0, P, s, r, sm.Rinv, r, nullptr, 0, 0, nullptr, 0, st);
-  std::swap(P, Q);
-  return r;
+  relres[p] = m;
+  itp[p] = it;
+  if (m <= tol) {
+    conv[p] = 1;
+    active[p] = 0;
+    atomicAdd(ndone, 1);
+  }
 }
 
-// Breakdown-free block PCG on S_Gamma D = W Omega, preconditioned by
-// A_Gamma^{-1}, from D = 0 (the inner solve of Algorithm alg:prec1, steps 2-4,
-// in the shifted Schur form: A_Gamma D = A_GammaI S_I^{-1} A_IGamma Omega by
-// eq. S-1).  Writes D (FP64, n_G x s) and returns the iteration count.
+// dims[p] = active[p] ? (rank ? rank[p] : s) : 0; skip[p] for the eigen-decomposition fallback
+__global__ void k_dims(int np, int s, const int* active, const int* rank, int* dims) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < np) dims[p] = active[p] ? (rank ? rank[p] : s) : 0;
+}
+__global__ void k_svqb_mask(int np, const int* active, const int* ok, int* skip) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < np) skip[p] = !(active[p] && !ok[p]);
+}
+// Transform per problem: the Cholesky-QR inverse when certified, else the eigen-decomposition based one
+// (copied into Rinv); rank: s, the number of directions kept, or 0 when inactive.  An active problem
+// left without directions stops (not converged).
+__global__ void k_orth_select(int np, int s, int* active, const int* ok, const int* svr, const double* Torth,
+                              double* Rinv, int* rank, int it, int* itp, int* ndone) {
+  const int p = blockIdx.x;
+  const bool use_svqb = active[p] && !ok[p];
+  if (use_svqb)
+    for (int e = threadIdx.x; e < s * s; e += blockDim.x) Rinv[int64_t(p) * s * s + e] = Torth[int64_t(p) * s * s + e];
+  if (threadIdx.x == 0) {
+    const int r = !active[p] ? 0 : (ok[p] ? s : svr[p]);
+    rank[p] = r;
+    if (active[p] && r == 0) {
+      active[p] = 0;
+      itp[p] = it;
+      atomicAdd(ndone, 1);
+    }
+  }
+}
+
+// Orthonormal basis of the columns of every active problem's block of V (n_G x s, ld s) into P, dropping
+// directions with singular value <= drop * sigma_max.  When a Cholesky of the Gram matrix certifies
+// that every singular value ratio exceeds the drop tolerance, nothing is dropped and Cholesky-QR2
+// yields a basis of the same span; otherwise the Gram matrix is eigen-decomposed (SVQB: keep the
+// eigenpairs above drop^2 * lambda_max) followed by one Cholesky-QR pass.  Inactive problems get zero
+// columns; dropped directions are zero columns at the end.  Q is scratch.
 template <class T>
-int block_pcg(Handle& h, SmallMats& sm, const double* Omega, double* D, double& relres, bool& converged) {
+void orth(Handle& h, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int s, int it) {
   hipStream_t st = h.stream;
-  const int s = h.s;
-  const int64_t nG = h.nG;
+  const Seg& sg = h.segG.view;
+  const int np = h.nprob;
+  const int64_t ss = int64_t(s) * s;
+  const double drop2 = h.drop_rel * h.drop_rel;
+  const int pb = (np + 255) / 256;
+  gram<T, T>(sg, V, s, s, V, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
+  k_dims<<<pb, 256, 0, st>>>(np, s, sm.active, nullptr, sm.dimA);
+  NS_LAUNCH_CHECK();
+  small_cholqr(Batch{np, sm.dimA}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.small.p, st, drop2,
+               sm.ok);
+  k_svqb_mask<<<pb, 256, 0, st>>>(np, sm.active, sm.ok, sm.skip);
+  NS_LAUNCH_CHECK();
+  small_svqb(np, s, sm.Gorth, ss, drop2, sm.Torth, ss, sm.svr, sm.skip, h.small.p, st);
+  k_orth_select<<<np, 256, 0, st>>>(np, s, sm.active, sm.ok, sm.svr, sm.Torth, sm.Rinv, sm.rank, it, sm.itp,
+                                    sm.ctr);
+  NS_LAUNCH_CHECK();
+  ts_update<T>(sg, s, P, s, 0.0, 1.0, V, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
+  gram<T, T>(sg, P, s, s, P, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
+  small_cholqr(Batch{np, sm.rank}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.small.p, st);
+  ts_update<T>(sg, s, Q, s, 0.0, 1.0, P, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
+  std::swap(P, Q);
+}
+
+// Breakdown-free block PCG on S_Gamma D = W Omega, preconditioned by A_Gamma^{-1}, from D = 0 (the inner
+// solve of Algorithm alg:prec1, steps 2-4, in the shifted Schur form: A_Gamma D = A_GammaI S_I^{-1}
+// A_IGamma Omega by eq. S-1), for every problem of the batch at once.  Writes D (FP64, n_G x s) and the
+// per-problem iteration counts, convergence and final column-max relative residuals.
+template <class T>
+void block_pcg(Handle& h, SmallMats& sm, const double* Omega, double* D) {
+  hipStream_t st = h.stream;
+  const Seg& sg = h.segG.view;
+  const int s = h.s, np = h.nprob;
+  const int64_t nG = h.nG, ss = int64_t(s) * s;
+  const int pb = (np + 255) / 256;
   DBuf<T> Om, X, R, Pb, Qb, Z;
   for (DBuf<T>* b : {&X, &R, &Pb, &Qb, &Z}) b->alloc(nG * s);
   DBuf<double> work;
-  work.alloc(gram_work_elems(s));
+  work.alloc(gram_work_elems(sg, s));
   const T* Omt;
   if constexpr (sizeof(T) == 8) {
     Omt = Omega;
@@ -143,126 +212,158 @@ int block_pcg(Handle& h, SmallMats& sm, const double* Omega, double* D, double& 
   }
   T* P = Pb.p;
   T* Q = Qb.p;
+  std::vector<int> ones(np, 1);
+  NS_HIP(hipMemcpyAsync(sm.active, ones.data(), np * sizeof(int), hipMemcpyHostToDevice, st));
+  NS_HIP(hipMemsetAsync(sm.conv, 0, np * sizeof(int), st));
+  NS_HIP(hipMemsetAsync(sm.ctr, 0, 4 * sizeof(int), st));
   op_schur<T>(h, Omt, s, R.p, s, s, /*w_only=*/true);  // F = W Omega
   NS_HIP(hipMemsetAsync(X.p, 0, nG * s * sizeof(T), st));
-  col_sumsq<T>(nG, s, R.p, s, sm.nF2, work, st);
-  std::vector<double> nF2(s), nr2(s);
-  read_back(h, nF2.data(), sm.nF2, s);
-  auto max_rel = [&](const std::vector<double>& r2) {
-    double m = 0.0;
-    for (int j = 0; j < s; ++j)
-      if (nF2[j] > 0.0) m = std::max(m, std::sqrt(r2[j] / nF2[j]));
-    return m;
-  };
-  relres = max_rel(nF2);
-  converged = relres <= h.tol_inner;
+  col_sumsq<T>(sg, s, R.p, s, sm.nF2, work, st);
+  NS_HIP(hipMemcpyAsync(sm.colsq, sm.nF2, size_t(np) * s * sizeof(double), hipMemcpyDeviceToDevice, st));
+  k_bcg_check<<<pb, 256, 0, st>>>(np, s, sm.colsq, sm.nF2, h.tol_inner, 0, sm.active, sm.itp, sm.conv, sm.relres,
+                                  sm.ctr);
+  NS_LAUNCH_CHECK();
+  int hc[2] = {0, 0};
+  read_back(h, hc, sm.ctr, 1);
   int it = 0;
-  if (!converged) {
+  if (hc[0] < np) {
     op_gamma_solve<T>(h, R.p, s, Z.p, s, s);
-    int r = orth<T>(h, sm, work, Z.p, P, Q, s);
-    while (r > 0 && it < h.max_inner) {
+    orth<T>(h, sm, work, Z.p, P, Q, s, 0);
+    while (it < h.max_inner) {
       ++it;
-      op_schur<T>(h, P, s, Q, s, r, false);                                   // Q = S P
-      gram<T, T>(nG, P, s, r, Q, s, r, sm.Delta, 1.0, 0.0, work, st);       // Delta = P^T Q
-      gram<T, T>(nG, P, s, r, R.p, s, s, sm.G1, 1.0, 0.0, work, st);        // P^T R
-      small_chol_solve(r, sm.Delta, sm.G1, s, sm.alpha, s, s, 1.0, sm.flag, h.small.p, st);  // alpha
-      ts_update<T>(nG, s, X.p, s, 1.0, 1.0, P, s, r, sm.alpha, s, nullptr, 0, 0, nullptr, 0, st);
-      ts_update<T>(nG, s, R.p, s, 1.0, -1.0, Q, s, r, sm.alpha, s, nullptr, 0, 0, nullptr, 0, st);
-      col_sumsq<T>(nG, s, R.p, s, sm.colsq, work, st);
-      read_back(h, nr2.data(), sm.colsq, s);
-      int fl = 0;
-      read_back(h, &fl, sm.flag, 1);
-      if (fl) fail(BREAKDOWN, "block CG: P^T S P is not positive definite");
-      relres = max_rel(nr2);
-      if (relres <= h.tol_inner) {
-        converged = true;
-        break;
-      }
-      op_gamma_solve<T>(h, R.p, s, Z.p, s, s);                            // Z = A_G^{-1} R
-      gram<T, T>(nG, Q, s, r, Z.p, s, s, sm.G2, 1.0, 0.0, work, st);       // Q^T Z
-      small_chol_apply(r, sm.Delta, sm.G2, s, sm.beta, s, s, -1.0, h.small.p, st);    // beta
-      ts_update<T>(nG, s, Z.p, s, 1.0, 1.0, P, s, r, sm.beta, s, nullptr, 0, 0, nullptr, 0, st);  // Z + P beta
-      r = orth<T>(h, sm, work, Z.p, P, Q, s);
+      op_schur<T>(h, P, s, Q, s, s, false);                                     // Q = S P
+      gram<T, T>(sg, P, s, s, Q, s, s, sm.Delta, ss, 1.0, 0.0, work, st);      // Delta = P^T Q
+      gram<T, T>(sg, P, s, s, R.p, s, s, sm.G1, ss, 1.0, 0.0, work, st);       // P^T R
+      k_dims<<<pb, 256, 0, st>>>(np, s, sm.active, sm.rank, sm.dimA);
+      NS_LAUNCH_CHECK();
+      small_chol_solve(Batch{np, sm.dimA}, s, sm.Delta, ss, sm.G1, s, ss, sm.alpha, s, ss, s, s, 1.0, sm.flag,
+                       h.small.p, st);  // alpha
+      ts_update<T>(sg, s, X.p, s, 1.0, 1.0, P, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
+      ts_update<T>(sg, s, R.p, s, 1.0, -1.0, Q, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
+      col_sumsq<T>(sg, s, R.p, s, sm.colsq, work, st);
+      k_bcg_check<<<pb, 256, 0, st>>>(np, s, sm.colsq, sm.nF2, h.tol_inner, it, sm.active, sm.itp, sm.conv,
+                                      sm.relres, sm.ctr);
+      NS_LAUNCH_CHECK();
+      NS_HIP(hipMemcpyAsync(hc + 1, sm.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+      read_back(h, hc, sm.ctr, 1);
+      if (hc[1]) fail(BREAKDOWN, "block CG: P^T S P is not positive definite");
+      if (hc[0] >= np) break;
+      op_gamma_solve<T>(h, R.p, s, Z.p, s, s);                                 // Z = A_G^{-1} R
+      gram<T, T>(sg, Q, s, s, Z.p, s, s, sm.G2, ss, 1.0, 0.0, work, st);       // Q^T Z
+      k_dims<<<pb, 256, 0, st>>>(np, s, sm.active, sm.rank, sm.dimA);
+      NS_LAUNCH_CHECK();
+      small_chol_apply(Batch{np, sm.dimA}, s, sm.Delta, ss, sm.G2, s, ss, sm.beta, s, ss, s, s, -1.0, h.small.p,
+                       st);  // beta
+      ts_update<T>(sg, s, Z.p, s, 1.0, 1.0, P, s, s, sm.beta, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);  // Z + P beta
+      orth<T>(h, sm, work, Z.p, P, Q, s, it);
     }
   }
   if constexpr (sizeof(T) == 8)
     NS_HIP(hipMemcpyAsync(D, X.p, nG * s * sizeof(double), hipMemcpyDeviceToDevice, st));
   else
     convert_block<float, double>(nG, s, X.p, s, D, s, st);
+  h.it_inner.resize(np);
+  h.conv_inner.resize(np);
+  h.relres_inner.resize(np);
+  NS_HIP(hipMemcpyAsync(h.it_inner.data(), sm.itp, np * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipMemcpyAsync(h.conv_inner.data(), sm.conv, np * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipMemcpyAsync(h.relres_inner.data(), sm.relres, np * sizeof(double), hipMemcpyDeviceToHost, st));
   NS_HIP(hipStreamSynchronize(st));
-  return it;
 }
 
-// Nystrom core (Algorithm alg:prec1 steps 5-11): QR of Y by shifted
-// Cholesky-QR (three passes), C = Omega^T Y, EVDs, U = Q W(:, 1:k'), Z = A_G^{-1} U.
+// Nystrom core (Algorithm alg:prec1 steps 5-11) per problem: QR of Y by shifted Cholesky-QR (three
+// passes), C = Omega^T Y, EVDs, U = Q W(:, 1:k'), Z = A_G^{-1} U.
 void nystrom(Handle& h, SmallMats& sm, const double* Omega, double* Y) {
   hipStream_t st = h.stream;
-  const int s = h.s, k = h.k;
-  const int64_t nG = h.nG;
+  const Seg& sg = h.segG.view;
+  const int s = h.s, k = h.k, np = h.nprob;
+  const int64_t nG = h.nG, ss = int64_t(s) * s;
   DBuf<double> Qb, U, work;
   Qb.alloc(nG * s);
-  work.alloc(gram_work_elems(s));
-  gram<double, double>(nG, Omega, s, s, Y, s, s, sm.C, 1.0, 0.0, work, st);  // C = Omega^T Y
-  const double u = std::ldexp(1.0, -53);
-  const double coef = 11.0 * (double(nG) * s + double(s) * (s + 1)) * u;
+  work.alloc(gram_work_elems(sg, s));
+  gram<double, double>(sg, Omega, s, s, Y, s, s, sm.C, ss, 1.0, 0.0, work, st);  // C = Omega^T Y
+  {
+    // shift of the first Cholesky-QR pass: 11 (n_G s + s (s + 1)) u, with n_G the problem's interface size
+    const double u = std::ldexp(1.0, -53);
+    std::vector<double> coef(np);
+    for (int q = 0; q < np; ++q)
+      coef[q] = 11.0 * (double(h.h_goff[q + 1] - h.h_goff[q]) * s + double(s) * (s + 1)) * u;
+    NS_HIP(hipMemcpy(sm.coef, coef.data(), np * sizeof(double), hipMemcpyHostToDevice));
+  }
   double* A = Y;
   double* B = Qb.p;
   for (int pass = 0; pass < 3; ++pass) {
-    gram<double, double>(nG, A, s, s, A, s, s, sm.Gorth, 1.0, 0.0, work, st);
-    small_cholqr(s, sm.Gorth, pass == 0 ? coef : 0.0, sm.Rinv, sm.Racc, pass == 0, sm.flag + 2, h.small.p, st);
-    ts_update<double>(nG, s, B, s, 0.0, 1.0, A, s, s, sm.Rinv, s, nullptr, 0, 0, nullptr, 0, st);
+    gram<double, double>(sg, A, s, s, A, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
+    small_cholqr(Batch{np, nullptr}, s, sm.Gorth, ss, pass == 0 ? sm.coef : nullptr, sm.Rinv, sm.Racc, pass == 0,
+                 sm.flag + 2, h.small.p, st);
+    ts_update<double>(sg, s, B, s, 0.0, 1.0, A, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
     std::swap(A, B);
   }
   // A now holds Q (orthonormal), sm.Racc holds R
-  small_nystrom(s, k, sm.C, sm.Racc, h.eig_rel, sm.Wk, sm.Ek, sm.rank, h.small.p, st);
-  int out[2];
-  read_back(h, out, sm.rank, 2);
-  h.k_eff = out[1];
+  small_nystrom(np, s, k, sm.C, sm.Racc, h.eig_rel, sm.Wk, sm.Ek, sm.nys, h.small.p, st);
+  std::vector<int> out(2 * np);
+  read_back(h, out.data(), sm.nys, 2 * np);
+  h.h_keff.resize(np);
+  h.k_eff = 0;
+  for (int q = 0; q < np; ++q) {
+    h.h_keff[q] = out[2 * q + 1];
+    h.k_eff = std::max(h.k_eff, h.h_keff[q]);
+  }
+  h.keff_d.alloc(np);
+  NS_HIP(hipMemcpy(h.keff_d.p, h.h_keff.data(), np * sizeof(int), hipMemcpyHostToDevice));
   h.Z.alloc(nG * (k > 0 ? k : 1));
-  h.Sigma.alloc(k > 0 ? k : 1);
-  if (h.k_eff == 0) return;
-  U.alloc(nG * k);
-  ts_update<double>(nG, h.k_eff, U.p, k, 0.0, 1.0, A, s, s, sm.Wk, k, nullptr, 0, 0, nullptr, 0, st);
-  op_gamma_solve<double>(h, U.p, k, h.Z.p, k, h.k_eff);
-  NS_HIP(hipMemcpyAsync(h.Sigma.p, sm.Ek, h.k_eff * sizeof(double), hipMemcpyDeviceToDevice, st));
+  h.Sigma.alloc(size_t(k > 0 ? k : 1) * np);
+  NS_HIP(hipMemsetAsync(h.Z.p, 0, h.Z.n * sizeof(double), st));
+  NS_HIP(hipMemcpyAsync(h.Sigma.p, sm.Ek, size_t(k) * np * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (h.k_eff > 0) {
+    U.alloc(nG * k);
+    ts_update<double>(sg, k, U.p, k, 0.0, 1.0, A, s, s, sm.Wk, k, int64_t(s) * k, nullptr, 0, 0, nullptr, 0, 0, st);
+    op_gamma_solve<double>(h, U.p, k, h.Z.p, k, k);
+  }
   NS_HIP(hipStreamSynchronize(st));
 }
 
-// Adapted deflation: SZ = S Z, E = Z^T S Z, chol(E).
+// Adapted deflation: SZ = S Z, E = Z^T S Z and chol(E), per problem.
 void setup_adef2(Handle& h) {
   hipStream_t st = h.stream;
-  const int k = h.k, ke = h.k_eff;
-  const int64_t nG = h.nG;
-  if (ke == 0) return;
+  const Seg& sg = h.segG.view;
+  const int k = h.k, np = h.nprob;
+  const int64_t nG = h.nG, kk = int64_t(k) * k;
+  if (h.k_eff == 0) return;
   h.SZ.alloc(nG * k);
-  h.Echol.alloc(size_t(k) * k);
-  op_schur<double>(h, h.Z.p, k, h.SZ.p, k, ke, false);
+  h.Echol.alloc(size_t(kk) * np);
+  op_schur<double>(h, h.Z.p, k, h.SZ.p, k, k, false);
   DBuf<double> work;
-  work.alloc(gram_work_elems(k));
-  gram<double, double>(nG, h.Z.p, k, ke, h.SZ.p, k, ke, h.Echol.p, 1.0, 0.0, work, st);
-  small_chol_solve(ke, h.Echol.p, nullptr, 0, nullptr, 0, 0, 1.0, h.dflags.p + 12, h.small.p, st);
+  work.alloc(gram_work_elems(sg, k));
+  gram<double, double>(sg, h.Z.p, k, k, h.SZ.p, k, k, h.Echol.p, kk, 1.0, 0.0, work, st);
+  NS_HIP(hipMemsetAsync(h.dflags.p + 12, 0, sizeof(int), st));
+  small_chol_solve(Batch{np, h.keff_d}, k, h.Echol.p, kk, nullptr, 0, 0, nullptr, 0, 0, 0, 0, 1.0, h.dflags.p + 12,
+                   h.small.p, st);
   int fl = 0;
   read_back(h, &fl, h.dflags.p + 12, 1);
   if (fl) fail(BREAKDOWN, "Z^T S Z is not positive definite");
 }
 
-// z = M r for ncols vectors (FP64, interface order, row-major).
+// z = M r for ncols vectors (FP64, interface order, row-major), every problem with its own low-rank term.
+// c1, c2: k x ncols per problem.
 void apply_prec(Handle& h, const double* r, int64_t ldr, double* z, int64_t ldz, int ncols, double* work,
                 double* c1, double* c2) {
   hipStream_t st = h.stream;
-  const int64_t nG = h.nG;
-  const int k = h.k, ke = h.k_eff;
+  const Seg& sg = h.segG.view;
+  const int k = h.k, np = h.nprob;
+  const int64_t cs = int64_t(k) * ncols;
   op_gamma_solve<double>(h, r, ldr, z, ldz, ncols);  // t = A_Gamma^{-1} r
-  if (ke == 0) return;
+  if (h.k_eff == 0) return;
   if (h.apply_mode == NS_APPLY_M2) {
-    gram<double, double>(nG, h.Z.p, k, ke, r, ldr, ncols, c1, 1.0, 0.0, work, st);  // Z^T r
-    small_rowscale(ke, ncols, h.Sigma.p, c1, ncols, st);
-    ts_update<double>(nG, ncols, z, ldz, 1.0, 1.0, h.Z.p, k, ke, c1, ncols, nullptr, 0, 0, nullptr, 0, st);
+    gram<double, double>(sg, h.Z.p, k, k, r, ldr, ncols, c1, cs, 1.0, 0.0, work, st);  // Z^T r
+    small_rowscale(np, k, ncols, h.Sigma.p, k, c1, ncols, cs, st);
+    ts_update<double>(sg, ncols, z, ldz, 1.0, 1.0, h.Z.p, k, k, c1, ncols, cs, nullptr, 0, 0, nullptr, 0, 0, st);
   } else {
-    gram<double, double>(nG, h.Z.p, k, ke, r, ldr, ncols, c1, 1.0, 0.0, work, st);   // Z^T r
-    gram<double, double>(nG, h.SZ.p, k, ke, z, ldz, ncols, c1, -1.0, 1.0, work, st);  // - (SZ)^T t
-    small_chol_apply(ke, h.Echol.p, c1, ncols, c2, ncols, ncols, 1.0, h.small.p, st);           // E^{-1} (...)
-    ts_update<double>(nG, ncols, z, ldz, 1.0, 1.0, h.Z.p, k, ke, c2, ncols, nullptr, 0, 0, nullptr, 0, st);
+    gram<double, double>(sg, h.Z.p, k, k, r, ldr, ncols, c1, cs, 1.0, 0.0, work, st);    // Z^T r
+    gram<double, double>(sg, h.SZ.p, k, k, z, ldz, ncols, c1, cs, -1.0, 1.0, work, st);  // - (SZ)^T t
+    small_chol_apply(Batch{np, h.keff_d}, k, h.Echol.p, int64_t(k) * k, c1, ncols, cs, c2, ncols, cs, ncols, k, 1.0,
+                     h.small.p, st);  // E^{-1} (...)
+    ts_update<double>(sg, ncols, z, ldz, 1.0, 1.0, h.Z.p, k, k, c2, ncols, cs, nullptr, 0, 0, nullptr, 0, 0, st);
   }
 }
 
@@ -278,10 +379,323 @@ __global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __r
   if (i < n) c[i] = a[i] - b[i];
 }
 
+__global__ void k_sqrt_inplace(int n, double* x, int stride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[int64_t(i) * stride] = sqrt(x[int64_t(i) * stride]);
+}
+
+// Results of one problem's solve.
+struct SolveOut {
+  int it = 0, converged = 0;
+  double relres_schur = 0.0, relres_true = 0.0;
+  std::vector<double> hist;
+};
+
+// f = b_Gamma - A_GammaI A_I^{-1} b_I; PCG on S_Gamma w = f with M (w0 = Q f for the adapted deflation);
+// x_I = A_I^{-1} (b_I - A_IGamma w), x_Gamma = w (eqs. A_LDLT and Sx=b), for every problem at once.
+// b, x: the batch's right-hand side and solution (original order of the block-diagonal matrix).
+void pcg_core(Handle& h, const double* b, double* x, double rtol, int maxit, std::vector<SolveOut>& res) {
+  hipStream_t st = h.stream;
+  const Seg& sg = h.segG.view;
+  const int np = h.nprob;
+  const int64_t n = h.n, nG = h.nG, nIp = h.L1.nrows_pad;
+  const int k = std::max(h.k, 1);
+  DBuf<double> bI, f, w, r, z, p, q, work, c1, c2, tmp, psd, hist;
+  DBuf<int> ist;
+  bI.alloc(nIp);
+  for (DBuf<double>* v : {&f, &w, &r, &z, &p, &q}) v->alloc(nG);
+  work.alloc(std::max<size_t>(gram_work_elems(sg, k), size_t(sg.nchunk) + 16));
+  c1.alloc(size_t(k) * np);
+  c2.alloc(size_t(k) * np);
+  tmp.alloc(std::max(n, nIp));  // gathers of the padded interior rows (n_I padded can exceed n)
+  psd.alloc(size_t(PS) * np);
+  const int64_t hs = int64_t(maxit) + 1;
+  hist.alloc(size_t(hs) * np);
+  ist.alloc(2 * size_t(np) + 4);
+  NS_HIP(hipMemsetAsync(psd.p, 0, psd.n * sizeof(double), st));
+  NS_HIP(hipMemsetAsync(ist.p, 0, ist.n * sizeof(int), st));
+  PcgState S{psd.p, ist.p, ist.p + np, ist.p + 2 * np, ist.p + 2 * np + 1, hist.p, hs, rtol, maxit};
+  // f = b_Gamma - A_GammaI A_I^{-1} b_I
+  gather_rows<double>(nIp, h.iperm, b, 1, bI.p, 1, 1, st);
+  tile_solve<double>(h.L1, bI.p, 1, 1, h.trsm_cols, st);
+  gather_rows<double>(nG, h.gperm, b, 1, tmp.p, 1, 1, st);
+  csr_mult<double>(h.AGI, bI.p, 1, f.p, 1, 1, st);
+  axpby(nG, 1.0, tmp.p, -1.0, f.p, st);
+  dot(sg, f.p, f.p, psd.p + PS_NF, PS, work, st);
+  k_sqrt_inplace<<<(np + 255) / 256, 256, 0, st>>>(np, psd.p + PS_NF, PS);
+  NS_LAUNCH_CHECK();
+  NS_HIP(hipMemsetAsync(w.p, 0, nG * sizeof(double), st));
+  NS_HIP(hipMemcpyAsync(r.p, f.p, nG * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (h.apply_mode == NS_APPLY_ADEF2 && h.k_eff > 0) {
+    // w0 = Z E^{-1} Z^T f ; r = f - S w0
+    const int kk = h.k;
+    gram<double, double>(sg, h.Z.p, kk, kk, f.p, 1, 1, c1.p, kk, 1.0, 0.0, work, st);
+    small_chol_apply(Batch{np, h.keff_d}, kk, h.Echol.p, int64_t(kk) * kk, c1.p, 1, kk, c2.p, 1, kk, 1, kk, 1.0,
+                     h.small.p, st);
+    ts_update<double>(sg, 1, w.p, 1, 0.0, 1.0, h.Z.p, kk, kk, c2.p, 1, kk, nullptr, 0, 0, nullptr, 0, 0, st);
+    op_schur<double>(h, w.p, 1, q.p, 1, 1, false);
+    axpby(nG, 1.0, f.p, -1.0, q.p, st);
+    NS_HIP(hipMemcpyAsync(r.p, q.p, nG * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  dot(sg, r.p, r.p, psd.p + PS_RN2, PS, work, st);
+  pcg_init_check(np, S, st);
+  int hc[2] = {0, 0};  // problems done, iterations run
+  read_back(h, hc, S.ndone, 2);
+  // One PCG iteration for every problem; the iteration index lives on the device, so the same launches
+  // (recorded once into a graph) serve every iteration.
+  auto head = [&](hipStream_t s) {
+    op_schur<double>(h, p.p, 1, q.p, 1, 1, false);  // q = S p
+    dot(sg, p.p, q.p, psd.p + PS_PQ, PS, work, s);  // p^T q
+    pcg_update_wr(sg, S, w.p, r.p, p.p, q.p, work, s);  // w, r, ||r||, stopping test
+  };
+  auto tail = [&](hipStream_t s) {
+    apply_prec(h, r.p, 1, z.p, 1, 1, work, c1, c2);        // z = M r
+    dot(sg, r.p, z.p, psd.p + PS_RHO_NEW, PS, work, s);  // rho_{j+1}
+    pcg_update_p(sg, S, z.p, p.p, s);
+    pcg_advance(np, S, s);
+  };
+  if (hc[0] < np && maxit > 0) {
+    apply_prec(h, r.p, 1, z.p, 1, 1, work, c1, c2);
+    dot(sg, r.p, z.p, psd.p + PS_RHO, PS, work, st);  // rho_0
+    NS_HIP(hipMemcpyAsync(p.p, z.p, nG * sizeof(double), hipMemcpyDeviceToDevice, st));
+    int m = h.pcg_graph == 0 ? (np > 1 ? 4 : 1) : h.pcg_graph;
+    // the first iteration runs with plain launches: it also sizes every workspace the body uses
+    head(st);
+    read_back(h, hc, S.ndone, 2);
+    if (hc[0] < np && hc[1] < maxit) tail(st);
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    if (m > 0 && hc[0] < np && hc[1] < maxit) {
+      // record m iterations on a private stream (the handle's stream may be the null stream)
+      NS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipGraph_t graph = nullptr;
+      h.stream = cap;
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        try {
+          for (int t = 0; t < m; ++t) {
+            head(cap);
+            tail(cap);
+          }
+        } catch (...) {
+          (void)hipStreamEndCapture(cap, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          h.stream = st;
+          (void)hipStreamDestroy(cap);
+          throw;
+        }
+        e = hipStreamEndCapture(cap, &graph);
+      }
+      h.stream = st;
+      if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamDestroy(cap);
+        fail(HIP, std::string("PCG graph capture failed: ") + hipGetErrorString(e));
+      }
+    }
+    while (hc[0] < np && hc[1] < maxit) {
+      if (exec) {
+        NS_HIP(hipGraphLaunch(exec, st));
+      } else {
+        head(st);
+        read_back(h, hc, S.ndone, 2);
+        if (hc[0] >= np || hc[1] >= maxit) break;
+        tail(st);
+      }
+      read_back(h, hc, S.ndone, 2);
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+  const int iters = std::min(hc[1], maxit);
+  // back-substitution: x_I = A_I^{-1} (b_I - A_IGamma w), x_Gamma = w
+  gather_rows<double>(nIp, h.iperm, b, 1, tmp.p, 1, 1, st);
+  csr_mult<double>(h.AIG, w.p, 1, bI.p, 1, 1, st);
+  axpby(nIp, 1.0, tmp.p, -1.0, bI.p, st);
+  tile_solve<double>(h.L1, bI.p, 1, 1, h.trsm_cols, st);
+  scatter_rows<double, double>(nIp, h.iperm, bI.p, 1, x, 1, 1, st);
+  scatter_rows<double, double>(nG, h.gperm, w.p, 1, x, 1, 1, st);
+  // true residual ||b - A x|| / ||b|| per problem
+  csr_mult<double>(h.Aorig, x, 1, tmp.p, 1, 1, st);
+  k_sub<<<unsigned((n + 255) / 256), 256, 0, st>>>(n, b, tmp.p, tmp.p);
+  NS_LAUNCH_CHECK();
+  const Seg& sn = h.segN.view;
+  DBuf<double> rr, work2;
+  rr.alloc(2 * size_t(np));
+  work2.alloc(size_t(sn.nchunk) + 16);
+  dot(sn, tmp.p, tmp.p, rr.p, 2, work2, st);
+  dot(sn, b, b, rr.p + 1, 2, work2, st);
+  std::vector<double> hrr(2 * np), hh(size_t(hs) * np);
+  std::vector<int> hi(2 * np);
+  NS_HIP(hipMemcpyAsync(hrr.data(), rr.p, 2 * np * sizeof(double), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipMemcpyAsync(hi.data(), ist.p, 2 * np * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipMemcpyAsync(hh.data(), hist.p, hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipStreamSynchronize(st));
+  res.assign(np, SolveOut{});
+  for (int g = 0; g < np; ++g) {
+    SolveOut& o = res[g];
+    const int done = hi[g];
+    o.it = done ? hi[np + g] : iters;
+    if (!done) o.it = std::min(o.it, maxit);
+    o.converged = done == 1;
+    o.hist.assign(hh.begin() + size_t(g) * hs, hh.begin() + size_t(g) * hs + o.it + 1);
+    o.relres_schur = o.hist.back();
+    o.relres_true = hrr[2 * g + 1] > 0 ? std::sqrt(hrr[2 * g] / hrr[2 * g + 1]) : 0.0;
+  }
+}
+
 ns_status finish(Handle* h, const Error& e) {
   g_last_error = e.msg;
   if (h) h->last_error = e.msg;
   return ns_status(e.status);
+}
+
+Handle* new_handle(const ns_options* opt) {
+  if (!opt) fail(INVALID_ARG, "opt must not be NULL");
+  if (opt->k < 0 || opt->p < 0) fail(INVALID_ARG, "k and p must be >= 0");
+  Handle* h = new Handle();
+  h->stream = static_cast<hipStream_t>(opt->stream);
+  h->k = opt->k;
+  h->p = opt->p;
+  h->s = opt->k + opt->p;
+  h->tol_inner = opt->tol_inner > 0 ? opt->tol_inner : 0.1;
+  h->eig_rel = opt->eig_thresh_rel > 0 ? opt->eig_thresh_rel : 1e-10;
+  h->prec_inner = opt->prec_inner == NS_FP32 ? 1 : 0;
+  h->drop_rel = opt->orth_drop_rel > 0 ? opt->orth_drop_rel : (h->prec_inner ? 1e-5 : 1e-6);
+  h->max_inner = opt->max_inner_iters > 0 ? opt->max_inner_iters : 500;
+  h->apply_mode = opt->apply_mode == NS_APPLY_ADEF2 ? 1 : 0;
+  h->trsm_cols = opt->trsm_cols;
+  h->schur_mode = opt->schur_mode;
+  h->pcg_graph = opt->pcg_graph_iters;
+  return h;
+}
+
+void check_options(Handle* h) {
+  if (h->schur_mode < 0 || h->schur_mode > 2) fail(INVALID_ARG, "schur_mode must be 0, 1 or 2");
+  if (h->trsm_cols != 0 && h->trsm_cols != 16 && h->trsm_cols != 32 && h->trsm_cols != 64)
+    fail(INVALID_ARG, "trsm_cols must be 0, 16, 32 or 64");
+  h->dflags.alloc(16);
+  NS_HIP(hipMemset(h->dflags.p, 0, 16 * sizeof(int)));
+  NS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hflags), 16 * sizeof(int), hipHostMallocDefault));
+  NS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hscal), 64 * sizeof(double), hipHostMallocDefault));
+}
+
+// Setup after the matrix is in place: extraction, factorisations, inner solve, Nystrom.
+// omega: n_G x s row-major (the problems' sketches stacked in interface order).
+void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx, const double* val,
+                const int32_t* part, const Pieces* pieces, const double* const* omegas, ns_setup_info* info) {
+  Events ev(h->stream);
+  ev.rec(0);
+  extract_dbbd(*h, n, nnz, row_ptr, col_idx, val, part, pieces);
+  for (int q = 0; q < h->nprob; ++q)
+    if (h->s > h->h_goff[q + 1] - h->h_goff[q]) fail(INVALID_ARG, "k + p exceeds the interface size n_gamma");
+  h->segG.build(h->h_goff, h->stream);
+  h->segN.build(h->h_noff, h->stream);
+  h->small.alloc(small_scratch_elems() * h->nprob);
+  ev.rec(1);
+  tile_cholesky(h->L1, h->dflags.p + 8, h->stream);
+  check_chol(*h, 1, info);
+  if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_build(*h);
+  tile_cholesky(h->L2, h->dflags.p + 8, h->stream);
+  check_chol(*h, 2, info);
+  assemble_junction(*h);
+  tile_cholesky(h->LJ, h->dflags.p + 8, h->stream);
+  check_chol(*h, 3, info);
+  if (trsv1_supported_size(h->L1)) tile_make_transposed(h->L1, h->stream);
+  for (ns::TileLevel* lv : {&h->L2, &h->LJ})
+    if (lv->nblk && lv->max_nt * TILE <= 4096 && lv->nrows_pad * lv->max_nt * TILE <= (int64_t(1) << 28))
+      tile_make_inverse(*lv, h->prec_inner != 0, h->stream);
+  if (h->prec_inner) {
+    if (!h->LS.built) tile_make_fp32(h->L1, h->stream);
+    tile_make_fp32(h->L2, h->stream);
+    tile_make_fp32(h->LJ, h->stream);
+  }
+  ev.rec(2);
+  const int np = h->nprob;
+  h->it_inner.assign(np, 0);
+  h->conv_inner.assign(np, 1);
+  h->relres_inner.assign(np, 0.0);
+  h->h_keff.assign(np, 0);
+  if (h->k > 0) {
+    SmallMats sm;
+    sm.init(np, h->s, h->k);
+    DBuf<double> Om, D;
+    const double* omega = omegas[0];
+    if (np > 1) {
+      Om.alloc(h->nG * h->s);
+      for (int q = 0; q < np; ++q)
+        NS_HIP(hipMemcpyAsync(Om.p + h->h_goff[q] * h->s, omegas[q],
+                              (h->h_goff[q + 1] - h->h_goff[q]) * h->s * sizeof(double), hipMemcpyDeviceToDevice,
+                              h->stream));
+      omega = Om.p;
+    }
+    D.alloc(h->nG * h->s);
+    if (h->prec_inner)
+      block_pcg<float>(*h, sm, omega, D.p);
+    else
+      block_pcg<double>(*h, sm, omega, D.p);
+    ev.rec(3);
+    DBuf<double> Y;
+    Y.alloc(h->nG * h->s);
+    csr_mult<double>(h->AGG, D.p, h->s, Y.p, h->s, h->s, h->stream);  // Y = A_Gamma D
+    nystrom(*h, sm, omega, Y.p);
+    if (h->apply_mode == NS_APPLY_ADEF2) setup_adef2(*h);
+  } else {
+    h->keff_d.alloc(np);
+    NS_HIP(hipMemset(h->keff_d.p, 0, np * sizeof(int)));
+    ev.rec(3);
+  }
+  ev.rec(4);
+  NS_HIP(hipStreamSynchronize(h->stream));
+  if (info) {
+    for (int q = 0; q < np; ++q) {
+      ns_setup_info& o = info[q];
+      o.n = h->h_noff[q + 1] - h->h_noff[q];
+      o.n_gamma = h->h_goff[q + 1] - h->h_goff[q];
+      o.n_interior = o.n - o.n_gamma;
+      o.n_junction = h->LJ.nblk ? h->LJ.h_nb[q] : 0;
+      o.n_sub = pieces ? pieces->sub[q + 1] - pieces->sub[q] : h->nsub;
+      o.n_level2_blocks = pieces ? pieces->l2[q + 1] - pieces->l2[q] : h->nl2;
+      o.k_eff = h->h_keff[q];
+      o.it_inner = h->it_inner[q];
+      o.inner_converged = h->conv_inner[q];
+      o.inner_relres = h->relres_inner[q];
+      o.t_extract = ev.sec(0, 1);
+      o.t_factor = ev.sec(1, 2);
+      o.t_inner = ev.sec(2, 3);
+      o.t_nystrom = ev.sec(3, 4);
+      o.t_total = ev.sec(0, 4);
+    }
+  }
+}
+
+// Batch layout: part labels of every problem shifted into one numbering.
+__global__ void k_part_minmax(int64_t n, const int32_t* __restrict__ part, int* mm) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  atomicMax(&mm[0], part[i]);
+  atomicMin(&mm[1], part[i]);
+}
+__global__ void k_concat(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ part, int64_t e0,
+                         int64_t a, int sub0, int l20, int64_t* __restrict__ rpu, int32_t* __restrict__ partu) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  rpu[a + i] = rp[i] + e0;
+  const int p = part[i];
+  partu[a + i] = p >= 0 ? p + sub0 : (p <= -2 ? p - l20 : -1);
+}
+__global__ void k_check_rows(int64_t n, int64_t nnz, const int64_t* __restrict__ rp, int* bad) {
+  if (rp[0] != 0 || rp[n] != nnz) bad[0] = 1;
+}
+__global__ void k_cols_in_range(int64_t m, const int32_t* __restrict__ c, int64_t n, int* bad) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < m && (c[e] < 0 || c[e] >= n)) bad[0] = 1;
+}
+__global__ void k_shift_cols(int64_t m, const int32_t* __restrict__ c, int64_t a, int32_t* __restrict__ cu) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e < m) cu[e] = int32_t(c[e] + a);
 }
 
 }  // namespace
@@ -311,90 +725,99 @@ ns_status nystrom_schur_setup(int64_t n, int64_t nnz, const int64_t* row_ptr, co
       std::memset(info, 0, sizeof(*info));
       info->bad_block = info->bad_col = -1;
     }
-    h = new Handle();
-    h->stream = static_cast<hipStream_t>(opt->stream);
-    h->k = opt->k;
-    h->p = opt->p;
-    h->s = opt->k + opt->p;
-    h->tol_inner = opt->tol_inner > 0 ? opt->tol_inner : 0.1;
-    h->eig_rel = opt->eig_thresh_rel > 0 ? opt->eig_thresh_rel : 1e-10;
-    h->prec_inner = opt->prec_inner == NS_FP32 ? 1 : 0;
-    h->drop_rel = opt->orth_drop_rel > 0 ? opt->orth_drop_rel : (h->prec_inner ? 1e-5 : 1e-6);
-    h->max_inner = opt->max_inner_iters > 0 ? opt->max_inner_iters : 500;
-    h->apply_mode = opt->apply_mode == NS_APPLY_ADEF2 ? 1 : 0;
-    h->trsm_cols = opt->trsm_cols;
-    h->schur_mode = opt->schur_mode;
-    if (h->schur_mode < 0 || h->schur_mode > 2) fail(INVALID_ARG, "schur_mode must be 0, 1 or 2");
-    if (h->trsm_cols != 0 && h->trsm_cols != 16 && h->trsm_cols != 32 && h->trsm_cols != 64)
-      fail(INVALID_ARG, "trsm_cols must be 0, 16, 32 or 64");
-    h->dflags.alloc(16);
-    NS_HIP(hipMemset(h->dflags.p, 0, 16 * sizeof(int)));
-    NS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hflags), 16 * sizeof(int), hipHostMallocDefault));
-    NS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hscal), 64 * sizeof(double), hipHostMallocDefault));
-    h->small.alloc(small_scratch_elems());
-    Events ev(h->stream);
-    ev.rec(0);
-    extract_dbbd(*h, n, nnz, row_ptr, col_idx, val, part);
-    if (h->s > h->nG) fail(INVALID_ARG, "k + p exceeds the interface size n_gamma");
-    ev.rec(1);
-    tile_cholesky(h->L1, h->dflags.p + 8, h->stream);
-    check_chol(*h, 1, info);
-    if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_build(*h);
-    tile_cholesky(h->L2, h->dflags.p + 8, h->stream);
-    check_chol(*h, 2, info);
-    assemble_junction(*h);
-    tile_cholesky(h->LJ, h->dflags.p + 8, h->stream);
-    check_chol(*h, 3, info);
-    tile_make_transposed(h->L1, h->stream);
-    for (ns::TileLevel* lv : {&h->L2, &h->LJ})
-      if (lv->nblk && lv->max_nt * TILE <= 4096 && lv->nrows_pad * lv->max_nt * TILE <= (int64_t(1) << 28))
-        tile_make_inverse(*lv, h->prec_inner != 0, h->stream);
-    if (h->prec_inner) {
-      if (!h->LS.built) tile_make_fp32(h->L1, h->stream);
-      tile_make_fp32(h->L2, h->stream);
-      tile_make_fp32(h->LJ, h->stream);
+    h = new_handle(opt);
+    check_options(h);
+    const double* om[1] = {opt->omega};
+    setup_core(h, n, nnz, row_ptr, col_idx, val, part, nullptr, om, info);
+    *out = h;
+    return NS_OK;
+  } catch (const Error& e) {
+    ns_status st = finish(h, e);
+    delete h;
+    return st;
+  }
+}
+
+ns_status nystrom_schur_setup_batched(int32_t nprob, const int64_t* n, const int64_t* nnz,
+                                      const int64_t* const* row_ptr, const int32_t* const* col_idx,
+                                      const double* const* val, const int32_t* const* part,
+                                      const double* const* omega, const ns_options* opt, ns_handle* out,
+                                      ns_setup_info* info) {
+  if (out) *out = nullptr;
+  Handle* h = nullptr;
+  try {
+    if (!out || !opt || !n || !nnz || !row_ptr || !col_idx || !val || !part)
+      fail(INVALID_ARG, "out, opt and the per-problem arrays must not be NULL");
+    if (nprob < 1 || nprob > 65535) fail(INVALID_ARG, "nprob must be in 1..65535");
+    if (opt->k > 0 && !omega) fail(INVALID_ARG, "omega (the sketches) is required when k > 0");
+    if (info)
+      for (int q = 0; q < nprob; ++q) {
+        std::memset(info + q, 0, sizeof(*info));
+        info[q].bad_block = info[q].bad_col = -1;
+      }
+    h = new_handle(opt);
+    check_options(h);
+    hipStream_t st = h->stream;
+    Pieces pc;
+    pc.node.assign(nprob + 1, 0);
+    pc.sub.assign(nprob + 1, 0);
+    pc.l2.assign(nprob + 1, 0);
+    std::vector<int64_t> eoff(nprob + 1, 0);
+    DBuf<int> mm;
+    mm.alloc(2 * size_t(nprob));
+    std::vector<int> hmm(2 * nprob);
+    for (int q = 0; q < nprob; ++q) {
+      hmm[2 * q] = INT32_MIN;
+      hmm[2 * q + 1] = INT32_MAX;
     }
-    ev.rec(2);
-    int it = 0;
-    double relres = 0.0;
-    bool conv = true;
-    if (h->k > 0) {
-      SmallMats sm;
-      sm.init(h->s);
-      DBuf<double> D;
-      D.alloc(h->nG * h->s);
-      if (h->prec_inner)
-        it = block_pcg<float>(*h, sm, opt->omega, D.p, relres, conv);
-      else
-        it = block_pcg<double>(*h, sm, opt->omega, D.p, relres, conv);
-      ev.rec(3);
-      DBuf<double> Y;
-      Y.alloc(h->nG * h->s);
-      csr_mult<double>(h->AGG, D.p, h->s, Y.p, h->s, h->s, h->stream);  // Y = A_Gamma D
-      nystrom(*h, sm, opt->omega, Y.p);
-      if (h->apply_mode == NS_APPLY_ADEF2) setup_adef2(*h);
-    } else {
-      ev.rec(3);
+    NS_HIP(hipMemcpy(mm.p, hmm.data(), hmm.size() * sizeof(int), hipMemcpyHostToDevice));
+    for (int q = 0; q < nprob; ++q) {
+      if (n[q] <= 0 || nnz[q] < n[q] || !row_ptr[q] || !col_idx[q] || !val[q] || !part[q])
+        fail(INVALID_ARG, "problem " + std::to_string(q) + ": need n > 0, nnz >= n and non-NULL arrays");
+      if (opt->k > 0 && !omega[q]) fail(INVALID_ARG, "problem " + std::to_string(q) + ": omega is NULL");
+      if (pc.node[q] + n[q] > INT32_MAX) fail(INVALID_ARG, "batch too large (more than 2^31 - 1 unknowns)");
+      pc.node[q + 1] = pc.node[q] + n[q];
+      eoff[q + 1] = eoff[q] + nnz[q];
+      k_part_minmax<<<unsigned((n[q] + 255) / 256), 256, 0, st>>>(n[q], part[q], mm.p + 2 * q);
+      NS_LAUNCH_CHECK();
     }
-    ev.rec(4);
-    NS_HIP(hipStreamSynchronize(h->stream));
-    if (info) {
-      info->n = h->n;
-      info->n_interior = h->nI;
-      info->n_gamma = h->nG;
-      info->n_junction = h->nJ;
-      info->n_sub = h->nsub;
-      info->n_level2_blocks = h->nl2;
-      info->k_eff = h->k_eff;
-      info->it_inner = it;
-      info->inner_converged = conv ? 1 : 0;
-      info->inner_relres = relres;
-      info->t_extract = ev.sec(0, 1);
-      info->t_factor = ev.sec(1, 2);
-      info->t_inner = ev.sec(2, 3);
-      info->t_nystrom = ev.sec(3, 4);
-      info->t_total = ev.sec(0, 4);
+    NS_HIP(hipMemcpyAsync(hmm.data(), mm.p, hmm.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+    NS_HIP(hipStreamSynchronize(st));
+    for (int q = 0; q < nprob; ++q) {
+      pc.sub[q + 1] = pc.sub[q] + (hmm[2 * q] >= 0 ? hmm[2 * q] + 1 : 0);
+      pc.l2[q + 1] = pc.l2[q] + (hmm[2 * q + 1] <= -2 ? -hmm[2 * q + 1] - 1 : 0);
     }
+    // the batch as one block-diagonal matrix (each problem's CSR is validated as part of it: its
+    // columns stay inside its own rows only if they were in range)
+    const int64_t nu = pc.node[nprob], nnzu = eoff[nprob];
+    DBuf<int64_t> rpu;
+    DBuf<int32_t> colu, partu;
+    DBuf<double> valu;
+    rpu.alloc(nu + 1);
+    colu.alloc(nnzu);
+    partu.alloc(nu);
+    valu.alloc(nnzu);
+    DBuf<int> bad;
+    bad.alloc(1);
+    NS_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
+    for (int q = 0; q < nprob; ++q) {
+      // per-problem CSR structure: row_ptr[0] == 0, row_ptr[n] == nnz, columns in [0, n)
+      k_check_rows<<<1, 1, 0, st>>>(n[q], nnz[q], row_ptr[q], bad.p);
+      NS_LAUNCH_CHECK();
+      k_concat<<<unsigned((n[q] + 255) / 256), 256, 0, st>>>(n[q], row_ptr[q], part[q], eoff[q], pc.node[q],
+                                                              pc.sub[q], pc.l2[q], rpu.p, partu.p);
+      NS_LAUNCH_CHECK();
+      k_cols_in_range<<<unsigned((nnz[q] + 255) / 256), 256, 0, st>>>(nnz[q], col_idx[q], n[q], bad.p);
+      NS_LAUNCH_CHECK();
+      k_shift_cols<<<unsigned((nnz[q] + 255) / 256), 256, 0, st>>>(nnz[q], col_idx[q], pc.node[q], colu.p + eoff[q]);
+      NS_LAUNCH_CHECK();
+      NS_HIP(hipMemcpyAsync(valu.p + eoff[q], val[q], nnz[q] * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    NS_HIP(hipMemcpyAsync(rpu.p + nu, &nnzu, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    int hb = 0;
+    read_back(*h, &hb, bad.p, 1);
+    if (hb) fail(INVALID_ARG, "CSR structure invalid (row_ptr/col_idx out of range) in some problem");
+    setup_core(h, nu, nnzu, rpu.p, colu.p, valu.p, partu.p, &pc, omega, info);
     *out = h;
     return NS_OK;
   } catch (const Error& e) {
@@ -409,9 +832,9 @@ ns_status nystrom_schur_apply(ns_handle h, const double* r_gamma, double* z_gamm
   try {
     if (ncols < 1 || ncols > 1024 || !r_gamma || !z_gamma) fail(INVALID_ARG, "bad apply arguments");
     DBuf<double> work, c1, c2;
-    work.alloc(gram_work_elems(std::max(h->k, ncols)));
-    c1.alloc(size_t(std::max(h->k, 1)) * ncols);
-    c2.alloc(size_t(std::max(h->k, 1)) * ncols);
+    work.alloc(gram_work_elems(h->segG.view, std::max(h->k, ncols)));
+    c1.alloc(size_t(std::max(h->k, 1)) * ncols * h->nprob);
+    c2.alloc(size_t(std::max(h->k, 1)) * ncols * h->nprob);
     apply_prec(*h, r_gamma, ncols, z_gamma, ncols, ncols, work, c1, c2);
     NS_HIP(hipStreamSynchronize(h->stream));
     return NS_OK;
@@ -425,120 +848,82 @@ ns_status nystrom_schur_pcg_solve(ns_handle h, const double* b, double* x, doubl
   if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
   try {
     if (!b || !x || maxit < 0 || !(rtol > 0.0)) fail(INVALID_ARG, "bad pcg_solve arguments");
+    if (h->nprob != 1) fail(INVALID_ARG, "batched handle: use nystrom_schur_pcg_solve_batched");
     hipStream_t st = h->stream;
-    const int64_t n = h->n, nG = h->nG, nIp = h->L1.nrows_pad;
     Events ev(st);
     ev.rec(0);
     NS_HIP(hipMemsetAsync(h->dflags.p + 14, 0, sizeof(int), st));
-    k_finite_check<<<unsigned((n + 255) / 256), 256, 0, st>>>(n, b, h->dflags.p + 14);
+    k_finite_check<<<unsigned((h->n + 255) / 256), 256, 0, st>>>(h->n, b, h->dflags.p + 14);
     NS_LAUNCH_CHECK();
     int bad = 0;
     read_back(*h, &bad, h->dflags.p + 14, 1);
     if (bad) fail(INVALID_ARG, "b contains NaN or Inf");
-    DBuf<double> bI, f, w, r, z, p, q, sc, work, c1, c2, tmp;
-    bI.alloc(nIp);
-    for (DBuf<double>* v : {&f, &w, &r, &z, &p, &q}) v->alloc(nG);
-    sc.alloc(4 * (size_t(maxit) + 2));
-    work.alloc(std::max<size_t>(gram_work_elems(std::max(h->k, 1)), 4096));
-    c1.alloc(std::max(h->k, 1));
-    c2.alloc(std::max(h->k, 1));
-    tmp.alloc(n);
-    // f = b_Gamma - A_GammaI A_I^{-1} b_I
-    gather_rows<double>(nIp, h->iperm, b, 1, bI.p, 1, 1, st);
-    tile_solve<double>(h->L1, bI.p, 1, 1, h->trsm_cols, st);
-    {
-      // f[g] = b[gperm[g]] - sum A_GI(g, :) bI
-      DBuf<double> bG;
-      bG.alloc(nG);
-      gather_rows<double>(nG, h->gperm, b, 1, bG.p, 1, 1, st);
-      csr_mult<double>(h->AGI, bI.p, 1, f.p, 1, 1, st);
-      axpby(nG, 1.0, bG.p, -1.0, f.p, st);
-      NS_HIP(hipStreamSynchronize(st));
-    }
-    dot(nG, f.p, f.p, sc.p + 3, work, st);
-    double nf2 = 0.0;
-    read_back(*h, &nf2, sc.p + 3, 1);
-    const double nf = std::sqrt(nf2);
-    NS_HIP(hipMemsetAsync(w.p, 0, nG * sizeof(double), st));
-    NS_HIP(hipMemcpyAsync(r.p, f.p, nG * sizeof(double), hipMemcpyDeviceToDevice, st));
-    if (h->apply_mode == NS_APPLY_ADEF2 && h->k_eff > 0 && nf > 0.0) {
-      // w0 = Z E^{-1} Z^T f ; r = f - S w0
-      const int k = h->k, ke = h->k_eff;
-      gram<double, double>(nG, h->Z.p, k, ke, f.p, 1, 1, c1.p, 1.0, 0.0, work, st);
-      small_chol_apply(ke, h->Echol.p, c1.p, 1, c2.p, 1, 1, 1.0, h->small.p, st);
-      ts_update<double>(nG, 1, w.p, 1, 0.0, 1.0, h->Z.p, k, ke, c2.p, 1, nullptr, 0, 0, nullptr, 0, st);
-      op_schur<double>(*h, w.p, 1, q.p, 1, 1, false);
-      axpby(nG, 1.0, f.p, -1.0, q.p, st);
-      NS_HIP(hipMemcpyAsync(r.p, q.p, nG * sizeof(double), hipMemcpyDeviceToDevice, st));
-    }
-    int it = 0;
-    bool conv = false;
-    double rel = 0.0;
-    std::vector<double> hist;
-    if (nf == 0.0) {
-      conv = true;
-      hist.push_back(0.0);
-    } else {
-      dot(nG, r.p, r.p, sc.p + 2, work, st);
-      double rn2 = 0.0;
-      read_back(*h, &rn2, sc.p + 2, 1);
-      rel = std::sqrt(rn2) / nf;
-      hist.push_back(rel);
-      conv = rel <= rtol;
-      if (!conv) {
-        apply_prec(*h, r.p, 1, z.p, 1, 1, work, c1, c2);
-        dot(nG, r.p, z.p, sc.p + 0, work, st);
-        NS_HIP(hipMemcpyAsync(p.p, z.p, nG * sizeof(double), hipMemcpyDeviceToDevice, st));
-        for (int j = 0; j < maxit; ++j) {
-          op_schur<double>(*h, p.p, 1, q.p, 1, 1, false);                 // q = S p
-          dot(nG, p.p, q.p, sc.p + 4 * j + 1, work, st);                 // p^T q
-          pcg_update_wr(nG, sc.p, j, w.p, r.p, p.p, q.p, sc.p + 4 * j + 2, work, st);
-          read_back(*h, h->hscal, sc.p + 4 * j + 2, 1);
-          rel = std::sqrt(h->hscal[0]) / nf;
-          hist.push_back(rel);
-          it = j + 1;
-          if (!(rel > rtol)) {
-            conv = rel <= rtol;
-            break;
-          }
-          apply_prec(*h, r.p, 1, z.p, 1, 1, work, c1, c2);              // z = M r
-          dot(nG, r.p, z.p, sc.p + 4 * (j + 1), work, st);               // rho_{j+1}
-          pcg_update_p(nG, sc.p, j, z.p, p.p, st);
-        }
+    std::vector<SolveOut> res;
+    pcg_core(*h, b, x, rtol, maxit, res);
+    ev.rec(1);
+    if (info) {
+      info->it_pcg = res[0].it;
+      info->converged = res[0].converged;
+      info->relres_schur = res[0].relres_schur;
+      info->relres_true = res[0].relres_true;
+      info->t_solve = ev.sec(0, 1);
+      if (info->res_hist && info->res_hist_cap > 0) {
+        const size_t m = std::min<size_t>(res[0].hist.size(), size_t(info->res_hist_cap));
+        std::memcpy(info->res_hist, res[0].hist.data(), m * sizeof(double));
       }
     }
-    // back-substitution: x_I = A_I^{-1} (b_I - A_IGamma w), x_Gamma = w
-    {
-      DBuf<double> rhs;
-      rhs.alloc(nIp);
-      gather_rows<double>(nIp, h->iperm, b, 1, rhs.p, 1, 1, st);
-      csr_mult<double>(h->AIG, w.p, 1, bI.p, 1, 1, st);
-      axpby(nIp, 1.0, rhs.p, -1.0, bI.p, st);
-      tile_solve<double>(h->L1, bI.p, 1, 1, h->trsm_cols, st);
-      scatter_rows<double, double>(nIp, h->iperm, bI.p, 1, x, 1, 1, st);
-      scatter_rows<double, double>(nG, h->gperm, w.p, 1, x, 1, 1, st);
-      // true residual ||b - A x|| / ||b||
-      csr_mult<double>(h->Aorig, x, 1, tmp.p, 1, 1, st);
-      k_sub<<<unsigned((n + 255) / 256), 256, 0, st>>>(n, b, tmp.p, tmp.p);
-      NS_LAUNCH_CHECK();
-      dot(n, tmp.p, tmp.p, sc.p + 1, work, st);
-      dot(n, b, b, sc.p + 2, work, st);
-      double rr[2];
-      read_back(*h, rr, sc.p + 1, 2);
-      ev.rec(1);
-      if (info) {
-        info->it_pcg = it;
-        info->converged = conv ? 1 : 0;
-        info->relres_schur = rel;
-        info->relres_true = rr[1] > 0 ? std::sqrt(rr[0] / rr[1]) : 0.0;
-        info->t_solve = ev.sec(0, 1);
-        if (info->res_hist && info->res_hist_cap > 0) {
-          const size_t m = std::min<size_t>(hist.size(), size_t(info->res_hist_cap));
-          std::memcpy(info->res_hist, hist.data(), m * sizeof(double));
-        }
+    if (!res[0].converged) fail(NOT_CONVERGED, "PCG did not reach rtol within maxit iterations");
+    return NS_OK;
+  } catch (const Error& e) {
+    return finish(h, e);
+  }
+}
+
+ns_status nystrom_schur_pcg_solve_batched(ns_handle h, const double* const* b, double* const* x, double rtol,
+                                          int32_t maxit, ns_solve_info* info) {
+  if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
+  try {
+    if (!b || !x || maxit < 0 || !(rtol > 0.0)) fail(INVALID_ARG, "bad pcg_solve_batched arguments");
+    hipStream_t st = h->stream;
+    const int np = h->nprob;
+    Events ev(st);
+    ev.rec(0);
+    DBuf<double> bu, xu;
+    bu.alloc(h->n);
+    xu.alloc(h->n);
+    for (int q = 0; q < np; ++q) {
+      if (!b[q] || !x[q]) fail(INVALID_ARG, "NULL right-hand side or solution pointer");
+      NS_HIP(hipMemcpyAsync(bu.p + h->h_noff[q], b[q], (h->h_noff[q + 1] - h->h_noff[q]) * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+    }
+    NS_HIP(hipMemsetAsync(h->dflags.p + 14, 0, sizeof(int), st));
+    k_finite_check<<<unsigned((h->n + 255) / 256), 256, 0, st>>>(h->n, bu.p, h->dflags.p + 14);
+    NS_LAUNCH_CHECK();
+    int bad = 0;
+    read_back(*h, &bad, h->dflags.p + 14, 1);
+    if (bad) fail(INVALID_ARG, "b contains NaN or Inf");
+    std::vector<SolveOut> res;
+    pcg_core(*h, bu.p, xu.p, rtol, maxit, res);
+    for (int q = 0; q < np; ++q)
+      NS_HIP(hipMemcpyAsync(x[q], xu.p + h->h_noff[q], (h->h_noff[q + 1] - h->h_noff[q]) * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
+    ev.rec(1);
+    const double t = ev.sec(0, 1);
+    bool all = true;
+    for (int q = 0; q < np; ++q) {
+      all = all && res[q].converged;
+      if (!info) continue;
+      info[q].it_pcg = res[q].it;
+      info[q].converged = res[q].converged;
+      info[q].relres_schur = res[q].relres_schur;
+      info[q].relres_true = res[q].relres_true;
+      info[q].t_solve = t;
+      if (info[q].res_hist && info[q].res_hist_cap > 0) {
+        const size_t m = std::min<size_t>(res[q].hist.size(), size_t(info[q].res_hist_cap));
+        std::memcpy(info[q].res_hist, res[q].hist.data(), m * sizeof(double));
       }
     }
-    if (!conv) fail(NOT_CONVERGED, "PCG did not reach rtol within maxit iterations");
+    if (!all) fail(NOT_CONVERGED, "PCG did not reach rtol within maxit iterations for some problem");
     return NS_OK;
   } catch (const Error& e) {
     return finish(h, e);
@@ -633,13 +1018,14 @@ ns_status nystrom_schur_get_sizes(ns_handle h, int64_t* out) {
   out[4] = h->nJ;
   out[5] = h->nl2;
   out[6] = h->k_eff;
-  out[7] = h->nsub ? h->L1.h_nb[0] : 0;
+  out[7] = h->nprob;
   return NS_OK;
 }
 
 ns_status nystrom_schur_get_lowrank(ns_handle h, double* Z, double* Sigma) {
   if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
   try {
+    if (h->nprob != 1) fail(INVALID_ARG, "batched handle: low-rank terms are per problem");
     if (h->k_eff > 0) {
       if (Z)
         NS_HIP(hipMemcpy2DAsync(Z, h->k_eff * sizeof(double), h->Z.p, h->k * sizeof(double),

@@ -1,64 +1,134 @@
 // Block-vector and small dense kernels (declarations).
+//
+// Block vectors are row-major n x c arrays over the interface rows.  The rows
+// are split into segments, one per problem of a batch (a single problem is one
+// segment): every reduction (Gram products, column norms, dot products) is
+// taken per segment, over a fixed number of row chunks that depends only on
+// the segment's row count, so a problem gives bitwise the same sums alone or
+// inside a batch.  Per-segment small matrices are stacked with a stride.
 #pragma once
 
 #include "ns_internal.h"
 
 namespace ns {
 
-// G (ra x rb, row-major) = alpha * A^T B + beta * G; A: n x ra (ld lda), B: n x rb.
-// work: at least gram_work_elems(max(ra, rb)) doubles.
-template <class TA, class TB>
-void gram(int64_t n, const TA* A, int64_t lda, int ra, const TB* B, int64_t ldb, int rb, double* G, double alpha,
-          double beta, double* work, hipStream_t st);
-size_t gram_work_elems(int maxw);
+// Row segments (device arrays; host copies for sizing).
+struct Seg {
+  int n = 0;                     // segments
+  int64_t rows = 0;              // total rows
+  const int64_t* off = nullptr;  // [n + 1] first row of each segment
+  const int* coff = nullptr;     // [n + 1] prefix of reduction chunks per segment
+  const int* toff = nullptr;     // [n + 1] prefix of 64-row tiles per segment
+  const int* rseg = nullptr;     // [rows] segment of each row
+  int nchunk = 0, ntile = 0;     // totals
+};
+// Owner of a segment description.
+struct SegBuf {
+  DBuf<int64_t> off;
+  DBuf<int> coff, toff, rseg;
+  std::vector<int64_t> h_off;
+  Seg view;
+  void build(const std::vector<int64_t>& offsets, hipStream_t st);
+};
+// reduction chunks of a segment with `rows` rows
+int seg_chunks(int64_t rows);
 
-// Out = beta * Out + gamma * (X M + X2 M2); M: rm x ncols (ld ldm), FP64; X2 optional (rm2 = 0).
+// G_p (ra x rb, row-major, at G + p * gstride) = alpha * A_p^T B_p + beta * G_p for every segment p.
+// work: at least gram_work_elems(seg, max(ra, rb)) doubles.
+template <class TA, class TB>
+void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t ldb, int rb, double* G,
+          int64_t gstride, double alpha, double beta, double* work, hipStream_t st);
+size_t gram_work_elems(const Seg& sg, int maxw);
+
+// Out_p = beta * Out_p + gamma * (X_p M_p + X2_p M2_p) on the rows of every segment p;
+// M_p: rm x ncols (ld ldm) at M + p * mstride, FP64; X2 optional (rm2 = 0).
 template <class T>
-void ts_update(int64_t n, int ncols, T* Out, int64_t ldo, double beta, double gamma, const T* X, int64_t ldx, int rm,
-               const double* M, int64_t ldm, const T* X2, int64_t ldx2, int rm2, const double* M2, int64_t ldm2,
-               hipStream_t st);
+void ts_update(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, double gamma, const T* X, int64_t ldx,
+               int rm, const double* M, int64_t ldm, int64_t mstride, const T* X2 = nullptr, int64_t ldx2 = 0,
+               int rm2 = 0, const double* M2 = nullptr, int64_t ldm2 = 0, int64_t m2stride = 0,
+               hipStream_t st = nullptr);
 
 template <class T, class U>
 void convert_block(int64_t n, int ncols, const T* X, int64_t ldx, U* Y, int64_t ldy, hipStream_t st);
 
-// out[c] = sum_r X[r, c]^2
+// out[p * ncols + c] = sum over the rows r of segment p of X[r, c]^2
 template <class T>
-void col_sumsq(int64_t n, int ncols, const T* X, int64_t ldx, double* out, double* work, hipStream_t st);
+void col_sumsq(const Seg& sg, int ncols, const T* X, int64_t ldx, double* out, double* work, hipStream_t st);
 
-void dot(int64_t n, const double* x, const double* y, double* out, double* work, hipStream_t st);
-void pcg_update_wr(int64_t n, const double* sc, int it, double* w, double* r, const double* p, const double* q,
-                   double* rn2_out, double* work, hipStream_t st);
-void pcg_update_p(int64_t n, const double* sc, int it, const double* z, double* p, hipStream_t st);
+// out[p * ostride] = x_p^T y_p
+void dot(const Seg& sg, const double* x, const double* y, double* out, int64_t ostride, double* work,
+         hipStream_t st);
+// y = a x + b y (no reduction)
 void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st);
 
-// ---------------------------------------------------------------- small dense (one workgroup)
-// All matrices row-major FP64 in device memory; gw: global scratch of
-// small_scratch_elems() doubles, used when a matrix does not fit in LDS.
+// ---------------------------------------------------------------- PCG with per-problem state
+// Scalars of problem p live at ps + p * PS: rho_j, rho_{j+1}, p^T q, ||r||^2, ||f||.  The iteration
+// index j is a device counter, so one captured iteration body serves every iteration.
+// done[p] freezes problem p's iterate once it met the tolerance (1) or its residual is not a number (2);
+// it[p] is its iteration count; hist[p * hstride + j] the relative residual after iteration j (j = 0:
+// initial).  Iterations j >= maxit change nothing.
+constexpr int PS = 8;
+constexpr int PS_RHO = 0, PS_RHO_NEW = 1, PS_PQ = 2, PS_RN2 = 3, PS_NF = 4;
+struct PcgState {
+  double* ps;
+  int* done;
+  int* it;
+  int* ndone;  // number of problems done (device counter)
+  int* j;      // current iteration (device counter)
+  double* hist;
+  int64_t hstride;
+  double rtol;
+  int maxit;
+};
+// w += alpha_p p, r -= alpha_p q for problems not done (alpha_p = rho_j / (p^T q)_p), then
+// ||r||^2 per problem, the stopping test, it and hist.
+void pcg_update_wr(const Seg& sg, const PcgState& s, double* w, double* r, const double* p, const double* q,
+                   double* work, hipStream_t st);
+// p = z + beta_p p with beta_p = rho_{j+1} / rho_j.
+void pcg_update_p(const Seg& sg, const PcgState& s, const double* z, double* p, hipStream_t st);
+// rho_j <- rho_{j+1} for every problem; j <- j + 1.
+void pcg_advance(int nseg, const PcgState& s, hipStream_t st);
+// hist[., 0] and done for the initial residual: rel = sqrt(rn2) / nf; j <- 0.
+void pcg_init_check(int nseg, const PcgState& s, hipStream_t st);
+
+// ---------------------------------------------------------------- small dense (one workgroup per problem)
+// Problem b (0 <= b < nb) of a batch uses the matrices at base + b * stride (row-major FP64, device) and
+// dimension dim[b] (dims == nullptr: the uniform value r); a problem of dimension 0 gets zero outputs.
+// gw: global scratch of small_scratch_elems() doubles per problem, used when a matrix does not fit in LDS.
+struct Batch {
+  int nb = 1;
+  const int* dims = nullptr;
+};
 
 // L (in place of D, lower) = chol(D) for an r x r SPD D; X = alpha * D^{-1} B (B: r x s, ld ldb; X ld ldx).
-// flag[0] is set to 1 when D is not numerically SPD.
-void small_chol_solve(int r, double* D, const double* B, int64_t ldb, double* X, int64_t ldx, int s, double alpha,
-                      int* flag, double* gw, hipStream_t st);
+// Rows r..s0-1 of X are set to zero (s0 = rows of the stacked X, pass r when unused).
+// flag[0] is set to 1 when some D is not numerically SPD.
+void small_chol_solve(Batch bt, int r, double* D, int64_t sD, const double* B, int64_t ldb, int64_t sB, double* X,
+                      int64_t ldx, int64_t sX, int s, int s0, double alpha, int* flag, double* gw, hipStream_t st);
 // X = alpha * (L L^T)^{-1} B with L from small_chol_solve.
-void small_chol_apply(int r, const double* L, const double* B, int64_t ldb, double* X, int64_t ldx, int s,
-                      double alpha, double* gw, hipStream_t st);
+void small_chol_apply(Batch bt, int r, const double* L, int64_t sL, const double* B, int64_t ldb, int64_t sB,
+                      double* X, int64_t ldx, int64_t sX, int s, int s0, double alpha, double* gw, hipStream_t st);
 // Orthonormalising transform of a block with Gram matrix G (s x s): T[:, c] = u_c / sqrt(lambda_c)
-// for the eigenpairs with lambda_c > drop2 * lambda_max, descending; out[0] = number kept.
-void small_svqb(int s, const double* G, double drop2, double* T, int* out, double* gw, hipStream_t st);
-// R = chol(G + shift_coef * trace(G) * I)^T (upper); Rinv = R^{-1}; Racc <- R * Racc (or R when init).
-// With ok != NULL: ok[0] = 1 when the Cholesky succeeded and 1/||R^{-1}||_F^2 > certify * trace(G), which
-// proves lambda_min(G) / lambda_max(G) > certify (so no direction falls below that ratio).
-void small_cholqr(int s, const double* G, double shift_coef, double* Rinv, double* Racc, int init, int* flag,
-                  double* gw, hipStream_t st, double certify = 0.0, int* ok = nullptr);
+// for the eigenpairs with lambda_c > drop2 * lambda_max, descending, zero columns after them;
+// out[b] = number kept.  Problems with skip[b] != 0 are left untouched.
+void small_svqb(int nb, int s, const double* G, int64_t sG, double drop2, double* T, int64_t sT, int* out,
+                const int* skip, double* gw, hipStream_t st);
+// R = chol(G + shift_b * trace(G) * I)^T (upper) on the leading dim_b block (zero elsewhere);
+// Rinv = R^{-1}; Racc <- R * Racc (or R when init).  shift_b = shift[b] when shift != nullptr.
+// With ok != nullptr: ok[b] = 1 when the Cholesky succeeded and 1/||R^{-1}||_F^2 > certify * trace(G),
+// which proves lambda_min(G) / lambda_max(G) > certify (no direction falls below that ratio).
+void small_cholqr(Batch bt, int s, const double* G, int64_t sG, const double* shift, double* Rinv, double* Racc,
+                  int init, int* flag, double* gw, hipStream_t st, double certify = 0.0, int* ok = nullptr);
 // Nystrom core: EVD of sym(C), keep eigenvalues >= eps_rel * max; T = (R V1) D1^{-1} (R V1)^T;
-// EVD of T descending; Wk = first k' eigenvectors (s x k, ld k), Ek = eigenvalues; out = {r, k'}.
-void small_nystrom(int s, int k, const double* C, const double* R, double eps_rel, double* Wk, double* Ek, int* out,
-                   double* gw, hipStream_t st);
-// c[i, j] *= sigma[i] for i < k, j < ncols (ld ldc)
-void small_rowscale(int k, int ncols, const double* sigma, double* c, int64_t ldc, hipStream_t st);
+// EVD of T descending; Wk = first k' eigenvectors (s x k, ld k), Ek = eigenvalues; out[2b..] = {r, k'}.
+void small_nystrom(int nb, int s, int k, const double* C, const double* R, double eps_rel, double* Wk, double* Ek,
+                   int* out, double* gw, hipStream_t st);
+// c_b[i, j] *= sigma_b[i] for i < k, j < ncols (ld ldc; c_b = c + b * sc, sigma_b = sigma + b * ssig)
+void small_rowscale(int nb, int k, int ncols, const double* sigma, int64_t ssig, double* c, int64_t ldc, int64_t sc,
+                    hipStream_t st);
 // Symmetric EVD (descending) of an m x m matrix: W (m x m) eigenvectors in columns, E eigenvalues.
 void small_sym_evd(int m, const double* A, double* W, double* E, double* gw, hipStream_t st);
-// scratch (doubles) the small EVD kernels need in global memory when s is large
+// scratch (doubles per problem) the small kernels need in global memory when s is large
 size_t small_scratch_elems();
 
 }  // namespace ns

@@ -14,6 +14,10 @@ namespace {
 constexpr int NT = 1024;                  // threads per workgroup
 constexpr size_t LDS_LIMIT = 136 * 1024;  // dynamic LDS used when the matrices fit
 constexpr int SMAX = 256;                 // largest s supported by the small kernels
+// global scratch per problem: two SMAX x (SMAX + 1) matrices or the Cholesky-solve layout
+constexpr size_t scratch_evd = size_t(2) * SMAX * (SMAX + 1);
+constexpr size_t scratch_cs = size_t(SMAX) * (SMAX + 1) + size_t(SMAX) * (4 * SMAX + 1);
+constexpr size_t small_scratch_per_problem = scratch_evd > scratch_cs ? scratch_evd : scratch_cs;
 
 __device__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
@@ -123,28 +127,28 @@ __device__ void sort_desc(const double* d, int n, int* order) {
   __syncthreads();
 }
 
-// In-place lower Cholesky of A (n x n, stride lda).  Returns 0 or the 1-based
-// index of the first non-positive pivot (the pivot is then taken as 1).
+// In-place lower Cholesky of A (n x n, stride lda), right-looking: every
+// thread reads the pivot, the column below it is scaled, then the trailing
+// lower triangle is updated by a 32 x 32 thread grid.  Returns 0 or the
+// 1-based index of the first non-positive pivot (the pivot is then taken as 1).
 __device__ int chol_dev(double* A, int n, int lda, int* sinfo) {
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   if (threadIdx.x == 0) *sinfo = 0;
   __syncthreads();
   for (int c = 0; c < n; ++c) {
+    double d = A[c * lda + c];
+    const bool bad = !(d > 0.0);
+    if (bad) d = 1.0;
+    const double sq = sqrt(d), inv = 1.0 / sq;
+    for (int r = c + 1 + threadIdx.x; r < n; r += NT) A[r * lda + c] *= inv;
+    __syncthreads();
     if (threadIdx.x == 0) {
-      double d = A[c * lda + c];
-      if (!(d > 0.0)) {
-        if (*sinfo == 0) *sinfo = c + 1;
-        d = 1.0;
-      }
-      A[c * lda + c] = sqrt(d);
+      A[c * lda + c] = sq;
+      if (bad && *sinfo == 0) *sinfo = c + 1;
     }
-    __syncthreads();
-    const double dinv = 1.0 / A[c * lda + c];
-    for (int r = c + 1 + threadIdx.x; r < n; r += NT) A[r * lda + c] *= dinv;
-    __syncthreads();
-    const int m = n - 1 - c;
-    for (int idx = threadIdx.x; idx < m * m; idx += NT) {
-      const int q = c + 1 + idx / m, r = c + 1 + idx % m;
-      if (r >= q) A[r * lda + q] -= A[r * lda + c] * A[q * lda + c];
+    for (int q = c + 1 + ty; q < n; q += 32) {
+      const double aq = A[q * lda + c];
+      for (int r = q + tx; r < n; r += 32) A[r * lda + q] -= A[r * lda + c] * aq;
     }
     __syncthreads();
   }
@@ -153,17 +157,17 @@ __device__ int chol_dev(double* A, int n, int lda, int* sinfo) {
   return info;
 }
 
-// X (r x s, stride ldx) <- (L L^T)^{-1} X, right-looking row sweeps, all
-// columns and rows of a step in parallel.
+// X (r x s, stride ldx) <- (L L^T)^{-1} X: forward then backward row sweeps,
+// each step's rows (32 thread rows) and columns (32 thread columns) in parallel.
 __device__ void chol_solve_inplace(const double* L, int r, int ldl, double* X, int ldx, int s) {
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int m = 0; m < r; ++m) {  // forward: L y = x
     const double inv = 1.0 / L[m * ldl + m];
     for (int j = threadIdx.x; j < s; j += NT) X[m * ldx + j] *= inv;
     __syncthreads();
-    const int rows = r - 1 - m;
-    for (int t = threadIdx.x; t < rows * s; t += NT) {
-      const int i = m + 1 + t / s, j = t % s;
-      X[i * ldx + j] -= L[i * ldl + m] * X[m * ldx + j];
+    for (int i = m + 1 + ty; i < r; i += 32) {
+      const double l = L[i * ldl + m];
+      for (int j = tx; j < s; j += 32) X[i * ldx + j] -= l * X[m * ldx + j];
     }
     __syncthreads();
   }
@@ -171,9 +175,9 @@ __device__ void chol_solve_inplace(const double* L, int r, int ldl, double* X, i
     const double inv = 1.0 / L[m * ldl + m];
     for (int j = threadIdx.x; j < s; j += NT) X[m * ldx + j] *= inv;
     __syncthreads();
-    for (int t = threadIdx.x; t < m * s; t += NT) {
-      const int i = t / s, j = t % s;
-      X[i * ldx + j] -= L[m * ldl + i] * X[m * ldx + j];
+    for (int i = ty; i < m; i += 32) {
+      const double l = L[m * ldl + i];
+      for (int j = tx; j < s; j += 32) X[i * ldx + j] -= l * X[m * ldx + j];
     }
     __syncthreads();
   }
@@ -184,22 +188,33 @@ __host__ __device__ inline size_t cs_lds(int r, int s) {
   return (size_t(r) * (r + 1) + size_t(r) * (s + 1)) * sizeof(double);
 }
 
-__global__ __launch_bounds__(NT) void k_small_chol_solve(int r, double* D, const double* B, int64_t ldb, double* X,
-                                                         int64_t ldx, int s, double alpha, int* flag, int factor,
-                                                         double* gw) {
+// Problem b: D (r0 x r0, ld r0) at D + b sD, leading rb = dims[b] block used; B, X likewise.
+__global__ __launch_bounds__(NT) void k_small_chol_solve(int r0, const int* __restrict__ dims, double* D, int64_t sD,
+                                                         const double* B, int64_t ldb, int64_t sB, double* X,
+                                                         int64_t ldx, int64_t sX, int s, int s0, double alpha,
+                                                         int* flag, int factor, double* gw) {
   extern __shared__ double sm[];
   __shared__ int sinfo;
-  const bool lds = cs_lds(r, s) <= LDS_LIMIT;
+  const int b = blockIdx.x;
+  const int r = dims ? dims[b] : r0;
+  D += b * sD;
+  B += b * sB;
+  X += b * sX;
+  gw += b * int64_t(small_scratch_per_problem);
+  // rows r .. s0 - 1 of X are zero (directions this problem does not have)
+  for (int e = threadIdx.x; e < (s0 - r) * s; e += NT) X[(r + e / s) * ldx + e % s] = 0.0;
+  if (r == 0) return;
+  const bool lds = cs_lds(r0, s) <= LDS_LIMIT;  // the launch's dynamic LDS is sized for r0 >= r
   double* Ls = lds ? sm : gw;
   const int ldl = r + 1, lx = s + 1;
   double* Xs = Ls + size_t(r) * ldl;
-  for (int e = threadIdx.x; e < r * r; e += NT) Ls[(e / r) * ldl + e % r] = D[e];
+  for (int e = threadIdx.x; e < r * r; e += NT) Ls[(e / r) * ldl + e % r] = D[(e / r) * r0 + e % r];
   for (int e = threadIdx.x; e < r * s; e += NT) Xs[(e / s) * lx + e % s] = B[(e / s) * ldb + e % s];
   __syncthreads();
   if (factor) {
     const int info = chol_dev(Ls, r, ldl, &sinfo);
     if (info && threadIdx.x == 0) flag[0] = 1;
-    for (int e = threadIdx.x; e < r * r; e += NT) D[e] = Ls[(e / r) * ldl + e % r];
+    for (int e = threadIdx.x; e < r * r; e += NT) D[(e / r) * r0 + e % r] = Ls[(e / r) * ldl + e % r];
     __syncthreads();
   }
   chol_solve_inplace(Ls, r, ldl, Xs, lx, s);
@@ -230,12 +245,17 @@ __device__ EvdSpace evd_space(int n, double* sm, double* gw, double* small_d, in
   return e;
 }
 
-__global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, double drop2, double* T, int* out,
-                                                   double* gw) {
+__global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, int64_t sG, double drop2, double* T,
+                                                   int64_t sT, int* out, const int* skip, double* gw) {
   extern __shared__ double sm[];
   __shared__ double red[NT];
   __shared__ double sd[3 * SMAX];
   __shared__ int si[3 * SMAX];
+  const int b = blockIdx.x;
+  if (skip && skip[b]) return;
+  G += b * sG;
+  T += b * sT;
+  gw += b * int64_t(small_scratch_per_problem);
   EvdSpace w = evd_space(s, sm, gw, sd, si);
   const int ld = w.ld;
   for (int e = threadIdx.x; e < s * s; e += NT) {
@@ -260,73 +280,78 @@ __global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, doubl
     const int i = e / s, c = e % s;
     T[e] = c < kept ? w.V[i * ld + w.ord[c]] / sqrt(w.d[w.ord[c]]) : 0.0;
   }
-  if (threadIdx.x == 0) out[0] = kept;
+  if (threadIdx.x == 0) out[b] = kept;
 }
 
-__global__ __launch_bounds__(NT) void k_small_cholqr(int s, const double* G, double shift_coef, double* Rinv,
-                                                     double* Racc, int init, int* flag, double* gw, double certify,
-                                                     int* ok) {
+// Problem b: G (s x s) at G + b sG; the leading n = dims[b] block is factored, everything else of Rinv and
+// Racc is zero.
+__global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restrict__ dims, const double* G, int64_t sG,
+                                                     const double* shift_coef, double* Rinv, double* Racc, int init,
+                                                     int* flag, double* gw, double certify, int* ok) {
   extern __shared__ double sm[];
   __shared__ int sinfo;
   __shared__ double sshift, strace;
+  __shared__ double red[NT];
+  const int b = blockIdx.x;
+  const int n = dims ? dims[b] : s;
+  G += b * sG;
+  Rinv += b * int64_t(s) * s;
+  Racc += b * int64_t(s) * s;
+  gw += b * int64_t(small_scratch_per_problem);
+  if (n == 0) {
+    for (int e = threadIdx.x; e < s * s; e += NT) Rinv[e] = Racc[e] = 0.0;
+    if (ok && threadIdx.x == 0) ok[b] = 0;
+    return;
+  }
   if (threadIdx.x == 0) {
     double tr = 0.0;
-    for (int i = 0; i < s; ++i) tr += G[i * s + i];
-    sshift = shift_coef * tr;
+    for (int i = 0; i < n; ++i) tr += G[i * s + i];
+    sshift = (shift_coef ? shift_coef[b] : 0.0) * tr;
     strace = tr;
   }
   __syncthreads();
   const double shift = sshift;
-  const bool lds = evd_bytes(s) <= LDS_LIMIT;
-  const int ld = s + 1;
+  const bool lds = evd_bytes(s) <= LDS_LIMIT;  // the launch's dynamic LDS is sized for s >= n
+  const int ld = n + 1;
   double* A = lds ? sm : gw;
-  double* X = A + size_t(s) * ld;
-  for (int e = threadIdx.x; e < s * s; e += NT) {
-    const int i = e / s, j = e % s;
+  double* X = A + size_t(n) * ld;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int e = threadIdx.x; e < n * n; e += NT) {
+    const int i = e / n, j = e % n;
     A[i * ld + j] = 0.5 * (G[i * s + j] + G[j * s + i]) + (i == j ? shift : 0.0);
     X[i * ld + j] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (chol_dev(A, s, ld, &sinfo) && threadIdx.x == 0) flag[0] = 1;
-  // X = L^{-1}: forward sweep on the identity
-  for (int m = 0; m < s; ++m) {
+  if (chol_dev(A, n, ld, &sinfo) && threadIdx.x == 0) flag[0] = 1;
+  // X = L^{-1}: forward sweep on the identity (row m scaled, then the rows below updated)
+  for (int m = 0; m < n; ++m) {
     const double inv = 1.0 / A[m * ld + m];
     for (int j = threadIdx.x; j <= m; j += NT) X[m * ld + j] *= inv;
     __syncthreads();
-    const int rows = s - 1 - m;
-    for (int t = threadIdx.x; t < rows * (m + 1); t += NT) {
-      const int i = m + 1 + t / (m + 1), j = t % (m + 1);
-      X[i * ld + j] -= A[i * ld + m] * X[m * ld + j];
+    for (int i = m + 1 + ty; i < n; i += 32) {
+      const double l = A[i * ld + m];
+      for (int j = tx; j <= m; j += 32) X[i * ld + j] -= l * X[m * ld + j];
     }
     __syncthreads();
   }
-  // Rinv = (L^{-1})^T (upper); R = L^T
+  // Rinv = (L^{-1})^T (upper) in the leading block, zero elsewhere; R = L^T
   double fro = 0.0;
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
-    const double x = X[j * ld + i];
+    const double x = (i < n && j < n) ? X[j * ld + i] : 0.0;
     Rinv[e] = x;
     fro += x * x;
   }
   if (ok) {
     // lambda_min(G) >= 1 / ||L^{-1}||_F^2 and lambda_max(G) <= trace(G): certify that no
     // singular value ratio of the block is at or below the drop tolerance
-    __shared__ double red[NT];
-    red[threadIdx.x] = fro;
-    __syncthreads();
-    for (int o = NT / 2; o > 0; o >>= 1) {
-      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      const double lmin_lb = 1.0 / red[0];
-      ok[0] = (sinfo == 0 && lmin_lb > certify * strace) ? 1 : 0;
-    }
+    const double f = block_sum(fro, red);
+    if (threadIdx.x == 0) ok[b] = (sinfo == 0 && 1.0 / f > certify * strace) ? 1 : 0;
   }
   __syncthreads();
   // Racc <- R * Racc ; X reused for the product
-  for (int e = threadIdx.x; e < s * s; e += NT) {
-    const int i = e / s, j = e % s;
+  for (int e = threadIdx.x; e < n * n; e += NT) {
+    const int i = e / n, j = e % n;
     double acc = 0.0;
     if (init) {
       acc = j >= i ? A[j * ld + i] : 0.0;
@@ -336,7 +361,10 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const double* G, dou
     X[i * ld + j] = acc;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < s * s; e += NT) Racc[e] = X[(e / s) * ld + e % s];
+  for (int e = threadIdx.x; e < s * s; e += NT) {
+    const int i = e / s, j = e % s;
+    Racc[e] = (i < n && j < n) ? X[i * ld + j] : 0.0;
+  }
 }
 
 __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double* C, const double* R, double eps_rel,
@@ -348,6 +376,13 @@ __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double
   __shared__ double dkeep[SMAX];
   __shared__ int ikeep[SMAX];
   __shared__ int nkeep;
+  const int b = blockIdx.x;
+  C += b * int64_t(s) * s;
+  R += b * int64_t(s) * s;
+  Wk += b * int64_t(s) * k;
+  Ek += b * int64_t(k);
+  out += 2 * b;
+  gw += b * int64_t(small_scratch_per_problem);
   EvdSpace w = evd_space(s, sm, gw, sd, si);
   const int ld = w.ld;
   for (int e = threadIdx.x; e < s * s; e += NT) {  // symmetrised C
@@ -407,11 +442,13 @@ __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double
   }
 }
 
-__global__ void k_small_rowscale(int k, int ncols, const double* sigma, double* c, int64_t ldc) {
+__global__ void k_small_rowscale(int k, int ncols, const double* sigma, int64_t ssig, double* c, int64_t ldc,
+                                 int64_t sc) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
   if (idx >= k * ncols) return;
   const int i = idx / ncols, j = idx % ncols;
-  c[i * ldc + j] *= sigma[i];
+  c[b * sc + i * ldc + j] *= sigma[b * ssig + i];
 }
 
 __global__ __launch_bounds__(NT) void k_small_sym_evd(int m, const double* Ain, double* W, double* E, double* gw) {
@@ -444,53 +481,53 @@ size_t evd_lds(int n) {
 
 }  // namespace
 
-size_t small_scratch_elems() {
-  const size_t evd = size_t(2) * SMAX * (SMAX + 1), cs = size_t(SMAX) * (SMAX + 1) + size_t(SMAX) * (4 * SMAX + 1);
-  return evd > cs ? evd : cs;
-}
+size_t small_scratch_elems() { return small_scratch_per_problem; }
 
-void small_chol_solve(int r, double* D, const double* B, int64_t ldb, double* X, int64_t ldx, int s, double alpha,
-                      int* flag, double* gw, hipStream_t st) {
-  if (r <= 0) return;
+void small_chol_solve(Batch bt, int r, double* D, int64_t sD, const double* B, int64_t ldb, int64_t sB, double* X,
+                      int64_t ldx, int64_t sX, int s, int s0, double alpha, int* flag, double* gw, hipStream_t st) {
+  if (bt.nb <= 0 || (r <= 0 && s0 <= 0)) return;  // s == 0: factor only
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
-  const size_t b = cs_lds(r, s);
-  k_small_chol_solve<<<1, NT, b <= LDS_LIMIT ? b : 0, st>>>(r, D, B, ldb, X, ldx, s, alpha, flag, 1, gw);
+  const size_t lb = cs_lds(r, s);
+  k_small_chol_solve<<<bt.nb, NT, lb <= LDS_LIMIT ? lb : 0, st>>>(r, bt.dims, D, sD, B, ldb, sB, X, ldx, sX, s, s0,
+                                                                   alpha, flag, 1, gw);
   NS_LAUNCH_CHECK();
 }
 
-void small_chol_apply(int r, const double* L, const double* B, int64_t ldb, double* X, int64_t ldx, int s,
-                      double alpha, double* gw, hipStream_t st) {
-  if (r <= 0 || s <= 0) return;
+void small_chol_apply(Batch bt, int r, const double* L, int64_t sL, const double* B, int64_t ldb, int64_t sB,
+                      double* X, int64_t ldx, int64_t sX, int s, int s0, double alpha, double* gw, hipStream_t st) {
+  if (bt.nb <= 0 || (r <= 0 && s0 <= 0) || s <= 0) return;
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
-  const size_t b = cs_lds(r, s);
-  k_small_chol_solve<<<1, NT, b <= LDS_LIMIT ? b : 0, st>>>(r, const_cast<double*>(L), B, ldb, X, ldx, s, alpha,
-                                                            nullptr, 0, gw);
+  const size_t lb = cs_lds(r, s);
+  k_small_chol_solve<<<bt.nb, NT, lb <= LDS_LIMIT ? lb : 0, st>>>(r, bt.dims, const_cast<double*>(L), sL, B, ldb, sB,
+                                                                   X, ldx, sX, s, s0, alpha, nullptr, 0, gw);
   NS_LAUNCH_CHECK();
 }
 
-void small_svqb(int s, const double* G, double drop2, double* T, int* out, double* gw, hipStream_t st) {
+void small_svqb(int nb, int s, const double* G, int64_t sG, double drop2, double* T, int64_t sT, int* out,
+                const int* skip, double* gw, hipStream_t st) {
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
-  k_small_svqb<<<1, NT, evd_lds(s), st>>>(s, G, drop2, T, out, gw);
+  k_small_svqb<<<nb, NT, evd_lds(s), st>>>(s, G, sG, drop2, T, sT, out, skip, gw);
   NS_LAUNCH_CHECK();
 }
 
-void small_cholqr(int s, const double* G, double shift_coef, double* Rinv, double* Racc, int init, int* flag,
-                  double* gw, hipStream_t st, double certify, int* ok) {
+void small_cholqr(Batch bt, int s, const double* G, int64_t sG, const double* shift, double* Rinv, double* Racc,
+                  int init, int* flag, double* gw, hipStream_t st, double certify, int* ok) {
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
-  k_small_cholqr<<<1, NT, evd_lds(s), st>>>(s, G, shift_coef, Rinv, Racc, init, flag, gw, certify, ok);
+  k_small_cholqr<<<bt.nb, NT, evd_lds(s), st>>>(s, bt.dims, G, sG, shift, Rinv, Racc, init, flag, gw, certify, ok);
   NS_LAUNCH_CHECK();
 }
 
-void small_nystrom(int s, int k, const double* C, const double* R, double eps_rel, double* Wk, double* Ek, int* out,
-                   double* gw, hipStream_t st) {
+void small_nystrom(int nb, int s, int k, const double* C, const double* R, double eps_rel, double* Wk, double* Ek,
+                   int* out, double* gw, hipStream_t st) {
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
-  k_small_nystrom<<<1, NT, evd_lds(s), st>>>(s, k, C, R, eps_rel, Wk, Ek, out, gw);
+  k_small_nystrom<<<nb, NT, evd_lds(s), st>>>(s, k, C, R, eps_rel, Wk, Ek, out, gw);
   NS_LAUNCH_CHECK();
 }
 
-void small_rowscale(int k, int ncols, const double* sigma, double* c, int64_t ldc, hipStream_t st) {
-  if (k * ncols == 0) return;
-  k_small_rowscale<<<(k * ncols + 255) / 256, 256, 0, st>>>(k, ncols, sigma, c, ldc);
+void small_rowscale(int nb, int k, int ncols, const double* sigma, int64_t ssig, double* c, int64_t ldc, int64_t sc,
+                    hipStream_t st) {
+  if (k * ncols == 0 || nb == 0) return;
+  k_small_rowscale<<<dim3((k * ncols + 255) / 256, nb), 256, 0, st>>>(k, ncols, sigma, ssig, c, ldc, sc);
   NS_LAUNCH_CHECK();
 }
 

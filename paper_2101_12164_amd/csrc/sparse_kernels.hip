@@ -237,12 +237,26 @@ __global__ void k_symcheck(int64_t n, const int64_t* __restrict__ ptr, const int
   }
 }
 
-__global__ void k_group(int64_t n, const int32_t* __restrict__ part, int nsub, int nl2, int32_t* __restrict__ grp,
-                        int32_t* __restrict__ grp2) {
+// piece of node i: the q with node[q] <= i < node[q + 1]
+__device__ __forceinline__ int piece_of(const int64_t* __restrict__ node, int P, int64_t i) {
+  int lo = 0, hi = P - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (node[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Groups local to one piece (problem): its subdomains, then its level-2 blocks, then its junction set.
+__global__ void k_group(int64_t n, const int32_t* __restrict__ part, int sub0, int nsub, int l20, int nl2,
+                        int32_t* __restrict__ grp, int32_t* __restrict__ grp2) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int p = part[i];
-  grp[i] = p >= 0 ? p : (p <= -2 ? nsub + (-2 - p) : nsub + nl2);
+  grp[i] = p >= 0 ? p - sub0 : (p <= -2 ? nsub + (-2 - p - l20) : nsub + nl2);
   grp2[i] = p < 0 ? 1 : 0;
 }
 
@@ -258,7 +272,10 @@ __global__ __launch_bounds__(1024) void k_chunk_hist(int64_t n, const int32_t* _
   for (int g = threadIdx.x; g < G; g += blockDim.x) cnt[int64_t(blockIdx.x) * G + g] = hist[g];
 }
 
-__global__ void k_chunk_offsets(int nchunk, int G, int32_t* __restrict__ cnt, int32_t* __restrict__ total) {
+// Exclusive prefix over the chunks per group; the group's total goes to total[d] with d = the piece's
+// destination of local group g (subdomains at d0 + g, level-2 blocks at d1 + g - nsub, the junction set at d2).
+__global__ void k_chunk_offsets(int nchunk, int G, int32_t* __restrict__ cnt, int32_t* __restrict__ total, int nsub,
+                                int nl2, int d0, int d1, int d2) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   int run = 0;
@@ -267,7 +284,16 @@ __global__ void k_chunk_offsets(int nchunk, int G, int32_t* __restrict__ cnt, in
     cnt[int64_t(c) * G + g] = run;
     run += v;
   }
-  total[g] = run;
+  const int d = g < nsub ? d0 + g : (g < nsub + nl2 ? d1 + g - nsub : d2);
+  if (d >= 0) total[d] = run;
+}
+
+// interface index of every interface node: rank inside its piece + the piece's interface offset
+__global__ void k_gidx_offset(int64_t n, const int32_t* __restrict__ part, const int64_t* __restrict__ node, int P,
+                              const int64_t* __restrict__ goff, int32_t* __restrict__ gidx) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n || part[i] >= 0) return;
+  gidx[i] += int32_t(goff[piece_of(node, P, i)]);
 }
 
 __global__ __launch_bounds__(1024) void k_chunk_rank(int64_t n, const int32_t* __restrict__ grp, int G,
@@ -285,11 +311,15 @@ __global__ __launch_bounds__(1024) void k_chunk_rank(int64_t n, const int32_t* _
 
 struct NodeMaps {
   const int32_t* part;
-  const int32_t* rank;   // rank inside (subdomain | level-2 block | junction set)
-  const int32_t* gidx;   // rank among interface nodes
+  const int32_t* rank;   // rank inside (subdomain | level-2 block | junction set of the piece)
+  const int32_t* gidx;   // interface index
   const int64_t* roff1;  // padded row offset of each subdomain block
   const int64_t* roff2;  // padded row offset of each level-2 block
   const int64_t* coff1;  // compact interior offset of each subdomain
+  const int64_t* node;   // [P + 1] first node of each piece
+  int P;
+  const int64_t* roffJ;  // padded row offset of each piece's junction block
+  const int* l2first;    // [P + 1] first level-2 block of each piece
 };
 
 __global__ void k_maps(int64_t n, NodeMaps m, int32_t* iperm, int32_t* icomp, int32_t* gperm, int32_t* l2src,
@@ -308,8 +338,20 @@ __global__ void k_maps(int64_t n, NodeMaps m, int32_t* iperm, int32_t* icomp, in
     if (p <= -2)
       l2src[m.roff2[-2 - p] + r] = g;
     else
-      jsrc[r] = g;
+      jsrc[m.roffJ[piece_of(m.node, m.P, i)] + r] = g;
   }
+}
+
+// padded level-2 row -> first padded row of its piece's junction block (for the dense A_s^{-1} A_sJ)
+__global__ void k_l2_jbase(int nl2, const int* __restrict__ nt2, const int64_t* __restrict__ roff2,
+                           const int* __restrict__ l2first, int P, const int64_t* __restrict__ roffJ,
+                           int64_t* __restrict__ jbase) {
+  const int b = blockIdx.y;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nt2[b] * TILE) return;
+  int q = 0;
+  while (q + 1 < P && l2first[q + 1] <= b) ++q;
+  jbase[roff2[b] + r] = roffJ[q];
 }
 
 
@@ -319,9 +361,8 @@ struct Outs {
   double *vIG, *vGI, *vGG, *vsJ, *vJs;
   float *fIG, *fGI, *fGG, *fsJ, *fJs;
   double *L1, *L2, *LJ;
-  const int *nt1, *nt2, *nbt1, *nbt2;
-  const int64_t *foff1, *foff2;
-  int ntJ;
+  const int *nt1, *nt2, *nbt1, *nbt2, *ntJ;
+  const int64_t *foff1, *foff2, *foffJ;
   int *bw1, *bw2;  // counting pass: element half-bandwidth of every diagonal block
 };
 
@@ -343,7 +384,7 @@ __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int3
   } else {
     rowG = m.gidx[i];
     if (pi <= -2) rowsJ = m.roff2[-2 - pi] + ri;
-    if (pi == -1) rowJs = ri;
+    if (pi == -1) rowJs = m.roffJ[piece_of(m.node, m.P, i)] + ri;
   }
   for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
     const int j = col[e];
@@ -396,7 +437,7 @@ __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int3
           } else {  // junction column
             if (FILL) {
               const int64_t q = o.psJ[rowsJ] + nsJ;
-              o.csJ[q] = rj;
+              o.csJ[q] = int32_t(m.roffJ[piece_of(m.node, m.P, j)] + rj);
               o.vsJ[q] = v;
               o.fsJ[q] = float(v);
             }
@@ -412,7 +453,8 @@ __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int3
             }
             ++nJs;
           } else if (FILL && ri >= rj) {
-            o.LJ[band_elem(o.ntJ, o.ntJ - 1, ri, rj)] = v;
+            const int q = piece_of(m.node, m.P, i);
+            o.LJ[o.foffJ[q] + band_elem(o.ntJ[q], o.ntJ[q] - 1, ri, rj)] = v;
           }
         }
       }
@@ -445,23 +487,32 @@ __global__ void k_pad_identity(const int* __restrict__ nt_arr, const int* __rest
   L[foff[b] + band_elem(nt, nbt_arr[b], r, r)] = 1.0;
 }
 
-__global__ void k_csr_to_dense(int64_t nrows, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                               const double* __restrict__ val, double* __restrict__ E, int64_t lde) {
-  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= nrows) return;
-  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) E[r * lde + col[e]] = val[e];
-}
-
-// S_J(ji, jj) -= sum_e A_Js(ji, e) * E(col_e, jj) on the lower triangle.
-__global__ void k_junction_update(int nJ, int ntJ, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                  const double* __restrict__ val, const double* __restrict__ E, double* __restrict__ LJ) {
+// Junction block q: S_J(ji, jj) -= sum_e A_Js(roffJ_q + ji, e) * E(col_e, jj) on the lower triangle,
+// E(row, jj) = (A_s^{-1} A_sJ) with the junction column local to the piece of the level-2 row.
+__global__ void k_junction_update(const int* __restrict__ nbJ, const int* __restrict__ ntJ,
+                                  const int64_t* __restrict__ roffJ, const int64_t* __restrict__ foffJ,
+                                  const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                  const double* __restrict__ val, const double* __restrict__ E, int64_t lde,
+                                  double* __restrict__ LJ) {
+  const int q = blockIdx.y;
+  const int nJ = nbJ[q];
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(nJ) * nJ) return;
   const int ji = int(idx / nJ), jj = int(idx % nJ);
   if (jj > ji) return;
+  const int64_t row = roffJ[q] + ji;
   double acc = 0.0;
-  for (int64_t e = ptr[ji]; e < ptr[ji + 1]; ++e) acc += val[e] * E[int64_t(col[e]) * nJ + jj];
-  LJ[band_elem(ntJ, ntJ - 1, ji, jj)] -= acc;
+  for (int64_t e = ptr[row]; e < ptr[row + 1]; ++e) acc += val[e] * E[int64_t(col[e]) * lde + jj];
+  LJ[foffJ[q] + band_elem(ntJ[q], ntJ[q] - 1, ji, jj)] -= acc;
+}
+
+// E(row, c - jbase(row)) = A_sJ(row, c)
+__global__ void k_sj_to_dense(int64_t nrows, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                              const double* __restrict__ val, const int64_t* __restrict__ jbase,
+                              double* __restrict__ E, int64_t lde) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) E[r * lde + (col[e] - jbase[r])] = val[e];
 }
 
 void pad_identity(TileLevel& lv, hipStream_t st) {
@@ -492,7 +543,7 @@ void finish_csr(Csr& A, hipStream_t st) {
 // ------------------------------------------------------------------------ API
 
 void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col, const double* val,
-                  const int32_t* part) {
+                  const int32_t* part, const Pieces* pcs) {
   hipStream_t st = h.stream;
   h.n = n;
   h.nnz = nnz;
@@ -512,54 +563,99 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
   if (h.hflags[F_NAN]) fail(INVALID_ARG, "matrix values contain NaN or Inf");
   k_symcheck<<<gn, 256, 0, st>>>(n, row_ptr, col, val, flags);
   NS_LAUNCH_CHECK();
-  h.nsub = mm[0] >= 0 ? mm[0] + 1 : 0;
-  h.nl2 = mm[1] <= -2 ? -mm[1] - 1 : 0;
-  const int G = h.nsub + h.nl2 + 1;
-  if (G > 32768) fail(INVALID_ARG, "too many subdomains + interface blocks (limit 32767)");
+  Pieces one;
+  if (!pcs) {
+    one.node = {0, n};
+    one.sub = {0, mm[0] >= 0 ? mm[0] + 1 : 0};
+    one.l2 = {0, mm[1] <= -2 ? -mm[1] - 1 : 0};
+    pcs = &one;
+  }
+  const int P = int(pcs->node.size()) - 1;
+  h.nsub = pcs->sub[P];
+  h.nl2 = pcs->l2[P];
+  if (mm[0] >= h.nsub || (mm[1] <= -2 && -mm[1] - 1 > h.nl2)) fail(INVALID_ARG, "part labels out of range");
+  h.nprob = P;
+  h.h_noff = pcs->node;
+  h.h_sub = pcs->sub;
 
-  // groups and stable ranks
-  DBuf<int32_t> grp, grp2, rank, gidx, cnt, total, total2;
+  // groups and stable ranks, piece by piece (groups never span two pieces)
+  DBuf<int32_t> grp, grp2, rank, gidx, cnt, totall;
   grp.alloc(n);
   grp2.alloc(n);
   rank.alloc(n);
   gidx.alloc(n);
-  const int nchunk = int((n + 1023) / 1024);
-  k_group<<<gn, 256, 0, st>>>(n, part, h.nsub, h.nl2, grp, grp2);
-  NS_LAUNCH_CHECK();
-  auto ranks = [&](const int32_t* g, int GG, int32_t* out, DBuf<int32_t>& tot) {
-    cnt.alloc(int64_t(nchunk) * GG);
-    tot.alloc(GG);
-    k_chunk_hist<<<nchunk, 1024, GG * sizeof(int), st>>>(n, g, GG, cnt);
+  const int ntot = h.nsub + h.nl2 + 2 * P;  // block sizes, junction counts, interface counts
+  totall.alloc(ntot);
+  NS_HIP(hipMemsetAsync(totall.p, 0, ntot * sizeof(int32_t), st));
+  int64_t cmax = 2;
+  for (int q = 0; q < P; ++q) {
+    const int64_t nq = pcs->node[q + 1] - pcs->node[q];
+    const int Gq = (pcs->sub[q + 1] - pcs->sub[q]) + (pcs->l2[q + 1] - pcs->l2[q]) + 1;
+    if (Gq > 32768) fail(INVALID_ARG, "too many subdomains + interface blocks in one problem (limit 32767)");
+    cmax = std::max(cmax, ((nq + 1023) / 1024) * std::max(Gq, 2));
+  }
+  cnt.alloc(cmax);
+  for (int q = 0; q < P; ++q) {
+    const int64_t a = pcs->node[q], nq = pcs->node[q + 1] - a;
+    if (nq == 0) continue;
+    const int nsq = pcs->sub[q + 1] - pcs->sub[q], nlq = pcs->l2[q + 1] - pcs->l2[q], Gq = nsq + nlq + 1;
+    const int nch = int((nq + 1023) / 1024);
+    k_group<<<unsigned((nq + 255) / 256), 256, 0, st>>>(nq, part + a, pcs->sub[q], nsq, pcs->l2[q], nlq, grp + a,
+                                                        grp2 + a);
     NS_LAUNCH_CHECK();
-    k_chunk_offsets<<<(GG + 255) / 256, 256, 0, st>>>(nchunk, GG, cnt, tot);
+    k_chunk_hist<<<nch, 1024, Gq * sizeof(int), st>>>(nq, grp + a, Gq, cnt);
     NS_LAUNCH_CHECK();
-    k_chunk_rank<<<nchunk, 1024, 0, st>>>(n, g, GG, cnt, out);
+    k_chunk_offsets<<<(Gq + 255) / 256, 256, 0, st>>>(nch, Gq, cnt, totall, nsq, nlq, pcs->sub[q],
+                                                       h.nsub + pcs->l2[q], h.nsub + h.nl2 + q);
     NS_LAUNCH_CHECK();
-  };
-  ranks(grp, G, rank, total);
-  ranks(grp2, 2, gidx, total2);
-  std::vector<int> tot(G);
-  NS_HIP(hipMemcpyAsync(tot.data(), total.p, G * sizeof(int), hipMemcpyDeviceToHost, st));
+    k_chunk_rank<<<nch, 1024, 0, st>>>(nq, grp + a, Gq, cnt, rank + a);
+    NS_LAUNCH_CHECK();
+    k_chunk_hist<<<nch, 1024, 2 * sizeof(int), st>>>(nq, grp2 + a, 2, cnt);
+    NS_LAUNCH_CHECK();
+    k_chunk_offsets<<<1, 256, 0, st>>>(nch, 2, cnt, totall, 1, 0, -1, -1, h.nsub + h.nl2 + P + q);
+    NS_LAUNCH_CHECK();
+    k_chunk_rank<<<nch, 1024, 0, st>>>(nq, grp2 + a, 2, cnt, gidx + a);
+    NS_LAUNCH_CHECK();
+  }
+  std::vector<int> tot(ntot);
+  NS_HIP(hipMemcpyAsync(tot.data(), totall.p, ntot * sizeof(int), hipMemcpyDeviceToHost, st));
   NS_HIP(hipMemcpyAsync(h.hflags, flags, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
   NS_HIP(hipStreamSynchronize(st));
   if (h.hflags[F_ASYM]) fail(INVALID_ARG, "A is not symmetric (pattern or values)");
 
   std::vector<int> nb1(tot.begin(), tot.begin() + h.nsub), nb2(tot.begin() + h.nsub, tot.begin() + h.nsub + h.nl2);
-  h.nJ = tot[G - 1];
-  h.nI = 0;
+  std::vector<int> nJq(tot.begin() + h.nsub + h.nl2, tot.begin() + h.nsub + h.nl2 + P);
+  h.h_goff.assign(P + 1, 0);
+  for (int q = 0; q < P; ++q) h.h_goff[q + 1] = h.h_goff[q] + tot[h.nsub + h.nl2 + P + q];
+  h.nJ = 0;
+  for (int q = 0; q < P; ++q) h.nJ += nJq[q];
   std::vector<int64_t> coff(h.nsub + 1, 0);
-  for (int b = 0; b < h.nsub; ++b) {
-    coff[b + 1] = coff[b] + nb1[b];
-  }
+  for (int b = 0; b < h.nsub; ++b) coff[b + 1] = coff[b] + nb1[b];
   h.nI = coff[h.nsub];
   h.nG = n - h.nI;
-  if (h.nG <= 0) fail(INVALID_ARG, "partition has no interface nodes");
+  if (h.nG != h.h_goff[P]) fail(INVALID_ARG, "interface count mismatch");
+  for (int q = 0; q < P; ++q) {
+    if (h.h_goff[q + 1] == h.h_goff[q]) fail(INVALID_ARG, "partition has no interface nodes");
+    if (pcs->sub[q + 1] == pcs->sub[q]) fail(INVALID_ARG, "partition has no interior nodes");
+  }
   if (h.nI <= 0) fail(INVALID_ARG, "partition has no interior nodes");
+  h.pnode.alloc(P + 1);
+  NS_HIP(hipMemcpy(h.pnode.p, pcs->node.data(), (P + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  h.l2first.alloc(P + 1);
+  NS_HIP(hipMemcpy(h.l2first.p, pcs->l2.data(), (P + 1) * sizeof(int), hipMemcpyHostToDevice));
+  if (P > 1) {
+    DBuf<int64_t> goff;
+    goff.alloc(P + 1);
+    NS_HIP(hipMemcpy(goff.p, h.h_goff.data(), (P + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    k_gidx_offset<<<gn, 256, 0, st>>>(n, part, h.pnode, P, goff, gidx);
+    NS_LAUNCH_CHECK();
+    NS_HIP(hipStreamSynchronize(st));
+  }
   h.L1.layout(nb1);
   h.L2.layout(nb2);
   h.L2.role = 1;
   h.LJ.role = 1;
-  h.LJ.layout(h.nJ > 0 ? std::vector<int>{int(h.nJ)} : std::vector<int>{});
+  h.LJ.layout(h.nJ > 0 ? nJq : std::vector<int>{});
   DBuf<int64_t> coff1;
   coff1.alloc(h.nsub > 0 ? h.nsub : 1);
   if (h.nsub) NS_HIP(hipMemcpy(coff1.p, coff.data(), h.nsub * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -575,7 +671,7 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
   NS_HIP(hipMemsetAsync(h.icomp.p, 0xFF, h.icomp.n * sizeof(int32_t), st));
   NS_HIP(hipMemsetAsync(h.l2src.p, 0xFF, h.l2src.n * sizeof(int32_t), st));
   NS_HIP(hipMemsetAsync(h.jsrc.p, 0xFF, h.jsrc.n * sizeof(int32_t), st));
-  NodeMaps m{part, rank, gidx, h.L1.roff.p, h.L2.roff.p, coff1.p};
+  NodeMaps m{part, rank, gidx, h.L1.roff.p, h.L2.roff.p, coff1.p, h.pnode.p, P, h.LJ.roff.p, h.l2first.p};
   k_maps<<<gn, 256, 0, st>>>(n, m, h.iperm, h.icomp, h.gperm, h.l2src, h.jsrc);
   NS_LAUNCH_CHECK();
 
@@ -607,14 +703,20 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
   // band storage of the diagonal blocks (the junction block is dense)
   h.L1.layout_band(std::vector<int>(bwh.begin(), bwh.begin() + h.nsub));
   h.L2.layout_band(std::vector<int>(bwh.begin() + h.nsub, bwh.begin() + h.nsub + h.nl2));
-  h.LJ.layout_band(h.nJ > 0 ? std::vector<int>{int(h.nJ) - 1} : std::vector<int>{});
+  {
+    std::vector<int> bwJ;
+    if (h.nJ > 0)
+      for (int q = 0; q < P; ++q) bwJ.push_back(std::max(nJq[q] - 1, 0));
+    h.LJ.layout_band(bwJ);  // dense junction blocks
+  }
   o.nt1 = h.L1.nt;
   o.nt2 = h.L2.nt;
   o.nbt1 = h.L1.nbt;
   o.nbt2 = h.L2.nbt;
   o.foff1 = h.L1.foff;
   o.foff2 = h.L2.foff;
-  o.ntJ = h.LJ.nblk ? h.LJ.h_nt[0] : 0;
+  o.ntJ = h.LJ.nt;
+  o.foffJ = h.LJ.foff;
   finish_csr(h.AIG, st);
   finish_csr(h.AGI, st);
   finish_csr(h.AGG, st);
@@ -664,15 +766,23 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
 void assemble_junction(Handle& h) {
   hipStream_t st = h.stream;
   if (h.nJ == 0 || h.L2.nblk == 0) return;
-  const int64_t nJ = h.nJ, n2pad = h.L2.nrows_pad;
+  const int64_t n2pad = h.L2.nrows_pad;
+  const int ldE = h.LJ.max_nt * TILE;  // junction columns of the level-2 rows' own piece
+  int maxJ = 0;
+  for (int q = 0; q < h.LJ.nblk; ++q) maxJ = std::max(maxJ, h.LJ.h_nb[q]);
   DBuf<double> E;
-  E.alloc(n2pad * nJ);
-  NS_HIP(hipMemsetAsync(E.p, 0, n2pad * nJ * sizeof(double), st));
-  k_csr_to_dense<<<int((n2pad + 255) / 256), 256, 0, st>>>(n2pad, h.AsJ.ptr, h.AsJ.col, h.AsJ.val64, E, nJ);
+  DBuf<int64_t> jbase;
+  E.alloc(n2pad * ldE);
+  jbase.alloc(n2pad);
+  NS_HIP(hipMemsetAsync(E.p, 0, n2pad * ldE * sizeof(double), st));
+  k_l2_jbase<<<dim3((h.L2.max_nt * TILE + 255) / 256, h.L2.nblk), 256, 0, st>>>(
+      h.nl2, h.L2.nt, h.L2.roff, h.l2first, h.nprob, h.LJ.roff, jbase);
   NS_LAUNCH_CHECK();
-  tile_solve<double>(h.L2, E.p, nJ, int(nJ), 64, st);
-  k_junction_update<<<int((nJ * nJ + 255) / 256), 256, 0, st>>>(int(nJ), h.LJ.h_nt[0], h.AJs.ptr, h.AJs.col,
-                                                                 h.AJs.val64, E, h.LJ.L64);
+  k_sj_to_dense<<<int((n2pad + 255) / 256), 256, 0, st>>>(n2pad, h.AsJ.ptr, h.AsJ.col, h.AsJ.val64, jbase, E, ldE);
+  NS_LAUNCH_CHECK();
+  tile_solve<double>(h.L2, E.p, ldE, maxJ, 64, st);  // E = A_s^{-1} A_sJ
+  k_junction_update<<<dim3(unsigned((int64_t(maxJ) * maxJ + 255) / 256), h.LJ.nblk), 256, 0, st>>>(
+      h.LJ.nb, h.LJ.nt, h.LJ.roff, h.LJ.foff, h.AJs.ptr, h.AJs.col, h.AJs.val64, E, ldE, h.LJ.L64);
   NS_LAUNCH_CHECK();
   NS_HIP(hipStreamSynchronize(st));
 }
@@ -689,19 +799,36 @@ void ensure_workspace(Handle& h, int64_t ncols) {
   if (ncols <= h.ws_cols) return;
   const int64_t c = ncols;
   auto grow = [&](auto& buf, int64_t rows) { buf.alloc(rows > 0 ? rows * c : 1); };
-  grow(h.wsT64, h.L1.nrows_pad);
   grow(h.wsB64, h.L2.nrows_pad);
   grow(h.wsJ64, h.LJ.nrows_pad);
   grow(h.wsB64b, h.L2.nrows_pad);
   grow(h.wsJ64b, h.LJ.nrows_pad);
   if (h.prec_inner) {
-    grow(h.wsT32, h.L1.nrows_pad);
     grow(h.wsB32, h.L2.nrows_pad);
     grow(h.wsJ32, h.LJ.nrows_pad);
     grow(h.wsB32b, h.L2.nrows_pad);
     grow(h.wsJ32b, h.LJ.nrows_pad);
   }
   h.ws_cols = c;
+}
+
+// Padded interior right-hand side (rows L1.nrows_pad, ncols columns), made on first use: the local
+// Schur blocks leave it unused in the inner solve.
+template <class T>
+static T* interior_ws(Handle& h, int64_t ncols) {
+  if constexpr (sizeof(T) == 8) {
+    if (ncols > h.wsT64_cols) {
+      h.wsT64.alloc(std::max<int64_t>(h.L1.nrows_pad * ncols, 1));
+      h.wsT64_cols = ncols;
+    }
+    return h.wsT64.p;
+  } else {
+    if (ncols > h.wsT32_cols) {
+      h.wsT32.alloc(std::max<int64_t>(h.L1.nrows_pad * ncols, 1));
+      h.wsT32_cols = ncols;
+    }
+    return h.wsT32.p;
+  }
 }
 
 template <class T>
@@ -725,7 +852,7 @@ void op_schur_tri(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int nco
   hipStream_t st = h.stream;
   need_l1<T>(h);
   ensure_workspace(h, ncols);
-  T* Tb = ws_ptr<T>(h.wsT64, h.wsT32);
+  T* Tb = interior_ws<T>(h, ncols);
   spmm<T>(h.AIG, X, ldx, Tb, ncols, ncols, st);
   tile_solve<T>(h.L1, Tb, ncols, ncols, h.trsm_cols, st);
   if (h.nG == 0) return;
@@ -775,8 +902,7 @@ template <class T>
 void op_interior_solve(Handle& h, const T* X, T* Y, int ncols) {
   hipStream_t st = h.stream;
   need_l1<T>(h);
-  ensure_workspace(h, ncols);
-  T* Tb = ws_ptr<T>(h.wsT64, h.wsT32);
+  T* Tb = interior_ws<T>(h, ncols);
   gather_sub<T>(h.L1.nrows_pad, h.icomp, X, ncols, nullptr, static_cast<const T*>(nullptr), 0, Tb, ncols, ncols, st);
   tile_solve<T>(h.L1, Tb, ncols, ncols, h.trsm_cols, st);
   scatter<T, T>(h.L1.nrows_pad, h.icomp, Tb, ncols, Y, ncols, ncols, st);

@@ -150,9 +150,9 @@ __global__ void k_to_fp32_g(const double* __restrict__ a, float* __restrict__ b,
 
 }  // namespace
 
-bool trsv1_supported(const TileLevel& lv) {
-  return lv.LT64.p != nullptr && size_t(lv.max_nt) * TILE * sizeof(double) <= 96 * 1024;
-}
+bool trsv1_supported_size(const TileLevel& lv) { return size_t(lv.max_nt) * TILE * sizeof(double) <= 96 * 1024; }
+
+bool trsv1_supported(const TileLevel& lv) { return lv.LT64.p != nullptr && trsv1_supported_size(lv); }
 
 void tile_make_transposed(TileLevel& lv, hipStream_t st) {
   if (lv.nblk == 0) return;

@@ -339,7 +339,8 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
                                               const int64_t* __restrict__ roff, const T* __restrict__ L,
                                               const T* __restrict__ Linv, T* __restrict__ B, int64_t ldb,
                                               int ncols, const int* __restrict__ ncols_blk = nullptr,
-                                              const int* __restrict__ first_tile = nullptr, int nchunk_all = 0) {
+                                              const int* __restrict__ first_tile = nullptr, int nchunk_all = 0,
+                                              int64_t row0 = 0) {
   using acc_t = typename MF<T>::acc_t;
   constexpr int NB = CW / 16;
   constexpr int YP = CW + 1;
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
   if (c0 >= ncols) return;
   if (ncols_blk && c0 >= ncols_blk[b]) return;  // this block's columns beyond its count are zero
   const int nt = nt_arr[b], nbt = nbt_arr[b];
-  T* Bb = B + roff[b] * ldb;
+  T* Bb = B + (roff[b] - row0) * ldb;  // B holds the padded rows from row0 on
   const T* Lb = L + foff[b];
   const T* Ib = Linv + ioff[b];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -524,8 +525,10 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
 
 template <class T>
 void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st,
-                    const int* ncols_blk, const int* first_tile, double alg_flops) {
-  if (lv.nblk == 0 || ncols == 0) return;
+                    const int* ncols_blk, const int* first_tile, double alg_flops, int b0, int b1, int64_t row0) {
+  if (b1 < 0) b1 = lv.nblk;
+  const int nblk = b1 - b0;
+  if (nblk <= 0 || ncols == 0) return;
   const T* L;
   const T* Li;
   if constexpr (sizeof(T) == 8) {
@@ -536,27 +539,29 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
     Li = lv.Linv32.p;
   }
   if (cw != 16 && cw != 32) cw = 64;
-  const int nbp8 = (lv.nblk + 7) / 8;
+  const int nbp8 = (nblk + 7) / 8;
   const double bytes = (lv.alg_tri + 2.0 * lv.alg_rows * ncols) * sizeof(T);
   const double flops = alg_flops > 0 ? alg_flops : lv.alg_sq * ncols;
   KScope ks(lv.role == 0 ? (sizeof(T) == 8 ? KF_TRSM_I64 : KF_TRSM_I32) : (sizeof(T) == 8 ? KF_TRSM_G64 : KF_TRSM_G32),
             st, bytes, flops);
   const int nchunk_all = (ncols + cw - 1) / cw;
-  if (cw == 16) {
-    k_trsm<T, 16, true><<<nbp8 * 8 * ((ncols + 15) / 16), 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L,
-                                                                         Li, B, ldb, ncols, ncols_blk, first_tile, nchunk_all);
-  } else if (cw == 32) {
-    k_trsm<T, 32, true><<<nbp8 * 8 * ((ncols + 31) / 32), 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L,
-                                                                         Li, B, ldb, ncols, ncols_blk, first_tile, nchunk_all);
-  } else {
-    k_trsm<T, 64, true><<<nbp8 * 8 * ((ncols + 63) / 64), 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L,
-                                                                         Li, B, ldb, ncols, ncols_blk, first_tile, nchunk_all);
-  }
+  const int* nc = ncols_blk ? ncols_blk + b0 : nullptr;
+  const int* ft = first_tile ? first_tile + int64_t(b0) * nchunk_all : nullptr;
+  const int grid = nbp8 * 8 * nchunk_all;
+  if (cw == 16)
+    k_trsm<T, 16, true><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0, lv.ioff + b0,
+                                              lv.roff + b0, L, Li, B, ldb, ncols, nc, ft, nchunk_all, row0);
+  else if (cw == 32)
+    k_trsm<T, 32, true><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0, lv.ioff + b0,
+                                              lv.roff + b0, L, Li, B, ldb, ncols, nc, ft, nchunk_all, row0);
+  else
+    k_trsm<T, 64, true><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0, lv.ioff + b0,
+                                              lv.roff + b0, L, Li, B, ldb, ncols, nc, ft, nchunk_all, row0);
   NS_LAUNCH_CHECK();
 }
 
 template void tile_solve_fwd<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t, const int*, const int*,
-                                     double);
+                                     double, int, int, int64_t);
 template void tile_solve<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t);
 template void tile_solve<float>(const TileLevel&, float*, int64_t, int, int, hipStream_t);
 

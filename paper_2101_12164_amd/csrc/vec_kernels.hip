@@ -1,26 +1,51 @@
-// Tall-skinny block-vector kernels: Gram products X^T Y with a deterministic
-// two-stage reduction, block updates Out = beta Out + X M (+ X2 M2), column
-// norms, dot products and the fused vector updates of PCG.
+// Tall-skinny block-vector kernels over row segments: Gram products X^T Y
+// with a deterministic two-stage reduction, block updates Out = beta Out +
+// X M (+ X2 M2), column norms, dot products and the fused vector updates of
+// PCG with per-problem scalars and done flags.
 #include "ns_vec.h"
 
 namespace ns {
 namespace {
 
-constexpr int GRAM_CHUNKS = 240;  // fixed partial count: bitwise-reproducible reductions
-constexpr int GRAM_RB = 16;       // rows staged per LDS batch
-constexpr int GRAM_MAXQ = 32;     // outputs per thread (1024 threads): up to 32768 entries
+constexpr int CHUNK_MAX = 240;   // reduction chunks per segment (at most)
+constexpr int CHUNK_ROWS = 128;  // target rows per chunk
+constexpr int GRAM_RB = 16;      // rows staged per LDS batch
+constexpr int GRAM_MAXQ = 32;    // outputs per thread (1024 threads): up to 32768 entries
+
+// index p of the segment whose range [pre[p], pre[p + 1]) holds b
+__device__ __forceinline__ int seg_of(const int* __restrict__ pre, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// rows [r0, r1) of reduction chunk b; returns the segment
+__device__ __forceinline__ int chunk_rows(const Seg& sg, int b, int64_t& r0, int64_t& r1) {
+  const int p = seg_of(sg.coff, sg.n, b);
+  const int c = b - sg.coff[p], nch = sg.coff[p + 1] - sg.coff[p];
+  const int64_t a = sg.off[p], e = sg.off[p + 1];
+  const int64_t per = (e - a + nch - 1) / nch;
+  r0 = a + int64_t(c) * per;
+  r1 = r0 + per < e ? r0 + per : e;
+  return p;
+}
 
 template <class TA, class TB>
-__global__ __launch_bounds__(1024) void k_gram_partial(int64_t n, const TA* __restrict__ A, int64_t lda, int ra,
+__global__ __launch_bounds__(1024) void k_gram_partial(Seg sg, const TA* __restrict__ A, int64_t lda, int ra,
                                                        const TB* __restrict__ B, int64_t ldb, int rb,
                                                        double* __restrict__ part) {
   extern __shared__ double sm[];
-  double* sA = sm;                    // GRAM_RB x ra
-  double* sB = sm + GRAM_RB * ra;     // GRAM_RB x rb
+  double* sA = sm;                 // GRAM_RB x ra
+  double* sB = sm + GRAM_RB * ra;  // GRAM_RB x rb
   const int nout = ra * rb;
-  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = int64_t(blockIdx.x) * per;
-  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  int64_t r0, r1;
+  chunk_rows(sg, blockIdx.x, r0, r1);
   double acc[GRAM_MAXQ];
 #pragma unroll
   for (int q = 0; q < GRAM_MAXQ; ++q) acc[q] = 0.0;
@@ -54,47 +79,59 @@ __global__ __launch_bounds__(1024) void k_gram_partial(int64_t n, const TA* __re
   }
 }
 
-__global__ void k_gram_final(int nchunk, int nout, const double* __restrict__ part, double* __restrict__ G,
-                             double alpha, double beta) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= nout) return;
+// sum of the chunk partials of segment p in a fixed order
+__device__ __forceinline__ double chunk_sum(const Seg& sg, int p, int nout, int o, const double* __restrict__ part) {
+  const int c0 = sg.coff[p], nch = sg.coff[p + 1] - c0;
   double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int c = 0;
-  for (; c + 8 <= nchunk; c += 8)
+  for (; c + 8 <= nch; c += 8)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] += part[int64_t(c + u) * nout + o];
-  for (; c < nchunk; ++c) s[0] += part[int64_t(c) * nout + o];
-  const double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-  G[o] = alpha * t + (beta != 0.0 ? beta * G[o] : 0.0);
+    for (int u = 0; u < 8; ++u) s[u] += part[int64_t(c0 + c + u) * nout + o];
+  for (; c < nch; ++c) s[0] += part[int64_t(c0 + c) * nout + o];
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
-// Out[r, c] = beta * Out[r, c] + sum_m X[r, m] M[m, c] + sum_m X2[r, m] M2[m, c]
+__global__ void k_seg_final(Seg sg, int nout, const double* __restrict__ part, double* __restrict__ G, int64_t gstride,
+                            double alpha, double beta) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (o >= nout) return;
+  const double t = chunk_sum(sg, p, nout, o, part);
+  double* g = G + int64_t(p) * gstride + o;
+  *g = alpha * t + (beta != 0.0 ? beta * *g : 0.0);
+}
+
+// Out[r, c] = beta * Out[r, c] + gamma * (sum_m X[r, m] M_p[m, c] + sum_m X2[r, m] M2_p[m, c]) on 64-row tiles
+// that never straddle two segments.
 template <class T>
-__global__ __launch_bounds__(256) void k_ts_update(int64_t n, int ncols, T* __restrict__ Out, int64_t ldo,
-                                                   double beta, double gamma, const T* __restrict__ X,
-                                                   int64_t ldx, int rm,
-                                                   const double* __restrict__ M, int64_t ldm,
+__global__ __launch_bounds__(256) void k_ts_update(Seg sg, int ncols, T* __restrict__ Out, int64_t ldo, double beta,
+                                                   double gamma, const T* __restrict__ X, int64_t ldx, int rm,
+                                                   const double* __restrict__ M, int64_t ldm, int64_t mstride,
                                                    const T* __restrict__ X2, int64_t ldx2, int rm2,
-                                                   const double* __restrict__ M2, int64_t ldm2) {
+                                                   const double* __restrict__ M2, int64_t ldm2, int64_t m2stride) {
   extern __shared__ double sm[];
   double* sM = sm;             // rm x 32
   double* sM2 = sm + rm * 32;  // rm2 x 32
+  const int p = seg_of(sg.toff, sg.n, blockIdx.x);
+  const int64_t rbase = sg.off[p] + int64_t(blockIdx.x - sg.toff[p]) * 64;
+  const int64_t rend = sg.off[p + 1];
+  const double* Mp = M + int64_t(p) * mstride;
+  const double* M2p = M2 + int64_t(p) * m2stride;
   const int c0 = blockIdx.y * 32;
   for (int e = threadIdx.x; e < rm * 32; e += blockDim.x) {
     const int m = e / 32, c = e % 32;
-    sM[e] = (c0 + c < ncols) ? M[int64_t(m) * ldm + c0 + c] : 0.0;
+    sM[e] = (c0 + c < ncols) ? Mp[int64_t(m) * ldm + c0 + c] : 0.0;
   }
   for (int e = threadIdx.x; e < rm2 * 32; e += blockDim.x) {
     const int m = e / 32, c = e % 32;
-    sM2[e] = (c0 + c < ncols) ? M2[int64_t(m) * ldm2 + c0 + c] : 0.0;
+    sM2[e] = (c0 + c < ncols) ? M2p[int64_t(m) * ldm2 + c0 + c] : 0.0;
   }
   __syncthreads();
   const int c = threadIdx.x & 31;
   if (c0 + c >= ncols) return;
-  const int64_t rbase = int64_t(blockIdx.x) * 64;
   for (int rr = threadIdx.x >> 5; rr < 64; rr += 8) {
     const int64_t r = rbase + rr;
-    if (r >= n) break;
+    if (r >= rend) break;
     double acc = 0.0;
     const T* xr = X + r * ldx;
     for (int m = 0; m < rm; ++m) acc += double(xr[m]) * sM[m * 32 + c];
@@ -117,64 +154,104 @@ __global__ void k_convert(int64_t n, int ncols, const T* __restrict__ X, int64_t
   Y[r * ldy + c] = U(X[r * ldx + c]);
 }
 
-// PCG vector updates; scalars live in device memory: sc[4 it + 0] = rho_it,
-// sc[4 it + 1] = p^T q, sc[4 it + 2] = ||r||^2 after the update.
-__global__ __launch_bounds__(256) void k_pcg_wr(int64_t n, const double* __restrict__ sc, int it,
-                                                double* __restrict__ w, double* __restrict__ r,
+__device__ __forceinline__ double block_sum256(double s, double* red) {
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ __launch_bounds__(256) void k_dot_partial(Seg sg, const double* __restrict__ x,
+                                                     const double* __restrict__ y, double* __restrict__ part) {
+  __shared__ double red[256];
+  int64_t r0, r1;
+  chunk_rows(sg, blockIdx.x, r0, r1);
+  double s = 0.0;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) s += x[i] * y[i];
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// PCG: w += alpha p, r -= alpha q on the chunk's rows unless its problem is done; partial ||r||^2.
+__global__ __launch_bounds__(256) void k_pcg_wr(Seg sg, PcgState S, double* __restrict__ w, double* __restrict__ r,
                                                 const double* __restrict__ p, const double* __restrict__ q,
                                                 double* __restrict__ part) {
   __shared__ double red[256];
-  const double alpha = sc[4 * it] / sc[4 * it + 1];
+  int64_t r0, r1;
+  const int g = chunk_rows(sg, blockIdx.x, r0, r1);
   double s = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-    w[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    s += ri * ri;
+  if (!S.done[g] && *S.j < S.maxit) {
+    const double* ps = S.ps + int64_t(g) * PS;
+    const double alpha = ps[PS_RHO] / ps[PS_PQ];
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
+      w[i] += alpha * p[i];
+      const double ri = r[i] - alpha * q[i];
+      r[i] = ri;
+      s += ri * ri;
+    }
   }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(256) void k_dot_partial(int64_t n, const double* __restrict__ x,
-                                                     const double* __restrict__ y, double* __restrict__ part) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    s += x[i] * y[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+// ||r||^2 per problem from the chunk partials, then the stopping test of iteration j.
+__global__ void k_pcg_check(Seg sg, PcgState S, const double* __restrict__ part) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = *S.j;
+  if (g >= sg.n || S.done[g] || j >= S.maxit) return;
+  const double rn2 = chunk_sum(sg, g, 1, 0, part);
+  double* ps = S.ps + int64_t(g) * PS;
+  ps[PS_RN2] = rn2;
+  const double rel = sqrt(rn2) / ps[PS_NF];
+  S.hist[int64_t(g) * S.hstride + j + 1] = rel;
+  S.it[g] = j + 1;
+  if (!(rel > S.rtol)) {
+    S.done[g] = rel <= S.rtol ? 1 : 2;
+    atomicAdd(S.ndone, 1);
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_sum_final(int np, const double* __restrict__ part, double* __restrict__ out) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < np; i += 256) s += part[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+__global__ void k_pcg_init(int nseg, PcgState S) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) *S.j = 0;
+  if (g >= nseg) return;
+  const double* ps = S.ps + int64_t(g) * PS;
+  const double nf = ps[PS_NF];
+  S.it[g] = 0;
+  S.done[g] = 0;
+  if (nf == 0.0) {
+    S.hist[int64_t(g) * S.hstride] = 0.0;
+    S.done[g] = 1;
+    atomicAdd(S.ndone, 1);
+    return;
   }
-  if (threadIdx.x == 0) *out = red[0];
+  const double rel = sqrt(ps[PS_RN2]) / nf;
+  S.hist[int64_t(g) * S.hstride] = rel;
+  if (!(rel > S.rtol)) {
+    S.done[g] = rel <= S.rtol ? 1 : 2;
+    atomicAdd(S.ndone, 1);
+  }
 }
 
-// p = z + (rho_{it+1} / rho_it) p
-__global__ void k_pcg_p(int64_t n, const double* __restrict__ sc, int it, const double* __restrict__ z,
-                        double* __restrict__ p) {
-  const double beta = sc[4 * (it + 1)] / sc[4 * it];
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    p[i] = z[i] + beta * p[i];
+// p = z + (rho_{j+1} / rho_j) p, per problem
+__global__ void k_pcg_p(Seg sg, PcgState S, const double* __restrict__ z, double* __restrict__ p) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= sg.rows) return;
+  const double* ps = S.ps + int64_t(sg.rseg[i]) * PS;
+  const double beta = ps[PS_RHO_NEW] / ps[PS_RHO];
+  p[i] = z[i] + beta * p[i];
+}
+
+// one workgroup: rho_j <- rho_{j+1} for every problem, then j <- j + 1
+__global__ __launch_bounds__(256) void k_pcg_advance(int nseg, PcgState S) {
+  for (int g = threadIdx.x; g < nseg; g += 256) {
+    double* ps = S.ps + int64_t(g) * PS;
+    ps[PS_RHO] = ps[PS_RHO_NEW];
+  }
+  if (threadIdx.x == 0) *S.j += 1;
 }
 
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
@@ -182,17 +259,18 @@ __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, doubl
     y[i] = a * x[i] + (b != 0.0 ? b * y[i] : 0.0);
 }
 
-// Column sums of squares of a row-major block, in two deterministic stages.
+// Column sums of squares of the chunk's rows: 64 columns x 4 row lanes per pass.
 template <class T>
-__global__ __launch_bounds__(256) void k_colsq_partial(int64_t n, int ncols, const T* __restrict__ X, int64_t ldx,
+__global__ __launch_bounds__(256) void k_colsq_partial(Seg sg, int ncols, const T* __restrict__ X, int64_t ldx,
                                                        double* __restrict__ part) {
-  // thread t: column t % 64 chunk..., rows strided over the grid
   __shared__ double red[256];
+  int64_t r0, r1;
+  chunk_rows(sg, blockIdx.x, r0, r1);
   for (int c0 = 0; c0 < ncols; c0 += 64) {
     const int c = c0 + (threadIdx.x & 63);
     double s = 0.0;
     if (c < ncols)
-      for (int64_t r = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); r < n; r += int64_t(gridDim.x) * 4) {
+      for (int64_t r = r0 + (threadIdx.x >> 6); r < r1; r += 4) {
         const double v = double(X[r * ldx + c]);
         s += v * v;
       }
@@ -200,36 +278,86 @@ __global__ __launch_bounds__(256) void k_colsq_partial(int64_t n, int ncols, con
     __syncthreads();
     if (threadIdx.x < 64 && c < ncols)
       part[int64_t(blockIdx.x) * ncols + c] =
-          red[threadIdx.x] + red[threadIdx.x + 64] + red[threadIdx.x + 128] + red[threadIdx.x + 192];
+          (red[threadIdx.x] + red[threadIdx.x + 64]) + (red[threadIdx.x + 128] + red[threadIdx.x + 192]);
     __syncthreads();
   }
 }
 
+__global__ void k_build_seg(int n, const int64_t* __restrict__ off, const int* __restrict__ toff,
+                            int* __restrict__ rseg) {
+  const int p = blockIdx.y;
+  const int64_t i = off[p] + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < off[p + 1]) rseg[i] = p;
+  (void)n;
+  (void)toff;
+}
+
 }  // namespace
 
+int seg_chunks(int64_t rows) {
+  if (rows <= 0) return 0;
+  const int64_t c = (rows + CHUNK_ROWS - 1) / CHUNK_ROWS;
+  return int(c < CHUNK_MAX ? c : CHUNK_MAX);
+}
+
+void SegBuf::build(const std::vector<int64_t>& offsets, hipStream_t st) {
+  const int n = int(offsets.size()) - 1;
+  h_off = offsets;
+  std::vector<int> co(n + 1, 0), to(n + 1, 0);
+  int64_t maxrows = 0;
+  for (int p = 0; p < n; ++p) {
+    const int64_t rows = offsets[p + 1] - offsets[p];
+    co[p + 1] = co[p] + seg_chunks(rows);
+    to[p + 1] = to[p] + int((rows + 63) / 64);
+    maxrows = std::max(maxrows, rows);
+  }
+  off.alloc(n + 1);
+  coff.alloc(n + 1);
+  toff.alloc(n + 1);
+  const int64_t rows = offsets[n];
+  rseg.alloc(rows > 0 ? rows : 1);
+  NS_HIP(hipMemcpy(off.p, offsets.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(coff.p, co.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+  NS_HIP(hipMemcpy(toff.p, to.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+  if (rows > 0 && n > 0) {
+    dim3 g(unsigned((maxrows + 255) / 256), unsigned(n));
+    k_build_seg<<<g, 256, 0, st>>>(n, off.p, toff.p, rseg.p);
+    NS_LAUNCH_CHECK();
+  }
+  view.n = n;
+  view.rows = rows;
+  view.off = off.p;
+  view.coff = coff.p;
+  view.toff = toff.p;
+  view.rseg = rseg.p;
+  view.nchunk = co[n];
+  view.ntile = to[n];
+}
+
 template <class TA, class TB>
-void gram(int64_t n, const TA* A, int64_t lda, int ra, const TB* B, int64_t ldb, int rb, double* G, double alpha,
-          double beta, double* work, hipStream_t st) {
+void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t ldb, int rb, double* G,
+          int64_t gstride, double alpha, double beta, double* work, hipStream_t st) {
   const int nout = ra * rb;
-  if (nout == 0) return;
+  if (nout == 0 || sg.n == 0) return;
   if (nout > 1024 * GRAM_MAXQ) fail(INVALID_ARG, "Gram product too wide");
   const size_t lds = size_t(GRAM_RB) * (ra + rb) * sizeof(double);
-  k_gram_partial<TA, TB><<<GRAM_CHUNKS, 1024, lds, st>>>(n, A, lda, ra, B, ldb, rb, work);
+  k_gram_partial<TA, TB><<<sg.nchunk, 1024, lds, st>>>(sg, A, lda, ra, B, ldb, rb, work);
   NS_LAUNCH_CHECK();
-  k_gram_final<<<(nout + 255) / 256, 256, 0, st>>>(GRAM_CHUNKS, nout, work, G, alpha, beta);
+  k_seg_final<<<dim3((nout + 255) / 256, sg.n), 256, 0, st>>>(sg, nout, work, G, gstride, alpha, beta);
   NS_LAUNCH_CHECK();
 }
 
-size_t gram_work_elems(int maxw) { return size_t(GRAM_CHUNKS) * maxw * maxw; }
+size_t gram_work_elems(const Seg& sg, int maxw) { return size_t(std::max(sg.nchunk, 1)) * maxw * maxw; }
 
 template <class T>
-void ts_update(int64_t n, int ncols, T* Out, int64_t ldo, double beta, double gamma, const T* X, int64_t ldx, int rm,
-               const double* M, int64_t ldm, const T* X2, int64_t ldx2, int rm2, const double* M2, int64_t ldm2,
-               hipStream_t st) {
-  if (n == 0 || ncols == 0) return;
-  dim3 g(unsigned((n + 63) / 64), unsigned((ncols + 31) / 32));
+void ts_update(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, double gamma, const T* X, int64_t ldx,
+               int rm, const double* M, int64_t ldm, int64_t mstride, const T* X2, int64_t ldx2, int rm2,
+               const double* M2, int64_t ldm2, int64_t m2stride, hipStream_t st) {
+  if (sg.rows == 0 || ncols == 0) return;
+  dim3 g(unsigned(sg.ntile), unsigned((ncols + 31) / 32));
   const size_t lds = size_t(rm + rm2) * 32 * sizeof(double);
-  k_ts_update<T><<<g, 256, lds, st>>>(n, ncols, Out, ldo, beta, gamma, X, ldx, rm, M, ldm, X2, ldx2, rm2, M2, ldm2);
+  k_ts_update<T><<<g, 256, lds, st>>>(sg, ncols, Out, ldo, beta, gamma, X, ldx, rm, M, ldm, mstride, X2, ldx2, rm2,
+                                      M2, ldm2, m2stride);
   NS_LAUNCH_CHECK();
 }
 
@@ -242,56 +370,66 @@ void convert_block(int64_t n, int ncols, const T* X, int64_t ldx, U* Y, int64_t 
 }
 
 template <class T>
-void col_sumsq(int64_t n, int ncols, const T* X, int64_t ldx, double* out, double* work, hipStream_t st) {
-  if (ncols == 0) return;
-  const int nb = 240;
-  k_colsq_partial<T><<<nb, 256, 0, st>>>(n, ncols, X, ldx, work);
+void col_sumsq(const Seg& sg, int ncols, const T* X, int64_t ldx, double* out, double* work, hipStream_t st) {
+  if (ncols == 0 || sg.n == 0) return;
+  k_colsq_partial<T><<<sg.nchunk, 256, 0, st>>>(sg, ncols, X, ldx, work);
   NS_LAUNCH_CHECK();
-  k_gram_final<<<(ncols + 255) / 256, 256, 0, st>>>(nb, ncols, work, out, 1.0, 0.0);
-  NS_LAUNCH_CHECK();
-}
-
-constexpr int VEC_BLOCKS = 480;
-
-void dot(int64_t n, const double* x, const double* y, double* out, double* work, hipStream_t st) {
-  k_dot_partial<<<VEC_BLOCKS, 256, 0, st>>>(n, x, y, work);
-  NS_LAUNCH_CHECK();
-  k_sum_final<<<1, 256, 0, st>>>(VEC_BLOCKS, work, out);
+  k_seg_final<<<dim3((ncols + 255) / 256, sg.n), 256, 0, st>>>(sg, ncols, work, out, ncols, 1.0, 0.0);
   NS_LAUNCH_CHECK();
 }
 
-void pcg_update_wr(int64_t n, const double* sc, int it, double* w, double* r, const double* p, const double* q,
-                   double* rn2_out, double* work, hipStream_t st) {
-  k_pcg_wr<<<VEC_BLOCKS, 256, 0, st>>>(n, sc, it, w, r, p, q, work);
+void dot(const Seg& sg, const double* x, const double* y, double* out, int64_t ostride, double* work,
+         hipStream_t st) {
+  if (sg.n == 0) return;
+  k_dot_partial<<<sg.nchunk, 256, 0, st>>>(sg, x, y, work);
   NS_LAUNCH_CHECK();
-  k_sum_final<<<1, 256, 0, st>>>(VEC_BLOCKS, work, rn2_out);
+  k_seg_final<<<dim3(1, sg.n), 256, 0, st>>>(sg, 1, work, out, ostride, 1.0, 0.0);
   NS_LAUNCH_CHECK();
 }
 
-void pcg_update_p(int64_t n, const double* sc, int it, const double* z, double* p, hipStream_t st) {
-  k_pcg_p<<<VEC_BLOCKS, 256, 0, st>>>(n, sc, it, z, p);
+void pcg_update_wr(const Seg& sg, const PcgState& s, double* w, double* r, const double* p, const double* q,
+                   double* work, hipStream_t st) {
+  k_pcg_wr<<<sg.nchunk, 256, 0, st>>>(sg, s, w, r, p, q, work);
+  NS_LAUNCH_CHECK();
+  k_pcg_check<<<(sg.n + 255) / 256, 256, 0, st>>>(sg, s, work);
+  NS_LAUNCH_CHECK();
+}
+
+void pcg_update_p(const Seg& sg, const PcgState& s, const double* z, double* p, hipStream_t st) {
+  k_pcg_p<<<unsigned((sg.rows + 255) / 256), 256, 0, st>>>(sg, s, z, p);
+  NS_LAUNCH_CHECK();
+}
+
+void pcg_advance(int nseg, const PcgState& s, hipStream_t st) {
+  k_pcg_advance<<<1, 256, 0, st>>>(nseg, s);
+  NS_LAUNCH_CHECK();
+}
+
+void pcg_init_check(int nseg, const PcgState& s, hipStream_t st) {
+  k_pcg_init<<<(nseg + 255) / 256, 256, 0, st>>>(nseg, s);
   NS_LAUNCH_CHECK();
 }
 
 void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t st) {
-  k_axpby<<<VEC_BLOCKS, 256, 0, st>>>(n, a, x, b, y);
+  if (n == 0) return;
+  k_axpby<<<unsigned(std::min<int64_t>((n + 255) / 256, 2048)), 256, 0, st>>>(n, a, x, b, y);
   NS_LAUNCH_CHECK();
 }
 
-template void gram<double, double>(int64_t, const double*, int64_t, int, const double*, int64_t, int, double*, double,
-                                   double, double*, hipStream_t);
-template void gram<float, float>(int64_t, const float*, int64_t, int, const float*, int64_t, int, double*, double,
-                                 double, double*, hipStream_t);
-template void ts_update<double>(int64_t, int, double*, int64_t, double, double, const double*, int64_t, int,
-                                const double*, int64_t, const double*, int64_t, int, const double*, int64_t,
-                                hipStream_t);
-template void ts_update<float>(int64_t, int, float*, int64_t, double, double, const float*, int64_t, int,
-                               const double*, int64_t, const float*, int64_t, int, const double*, int64_t,
-                               hipStream_t);
+template void gram<double, double>(const Seg&, const double*, int64_t, int, const double*, int64_t, int, double*,
+                                   int64_t, double, double, double*, hipStream_t);
+template void gram<float, float>(const Seg&, const float*, int64_t, int, const float*, int64_t, int, double*,
+                                 int64_t, double, double, double*, hipStream_t);
+template void ts_update<double>(const Seg&, int, double*, int64_t, double, double, const double*, int64_t, int,
+                                const double*, int64_t, int64_t, const double*, int64_t, int, const double*, int64_t,
+                                int64_t, hipStream_t);
+template void ts_update<float>(const Seg&, int, float*, int64_t, double, double, const float*, int64_t, int,
+                               const double*, int64_t, int64_t, const float*, int64_t, int, const double*, int64_t,
+                               int64_t, hipStream_t);
 template void convert_block<double, float>(int64_t, int, const double*, int64_t, float*, int64_t, hipStream_t);
 template void convert_block<float, double>(int64_t, int, const float*, int64_t, double*, int64_t, hipStream_t);
 template void convert_block<double, double>(int64_t, int, const double*, int64_t, double*, int64_t, hipStream_t);
-template void col_sumsq<double>(int64_t, int, const double*, int64_t, double*, double*, hipStream_t);
-template void col_sumsq<float>(int64_t, int, const float*, int64_t, double*, double*, hipStream_t);
+template void col_sumsq<double>(const Seg&, int, const double*, int64_t, double*, double*, hipStream_t);
+template void col_sumsq<float>(const Seg&, int, const float*, int64_t, double*, double*, hipStream_t);
 
 }  // namespace ns

@@ -36,6 +36,8 @@ EXPORTED = [
     "nystrom_schur_setup",
     "nystrom_schur_apply",
     "nystrom_schur_pcg_solve",
+    "nystrom_schur_setup_batched",
+    "nystrom_schur_pcg_solve_batched",
     "nystrom_schur_schur_apply",
     "nystrom_schur_interface_solve",
     "nystrom_schur_interior_solve",
@@ -69,6 +71,7 @@ class NsOptions(ctypes.Structure):
         ("proposal", c_void_p),
         ("accept_tol", c_double),
         ("stream", c_void_p),
+        ("pcg_graph_iters", c_int32),
     ]
 
 
@@ -130,6 +133,14 @@ def load_library() -> ctypes.CDLL:
     lib.nystrom_schur_setup.argtypes = [c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(NsOptions),
                                         POINTER(H), POINTER(NsSetupInfo)]
     lib.nystrom_schur_setup.restype = c_int32
+    lib.nystrom_schur_setup_batched.argtypes = [c_int32, POINTER(c_int64), POINTER(c_int64), POINTER(c_void_p),
+                                                POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                                POINTER(c_void_p), POINTER(NsOptions), POINTER(c_void_p),
+                                                POINTER(NsSetupInfo)]
+    lib.nystrom_schur_setup_batched.restype = c_int32
+    lib.nystrom_schur_pcg_solve_batched.argtypes = [H, POINTER(c_void_p), POINTER(c_void_p), c_double, c_int32,
+                                                    POINTER(NsSolveInfo)]
+    lib.nystrom_schur_pcg_solve_batched.restype = c_int32
     lib.nystrom_schur_apply.argtypes = [H, c_void_p, c_void_p, c_int32]
     lib.nystrom_schur_apply.restype = c_int32
     lib.nystrom_schur_pcg_solve.argtypes = [H, c_void_p, c_void_p, c_double, c_int32, POINTER(NsSolveInfo)]
@@ -183,7 +194,7 @@ def _setup_info_dict(si: NsSetupInfo) -> dict:
 
 def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_inner=0.1, eig_thresh_rel=1e-10,
                         orth_drop_rel=0.0, max_inner_iters=500, prec_inner=NS_FP64, apply_mode=NS_APPLY_M2,
-                        trsm_cols=0, schur_mode=0, proposal=None, accept_tol=0.2):
+                        trsm_cols=0, schur_mode=0, proposal=None, accept_tol=0.2, pcg_graph_iters=0):
     """Returns (handle, info dict).  row_ptr int64, col_idx int32, val float64, part int32, omega float64
     (n_gamma x (k+p), row-major), all CUDA tensors."""
     lib = load_library()
@@ -203,6 +214,7 @@ def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_in
     opt.proposal = _dev(proposal, torch.float64, "proposal") if proposal is not None else None
     opt.accept_tol = accept_tol
     opt.stream = _stream()
+    opt.pcg_graph_iters = pcg_graph_iters
     h = c_void_p()
     info = NsSetupInfo()
     st = lib.nystrom_schur_setup(n, nnz, _dev(row_ptr, torch.int64, "row_ptr"), _dev(col_idx, torch.int32, "col_idx"),
@@ -210,6 +222,77 @@ def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_in
                                  ctypes.byref(h), ctypes.byref(info))
     _check(st, None, _setup_info_dict(info))
     return h, _setup_info_dict(info)
+
+
+def _options(k, p, tol_inner, eig_thresh_rel, orth_drop_rel, max_inner_iters, prec_inner, apply_mode, trsm_cols,
+             schur_mode, accept_tol, pcg_graph_iters=0):
+    opt = NsOptions()
+    opt.k, opt.p = int(k), int(p)
+    opt.tol_inner = tol_inner
+    opt.eig_thresh_rel = eig_thresh_rel
+    opt.orth_drop_rel = orth_drop_rel
+    opt.max_inner_iters = max_inner_iters
+    opt.prec_inner = prec_inner
+    opt.apply_mode = apply_mode
+    opt.trsm_cols = trsm_cols
+    opt.schur_mode = schur_mode
+    opt.accept_tol = accept_tol
+    opt.stream = _stream()
+    opt.pcg_graph_iters = pcg_graph_iters
+    return opt
+
+
+def nystrom_schur_setup_batched(problems, *, k, p, omegas=None, tol_inner=0.1, eig_thresh_rel=1e-10,
+                                orth_drop_rel=0.0, max_inner_iters=500, prec_inner=NS_FP64, apply_mode=NS_APPLY_M2,
+                                trsm_cols=0, schur_mode=0, pcg_graph_iters=0):
+    """problems: list of (row_ptr, col_idx, val, part) CUDA tensors; omegas: list of n_gamma(q) x (k+p) float64
+    CUDA tensors.  Returns (handle, list of info dicts)."""
+    lib = load_library()
+    m = len(problems)
+    opt = _options(k, p, tol_inner, eig_thresh_rel, orth_drop_rel, max_inner_iters, prec_inner, apply_mode,
+                   trsm_cols, schur_mode, 0.2, pcg_graph_iters)
+    n = (c_int64 * m)(*[pr[0].numel() - 1 for pr in problems])
+    nnz = (c_int64 * m)(*[pr[2].numel() for pr in problems])
+    ptrs = [(c_void_p * m)(*[_dev(pr[i], dt, nm) for pr in problems])
+            for i, (dt, nm) in enumerate([(torch.int64, "row_ptr"), (torch.int32, "col_idx"),
+                                          (torch.float64, "val"), (torch.int32, "part")])]
+    om = (c_void_p * m)(*[_dev(o, torch.float64, "omega") for o in omegas]) if omegas is not None else None
+    h = c_void_p()
+    infos = (NsSetupInfo * m)()
+    st = lib.nystrom_schur_setup_batched(m, n, nnz, ptrs[0], ptrs[1], ptrs[2], ptrs[3], om, ctypes.byref(opt),
+                                         ctypes.byref(h), infos)
+    out = [_setup_info_dict(infos[q]) for q in range(m)]
+    _check(st, None, out)
+    return h, out
+
+
+def nystrom_schur_pcg_solve_batched(handle, bs, xs=None, rtol=1e-8, maxit=1000, hist_cap=0,
+                                    raise_on_not_converged=True):
+    """bs: list of float64 CUDA tensors (each problem's right-hand side, its own node order)."""
+    lib = load_library()
+    m = len(bs)
+    if xs is None:
+        xs = [torch.empty_like(b) for b in bs]
+    infos = (NsSolveInfo * m)()
+    hists = [(c_double * max(hist_cap, 1))() for _ in range(m)]
+    for q in range(m):
+        infos[q].res_hist = ctypes.cast(hists[q], POINTER(c_double))
+        infos[q].res_hist_cap = hist_cap
+    bp = (c_void_p * m)(*[_dev(b, torch.float64, "b") for b in bs])
+    xp = (c_void_p * m)(*[_dev(x, torch.float64, "x") for x in xs])
+    st = lib.nystrom_schur_pcg_solve_batched(handle, bp, xp, rtol, maxit, infos)
+    out = []
+    for q in range(m):
+        i = infos[q]
+        d = dict(it_pcg=i.it_pcg, converged=i.converged, relres_schur=i.relres_schur, relres_true=i.relres_true,
+                 t_solve=i.t_solve, status=st)
+        if hist_cap:
+            d["res_hist"] = [hists[q][j] for j in range(min(hist_cap, i.it_pcg + 1))]
+        out.append(d)
+    if st == NS_ERR_NOT_CONVERGED and not raise_on_not_converged:
+        return xs, out
+    _check(st, handle, out)
+    return xs, out
 
 
 def nystrom_schur_apply(handle, r: torch.Tensor, z: torch.Tensor = None):
@@ -266,7 +349,7 @@ def nystrom_schur_get_sizes(handle) -> dict:
     lib = load_library()
     out = (c_int64 * 8)()
     _check(lib.nystrom_schur_get_sizes(handle, out), handle)
-    keys = ["n", "n_interior", "n_gamma", "n_sub", "n_junction", "n_level2_blocks", "k_eff", "nb0"]
+    keys = ["n", "n_interior", "n_gamma", "n_sub", "n_junction", "n_level2_blocks", "k_eff", "nprob"]
     return dict(zip(keys, list(out)))
 
 

@@ -71,3 +71,10 @@ def test_setup_rejects_bad_arguments_without_touching_the_gpu():
     st = lib.nystrom_schur_setup(ctypes.c_int64(4), ctypes.c_int64(4), ctypes.c_void_p(8), ctypes.c_void_p(8),
                                  ctypes.c_void_p(8), ctypes.c_void_p(8), ctypes.byref(opt), ctypes.byref(h), None)
     assert st == 1
+
+
+def test_package_exposes_every_entry_point():
+    import paper_2101_12164_amd as ns
+
+    for name in ns.EXPORTED:
+        assert callable(getattr(ns, name, None)), name

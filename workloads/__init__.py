@@ -10,6 +10,7 @@ from .grids import (  # noqa: F401
     GridProblem,
     box_ids_1d,
     diffusion_fd,
+    aniso_problem,
     anisotropic_q1,
     lognormal_field,
     partition_boxes,

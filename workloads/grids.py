@@ -383,17 +383,23 @@ def config_c2(level2: bool = True, N: int = 64, nb: int = 4) -> GridProblem:
                         name=f"c2_lognormal3d_{N}")
 
 
-def config_c3_problem(i: int, level2: bool = True) -> GridProblem:
+def aniso_problem(L: int, theta: float, *, eps: float = 1e-3, nboxes=(4, 4), k: int = 32, p: int = 8,
+                  seed: int = 0, level2: bool = True, name: Optional[str] = None) -> GridProblem:
+    """2D anisotropic Q1 problem on an L x L grid split into box subdomains."""
+    A = anisotropic_q1(L, eps, theta)
+    part = partition_boxes((L, L), nboxes)
+    if level2:
+        part = level2_labels(A, part)
+    return _to_problem(name or f"aniso_q1_L{L}", (L, L), A, part, k, p, 0.1, 1e-8, seed)
+
+
+def config_c3_problem(i: int, level2: bool = True, L_range=(128, 512)) -> GridProblem:
     """Problem i of the batched set: 2D anisotropic Q1, L ~ U{128..512}, eps=1e-3,
     random rotation, 4x4 boxes, k=32, p=8; everything drawn from default_rng(7000+i)."""
     rng = np.random.default_rng(7000 + i)
-    L = int(rng.integers(128, 513))
+    L = int(rng.integers(L_range[0], L_range[1] + 1))
     theta = float(rng.uniform(0.0, math.pi))
-    A = anisotropic_q1(L, 1e-3, theta)
-    part = partition_boxes((L, L), (4, 4))
-    if level2:
-        part = level2_labels(A, part)
-    return _to_problem(f"c3_aniso_q1_{i}_L{L}", (L, L), A, part, 32, 8, 0.1, 1e-8, i)
+    return aniso_problem(L, theta, k=32, p=8, seed=i, level2=level2, name=f"c3_aniso_q1_{i}_L{L}")
 
 
 def config_c4(seed: int = 0, level2: bool = True, N: int = 48) -> GridProblem:
