@@ -25,3 +25,4 @@ from .nystrom_schur_oracle import (  # noqa: F401
     ideal_s2,
     full_system_pcg,
 )
+from . import learned  # noqa: F401

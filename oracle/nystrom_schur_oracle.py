@@ -337,6 +337,8 @@ class SetupResult:
     Sigma: np.ndarray
     Z: np.ndarray
     Y: np.ndarray
+    proposal_accepted: bool = False
+    ritz_rho: Optional[np.ndarray] = None
 
 
 @dataclasses.dataclass
@@ -363,7 +365,8 @@ class NystromSchurOracle:
     """
 
     def __init__(self, n, row_ptr, col, val, part, *, k, p, omega, tol_inner=0.1, eps_rel=1e-10, delta=1e-6,
-                 maxit_inner=500, factor="dense", apply_mode="M2", inner="shifted", gamma_factor=None):
+                 maxit_inner=500, factor="dense", apply_mode="M2", inner="shifted", gamma_factor=None,
+                 proposal=None, accept_tol=0.2):
         self.dbbd = DBBD(n, row_ptr, col, val, part)
         self.ops = Operators(self.dbbd, factor=factor, gamma_factor=gamma_factor)
         self.k, self.p = int(k), int(p)
@@ -374,6 +377,8 @@ class NystromSchurOracle:
         self.maxit_inner = maxit_inner
         self.apply_mode = apply_mode
         self.inner = inner
+        self.proposal = np.asarray(proposal, dtype=np.float64) if proposal is not None else None
+        self.accept_tol = accept_tol
         self.setup_result: Optional[SetupResult] = None
 
     # -- Algorithm alg:prec1 ------------------------------------------------
@@ -386,6 +391,24 @@ class NystromSchurOracle:
             self.setup_result = SetupResult(0, True, 0, 0, np.zeros((ng, 0)), self.Sigma, self.Z, np.zeros((ng, 0)))
             self._post_setup()
             return self.setup_result
+        rho = None
+        if self.proposal is not None:
+            # learned starting subspace: Z = A_Gamma^{-1} Z0, judged by Rayleigh-Ritz on (S_Gamma, A_Gamma);
+            # accepted -> adapted deflation with the Ritz vectors (eqs. adapted_deflation_prec,
+            # deflation_comp_from_low_rank), rejected -> plain Nystrom below
+            from .learned import accept, rayleigh_ritz
+
+            Zp = ops.solve_G(self.proposal)
+            lam, Yr, rho = rayleigh_ritz(ops.S, lambda X: d.A_G @ X, Zp)
+            if accept(rho, self.k, self.accept_tol):
+                self.apply_mode = "ADEF2"
+                self.Z = Yr
+                self.Sigma = np.zeros(Yr.shape[1])
+                ng = d.n_gamma
+                self.setup_result = SetupResult(0, True, Yr.shape[1], 0, np.zeros((ng, 0)), self.Sigma, self.Z,
+                                                np.zeros((ng, 0)), True, rho)
+                self._post_setup()
+                return self.setup_result
         Om = self.omega
         if self.inner == "shifted":
             F = ops.W(Om)
@@ -400,7 +423,7 @@ class NystromSchurOracle:
         U, Sig, r = nystrom_core(Y, Om, self.k, self.eps_rel)
         self.Z = ops.solve_G(U)
         self.Sigma = Sig
-        self.setup_result = SetupResult(res.iters, res.converged, U.shape[1], r, U, Sig, self.Z, Y)
+        self.setup_result = SetupResult(res.iters, res.converged, U.shape[1], r, U, Sig, self.Z, Y, False, rho)
         self._post_setup()
         return self.setup_result
 
