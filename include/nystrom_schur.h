@@ -239,6 +239,54 @@ ns_status nystrom_schur_get_sizes(ns_handle h, int64_t* out);
  * NS_ERR_INVALID_ARG for a batched handle. */
 ns_status nystrom_schur_get_lowrank(ns_handle h, double* Z, double* Sigma);
 
+/* Copy the Nystrom basis U (the orthonormal n_gamma x k_eff factor of Algorithm
+ * alg:nystrom before Z = A_Gamma^{-1} U; DEVICE, row-major, interface order) and
+ * the eigen-residual of the judged proposal (HOST, may be NULL; 0 when no
+ * proposal was given).  NS_ERR_INVALID_ARG for a batched handle, or for U when
+ * an accepted proposal replaced the Nystrom step. */
+ns_status nystrom_schur_get_basis(ns_handle h, double* U, double* rho);
+
+/* ---------------------------------------------------------------------------
+ * Learned starting subspace.  The adapted deflation (eqs.
+ * adapted_deflation_prec, deflation_comp_from_low_rank) works with any
+ * full-rank basis; a small network over interface nodes proposes one
+ * (ns_options.proposal), setup judges it by Rayleigh-Ritz on the pencil
+ * (S_Gamma, A_Gamma) and uses it, or falls back to plain Nystrom.
+ * ------------------------------------------------------------------------- */
+
+/* Interface-node features, 16 per node, rows in interface order (ascending node
+ * index among part < 0): coordinates (coords: DEVICE n x 3 or NULL -> 0), log A_ii,
+ * mean/min/max log|A_ij| off the diagonal, log of the summed |A_ij| to interior
+ * and to interface neighbours, junction flag, distinct neighbouring subdomains/4,
+ * log A_ii averaged over the interface graph 1, 2 and 4 times, interface
+ * degree/8, 1.  X: DEVICE float, at least n_gamma x 16; *n_gamma (HOST) receives
+ * the row count.  CSR as in nystrom_schur_setup (not validated here).
+ * Synchronises `stream`. */
+ns_status nystrom_schur_features(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                                 const double* val, const int32_t* part, const double* coords, float* X,
+                                 int64_t* n_gamma, void* stream);
+
+/* The network: d_in -> hidden -> hidden -> d_out, ReLU hidden layers, linear
+ * output; BF16 operands on MFMA with FP32 accumulation; FP32 master weights.
+ * params: HOST float array, in order W1 (d_in x hidden, row-major in x out), b1,
+ * W2 (hidden x hidden), b2, W3 (hidden x d_out), b3; the library copies it. */
+typedef struct ns_mlp_s* ns_mlp;
+ns_status nystrom_schur_mlp_create(int32_t d_in, int32_t hidden, int32_t d_out, const float* params, ns_mlp* out);
+/* HOST copies of the parameters and of the last gradient (either may be NULL). */
+ns_status nystrom_schur_mlp_get_params(ns_mlp m, float* params, float* grad);
+/* Z0 (DEVICE double, n x d_out) = network(X) for X (DEVICE float, n x d_in). */
+ns_status nystrom_schur_mlp_forward(ns_mlp m, const float* X, int64_t n, double* Z0, void* stream);
+/* Forward, the subspace loss L = 1 - tr(G^{-1} Z0^T U U^T Z0) / k (G = Z0^T Z0,
+ * U: DEVICE n x d_out with orthonormal columns) into *loss (HOST), and its
+ * gradient with respect to the parameters (kept in the network for the next
+ * adam_step).  NS_ERR_BREAKDOWN when Z0 is rank deficient. */
+ns_status nystrom_schur_mlp_loss_grad(ns_mlp m, const float* X, const double* U, int64_t n, double* loss,
+                                      void* stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) with the last gradient. */
+ns_status nystrom_schur_mlp_adam_step(ns_mlp m, double lr, void* stream);
+void nystrom_schur_mlp_destroy(ns_mlp m);
+const char* nystrom_schur_mlp_last_error(ns_mlp m);
+
 /* Opt-in kernel timing for performance measurement (callers: benchmarks).
  * enable != 0 brackets every launch of the main kernel families with HIP
  * events on the launching stream (adds a few microseconds per launch);

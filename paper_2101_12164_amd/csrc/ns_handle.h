@@ -77,6 +77,13 @@ struct ns_handle_s {
   ns::DBuf<double> Z, Sigma;
   // adapted deflation: SZ = S Z, chol(E) (k x k lower, ld = k, per problem)
   ns::DBuf<double> SZ, Echol;
+  // Nystrom basis U (n_G x k, before the A_Gamma^{-1} of Z = A_Gamma^{-1} U), kept for export
+  ns::DBuf<double> U;
+  // learned starting subspace: caller's n_G x k proposal, eigen-residual threshold, outcome
+  const double* proposal = nullptr;
+  double accept_tol = 0.2;
+  int proposal_accepted = 0;
+  double proposal_rho = 0.0;  // largest eigen-residual over the ceil(k/2) smallest Ritz values
 
   // error flags written by kernels (pinned host-visible copy in hflags)
   ns::DBuf<int> dflags;

@@ -278,7 +278,7 @@ void nystrom(Handle& h, SmallMats& sm, const double* Omega, double* Y) {
   const Seg& sg = h.segG.view;
   const int s = h.s, k = h.k, np = h.nprob;
   const int64_t nG = h.nG, ss = int64_t(s) * s;
-  DBuf<double> Qb, U, work;
+  DBuf<double> Qb, work;
   Qb.alloc(nG * s);
   work.alloc(gram_work_elems(sg, s));
   gram<double, double>(sg, Omega, s, s, Y, s, s, sm.C, ss, 1.0, 0.0, work, st);  // C = Omega^T Y
@@ -316,11 +316,72 @@ void nystrom(Handle& h, SmallMats& sm, const double* Omega, double* Y) {
   NS_HIP(hipMemsetAsync(h.Z.p, 0, h.Z.n * sizeof(double), st));
   NS_HIP(hipMemcpyAsync(h.Sigma.p, sm.Ek, size_t(k) * np * sizeof(double), hipMemcpyDeviceToDevice, st));
   if (h.k_eff > 0) {
-    U.alloc(nG * k);
-    ts_update<double>(sg, k, U.p, k, 0.0, 1.0, A, s, s, sm.Wk, k, int64_t(s) * k, nullptr, 0, 0, nullptr, 0, 0, st);
-    op_gamma_solve<double>(h, U.p, k, h.Z.p, k, k);
+    h.U.alloc(nG * k);
+    ts_update<double>(sg, k, h.U.p, k, 0.0, 1.0, A, s, s, sm.Wk, k, int64_t(s) * k, nullptr, 0, 0, nullptr, 0, 0, st);
+    op_gamma_solve<double>(h, h.U.p, k, h.Z.p, k, k);
   }
   NS_HIP(hipStreamSynchronize(st));
+}
+
+// Judge a proposed starting subspace Z0 (n_G x k, one problem): Z = A_Gamma^{-1} Z0, Rayleigh-Ritz on the
+// pencil (S_Gamma, A_Gamma) over span(Z) (Ritz values ascending, Ritz vectors Y = Z C with Y^T A_Gamma Y = I),
+// eigen-residuals rho_i = ||S y_i - lambda_i A_Gamma y_i|| / ||A_Gamma y_i||; accepted when the ceil(k/2) smallest
+// Ritz values have rho_i <= accept_tol.  Accepted: Z <- Y (the deflation space of the adapted deflation).
+bool judge_proposal(Handle& h) {
+  hipStream_t st = h.stream;
+  const Seg& sg = h.segG.view;
+  const int k = h.k;
+  const int64_t nG = h.nG, kk = int64_t(k) * k;
+  DBuf<double> Zp, SZ, AZ, Y, R, work, sm, colsq;
+  for (DBuf<double>* b : {&Zp, &SZ, &AZ, &Y, &R}) b->alloc(nG * k);
+  work.alloc(gram_work_elems(sg, k));
+  sm.alloc(10 * kk + 4 * size_t(k) + 16);
+  colsq.alloc(2 * size_t(k));
+  double* Ar = sm.p;
+  double* Br = Ar + kk;
+  double* C = Br + kk;
+  double* Cl = C + kk;
+  double* lam = Cl + kk;
+  double* ws = lam + k;
+  DBuf<int> flag;
+  flag.alloc(1);
+  NS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
+  op_gamma_solve<double>(h, h.proposal, k, Zp.p, k, k);                // Z = A_Gamma^{-1} Z0
+  op_schur<double>(h, Zp.p, k, SZ.p, k, k, false);                      // S Z
+  csr_mult<double>(h.AGG, Zp.p, k, AZ.p, k, k, st);                     // A_Gamma Z
+  gram<double, double>(sg, Zp.p, k, k, SZ.p, k, k, Ar, kk, 1.0, 0.0, work, st);
+  gram<double, double>(sg, Zp.p, k, k, AZ.p, k, k, Br, kk, 1.0, 0.0, work, st);
+  small_gevd(k, Ar, Br, lam, C, Cl, flag, ws, h.small.p, st);
+  ts_update<double>(sg, k, Y.p, k, 0.0, 1.0, Zp.p, k, k, C, k, 0, nullptr, 0, 0, nullptr, 0, 0, st);   // Y = Z C
+  ts_update<double>(sg, k, R.p, k, 0.0, 1.0, SZ.p, k, k, C, k, 0, AZ.p, k, k, Cl, k, 0, st);           // S Y - A Y L
+  col_sumsq<double>(sg, k, R.p, k, colsq.p, work, st);
+  ts_update<double>(sg, k, SZ.p, k, 0.0, 1.0, AZ.p, k, k, C, k, 0, nullptr, 0, 0, nullptr, 0, 0, st);  // A Y
+  col_sumsq<double>(sg, k, SZ.p, k, colsq.p + k, work, st);
+  std::vector<double> cs(2 * k);
+  int fl = 0;
+  NS_HIP(hipMemcpyAsync(&fl, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  read_back(h, cs.data(), colsq.p, 2 * k);
+  if (fl) {  // Z^T A_Gamma Z singular: the proposal is rank deficient
+    h.proposal_rho = INFINITY;
+    return false;
+  }
+  double rmax = 0.0;
+  for (int i = 0; i < (k + 1) / 2; ++i) {
+    const double rho = cs[k + i] > 0.0 ? std::sqrt(cs[i] / cs[k + i]) : INFINITY;
+    rmax = (rho > rmax || !(rho == rho)) ? rho : rmax;
+  }
+  h.proposal_rho = rmax;
+  if (!(rmax <= h.accept_tol)) return false;
+  h.Z.alloc(nG * k);
+  NS_HIP(hipMemcpyAsync(h.Z.p, Y.p, nG * k * sizeof(double), hipMemcpyDeviceToDevice, st));
+  h.Sigma.alloc(k);
+  NS_HIP(hipMemsetAsync(h.Sigma.p, 0, k * sizeof(double), st));
+  h.k_eff = k;
+  h.h_keff.assign(1, k);
+  h.keff_d.alloc(1);
+  NS_HIP(hipMemcpy(h.keff_d.p, h.h_keff.data(), sizeof(int), hipMemcpyHostToDevice));
+  NS_HIP(hipStreamSynchronize(st));
+  return true;
 }
 
 // Adapted deflation: SZ = S Z, E = Z^T S Z and chol(E), per problem.
@@ -569,6 +630,8 @@ Handle* new_handle(const ns_options* opt) {
   h->trsm_cols = opt->trsm_cols;
   h->schur_mode = opt->schur_mode;
   h->pcg_graph = opt->pcg_graph_iters;
+  h->proposal = opt->proposal;
+  h->accept_tol = opt->accept_tol > 0 ? opt->accept_tol : 0.2;
   return h;
 }
 
@@ -618,7 +681,20 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
   h->conv_inner.assign(np, 1);
   h->relres_inner.assign(np, 0.0);
   h->h_keff.assign(np, 0);
-  if (h->k > 0) {
+  h->proposal_accepted = 0;
+  if (h->k > 0 && h->proposal) {
+    if (np != 1) fail(INVALID_ARG, "a proposal applies to one problem (not a batch)");
+    if (judge_proposal(*h)) {
+      h->proposal_accepted = 1;
+      h->apply_mode = NS_APPLY_ADEF2;
+      h->conv_inner.assign(1, 1);
+      ev.rec(3);
+      setup_adef2(*h);
+    }
+  }
+  if (h->proposal_accepted) {
+    // the accepted subspace replaces the inner solve and the Nystrom core
+  } else if (h->k > 0) {
     SmallMats sm;
     sm.init(np, h->s, h->k);
     DBuf<double> Om, D;
@@ -659,6 +735,7 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
       o.n_sub = pieces ? pieces->sub[q + 1] - pieces->sub[q] : h->nsub;
       o.n_level2_blocks = pieces ? pieces->l2[q + 1] - pieces->l2[q] : h->nl2;
       o.k_eff = h->h_keff[q];
+      o.proposal_accepted = h->proposal_accepted;
       o.it_inner = h->it_inner[q];
       o.inner_converged = h->conv_inner[q];
       o.inner_relres = h->relres_inner[q];
@@ -1032,6 +1109,23 @@ ns_status nystrom_schur_get_lowrank(ns_handle h, double* Z, double* Sigma) {
                                 h->k_eff * sizeof(double), h->nG, hipMemcpyDeviceToDevice, h->stream));
       if (Sigma)
         NS_HIP(hipMemcpyAsync(Sigma, h->Sigma.p, h->k_eff * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+      NS_HIP(hipStreamSynchronize(h->stream));
+    }
+    return NS_OK;
+  } catch (const Error& e) {
+    return finish(h, e);
+  }
+}
+
+ns_status nystrom_schur_get_basis(ns_handle h, double* U, double* rho) {
+  if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
+  try {
+    if (h->nprob != 1) fail(INVALID_ARG, "batched handle: bases are per problem");
+    if (rho) *rho = h->proposal_rho;
+    if (U && h->k_eff > 0) {
+      if (h->proposal_accepted || !h->U.p) fail(INVALID_ARG, "no Nystrom basis (the proposal was accepted)");
+      NS_HIP(hipMemcpy2DAsync(U, h->k_eff * sizeof(double), h->U.p, h->k * sizeof(double), h->k_eff * sizeof(double),
+                              h->nG, hipMemcpyDeviceToDevice, h->stream));
       NS_HIP(hipStreamSynchronize(h->stream));
     }
     return NS_OK;

@@ -128,6 +128,10 @@ void small_rowscale(int nb, int k, int ncols, const double* sigma, int64_t ssig,
                     hipStream_t st);
 // Symmetric EVD (descending) of an m x m matrix: W (m x m) eigenvectors in columns, E eigenvalues.
 void small_sym_evd(int m, const double* A, double* W, double* E, double* gw, hipStream_t st);
+// Generalised symmetric EVD A c = lambda B c (B SPD), ascending: lam (k), C (k x k, C^T B C = I),
+// Cl = -C diag(lam); ws: 4 k^2 + k doubles; flag[0] = 1 when B is not numerically SPD.
+void small_gevd(int k, const double* A, const double* B, double* lam, double* C, double* Cl, int* flag, double* ws,
+                double* gw, hipStream_t st);
 // scratch (doubles per problem) the small kernels need in global memory when s is large
 size_t small_scratch_elems();
 

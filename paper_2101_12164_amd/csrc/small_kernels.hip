@@ -474,6 +474,58 @@ __global__ __launch_bounds__(NT) void k_small_sym_evd(int m, const double* Ain, 
   for (int c = threadIdx.x; c < m; c += NT) E[c] = w.d[w.ord[c]];
 }
 
+// Generalised symmetric eigenproblem A c = lambda B c, step 1: B = L L^T (Cholesky), Linv = L^{-1},
+// M = Linv sym(A) Linv^T (all k x k row-major in global memory; one workgroup).
+__global__ __launch_bounds__(NT) void k_gevd_reduce(int k, const double* A, const double* B, double* L,
+                                                    double* Linv, double* M, int* flag) {
+  __shared__ int sinfo;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int e = threadIdx.x; e < k * k; e += NT) {
+    const int i = e / k, j = e % k;
+    L[e] = 0.5 * (B[i * k + j] + B[j * k + i]);
+    Linv[e] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (chol_dev(L, k, k, &sinfo) && threadIdx.x == 0) flag[0] = 1;
+  for (int m = 0; m < k; ++m) {  // Linv = L^{-1} by a forward sweep on the identity
+    const double inv = 1.0 / L[m * k + m];
+    for (int j = threadIdx.x; j <= m; j += NT) Linv[m * k + j] *= inv;
+    __syncthreads();
+    for (int i = m + 1 + ty; i < k; i += 32) {
+      const double l = L[i * k + m];
+      for (int j = tx; j <= m; j += 32) Linv[i * k + j] -= l * Linv[m * k + j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < k * k; e += NT) {  // L <- Linv sym(A)  (L is no longer needed)
+    const int i = e / k, j = e % k;
+    double acc = 0.0;
+    for (int c = 0; c <= i; ++c) acc += Linv[i * k + c] * 0.5 * (A[c * k + j] + A[j * k + c]);
+    L[e] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < k * k; e += NT) {  // M = (Linv sym(A)) Linv^T
+    const int i = e / k, j = e % k;
+    double acc = 0.0;
+    for (int c = 0; c <= j; ++c) acc += L[i * k + c] * Linv[j * k + c];
+    M[e] = acc;
+  }
+}
+
+// step 3: ascending order; C = Linv^T W (B-orthonormal eigenvectors), Cl = -C diag(lambda)
+__global__ void k_gevd_back(int k, const double* Linv, const double* W, const double* E, double* lam, double* C,
+                            double* Cl) {
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int i = e / k, j = e % k;  // C(i, j): column j <- eigenpair k - 1 - j of the descending EVD
+    const int jj = k - 1 - j;
+    double acc = 0.0;
+    for (int c = i; c < k; ++c) acc += Linv[c * k + i] * W[c * k + jj];
+    C[e] = acc;
+    Cl[e] = -acc * E[jj];
+  }
+  for (int j = threadIdx.x; j < k; j += blockDim.x) lam[j] = E[k - 1 - j];
+}
+
 size_t evd_lds(int n) {
   const size_t b = evd_bytes(n);
   return b <= LDS_LIMIT ? b : 0;
@@ -528,6 +580,21 @@ void small_rowscale(int nb, int k, int ncols, const double* sigma, int64_t ssig,
                     hipStream_t st) {
   if (k * ncols == 0 || nb == 0) return;
   k_small_rowscale<<<dim3((k * ncols + 255) / 256, nb), 256, 0, st>>>(k, ncols, sigma, ssig, c, ldc, sc);
+  NS_LAUNCH_CHECK();
+}
+
+void small_gevd(int k, const double* A, const double* B, double* lam, double* C, double* Cl, int* flag, double* ws,
+                double* gw, hipStream_t st) {
+  if (k > SMAX) fail(INVALID_ARG, "matrix too large for the small dense kernels (limit 256)");
+  double* L = ws;
+  double* Linv = ws + size_t(k) * k;
+  double* M = Linv + size_t(k) * k;
+  double* W = M + size_t(k) * k;
+  double* E = W + size_t(k) * k;
+  k_gevd_reduce<<<1, NT, 0, st>>>(k, A, B, L, Linv, M, flag);
+  NS_LAUNCH_CHECK();
+  small_sym_evd(k, M, W, E, gw, st);
+  k_gevd_back<<<1, 256, 0, st>>>(k, Linv, W, E, lam, C, Cl);
   NS_LAUNCH_CHECK();
 }
 

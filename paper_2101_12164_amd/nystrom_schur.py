@@ -44,6 +44,15 @@ EXPORTED = [
     "nystrom_schur_export_factor",
     "nystrom_schur_get_sizes",
     "nystrom_schur_get_lowrank",
+    "nystrom_schur_get_basis",
+    "nystrom_schur_features",
+    "nystrom_schur_mlp_create",
+    "nystrom_schur_mlp_get_params",
+    "nystrom_schur_mlp_forward",
+    "nystrom_schur_mlp_loss_grad",
+    "nystrom_schur_mlp_adam_step",
+    "nystrom_schur_mlp_destroy",
+    "nystrom_schur_mlp_last_error",
     "nystrom_schur_kernel_timing",
     "nystrom_schur_kernel_stats",
     "nystrom_schur_destroy",
@@ -141,6 +150,25 @@ def load_library() -> ctypes.CDLL:
     lib.nystrom_schur_pcg_solve_batched.argtypes = [H, POINTER(c_void_p), POINTER(c_void_p), c_double, c_int32,
                                                     POINTER(NsSolveInfo)]
     lib.nystrom_schur_pcg_solve_batched.restype = c_int32
+    lib.nystrom_schur_get_basis.argtypes = [H, c_void_p, POINTER(c_double)]
+    lib.nystrom_schur_get_basis.restype = c_int32
+    lib.nystrom_schur_features.argtypes = [c_int64, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                           c_void_p, POINTER(c_int64), c_void_p]
+    lib.nystrom_schur_features.restype = c_int32
+    lib.nystrom_schur_mlp_create.argtypes = [c_int32, c_int32, c_int32, c_void_p, POINTER(c_void_p)]
+    lib.nystrom_schur_mlp_create.restype = c_int32
+    lib.nystrom_schur_mlp_get_params.argtypes = [c_void_p, c_void_p, c_void_p]
+    lib.nystrom_schur_mlp_get_params.restype = c_int32
+    lib.nystrom_schur_mlp_forward.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]
+    lib.nystrom_schur_mlp_forward.restype = c_int32
+    lib.nystrom_schur_mlp_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(c_double), c_void_p]
+    lib.nystrom_schur_mlp_loss_grad.restype = c_int32
+    lib.nystrom_schur_mlp_adam_step.argtypes = [c_void_p, c_double, c_void_p]
+    lib.nystrom_schur_mlp_adam_step.restype = c_int32
+    lib.nystrom_schur_mlp_destroy.argtypes = [c_void_p]
+    lib.nystrom_schur_mlp_destroy.restype = None
+    lib.nystrom_schur_mlp_last_error.argtypes = [c_void_p]
+    lib.nystrom_schur_mlp_last_error.restype = c_char_p
     lib.nystrom_schur_apply.argtypes = [H, c_void_p, c_void_p, c_int32]
     lib.nystrom_schur_apply.restype = c_int32
     lib.nystrom_schur_pcg_solve.argtypes = [H, c_void_p, c_void_p, c_double, c_int32, POINTER(NsSolveInfo)]
@@ -369,6 +397,90 @@ def nystrom_schur_get_lowrank(handle, device="cuda"):
     _check(lib.nystrom_schur_get_lowrank(handle, _dev(Z, torch.float64, "Z"), _dev(S, torch.float64, "Sigma")),
            handle)
     return Z[:, :ke], S[:ke]
+
+
+def nystrom_schur_get_basis(handle, device="cuda"):
+    """(U, rho): the Nystrom basis (n_gamma x k_eff, or None when an accepted proposal replaced it) and the
+    eigen-residual of the judged proposal (0 when none was given)."""
+    lib = load_library()
+    sz = nystrom_schur_get_sizes(handle)
+    ke, ng = sz["k_eff"], sz["n_gamma"]
+    rho = c_double()
+    U = torch.empty((ng, max(ke, 1)), dtype=torch.float64, device=device)
+    st = lib.nystrom_schur_get_basis(handle, _dev(U, torch.float64, "U"), ctypes.byref(rho))
+    if st == NS_ERR_INVALID_ARG:
+        _check(lib.nystrom_schur_get_basis(handle, None, ctypes.byref(rho)), handle)
+        return None, rho.value
+    _check(st, handle)
+    return U[:, :ke], rho.value
+
+
+def nystrom_schur_features(row_ptr, col_idx, val, part, coords=None):
+    """Interface-node features (n_gamma x 16 float32 CUDA tensor)."""
+    lib = load_library()
+    n = row_ptr.numel() - 1
+    X = torch.empty((n, 16), dtype=torch.float32, device=row_ptr.device)
+    ng = c_int64()
+    cp = _dev(coords, torch.float64, "coords") if coords is not None else None
+    st = lib.nystrom_schur_features(n, val.numel(), _dev(row_ptr, torch.int64, "row_ptr"),
+                                    _dev(col_idx, torch.int32, "col_idx"), _dev(val, torch.float64, "val"),
+                                    _dev(part, torch.int32, "part"), cp, _dev(X, torch.float32, "X"),
+                                    ctypes.byref(ng), _stream())
+    _check(st, None)
+    return X[:ng.value]
+
+
+def _mlp_check(status, m):
+    if status != NS_OK:
+        raise NsError(status, load_library().nystrom_schur_mlp_last_error(m).decode())
+
+
+def nystrom_schur_mlp_create(d_in, hidden, d_out, params):
+    """params: flat float32 array (W1, b1, W2, b2, W3, b3; weights row-major in x out)."""
+    import numpy as np
+
+    lib = load_library()
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    m = c_void_p()
+    st = lib.nystrom_schur_mlp_create(d_in, hidden, d_out, p.ctypes.data_as(c_void_p), ctypes.byref(m))
+    _mlp_check(st, None)
+    return m
+
+
+def nystrom_schur_mlp_get_params(m, n_params):
+    import numpy as np
+
+    p = np.empty(n_params, dtype=np.float32)
+    g = np.empty(n_params, dtype=np.float32)
+    _mlp_check(load_library().nystrom_schur_mlp_get_params(m, p.ctypes.data_as(c_void_p),
+                                                           g.ctypes.data_as(c_void_p)), m)
+    return p, g
+
+
+def nystrom_schur_mlp_forward(m, X, d_out):
+    Z0 = torch.empty((X.shape[0], d_out), dtype=torch.float64, device=X.device)
+    _mlp_check(load_library().nystrom_schur_mlp_forward(m, _dev(X, torch.float32, "X"), X.shape[0],
+                                                        _dev(Z0, torch.float64, "Z0"), _stream()), m)
+    return Z0
+
+
+def nystrom_schur_mlp_loss_grad(m, X, U):
+    loss = c_double()
+    _mlp_check(load_library().nystrom_schur_mlp_loss_grad(m, _dev(X, torch.float32, "X"), _dev(U, torch.float64, "U"),
+                                                          X.shape[0], ctypes.byref(loss), _stream()), m)
+    return loss.value
+
+
+def nystrom_schur_mlp_adam_step(m, lr):
+    _mlp_check(load_library().nystrom_schur_mlp_adam_step(m, lr, _stream()), m)
+
+
+def nystrom_schur_mlp_destroy(m):
+    load_library().nystrom_schur_mlp_destroy(m)
+
+
+def nystrom_schur_mlp_last_error(m=None) -> str:
+    return load_library().nystrom_schur_mlp_last_error(m).decode()
 
 
 def nystrom_schur_kernel_timing(enable: bool):
