@@ -44,9 +44,14 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trsm-cols", type=int, default=0)
-    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
-                    help="c2: the 64^3 lognormal system (default line); c3: the batched anisotropic set")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
+                    help="c2: the 64^3 lognormal system (default line); c3: the batched anisotropic set; "
+                         "c4: the learned proposal on the 48^3 lognormal family")
     ap.add_argument("--nprob", type=int, default=256, help="problems of the batched workload")
+    ap.add_argument("--ntrain", type=int, default=2000, help="c4: training instances (seeds 0..ntrain-1)")
+    ap.add_argument("--nheld", type=int, default=32, help="c4: held-out instances (seeds 10000..)")
+    ap.add_argument("--epochs", type=int, default=6, help="c4: passes over the training instances")
+    ap.add_argument("--nval", type=int, default=16, help="c4: validation seeds (5000..) for the threshold")
     return ap.parse_args()
 
 
@@ -85,6 +90,183 @@ def _c3_problem(i):
     from workloads import config_c3_problem
 
     return config_c3_problem(i)
+
+
+def _c4_problem(seed):
+    import numpy as np
+
+    from workloads import config_c4
+
+    P = config_c4(seed=seed)
+    N = P.shape[0]
+    idx = np.indices(P.shape).reshape(3, -1).T[:, ::-1]
+    coords = 2.0 * idx / (N - 1) - 1.0
+    return P, coords
+
+
+def bench_c4(args):
+    """Learned proposal: train the network on the GPU with the Nystrom bases the method produces for the
+    training seeds, then set up + solve held-out seeds with the network's proposal (judged by Rayleigh-Ritz,
+    plain Nystrom on rejection) and with plain Nystrom."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    # the generator processes start before anything touches the GPU and serve every chunk
+    ex = ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1), mp_context=mp.get_context("spawn"))
+
+    def gen(seeds):
+        return list(ex.map(_c4_problem, seeds, chunksize=4))
+
+    t0 = time.perf_counter()
+    held = gen(range(10000, 10000 + args.nheld))
+    val = gen(range(5000, 5000 + args.nval))
+    first_chunk = gen(range(0, min(100, args.ntrain)))
+    print(f"generated first problems in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    import numpy as np
+    import torch
+
+    import paper_2101_12164_amd as ns
+
+    def T(a, dt):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+    def dev(P):
+        return T(P.row_ptr, torch.int64), T(P.col, torch.int32), T(P.val, torch.float64), T(P.part, torch.int32)
+
+    def setup(P, A, proposal=None, accept_tol=0.2):
+        return ns.NystromSchur(*A, k=P.k, p=P.p, omega=T(P.omega(), torch.float64), tol_inner=P.tol_inner,
+                               prec_inner=ns.NS_FP32, proposal=proposal, accept_tol=accept_tol)
+
+    k, hidden = first_chunk[0][0].k, 256
+    data = []
+    t_collect = time.perf_counter()
+    chunk = first_chunk
+    for c0 in range(0, args.ntrain, 100):
+        if c0 > 0:
+            chunk = gen(range(c0, min(c0 + 100, args.ntrain)))
+        for P, C in chunk:
+            A = dev(P)
+            h = setup(P, A)
+            U, _ = ns.nystrom_schur_get_basis(h.handle)
+            h.close()
+            X = ns.nystrom_schur_features(*A, T(C, torch.float64))
+            data.append((X, U.contiguous()))
+        print(f"collected {len(data)} training bases", file=sys.stderr, flush=True)
+    t_collect = time.perf_counter() - t_collect
+    ex.shutdown()
+
+    # initial weights, drawn here (He-normal weights, zero biases; order W1 b1 W2 b2 W3 b3, weights in x out)
+    rng0 = np.random.default_rng(12345)
+    init = []
+    for fan_in, fan_out in ((16, hidden), (hidden, hidden), (hidden, k)):
+        init += [rng0.standard_normal(fan_in * fan_out) * np.sqrt(2.0 / fan_in), np.zeros(fan_out)]
+    m = ns.nystrom_schur_mlp_create(16, hidden, k, np.concatenate(init).astype(np.float32))
+    ns.nystrom_schur_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    rng = np.random.default_rng(0)
+    for ep in range(args.epochs):
+        tot = 0.0
+        for i in rng.permutation(len(data)):
+            X, U = data[i]
+            tot += ns.nystrom_schur_mlp_loss_grad(m, X, U)
+            ns.nystrom_schur_mlp_adam_step(m, 1e-3)
+        losses.append(tot / len(data))
+        print(f"epoch {ep} loss {losses[-1]:.4f}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    stats = {f: ns.nystrom_schur_kernel_stats(f) for f in ("mlp_forward_bf16", "mlp_backward_f32")}
+    ns.nystrom_schur_kernel_timing(False)
+
+    # acceptance threshold from validation seeds: proposals forced through, the largest eigen-residual up to
+    # which every validation seed converges within one PCG iteration of plain Nystrom (never below 0.2)
+    tune = []
+    for P, C in val:
+        A = dev(P)
+        b = T(P.b(), torch.float64)
+        Z0 = ns.nystrom_schur_mlp_forward(m, ns.nystrom_schur_features(*A, T(C, torch.float64)), k)
+        hf = setup(P, A, Z0, accept_tol=1e30)
+        rho = ns.nystrom_schur_get_basis(hf.handle)[1]
+        _, of = hf.solve(b, rtol=P.tol_outer, maxit=2000)
+        hf.close()
+        hp = setup(P, A)
+        _, op = hp.solve(b, rtol=P.tol_outer, maxit=2000)
+        hp.close()
+        tune.append((rho, of["it_pcg"], op["it_pcg"]))
+    tau = 0.2
+    for rho, itf, itp in sorted(tune):
+        if itf > itp + 1:
+            break
+        tau = max(tau, rho)
+    print(f"threshold {tau:.3f} from {len(tune)} validation seeds", file=sys.stderr, flush=True)
+
+    rows = []
+    for P, C in held:
+        A = dev(P)
+        b = T(P.b(), torch.float64)
+        Cd = T(C, torch.float64)
+        res = {}
+        for mode in ("plain", "learned", "plain", "learned"):  # the second pass is timed
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            Z0 = ns.nystrom_schur_mlp_forward(m, ns.nystrom_schur_features(*A, Cd), k) if mode == "learned" else None
+            h = setup(P, A, Z0, accept_tol=tau)
+            x, info = h.solve(b, rtol=P.tol_outer, maxit=2000)
+            torch.cuda.synchronize()
+            res[mode] = dict(sec=time.perf_counter() - t1, it_pcg=info["it_pcg"], relres=info["relres_true"],
+                             accepted=h.setup_info["proposal_accepted"], it_si=h.setup_info["it_inner"],
+                             rho=ns.nystrom_schur_get_basis(h.handle)[1] if mode == "learned" else None)
+            h.close()
+        rows.append(res)
+    ns.nystrom_schur_mlp_destroy(m)
+    acc = [r["learned"]["accepted"] for r in rows]
+    sec_l = float(np.mean([r["learned"]["sec"] for r in rows]))
+    sec_p = float(np.mean([r["plain"]["sec"] for r in rows]))
+    fw = stats["mlp_forward_bf16"]
+    bw = stats["mlp_backward_f32"]
+    ach = fw["flops"] / (fw["ms"] * 1e-3) / 1e12 if fw["ms"] > 0 else 0.0
+    line = {
+        "metric": METRIC,
+        "value": sec_l,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": len(rows),
+        "warmup": len(rows),
+        "ms_per_step": sec_l * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (inner block CG f32; network BF16 forward, FP32 backward)",
+        "data": "synthetic",
+        "config": {"workload": f"learned proposal on 3D 7-point lognormal sigma=1.5 ell=8, 48^3 grid, 3^3 box "
+                               f"subdomains, k={k} p={held[0][0].p}; network 16-{hidden}-{hidden}-{k} trained on "
+                               f"{len(data)} seeds x {args.epochs} epochs; {len(rows)} held-out seeds",
+                   "n": held[0][0].n, "n_gamma": held[0][0].n_gamma},
+        "plain_sec_per_problem": sec_p,
+        "learned_speedup": sec_p / sec_l,
+        "accepted": int(sum(acc)),
+        "held_out": len(rows),
+        "accept_tol": tau,
+        "validation": [{"rho": r, "it_pcg_forced": f, "it_pcg_plain": q} for r, f, q in tune],
+        "accepted_sec_learned_vs_plain": [float(np.mean([r[m_]["sec"] for r in rows if r["learned"]["accepted"]]))
+                                          if any(acc) else None for m_ in ("learned", "plain")],
+        "rejected_sec_learned_vs_plain": [float(np.mean([r[m_]["sec"] for r in rows if not r["learned"]["accepted"]]))
+                                          if not all(acc) else None for m_ in ("learned", "plain")],
+        "rho": {"min": min(r["learned"]["rho"] for r in rows), "max": max(r["learned"]["rho"] for r in rows)},
+        "it_PCG_learned": float(np.mean([r["learned"]["it_pcg"] for r in rows])),
+        "it_PCG_plain": float(np.mean([r["plain"]["it_pcg"] for r in rows])),
+        "it_SI_plain": float(np.mean([r["plain"]["it_si"] for r in rows])),
+        "relres_true_max": max(max(r["learned"]["relres"], r["plain"]["relres"]) for r in rows),
+        "train": {"loss_per_epoch": losses, "seconds": t_train, "collect_seconds": t_collect,
+                  "steps": args.epochs * len(data)},
+        "roofline": {"kernel": "mlp_forward_bf16", "bound": "mfma", "achieved": ach, "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": ach / 2500.0, "traffic": None,
+                     "avg_launch_ms": fw["ms"] / max(fw["launches"], 1), "launches": fw["launches"]},
+        "mlp_backward_tflops": bw["flops"] / (bw["ms"] * 1e-3) / 1e12 if bw["ms"] > 0 else 0.0,
+    }
+    print(json.dumps(line))
 
 
 def bench_c3(args):
@@ -180,6 +362,9 @@ def main():
 
     if args.workload == "c3":
         bench_c3(args)
+        return
+    if args.workload == "c4":
+        bench_c4(args)
         return
 
     import numpy as np

@@ -300,7 +300,8 @@ void nystrom_schur_kernel_timing(int32_t enable);
  * "trsm_interior_f64", "trsm_interior_f32", "trsm_interface_f64",
  * "trsm_interface_f32" (forward and backward sweeps), "schur_epi", "spmm",
  * "local_schur_form", "local_schur_apply_f64", "local_schur_apply_f32",
- * "interface_inverse_f64", "interface_inverse_f32".
+ * "interface_inverse_f64", "interface_inverse_f32", "mlp_forward_bf16",
+ * "mlp_backward_f32".
  * Waits for the recorded events.  All outputs are HOST pointers (may be NULL).
  * NS_ERR_INVALID_ARG for an unknown family. */
 ns_status nystrom_schur_kernel_stats(const char* family, double* total_ms, int64_t* launches, double* bytes,

@@ -238,13 +238,16 @@ __global__ void k_sum_partials(int64_t MN, int nz, const float* __restrict__ par
   out[e] = s;
 }
 
-// column sums of an FP32 n x N matrix (bias gradients), one thread per column, fixed order
-__global__ void k_colsum(int64_t n, int N, const float* __restrict__ X, float* __restrict__ out) {
+// column sums of an FP32 n x N matrix (bias gradients): stage 1 sums rows [z * RC, (z + 1) * RC) per column
+// (grid.y = z), stage 2 adds the partials in a fixed order
+constexpr int COLSUM_ROWS = 256;
+__global__ void k_colsum_part(int64_t n, int N, const float* __restrict__ X, float* __restrict__ part) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
+  const int64_t r0 = int64_t(blockIdx.y) * COLSUM_ROWS, r1 = min(n, r0 + COLSUM_ROWS);
   float s = 0.f;
-  for (int64_t r = 0; r < n; ++r) s += X[r * N + c];
-  out[c] = s;
+  for (int64_t r = r0; r < r1; ++r) s += X[r * N + c];
+  part[int64_t(blockIdx.y) * N + c] = s;
 }
 
 __global__ void k_to_bf(int64_t m, const float* __restrict__ x, uint16_t* __restrict__ y) {
@@ -310,7 +313,13 @@ struct ns_mlp_s {
   DBuf<uint16_t> Xb, H1, H2;
   DBuf<float> dZf, dH1, dH2;
   DBuf<double> Z0, dZ;
-  DBuf<float> part;
+  DBuf<float> part, cpart;
+  // loss workspaces, sized for `cap` rows
+  SegBuf seg;
+  int64_t seg_rows = -1;
+  DBuf<double> small, work, gs;
+  DBuf<int> flag;
+  DBuf<double> lossd;
   std::string last_error;
 };
 
@@ -349,6 +358,9 @@ template <int OUT>
 void bgemm(int M, int N, int K, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
            int64_t sbn, const float* bias, int relu, const uint16_t* mask, int64_t ldm, void* C, int64_t ldc,
            int kchunk, hipStream_t st) {
+  // algorithmic work: 2 M N K flops; operands read once, the output written once
+  KScope ks(KF_MLP_FWD, st, (double(M) * K + double(K) * N) * 2.0 + double(M) * N * (OUT == 2 ? 8.0 : 2.0),
+            2.0 * M * N * double(K));
   const int nz = (K + kchunk - 1) / kchunk;
   dim3 grid((N + 63) / 64, (M + 63) / 64, nz);
   k_bgemm<OUT><<<grid, 256, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, bias, relu, mask, ldm, C, ldc, kchunk);
@@ -371,6 +383,8 @@ void mlp_forward(ns_mlp_s& m, const float* X, int64_t n, hipStream_t st) {
 template <class TA, class TB, int OUT>
 void fgemm(int M, int N, int K, const TA* A, int64_t sam, int64_t sak, const TB* B, int64_t sbk, int64_t sbn,
            const uint16_t* mask, int64_t ldm, float* C, int64_t ldc, int kchunk, hipStream_t st) {
+  KScope ks(KF_MLP_BWD, st, double(M) * K * sizeof(TA) + double(K) * N * sizeof(TB) + double(M) * N * 4.0,
+            2.0 * M * N * double(K));
   const int nz = (K + kchunk - 1) / kchunk;
   dim3 grid((N + 63) / 64, (M + 63) / 64, nz);
   k_fgemm<TA, TB, OUT><<<grid, 256, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, mask, ldm, C, ldc, kchunk);
@@ -389,6 +403,15 @@ void mlp_backward(ns_mlp_s& m, int64_t n, hipStream_t st) {
   if (m.part.n < need) m.part.alloc(need);
   k_d_to_f<<<blocks(n * k), 256, 0, st>>>(n * k, m.dZ, m.dZf);
   NS_LAUNCH_CHECK();
+  const int nzc = int((n + COLSUM_ROWS - 1) / COLSUM_ROWS);
+  const size_t needc = size_t(nzc) * std::max(h, k);
+  if (m.cpart.n < needc) m.cpart.alloc(needc);
+  auto colsum = [&](const float* X, int N, float* out) {
+    k_colsum_part<<<dim3(blocks(N), nzc), 256, 0, st>>>(n, N, X, m.cpart);
+    NS_LAUNCH_CHECK();
+    k_sum_partials<<<blocks(N), 256, 0, st>>>(N, nzc, m.cpart, out);
+    NS_LAUNCH_CHECK();
+  };
   auto wgrad = [&](const uint16_t* A, int a_cols, const float* B, int b_cols, float* out) {
     // out (a_cols x b_cols) = A^T B over the n rows, in fixed row chunks
     fgemm<uint16_t, float, 1>(a_cols, b_cols, int(n), A, 1, a_cols, B, b_cols, 1, nullptr, 0, m.part, b_cols, KC,
@@ -398,18 +421,15 @@ void mlp_backward(ns_mlp_s& m, int64_t n, hipStream_t st) {
   };
   // layer 3
   wgrad(m.H2, h, m.dZf, k, G + m.off[4]);
-  k_colsum<<<blocks(k), 256, 0, st>>>(n, k, m.dZf, G + m.off[5]);
-  NS_LAUNCH_CHECK();
+  colsum(m.dZf, k, G + m.off[5]);
   // dH2 = (dZ W3^T) * 1[H2 > 0]
   fgemm<float, uint16_t, 3>(int(n), h, k, m.dZf, k, 1, W + m.off[4], 1, k, m.H2, h, m.dH2, h, k, st);
   wgrad(m.H1, h, m.dH2, h, G + m.off[2]);
-  k_colsum<<<blocks(h), 256, 0, st>>>(n, h, m.dH2, G + m.off[3]);
-  NS_LAUNCH_CHECK();
+  colsum(m.dH2, h, G + m.off[3]);
   // dH1 = (dH2 W2^T) * 1[H1 > 0]
   fgemm<float, uint16_t, 3>(int(n), h, h, m.dH2, h, 1, W + m.off[2], 1, h, m.H1, h, m.dH1, h, h, st);
   wgrad(m.Xb, din, m.dH1, h, G + m.off[0]);
-  k_colsum<<<blocks(h), 256, 0, st>>>(n, h, m.dH1, G + m.off[1]);
-  NS_LAUNCH_CHECK();
+  colsum(m.dH1, h, G + m.off[1]);
 }
 
 thread_local std::string g_mlp_error = "no error";
@@ -528,32 +548,35 @@ ns_status nystrom_schur_mlp_loss_grad(ns_mlp m, const float* X, const double* U,
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int k = m->k;
     mlp_forward(*m, X, n, st);
-    SegBuf sb;
-    sb.build({0, n}, st);
-    const Seg& sg = sb.view;
-    DBuf<double> small, work, gs;
-    small.alloc(size_t(k) * k * 5 + 8);
-    work.alloc(gram_work_elems(sg, k));
-    gs.alloc(small_scratch_elems());
-    double* Gm = small.p;
+    if (m->seg_rows != n) {  // loss workspaces for this row count (kept for the next calls)
+      m->seg.build({0, n}, st);
+      m->seg_rows = n;
+      m->work.alloc(gram_work_elems(m->seg.view, k));
+    }
+    if (!m->small.p) {
+      m->small.alloc(size_t(k) * k * 5 + 8);
+      m->gs.alloc(small_scratch_elems());
+      m->flag.alloc(1);
+      m->lossd.alloc(1);
+    }
+    const Seg& sg = m->seg.view;
+    double* Gm = m->small.p;
     double* Mm = Gm + k * k;
     double* Xs = Mm + k * k;
     double* P1 = Xs + k * k;
     double* P2 = P1 + k * k;
-    double* dl = P2 + k * k;
-    DBuf<int> flag;
-    flag.alloc(1);
-    NS_HIP(hipMemsetAsync(flag.p, 0, sizeof(int), st));
-    gram<double, double>(sg, m->Z0.p, k, k, m->Z0.p, k, k, Gm, k * k, 1.0, 0.0, work, st);  // G = Z0^T Z0
-    gram<double, double>(sg, m->Z0.p, k, k, U, k, k, Mm, k * k, 1.0, 0.0, work, st);        // M = Z0^T U
-    small_chol_solve(Batch{1, nullptr}, k, Gm, k * k, Mm, k, k * k, Xs, k, k * k, k, k, 1.0, flag, gs, st);
+    double* dl = m->lossd.p;
+    NS_HIP(hipMemsetAsync(m->flag.p, 0, sizeof(int), st));
+    gram<double, double>(sg, m->Z0.p, k, k, m->Z0.p, k, k, Gm, k * k, 1.0, 0.0, m->work, st);  // G = Z0^T Z0
+    gram<double, double>(sg, m->Z0.p, k, k, U, k, k, Mm, k * k, 1.0, 0.0, m->work, st);        // M = Z0^T U
+    small_chol_solve(Batch{1, nullptr}, k, Gm, k * k, Mm, k, k * k, Xs, k, k * k, k, k, 1.0, m->flag, m->gs, st);
     k_loss_mats<<<1, 256, 0, st>>>(k, Xs, Mm, P1, P2, dl);
     NS_LAUNCH_CHECK();
     // dZ = U P1 + Z0 P2
     ts_update<double>(sg, k, m->dZ.p, k, 0.0, 1.0, U, k, k, P1, k, 0, m->Z0.p, k, k, P2, k, 0, st);
     mlp_backward(*m, n, st);
     int fl = 0;
-    NS_HIP(hipMemcpyAsync(&fl, flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    NS_HIP(hipMemcpyAsync(&fl, m->flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
     NS_HIP(hipMemcpyAsync(loss, dl, sizeof(double), hipMemcpyDeviceToHost, st));
     NS_HIP(hipStreamSynchronize(st));
     if (fl) fail(BREAKDOWN, "the proposal Z0 is rank deficient (Z0^T Z0 not positive definite)");
@@ -573,8 +596,7 @@ ns_status nystrom_schur_mlp_adam_step(ns_mlp m, double lr, void* stream) {
     const float c1 = 1.f - std::pow(b1, float(m->steps)), c2 = 1.f - std::pow(b2, float(m->steps));
     k_adam<<<blocks(m->np), 256, 0, st>>>(m->np, m->p, m->g, m->m1, m->m2, float(lr), b1, b2, c1, c2, 1e-8f);
     NS_LAUNCH_CHECK();
-    mlp_refresh_bf(*m, st);
-    NS_HIP(hipStreamSynchronize(st));
+    mlp_refresh_bf(*m, st);  // stream-ordered: the next forward on this stream sees the new weights
     return NS_OK;
   } catch (const Error& e) {
     return mlp_fail(m, e);

@@ -132,6 +132,8 @@ enum KFamily {
   KF_LS_APPLY32,
   KF_INV64,  // explicit interface-block inverses applied, FP64
   KF_INV32,
+  KF_MLP_FWD,  // learned proposal: network forward GEMMs (BF16 MFMA)
+  KF_MLP_BWD,  // learned proposal: backward GEMMs (FP32 MFMA)
   KF_COUNT
 };
 // Brackets one launch when timing is on; bytes / flops are the algorithmic
