@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trsm-cols", type=int, default=0)
+    ap.add_argument("--pcg-graph", type=int, default=0,
+                    help="PCG iterations per replayed HIP graph (0: library default, -1: plain launches)")
     ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
                     help="c2: the 64^3 lognormal system (default line); c3: the batched anisotropic set; "
                          "c4: the learned proposal on the 48^3 lognormal family")
@@ -388,7 +390,8 @@ def main():
 
     def step(prec):
         s = ns.NystromSchur(A["row_ptr"], A["col_idx"], A["val"], A["part"], k=P.k, p=P.p, omega=omega,
-                            tol_inner=P.tol_inner, prec_inner=prec, trsm_cols=args.trsm_cols)
+                            tol_inner=P.tol_inner, prec_inner=prec, trsm_cols=args.trsm_cols,
+                            pcg_graph_iters=args.pcg_graph)
         x, info = s.solve(b, rtol=P.tol_outer, maxit=2000)
         si = s.setup_info
         s.close()

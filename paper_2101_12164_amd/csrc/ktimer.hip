@@ -89,6 +89,14 @@ KScope::~KScope() {
   if (hipEventRecord(b, st) == hipSuccess) t.pending.push_back(Rec{a, b, fam, bytes, flops});
 }
 
+void kscope_add_work(int fam, double bytes, double flops) {
+  KTimer& t = timer();
+  std::lock_guard<std::mutex> g(t.mu);
+  if (!t.on || fam < 0 || fam >= KF_COUNT) return;
+  t.bytes[fam] += bytes;
+  t.flops[fam] += flops;
+}
+
 }  // namespace ns
 
 extern "C" {

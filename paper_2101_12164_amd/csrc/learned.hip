@@ -321,6 +321,8 @@ struct ns_mlp_s {
   DBuf<int> flag;
   DBuf<double> lossd;
   std::string last_error;
+  hipEvent_t ev = nullptr;       // recorded at the end of every call
+  hipStream_t last = nullptr;    // stream of the previous call
 };
 
 namespace ns {
@@ -434,6 +436,21 @@ void mlp_backward(ns_mlp_s& m, int64_t n, hipStream_t st) {
 
 thread_local std::string g_mlp_error = "no error";
 
+// Calls may come on different streams: a call on another stream than the previous one first waits (on the
+// device) for the previous call's work, so buffers that are reused or freed in stream order stay safe.
+struct MlpCall {
+  ns_mlp_s& m;
+  hipStream_t st;
+  StreamScope ss;
+  MlpCall(ns_mlp_s& m_, hipStream_t s) : m(m_), st(s), ss(s) {
+    if (m.ev && s != m.last) NS_HIP(hipStreamWaitEvent(s, m.ev, 0));
+  }
+  ~MlpCall() {
+    if (m.ev) (void)hipEventRecord(m.ev, st);
+    m.last = st;
+  }
+};
+
 ns_status mlp_fail(ns_mlp_s* m, const Error& e) {
   g_mlp_error = e.msg;
   if (m) m->last_error = e.msg;
@@ -452,6 +469,7 @@ ns_status nystrom_schur_features(int64_t n, int64_t nnz, const int64_t* row_ptr,
     if (n <= 0 || nnz < 0 || !row_ptr || !col_idx || !val || !part || !X || !n_gamma)
       fail(INVALID_ARG, "bad features arguments");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    StreamScope ss(st);
     DBuf<int64_t> gpos;
     gpos.alloc(n);
     k_flag_interface<<<blocks(n), 256, 0, st>>>(n, part, gpos);
@@ -499,6 +517,7 @@ ns_status nystrom_schur_mlp_create(int32_t d_in, int32_t hidden, int32_t d_out, 
     m->m1.alloc(m->np);
     m->m2.alloc(m->np);
     m->wb.alloc(m->np);
+    NS_HIP(hipEventCreateWithFlags(&m->ev, hipEventDisableTiming));
     NS_HIP(hipMemcpy(m->p.p, params, m->np * sizeof(float), hipMemcpyHostToDevice));
     NS_HIP(hipMemset(m->g.p, 0, m->np * sizeof(float)));
     NS_HIP(hipMemset(m->m1.p, 0, m->np * sizeof(float)));
@@ -509,7 +528,7 @@ ns_status nystrom_schur_mlp_create(int32_t d_in, int32_t hidden, int32_t d_out, 
     return NS_OK;
   } catch (const Error& e) {
     ns_status s = mlp_fail(m, e);
-    delete m;
+    nystrom_schur_mlp_destroy(m);
     return s;
   }
 }
@@ -531,6 +550,7 @@ ns_status nystrom_schur_mlp_forward(ns_mlp m, const float* X, int64_t n, double*
   try {
     if (!X || !Z0 || n < 1 || n > (int64_t(1) << 30)) fail(INVALID_ARG, "bad forward arguments");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    MlpCall call(*m, st);
     mlp_forward(*m, X, n, st);
     NS_HIP(hipMemcpyAsync(Z0, m->Z0.p, n * m->k * sizeof(double), hipMemcpyDeviceToDevice, st));
     NS_HIP(hipStreamSynchronize(st));
@@ -546,6 +566,7 @@ ns_status nystrom_schur_mlp_loss_grad(ns_mlp m, const float* X, const double* U,
   try {
     if (!X || !U || !loss || n < m->k || n > (int64_t(1) << 30)) fail(INVALID_ARG, "bad loss_grad arguments");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    MlpCall call(*m, st);
     const int k = m->k;
     mlp_forward(*m, X, n, st);
     if (m->seg_rows != n) {  // loss workspaces for this row count (kept for the next calls)
@@ -591,6 +612,7 @@ ns_status nystrom_schur_mlp_adam_step(ns_mlp m, double lr, void* stream) {
   try {
     if (!(lr > 0.0)) fail(INVALID_ARG, "learning rate must be positive");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    MlpCall call(*m, st);
     const float b1 = 0.9f, b2 = 0.999f;
     ++m->steps;
     const float c1 = 1.f - std::pow(b1, float(m->steps)), c2 = 1.f - std::pow(b2, float(m->steps));
@@ -603,7 +625,12 @@ ns_status nystrom_schur_mlp_adam_step(ns_mlp m, double lr, void* stream) {
   }
 }
 
-void nystrom_schur_mlp_destroy(ns_mlp m) { delete m; }
+void nystrom_schur_mlp_destroy(ns_mlp m) {
+  if (!m) return;
+  (void)hipDeviceSynchronize();  // calls may have used several streams: free after all of them
+  if (m->ev) (void)hipEventDestroy(m->ev);
+  delete m;
+}
 
 const char* nystrom_schur_mlp_last_error(ns_mlp m) { return m ? m->last_error.c_str() : g_mlp_error.c_str(); }
 

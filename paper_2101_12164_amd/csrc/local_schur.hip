@@ -387,8 +387,8 @@ void local_schur_build(Handle& h) {
   DBuf<int64_t> gbase_d, gcnt_d;
   gbase_d.alloc(nb);
   gcnt_d.alloc(nb);
-  NS_HIP(hipMemcpy(gbase_d.p, gbase.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(gcnt_d.p, gcnt.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+  upload(gbase_d.p, gbase.data(), nb * sizeof(int64_t), st);
+  upload(gcnt_d.p, gcnt.data(), nb * sizeof(int64_t), st);
   DBuf<int> flag, cnt;
   DBuf<int32_t> cidx;
   flag.alloc(int64_t(nb) * ldf);
@@ -422,7 +422,7 @@ void local_schur_build(Handle& h) {
   const int64_t ldw = std::max(ls.max_m, 1);
   for (int j = 0; j < nb; ++j) wld[j] = ldw;
   ls.goff.alloc(nb);
-  NS_HIP(hipMemcpy(ls.goff.p, goff.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+  upload(ls.goff.p, goff.data(), nb * sizeof(int64_t), st);
   ls.glist.alloc(gp > 0 ? gp : 1);
   NS_HIP(hipMemsetAsync(ls.glist.p, 0xFF, ls.glist.n * sizeof(int32_t), st));
   k_compact<<<nb, 1024, 0, st>>>(gcnt_d, gbase_d, ldf, flag, cnt, ls.goff, cidx, ls.glist, 1);
@@ -430,14 +430,14 @@ void local_schur_build(Handle& h) {
   // per-block metadata for the batched GEMMs
   auto up = [&](DBuf<int64_t>& d, const std::vector<int64_t>& v) {
     d.alloc(nb);
-    NS_HIP(hipMemcpy(d.p, v.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice));
+    upload(d.p, v.data(), nb * sizeof(int64_t), st);
   };
   ls.M.alloc(nb);
   ls.K.alloc(nb);
   ls.Kg.alloc(nb);
-  NS_HIP(hipMemcpy(ls.M.p, ls.h_m.data(), nb * sizeof(int), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(ls.K.p, Kv.data(), nb * sizeof(int), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(ls.Kg.p, ls.h_m.data(), nb * sizeof(int), hipMemcpyHostToDevice));
+  upload(ls.M.p, ls.h_m.data(), nb * sizeof(int), st);
+  upload(ls.K.p, Kv.data(), nb * sizeof(int), st);
+  upload(ls.Kg.p, ls.h_m.data(), nb * sizeof(int), st);
   up(ls.soff, soff);
   up(ls.sld, sld);
   up(ls.wld, wld);
@@ -476,23 +476,10 @@ void local_schur_build(Handle& h) {
     k_first_tiles<<<(nbs * ctiles + 255) / 256, 256, 0, st>>>(nbs, int(ldw), ctiles, first.p + int64_t(b0) * ldw,
                                                                ftile.p + int64_t(b0) * ctiles);
     NS_LAUNCH_CHECK();
-    // algorithmic flops: a column with first nonzero row r_c costs, over the rows below r_c, two flops per
-    // factor entry within the half-bandwidth bw_j, i.e. t(t-1) + 2 (rem - t) bw_j + rem with rem = n_b - r_c
-    // and t = min(rem, bw_j) (r_c approximated per 64-column tile by the tile's first row)
-    std::vector<int> hf(size_t(nbs) * ctiles);
-    NS_HIP(hipMemcpy(hf.data(), ftile.p + int64_t(b0) * ctiles, hf.size() * sizeof(int), hipMemcpyDeviceToHost));
-    double fl = 0.0;
-    for (int j = b0; j < b1; ++j)
-      for (int t = 0; t < ctiles; ++t) {
-        const int cols = std::max(0, std::min(64, ls.h_m[j] - 64 * t));
-        const double rem =
-            std::max(0.0, double(lv.h_nb[j]) - 64.0 * std::min(hf[size_t(j - b0) * ctiles + t], 1 << 20));
-        const double tb = std::min(rem, double(lv.h_bw[j]));
-        fl += (tb * (tb - 1.0) + 2.0 * (rem - tb) * lv.h_bw[j] + rem) * cols;
-      }
-    tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p, ftile.p, fl, b0, b1, row0);  // W_j = L_j^{-1} B_j
+    // the sweep's algorithmic flops are added once all groups are queued (they need the first tiles)
+    tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p, ftile.p, 0.0, b0, b1, row0);  // W_j = L_j^{-1} B_j
     for (int j = b0; j < b1; ++j) hwo[j] = (lv.h_roff[j] - row0) * ldw;
-    NS_HIP(hipMemcpyAsync(woffg.p + b0, hwo.data() + b0, nbs * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    upload(woffg.p + b0, hwo.data() + b0, nbs * sizeof(int64_t), st);
     // B_j = W_j: offset woff[j] inside the group, common leading dimension ldw
     GemmBatch g{ftile.p + int64_t(b0) * ctiles, ctiles, ls.M.p + b0, ls.K.p + b0, woffg.p + b0, ls.wld.p + b0,
                 woffg.p + b0, 1, ldw, ls.soff.p + b0, 1, ls.sld.p + b0, 0};
@@ -500,7 +487,6 @@ void local_schur_build(Handle& h) {
     for (int j = b0; j < b1; ++j) flg += 2.0 * Kv[j] * ls.h_m[j] * (ls.h_m[j] + 1) / 2;
     KScope ks(KF_LS_FORM, st, double(rows) * ldw * 8.0, flg);
     launch_gemm<double>(ls, W.p, W.p, ls.S64.p, 0, st, true, g, ls.max_m, nbs);
-    NS_HIP(hipStreamSynchronize(st));  // W and hwo are reused by the next group
   }
   if (h.prec_inner) {
     ls.S32.alloc(ls.S64.n);
@@ -516,7 +502,25 @@ void local_schur_build(Handle& h) {
   NS_LAUNCH_CHECK();
   scan_inclusive(C.ptr.p + 1, nG, st);
   NS_HIP(hipMemcpyAsync(&C.nnz, C.ptr.p + nG, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  // algorithmic flops of the forward sweeps W_j = L_j^{-1} B_j: a column with first nonzero row r_c costs,
+  // over the rows below r_c, two flops per factor entry within the half-bandwidth bw_j, i.e.
+  // t(t-1) + 2 (rem - t) bw_j + rem with rem = n_b - r_c and t = min(rem, bw_j) (r_c approximated per
+  // 64-column tile by the tile's first row)
+  std::vector<int> hf(size_t(nb) * ctiles);
+  NS_HIP(hipMemcpyAsync(hf.data(), ftile.p, hf.size() * sizeof(int), hipMemcpyDeviceToHost, st));
   NS_HIP(hipStreamSynchronize(st));
+  stream_idle(st);
+  {
+    double fl = 0.0;
+    for (int j = 0; j < nb; ++j)
+      for (int t = 0; t < ctiles; ++t) {
+        const int cols = std::max(0, std::min(64, ls.h_m[j] - 64 * t));
+        const double rem = std::max(0.0, double(lv.h_nb[j]) - 64.0 * std::min(hf[size_t(j) * ctiles + t], 1 << 20));
+        const double tb = std::min(rem, double(lv.h_bw[j]));
+        fl += (tb * (tb - 1.0) + 2.0 * (rem - tb) * lv.h_bw[j] + rem) * cols;
+      }
+    kscope_add_work(KF_TRSM_I64, 0.0, fl);
+  }
   C.col.alloc(C.nnz > 0 ? C.nnz : 1);
   C.val64.alloc(C.nnz > 0 ? C.nnz : 1);
   C.val32.alloc(C.nnz > 0 ? C.nnz : 1);
@@ -534,7 +538,6 @@ void local_schur_build(Handle& h) {
     ls.alg_bytes += double(ls.h_m[j]) * ls.h_m[j];
     ls.alg_flops += 2.0 * ls.h_m[j] * ls.h_m[j];
   }
-  NS_HIP(hipStreamSynchronize(st));
   ls.built = true;
 }
 

@@ -85,10 +85,9 @@ struct ns_handle_s {
   int proposal_accepted = 0;
   double proposal_rho = 0.0;  // largest eigen-residual over the ceil(k/2) smallest Ritz values
 
-  // error flags written by kernels (pinned host-visible copy in hflags)
+  // error flags written by kernels and their host copy
   ns::DBuf<int> dflags;
-  int* hflags = nullptr;    // pinned
-  double* hscal = nullptr;  // pinned scalars for readbacks
+  int hflags[16] = {};
 
   // workspaces (sized at setup)
   ns::DBuf<double> wsT64, wsB64, wsJ64, wsB64b, wsJ64b;  // interior rhs, level-2 rhs, junction rhs, outputs
@@ -98,7 +97,6 @@ struct ns_handle_s {
   int64_t ws_cols = 0;     // column capacity of the workspaces
   int64_t wsT64_cols = 0, wsT32_cols = 0;  // column capacity of the interior workspaces
 
-  ~ns_handle_s();
 };
 
 namespace ns {

@@ -27,6 +27,30 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 #define NS_HIP(call) ::ns::hip_check((call), #call, __FILE__, __LINE__)
 #define NS_LAUNCH_CHECK() ::ns::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
 
+// Device memory is stream-ordered: every library call sets the stream its
+// buffers are allocated and freed on (StreamScope), allocations come from the
+// device's default memory pool (hipMallocAsync) and frees are queued behind
+// the work already on that stream (hipFreeAsync), so neither waits for the
+// device.  The pool keeps freed memory for reuse by later calls (its release
+// threshold is raised once per device) instead of returning it at every
+// synchronisation.
+hipStream_t& alloc_stream();  // thread-local; the null stream outside a call
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(alloc_stream()) { alloc_stream() = s; }
+  ~StreamScope() { alloc_stream() = prev; }
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
+};
+void* dev_alloc(size_t bytes);  // throws OOM
+void dev_free(void* p);         // ordered on alloc_stream()
+// Host-to-device copy ordered on st that returns at once: the bytes are first
+// copied into a pinned staging area of the calling thread (src may be freed on
+// return).  A staging area is reused only after the copies from it completed.
+void upload(void* dst, const void* src, size_t bytes, hipStream_t st);
+// Tells the staging area that stream st has been synchronised.
+void stream_idle(hipStream_t st);
+
 // Owning device buffer.
 template <class T>
 struct DBuf {
@@ -39,16 +63,11 @@ struct DBuf {
   void alloc(size_t count) {
     release();
     if (count == 0) return;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
-    if (e != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      fail(OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-    }
+    p = static_cast<T*>(dev_alloc(count * sizeof(T)));
     n = count;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p);
     p = nullptr;
     n = 0;
   }
@@ -147,6 +166,8 @@ struct KScope {
   KScope(int fam, hipStream_t st, double bytes = 0.0, double flops = 0.0);
   ~KScope();
 };
+// Adds work to a family's totals when timing is on (work known only after its launches were queued).
+void kscope_add_work(int fam, double bytes, double flops);
 
 // ---------------------------------------------------------------- dense tiles
 // Batched Cholesky of all blocks of a level (FP64, in place), with inverted
@@ -161,11 +182,11 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
 // Forward sweep only: B <- L^{-1} B.
 // ncols_blk: optional per-block column count (chunks beyond it are skipped);
 // first_tile: optional [block * nchunks + chunk] first tile row with a nonzero
-// right-hand side (rows above stay zero); alg_flops overrides the timing work.
+// right-hand side (rows above stay zero); alg_flops >= 0 overrides the timing work.
 // Blocks b0 .. b1-1 only (b1 < 0: all), with B holding the padded rows from row0 on.
 template <class T>
 void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st,
-                    const int* ncols_blk = nullptr, const int* first_tile = nullptr, double alg_flops = 0.0,
+                    const int* ncols_blk = nullptr, const int* first_tile = nullptr, double alg_flops = -1.0,
                     int b0 = 0, int b1 = -1, int64_t row0 = 0);
 // Single right-hand side sweeps (FP64) with 16-wave workgroups; need LT64.
 bool trsv1_supported(const TileLevel& lv);

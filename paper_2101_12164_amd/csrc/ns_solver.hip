@@ -73,7 +73,7 @@ struct SmallMats {
     p += np;
     relres = p;
     ibuf.alloc(8 + 10 * size_t(np));
-    NS_HIP(hipMemset(ibuf.p, 0, ibuf.n * sizeof(int)));
+    NS_HIP(hipMemsetAsync(ibuf.p, 0, ibuf.n * sizeof(int), alloc_stream()));
     flag = ibuf.p;
     ctr = ibuf.p + 4;
     int* q = ibuf.p + 8;
@@ -89,20 +89,28 @@ template <class T>
 void read_back(Handle& h, T* host, const T* dev, size_t count) {
   NS_HIP(hipMemcpyAsync(host, dev, count * sizeof(T), hipMemcpyDeviceToHost, h.stream));
   NS_HIP(hipStreamSynchronize(h.stream));
+  stream_idle(h.stream);
 }
 
-void check_chol(Handle& h, int level, ns_setup_info* info) {
-  int e[3];
-  read_back(h, e, h.dflags.p + 8, 3);
-  if (!e[0]) return;
-  int blk = e[1];
-  if (level == 2) blk = -2 - blk;
-  if (level == 3) blk = -1;
-  if (info) {
-    info->bad_block = blk;
-    info->bad_col = e[2];
+// Pivot flags of the three factorisation levels (subdomains, interface blocks, junction), read once after
+// all of them: a failed level only leaves meaningless values in the later ones, whose launches do not depend
+// on them, and the first failing level is reported.
+constexpr int CHOL_FLAGS = 16;  // dflags[16 + 3 (level - 1) ..]: (flag, block, column)
+void check_chol(Handle& h, ns_setup_info* info) {
+  int e[9];
+  read_back(h, e, h.dflags.p + CHOL_FLAGS, 9);
+  for (int level = 1; level <= 3; ++level) {
+    const int* f = e + 3 * (level - 1);
+    if (!f[0]) continue;
+    int blk = f[1];
+    if (level == 2) blk = -2 - blk;
+    if (level == 3) blk = -1;
+    if (info) {
+      info->bad_block = blk;
+      info->bad_col = f[2];
+    }
+    fail(NOT_SPD, "Cholesky pivot <= 0 in block " + std::to_string(blk) + ", column " + std::to_string(f[2]));
   }
-  fail(NOT_SPD, "Cholesky pivot <= 0 in block " + std::to_string(blk) + ", column " + std::to_string(e[2]));
 }
 
 // ------------------------------------------------------------------ inner-solve control (per problem)
@@ -213,7 +221,7 @@ void block_pcg(Handle& h, SmallMats& sm, const double* Omega, double* D) {
   T* P = Pb.p;
   T* Q = Qb.p;
   std::vector<int> ones(np, 1);
-  NS_HIP(hipMemcpyAsync(sm.active, ones.data(), np * sizeof(int), hipMemcpyHostToDevice, st));
+  upload(sm.active, ones.data(), np * sizeof(int), st);
   NS_HIP(hipMemsetAsync(sm.conv, 0, np * sizeof(int), st));
   NS_HIP(hipMemsetAsync(sm.ctr, 0, 4 * sizeof(int), st));
   op_schur<T>(h, Omt, s, R.p, s, s, /*w_only=*/true);  // F = W Omega
@@ -288,7 +296,7 @@ void nystrom(Handle& h, SmallMats& sm, const double* Omega, double* Y) {
     std::vector<double> coef(np);
     for (int q = 0; q < np; ++q)
       coef[q] = 11.0 * (double(h.h_goff[q + 1] - h.h_goff[q]) * s + double(s) * (s + 1)) * u;
-    NS_HIP(hipMemcpy(sm.coef, coef.data(), np * sizeof(double), hipMemcpyHostToDevice));
+    upload(sm.coef, coef.data(), np * sizeof(double), st);
   }
   double* A = Y;
   double* B = Qb.p;
@@ -310,7 +318,7 @@ void nystrom(Handle& h, SmallMats& sm, const double* Omega, double* Y) {
     h.k_eff = std::max(h.k_eff, h.h_keff[q]);
   }
   h.keff_d.alloc(np);
-  NS_HIP(hipMemcpy(h.keff_d.p, h.h_keff.data(), np * sizeof(int), hipMemcpyHostToDevice));
+  upload(h.keff_d.p, h.h_keff.data(), np * sizeof(int), st);
   h.Z.alloc(nG * (k > 0 ? k : 1));
   h.Sigma.alloc(size_t(k > 0 ? k : 1) * np);
   NS_HIP(hipMemsetAsync(h.Z.p, 0, h.Z.n * sizeof(double), st));
@@ -379,7 +387,7 @@ bool judge_proposal(Handle& h) {
   h.k_eff = k;
   h.h_keff.assign(1, k);
   h.keff_d.alloc(1);
-  NS_HIP(hipMemcpy(h.keff_d.p, h.h_keff.data(), sizeof(int), hipMemcpyHostToDevice));
+  upload(h.keff_d.p, h.h_keff.data(), sizeof(int), st);
   NS_HIP(hipStreamSynchronize(st));
   return true;
 }
@@ -639,10 +647,8 @@ void check_options(Handle* h) {
   if (h->schur_mode < 0 || h->schur_mode > 2) fail(INVALID_ARG, "schur_mode must be 0, 1 or 2");
   if (h->trsm_cols != 0 && h->trsm_cols != 16 && h->trsm_cols != 32 && h->trsm_cols != 64)
     fail(INVALID_ARG, "trsm_cols must be 0, 16, 32 or 64");
-  h->dflags.alloc(16);
-  NS_HIP(hipMemset(h->dflags.p, 0, 16 * sizeof(int)));
-  NS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hflags), 16 * sizeof(int), hipHostMallocDefault));
-  NS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->hscal), 64 * sizeof(double), hipHostMallocDefault));
+  h->dflags.alloc(32);
+  NS_HIP(hipMemsetAsync(h->dflags.p, 0, 32 * sizeof(int), h->stream));
 }
 
 // Setup after the matrix is in place: extraction, factorisations, inner solve, Nystrom.
@@ -658,14 +664,11 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
   h->segN.build(h->h_noff, h->stream);
   h->small.alloc(small_scratch_elems() * h->nprob);
   ev.rec(1);
-  tile_cholesky(h->L1, h->dflags.p + 8, h->stream);
-  check_chol(*h, 1, info);
+  tile_cholesky(h->L1, h->dflags.p + CHOL_FLAGS, h->stream);
   if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_build(*h);
-  tile_cholesky(h->L2, h->dflags.p + 8, h->stream);
-  check_chol(*h, 2, info);
+  tile_cholesky(h->L2, h->dflags.p + CHOL_FLAGS + 3, h->stream);
   assemble_junction(*h);
-  tile_cholesky(h->LJ, h->dflags.p + 8, h->stream);
-  check_chol(*h, 3, info);
+  tile_cholesky(h->LJ, h->dflags.p + CHOL_FLAGS + 6, h->stream);
   if (trsv1_supported_size(h->L1)) tile_make_transposed(h->L1, h->stream);
   for (ns::TileLevel* lv : {&h->L2, &h->LJ})
     if (lv->nblk && lv->max_nt * TILE <= 4096 && lv->nrows_pad * lv->max_nt * TILE <= (int64_t(1) << 28))
@@ -675,6 +678,7 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
     tile_make_fp32(h->L2, h->stream);
     tile_make_fp32(h->LJ, h->stream);
   }
+  check_chol(*h, info);
   ev.rec(2);
   const int np = h->nprob;
   h->it_inner.assign(np, 0);
@@ -720,7 +724,7 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
     if (h->apply_mode == NS_APPLY_ADEF2) setup_adef2(*h);
   } else {
     h->keff_d.alloc(np);
-    NS_HIP(hipMemset(h->keff_d.p, 0, np * sizeof(int)));
+    NS_HIP(hipMemsetAsync(h->keff_d.p, 0, np * sizeof(int), h->stream));
     ev.rec(3);
   }
   ev.rec(4);
@@ -780,10 +784,16 @@ __global__ void k_shift_cols(int64_t m, const int32_t* __restrict__ c, int64_t a
 
 using namespace ns;
 
-ns_handle_s::~ns_handle_s() {
-  if (hflags) (void)hipHostFree(hflags);
-  if (hscal) (void)hipHostFree(hscal);
+namespace ns {
+namespace {
+// Frees the handle's buffers in order behind the work queued on its stream.
+void destroy_handle(Handle* h) {
+  if (!h) return;
+  StreamScope ss(h->stream);
+  delete h;
 }
+}  // namespace
+}  // namespace ns
 
 extern "C" {
 
@@ -803,6 +813,7 @@ ns_status nystrom_schur_setup(int64_t n, int64_t nnz, const int64_t* row_ptr, co
       info->bad_block = info->bad_col = -1;
     }
     h = new_handle(opt);
+    StreamScope ss(h->stream);
     check_options(h);
     const double* om[1] = {opt->omega};
     setup_core(h, n, nnz, row_ptr, col_idx, val, part, nullptr, om, info);
@@ -810,7 +821,7 @@ ns_status nystrom_schur_setup(int64_t n, int64_t nnz, const int64_t* row_ptr, co
     return NS_OK;
   } catch (const Error& e) {
     ns_status st = finish(h, e);
-    delete h;
+    destroy_handle(h);
     return st;
   }
 }
@@ -833,6 +844,7 @@ ns_status nystrom_schur_setup_batched(int32_t nprob, const int64_t* n, const int
         info[q].bad_block = info[q].bad_col = -1;
       }
     h = new_handle(opt);
+    StreamScope ss(h->stream);
     check_options(h);
     hipStream_t st = h->stream;
     Pieces pc;
@@ -847,7 +859,7 @@ ns_status nystrom_schur_setup_batched(int32_t nprob, const int64_t* n, const int
       hmm[2 * q] = INT32_MIN;
       hmm[2 * q + 1] = INT32_MAX;
     }
-    NS_HIP(hipMemcpy(mm.p, hmm.data(), hmm.size() * sizeof(int), hipMemcpyHostToDevice));
+    upload(mm.p, hmm.data(), hmm.size() * sizeof(int), st);
     for (int q = 0; q < nprob; ++q) {
       if (n[q] <= 0 || nnz[q] < n[q] || !row_ptr[q] || !col_idx[q] || !val[q] || !part[q])
         fail(INVALID_ARG, "problem " + std::to_string(q) + ": need n > 0, nnz >= n and non-NULL arrays");
@@ -890,7 +902,7 @@ ns_status nystrom_schur_setup_batched(int32_t nprob, const int64_t* n, const int
       NS_LAUNCH_CHECK();
       NS_HIP(hipMemcpyAsync(valu.p + eoff[q], val[q], nnz[q] * sizeof(double), hipMemcpyDeviceToDevice, st));
     }
-    NS_HIP(hipMemcpyAsync(rpu.p + nu, &nnzu, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    upload(rpu.p + nu, &nnzu, sizeof(int64_t), st);
     int hb = 0;
     read_back(*h, &hb, bad.p, 1);
     if (hb) fail(INVALID_ARG, "CSR structure invalid (row_ptr/col_idx out of range) in some problem");
@@ -899,7 +911,7 @@ ns_status nystrom_schur_setup_batched(int32_t nprob, const int64_t* n, const int
     return NS_OK;
   } catch (const Error& e) {
     ns_status st = finish(h, e);
-    delete h;
+    destroy_handle(h);
     return st;
   }
 }
@@ -907,6 +919,7 @@ ns_status nystrom_schur_setup_batched(int32_t nprob, const int64_t* n, const int
 ns_status nystrom_schur_apply(ns_handle h, const double* r_gamma, double* z_gamma, int32_t ncols) {
   if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
   try {
+    StreamScope ss(h->stream);
     if (ncols < 1 || ncols > 1024 || !r_gamma || !z_gamma) fail(INVALID_ARG, "bad apply arguments");
     DBuf<double> work, c1, c2;
     work.alloc(gram_work_elems(h->segG.view, std::max(h->k, ncols)));
@@ -924,6 +937,7 @@ ns_status nystrom_schur_pcg_solve(ns_handle h, const double* b, double* x, doubl
                                   ns_solve_info* info) {
   if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
   try {
+    StreamScope ss(h->stream);
     if (!b || !x || maxit < 0 || !(rtol > 0.0)) fail(INVALID_ARG, "bad pcg_solve arguments");
     if (h->nprob != 1) fail(INVALID_ARG, "batched handle: use nystrom_schur_pcg_solve_batched");
     hipStream_t st = h->stream;
@@ -960,6 +974,7 @@ ns_status nystrom_schur_pcg_solve_batched(ns_handle h, const double* const* b, d
                                           int32_t maxit, ns_solve_info* info) {
   if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
   try {
+    StreamScope ss(h->stream);
     if (!b || !x || maxit < 0 || !(rtol > 0.0)) fail(INVALID_ARG, "bad pcg_solve_batched arguments");
     hipStream_t st = h->stream;
     const int np = h->nprob;
@@ -1010,6 +1025,7 @@ ns_status nystrom_schur_pcg_solve_batched(ns_handle h, const double* const* b, d
 ns_status nystrom_schur_schur_apply(ns_handle h, const double* X, double* Y, int32_t ncols, int32_t prec) {
   if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
   try {
+    StreamScope ss(h->stream);
     if (ncols < 1 || ncols > 1024 || !X || !Y) fail(INVALID_ARG, "bad arguments");
     if (prec == NS_FP32) {
       if (!h->prec_inner) fail(INVALID_ARG, "FP32 operators exist only with prec_inner = NS_FP32");
@@ -1033,6 +1049,7 @@ ns_status nystrom_schur_schur_apply(ns_handle h, const double* X, double* Y, int
 ns_status nystrom_schur_interface_solve(ns_handle h, const double* X, double* Y, int32_t ncols, int32_t prec) {
   if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
   try {
+    StreamScope ss(h->stream);
     if (ncols < 1 || ncols > 1024 || !X || !Y) fail(INVALID_ARG, "bad arguments");
     if (prec == NS_FP32) {
       if (!h->prec_inner) fail(INVALID_ARG, "FP32 operators exist only with prec_inner = NS_FP32");
@@ -1055,6 +1072,7 @@ ns_status nystrom_schur_interface_solve(ns_handle h, const double* X, double* Y,
 ns_status nystrom_schur_interior_solve(ns_handle h, const double* X, double* Y, int32_t ncols, int32_t prec) {
   if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
   try {
+    StreamScope ss(h->stream);
     if (ncols < 1 || ncols > 1024 || !X || !Y) fail(INVALID_ARG, "bad arguments");
     if (prec == NS_FP32) {
       if (!h->prec_inner) fail(INVALID_ARG, "FP32 operators exist only with prec_inner = NS_FP32");
@@ -1077,6 +1095,7 @@ ns_status nystrom_schur_interior_solve(ns_handle h, const double* X, double* Y, 
 ns_status nystrom_schur_export_factor(ns_handle h, int32_t block, double* L) {
   if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
   try {
+    StreamScope ss(h->stream);
     if (block < 0 || block >= h->nsub || !L) fail(INVALID_ARG, "bad block index");
     tile_export(h->L1, block, L, h->stream);
     NS_HIP(hipStreamSynchronize(h->stream));
@@ -1102,6 +1121,7 @@ ns_status nystrom_schur_get_sizes(ns_handle h, int64_t* out) {
 ns_status nystrom_schur_get_lowrank(ns_handle h, double* Z, double* Sigma) {
   if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
   try {
+    StreamScope ss(h->stream);
     if (h->nprob != 1) fail(INVALID_ARG, "batched handle: low-rank terms are per problem");
     if (h->k_eff > 0) {
       if (Z)
@@ -1120,6 +1140,7 @@ ns_status nystrom_schur_get_lowrank(ns_handle h, double* Z, double* Sigma) {
 ns_status nystrom_schur_get_basis(ns_handle h, double* U, double* rho) {
   if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
   try {
+    StreamScope ss(h->stream);
     if (h->nprob != 1) fail(INVALID_ARG, "batched handle: bases are per problem");
     if (rho) *rho = h->proposal_rho;
     if (U && h->k_eff > 0) {
@@ -1134,7 +1155,7 @@ ns_status nystrom_schur_get_basis(ns_handle h, double* U, double* rho) {
   }
 }
 
-void nystrom_schur_destroy(ns_handle h) { delete h; }
+void nystrom_schur_destroy(ns_handle h) { destroy_handle(h); }
 
 const char* nystrom_schur_last_error(ns_handle h) {
   if (h) return h->last_error.c_str();

@@ -192,7 +192,6 @@ void scan_inclusive(int64_t* a, int64_t m, hipStream_t st) {
     k_scan_add<<<int(nb - 1), 1024, 0, st>>>(a, m, bsum);
     NS_LAUNCH_CHECK();
   }
-  NS_HIP(hipStreamSynchronize(st));  // bsum is freed on return
 }
 
 namespace {
@@ -525,7 +524,7 @@ void pad_identity(TileLevel& lv, hipStream_t st) {
 void alloc_csr(Csr& A, int64_t nrows) {
   A.nrows = nrows;
   A.ptr.alloc(nrows + 1);
-  NS_HIP(hipMemset(A.ptr.p, 0, (nrows + 1) * sizeof(int64_t)));
+  NS_HIP(hipMemsetAsync(A.ptr.p, 0, (nrows + 1) * sizeof(int64_t), alloc_stream()));
 }
 
 void finish_csr(Csr& A, hipStream_t st) {
@@ -551,7 +550,7 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
   DBuf<int> minmax;
   minmax.alloc(2);
   const int hm[2] = {INT32_MIN, INT32_MAX};
-  NS_HIP(hipMemcpy(minmax.p, hm, sizeof(hm), hipMemcpyHostToDevice));
+  upload(minmax.p, hm, sizeof(hm), st);
   const int gn = int((n + 255) / 256);
   k_validate<<<gn, 256, 0, st>>>(n, nnz, row_ptr, col, val, part, flags, minmax);
   NS_LAUNCH_CHECK();
@@ -640,13 +639,13 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
   }
   if (h.nI <= 0) fail(INVALID_ARG, "partition has no interior nodes");
   h.pnode.alloc(P + 1);
-  NS_HIP(hipMemcpy(h.pnode.p, pcs->node.data(), (P + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  upload(h.pnode.p, pcs->node.data(), (P + 1) * sizeof(int64_t), st);
   h.l2first.alloc(P + 1);
-  NS_HIP(hipMemcpy(h.l2first.p, pcs->l2.data(), (P + 1) * sizeof(int), hipMemcpyHostToDevice));
+  upload(h.l2first.p, pcs->l2.data(), (P + 1) * sizeof(int), st);
   if (P > 1) {
     DBuf<int64_t> goff;
     goff.alloc(P + 1);
-    NS_HIP(hipMemcpy(goff.p, h.h_goff.data(), (P + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+    upload(goff.p, h.h_goff.data(), (P + 1) * sizeof(int64_t), st);
     k_gidx_offset<<<gn, 256, 0, st>>>(n, part, h.pnode, P, goff, gidx);
     NS_LAUNCH_CHECK();
     NS_HIP(hipStreamSynchronize(st));
@@ -658,7 +657,7 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
   h.LJ.layout(h.nJ > 0 ? nJq : std::vector<int>{});
   DBuf<int64_t> coff1;
   coff1.alloc(h.nsub > 0 ? h.nsub : 1);
-  if (h.nsub) NS_HIP(hipMemcpy(coff1.p, coff.data(), h.nsub * sizeof(int64_t), hipMemcpyHostToDevice));
+  if (h.nsub) upload(coff1.p, coff.data(), h.nsub * sizeof(int64_t), st);
 
   // maps
   const int64_t nIpad = h.L1.nrows_pad, n2pad = h.L2.nrows_pad, nJpad = h.LJ.nrows_pad;

@@ -196,15 +196,14 @@ void tile_make_inverse(TileLevel& lv, bool fp32, hipStream_t st) {
   lv.inv_off.alloc(lv.nblk);
   lv.inv_lda.alloc(lv.nblk);
   lv.npad_d.alloc(lv.nblk);
-  NS_HIP(hipMemcpy(lv.inv_off.p, aoff.data(), lv.nblk * sizeof(int64_t), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(lv.inv_lda.p, lda.data(), lv.nblk * sizeof(int64_t), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(lv.npad_d.p, np.data(), lv.nblk * sizeof(int), hipMemcpyHostToDevice));
+  upload(lv.inv_off.p, aoff.data(), lv.nblk * sizeof(int64_t), st);
+  upload(lv.inv_lda.p, lda.data(), lv.nblk * sizeof(int64_t), st);
+  upload(lv.npad_d.p, np.data(), lv.nblk * sizeof(int), st);
   if (fp32) {
     lv.Ainv32.alloc(lv.Ainv64.n);
     k_to_fp32_g<<<2048, 256, 0, st>>>(lv.Ainv64, lv.Ainv32, lv.Ainv64.n);
     NS_LAUNCH_CHECK();
   }
-  NS_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace ns

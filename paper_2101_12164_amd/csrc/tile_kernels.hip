@@ -541,7 +541,7 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
   if (cw != 16 && cw != 32) cw = 64;
   const int nbp8 = (nblk + 7) / 8;
   const double bytes = (lv.alg_tri + 2.0 * lv.alg_rows * ncols) * sizeof(T);
-  const double flops = alg_flops > 0 ? alg_flops : lv.alg_sq * ncols;
+  const double flops = alg_flops >= 0 ? alg_flops : lv.alg_sq * ncols;
   KScope ks(lv.role == 0 ? (sizeof(T) == 8 ? KF_TRSM_I64 : KF_TRSM_I32) : (sizeof(T) == 8 ? KF_TRSM_G64 : KF_TRSM_G32),
             st, bytes, flops);
   const int nchunk_all = (ncols + cw - 1) / cw;
@@ -599,10 +599,10 @@ void TileLevel::layout(const std::vector<int>& sizes) {
   nb.alloc(nblk);
   ioff.alloc(nblk);
   roff.alloc(nblk);
-  NS_HIP(hipMemcpy(nt.p, h_nt.data(), nblk * sizeof(int), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(nb.p, h_nb.data(), nblk * sizeof(int), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(ioff.p, h_ioff.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(roff.p, h_roff.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice));
+  upload(nt.p, h_nt.data(), nblk * sizeof(int), alloc_stream());
+  upload(nb.p, h_nb.data(), nblk * sizeof(int), alloc_stream());
+  upload(ioff.p, h_ioff.data(), nblk * sizeof(int64_t), alloc_stream());
+  upload(roff.p, h_roff.data(), nblk * sizeof(int64_t), alloc_stream());
 }
 
 namespace {
@@ -693,8 +693,8 @@ void TileLevel::layout_band(const std::vector<int>& bw) {
   if (nblk == 0) return;
   nbt.alloc(nblk);
   foff.alloc(nblk);
-  NS_HIP(hipMemcpy(nbt.p, h_nbt.data(), nblk * sizeof(int), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(foff.p, h_foff.data(), nblk * sizeof(int64_t), hipMemcpyHostToDevice));
+  upload(nbt.p, h_nbt.data(), nblk * sizeof(int), alloc_stream());
+  upload(foff.p, h_foff.data(), nblk * sizeof(int64_t), alloc_stream());
   L64.alloc(f_elems);
   Linv64.alloc(i_elems);
 }

@@ -316,9 +316,9 @@ void SegBuf::build(const std::vector<int64_t>& offsets, hipStream_t st) {
   toff.alloc(n + 1);
   const int64_t rows = offsets[n];
   rseg.alloc(rows > 0 ? rows : 1);
-  NS_HIP(hipMemcpy(off.p, offsets.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(coff.p, co.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
-  NS_HIP(hipMemcpy(toff.p, to.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice));
+  upload(off.p, offsets.data(), (n + 1) * sizeof(int64_t), st);
+  upload(coff.p, co.data(), (n + 1) * sizeof(int), st);
+  upload(toff.p, to.data(), (n + 1) * sizeof(int), st);
   if (rows > 0 && n > 0) {
     dim3 g(unsigned((maxrows + 255) / 256), unsigned(n));
     k_build_seg<<<g, 256, 0, st>>>(n, off.p, toff.p, rseg.p);
