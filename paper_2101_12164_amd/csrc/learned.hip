@@ -318,6 +318,7 @@ struct ns_mlp_s {
   SegBuf seg;
   int64_t seg_rows = -1;
   DBuf<double> small, work, gs;
+  SmallWs gsw;
   DBuf<int> flag;
   DBuf<double> lossd;
   std::string last_error;
@@ -576,7 +577,7 @@ ns_status nystrom_schur_mlp_loss_grad(ns_mlp m, const float* X, const double* U,
     }
     if (!m->small.p) {
       m->small.alloc(size_t(k) * k * 5 + 8);
-      m->gs.alloc(small_scratch_elems());
+      m->gsw = small_ws(m->gs, 1, k, k);
       m->flag.alloc(1);
       m->lossd.alloc(1);
     }
@@ -590,7 +591,7 @@ ns_status nystrom_schur_mlp_loss_grad(ns_mlp m, const float* X, const double* U,
     NS_HIP(hipMemsetAsync(m->flag.p, 0, sizeof(int), st));
     gram<double, double>(sg, m->Z0.p, k, k, m->Z0.p, k, k, Gm, k * k, 1.0, 0.0, m->work, st);  // G = Z0^T Z0
     gram<double, double>(sg, m->Z0.p, k, k, U, k, k, Mm, k * k, 1.0, 0.0, m->work, st);        // M = Z0^T U
-    small_chol_solve(Batch{1, nullptr}, k, Gm, k * k, Mm, k, k * k, Xs, k, k * k, k, k, 1.0, m->flag, m->gs, st);
+    small_chol_solve(Batch{1, nullptr}, k, Gm, k * k, Mm, k, k * k, Xs, k, k * k, k, k, 1.0, m->flag, m->gsw, st);
     k_loss_mats<<<1, 256, 0, st>>>(k, Xs, Mm, P1, P2, dl);
     NS_LAUNCH_CHECK();
     // dZ = U P1 + Z0 P2

@@ -93,7 +93,8 @@ struct ns_handle_s {
   ns::DBuf<double> wsT64, wsB64, wsJ64, wsB64b, wsJ64b;  // interior rhs, level-2 rhs, junction rhs, outputs
   ns::DBuf<float> wsT32, wsB32, wsJ32, wsB32b, wsJ32b;
   ns::DBuf<double> red;    // reduction partials
-  ns::DBuf<double> small;  // small dense scratch (per problem)
+  ns::DBuf<double> small;  // small dense scratch (per problem), described by sws
+  ns::SmallWs sws;
   int64_t ws_cols = 0;     // column capacity of the workspaces
   int64_t wsT64_cols = 0, wsT32_cols = 0;  // column capacity of the interior workspaces
 

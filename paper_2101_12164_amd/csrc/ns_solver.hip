@@ -180,17 +180,17 @@ void orth(Handle& h, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int 
   gram<T, T>(sg, V, s, s, V, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
   k_dims<<<pb, 256, 0, st>>>(np, s, sm.active, nullptr, sm.dimA);
   NS_LAUNCH_CHECK();
-  small_cholqr(Batch{np, sm.dimA}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.small.p, st, drop2,
+  small_cholqr(Batch{np, sm.dimA}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.sws, st, drop2,
                sm.ok);
   k_svqb_mask<<<pb, 256, 0, st>>>(np, sm.active, sm.ok, sm.skip);
   NS_LAUNCH_CHECK();
-  small_svqb(np, s, sm.Gorth, ss, drop2, sm.Torth, ss, sm.svr, sm.skip, h.small.p, st);
+  small_svqb(np, s, sm.Gorth, ss, drop2, sm.Torth, ss, sm.svr, sm.skip, h.sws, st);
   k_orth_select<<<np, 256, 0, st>>>(np, s, sm.active, sm.ok, sm.svr, sm.Torth, sm.Rinv, sm.rank, it, sm.itp,
                                     sm.ctr);
   NS_LAUNCH_CHECK();
   ts_update<T>(sg, s, P, s, 0.0, 1.0, V, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
   gram<T, T>(sg, P, s, s, P, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
-  small_cholqr(Batch{np, sm.rank}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.small.p, st);
+  small_cholqr(Batch{np, sm.rank}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.sws, st);
   ts_update<T>(sg, s, Q, s, 0.0, 1.0, P, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
   std::swap(P, Q);
 }
@@ -245,7 +245,7 @@ void block_pcg(Handle& h, SmallMats& sm, const double* Omega, double* D) {
       k_dims<<<pb, 256, 0, st>>>(np, s, sm.active, sm.rank, sm.dimA);
       NS_LAUNCH_CHECK();
       small_chol_solve(Batch{np, sm.dimA}, s, sm.Delta, ss, sm.G1, s, ss, sm.alpha, s, ss, s, s, 1.0, sm.flag,
-                       h.small.p, st);  // alpha
+                       h.sws, st);  // alpha
       ts_update<T>(sg, s, X.p, s, 1.0, 1.0, P, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
       ts_update<T>(sg, s, R.p, s, 1.0, -1.0, Q, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
       col_sumsq<T>(sg, s, R.p, s, sm.colsq, work, st);
@@ -260,7 +260,7 @@ void block_pcg(Handle& h, SmallMats& sm, const double* Omega, double* D) {
       gram<T, T>(sg, Q, s, s, Z.p, s, s, sm.G2, ss, 1.0, 0.0, work, st);       // Q^T Z
       k_dims<<<pb, 256, 0, st>>>(np, s, sm.active, sm.rank, sm.dimA);
       NS_LAUNCH_CHECK();
-      small_chol_apply(Batch{np, sm.dimA}, s, sm.Delta, ss, sm.G2, s, ss, sm.beta, s, ss, s, s, -1.0, h.small.p,
+      small_chol_apply(Batch{np, sm.dimA}, s, sm.Delta, ss, sm.G2, s, ss, sm.beta, s, ss, s, s, -1.0, h.sws,
                        st);  // beta
       ts_update<T>(sg, s, Z.p, s, 1.0, 1.0, P, s, s, sm.beta, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);  // Z + P beta
       orth<T>(h, sm, work, Z.p, P, Q, s, it);
@@ -303,12 +303,12 @@ void nystrom(Handle& h, SmallMats& sm, const double* Omega, double* Y) {
   for (int pass = 0; pass < 3; ++pass) {
     gram<double, double>(sg, A, s, s, A, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
     small_cholqr(Batch{np, nullptr}, s, sm.Gorth, ss, pass == 0 ? sm.coef : nullptr, sm.Rinv, sm.Racc, pass == 0,
-                 sm.flag + 2, h.small.p, st);
+                 sm.flag + 2, h.sws, st);
     ts_update<double>(sg, s, B, s, 0.0, 1.0, A, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
     std::swap(A, B);
   }
   // A now holds Q (orthonormal), sm.Racc holds R
-  small_nystrom(np, s, k, sm.C, sm.Racc, h.eig_rel, sm.Wk, sm.Ek, sm.nys, h.small.p, st);
+  small_nystrom(np, s, k, sm.C, sm.Racc, h.eig_rel, sm.Wk, sm.Ek, sm.nys, h.sws, st);
   std::vector<int> out(2 * np);
   read_back(h, out.data(), sm.nys, 2 * np);
   h.h_keff.resize(np);
@@ -359,7 +359,7 @@ bool judge_proposal(Handle& h) {
   csr_mult<double>(h.AGG, Zp.p, k, AZ.p, k, k, st);                     // A_Gamma Z
   gram<double, double>(sg, Zp.p, k, k, SZ.p, k, k, Ar, kk, 1.0, 0.0, work, st);
   gram<double, double>(sg, Zp.p, k, k, AZ.p, k, k, Br, kk, 1.0, 0.0, work, st);
-  small_gevd(k, Ar, Br, lam, C, Cl, flag, ws, h.small.p, st);
+  small_gevd(k, Ar, Br, lam, C, Cl, flag, ws, h.sws, st);
   ts_update<double>(sg, k, Y.p, k, 0.0, 1.0, Zp.p, k, k, C, k, 0, nullptr, 0, 0, nullptr, 0, 0, st);   // Y = Z C
   ts_update<double>(sg, k, R.p, k, 0.0, 1.0, SZ.p, k, k, C, k, 0, AZ.p, k, k, Cl, k, 0, st);           // S Y - A Y L
   col_sumsq<double>(sg, k, R.p, k, colsq.p, work, st);
@@ -407,7 +407,7 @@ void setup_adef2(Handle& h) {
   gram<double, double>(sg, h.Z.p, k, k, h.SZ.p, k, k, h.Echol.p, kk, 1.0, 0.0, work, st);
   NS_HIP(hipMemsetAsync(h.dflags.p + 12, 0, sizeof(int), st));
   small_chol_solve(Batch{np, h.keff_d}, k, h.Echol.p, kk, nullptr, 0, 0, nullptr, 0, 0, 0, 0, 1.0, h.dflags.p + 12,
-                   h.small.p, st);
+                   h.sws, st);
   int fl = 0;
   read_back(h, &fl, h.dflags.p + 12, 1);
   if (fl) fail(BREAKDOWN, "Z^T S Z is not positive definite");
@@ -416,7 +416,7 @@ void setup_adef2(Handle& h) {
 // z = M r for ncols vectors (FP64, interface order, row-major), every problem with its own low-rank term.
 // c1, c2: k x ncols per problem.
 void apply_prec(Handle& h, const double* r, int64_t ldr, double* z, int64_t ldz, int ncols, double* work,
-                double* c1, double* c2) {
+                double* c1, double* c2, const SmallWs& ws) {
   hipStream_t st = h.stream;
   const Seg& sg = h.segG.view;
   const int k = h.k, np = h.nprob;
@@ -431,7 +431,7 @@ void apply_prec(Handle& h, const double* r, int64_t ldr, double* z, int64_t ldz,
     gram<double, double>(sg, h.Z.p, k, k, r, ldr, ncols, c1, cs, 1.0, 0.0, work, st);    // Z^T r
     gram<double, double>(sg, h.SZ.p, k, k, z, ldz, ncols, c1, cs, -1.0, 1.0, work, st);  // - (SZ)^T t
     small_chol_apply(Batch{np, h.keff_d}, k, h.Echol.p, int64_t(k) * k, c1, ncols, cs, c2, ncols, cs, ncols, k, 1.0,
-                     h.small.p, st);  // E^{-1} (...)
+                     ws, st);  // E^{-1} (...)
     ts_update<double>(sg, ncols, z, ldz, 1.0, 1.0, h.Z.p, k, k, c2, ncols, cs, nullptr, 0, 0, nullptr, 0, 0, st);
   }
 }
@@ -500,7 +500,7 @@ void pcg_core(Handle& h, const double* b, double* x, double rtol, int maxit, std
     const int kk = h.k;
     gram<double, double>(sg, h.Z.p, kk, kk, f.p, 1, 1, c1.p, kk, 1.0, 0.0, work, st);
     small_chol_apply(Batch{np, h.keff_d}, kk, h.Echol.p, int64_t(kk) * kk, c1.p, 1, kk, c2.p, 1, kk, 1, kk, 1.0,
-                     h.small.p, st);
+                     h.sws, st);
     ts_update<double>(sg, 1, w.p, 1, 0.0, 1.0, h.Z.p, kk, kk, c2.p, 1, kk, nullptr, 0, 0, nullptr, 0, 0, st);
     op_schur<double>(h, w.p, 1, q.p, 1, 1, false);
     axpby(nG, 1.0, f.p, -1.0, q.p, st);
@@ -518,13 +518,13 @@ void pcg_core(Handle& h, const double* b, double* x, double rtol, int maxit, std
     pcg_update_wr(sg, S, w.p, r.p, p.p, q.p, work, s);  // w, r, ||r||, stopping test
   };
   auto tail = [&](hipStream_t s) {
-    apply_prec(h, r.p, 1, z.p, 1, 1, work, c1, c2);        // z = M r
+    apply_prec(h, r.p, 1, z.p, 1, 1, work, c1, c2, h.sws);        // z = M r
     dot(sg, r.p, z.p, psd.p + PS_RHO_NEW, PS, work, s);  // rho_{j+1}
     pcg_update_p(sg, S, z.p, p.p, s);
     pcg_advance(np, S, s);
   };
   if (hc[0] < np && maxit > 0) {
-    apply_prec(h, r.p, 1, z.p, 1, 1, work, c1, c2);
+    apply_prec(h, r.p, 1, z.p, 1, 1, work, c1, c2, h.sws);
     dot(sg, r.p, z.p, psd.p + PS_RHO, PS, work, st);  // rho_0
     NS_HIP(hipMemcpyAsync(p.p, z.p, nG * sizeof(double), hipMemcpyDeviceToDevice, st));
     int m = h.pcg_graph == 0 ? (np > 1 ? 4 : 1) : h.pcg_graph;
@@ -662,7 +662,7 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
     if (h->s > h->h_goff[q + 1] - h->h_goff[q]) fail(INVALID_ARG, "k + p exceeds the interface size n_gamma");
   h->segG.build(h->h_goff, h->stream);
   h->segN.build(h->h_noff, h->stream);
-  h->small.alloc(small_scratch_elems() * h->nprob);
+  h->sws = small_ws(h->small, h->nprob, h->s, h->s);
   ev.rec(1);
   tile_cholesky(h->L1, h->dflags.p + CHOL_FLAGS, h->stream);
   if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_build(*h);
@@ -925,7 +925,9 @@ ns_status nystrom_schur_apply(ns_handle h, const double* r_gamma, double* z_gamm
     work.alloc(gram_work_elems(h->segG.view, std::max(h->k, ncols)));
     c1.alloc(size_t(std::max(h->k, 1)) * ncols * h->nprob);
     c2.alloc(size_t(std::max(h->k, 1)) * ncols * h->nprob);
-    apply_prec(*h, r_gamma, ncols, z_gamma, ncols, ncols, work, c1, c2);
+    DBuf<double> gs;
+    const SmallWs ws = small_ws(gs, h->nprob, std::max(h->s, 1), ncols);
+    apply_prec(*h, r_gamma, ncols, z_gamma, ncols, ncols, work, c1, c2, ws);
     NS_HIP(hipStreamSynchronize(h->stream));
     return NS_OK;
   } catch (const Error& e) {

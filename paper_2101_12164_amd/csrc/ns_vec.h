@@ -94,45 +94,57 @@ void pcg_init_check(int nseg, const PcgState& s, hipStream_t st);
 // ---------------------------------------------------------------- small dense (one workgroup per problem)
 // Problem b (0 <= b < nb) of a batch uses the matrices at base + b * stride (row-major FP64, device) and
 // dimension dim[b] (dims == nullptr: the uniform value r); a problem of dimension 0 gets zero outputs.
-// gw: global scratch of small_scratch_elems() doubles per problem, used when a matrix does not fit in LDS.
 struct Batch {
   int nb = 1;
   const int* dims = nullptr;
 };
+// Global scratch for launches whose matrices do not fit in LDS: `stride` doubles per problem, valid for
+// dimensions <= n and column counts <= c; p == nullptr when every such launch fits in LDS.  A launch that
+// needs more than the scratch provides fails with INVALID_ARG.
+struct SmallWs {
+  double* p = nullptr;
+  int64_t stride = 0;
+  int n = 0, c = 0;
+};
+// doubles per problem for dimensions <= n and column counts <= c (0 when everything fits in LDS)
+size_t small_scratch_elems(int n, int c);
+// a scratch for nb problems (buf is allocated only when needed)
+SmallWs small_ws(DBuf<double>& buf, int nb, int n, int c);
 
 // L (in place of D, lower) = chol(D) for an r x r SPD D; X = alpha * D^{-1} B (B: r x s, ld ldb; X ld ldx).
-// Rows r..s0-1 of X are set to zero (s0 = rows of the stacked X, pass r when unused).
+// Rows r..s0-1 of X are set to zero (s0 = rows of the stacked X, pass r when unused).  s = 0: factor only.
 // flag[0] is set to 1 when some D is not numerically SPD.
 void small_chol_solve(Batch bt, int r, double* D, int64_t sD, const double* B, int64_t ldb, int64_t sB, double* X,
-                      int64_t ldx, int64_t sX, int s, int s0, double alpha, int* flag, double* gw, hipStream_t st);
+                      int64_t ldx, int64_t sX, int s, int s0, double alpha, int* flag, const SmallWs& ws,
+                      hipStream_t st);
 // X = alpha * (L L^T)^{-1} B with L from small_chol_solve.
 void small_chol_apply(Batch bt, int r, const double* L, int64_t sL, const double* B, int64_t ldb, int64_t sB,
-                      double* X, int64_t ldx, int64_t sX, int s, int s0, double alpha, double* gw, hipStream_t st);
+                      double* X, int64_t ldx, int64_t sX, int s, int s0, double alpha, const SmallWs& ws,
+                      hipStream_t st);
 // Orthonormalising transform of a block with Gram matrix G (s x s): T[:, c] = u_c / sqrt(lambda_c)
 // for the eigenpairs with lambda_c > drop2 * lambda_max, descending, zero columns after them;
 // out[b] = number kept.  Problems with skip[b] != 0 are left untouched.
 void small_svqb(int nb, int s, const double* G, int64_t sG, double drop2, double* T, int64_t sT, int* out,
-                const int* skip, double* gw, hipStream_t st);
+                const int* skip, const SmallWs& ws, hipStream_t st);
 // R = chol(G + shift_b * trace(G) * I)^T (upper) on the leading dim_b block (zero elsewhere);
 // Rinv = R^{-1}; Racc <- R * Racc (or R when init).  shift_b = shift[b] when shift != nullptr.
 // With ok != nullptr: ok[b] = 1 when the Cholesky succeeded and 1/||R^{-1}||_F^2 > certify * trace(G),
 // which proves lambda_min(G) / lambda_max(G) > certify (no direction falls below that ratio).
 void small_cholqr(Batch bt, int s, const double* G, int64_t sG, const double* shift, double* Rinv, double* Racc,
-                  int init, int* flag, double* gw, hipStream_t st, double certify = 0.0, int* ok = nullptr);
+                  int init, int* flag, const SmallWs& ws, hipStream_t st, double certify = 0.0, int* ok = nullptr);
 // Nystrom core: EVD of sym(C), keep eigenvalues >= eps_rel * max; T = (R V1) D1^{-1} (R V1)^T;
 // EVD of T descending; Wk = first k' eigenvectors (s x k, ld k), Ek = eigenvalues; out[2b..] = {r, k'}.
+// (A Cholesky of C that certifies every eigenvalue above the threshold replaces the first EVD.)
 void small_nystrom(int nb, int s, int k, const double* C, const double* R, double eps_rel, double* Wk, double* Ek,
-                   int* out, double* gw, hipStream_t st);
+                   int* out, const SmallWs& ws, hipStream_t st);
 // c_b[i, j] *= sigma_b[i] for i < k, j < ncols (ld ldc; c_b = c + b * sc, sigma_b = sigma + b * ssig)
 void small_rowscale(int nb, int k, int ncols, const double* sigma, int64_t ssig, double* c, int64_t ldc, int64_t sc,
                     hipStream_t st);
 // Symmetric EVD (descending) of an m x m matrix: W (m x m) eigenvectors in columns, E eigenvalues.
-void small_sym_evd(int m, const double* A, double* W, double* E, double* gw, hipStream_t st);
+void small_sym_evd(int m, const double* A, double* W, double* E, const SmallWs& ws, hipStream_t st);
 // Generalised symmetric EVD A c = lambda B c (B SPD), ascending: lam (k), C (k x k, C^T B C = I),
-// Cl = -C diag(lam); ws: 4 k^2 + k doubles; flag[0] = 1 when B is not numerically SPD.
+// Cl = -C diag(lambda); ws: 4 k^2 + k doubles; flag[0] = 1 when B is not numerically SPD.
 void small_gevd(int k, const double* A, const double* B, double* lam, double* C, double* Cl, int* flag, double* ws,
-                double* gw, hipStream_t st);
-// scratch (doubles per problem) the small kernels need in global memory when s is large
-size_t small_scratch_elems();
+                const SmallWs& sw, hipStream_t st);
 
 }  // namespace ns

@@ -14,10 +14,16 @@ namespace {
 constexpr int NT = 1024;                  // threads per workgroup
 constexpr size_t LDS_LIMIT = 136 * 1024;  // dynamic LDS used when the matrices fit
 constexpr int SMAX = 256;                 // largest s supported by the small kernels
-// global scratch per problem: two SMAX x (SMAX + 1) matrices or the Cholesky-solve layout
-constexpr size_t scratch_evd = size_t(2) * SMAX * (SMAX + 1);
-constexpr size_t scratch_cs = size_t(SMAX) * (SMAX + 1) + size_t(SMAX) * (4 * SMAX + 1);
-constexpr size_t small_scratch_per_problem = scratch_evd > scratch_cs ? scratch_evd : scratch_cs;
+constexpr int NB = 16;                    // block size of the blocked factorisations and solves
+constexpr int NBL = NB + 1;               // row stride of a diagonal-block inverse
+
+// Workspace (doubles) of the blocked Cholesky kernels: factor L (r x (r+1)), right-hand sides / inverse
+// X (r x (c+1)), diagonal-block inverses, panel buffer (r x NBL) and block-row buffer (NB x (c+1)).
+__host__ __device__ inline size_t chol_ws(int r, int c) {
+  const size_t nbk = size_t((r + NB - 1) / NB);
+  return size_t(r) * (r + 1) + size_t(r) * (c + 1) + nbk * NB * NBL + size_t(r) * NBL + size_t(NB) * (c + 1);
+}
+__host__ __device__ inline size_t evd_elems(int n) { return size_t(2) * n * (n + 1); }
 
 __device__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
@@ -183,16 +189,228 @@ __device__ void chol_solve_inplace(const double* L, int r, int ldl, double* X, i
   }
 }
 
-// Dynamic LDS layout of the Cholesky-solve kernels: L (r x (r+1)) and X (r x (s+1)).
-__host__ __device__ inline size_t cs_lds(int r, int s) {
-  return (size_t(r) * (r + 1) + size_t(r) * (s + 1)) * sizeof(double);
+// ---------------------------------------------------------------- blocked Cholesky toolkit
+// Right-looking Cholesky in NB-wide block columns: one wave factors the diagonal block in registers (lane i
+// holds row i, pivots and columns broadcast with readlane, no workgroup barrier) and inverts it; the panel
+// below is L21 = A21 L11^{-T} through that inverse; the trailing lower triangle is updated by every thread.
+// Three workgroup barriers per block column instead of two per column.
+
+__device__ __forceinline__ double lane_of(double v, int lane) {  // v of `lane` (lane uniform)
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
 }
 
-// Problem b: D (r0 x r0, ld r0) at D + b sD, leading rb = dims[b] block used; B, X likewise.
+// Wave-level: factor the jb x jb block at A[j0][j0] (stride ld) in place (lower) and write its inverse to
+// Di (NB x NB, stride NBL; lower, zero above).  Returns 0 or the 1-based column of the first pivot <= 0
+// (taken as 1).  Called by all 64 lanes of one wave.
+__device__ int diag_factor_wave(double* A, int ld, int j0, int jb, double* Di) {
+  const int lane = threadIdx.x & 63;
+  double r[NB];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) r[t] = (lane < jb && t <= lane) ? A[(j0 + lane) * ld + j0 + t] : 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c < jb) {
+      double d = lane_of(r[c], c);
+      if (!(d > 0.0)) {
+        if (!bad) bad = c + 1;
+        d = 1.0;
+      }
+      const double sq = sqrt(d), inv = 1.0 / sq;
+      r[c] = lane == c ? sq : (lane > c ? r[c] * inv : 0.0);
+#pragma unroll
+      for (int q = c + 1; q < NB; ++q) {
+        const double lqc = lane_of(r[c], q);  // L[q][c]
+        if (q < jb && lane >= q) r[q] -= r[c] * lqc;
+      }
+    }
+  }
+  // column `lane` of L^{-1} by forward substitution (lanes >= jb compute nothing useful)
+  double x[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    double acc = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+    for (int t = 0; t < i; ++t) acc -= lane_of(r[t], i) * x[t];
+    x[i] = (i < jb) ? acc / lane_of(r[i], i) : 0.0;
+  }
+  if (lane < jb) {
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+      if (t <= lane) A[(j0 + lane) * ld + j0 + t] = r[t];
+  }
+  if (lane < NB) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Di[i * NBL + lane] = (lane < jb && i < jb) ? x[i] : 0.0;
+  }
+  return bad;
+}
+
+// In-place lower Cholesky of A (n x n, stride ld).  Dinv: ceil(n/NB) diagonal-block inverses (NB x NBL
+// each), Pn: n x NBL panel scratch.  Returns 0 or the 1-based index of the first pivot <= 0.
+__device__ int chol_blocked(double* A, int n, int ld, double* Dinv, double* Pn, int* sinfo) {
+  const int wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) *sinfo = 0;
+  __syncthreads();
+  for (int j0 = 0; j0 < n; j0 += NB) {
+    const int jb = n - j0 < NB ? n - j0 : NB;
+    const double* Di = Dinv + (j0 / NB) * (NB * NBL);
+    if (wave == 0) {
+      const int bad = diag_factor_wave(A, ld, j0, jb, Dinv + (j0 / NB) * (NB * NBL));
+      if (bad && (threadIdx.x & 63) == 0 && *sinfo == 0) *sinfo = j0 + bad;
+    }
+    __syncthreads();
+    const int j1 = j0 + jb, m = n - j1;
+    for (int e = threadIdx.x; e < m * jb; e += NT) {  // Pn = A21 L11^{-T}
+      const int i = e / jb, c = e - i * jb;
+      const double* a = A + (j1 + i) * ld + j0;
+      double acc = 0.0;
+      for (int t = 0; t <= c; ++t) acc += a[t] * Di[c * NBL + t];
+      Pn[i * NBL + c] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * m; e += NT) {  // A22 -= L21 L21^T (lower)
+      const int i = e / m, q = e - i * m;
+      if (q > i) continue;
+      double acc = A[(j1 + i) * ld + j1 + q];
+      for (int t = 0; t < jb; ++t) acc -= Pn[i * NBL + t] * Pn[q * NBL + t];
+      A[(j1 + i) * ld + j1 + q] = acc;
+    }
+    for (int e = threadIdx.x; e < m * jb; e += NT) {
+      const int i = e / jb, c = e - i * jb;
+      A[(j1 + i) * ld + j0 + c] = Pn[i * NBL + c];
+    }
+    __syncthreads();
+  }
+  const int info = *sinfo;
+  __syncthreads();
+  return info;
+}
+
+// Diagonal-block inverses of an existing factor L (n x n, stride ld): one wave per block.
+__device__ void diag_inverses(const double* L, int n, int ld, double* Dinv) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nbk = (n + NB - 1) / NB;
+  for (int bk = wave; bk < nbk; bk += NT / 64) {
+    const int j0 = bk * NB, jb = n - j0 < NB ? n - j0 : NB;
+    double x[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int ii = i < jb ? i : jb - 1;  // clamped: rows past the block are never read
+      double acc = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+      for (int t = 0; t < i; ++t) acc -= L[(j0 + ii) * ld + j0 + (t < ii ? t : ii)] * x[t];
+      x[i] = (i < jb) ? acc / L[(j0 + ii) * ld + j0 + ii] : 0.0;
+    }
+    if (lane < NB) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) Dinv[bk * (NB * NBL) + i * NBL + lane] = (lane < jb && i < jb) ? x[i] : 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+// X (r x c, stride lx) <- (L L^T)^{-1} X by block rows: forward L Y = X, then backward L^T X = Y.
+// Tb: NB x (c + 1) scratch.
+__device__ void chol_solve_blocked(const double* L, int r, int ld, const double* Dinv, double* X, int lx, int c,
+                                   double* Tb) {
+  const int nbk = (r + NB - 1) / NB, lt = c + 1;
+  for (int bk = 0; bk < nbk; ++bk) {
+    const int i0 = bk * NB, ib = r - i0 < NB ? r - i0 : NB;
+    const double* Di = Dinv + bk * (NB * NBL);
+    for (int e = threadIdx.x; e < ib * c; e += NT) {  // Tb = X_i - L_{i,<i} Y_{<i}
+      const int a = e / c, j = e - a * c;
+      const double* l = L + (i0 + a) * ld;
+      double acc = X[(i0 + a) * lx + j];
+      for (int t = 0; t < i0; ++t) acc -= l[t] * X[t * lx + j];
+      Tb[a * lt + j] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ib * c; e += NT) {  // Y_i = L_ii^{-1} Tb
+      const int a = e / c, j = e - a * c;
+      double acc = 0.0;
+      for (int t = 0; t <= a; ++t) acc += Di[a * NBL + t] * Tb[t * lt + j];
+      X[(i0 + a) * lx + j] = acc;
+    }
+    __syncthreads();
+  }
+  for (int bk = nbk - 1; bk >= 0; --bk) {
+    const int i0 = bk * NB, ib = r - i0 < NB ? r - i0 : NB;
+    const double* Di = Dinv + bk * (NB * NBL);
+    for (int e = threadIdx.x; e < ib * c; e += NT) {  // Tb = Y_i - L_{>i,i}^T X_{>i}
+      const int a = e / c, j = e - a * c;
+      double acc = X[(i0 + a) * lx + j];
+      for (int t = i0 + ib; t < r; ++t) acc -= L[t * ld + i0 + a] * X[t * lx + j];
+      Tb[a * lt + j] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ib * c; e += NT) {  // X_i = L_ii^{-T} Tb
+      const int a = e / c, j = e - a * c;
+      double acc = 0.0;
+      for (int t = a; t < ib; ++t) acc += Di[t * NBL + a] * Tb[t * lt + j];
+      X[(i0 + a) * lx + j] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// X = L^{-1} (n x n, stride ld, zero above the diagonal) from the factor and its diagonal-block inverses,
+// by block rows: X_ij = -L_ii^{-1} sum_{j <= t < i} L_it X_tj.  Tb: NB x (n + 1) scratch.
+__device__ void tri_inverse_blocked(const double* L, int n, int ld, const double* Dinv, double* X, double* Tb) {
+  const int lt = n + 1;
+  for (int e = threadIdx.x; e < n * n; e += NT) {
+    const int i = e / n, j = e - i * n;
+    const int bi = i / NB, bj = j / NB;
+    X[i * ld + j] = (bi == bj && j <= i) ? Dinv[bi * (NB * NBL) + (i - bi * NB) * NBL + (j - bj * NB)] : 0.0;
+  }
+  __syncthreads();
+  const int nbk = (n + NB - 1) / NB;
+  for (int bk = 1; bk < nbk; ++bk) {
+    const int i0 = bk * NB, ib = n - i0 < NB ? n - i0 : NB;
+    const double* Di = Dinv + bk * (NB * NBL);
+    for (int e = threadIdx.x; e < ib * i0; e += NT) {  // Tb[a][j] = sum_{j <= t < i0} L[i0+a][t] X[t][j]
+      const int a = e / i0, j = e - a * i0;
+      const double* l = L + (i0 + a) * ld;
+      double acc = 0.0;
+      for (int t = j; t < i0; ++t) acc += l[t] * X[t * ld + j];
+      Tb[a * lt + j] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ib * i0; e += NT) {
+      const int a = e / i0, j = e - a * i0;
+      double acc = 0.0;
+      for (int t = 0; t <= a; ++t) acc += Di[a * NBL + t] * Tb[t * lt + j];
+      X[(i0 + a) * ld + j] = -acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Carve of a chol_ws(r, c) workspace.
+struct CholWs {
+  double *L, *X, *Dinv, *Pn, *Tb;
+  int ldl, ldx;
+};
+__device__ CholWs chol_carve(double* base, int r, int c) {
+  CholWs w;
+  w.ldl = r + 1;
+  w.ldx = c + 1;
+  w.L = base;
+  w.X = w.L + size_t(r) * w.ldl;
+  w.Dinv = w.X + size_t(r) * w.ldx;
+  w.Pn = w.Dinv + size_t((r + NB - 1) / NB) * NB * NBL;
+  w.Tb = w.Pn + size_t(r) * NBL;
+  return w;
+}
+
+// Problem b: D (r0 x r0, ld r0) at D + b sD, leading rb = dims[b] block used; B, X likewise.  factor: D is
+// factored (L written back); otherwise D holds the factor from an earlier call.
 __global__ __launch_bounds__(NT) void k_small_chol_solve(int r0, const int* __restrict__ dims, double* D, int64_t sD,
                                                          const double* B, int64_t ldb, int64_t sB, double* X,
                                                          int64_t ldx, int64_t sX, int s, int s0, double alpha,
-                                                         int* flag, int factor, double* gw) {
+                                                         int* flag, int factor, double* gw, int64_t gws, int lds) {
   extern __shared__ double sm[];
   __shared__ int sinfo;
   const int b = blockIdx.x;
@@ -200,25 +418,23 @@ __global__ __launch_bounds__(NT) void k_small_chol_solve(int r0, const int* __re
   D += b * sD;
   B += b * sB;
   X += b * sX;
-  gw += b * int64_t(small_scratch_per_problem);
   // rows r .. s0 - 1 of X are zero (directions this problem does not have)
   for (int e = threadIdx.x; e < (s0 - r) * s; e += NT) X[(r + e / s) * ldx + e % s] = 0.0;
   if (r == 0) return;
-  const bool lds = cs_lds(r0, s) <= LDS_LIMIT;  // the launch's dynamic LDS is sized for r0 >= r
-  double* Ls = lds ? sm : gw;
-  const int ldl = r + 1, lx = s + 1;
-  double* Xs = Ls + size_t(r) * ldl;
-  for (int e = threadIdx.x; e < r * r; e += NT) Ls[(e / r) * ldl + e % r] = D[(e / r) * r0 + e % r];
-  for (int e = threadIdx.x; e < r * s; e += NT) Xs[(e / s) * lx + e % s] = B[(e / s) * ldb + e % s];
+  CholWs w = chol_carve(lds ? sm : gw + b * gws, r, s);
+  for (int e = threadIdx.x; e < r * r; e += NT) w.L[(e / r) * w.ldl + e % r] = D[(e / r) * r0 + e % r];
+  for (int e = threadIdx.x; e < r * s; e += NT) w.X[(e / s) * w.ldx + e % s] = B[(e / s) * ldb + e % s];
   __syncthreads();
   if (factor) {
-    const int info = chol_dev(Ls, r, ldl, &sinfo);
+    const int info = chol_blocked(w.L, r, w.ldl, w.Dinv, w.Pn, &sinfo);
     if (info && threadIdx.x == 0) flag[0] = 1;
-    for (int e = threadIdx.x; e < r * r; e += NT) D[(e / r) * r0 + e % r] = Ls[(e / r) * ldl + e % r];
-    __syncthreads();
+    for (int e = threadIdx.x; e < r * r; e += NT) D[(e / r) * r0 + e % r] = w.L[(e / r) * w.ldl + e % r];
+  } else {
+    diag_inverses(w.L, r, w.ldl, w.Dinv);
   }
-  chol_solve_inplace(Ls, r, ldl, Xs, lx, s);
-  for (int e = threadIdx.x; e < r * s; e += NT) X[(e / s) * ldx + e % s] = alpha * Xs[(e / s) * lx + e % s];
+  if (s == 0) return;
+  chol_solve_blocked(w.L, r, w.ldl, w.Dinv, w.X, w.ldx, s, w.Tb);
+  for (int e = threadIdx.x; e < r * s; e += NT) X[(e / s) * ldx + e % s] = alpha * w.X[(e / s) * w.ldx + e % s];
 }
 
 // Workspace for the Jacobi kernels: two n x (n+1) matrices + small arrays, in
@@ -229,12 +445,8 @@ struct EvdSpace {
   int ld;
 };
 
-__host__ __device__ inline size_t evd_bytes(int n) { return size_t(2) * n * (n + 1) * sizeof(double); }
-
-__device__ EvdSpace evd_space(int n, double* sm, double* gw, double* small_d, int* small_i) {
+__device__ EvdSpace evd_space(int n, double* base, double* small_d, int* small_i) {
   EvdSpace e;
-  const bool lds = evd_bytes(n) <= LDS_LIMIT;
-  double* base = lds ? sm : gw;
   e.ld = n + 1;
   e.A = base;
   e.V = base + size_t(n) * e.ld;
@@ -246,7 +458,8 @@ __device__ EvdSpace evd_space(int n, double* sm, double* gw, double* small_d, in
 }
 
 __global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, int64_t sG, double drop2, double* T,
-                                                   int64_t sT, int* out, const int* skip, double* gw) {
+                                                   int64_t sT, int* out, const int* skip, double* gw, int64_t gws,
+                                                   int lds) {
   extern __shared__ double sm[];
   __shared__ double red[NT];
   __shared__ double sd[3 * SMAX];
@@ -255,8 +468,7 @@ __global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, int64
   if (skip && skip[b]) return;
   G += b * sG;
   T += b * sT;
-  gw += b * int64_t(small_scratch_per_problem);
-  EvdSpace w = evd_space(s, sm, gw, sd, si);
+  EvdSpace w = evd_space(s, lds ? sm : gw + b * gws, sd, si);
   const int ld = w.ld;
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
@@ -287,7 +499,8 @@ __global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, int64
 // Racc is zero.
 __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restrict__ dims, const double* G, int64_t sG,
                                                      const double* shift_coef, double* Rinv, double* Racc, int init,
-                                                     int* flag, double* gw, double certify, int* ok) {
+                                                     int* flag, double* gw, int64_t gws, int lds, double certify,
+                                                     int* ok) {
   extern __shared__ double sm[];
   __shared__ int sinfo;
   __shared__ double sshift, strace;
@@ -297,7 +510,6 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
   G += b * sG;
   Rinv += b * int64_t(s) * s;
   Racc += b * int64_t(s) * s;
-  gw += b * int64_t(small_scratch_per_problem);
   if (n == 0) {
     for (int e = threadIdx.x; e < s * s; e += NT) Rinv[e] = Racc[e] = 0.0;
     if (ok && threadIdx.x == 0) ok[b] = 0;
@@ -311,29 +523,17 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
   }
   __syncthreads();
   const double shift = sshift;
-  const bool lds = evd_bytes(s) <= LDS_LIMIT;  // the launch's dynamic LDS is sized for s >= n
-  const int ld = n + 1;
-  double* A = lds ? sm : gw;
-  double* X = A + size_t(n) * ld;
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  CholWs w = chol_carve(lds ? sm : gw + b * gws, n, n);
+  const int ld = w.ldl;
+  double* A = w.L;
+  double* X = w.X;
   for (int e = threadIdx.x; e < n * n; e += NT) {
     const int i = e / n, j = e % n;
     A[i * ld + j] = 0.5 * (G[i * s + j] + G[j * s + i]) + (i == j ? shift : 0.0);
-    X[i * ld + j] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (chol_dev(A, n, ld, &sinfo) && threadIdx.x == 0) flag[0] = 1;
-  // X = L^{-1}: forward sweep on the identity (row m scaled, then the rows below updated)
-  for (int m = 0; m < n; ++m) {
-    const double inv = 1.0 / A[m * ld + m];
-    for (int j = threadIdx.x; j <= m; j += NT) X[m * ld + j] *= inv;
-    __syncthreads();
-    for (int i = m + 1 + ty; i < n; i += 32) {
-      const double l = A[i * ld + m];
-      for (int j = tx; j <= m; j += 32) X[i * ld + j] -= l * X[m * ld + j];
-    }
-    __syncthreads();
-  }
+  if (chol_blocked(A, n, ld, w.Dinv, w.Pn, &sinfo) && threadIdx.x == 0) flag[0] = 1;
+  tri_inverse_blocked(A, n, ld, w.Dinv, X, w.Tb);  // X = L^{-1}
   // Rinv = (L^{-1})^T (upper) in the leading block, zero elsewhere; R = L^T
   double fro = 0.0;
   for (int e = threadIdx.x; e < s * s; e += NT) {
@@ -349,83 +549,135 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
     if (threadIdx.x == 0) ok[b] = (sinfo == 0 && 1.0 / f > certify * strace) ? 1 : 0;
   }
   __syncthreads();
-  // Racc <- R * Racc ; X reused for the product
+  if (init) {
+    for (int e = threadIdx.x; e < s * s; e += NT) {
+      const int i = e / s, j = e % s;
+      Racc[e] = (i < n && j < n && j >= i) ? A[j * ld + i] : 0.0;
+    }
+    return;
+  }
+  // Racc <- R * Racc, with Racc staged in X
   for (int e = threadIdx.x; e < n * n; e += NT) {
     const int i = e / n, j = e % n;
-    double acc = 0.0;
-    if (init) {
-      acc = j >= i ? A[j * ld + i] : 0.0;
-    } else {
-      for (int m = i; m <= j; ++m) acc += A[m * ld + i] * Racc[m * s + j];
-    }
-    X[i * ld + j] = acc;
+    X[i * ld + j] = Racc[i * s + j];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
-    Racc[e] = (i < n && j < n) ? X[i * ld + j] : 0.0;
+    double acc = 0.0;
+    if (i < n && j < n)
+      for (int m = i; m <= j; ++m) acc += A[m * ld + i] * X[m * ld + j];
+    Racc[e] = acc;
   }
 }
 
+// Nystrom core of one problem.  C = Omega^T Y (s x s) and the Cholesky-QR factor R of Y give
+// T = R C_1^+ R^T over the eigenpairs of sym(C) with lambda >= eps_rel lambda_max, whose EVD yields the
+// basis.  When a Cholesky C = L L^T succeeds with 1/||L^{-1}||_F^2 >= eps_rel trace(C) (a lower bound of
+// lambda_min against an upper bound of lambda_max), every eigenpair passes the threshold and
+// T = R C^{-1} R^T = F F^T with F = R L^{-T}: the EVD of C is skipped.
 __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double* C, const double* R, double eps_rel,
-                                                      double* Wk, double* Ek, int* out, double* gw) {
+                                                      double* Wk, double* Ek, int* out, double* gw, int64_t gws,
+                                                      int lds) {
   extern __shared__ double sm[];
   __shared__ double red[NT];
   __shared__ double sd[3 * SMAX];
   __shared__ int si[3 * SMAX];
   __shared__ double dkeep[SMAX];
   __shared__ int ikeep[SMAX];
-  __shared__ int nkeep;
+  __shared__ int nkeep, sinfo;
   const int b = blockIdx.x;
   C += b * int64_t(s) * s;
   R += b * int64_t(s) * s;
   Wk += b * int64_t(s) * k;
   Ek += b * int64_t(k);
   out += 2 * b;
-  gw += b * int64_t(small_scratch_per_problem);
-  EvdSpace w = evd_space(s, sm, gw, sd, si);
+  CholWs cw = chol_carve(lds ? sm : gw + b * gws, s, s);  // regions L and X double as the EVD's A and V
+  EvdSpace w = evd_space(s, cw.L, sd, si);
   const int ld = w.ld;
   for (int e = threadIdx.x; e < s * s; e += NT) {  // symmetrised C
     const int i = e / s, j = e % s;
     w.A[i * ld + j] = 0.5 * (C[i * s + j] + C[j * s + i]);
   }
-  __syncthreads();
-  jacobi(w.A, w.V, s, ld, w.cs, w.pr, red);
-  for (int i = threadIdx.x; i < s; i += NT) w.d[i] = w.A[i * ld + i];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double dmax = w.d[0];
-    for (int i = 1; i < s; ++i) dmax = w.d[i] > dmax ? w.d[i] : dmax;
-    int r = 0;
-    if (dmax > 0.0)
-      for (int i = 0; i < s; ++i)
-        if (w.d[i] >= eps_rel * dmax) {
-          ikeep[r] = i;
-          dkeep[r] = w.d[i];
-          ++r;
-        }
-    nkeep = r;
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < s; i += NT) tr += C[i * s + i];
+  tr = block_sum(tr, red);
+  const int info = chol_blocked(w.A, s, ld, cw.Dinv, cw.Pn, &sinfo);
+  bool certified = false;
+  if (info == 0) {
+    tri_inverse_blocked(w.A, s, ld, cw.Dinv, w.V, cw.Tb);  // V = L^{-1}
+    double fro = 0.0;
+    for (int e = threadIdx.x; e < s * s; e += NT) {
+      const double x = w.V[(e / s) * ld + e % s];
+      fro += x * x;
+    }
+    fro = block_sum(fro, red);
+    certified = tr > 0.0 && 1.0 / fro >= eps_rel * tr;
   }
-  __syncthreads();
-  const int r = nkeep;
-  // M = R V_1 (s x r) into A (stride ld >= r)
-  for (int e = threadIdx.x; e < s * r; e += NT) {
-    const int i = e / r, c = e % r;
-    double acc = 0.0;
-    for (int m = i; m < s; ++m) acc += R[i * s + m] * w.V[m * ld + ikeep[c]];
-    w.A[i * ld + c] = acc;
+  int r;
+  if (certified) {
+    r = s;
+    // F = R L^{-T} into A: F[i][j] = sum_{i <= m <= j} R[i][m] Linv[j][m]
+    for (int e = threadIdx.x; e < s * s; e += NT) {
+      const int i = e / s, j = e % s;
+      double acc = 0.0;
+      for (int m = i; m <= j; ++m) acc += R[i * s + m] * w.V[j * ld + m];
+      w.A[i * ld + j] = acc;
+    }
+    __syncthreads();
+    // T = F F^T into V
+    for (int e = threadIdx.x; e < s * s; e += NT) {
+      const int i = e / s, j = e % s;
+      if (j > i) continue;
+      double acc = 0.0;
+      for (int m = 0; m < s; ++m) acc += w.A[i * ld + m] * w.A[j * ld + m];
+      w.V[i * ld + j] = acc;
+      w.V[j * ld + i] = acc;
+    }
+    __syncthreads();
+  } else {
+    for (int e = threadIdx.x; e < s * s; e += NT) {  // symmetrised C again (the factorisation overwrote it)
+      const int i = e / s, j = e % s;
+      w.A[i * ld + j] = 0.5 * (C[i * s + j] + C[j * s + i]);
+    }
+    __syncthreads();
+    jacobi(w.A, w.V, s, ld, w.cs, w.pr, red);
+    for (int i = threadIdx.x; i < s; i += NT) w.d[i] = w.A[i * ld + i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double dmax = w.d[0];
+      for (int i = 1; i < s; ++i) dmax = w.d[i] > dmax ? w.d[i] : dmax;
+      int q = 0;
+      if (dmax > 0.0)
+        for (int i = 0; i < s; ++i)
+          if (w.d[i] >= eps_rel * dmax) {
+            ikeep[q] = i;
+            dkeep[q] = w.d[i];
+            ++q;
+          }
+      nkeep = q;
+    }
+    __syncthreads();
+    r = nkeep;
+    // M = R V_1 (s x r) into A (stride ld >= r)
+    for (int e = threadIdx.x; e < s * r; e += NT) {
+      const int i = e / r, c = e % r;
+      double acc = 0.0;
+      for (int m = i; m < s; ++m) acc += R[i * s + m] * w.V[m * ld + ikeep[c]];
+      w.A[i * ld + c] = acc;
+    }
+    __syncthreads();
+    // T = M D_1^{-1} M^T into V, symmetric by construction of the sum
+    for (int e = threadIdx.x; e < s * s; e += NT) {
+      const int i = e / s, j = e % s;
+      if (j > i) continue;
+      double acc = 0.0;
+      for (int c = 0; c < r; ++c) acc += w.A[i * ld + c] * w.A[j * ld + c] / dkeep[c];
+      w.V[i * ld + j] = acc;
+      w.V[j * ld + i] = acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // T = M D_1^{-1} M^T into V, symmetric by construction of the sum
-  for (int e = threadIdx.x; e < s * s; e += NT) {
-    const int i = e / s, j = e % s;
-    if (j > i) continue;
-    double acc = 0.0;
-    for (int c = 0; c < r; ++c) acc += w.A[i * ld + c] * w.A[j * ld + c] / dkeep[c];
-    w.V[i * ld + j] = acc;
-    w.V[j * ld + i] = acc;
-  }
-  __syncthreads();
   jacobi(w.V, w.A, s, ld, w.cs, w.pr, red);  // EVD of T: eigenvectors in A
   for (int i = threadIdx.x; i < s; i += NT) w.d[i] = w.V[i * ld + i];
   __syncthreads();
@@ -451,12 +703,13 @@ __global__ void k_small_rowscale(int k, int ncols, const double* sigma, int64_t 
   c[b * sc + i * ldc + j] *= sigma[b * ssig + i];
 }
 
-__global__ __launch_bounds__(NT) void k_small_sym_evd(int m, const double* Ain, double* W, double* E, double* gw) {
+__global__ __launch_bounds__(NT) void k_small_sym_evd(int m, const double* Ain, double* W, double* E, double* gw,
+                                                      int lds) {
   extern __shared__ double sm[];
   __shared__ double red[NT];
   __shared__ double sd[3 * SMAX];
   __shared__ int si[3 * SMAX];
-  EvdSpace w = evd_space(m, sm, gw, sd, si);
+  EvdSpace w = evd_space(m, lds ? sm : gw, sd, si);
   const int ld = w.ld;
   for (int e = threadIdx.x; e < m * m; e += NT) {
     const int i = e / m, j = e % m;
@@ -526,53 +779,84 @@ __global__ void k_gevd_back(int k, const double* Linv, const double* W, const do
   for (int j = threadIdx.x; j < k; j += blockDim.x) lam[j] = E[k - 1 - j];
 }
 
-size_t evd_lds(int n) {
-  const size_t b = evd_bytes(n);
-  return b <= LDS_LIMIT ? b : 0;
+// Where a launch's workspace lives: LDS when it fits, else the caller's global scratch (checked).
+int ws_mode(const SmallWs& ws, size_t elems, int r, int c) {
+  if (elems * sizeof(double) <= LDS_LIMIT) return 1;
+  if (!ws.p || r > ws.n || c > ws.c)
+    fail(INVALID_ARG, "small dense workspace missing or too small for " + std::to_string(r) + " x " +
+                          std::to_string(c));
+  return 0;
 }
+size_t dyn_lds(int mode, size_t elems) { return mode ? elems * sizeof(double) : 0; }
 
 }  // namespace
 
-size_t small_scratch_elems() { return small_scratch_per_problem; }
+size_t small_scratch_elems(int n, int c) {
+  const size_t e = std::max(chol_ws(n, std::max(n, c)), evd_elems(n));
+  return e * sizeof(double) <= LDS_LIMIT ? 0 : e;
+}
+
+SmallWs small_ws(DBuf<double>& buf, int nb, int n, int c) {
+  SmallWs w;
+  w.n = n;
+  w.c = c;
+  w.stride = int64_t(small_scratch_elems(n, c));
+  if (w.stride > 0) {
+    buf.alloc(size_t(w.stride) * std::max(nb, 1));
+    w.p = buf.p;
+  }
+  return w;
+}
 
 void small_chol_solve(Batch bt, int r, double* D, int64_t sD, const double* B, int64_t ldb, int64_t sB, double* X,
-                      int64_t ldx, int64_t sX, int s, int s0, double alpha, int* flag, double* gw, hipStream_t st) {
+                      int64_t ldx, int64_t sX, int s, int s0, double alpha, int* flag, const SmallWs& ws,
+                      hipStream_t st) {
   if (bt.nb <= 0 || (r <= 0 && s0 <= 0)) return;  // s == 0: factor only
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
-  const size_t lb = cs_lds(r, s);
-  k_small_chol_solve<<<bt.nb, NT, lb <= LDS_LIMIT ? lb : 0, st>>>(r, bt.dims, D, sD, B, ldb, sB, X, ldx, sX, s, s0,
-                                                                   alpha, flag, 1, gw);
+  const size_t el = chol_ws(r, s);
+  const int mode = ws_mode(ws, el, r, s);
+  k_small_chol_solve<<<bt.nb, NT, dyn_lds(mode, el), st>>>(r, bt.dims, D, sD, B, ldb, sB, X, ldx, sX, s, s0, alpha,
+                                                           flag, 1, ws.p, ws.stride, mode);
   NS_LAUNCH_CHECK();
 }
 
 void small_chol_apply(Batch bt, int r, const double* L, int64_t sL, const double* B, int64_t ldb, int64_t sB,
-                      double* X, int64_t ldx, int64_t sX, int s, int s0, double alpha, double* gw, hipStream_t st) {
+                      double* X, int64_t ldx, int64_t sX, int s, int s0, double alpha, const SmallWs& ws,
+                      hipStream_t st) {
   if (bt.nb <= 0 || (r <= 0 && s0 <= 0) || s <= 0) return;
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
-  const size_t lb = cs_lds(r, s);
-  k_small_chol_solve<<<bt.nb, NT, lb <= LDS_LIMIT ? lb : 0, st>>>(r, bt.dims, const_cast<double*>(L), sL, B, ldb, sB,
-                                                                   X, ldx, sX, s, s0, alpha, nullptr, 0, gw);
+  const size_t el = chol_ws(r, s);
+  const int mode = ws_mode(ws, el, r, s);
+  k_small_chol_solve<<<bt.nb, NT, dyn_lds(mode, el), st>>>(r, bt.dims, const_cast<double*>(L), sL, B, ldb, sB, X,
+                                                           ldx, sX, s, s0, alpha, nullptr, 0, ws.p, ws.stride, mode);
   NS_LAUNCH_CHECK();
 }
 
 void small_svqb(int nb, int s, const double* G, int64_t sG, double drop2, double* T, int64_t sT, int* out,
-                const int* skip, double* gw, hipStream_t st) {
+                const int* skip, const SmallWs& ws, hipStream_t st) {
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
-  k_small_svqb<<<nb, NT, evd_lds(s), st>>>(s, G, sG, drop2, T, sT, out, skip, gw);
+  const size_t el = evd_elems(s);
+  const int mode = ws_mode(ws, el, s, s);
+  k_small_svqb<<<nb, NT, dyn_lds(mode, el), st>>>(s, G, sG, drop2, T, sT, out, skip, ws.p, ws.stride, mode);
   NS_LAUNCH_CHECK();
 }
 
 void small_cholqr(Batch bt, int s, const double* G, int64_t sG, const double* shift, double* Rinv, double* Racc,
-                  int init, int* flag, double* gw, hipStream_t st, double certify, int* ok) {
+                  int init, int* flag, const SmallWs& ws, hipStream_t st, double certify, int* ok) {
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
-  k_small_cholqr<<<bt.nb, NT, evd_lds(s), st>>>(s, bt.dims, G, sG, shift, Rinv, Racc, init, flag, gw, certify, ok);
+  const size_t el = chol_ws(s, s);
+  const int mode = ws_mode(ws, el, s, s);
+  k_small_cholqr<<<bt.nb, NT, dyn_lds(mode, el), st>>>(s, bt.dims, G, sG, shift, Rinv, Racc, init, flag, ws.p,
+                                                       ws.stride, mode, certify, ok);
   NS_LAUNCH_CHECK();
 }
 
 void small_nystrom(int nb, int s, int k, const double* C, const double* R, double eps_rel, double* Wk, double* Ek,
-                   int* out, double* gw, hipStream_t st) {
+                   int* out, const SmallWs& ws, hipStream_t st) {
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
-  k_small_nystrom<<<nb, NT, evd_lds(s), st>>>(s, k, C, R, eps_rel, Wk, Ek, out, gw);
+  const size_t el = chol_ws(s, s);
+  const int mode = ws_mode(ws, el, s, s);
+  k_small_nystrom<<<nb, NT, dyn_lds(mode, el), st>>>(s, k, C, R, eps_rel, Wk, Ek, out, ws.p, ws.stride, mode);
   NS_LAUNCH_CHECK();
 }
 
@@ -584,7 +868,7 @@ void small_rowscale(int nb, int k, int ncols, const double* sigma, int64_t ssig,
 }
 
 void small_gevd(int k, const double* A, const double* B, double* lam, double* C, double* Cl, int* flag, double* ws,
-                double* gw, hipStream_t st) {
+                const SmallWs& sw, hipStream_t st) {
   if (k > SMAX) fail(INVALID_ARG, "matrix too large for the small dense kernels (limit 256)");
   double* L = ws;
   double* Linv = ws + size_t(k) * k;
@@ -593,14 +877,16 @@ void small_gevd(int k, const double* A, const double* B, double* lam, double* C,
   double* E = W + size_t(k) * k;
   k_gevd_reduce<<<1, NT, 0, st>>>(k, A, B, L, Linv, M, flag);
   NS_LAUNCH_CHECK();
-  small_sym_evd(k, M, W, E, gw, st);
+  small_sym_evd(k, M, W, E, sw, st);
   k_gevd_back<<<1, 256, 0, st>>>(k, Linv, W, E, lam, C, Cl);
   NS_LAUNCH_CHECK();
 }
 
-void small_sym_evd(int m, const double* A, double* W, double* E, double* gw, hipStream_t st) {
+void small_sym_evd(int m, const double* A, double* W, double* E, const SmallWs& ws, hipStream_t st) {
   if (m > SMAX) fail(INVALID_ARG, "matrix too large for the small dense kernels (limit 256)");
-  k_small_sym_evd<<<1, NT, evd_lds(m), st>>>(m, A, W, E, gw);
+  const size_t el = evd_elems(m);
+  const int mode = ws_mode(ws, el, m, m);
+  k_small_sym_evd<<<1, NT, dyn_lds(mode, el), st>>>(m, A, W, E, ws.p, mode);
   NS_LAUNCH_CHECK();
 }
 

@@ -79,6 +79,75 @@ __global__ __launch_bounds__(1024) void k_gram_partial(Seg sg, const TA* __restr
   }
 }
 
+// The same partial Gram products on FP64 MFMA (16x16x4): the chunk's rows are staged in LDS as FP64 in
+// batches of GM_R rows (zero-padded to whole 16-column tiles), and each wave accumulates 16x16 output
+// tiles; lane l feeds A(r0 + l/16, a0 + l%16) and B(r0 + l/16, b0 + l%16) and holds output rows
+// a0 + 4v + l/16, column b0 + l%16 (v = 0..3).  The accumulation order is fixed per chunk.
+typedef double gv4d __attribute__((ext_vector_type(4)));
+constexpr int GM_R = 32;       // rows per LDS batch
+constexpr int GM_WAVES = 8;    // waves per workgroup
+constexpr int GM_MAXT = 16;    // output tiles per wave
+template <class TA, class TB>
+__global__ __launch_bounds__(GM_WAVES * 64) void k_gram_mfma(Seg sg, const TA* __restrict__ A, int64_t lda, int ra,
+                                                          const TB* __restrict__ B, int64_t ldb, int rb,
+                                                          double* __restrict__ part) {
+  extern __shared__ double sm[];
+  const int wa = (ra + 15) & ~15, wb = (rb + 15) & ~15;
+  double* sA = sm;              // GM_R x wa
+  double* sB = sm + GM_R * wa;  // GM_R x wb
+  const int ta = wa / 16, tb = wb / 16, T = ta * tb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  int64_t r0, r1;
+  chunk_rows(sg, blockIdx.x, r0, r1);
+  gv4d acc[GM_MAXT];
+#pragma unroll
+  for (int q = 0; q < GM_MAXT; ++q) acc[q] = gv4d{0.0, 0.0, 0.0, 0.0};
+  for (int64_t rs = r0; rs < r1; rs += GM_R) {
+    const int nr = int(r1 - rs < GM_R ? r1 - rs : GM_R);
+    __syncthreads();
+    for (int e = threadIdx.x; e < GM_R * wa; e += blockDim.x) {
+      const int rr = e / wa, c = e - rr * wa;
+      sA[e] = (rr < nr && c < ra) ? double(A[(rs + rr) * lda + c]) : 0.0;
+    }
+    for (int e = threadIdx.x; e < GM_R * wb; e += blockDim.x) {
+      const int rr = e / wb, c = e - rr * wb;
+      sB[e] = (rr < nr && c < rb) ? double(B[(rs + rr) * ldb + c]) : 0.0;
+    }
+    __syncthreads();
+    const int kend = (nr + 3) & ~3;
+#pragma unroll
+    for (int q = 0; q < GM_MAXT; ++q) {
+      const int t = wave + q * GM_WAVES;
+      if (t < T) {
+        const int a0 = (t / tb) * 16, b0 = (t % tb) * 16;
+        gv4d c = acc[q];
+        for (int k = 0; k < kend; k += 4) {
+          const double x = sA[(k + lk) * wa + a0 + li];
+          const double y = sB[(k + lk) * wb + b0 + li];
+          c = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+        }
+        acc[q] = c;
+      }
+    }
+  }
+  const int nout = ra * rb;
+  double* out = part + int64_t(blockIdx.x) * nout;
+#pragma unroll
+  for (int q = 0; q < GM_MAXT; ++q) {
+    const int t = wave + q * GM_WAVES;
+    if (t < T) {
+      const int a0 = (t / tb) * 16, b0 = (t % tb) * 16;
+      const int b = b0 + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = a0 + 4 * v + lk;
+        if (a < ra && b < rb) out[a * rb + b] = acc[q][v];
+      }
+    }
+  }
+}
+
 // sum of the chunk partials of segment p in a fixed order
 __device__ __forceinline__ double chunk_sum(const Seg& sg, int p, int nout, int o, const double* __restrict__ part) {
   const int c0 = sg.coff[p], nch = sg.coff[p + 1] - c0;
@@ -340,8 +409,14 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
   const int nout = ra * rb;
   if (nout == 0 || sg.n == 0) return;
   if (nout > 1024 * GRAM_MAXQ) fail(INVALID_ARG, "Gram product too wide");
-  const size_t lds = size_t(GRAM_RB) * (ra + rb) * sizeof(double);
-  k_gram_partial<TA, TB><<<sg.nchunk, 1024, lds, st>>>(sg, A, lda, ra, B, ldb, rb, work);
+  const int wa = (ra + 15) & ~15, wb = (rb + 15) & ~15;
+  const size_t lds_m = size_t(GM_R) * (wa + wb) * sizeof(double);
+  if ((wa / 16) * (wb / 16) <= GM_WAVES * GM_MAXT && lds_m <= 64 * 1024) {
+    k_gram_mfma<TA, TB><<<sg.nchunk, GM_WAVES * 64, lds_m, st>>>(sg, A, lda, ra, B, ldb, rb, work);
+  } else {
+    const size_t lds = size_t(GRAM_RB) * (ra + rb) * sizeof(double);
+    k_gram_partial<TA, TB><<<sg.nchunk, 1024, lds, st>>>(sg, A, lda, ra, B, ldb, rb, work);
+  }
   NS_LAUNCH_CHECK();
   k_seg_final<<<dim3((nout + 255) / 256, sg.n), 256, 0, st>>>(sg, nout, work, G, gstride, alpha, beta);
   NS_LAUNCH_CHECK();
