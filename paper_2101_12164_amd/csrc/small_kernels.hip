@@ -17,11 +17,13 @@ constexpr int SMAX = 256;                 // largest s supported by the small ke
 constexpr int NB = 16;                    // block size of the blocked factorisations and solves
 constexpr int NBL = NB + 1;               // row stride of a diagonal-block inverse
 
-// Workspace (doubles) of the blocked Cholesky kernels: factor L (r x (r+1)), right-hand sides / inverse
-// X (r x (c+1)), diagonal-block inverses, panel buffer (r x NBL) and block-row buffer (NB x (c+1)).
+// Workspace (doubles) of the blocked Cholesky kernels, dimensions padded to whole 16-wide tiles
+// (rp = ceil16(r), cp = ceil16(c)): factor L (rp x (rp+1)), right-hand sides / inverse X (rp x (cp+1)),
+// diagonal-block inverses, panel buffer (rp x NBL) and block-row buffer (NB x (cp+1)).
+__host__ __device__ inline int pad16(int n) { return (n + 15) & ~15; }
 __host__ __device__ inline size_t chol_ws(int r, int c) {
-  const size_t nbk = size_t((r + NB - 1) / NB);
-  return size_t(r) * (r + 1) + size_t(r) * (c + 1) + nbk * NB * NBL + size_t(r) * NBL + size_t(NB) * (c + 1);
+  const size_t rp = size_t(pad16(r)), cp = size_t(pad16(c));
+  return rp * (rp + 1) + rp * (cp + 1) + (rp / NB) * NB * NBL + rp * NBL + size_t(NB) * (cp + 1);
 }
 __host__ __device__ inline size_t evd_elems(int n) { return size_t(2) * n * (n + 1); }
 
@@ -248,38 +250,58 @@ __device__ int diag_factor_wave(double* A, int ld, int j0, int jb, double* Di) {
   return bad;
 }
 
-// In-place lower Cholesky of A (n x n, stride ld).  Dinv: ceil(n/NB) diagonal-block inverses (NB x NBL
-// each), Pn: n x NBL panel scratch.  Returns 0 or the 1-based index of the first pivot <= 0.
-__device__ int chol_blocked(double* A, int n, int ld, double* Dinv, double* Pn, int* sinfo) {
+// 16x16 tile product on FP64 MFMA: acc += A (16 x K) B (K x 16) with A(i, k) = pa[i sai + k sak] and
+// B(k, j) = pb[k sbk + j sbj], K a multiple of 4.  Lane l feeds A(l%16, k + l/16) and B(k + l/16, l%16) and
+// holds the output elements (4v + l/16, l%16), v = 0..3.  Called by all lanes of a wave.
+typedef double sv4d __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ sv4d mma16(sv4d acc, const double* pa, int sai, int sak, const double* pb, int sbk,
+                                      int sbj, int K) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  pa += li * sai + lk * sak;
+  pb += lk * sbk + li * sbj;
+#pragma unroll 4
+  for (int k = 0; k < K; k += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[k * sak], pb[k * sbk], acc, 0, 0, 0);
+  return acc;
+}
+__device__ __forceinline__ int tile_row(int v) { return 4 * v + ((threadIdx.x & 63) >> 4); }
+__device__ __forceinline__ int tile_col() { return threadIdx.x & 15; }
+constexpr int NW = NT / 64;  // waves per workgroup
+
+// In-place lower Cholesky of A (np x np, np a multiple of NB, stride ld; rows and columns past the problem's
+// dimension hold the identity).  Dinv: np/NB diagonal-block inverses (NB x NBL each), Pn: np x NBL panel
+// scratch.  Panels and trailing updates are 16x16 MFMA tiles.  Returns 0 or the 1-based index of the first
+// pivot <= 0.
+__device__ int chol_blocked(double* A, int np, int ld, double* Dinv, double* Pn, int* sinfo) {
   const int wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) *sinfo = 0;
   __syncthreads();
-  for (int j0 = 0; j0 < n; j0 += NB) {
-    const int jb = n - j0 < NB ? n - j0 : NB;
-    const double* Di = Dinv + (j0 / NB) * (NB * NBL);
+  for (int j0 = 0; j0 < np; j0 += NB) {
+    double* Di = Dinv + (j0 / NB) * (NB * NBL);
     if (wave == 0) {
-      const int bad = diag_factor_wave(A, ld, j0, jb, Dinv + (j0 / NB) * (NB * NBL));
+      const int bad = diag_factor_wave(A, ld, j0, NB, Di);
       if (bad && (threadIdx.x & 63) == 0 && *sinfo == 0) *sinfo = j0 + bad;
     }
     __syncthreads();
-    const int j1 = j0 + jb, m = n - j1;
-    for (int e = threadIdx.x; e < m * jb; e += NT) {  // Pn = A21 L11^{-T}
-      const int i = e / jb, c = e - i * jb;
-      const double* a = A + (j1 + i) * ld + j0;
-      double acc = 0.0;
-      for (int t = 0; t <= c; ++t) acc += a[t] * Di[c * NBL + t];
-      Pn[i * NBL + c] = acc;
+    const int j1 = j0 + NB, mt = (np - j1) / NB;
+    for (int t = wave; t < mt; t += NW) {  // Pn = A21 L11^{-T}
+      sv4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(acc, A + (j1 + NB * t) * ld + j0, ld, 1, Di, 1, NBL, NB);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Pn[(NB * t + tile_row(v)) * NBL + tile_col()] = acc[v];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < m * m; e += NT) {  // A22 -= L21 L21^T (lower)
-      const int i = e / m, q = e - i * m;
-      if (q > i) continue;
-      double acc = A[(j1 + i) * ld + j1 + q];
-      for (int t = 0; t < jb; ++t) acc -= Pn[i * NBL + t] * Pn[q * NBL + t];
-      A[(j1 + i) * ld + j1 + q] = acc;
+    const int ntri = mt * (mt + 1) / 2;
+    for (int u = wave; u < ntri; u += NW) {  // A22 -= L21 L21^T on the lower tiles
+      int ti = 0;
+      while ((ti + 1) * (ti + 2) / 2 <= u) ++ti;
+      const int tq = u - ti * (ti + 1) / 2;
+      sv4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(acc, Pn + NB * ti * NBL, NBL, 1, Pn + NB * tq * NBL, 1, NBL, NB);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(j1 + NB * ti + tile_row(v)) * ld + j1 + NB * tq + tile_col()] -= acc[v];
     }
-    for (int e = threadIdx.x; e < m * jb; e += NT) {
-      const int i = e / jb, c = e - i * jb;
+    for (int e = threadIdx.x; e < (np - j1) * NB; e += NT) {
+      const int i = e / NB, c = e - i * NB;
       A[(j1 + i) * ld + j0 + c] = Pn[i * NBL + c];
     }
     __syncthreads();
@@ -289,124 +311,128 @@ __device__ int chol_blocked(double* A, int n, int ld, double* Dinv, double* Pn, 
   return info;
 }
 
-// Diagonal-block inverses of an existing factor L (n x n, stride ld): one wave per block.
-__device__ void diag_inverses(const double* L, int n, int ld, double* Dinv) {
+// Diagonal-block inverses of an existing factor L (np x np, stride ld): one wave per block.
+__device__ void diag_inverses(const double* L, int np, int ld, double* Dinv) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nbk = (n + NB - 1) / NB;
-  for (int bk = wave; bk < nbk; bk += NT / 64) {
-    const int j0 = bk * NB, jb = n - j0 < NB ? n - j0 : NB;
+  for (int bk = wave; bk < np / NB; bk += NW) {
+    const int j0 = bk * NB;
     double x[NB];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int ii = i < jb ? i : jb - 1;  // clamped: rows past the block are never read
       double acc = (i == lane) ? 1.0 : 0.0;
 #pragma unroll
-      for (int t = 0; t < i; ++t) acc -= L[(j0 + ii) * ld + j0 + (t < ii ? t : ii)] * x[t];
-      x[i] = (i < jb) ? acc / L[(j0 + ii) * ld + j0 + ii] : 0.0;
+      for (int t = 0; t < i; ++t) acc -= L[(j0 + i) * ld + j0 + t] * x[t];
+      x[i] = acc / L[(j0 + i) * ld + j0 + i];
     }
     if (lane < NB) {
 #pragma unroll
-      for (int i = 0; i < NB; ++i) Dinv[bk * (NB * NBL) + i * NBL + lane] = (lane < jb && i < jb) ? x[i] : 0.0;
+      for (int i = 0; i < NB; ++i) Dinv[bk * (NB * NBL) + i * NBL + lane] = x[i];
     }
   }
   __syncthreads();
 }
 
-// X (r x c, stride lx) <- (L L^T)^{-1} X by block rows: forward L Y = X, then backward L^T X = Y.
-// Tb: NB x (c + 1) scratch.
-__device__ void chol_solve_blocked(const double* L, int r, int ld, const double* Dinv, double* X, int lx, int c,
+// X (rp x cp, stride lx; rp, cp multiples of NB) <- (L L^T)^{-1} X by block rows: forward L Y = X, then
+// backward L^T X = Y.  Tb: NB x (cp + 1) scratch.
+__device__ void chol_solve_blocked(const double* L, int rp, int ld, const double* Dinv, double* X, int lx, int cp,
                                    double* Tb) {
-  const int nbk = (r + NB - 1) / NB, lt = c + 1;
+  const int wave = threadIdx.x >> 6, nbk = rp / NB, ct = cp / NB, lt = cp + 1;
   for (int bk = 0; bk < nbk; ++bk) {
-    const int i0 = bk * NB, ib = r - i0 < NB ? r - i0 : NB;
+    const int i0 = bk * NB;
     const double* Di = Dinv + bk * (NB * NBL);
-    for (int e = threadIdx.x; e < ib * c; e += NT) {  // Tb = X_i - L_{i,<i} Y_{<i}
-      const int a = e / c, j = e - a * c;
-      const double* l = L + (i0 + a) * ld;
-      double acc = X[(i0 + a) * lx + j];
-      for (int t = 0; t < i0; ++t) acc -= l[t] * X[t * lx + j];
-      Tb[a * lt + j] = acc;
+    for (int jt = wave; jt < ct; jt += NW) {  // Tb = X_i - L_{i,<i} Y_{<i}
+      sv4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(acc, L + i0 * ld, ld, 1, X + NB * jt, lx, 1, i0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = tile_row(v), j = NB * jt + tile_col();
+        Tb[a * lt + j] = X[(i0 + a) * lx + j] - acc[v];
+      }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < ib * c; e += NT) {  // Y_i = L_ii^{-1} Tb
-      const int a = e / c, j = e - a * c;
-      double acc = 0.0;
-      for (int t = 0; t <= a; ++t) acc += Di[a * NBL + t] * Tb[t * lt + j];
-      X[(i0 + a) * lx + j] = acc;
+    for (int jt = wave; jt < ct; jt += NW) {  // Y_i = L_ii^{-1} Tb
+      sv4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(acc, Di, NBL, 1, Tb + NB * jt, lt, 1, NB);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[(i0 + tile_row(v)) * lx + NB * jt + tile_col()] = acc[v];
     }
     __syncthreads();
   }
   for (int bk = nbk - 1; bk >= 0; --bk) {
-    const int i0 = bk * NB, ib = r - i0 < NB ? r - i0 : NB;
+    const int i0 = bk * NB, i1 = i0 + NB;
     const double* Di = Dinv + bk * (NB * NBL);
-    for (int e = threadIdx.x; e < ib * c; e += NT) {  // Tb = Y_i - L_{>i,i}^T X_{>i}
-      const int a = e / c, j = e - a * c;
-      double acc = X[(i0 + a) * lx + j];
-      for (int t = i0 + ib; t < r; ++t) acc -= L[t * ld + i0 + a] * X[t * lx + j];
-      Tb[a * lt + j] = acc;
+    for (int jt = wave; jt < ct; jt += NW) {  // Tb = Y_i - L_{>i,i}^T X_{>i}
+      sv4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(acc, L + i1 * ld + i0, 1, ld, X + i1 * lx + NB * jt, lx, 1, rp - i1);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = tile_row(v), j = NB * jt + tile_col();
+        Tb[a * lt + j] = X[(i0 + a) * lx + j] - acc[v];
+      }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < ib * c; e += NT) {  // X_i = L_ii^{-T} Tb
-      const int a = e / c, j = e - a * c;
-      double acc = 0.0;
-      for (int t = a; t < ib; ++t) acc += Di[t * NBL + a] * Tb[t * lt + j];
-      X[(i0 + a) * lx + j] = acc;
+    for (int jt = wave; jt < ct; jt += NW) {  // X_i = L_ii^{-T} Tb
+      sv4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(acc, Di, 1, NBL, Tb + NB * jt, lt, 1, NB);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[(i0 + tile_row(v)) * lx + NB * jt + tile_col()] = acc[v];
     }
     __syncthreads();
   }
 }
 
-// X = L^{-1} (n x n, stride ld, zero above the diagonal) from the factor and its diagonal-block inverses,
-// by block rows: X_ij = -L_ii^{-1} sum_{j <= t < i} L_it X_tj.  Tb: NB x (n + 1) scratch.
-__device__ void tri_inverse_blocked(const double* L, int n, int ld, const double* Dinv, double* X, double* Tb) {
-  const int lt = n + 1;
-  for (int e = threadIdx.x; e < n * n; e += NT) {
-    const int i = e / n, j = e - i * n;
+// X = L^{-1} (np x np, stride ld, zero above the diagonal) from the factor and its diagonal-block inverses,
+// by block rows: X_ij = -L_ii^{-1} sum_{j <= t < i} L_it X_tj.  Tb: NB x (np + 1) scratch.
+__device__ void tri_inverse_blocked(const double* L, int np, int ld, const double* Dinv, double* X, double* Tb) {
+  const int wave = threadIdx.x >> 6, lt = np + 1;
+  for (int e = threadIdx.x; e < np * np; e += NT) {
+    const int i = e / np, j = e - i * np;
     const int bi = i / NB, bj = j / NB;
     X[i * ld + j] = (bi == bj && j <= i) ? Dinv[bi * (NB * NBL) + (i - bi * NB) * NBL + (j - bj * NB)] : 0.0;
   }
   __syncthreads();
-  const int nbk = (n + NB - 1) / NB;
-  for (int bk = 1; bk < nbk; ++bk) {
-    const int i0 = bk * NB, ib = n - i0 < NB ? n - i0 : NB;
+  for (int bk = 1; bk < np / NB; ++bk) {
+    const int i0 = bk * NB;
     const double* Di = Dinv + bk * (NB * NBL);
-    for (int e = threadIdx.x; e < ib * i0; e += NT) {  // Tb[a][j] = sum_{j <= t < i0} L[i0+a][t] X[t][j]
-      const int a = e / i0, j = e - a * i0;
-      const double* l = L + (i0 + a) * ld;
-      double acc = 0.0;
-      for (int t = j; t < i0; ++t) acc += l[t] * X[t * ld + j];
-      Tb[a * lt + j] = acc;
+    for (int jt = wave; jt < bk; jt += NW) {  // Tb_j = L_{i, j..i-1} X_{j..i-1, j}
+      sv4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(acc, L + i0 * ld + NB * jt, ld, 1, X + NB * jt * ld + NB * jt, ld, 1, i0 - NB * jt);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tb[tile_row(v) * lt + NB * jt + tile_col()] = acc[v];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < ib * i0; e += NT) {
-      const int a = e / i0, j = e - a * i0;
-      double acc = 0.0;
-      for (int t = 0; t <= a; ++t) acc += Di[a * NBL + t] * Tb[t * lt + j];
-      X[(i0 + a) * ld + j] = -acc;
+    for (int jt = wave; jt < bk; jt += NW) {  // X_ij = -L_ii^{-1} Tb_j
+      sv4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(acc, Di, NBL, 1, Tb + NB * jt, lt, 1, NB);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[(i0 + tile_row(v)) * ld + NB * jt + tile_col()] = -acc[v];
     }
     __syncthreads();
   }
 }
 
-// Carve of a chol_ws(r, c) workspace.
+// Carve of a chol_ws(r, c) workspace (padded dimensions rp, cp).
 struct CholWs {
   double *L, *X, *Dinv, *Pn, *Tb;
-  int ldl, ldx;
+  int rp, cp, ldl, ldx;
 };
 __device__ CholWs chol_carve(double* base, int r, int c) {
   CholWs w;
-  w.ldl = r + 1;
-  w.ldx = c + 1;
+  w.rp = pad16(r);
+  w.cp = pad16(c);
+  w.ldl = w.rp + 1;
+  w.ldx = w.cp + 1;
   w.L = base;
-  w.X = w.L + size_t(r) * w.ldl;
-  w.Dinv = w.X + size_t(r) * w.ldx;
-  w.Pn = w.Dinv + size_t((r + NB - 1) / NB) * NB * NBL;
-  w.Tb = w.Pn + size_t(r) * NBL;
+  w.X = w.L + size_t(w.rp) * w.ldl;
+  w.Dinv = w.X + size_t(w.rp) * w.ldx;
+  w.Pn = w.Dinv + size_t(w.rp / NB) * NB * NBL;
+  w.Tb = w.Pn + size_t(w.rp) * NBL;
   return w;
 }
 
 // Problem b: D (r0 x r0, ld r0) at D + b sD, leading rb = dims[b] block used; B, X likewise.  factor: D is
-// factored (L written back); otherwise D holds the factor from an earlier call.
+// factored (L written back); otherwise D holds the factor from an earlier call.  In LDS the factor is padded
+// with the identity and the right-hand sides with zeros to whole 16-wide tiles.
 __global__ __launch_bounds__(NT) void k_small_chol_solve(int r0, const int* __restrict__ dims, double* D, int64_t sD,
                                                          const double* B, int64_t ldb, int64_t sB, double* X,
                                                          int64_t ldx, int64_t sX, int s, int s0, double alpha,
@@ -422,18 +448,28 @@ __global__ __launch_bounds__(NT) void k_small_chol_solve(int r0, const int* __re
   for (int e = threadIdx.x; e < (s0 - r) * s; e += NT) X[(r + e / s) * ldx + e % s] = 0.0;
   if (r == 0) return;
   CholWs w = chol_carve(lds ? sm : gw + b * gws, r, s);
-  for (int e = threadIdx.x; e < r * r; e += NT) w.L[(e / r) * w.ldl + e % r] = D[(e / r) * r0 + e % r];
-  for (int e = threadIdx.x; e < r * s; e += NT) w.X[(e / s) * w.ldx + e % s] = B[(e / s) * ldb + e % s];
+  const int rp = w.rp, cp = w.cp;
+  for (int e = threadIdx.x; e < rp * rp; e += NT) {
+    const int i = e / rp, j = e - i * rp;
+    w.L[i * w.ldl + j] = (i < r && j < r) ? D[i * r0 + j] : (i == j ? 1.0 : 0.0);
+  }
+  for (int e = threadIdx.x; e < rp * cp; e += NT) {
+    const int i = e / cp, j = e - i * cp;
+    w.X[i * w.ldx + j] = (i < r && j < s) ? B[i * ldb + j] : 0.0;
+  }
   __syncthreads();
   if (factor) {
-    const int info = chol_blocked(w.L, r, w.ldl, w.Dinv, w.Pn, &sinfo);
+    const int info = chol_blocked(w.L, rp, w.ldl, w.Dinv, w.Pn, &sinfo);
     if (info && threadIdx.x == 0) flag[0] = 1;
-    for (int e = threadIdx.x; e < r * r; e += NT) D[(e / r) * r0 + e % r] = w.L[(e / r) * w.ldl + e % r];
+    for (int e = threadIdx.x; e < r * r; e += NT) {
+      const int i = e / r, j = e % r;
+      D[i * r0 + j] = j <= i ? w.L[i * w.ldl + j] : 0.0;
+    }
   } else {
-    diag_inverses(w.L, r, w.ldl, w.Dinv);
+    diag_inverses(w.L, rp, w.ldl, w.Dinv);
   }
   if (s == 0) return;
-  chol_solve_blocked(w.L, r, w.ldl, w.Dinv, w.X, w.ldx, s, w.Tb);
+  chol_solve_blocked(w.L, rp, w.ldl, w.Dinv, w.X, w.ldx, cp, w.Tb);
   for (int e = threadIdx.x; e < r * s; e += NT) X[(e / s) * ldx + e % s] = alpha * w.X[(e / s) * w.ldx + e % s];
 }
 
@@ -503,10 +539,10 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
                                                      int* ok) {
   extern __shared__ double sm[];
   __shared__ int sinfo;
-  __shared__ double sshift, strace;
   __shared__ double red[NT];
   const int b = blockIdx.x;
   const int n = dims ? dims[b] : s;
+  const int wave = threadIdx.x >> 6;
   G += b * sG;
   Rinv += b * int64_t(s) * s;
   Racc += b * int64_t(s) * s;
@@ -515,25 +551,26 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
     if (ok && threadIdx.x == 0) ok[b] = 0;
     return;
   }
-  if (threadIdx.x == 0) {
-    double tr = 0.0;
-    for (int i = 0; i < n; ++i) tr += G[i * s + i];
-    sshift = (shift_coef ? shift_coef[b] : 0.0) * tr;
-    strace = tr;
-  }
-  __syncthreads();
-  const double shift = sshift;
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) tr += G[i * s + i];
+  tr = block_sum(tr, red);
+  const double shift = (shift_coef ? shift_coef[b] : 0.0) * tr;
   CholWs w = chol_carve(lds ? sm : gw + b * gws, n, n);
-  const int ld = w.ldl;
+  const int np = w.rp, ld = w.ldl;
   double* A = w.L;
   double* X = w.X;
-  for (int e = threadIdx.x; e < n * n; e += NT) {
-    const int i = e / n, j = e % n;
-    A[i * ld + j] = 0.5 * (G[i * s + j] + G[j * s + i]) + (i == j ? shift : 0.0);
+  for (int e = threadIdx.x; e < np * np; e += NT) {
+    const int i = e / np, j = e - i * np;
+    A[i * ld + j] = (i < n && j < n) ? 0.5 * (G[i * s + j] + G[j * s + i]) + (i == j ? shift : 0.0)
+                                     : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  if (chol_blocked(A, n, ld, w.Dinv, w.Pn, &sinfo) && threadIdx.x == 0) flag[0] = 1;
-  tri_inverse_blocked(A, n, ld, w.Dinv, X, w.Tb);  // X = L^{-1}
+  if (chol_blocked(A, np, ld, w.Dinv, w.Pn, &sinfo) && threadIdx.x == 0) flag[0] = 1;
+  tri_inverse_blocked(A, np, ld, w.Dinv, X, w.Tb);  // X = L^{-1}
+  for (int e = threadIdx.x; e < np * np; e += NT) {  // the factorisation leaves values above the diagonal
+    const int i = e / np, j = e - i * np;
+    if (j > i) A[i * ld + j] = 0.0;
+  }
   // Rinv = (L^{-1})^T (upper) in the leading block, zero elsewhere; R = L^T
   double fro = 0.0;
   for (int e = threadIdx.x; e < s * s; e += NT) {
@@ -546,7 +583,7 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
     // lambda_min(G) >= 1 / ||L^{-1}||_F^2 and lambda_max(G) <= trace(G): certify that no
     // singular value ratio of the block is at or below the drop tolerance
     const double f = block_sum(fro, red);
-    if (threadIdx.x == 0) ok[b] = (sinfo == 0 && 1.0 / f > certify * strace) ? 1 : 0;
+    if (threadIdx.x == 0) ok[b] = (sinfo == 0 && 1.0 / f > certify * tr) ? 1 : 0;
   }
   __syncthreads();
   if (init) {
@@ -556,18 +593,27 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
     }
     return;
   }
-  // Racc <- R * Racc, with Racc staged in X
-  for (int e = threadIdx.x; e < n * n; e += NT) {
-    const int i = e / n, j = e % n;
-    X[i * ld + j] = Racc[i * s + j];
+  // Racc <- R * Racc (R = L^T), with Racc staged in X (zero-padded)
+  for (int e = threadIdx.x; e < np * np; e += NT) {
+    const int i = e / np, j = e - i * np;
+    X[i * ld + j] = (i < n && j < n) ? Racc[i * s + j] : 0.0;
   }
   __syncthreads();
+  const int nt = np / NB;
+  for (int t = wave; t < nt * nt; t += NW) {
+    const int ti = t / nt, tj = t - ti * nt;
+    sv4d acc = {0.0, 0.0, 0.0, 0.0};
+    acc = mma16(acc, A + NB * ti, 1, ld, X + NB * tj, ld, 1, np);  // R(i, m) = L(m, i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = NB * ti + tile_row(v), j = NB * tj + tile_col();
+      if (i < s && j < s) Racc[i * s + j] = (i < n && j < n && j >= i) ? acc[v] : 0.0;
+    }
+  }
+  // rows and columns of Racc beyond the padded tiles (none when s <= np) are zero
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
-    double acc = 0.0;
-    if (i < n && j < n)
-      for (int m = i; m <= j; ++m) acc += A[m * ld + i] * X[m * ld + j];
-    Racc[e] = acc;
+    if (i >= np || j >= np) Racc[e] = 0.0;
   }
 }
 
@@ -575,7 +621,7 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
 // T = R C_1^+ R^T over the eigenpairs of sym(C) with lambda >= eps_rel lambda_max, whose EVD yields the
 // basis.  When a Cholesky C = L L^T succeeds with 1/||L^{-1}||_F^2 >= eps_rel trace(C) (a lower bound of
 // lambda_min against an upper bound of lambda_max), every eigenpair passes the threshold and
-// T = R C^{-1} R^T = F F^T with F = R L^{-T}: the EVD of C is skipped.
+// T = R C^{-1} R^T = H^T H with H = L^{-1} R^T: the EVD of C is skipped.
 __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double* C, const double* R, double eps_rel,
                                                       double* Wk, double* Ek, int* out, double* gw, int64_t gws,
                                                       int lds) {
@@ -587,72 +633,110 @@ __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double
   __shared__ int ikeep[SMAX];
   __shared__ int nkeep, sinfo;
   const int b = blockIdx.x;
+  const int wave = threadIdx.x >> 6;
   C += b * int64_t(s) * s;
   R += b * int64_t(s) * s;
   Wk += b * int64_t(s) * k;
   Ek += b * int64_t(k);
   out += 2 * b;
-  CholWs cw = chol_carve(lds ? sm : gw + b * gws, s, s);  // regions L and X double as the EVD's A and V
-  EvdSpace w = evd_space(s, cw.L, sd, si);
-  const int ld = w.ld;
-  for (int e = threadIdx.x; e < s * s; e += NT) {  // symmetrised C
-    const int i = e / s, j = e % s;
-    w.A[i * ld + j] = 0.5 * (C[i * s + j] + C[j * s + i]);
+  CholWs cw = chol_carve(lds ? sm : gw + b * gws, s, s);  // regions L and X double as the EVD's matrices
+  const int np = cw.rp, ld = cw.ldl;
+  double* A = cw.L;
+  double* V = cw.X;
+  double* cs = sd;
+  double* d = sd + 2 * s;
+  int* pr = si;
+  int* ord = si + 2 * s;
+  for (int e = threadIdx.x; e < np * np; e += NT) {  // symmetrised C, identity-padded
+    const int i = e / np, j = e - i * np;
+    A[i * ld + j] = (i < s && j < s) ? 0.5 * (C[i * s + j] + C[j * s + i]) : (i == j ? 1.0 : 0.0);
   }
   double tr = 0.0;
   for (int i = threadIdx.x; i < s; i += NT) tr += C[i * s + i];
   tr = block_sum(tr, red);
-  const int info = chol_blocked(w.A, s, ld, cw.Dinv, cw.Pn, &sinfo);
+  const int info = chol_blocked(A, np, ld, cw.Dinv, cw.Pn, &sinfo);
   bool certified = false;
   if (info == 0) {
-    tri_inverse_blocked(w.A, s, ld, cw.Dinv, w.V, cw.Tb);  // V = L^{-1}
+    tri_inverse_blocked(A, np, ld, cw.Dinv, V, cw.Tb);  // V = L^{-1}
     double fro = 0.0;
     for (int e = threadIdx.x; e < s * s; e += NT) {
-      const double x = w.V[(e / s) * ld + e % s];
+      const double x = V[(e / s) * ld + e % s];
       fro += x * x;
     }
     fro = block_sum(fro, red);
     certified = tr > 0.0 && 1.0 / fro >= eps_rel * tr;
   }
+  double* Tm;  // T
+  double* Ev;  // its eigenvectors
   int r;
   if (certified) {
     r = s;
-    // F = R L^{-T} into A: F[i][j] = sum_{i <= m <= j} R[i][m] Linv[j][m]
-    for (int e = threadIdx.x; e < s * s; e += NT) {
-      const int i = e / s, j = e % s;
-      double acc = 0.0;
-      for (int m = i; m <= j; ++m) acc += R[i * s + m] * w.V[j * ld + m];
-      w.A[i * ld + j] = acc;
+    for (int e = threadIdx.x; e < np * np; e += NT) {  // V = R^T (zero-padded)
+      const int i = e / np, j = e - i * np;
+      V[i * ld + j] = (i < s && j < s) ? R[j * s + i] : 0.0;
     }
     __syncthreads();
-    // T = F F^T into V
-    for (int e = threadIdx.x; e < s * s; e += NT) {
-      const int i = e / s, j = e % s;
-      if (j > i) continue;
-      double acc = 0.0;
-      for (int m = 0; m < s; ++m) acc += w.A[i * ld + m] * w.A[j * ld + m];
-      w.V[i * ld + j] = acc;
-      w.V[j * ld + i] = acc;
+    // H = L^{-1} R^T: the forward block sweep of chol_solve_blocked
+    for (int bk = 0; bk < np / NB; ++bk) {
+      const int i0 = bk * NB, lt = np + 1;
+      const double* Di = cw.Dinv + bk * (NB * NBL);
+      for (int jt = wave; jt < np / NB; jt += NW) {
+        sv4d acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mma16(acc, A + i0 * ld, ld, 1, V + NB * jt, ld, 1, i0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = tile_row(v), j = NB * jt + tile_col();
+          cw.Tb[a * lt + j] = V[(i0 + a) * ld + j] - acc[v];
+        }
+      }
+      __syncthreads();
+      for (int jt = wave; jt < np / NB; jt += NW) {
+        sv4d acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mma16(acc, Di, NBL, 1, cw.Tb + NB * jt, lt, 1, NB);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) V[(i0 + tile_row(v)) * ld + NB * jt + tile_col()] = acc[v];
+      }
+      __syncthreads();
+    }
+    // T = H^T H into A (the factor is no longer needed)
+    const int nt = np / NB;
+    for (int t = wave; t < nt * nt; t += NW) {
+      const int ti = t / nt, tj = t - ti * nt;
+      sv4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(acc, V + NB * ti, 1, ld, V + NB * tj, ld, 1, np);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(NB * ti + tile_row(v)) * ld + NB * tj + tile_col()] = acc[v];
     }
     __syncthreads();
+    for (int e = threadIdx.x; e < s * s; e += NT) {  // exact symmetry
+      const int i = e / s, j = e % s;
+      if (j < i) {
+        const double x = 0.5 * (A[i * ld + j] + A[j * ld + i]);
+        A[i * ld + j] = x;
+        A[j * ld + i] = x;
+      }
+    }
+    __syncthreads();
+    Tm = A;
+    Ev = V;
   } else {
     for (int e = threadIdx.x; e < s * s; e += NT) {  // symmetrised C again (the factorisation overwrote it)
       const int i = e / s, j = e % s;
-      w.A[i * ld + j] = 0.5 * (C[i * s + j] + C[j * s + i]);
+      A[i * ld + j] = 0.5 * (C[i * s + j] + C[j * s + i]);
     }
     __syncthreads();
-    jacobi(w.A, w.V, s, ld, w.cs, w.pr, red);
-    for (int i = threadIdx.x; i < s; i += NT) w.d[i] = w.A[i * ld + i];
+    jacobi(A, V, s, ld, cs, pr, red);
+    for (int i = threadIdx.x; i < s; i += NT) d[i] = A[i * ld + i];
     __syncthreads();
     if (threadIdx.x == 0) {
-      double dmax = w.d[0];
-      for (int i = 1; i < s; ++i) dmax = w.d[i] > dmax ? w.d[i] : dmax;
+      double dmax = d[0];
+      for (int i = 1; i < s; ++i) dmax = d[i] > dmax ? d[i] : dmax;
       int q = 0;
       if (dmax > 0.0)
         for (int i = 0; i < s; ++i)
-          if (w.d[i] >= eps_rel * dmax) {
+          if (d[i] >= eps_rel * dmax) {
             ikeep[q] = i;
-            dkeep[q] = w.d[i];
+            dkeep[q] = d[i];
             ++q;
           }
       nkeep = q;
@@ -663,8 +747,8 @@ __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double
     for (int e = threadIdx.x; e < s * r; e += NT) {
       const int i = e / r, c = e % r;
       double acc = 0.0;
-      for (int m = i; m < s; ++m) acc += R[i * s + m] * w.V[m * ld + ikeep[c]];
-      w.A[i * ld + c] = acc;
+      for (int m = i; m < s; ++m) acc += R[i * s + m] * V[m * ld + ikeep[c]];
+      A[i * ld + c] = acc;
     }
     __syncthreads();
     // T = M D_1^{-1} M^T into V, symmetric by construction of the sum
@@ -672,22 +756,24 @@ __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double
       const int i = e / s, j = e % s;
       if (j > i) continue;
       double acc = 0.0;
-      for (int c = 0; c < r; ++c) acc += w.A[i * ld + c] * w.A[j * ld + c] / dkeep[c];
-      w.V[i * ld + j] = acc;
-      w.V[j * ld + i] = acc;
+      for (int c = 0; c < r; ++c) acc += A[i * ld + c] * A[j * ld + c] / dkeep[c];
+      V[i * ld + j] = acc;
+      V[j * ld + i] = acc;
     }
     __syncthreads();
+    Tm = V;
+    Ev = A;
   }
-  jacobi(w.V, w.A, s, ld, w.cs, w.pr, red);  // EVD of T: eigenvectors in A
-  for (int i = threadIdx.x; i < s; i += NT) w.d[i] = w.V[i * ld + i];
+  jacobi(Tm, Ev, s, ld, cs, pr, red);  // EVD of T
+  for (int i = threadIdx.x; i < s; i += NT) d[i] = Tm[i * ld + i];
   __syncthreads();
-  sort_desc(w.d, s, w.ord);
+  sort_desc(d, s, ord);
   const int kk = k < r ? k : r;
   for (int e = threadIdx.x; e < s * k; e += NT) {
     const int i = e / k, c = e % k;
-    Wk[e] = c < kk ? w.A[i * ld + w.ord[c]] : 0.0;
+    Wk[e] = c < kk ? Ev[i * ld + ord[c]] : 0.0;
   }
-  for (int c = threadIdx.x; c < k; c += NT) Ek[c] = c < kk ? w.d[w.ord[c]] : 0.0;
+  for (int c = threadIdx.x; c < k; c += NT) Ek[c] = c < kk ? d[ord[c]] : 0.0;
   if (threadIdx.x == 0) {
     out[0] = r;
     out[1] = kk;
