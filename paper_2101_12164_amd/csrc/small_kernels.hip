@@ -27,7 +27,19 @@ __host__ __device__ inline size_t chol_ws(int r, int c) {
 }
 __host__ __device__ inline size_t evd_elems(int n) { return size_t(2) * n * (n + 1); }
 
-__device__ double block_sum(double v, double* red) {
+// 1 / sqrt(d) for d > 0: the hardware estimate refined by two Newton steps y <- y (3 - d y^2) / 2.
+__device__ __forceinline__ double rcp_nr(double x) {  // 1 / x: estimate and one Newton step
+  const double y = __builtin_amdgcn_rcp(x);
+  return y * fma(-x, y, 2.0);
+}
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  y = y * fma(-0.5 * d * y, y, 1.5);
+  return y;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
   __syncthreads();
   for (int o = NT / 2; o > 0; o >>= 1) {
@@ -41,10 +53,11 @@ __device__ double block_sum(double v, double* red) {
 
 // Cyclic Jacobi: A (n x n, row stride ld, symmetric) is diagonalised in place;
 // V (stride ld) receives the eigenvectors in its columns.  cs: 2n doubles,
-// pr: n+2 ints.  Each round applies the n/2 disjoint rotations of a
-// round-robin ordering at once: every 2x2 block (pair P rows, pair Q columns)
-// of A becomes J_P^T B J_Q, and V's column pairs become V J_Q.
-__device__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr, double* red) {
+// pr: n+2 ints.  Each round applies the n/2 disjoint rotations J of a
+// round-robin ordering at once, as A <- A J and V <- V J (columns p, q of every
+// row), then A <- J^T A (rows p, q of every column); consecutive threads take
+// consecutive rows or columns, so LDS accesses do not collide.
+__device__ __forceinline__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr, double* red) {
   const int tid = threadIdx.x;
   for (int e = tid; e < n * n; e += NT) {
     const int i = e / n, j = e % n;
@@ -54,7 +67,6 @@ __device__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr,
   if (n < 2) return;
   const int m = n + (n & 1);
   const int half = m / 2;
-  const float inv_half = 1.0f / float(half);
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < n * n; e += NT) {
@@ -79,10 +91,21 @@ __device__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr,
         double c = 1.0, s = 0.0;
         if (q < n) {
           const double apq = A[p * ld + q];
-          if (fabs(apq) > 1e-18 * sqrt(fabs(A[p * ld + p] * A[q * ld + q])) && fabs(apq) > 1e-300) {
-            const double tau = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
+          const double app = A[p * ld + p], aqq = A[q * ld + q];
+          if (apq * apq > 1e-36 * fabs(app * aqq) && fabs(apq) > 1e-300) {
+            // the angle from hardware reciprocal / square-root estimates with one Newton step each; c and s
+            // from t keep the rotation orthogonal to rounding whatever the angle's accuracy
+            const double tau = (aqq - app) * rcp_nr(2.0 * apq);
+            const double at = fabs(tau);
+            double tf;
+            if (at > 1e15) {
+              tf = 0.5 * rcp_nr(at);
+            } else {
+              const double u = 1.0 + at * at;
+              tf = rcp_nr(at + u * rsqrt_nr(u));
+            }
+            const double t = tau >= 0.0 ? tf : -tf;
+            c = rsqrt_nr(1.0 + t * t);
             s = t * c;
           }
         }
@@ -92,32 +115,27 @@ __device__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr,
         cs[2 * tid + 1] = s;
       }
       __syncthreads();
-      // A <- J^T A J on all 2x2 pair blocks
-      for (int t = tid; t < half * half; t += NT) {
-        const int P = int((float(t) + 0.5f) * inv_half), Q = t - P * half;
-        const int p0 = pr[2 * P], q0 = pr[2 * P + 1], p1 = pr[2 * Q], q1 = pr[2 * Q + 1];
-        const double cP = cs[2 * P], sP = cs[2 * P + 1], cQ = cs[2 * Q], sQ = cs[2 * Q + 1];
-        const bool hq0 = q0 < n, hq1 = q1 < n;
-        const double b00 = A[p0 * ld + p1];
-        const double b01 = hq1 ? A[p0 * ld + q1] : 0.0;
-        const double b10 = hq0 ? A[q0 * ld + p1] : 0.0;
-        const double b11 = (hq0 && hq1) ? A[q0 * ld + q1] : 0.0;
-        const double x00 = cP * b00 - sP * b10, x01 = cP * b01 - sP * b11;  // J_P^T B
-        const double x10 = sP * b00 + cP * b10, x11 = sP * b01 + cP * b11;
-        A[p0 * ld + p1] = x00 * cQ - x01 * sQ;
-        if (hq1) A[p0 * ld + q1] = x00 * sQ + x01 * cQ;
-        if (hq0) A[q0 * ld + p1] = x10 * cQ - x11 * sQ;
-        if (hq0 && hq1) A[q0 * ld + q1] = x10 * sQ + x11 * cQ;
+      for (int t = tid; t < n * half; t += NT) {  // A <- A J, V <- V J
+        const int P = t / n, i = t - P * n;
+        const int p = pr[2 * P], q = pr[2 * P + 1];
+        if (q >= n) continue;
+        const double c = cs[2 * P], s = cs[2 * P + 1];
+        const double ap = A[i * ld + p], aq = A[i * ld + q];
+        A[i * ld + p] = c * ap - s * aq;
+        A[i * ld + q] = s * ap + c * aq;
+        const double vp = V[i * ld + p], vq = V[i * ld + q];
+        V[i * ld + p] = c * vp - s * vq;
+        V[i * ld + q] = s * vp + c * vq;
       }
-      // V <- V J
-      for (int t = tid; t < n * half; t += NT) {
-        const int i = int((float(t) + 0.5f) * inv_half), Q = t - i * half;
-        const int p1 = pr[2 * Q], q1 = pr[2 * Q + 1];
-        if (q1 >= n) continue;
-        const double cQ = cs[2 * Q], sQ = cs[2 * Q + 1];
-        const double vp = V[i * ld + p1], vq = V[i * ld + q1];
-        V[i * ld + p1] = cQ * vp - sQ * vq;
-        V[i * ld + q1] = sQ * vp + cQ * vq;
+      __syncthreads();
+      for (int t = tid; t < n * half; t += NT) {  // A <- J^T A
+        const int P = t / n, j = t - P * n;
+        const int p = pr[2 * P], q = pr[2 * P + 1];
+        if (q >= n) continue;
+        const double c = cs[2 * P], s = cs[2 * P + 1];
+        const double ap = A[p * ld + j], aq = A[q * ld + j];
+        A[p * ld + j] = c * ap - s * aq;
+        A[q * ld + j] = s * ap + c * aq;
       }
       __syncthreads();
     }
@@ -125,7 +143,7 @@ __device__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr,
 }
 
 // order[i] = index of the i-th largest of d[0..n) (ties by index).
-__device__ void sort_desc(const double* d, int n, int* order) {
+__device__ __forceinline__ void sort_desc(const double* d, int n, int* order) {
   for (int i = threadIdx.x; i < n; i += NT) {
     int rk = 0;
     const double di = d[i];
@@ -139,7 +157,7 @@ __device__ void sort_desc(const double* d, int n, int* order) {
 // thread reads the pivot, the column below it is scaled, then the trailing
 // lower triangle is updated by a 32 x 32 thread grid.  Returns 0 or the
 // 1-based index of the first non-positive pivot (the pivot is then taken as 1).
-__device__ int chol_dev(double* A, int n, int lda, int* sinfo) {
+__device__ __forceinline__ int chol_dev(double* A, int n, int lda, int* sinfo) {
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   if (threadIdx.x == 0) *sinfo = 0;
   __syncthreads();
@@ -167,7 +185,7 @@ __device__ int chol_dev(double* A, int n, int lda, int* sinfo) {
 
 // X (r x s, stride ldx) <- (L L^T)^{-1} X: forward then backward row sweeps,
 // each step's rows (32 thread rows) and columns (32 thread columns) in parallel.
-__device__ void chol_solve_inplace(const double* L, int r, int ldl, double* X, int ldx, int s) {
+__device__ __forceinline__ void chol_solve_inplace(const double* L, int r, int ldl, double* X, int ldx, int s) {
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int m = 0; m < r; ++m) {  // forward: L y = x
     const double inv = 1.0 / L[m * ldl + m];
@@ -206,11 +224,15 @@ __device__ __forceinline__ double lane_of(double v, int lane) {  // v of `lane` 
 // Wave-level: factor the jb x jb block at A[j0][j0] (stride ld) in place (lower) and write its inverse to
 // Di (NB x NB, stride NBL; lower, zero above).  Returns 0 or the 1-based column of the first pivot <= 0
 // (taken as 1).  Called by all 64 lanes of one wave.
-__device__ int diag_factor_wave(double* A, int ld, int j0, int jb, double* Di) {
+
+__device__ __forceinline__ int diag_factor_wave(double* A, int ld, int j0, int jb, double* Di) {
   const int lane = threadIdx.x & 63;
-  double r[NB];
+  double r[NB], invd[NB];
 #pragma unroll
-  for (int t = 0; t < NB; ++t) r[t] = (lane < jb && t <= lane) ? A[(j0 + lane) * ld + j0 + t] : 0.0;
+  for (int t = 0; t < NB; ++t) {
+    r[t] = (lane < jb && t <= lane) ? A[(j0 + lane) * ld + j0 + t] : 0.0;
+    invd[t] = 1.0;
+  }
   int bad = 0;
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
@@ -220,8 +242,9 @@ __device__ int diag_factor_wave(double* A, int ld, int j0, int jb, double* Di) {
         if (!bad) bad = c + 1;
         d = 1.0;
       }
-      const double sq = sqrt(d), inv = 1.0 / sq;
-      r[c] = lane == c ? sq : (lane > c ? r[c] * inv : 0.0);
+      const double inv = rsqrt_nr(d);
+      invd[c] = inv;
+      r[c] = lane == c ? d * inv : (lane > c ? r[c] * inv : 0.0);
 #pragma unroll
       for (int q = c + 1; q < NB; ++q) {
         const double lqc = lane_of(r[c], q);  // L[q][c]
@@ -236,7 +259,7 @@ __device__ int diag_factor_wave(double* A, int ld, int j0, int jb, double* Di) {
     double acc = (i == lane) ? 1.0 : 0.0;
 #pragma unroll
     for (int t = 0; t < i; ++t) acc -= lane_of(r[t], i) * x[t];
-    x[i] = (i < jb) ? acc / lane_of(r[i], i) : 0.0;
+    x[i] = (i < jb) ? acc * invd[i] : 0.0;
   }
   if (lane < jb) {
 #pragma unroll
@@ -271,7 +294,7 @@ constexpr int NW = NT / 64;  // waves per workgroup
 // dimension hold the identity).  Dinv: np/NB diagonal-block inverses (NB x NBL each), Pn: np x NBL panel
 // scratch.  Panels and trailing updates are 16x16 MFMA tiles.  Returns 0 or the 1-based index of the first
 // pivot <= 0.
-__device__ int chol_blocked(double* A, int np, int ld, double* Dinv, double* Pn, int* sinfo) {
+__device__ __forceinline__ int chol_blocked(double* A, int np, int ld, double* Dinv, double* Pn, int* sinfo) {
   const int wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) *sinfo = 0;
   __syncthreads();
@@ -312,7 +335,7 @@ __device__ int chol_blocked(double* A, int np, int ld, double* Dinv, double* Pn,
 }
 
 // Diagonal-block inverses of an existing factor L (np x np, stride ld): one wave per block.
-__device__ void diag_inverses(const double* L, int np, int ld, double* Dinv) {
+__device__ __forceinline__ void diag_inverses(const double* L, int np, int ld, double* Dinv) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int bk = wave; bk < np / NB; bk += NW) {
     const int j0 = bk * NB;
@@ -334,7 +357,7 @@ __device__ void diag_inverses(const double* L, int np, int ld, double* Dinv) {
 
 // X (rp x cp, stride lx; rp, cp multiples of NB) <- (L L^T)^{-1} X by block rows: forward L Y = X, then
 // backward L^T X = Y.  Tb: NB x (cp + 1) scratch.
-__device__ void chol_solve_blocked(const double* L, int rp, int ld, const double* Dinv, double* X, int lx, int cp,
+__device__ __forceinline__ void chol_solve_blocked(const double* L, int rp, int ld, const double* Dinv, double* X, int lx, int cp,
                                    double* Tb) {
   const int wave = threadIdx.x >> 6, nbk = rp / NB, ct = cp / NB, lt = cp + 1;
   for (int bk = 0; bk < nbk; ++bk) {
@@ -383,7 +406,7 @@ __device__ void chol_solve_blocked(const double* L, int rp, int ld, const double
 
 // X = L^{-1} (np x np, stride ld, zero above the diagonal) from the factor and its diagonal-block inverses,
 // by block rows: X_ij = -L_ii^{-1} sum_{j <= t < i} L_it X_tj.  Tb: NB x (np + 1) scratch.
-__device__ void tri_inverse_blocked(const double* L, int np, int ld, const double* Dinv, double* X, double* Tb) {
+__device__ __forceinline__ void tri_inverse_blocked(const double* L, int np, int ld, const double* Dinv, double* X, double* Tb) {
   const int wave = threadIdx.x >> 6, lt = np + 1;
   for (int e = threadIdx.x; e < np * np; e += NT) {
     const int i = e / np, j = e - i * np;
@@ -416,7 +439,7 @@ struct CholWs {
   double *L, *X, *Dinv, *Pn, *Tb;
   int rp, cp, ldl, ldx;
 };
-__device__ CholWs chol_carve(double* base, int r, int c) {
+__device__ __forceinline__ CholWs chol_carve(double* base, int r, int c) {
   CholWs w;
   w.rp = pad16(r);
   w.cp = pad16(c);
@@ -433,10 +456,11 @@ __device__ CholWs chol_carve(double* base, int r, int c) {
 // Problem b: D (r0 x r0, ld r0) at D + b sD, leading rb = dims[b] block used; B, X likewise.  factor: D is
 // factored (L written back); otherwise D holds the factor from an earlier call.  In LDS the factor is padded
 // with the identity and the right-hand sides with zeros to whole 16-wide tiles.
+template <int kLds>
 __global__ __launch_bounds__(NT) void k_small_chol_solve(int r0, const int* __restrict__ dims, double* D, int64_t sD,
                                                          const double* B, int64_t ldb, int64_t sB, double* X,
                                                          int64_t ldx, int64_t sX, int s, int s0, double alpha,
-                                                         int* flag, int factor, double* gw, int64_t gws, int lds) {
+                                                         int* flag, int factor, double* gw, int64_t gws) {
   extern __shared__ double sm[];
   __shared__ int sinfo;
   const int b = blockIdx.x;
@@ -447,7 +471,7 @@ __global__ __launch_bounds__(NT) void k_small_chol_solve(int r0, const int* __re
   // rows r .. s0 - 1 of X are zero (directions this problem does not have)
   for (int e = threadIdx.x; e < (s0 - r) * s; e += NT) X[(r + e / s) * ldx + e % s] = 0.0;
   if (r == 0) return;
-  CholWs w = chol_carve(lds ? sm : gw + b * gws, r, s);
+  CholWs w = chol_carve(kLds ? sm : gw + b * gws, r, s);
   const int rp = w.rp, cp = w.cp;
   for (int e = threadIdx.x; e < rp * rp; e += NT) {
     const int i = e / rp, j = e - i * rp;
@@ -481,7 +505,7 @@ struct EvdSpace {
   int ld;
 };
 
-__device__ EvdSpace evd_space(int n, double* base, double* small_d, int* small_i) {
+__device__ __forceinline__ EvdSpace evd_space(int n, double* base, double* small_d, int* small_i) {
   EvdSpace e;
   e.ld = n + 1;
   e.A = base;
@@ -493,9 +517,9 @@ __device__ EvdSpace evd_space(int n, double* base, double* small_d, int* small_i
   return e;
 }
 
+template <int kLds>
 __global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, int64_t sG, double drop2, double* T,
-                                                   int64_t sT, int* out, const int* skip, double* gw, int64_t gws,
-                                                   int lds) {
+                                                   int64_t sT, int* out, const int* skip, double* gw, int64_t gws) {
   extern __shared__ double sm[];
   __shared__ double red[NT];
   __shared__ double sd[3 * SMAX];
@@ -504,7 +528,7 @@ __global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, int64
   if (skip && skip[b]) return;
   G += b * sG;
   T += b * sT;
-  EvdSpace w = evd_space(s, lds ? sm : gw + b * gws, sd, si);
+  EvdSpace w = evd_space(s, kLds ? sm : gw + b * gws, sd, si);
   const int ld = w.ld;
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
@@ -533,9 +557,10 @@ __global__ __launch_bounds__(NT) void k_small_svqb(int s, const double* G, int64
 
 // Problem b: G (s x s) at G + b sG; the leading n = dims[b] block is factored, everything else of Rinv and
 // Racc is zero.
+template <int kLds>
 __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restrict__ dims, const double* G, int64_t sG,
                                                      const double* shift_coef, double* Rinv, double* Racc, int init,
-                                                     int* flag, double* gw, int64_t gws, int lds, double certify,
+                                                     int* flag, double* gw, int64_t gws, double certify,
                                                      int* ok) {
   extern __shared__ double sm[];
   __shared__ int sinfo;
@@ -555,7 +580,7 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
   for (int i = threadIdx.x; i < n; i += NT) tr += G[i * s + i];
   tr = block_sum(tr, red);
   const double shift = (shift_coef ? shift_coef[b] : 0.0) * tr;
-  CholWs w = chol_carve(lds ? sm : gw + b * gws, n, n);
+  CholWs w = chol_carve(kLds ? sm : gw + b * gws, n, n);
   const int np = w.rp, ld = w.ldl;
   double* A = w.L;
   double* X = w.X;
@@ -622,9 +647,9 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
 // basis.  When a Cholesky C = L L^T succeeds with 1/||L^{-1}||_F^2 >= eps_rel trace(C) (a lower bound of
 // lambda_min against an upper bound of lambda_max), every eigenpair passes the threshold and
 // T = R C^{-1} R^T = H^T H with H = L^{-1} R^T: the EVD of C is skipped.
+template <int kLds>
 __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double* C, const double* R, double eps_rel,
-                                                      double* Wk, double* Ek, int* out, double* gw, int64_t gws,
-                                                      int lds) {
+                                                      double* Wk, double* Ek, int* out, double* gw, int64_t gws) {
   extern __shared__ double sm[];
   __shared__ double red[NT];
   __shared__ double sd[3 * SMAX];
@@ -639,7 +664,7 @@ __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double
   Wk += b * int64_t(s) * k;
   Ek += b * int64_t(k);
   out += 2 * b;
-  CholWs cw = chol_carve(lds ? sm : gw + b * gws, s, s);  // regions L and X double as the EVD's matrices
+  CholWs cw = chol_carve(kLds ? sm : gw + b * gws, s, s);  // regions L and X double as the EVD's matrices
   const int np = cw.rp, ld = cw.ldl;
   double* A = cw.L;
   double* V = cw.X;
@@ -789,13 +814,13 @@ __global__ void k_small_rowscale(int k, int ncols, const double* sigma, int64_t 
   c[b * sc + i * ldc + j] *= sigma[b * ssig + i];
 }
 
-__global__ __launch_bounds__(NT) void k_small_sym_evd(int m, const double* Ain, double* W, double* E, double* gw,
-                                                      int lds) {
+template <int kLds>
+__global__ __launch_bounds__(NT) void k_small_sym_evd(int m, const double* Ain, double* W, double* E, double* gw) {
   extern __shared__ double sm[];
   __shared__ double red[NT];
   __shared__ double sd[3 * SMAX];
   __shared__ int si[3 * SMAX];
-  EvdSpace w = evd_space(m, lds ? sm : gw, sd, si);
+  EvdSpace w = evd_space(m, kLds ? sm : gw, sd, si);
   const int ld = w.ld;
   for (int e = threadIdx.x; e < m * m; e += NT) {
     const int i = e / m, j = e % m;
@@ -901,8 +926,12 @@ void small_chol_solve(Batch bt, int r, double* D, int64_t sD, const double* B, i
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
   const size_t el = chol_ws(r, s);
   const int mode = ws_mode(ws, el, r, s);
-  k_small_chol_solve<<<bt.nb, NT, dyn_lds(mode, el), st>>>(r, bt.dims, D, sD, B, ldb, sB, X, ldx, sX, s, s0, alpha,
-                                                           flag, 1, ws.p, ws.stride, mode);
+  if (mode)
+    k_small_chol_solve<1><<<bt.nb, NT, dyn_lds(mode, el), st>>>(r, bt.dims, D, sD, B, ldb, sB, X, ldx, sX, s, s0,
+                                                                alpha, flag, 1, ws.p, ws.stride);
+  else
+    k_small_chol_solve<0><<<bt.nb, NT, 0, st>>>(r, bt.dims, D, sD, B, ldb, sB, X, ldx, sX, s, s0, alpha, flag, 1, ws.p,
+                                               ws.stride);
   NS_LAUNCH_CHECK();
 }
 
@@ -913,8 +942,12 @@ void small_chol_apply(Batch bt, int r, const double* L, int64_t sL, const double
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
   const size_t el = chol_ws(r, s);
   const int mode = ws_mode(ws, el, r, s);
-  k_small_chol_solve<<<bt.nb, NT, dyn_lds(mode, el), st>>>(r, bt.dims, const_cast<double*>(L), sL, B, ldb, sB, X,
-                                                           ldx, sX, s, s0, alpha, nullptr, 0, ws.p, ws.stride, mode);
+  if (mode)
+    k_small_chol_solve<1><<<bt.nb, NT, dyn_lds(mode, el), st>>>(r, bt.dims, const_cast<double*>(L), sL, B, ldb, sB,
+                                                                X, ldx, sX, s, s0, alpha, nullptr, 0, ws.p, ws.stride);
+  else
+    k_small_chol_solve<0><<<bt.nb, NT, 0, st>>>(r, bt.dims, const_cast<double*>(L), sL, B, ldb, sB, X, ldx, sX, s, s0,
+                                               alpha, nullptr, 0, ws.p, ws.stride);
   NS_LAUNCH_CHECK();
 }
 
@@ -923,7 +956,10 @@ void small_svqb(int nb, int s, const double* G, int64_t sG, double drop2, double
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
   const size_t el = evd_elems(s);
   const int mode = ws_mode(ws, el, s, s);
-  k_small_svqb<<<nb, NT, dyn_lds(mode, el), st>>>(s, G, sG, drop2, T, sT, out, skip, ws.p, ws.stride, mode);
+  if (mode)
+    k_small_svqb<1><<<nb, NT, dyn_lds(mode, el), st>>>(s, G, sG, drop2, T, sT, out, skip, ws.p, ws.stride);
+  else
+    k_small_svqb<0><<<nb, NT, 0, st>>>(s, G, sG, drop2, T, sT, out, skip, ws.p, ws.stride);
   NS_LAUNCH_CHECK();
 }
 
@@ -932,8 +968,12 @@ void small_cholqr(Batch bt, int s, const double* G, int64_t sG, const double* sh
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
   const size_t el = chol_ws(s, s);
   const int mode = ws_mode(ws, el, s, s);
-  k_small_cholqr<<<bt.nb, NT, dyn_lds(mode, el), st>>>(s, bt.dims, G, sG, shift, Rinv, Racc, init, flag, ws.p,
-                                                       ws.stride, mode, certify, ok);
+  if (mode)
+    k_small_cholqr<1><<<bt.nb, NT, dyn_lds(mode, el), st>>>(s, bt.dims, G, sG, shift, Rinv, Racc, init, flag, ws.p,
+                                                            ws.stride, certify, ok);
+  else
+    k_small_cholqr<0><<<bt.nb, NT, 0, st>>>(s, bt.dims, G, sG, shift, Rinv, Racc, init, flag, ws.p, ws.stride, certify,
+                                           ok);
   NS_LAUNCH_CHECK();
 }
 
@@ -942,7 +982,10 @@ void small_nystrom(int nb, int s, int k, const double* C, const double* R, doubl
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
   const size_t el = chol_ws(s, s);
   const int mode = ws_mode(ws, el, s, s);
-  k_small_nystrom<<<nb, NT, dyn_lds(mode, el), st>>>(s, k, C, R, eps_rel, Wk, Ek, out, ws.p, ws.stride, mode);
+  if (mode)
+    k_small_nystrom<1><<<nb, NT, dyn_lds(mode, el), st>>>(s, k, C, R, eps_rel, Wk, Ek, out, ws.p, ws.stride);
+  else
+    k_small_nystrom<0><<<nb, NT, 0, st>>>(s, k, C, R, eps_rel, Wk, Ek, out, ws.p, ws.stride);
   NS_LAUNCH_CHECK();
 }
 
@@ -972,7 +1015,10 @@ void small_sym_evd(int m, const double* A, double* W, double* E, const SmallWs& 
   if (m > SMAX) fail(INVALID_ARG, "matrix too large for the small dense kernels (limit 256)");
   const size_t el = evd_elems(m);
   const int mode = ws_mode(ws, el, m, m);
-  k_small_sym_evd<<<1, NT, dyn_lds(mode, el), st>>>(m, A, W, E, ws.p, mode);
+  if (mode)
+    k_small_sym_evd<1><<<1, NT, dyn_lds(mode, el), st>>>(m, A, W, E, ws.p);
+  else
+    k_small_sym_evd<0><<<1, NT, 0, st>>>(m, A, W, E, ws.p);
   NS_LAUNCH_CHECK();
 }
 
