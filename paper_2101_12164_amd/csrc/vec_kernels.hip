@@ -86,7 +86,8 @@ __global__ __launch_bounds__(1024) void k_gram_partial(Seg sg, const TA* __restr
 typedef double gv4d __attribute__((ext_vector_type(4)));
 constexpr int GM_R = 32;       // rows per LDS batch
 constexpr int GM_WAVES = 8;    // waves per workgroup
-constexpr int GM_MAXT = 16;    // output tiles per wave
+constexpr int GM_MAXT = 8;     // output tiles per wave
+constexpr int GM_PRE = 16;     // prefetched values per thread: GM_R (wa + wb) <= GM_PRE * 64 GM_WAVES
 template <class TA, class TB>
 __global__ __launch_bounds__(GM_WAVES * 64) void k_gram_mfma(Seg sg, const TA* __restrict__ A, int64_t lda, int ra,
                                                           const TB* __restrict__ B, int64_t ldb, int rb,
@@ -98,22 +99,47 @@ __global__ __launch_bounds__(GM_WAVES * 64) void k_gram_mfma(Seg sg, const TA* _
   const int ta = wa / 16, tb = wb / 16, T = ta * tb;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  constexpr int NTH = GM_WAVES * 64;
+  const int na = (GM_R * wa + NTH - 1) / NTH, nb = (GM_R * wb + NTH - 1) / NTH;  // <= GM_PRE together
   int64_t r0, r1;
   chunk_rows(sg, blockIdx.x, r0, r1);
   gv4d acc[GM_MAXT];
 #pragma unroll
   for (int q = 0; q < GM_MAXT; ++q) acc[q] = gv4d{0.0, 0.0, 0.0, 0.0};
+  // the next batch of rows is read into registers while the current one is multiplied
+  double pre[GM_PRE];
+  auto fetch = [&](int64_t rs) {
+    const int nr = int(r1 - rs < GM_R ? r1 - rs : GM_R);
+#pragma unroll
+    for (int q = 0; q < GM_PRE; ++q) {
+      double v = 0.0;
+      if (q < na) {
+        const int e = threadIdx.x + q * NTH;
+        const int rr = e / wa, c = e - rr * wa;
+        if (e < GM_R * wa && rr < nr && c < ra) v = double(A[(rs + rr) * lda + c]);
+      } else if (q < na + nb) {
+        const int e = threadIdx.x + (q - na) * NTH;
+        const int rr = e / wb, c = e - rr * wb;
+        if (e < GM_R * wb && rr < nr && c < rb) v = double(B[(rs + rr) * ldb + c]);
+      }
+      pre[q] = v;
+    }
+  };
+  if (r0 < r1) fetch(r0);
   for (int64_t rs = r0; rs < r1; rs += GM_R) {
     const int nr = int(r1 - rs < GM_R ? r1 - rs : GM_R);
     __syncthreads();
-    for (int e = threadIdx.x; e < GM_R * wa; e += blockDim.x) {
-      const int rr = e / wa, c = e - rr * wa;
-      sA[e] = (rr < nr && c < ra) ? double(A[(rs + rr) * lda + c]) : 0.0;
+#pragma unroll
+    for (int q = 0; q < GM_PRE; ++q) {
+      if (q < na) {
+        const int e = threadIdx.x + q * NTH;
+        if (e < GM_R * wa) sA[e] = pre[q];
+      } else if (q < na + nb) {
+        const int e = threadIdx.x + (q - na) * NTH;
+        if (e < GM_R * wb) sB[e] = pre[q];
+      }
     }
-    for (int e = threadIdx.x; e < GM_R * wb; e += blockDim.x) {
-      const int rr = e / wb, c = e - rr * wb;
-      sB[e] = (rr < nr && c < rb) ? double(B[(rs + rr) * ldb + c]) : 0.0;
-    }
+    if (rs + GM_R < r1) fetch(rs + GM_R);
     __syncthreads();
     const int kend = (nr + 3) & ~3;
 #pragma unroll
@@ -148,70 +174,119 @@ __global__ __launch_bounds__(GM_WAVES * 64) void k_gram_mfma(Seg sg, const TA* _
   }
 }
 
-// sum of the chunk partials of segment p in a fixed order
-__device__ __forceinline__ double chunk_sum(const Seg& sg, int p, int nout, int o, const double* __restrict__ part) {
+// G_p[o] = alpha * (sum of segment p's chunk partials of output o) + beta * G_p[o].  TX outputs per block;
+// the TY = 1024 / TX threads of an output take the chunks c = ty, ty + TY, ... and a fixed tree combines them.
+template <int TX>
+__global__ __launch_bounds__(1024) void k_seg_final(Seg sg, int nout, const double* __restrict__ part,
+                                                    double* __restrict__ G, int64_t gstride, double alpha,
+                                                    double beta) {
+  constexpr int TY = 1024 / TX;
+  __shared__ double red[1024];
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int o = blockIdx.x * TX + tx;
+  const int p = blockIdx.y;
   const int c0 = sg.coff[p], nch = sg.coff[p + 1] - c0;
-  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int c = 0;
-  for (; c + 8 <= nch; c += 8)
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] += part[int64_t(c0 + c + u) * nout + o];
-  for (; c < nch; ++c) s[0] += part[int64_t(c0 + c) * nout + o];
-  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  double s = 0.0;
+  if (o < nout)
+    for (int c = ty; c < nch; c += TY) s += part[int64_t(c0 + c) * nout + o];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = TY / 2; h > 0; h >>= 1) {
+    if (ty < h) red[threadIdx.x] += red[threadIdx.x + h * TX];
+    __syncthreads();
+  }
+  if (ty == 0 && o < nout) {
+    double* g = G + int64_t(p) * gstride + o;
+    *g = alpha * red[tx] + (beta != 0.0 ? beta * *g : 0.0);
+  }
 }
 
-__global__ void k_seg_final(Seg sg, int nout, const double* __restrict__ part, double* __restrict__ G, int64_t gstride,
-                            double alpha, double beta) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
-  if (o >= nout) return;
-  const double t = chunk_sum(sg, p, nout, o, part);
-  double* g = G + int64_t(p) * gstride + o;
-  *g = alpha * t + (beta != 0.0 ? beta * *g : 0.0);
+void seg_final(const Seg& sg, int nout, const double* part, double* G, int64_t gstride, double alpha, double beta,
+               hipStream_t st) {
+  if (nout >= 16) {
+    k_seg_final<64><<<dim3((nout + 63) / 64, sg.n), 1024, 0, st>>>(sg, nout, part, G, gstride, alpha, beta);
+  } else {
+    k_seg_final<1><<<dim3(nout, sg.n), 1024, 0, st>>>(sg, nout, part, G, gstride, alpha, beta);
+  }
+  NS_LAUNCH_CHECK();
 }
 
 // Out[r, c] = beta * Out[r, c] + gamma * (sum_m X[r, m] M_p[m, c] + sum_m X2[r, m] M2_p[m, c]) on 64-row tiles
-// that never straddle two segments.
+// that never straddle two segments, in FP64 on MFMA.  A workgroup computes a 64 x 64 output block (wave w:
+// rows 16 w .. 16 w + 15, four 16-column tiles); the reduction index runs over [X | X2] in batches of 32
+// staged through LDS, the next batch read into registers while the current one is multiplied.
+constexpr int TS_K = 32;
 template <class T>
-__global__ __launch_bounds__(256) void k_ts_update(Seg sg, int ncols, T* __restrict__ Out, int64_t ldo, double beta,
-                                                   double gamma, const T* __restrict__ X, int64_t ldx, int rm,
-                                                   const double* __restrict__ M, int64_t ldm, int64_t mstride,
-                                                   const T* __restrict__ X2, int64_t ldx2, int rm2,
-                                                   const double* __restrict__ M2, int64_t ldm2, int64_t m2stride) {
-  extern __shared__ double sm[];
-  double* sM = sm;             // rm x 32
-  double* sM2 = sm + rm * 32;  // rm2 x 32
+__global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* __restrict__ Out, int64_t ldo, double beta,
+                                                 double gamma, const T* __restrict__ X, int64_t ldx, int rm,
+                                                 const double* __restrict__ M, int64_t ldm, int64_t mstride,
+                                                 const T* __restrict__ X2, int64_t ldx2, int rm2,
+                                                 const double* __restrict__ M2, int64_t ldm2, int64_t m2stride) {
+  __shared__ double sX[64 * (TS_K + 1)];
+  __shared__ double sM[TS_K * 65];
   const int p = seg_of(sg.toff, sg.n, blockIdx.x);
   const int64_t rbase = sg.off[p] + int64_t(blockIdx.x - sg.toff[p]) * 64;
   const int64_t rend = sg.off[p + 1];
   const double* Mp = M + int64_t(p) * mstride;
-  const double* M2p = M2 + int64_t(p) * m2stride;
-  const int c0 = blockIdx.y * 32;
-  for (int e = threadIdx.x; e < rm * 32; e += blockDim.x) {
-    const int m = e / 32, c = e % 32;
-    sM[e] = (c0 + c < ncols) ? Mp[int64_t(m) * ldm + c0 + c] : 0.0;
-  }
-  for (int e = threadIdx.x; e < rm2 * 32; e += blockDim.x) {
-    const int m = e / 32, c = e % 32;
-    sM2[e] = (c0 + c < ncols) ? M2p[int64_t(m) * ldm2 + c0 + c] : 0.0;
-  }
-  __syncthreads();
-  const int c = threadIdx.x & 31;
-  if (c0 + c >= ncols) return;
-  for (int rr = threadIdx.x >> 5; rr < 64; rr += 8) {
-    const int64_t r = rbase + rr;
-    if (r >= rend) break;
-    double acc = 0.0;
-    const T* xr = X + r * ldx;
-    for (int m = 0; m < rm; ++m) acc += double(xr[m]) * sM[m * 32 + c];
-    if (rm2) {
-      const T* x2 = X2 + r * ldx2;
-      for (int m = 0; m < rm2; ++m) acc += double(x2[m]) * sM2[m * 32 + c];
+  const double* M2p = M2 ? M2 + int64_t(p) * m2stride : nullptr;
+  const int c0 = blockIdx.y * 64;
+  const int K = rm + rm2;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  gv4d acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = gv4d{0.0, 0.0, 0.0, 0.0};
+  double px[8], pm[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {  // X batch: 64 rows x TS_K
+      const int e = threadIdx.x + 256 * q, r = e / TS_K, k = k0 + e % TS_K;
+      const int64_t row = rbase + r;
+      double v = 0.0;
+      if (row < rend && k < K) v = k < rm ? double(X[row * ldx + k]) : double(X2[row * ldx2 + (k - rm)]);
+      px[q] = v;
     }
-    acc *= gamma;
-    if (beta != 0.0) acc += beta * double(Out[r * ldo + c0 + c]);
-    Out[r * ldo + c0 + c] = T(acc);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {  // M batch: TS_K x 64
+      const int e = threadIdx.x + 256 * q, kk = e / 64, c = c0 + e % 64, k = k0 + kk;
+      double v = 0.0;
+      if (c < ncols && k < K) v = k < rm ? Mp[int64_t(k) * ldm + c] : M2p[int64_t(k - rm) * ldm2 + c];
+      pm[q] = v;
+    }
+  };
+  if (K > 0) fetch(0);
+  for (int k0 = 0; k0 < K; k0 += TS_K) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      sX[(e / TS_K) * (TS_K + 1) + e % TS_K] = px[q];
+      sM[(e / 64) * 65 + e % 64] = pm[q];
+    }
+    if (k0 + TS_K < K) fetch(k0 + TS_K);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TS_K; kk += 4) {
+      const double a = sX[(16 * w + li) * (TS_K + 1) + kk + lk];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double b = sM[(kk + lk) * 65 + 16 * t + li];
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+      }
+    }
   }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = rbase + 16 * w + 4 * v + lk;
+      const int c = c0 + 16 * t + li;
+      if (r < rend && c < ncols) {
+        double y = gamma * acc[t][v];
+        if (beta != 0.0) y += beta * double(Out[r * ldo + c]);
+        Out[r * ldo + c] = T(y);
+      }
+    }
 }
 
 template <class T, class U>
@@ -266,12 +341,18 @@ __global__ __launch_bounds__(256) void k_pcg_wr(Seg sg, PcgState S, double* __re
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// ||r||^2 per problem from the chunk partials, then the stopping test of iteration j.
-__global__ void k_pcg_check(Seg sg, PcgState S, const double* __restrict__ part) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+// ||r||^2 per problem from the chunk partials (one block per problem, fixed summation order), then the
+// stopping test of iteration j.
+__global__ __launch_bounds__(256) void k_pcg_check(Seg sg, PcgState S, const double* __restrict__ part) {
+  __shared__ double red[256];
+  const int g = blockIdx.x;
   const int j = *S.j;
-  if (g >= sg.n || S.done[g] || j >= S.maxit) return;
-  const double rn2 = chunk_sum(sg, g, 1, 0, part);
+  if (S.done[g] || j >= S.maxit) return;
+  const int c0 = sg.coff[g], nch = sg.coff[g + 1] - c0;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < nch; c += 256) s += part[c0 + c];
+  const double rn2 = block_sum256(s, red);
+  if (threadIdx.x != 0) return;
   double* ps = S.ps + int64_t(g) * PS;
   ps[PS_RN2] = rn2;
   const double rel = sqrt(rn2) / ps[PS_NF];
@@ -411,15 +492,15 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
   if (nout > 1024 * GRAM_MAXQ) fail(INVALID_ARG, "Gram product too wide");
   const int wa = (ra + 15) & ~15, wb = (rb + 15) & ~15;
   const size_t lds_m = size_t(GM_R) * (wa + wb) * sizeof(double);
-  if ((wa / 16) * (wb / 16) <= GM_WAVES * GM_MAXT && lds_m <= 64 * 1024) {
+  if ((wa / 16) * (wb / 16) <= GM_WAVES * GM_MAXT && GM_R * (wa + wb) <= GM_PRE * GM_WAVES * 64 &&
+      lds_m <= 64 * 1024) {
     k_gram_mfma<TA, TB><<<sg.nchunk, GM_WAVES * 64, lds_m, st>>>(sg, A, lda, ra, B, ldb, rb, work);
   } else {
     const size_t lds = size_t(GRAM_RB) * (ra + rb) * sizeof(double);
     k_gram_partial<TA, TB><<<sg.nchunk, 1024, lds, st>>>(sg, A, lda, ra, B, ldb, rb, work);
   }
   NS_LAUNCH_CHECK();
-  k_seg_final<<<dim3((nout + 255) / 256, sg.n), 256, 0, st>>>(sg, nout, work, G, gstride, alpha, beta);
-  NS_LAUNCH_CHECK();
+  seg_final(sg, nout, work, G, gstride, alpha, beta, st);
 }
 
 size_t gram_work_elems(const Seg& sg, int maxw) { return size_t(std::max(sg.nchunk, 1)) * maxw * maxw; }
@@ -429,10 +510,9 @@ void ts_update(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, doubl
                int rm, const double* M, int64_t ldm, int64_t mstride, const T* X2, int64_t ldx2, int rm2,
                const double* M2, int64_t ldm2, int64_t m2stride, hipStream_t st) {
   if (sg.rows == 0 || ncols == 0) return;
-  dim3 g(unsigned(sg.ntile), unsigned((ncols + 31) / 32));
-  const size_t lds = size_t(rm + rm2) * 32 * sizeof(double);
-  k_ts_update<T><<<g, 256, lds, st>>>(sg, ncols, Out, ldo, beta, gamma, X, ldx, rm, M, ldm, mstride, X2, ldx2, rm2,
-                                      M2, ldm2, m2stride);
+  dim3 g(unsigned(sg.ntile), unsigned((ncols + 63) / 64));
+  k_ts_mfma<T><<<g, 256, 0, st>>>(sg, ncols, Out, ldo, beta, gamma, X, ldx, rm, M, ldm, mstride, X2, ldx2, rm2, M2,
+                                  ldm2, m2stride);
   NS_LAUNCH_CHECK();
 }
 
@@ -449,8 +529,7 @@ void col_sumsq(const Seg& sg, int ncols, const T* X, int64_t ldx, double* out, d
   if (ncols == 0 || sg.n == 0) return;
   k_colsq_partial<T><<<sg.nchunk, 256, 0, st>>>(sg, ncols, X, ldx, work);
   NS_LAUNCH_CHECK();
-  k_seg_final<<<dim3((ncols + 255) / 256, sg.n), 256, 0, st>>>(sg, ncols, work, out, ncols, 1.0, 0.0);
-  NS_LAUNCH_CHECK();
+  seg_final(sg, ncols, work, out, ncols, 1.0, 0.0, st);
 }
 
 void dot(const Seg& sg, const double* x, const double* y, double* out, int64_t ostride, double* work,
@@ -458,15 +537,14 @@ void dot(const Seg& sg, const double* x, const double* y, double* out, int64_t o
   if (sg.n == 0) return;
   k_dot_partial<<<sg.nchunk, 256, 0, st>>>(sg, x, y, work);
   NS_LAUNCH_CHECK();
-  k_seg_final<<<dim3(1, sg.n), 256, 0, st>>>(sg, 1, work, out, ostride, 1.0, 0.0);
-  NS_LAUNCH_CHECK();
+  seg_final(sg, 1, work, out, ostride, 1.0, 0.0, st);
 }
 
 void pcg_update_wr(const Seg& sg, const PcgState& s, double* w, double* r, const double* p, const double* q,
                    double* work, hipStream_t st) {
   k_pcg_wr<<<sg.nchunk, 256, 0, st>>>(sg, s, w, r, p, q, work);
   NS_LAUNCH_CHECK();
-  k_pcg_check<<<(sg.n + 255) / 256, 256, 0, st>>>(sg, s, work);
+  k_pcg_check<<<sg.n, 256, 0, st>>>(sg, s, work);
   NS_LAUNCH_CHECK();
 }
 
