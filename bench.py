@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trsm-cols", type=int, default=0)
+    ap.add_argument("--timing", choices=["dominant", "all", "none"], default="dominant",
+                    help="kernel families timed with HIP events in the measured steps")
     ap.add_argument("--pcg-graph", type=int, default=0,
                     help="PCG iterations per replayed HIP graph (0: library default, -1: plain launches)")
     ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
@@ -57,10 +59,23 @@ def parse():
     return ap.parse_args()
 
 
+def dominant_families(stats, scope="dominant"):
+    """Kernel families to time in the measured steps: the one with the most device time (the two
+    factorisation families together), all of them, or none."""
+    if scope == "none":
+        return []
+    if scope == "all":
+        return list(stats)
+    dom = max(stats, key=lambda f: stats[f]["ms"])
+    return ["chol_update", "chol_panel"] if dom.startswith("chol") else [dom]
+
+
 def roofline(stats, steps):
     """Roofline of the dominant kernel family from the live HIP-event totals."""
     dom = max(stats, key=lambda f: stats[f]["ms"])
     d = stats[dom]
+    if not d["launches"]:
+        return None
     avg_ms = d["ms"] / max(d["launches"], 1)
     if dom.startswith("chol"):
         # factorisation: both kernel families together, flop bound (FP64 MFMA)
@@ -398,11 +413,15 @@ def main():
         return si, info
 
     main_prec = ns.NS_FP32 if args.prec == "fp32" else ns.NS_FP64
-    for _ in range(args.warmup):
+    # warmup with every kernel family timed: it names the dominant family, the only one timed in the
+    # measured steps (events around every launch would perturb the measured throughput)
+    ns.nystrom_schur_kernel_timing(True)
+    for _ in range(max(args.warmup, 1)):
         step(main_prec)
         print("warmup step done", file=sys.stderr, flush=True)
-
-    ns.nystrom_schur_kernel_timing(True)
+    warm = {f: ns.nystrom_schur_kernel_stats(f) for f in ns.KERNEL_FAMILIES}
+    timed = dominant_families(warm, args.timing)
+    ns.nystrom_schur_kernel_timing_families(timed)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []

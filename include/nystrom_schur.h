@@ -293,6 +293,11 @@ const char* nystrom_schur_mlp_last_error(ns_mlp m);
  * calling it also resets the accumulated totals.  Process-wide. */
 void nystrom_schur_kernel_timing(int32_t enable);
 
+/* As nystrom_schur_kernel_timing, for the families whose bit is set in mask
+ * (bit f = the f-th family in the list below, from 0); mask 0 turns timing
+ * off.  Timing fewer families perturbs the timed run less. */
+void nystrom_schur_kernel_timing_families(uint32_t mask);
+
 /* Accumulated device time (milliseconds, from the events), launch count and
  * algorithmic work (bytes the method must move, flops it must compute: the
  * unpadded dense factor once per sweep, no re-reads) of one kernel family

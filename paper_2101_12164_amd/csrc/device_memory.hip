@@ -1,12 +1,18 @@
-// Stream-ordered device memory and pinned staging of host-to-device copies.
+// Device memory cache and pinned staging of host-to-device copies.
 //
-// hipMalloc and hipFree wait for the device (hipFree synchronises it), so a
-// setup made of many short launches with buffers allocated and freed between
-// them would leave the GPU idle at every allocation.  Buffers are instead
-// taken from the device's default memory pool in stream order, and metadata
-// uploads go through a pinned staging area so the host never waits on them.
+// hipMalloc and hipFree (and their stream-ordered forms) cost tens to hundreds
+// of microseconds per call and hipFree synchronises the device, so a setup
+// made of many short launches with buffers allocated and freed between them
+// would spend milliseconds in the allocator.  Freed buffers are instead kept
+// in a per-device cache and handed out again: a block freed on the calling
+// stream is reused at once (stream order protects the work still reading
+// it), a block freed on another stream once an event recorded at the free has
+// completed.  Metadata uploads go through a pinned staging area so the host
+// never waits on them.
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <unordered_map>
 
 #include "ns_internal.h"
 
@@ -20,23 +26,39 @@ hipStream_t& alloc_stream() {
 namespace {
 
 constexpr int MAX_DEVICES = 64;
-std::once_flag g_pool_once[MAX_DEVICES];
 
-// Keep freed pool memory for reuse instead of returning it at each synchronisation.
-void keep_pool_memory(int dev) {
-  hipMemPool_t pool = nullptr;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-  }
-  (void)hipGetLastError();
+struct Block {
+  void* p = nullptr;
+  size_t size = 0;
+  int dev = 0;
+  hipStream_t st = nullptr;  // stream of the last free
+  hipEvent_t ev = nullptr;   // recorded on st at the last free
+};
+
+struct Cache {
+  std::mutex mu;
+  std::multimap<size_t, Block> idle[MAX_DEVICES];  // freed blocks by size
+  std::unordered_map<void*, Block> live;
+};
+
+Cache& cache() {
+  static Cache* c = new Cache();  // process lifetime: the blocks are returned when the process ends
+  return *c;
 }
 
-// Return the pool's unused memory to the device (before retrying an allocation that failed).
-void trim_pool(int dev) {
-  hipMemPool_t pool = nullptr;
+size_t round_size(size_t b) {
+  const size_t small = size_t(1) << 20, big = size_t(2) << 20;
+  return b <= small ? (b + 511) & ~size_t(511) : (b + big - 1) / big * big;
+}
+
+// Return every idle block of device dev to the driver (before retrying an allocation that failed).
+void release_idle(Cache& c, int dev) {
   (void)hipDeviceSynchronize();
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) (void)hipMemPoolTrimTo(pool, 0);
+  for (auto& kv : c.idle[dev]) {
+    (void)hipFree(kv.second.p);
+    if (kv.second.ev) (void)hipEventDestroy(kv.second.ev);
+  }
+  c.idle[dev].clear();
   (void)hipGetLastError();
 }
 
@@ -79,24 +101,60 @@ bool staging_ready(Staging& s) {
 void* dev_alloc(size_t bytes) {
   int dev = 0;
   NS_HIP(hipGetDevice(&dev));
-  if (dev >= 0 && dev < MAX_DEVICES) std::call_once(g_pool_once[dev], keep_pool_memory, dev);
-  void* p = nullptr;
-  hipError_t e = hipMallocAsync(&p, bytes, alloc_stream());
+  if (dev < 0 || dev >= MAX_DEVICES) fail(HIP, "device index out of range");
+  const size_t size = round_size(bytes);
+  const size_t limit = size + size / 4 + 4096;  // reuse blocks up to a quarter larger
+  hipStream_t st = alloc_stream();
+  Cache& c = cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  auto& idle = c.idle[dev];
+  for (auto it = idle.lower_bound(size); it != idle.end() && it->first <= limit; ++it) {
+    Block& b = it->second;
+    if (b.st == st || hipEventQuery(b.ev) == hipSuccess) {
+      Block blk = b;
+      idle.erase(it);
+      c.live[blk.p] = blk;
+      return blk.p;
+    }
+  }
+  (void)hipGetLastError();  // hipEventQuery reports not-ready as an error code
+  Block blk;
+  blk.size = size;
+  blk.dev = dev;
+  hipError_t e = hipMalloc(&blk.p, size);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    trim_pool(dev);
-    p = nullptr;
-    e = hipMallocAsync(&p, bytes, alloc_stream());
+    release_idle(c, dev);
+    blk.p = nullptr;
+    e = hipMalloc(&blk.p, size);
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     fail(OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   }
-  return p;
+  c.live[blk.p] = blk;
+  return blk.p;
 }
 
 void dev_free(void* p) {
-  if (p) (void)hipFreeAsync(p, alloc_stream());
+  if (!p) return;
+  Cache& c = cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  auto it = c.live.find(p);
+  if (it == c.live.end()) return;
+  Block b = it->second;
+  c.live.erase(it);
+  b.st = alloc_stream();
+  if (!b.ev && hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) b.ev = nullptr;
+  if (!b.ev || hipEventRecord(b.ev, b.st) != hipSuccess) {
+    // no event to order a reuse by: keep the block out of the cache
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(b.st);
+    (void)hipFree(b.p);
+    if (b.ev) (void)hipEventDestroy(b.ev);
+    return;
+  }
+  c.idle[b.dev].emplace(b.size, b);
 }
 
 void upload(void* dst, const void* src, size_t bytes, hipStream_t st) {

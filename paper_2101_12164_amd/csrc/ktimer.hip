@@ -25,6 +25,7 @@ struct Rec {
 struct KTimer {
   std::mutex mu;
   bool on = false;
+  uint32_t mask = 0;  // families timed (bit f = family f)
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
   double total_ms[KF_COUNT] = {};
@@ -69,7 +70,7 @@ void resolve(KTimer& t) {
 KScope::KScope(int fam_, hipStream_t st_, double bytes_, double flops_)
     : fam(fam_), st(st_), bytes(bytes_), flops(flops_) {
   KTimer& t = timer();
-  on = t.on;
+  on = t.on && ((t.mask >> fam_) & 1u);
   if (!on) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
@@ -92,7 +93,7 @@ KScope::~KScope() {
 void kscope_add_work(int fam, double bytes, double flops) {
   KTimer& t = timer();
   std::lock_guard<std::mutex> g(t.mu);
-  if (!t.on || fam < 0 || fam >= KF_COUNT) return;
+  if (!t.on || fam < 0 || fam >= KF_COUNT || !((t.mask >> fam) & 1u)) return;
   t.bytes[fam] += bytes;
   t.flops[fam] += flops;
 }
@@ -101,7 +102,7 @@ void kscope_add_work(int fam, double bytes, double flops) {
 
 extern "C" {
 
-void nystrom_schur_kernel_timing(int32_t enable) {
+void nystrom_schur_kernel_timing_families(uint32_t mask) {
   ns::KTimer& t = ns::timer();
   std::lock_guard<std::mutex> g(t.mu);
   try {
@@ -112,8 +113,11 @@ void nystrom_schur_kernel_timing(int32_t enable) {
   std::memset(t.count, 0, sizeof(t.count));
   std::memset(t.bytes, 0, sizeof(t.bytes));
   std::memset(t.flops, 0, sizeof(t.flops));
-  t.on = enable != 0;
+  t.mask = mask;
+  t.on = mask != 0;
 }
+
+void nystrom_schur_kernel_timing(int32_t enable) { nystrom_schur_kernel_timing_families(enable ? ~0u : 0u); }
 
 ns_status nystrom_schur_kernel_stats(const char* family, double* total_ms, int64_t* launches, double* bytes,
                                      double* flops) {

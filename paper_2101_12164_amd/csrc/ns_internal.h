@@ -27,13 +27,13 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 #define NS_HIP(call) ::ns::hip_check((call), #call, __FILE__, __LINE__)
 #define NS_LAUNCH_CHECK() ::ns::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
 
-// Device memory is stream-ordered: every library call sets the stream its
-// buffers are allocated and freed on (StreamScope), allocations come from the
-// device's default memory pool (hipMallocAsync) and frees are queued behind
-// the work already on that stream (hipFreeAsync), so neither waits for the
-// device.  The pool keeps freed memory for reuse by later calls (its release
-// threshold is raised once per device) instead of returning it at every
-// synchronisation.
+// Device memory comes from a per-device cache of blocks: every library call
+// sets the stream its buffers are allocated and freed on (StreamScope); a
+// freed block is reused at once by later allocations on the same stream (work
+// already queued on it still reads the block before any new work) and by other
+// streams once an event recorded at the free has completed.  Blocks are
+// obtained with hipMalloc on a miss and kept until the process ends (or an
+// allocation fails, which first returns the idle blocks to the driver).
 hipStream_t& alloc_stream();  // thread-local; the null stream outside a call
 struct StreamScope {
   hipStream_t prev;
@@ -43,7 +43,7 @@ struct StreamScope {
   StreamScope& operator=(const StreamScope&) = delete;
 };
 void* dev_alloc(size_t bytes);  // throws OOM
-void dev_free(void* p);         // ordered on alloc_stream()
+void dev_free(void* p);         // back to the cache, ordered on alloc_stream()
 // Host-to-device copy ordered on st that returns at once: the bytes are first
 // copied into a pinned staging area of the calling thread (src may be freed on
 // return).  A staging area is reused only after the copies from it completed.

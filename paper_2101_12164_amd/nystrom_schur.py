@@ -54,6 +54,7 @@ EXPORTED = [
     "nystrom_schur_mlp_destroy",
     "nystrom_schur_mlp_last_error",
     "nystrom_schur_kernel_timing",
+    "nystrom_schur_kernel_timing_families",
     "nystrom_schur_kernel_stats",
     "nystrom_schur_destroy",
     "nystrom_schur_last_error",
@@ -186,6 +187,8 @@ def load_library() -> ctypes.CDLL:
     lib.nystrom_schur_get_lowrank.restype = c_int32
     lib.nystrom_schur_kernel_timing.argtypes = [c_int32]
     lib.nystrom_schur_kernel_timing.restype = None
+    lib.nystrom_schur_kernel_timing_families.argtypes = [ctypes.c_uint32]
+    lib.nystrom_schur_kernel_timing_families.restype = None
     lib.nystrom_schur_kernel_stats.argtypes = [c_char_p, POINTER(c_double), POINTER(c_int64), POINTER(c_double),
                                                POINTER(c_double)]
     lib.nystrom_schur_kernel_stats.restype = c_int32
@@ -487,6 +490,14 @@ def nystrom_schur_mlp_last_error(m=None) -> str:
 def nystrom_schur_kernel_timing(enable: bool):
     """Turn per-kernel HIP-event timing on/off (and reset the totals)."""
     load_library().nystrom_schur_kernel_timing(1 if enable else 0)
+
+
+def nystrom_schur_kernel_timing_families(families):
+    """Time only the named kernel families (and reset the totals); an empty list turns timing off."""
+    mask = 0
+    for f in families:
+        mask |= 1 << KERNEL_FAMILIES.index(f)
+    load_library().nystrom_schur_kernel_timing_families(mask)
 
 
 def nystrom_schur_kernel_stats(family: str):
