@@ -471,7 +471,10 @@ def main():
         }
 
     # dominant kernel family in the timed region -> roofline
-    kern = {f: {"ms_total": v["ms"], "launches": v["launches"]} for f, v in stats.items() if v["launches"]}
+    kern = {f: {"ms_total": v["ms"], "launches": v["launches"],
+                "gbs": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] else None,
+                "tflops": v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] else None}
+            for f, v in stats.items() if v["launches"]}
     roof = roofline(stats, args.steps)
 
     line = {
