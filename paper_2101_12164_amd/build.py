@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnystrom_schur.so")
 SOURCES = [
     "tile_kernels.hip", "sparse_kernels.hip", "vec_kernels.hip", "small_kernels.hip", "ns_solver.hip", "ktimer.hip",
-    "local_schur.hip", "tile_gemv.hip", "learned.hip", "device_memory.hip"
+    "local_schur.hip", "tile_gemv.hip", "learned.hip", "device_memory.hip", "sym_gemv.hip"
 ]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

@@ -343,6 +343,13 @@ void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStr
     A = lv.Ainv32.p;
   GemmBatch g{nullptr, 0, lv.npad_d, lv.npad_d, lv.inv_off, lv.inv_lda, lv.roff, ncols, ncols, lv.roff, ncols, nullptr,
               ncols};
+  if constexpr (sizeof(T) == 8) {
+    if (ncols == 1 && lv.inv_sym.built()) {  // packed symmetric tiles: every stored entry read once
+      KScope ks(KF_INV64, st, lv.inv_sym.alg_bytes + 2.0 * lv.alg_rows * sizeof(T), lv.inv_sym.alg_flops);
+      sym_gemv(lv.inv_sym, B, C, st);
+      return;
+    }
+  }
   double sq = 0;
   for (int b = 0; b < lv.nblk; ++b) sq += double(lv.h_nb[b]) * lv.h_nb[b];
   KScope ks(sizeof(T) == 8 ? KF_INV64 : KF_INV32, st, (sq + 2.0 * lv.alg_rows * ncols) * sizeof(T), 2.0 * sq * ncols);
@@ -538,6 +545,7 @@ void local_schur_build(Handle& h) {
     ls.alg_bytes += double(ls.h_m[j]) * ls.h_m[j];
     ls.alg_flops += 2.0 * ls.h_m[j] * ls.h_m[j];
   }
+  sym_pack(ls.sym, ls.h_m, ls.S64.p, ls.soff.p, ls.sld.p, ls.goff.p, st);
   ls.built = true;
 }
 
@@ -574,7 +582,11 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
   NS_TPR_DISPATCH_LS(ncols, (k_gather_ls<T, TPR><<<unsigned((np * TPR + 255) / 256), 256, 0, st>>>(
                                  np, ls.glist, X, ldx, Xg, ncols, ncols)));
   NS_LAUNCH_CHECK();
-  {
+  if (sizeof(T) == 8 && ncols == 1 && ls.sym.built()) {
+    // one column: the packed symmetric tiles (every stored entry of S_j read once)
+    KScope ks(KF_LS_APPLY64, st, ls.sym.alg_bytes + 2.0 * np * sizeof(T), ls.sym.alg_flops);
+    sym_gemv(ls.sym, reinterpret_cast<const double*>(Xg), reinterpret_cast<double*>(Yg), st);
+  } else {
     // X_j / Y_j: stacked rows goff[j], leading dimension ncols
     GemmBatch g{nullptr, 0, ls.M, ls.Kg, ls.soff, ls.sld, ls.goff, ncols, ncols, ls.goff, ncols, nullptr, ncols};
     KScope ks(sizeof(T) == 8 ? KF_LS_APPLY64 : KF_LS_APPLY32, st,

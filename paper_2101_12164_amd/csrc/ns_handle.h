@@ -24,6 +24,7 @@ struct LocalSchur {
   DBuf<float> wsX32, wsY32;
   int64_t ws_cols = 0;
   double alg_bytes = 0, alg_flops = 0;  // per apply and column: sum m_j^2 entries, 2 sum m_j^2 flops
+  SymPacked sym;                         // S_j packed for single-column FP64 applies
 };
 
 }  // namespace ns

@@ -107,6 +107,29 @@ inline int band_tiles_for(int n, int bw) {
 //   Inverse diagonal tiles: nt[b] tiles from element ioff[b].
 //   Padded rows of block b start at row roff[b] of a padded right-hand side.
 // layout() sets the row layout; layout_band() the band and the factor storage.
+// Symmetric blocks in packed lower tile storage for single-column products
+// y_b = A_b x_b: block b (dimension dim_b, mt_b = ceil(dim_b / 64) tile rows)
+// keeps the tiles (ti, tj), tj <= ti, row-major 64 x 64 each, at tile index
+// toff_b + ti (ti + 1) / 2 + tj (zero beyond dim_b).  Each tile is read once
+// and serves both A_{ti,tj} x_tj and A_{ti,tj}^T x_ti; the per-tile partial
+// results are summed in a fixed order.  x_b and y_b start at row xoff_b of x
+// and y (device offsets owned by the caller's structure).
+struct SymPacked {
+  int nblk = 0, max_tiles = 0, max_mt = 0;
+  int64_t total_tiles = 0;
+  DBuf<int> mt, dim;
+  DBuf<int64_t> toff, pboff;
+  const int64_t* xoff = nullptr;
+  DBuf<double> tiles, part;
+  double alg_bytes = 0, alg_flops = 0;  // per product: distinct entries read, 2 dim^2 flops
+  bool built() const { return tiles.p != nullptr; }
+};
+// Pack block b of src (dim_b x dim_b at src + src_off[b], leading dimension src_ld[b]; device arrays).
+void sym_pack(SymPacked& sp, const std::vector<int>& dims, const double* src, const int64_t* src_off,
+              const int64_t* src_ld, const int64_t* xoff, hipStream_t st);
+// y_b = A_b x_b for every block (one column).
+void sym_gemv(const SymPacked& sp, const double* x, double* y, hipStream_t st);
+
 struct TileLevel {
   int role = 0;  // 0: interior blocks, 1: interface blocks (timing family)
   int nblk = 0;
@@ -125,6 +148,7 @@ struct TileLevel {
   DBuf<int64_t> inv_off, inv_lda;
   DBuf<int> npad_d;
   int64_t inv_ld = 0;
+  SymPacked inv_sym;  // the FP64 inverses packed for single-column applies
   // algorithmic work: factor entries (band lower triangle), flops of one
   // triangular sweep per right-hand side, rows; per tile column of the
   // factorisation: update flops, panel flops, bytes

@@ -199,6 +199,9 @@ void tile_make_inverse(TileLevel& lv, bool fp32, hipStream_t st) {
   upload(lv.inv_off.p, aoff.data(), lv.nblk * sizeof(int64_t), st);
   upload(lv.inv_lda.p, lda.data(), lv.nblk * sizeof(int64_t), st);
   upload(lv.npad_d.p, np.data(), lv.nblk * sizeof(int), st);
+  std::vector<int> dims(lv.nblk);
+  for (int b = 0; b < lv.nblk; ++b) dims[b] = lv.h_nt[b] * TILE;
+  sym_pack(lv.inv_sym, dims, lv.Ainv64.p, lv.inv_off.p, lv.inv_lda.p, lv.roff.p, st);
   if (fp32) {
     lv.Ainv32.alloc(lv.Ainv64.n);
     k_to_fp32_g<<<2048, 256, 0, st>>>(lv.Ainv64, lv.Ainv32, lv.Ainv64.n);
