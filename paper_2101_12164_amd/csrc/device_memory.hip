@@ -62,38 +62,45 @@ void release_idle(Cache& c, int dev) {
   (void)hipGetLastError();
 }
 
-// Pinned staging area of the calling thread.  Copies from base[0, used) may be in flight; ev is recorded
-// after the last of them on stream st.  The area is allocated on first use and kept until the process ends.
+// Pinned staging area of the calling thread for one stream.  Copies from base[0, used) may be in flight; ev is
+// recorded after the last of them.  Areas are allocated on first use and kept until the process ends.
 struct Staging {
+  hipStream_t st = nullptr;
   char* base = nullptr;
   size_t cap = 0, used = 0;
   hipEvent_t ev = nullptr;
-  hipStream_t st = nullptr;
-  bool pending = false, unavailable = false;
+  bool pending = false;
 };
-thread_local Staging g_stage;
+constexpr int STAGE_STREAMS = 4;  // streams with an area of their own per thread
+thread_local Staging g_stage[STAGE_STREAMS];
+thread_local int g_nstage = 0;
+thread_local bool g_stage_failed = false;
 constexpr size_t STAGE_BYTES = size_t(4) << 20;
 
-bool staging_ready(Staging& s) {
-  if (s.base) return true;
-  if (s.unavailable) return false;
+// The area of stream st (created on first use), or nullptr (then copies wait on the host).
+Staging* staging_for(hipStream_t st) {
+  for (int i = 0; i < g_nstage; ++i)
+    if (g_stage[i].st == st) return &g_stage[i];
+  if (g_stage_failed || g_nstage == STAGE_STREAMS) return nullptr;
   void* b = nullptr;
   hipEvent_t e = nullptr;
   if (hipHostMalloc(&b, STAGE_BYTES, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
-    s.unavailable = true;
-    return false;
+    g_stage_failed = true;
+    return nullptr;
   }
   if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipHostFree(b);
-    s.unavailable = true;
-    return false;
+    g_stage_failed = true;
+    return nullptr;
   }
+  Staging& s = g_stage[g_nstage++];
+  s.st = st;
   s.base = static_cast<char*>(b);
   s.cap = STAGE_BYTES;
   s.ev = e;
-  return true;
+  return &s;
 }
 
 }  // namespace
@@ -159,36 +166,33 @@ void dev_free(void* p) {
 
 void upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
   if (bytes == 0) return;
-  Staging& s = g_stage;
   const size_t need = (bytes + 255) & ~size_t(255);
-  if (!staging_ready(s) || need > s.cap) {
+  Staging* s = staging_for(st);
+  if (!s || need > s->cap) {
     // no staging area, or too large for it: a copy the host waits for
     NS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
     NS_HIP(hipStreamSynchronize(st));
     return;
   }
-  if (s.pending && (st != s.st || s.used + need > s.cap)) {
-    // copies from the area may still read it: wait for the last one (ordered after every earlier one
-    // when they share a stream; on a stream switch this wait also covers the previous stream's copies)
-    NS_HIP(hipEventSynchronize(s.ev));
-    s.used = 0;
-    s.pending = false;
+  if (s->pending && s->used + need > s->cap) {
+    // the area is full: wait for its last copy (the earlier ones precede it on the same stream)
+    NS_HIP(hipEventSynchronize(s->ev));
+    s->used = 0;
+    s->pending = false;
   }
-  if (s.used + need > s.cap) s.used = 0;
-  std::memcpy(s.base + s.used, src, bytes);
-  NS_HIP(hipMemcpyAsync(dst, s.base + s.used, bytes, hipMemcpyHostToDevice, st));
-  NS_HIP(hipEventRecord(s.ev, st));
-  s.used += need;
-  s.st = st;
-  s.pending = true;
+  std::memcpy(s->base + s->used, src, bytes);
+  NS_HIP(hipMemcpyAsync(dst, s->base + s->used, bytes, hipMemcpyHostToDevice, st));
+  NS_HIP(hipEventRecord(s->ev, st));
+  s->used += need;
+  s->pending = true;
 }
 
 void stream_idle(hipStream_t st) {
-  Staging& s = g_stage;
-  if (s.pending && s.st == st) {
-    s.used = 0;
-    s.pending = false;
-  }
+  for (int i = 0; i < g_nstage; ++i)
+    if (g_stage[i].st == st) {
+      g_stage[i].used = 0;
+      g_stage[i].pending = false;
+    }
 }
 
 }  // namespace ns

@@ -31,6 +31,7 @@ struct LocalSchur {
 
 struct ns_handle_s {
   hipStream_t stream = nullptr;
+  hipStream_t aux = nullptr;  // second stream of the setup (interface levels), created on first use
   std::string last_error;
 
   // sizes (a batch of problems is one block-diagonal matrix: totals over the problems)

@@ -85,6 +85,28 @@ struct SmallMats {
   }
 };
 
+// An event without timing, destroyed with its owner.
+struct Event {
+  hipEvent_t e = nullptr;
+  Event() { NS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+  ~Event() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  Event(const Event&) = delete;
+  Event& operator=(const Event&) = delete;
+};
+
+// Issues the handle's work on another stream (allocations included) until the end of the scope.
+struct StreamSwap {
+  Handle& h;
+  hipStream_t prev;
+  StreamScope ss;
+  StreamSwap(Handle& hh, hipStream_t s) : h(hh), prev(hh.stream), ss(s) { h.stream = s; }
+  ~StreamSwap() { h.stream = prev; }
+  StreamSwap(const StreamSwap&) = delete;
+  StreamSwap& operator=(const StreamSwap&) = delete;
+};
+
 template <class T>
 void read_back(Handle& h, T* host, const T* dev, size_t count) {
   NS_HIP(hipMemcpyAsync(host, dev, count * sizeof(T), hipMemcpyDeviceToHost, h.stream));
@@ -664,20 +686,32 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
   h->segN.build(h->h_noff, h->stream);
   h->sws = small_ws(h->small, h->nprob, h->s, h->s);
   ev.rec(1);
+  // The interface levels (patch factorisation, junction complement, explicit inverses) do not depend on the
+  // interior factorisation and the local Schur formation: they run on a second stream, joined before the pivot
+  // check, so the two latency-bound chains fill the device together.
+  if (!h->aux) NS_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
+  Event fork, join;
+  NS_HIP(hipEventRecord(fork.e, h->stream));
+  NS_HIP(hipStreamWaitEvent(h->aux, fork.e, 0));
+  {
+    StreamSwap sw(*h, h->aux);
+    tile_cholesky(h->L2, h->dflags.p + CHOL_FLAGS + 3, h->stream);
+    assemble_junction(*h);
+    tile_cholesky(h->LJ, h->dflags.p + CHOL_FLAGS + 6, h->stream);
+    for (ns::TileLevel* lv : {&h->L2, &h->LJ})
+      if (lv->nblk && lv->max_nt * TILE <= 4096 && lv->nrows_pad * lv->max_nt * TILE <= (int64_t(1) << 28))
+        tile_make_inverse(*lv, h->prec_inner != 0, h->stream);
+    if (h->prec_inner) {
+      tile_make_fp32(h->L2, h->stream);
+      tile_make_fp32(h->LJ, h->stream);
+    }
+    NS_HIP(hipEventRecord(join.e, h->stream));
+  }
   tile_cholesky(h->L1, h->dflags.p + CHOL_FLAGS, h->stream);
   if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_build(*h);
-  tile_cholesky(h->L2, h->dflags.p + CHOL_FLAGS + 3, h->stream);
-  assemble_junction(*h);
-  tile_cholesky(h->LJ, h->dflags.p + CHOL_FLAGS + 6, h->stream);
   if (trsv1_supported_size(h->L1)) tile_make_transposed(h->L1, h->stream);
-  for (ns::TileLevel* lv : {&h->L2, &h->LJ})
-    if (lv->nblk && lv->max_nt * TILE <= 4096 && lv->nrows_pad * lv->max_nt * TILE <= (int64_t(1) << 28))
-      tile_make_inverse(*lv, h->prec_inner != 0, h->stream);
-  if (h->prec_inner) {
-    if (!h->LS.built) tile_make_fp32(h->L1, h->stream);
-    tile_make_fp32(h->L2, h->stream);
-    tile_make_fp32(h->LJ, h->stream);
-  }
+  if (h->prec_inner && !h->LS.built) tile_make_fp32(h->L1, h->stream);
+  NS_HIP(hipStreamWaitEvent(h->stream, join.e, 0));
   check_chol(*h, info);
   ev.rec(2);
   const int np = h->nprob;
@@ -789,8 +823,13 @@ namespace {
 // Frees the handle's buffers in order behind the work queued on its stream.
 void destroy_handle(Handle* h) {
   if (!h) return;
-  StreamScope ss(h->stream);
-  delete h;
+  if (h->aux) (void)hipStreamSynchronize(h->aux);  // a failed setup may leave work queued there
+  {
+    StreamScope ss(h->stream);
+    hipStream_t aux = h->aux;
+    delete h;
+    if (aux) (void)hipStreamDestroy(aux);
+  }
 }
 }  // namespace
 }  // namespace ns

@@ -759,7 +759,6 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
     NS_HIP(hipMemcpyAsync(h.Aorig.col.p, col, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
     NS_HIP(hipMemcpyAsync(h.Aorig.val64.p, val, nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
   }
-  NS_HIP(hipStreamSynchronize(st));
 }
 
 void assemble_junction(Handle& h) {
@@ -783,7 +782,6 @@ void assemble_junction(Handle& h) {
   k_junction_update<<<dim3(unsigned((int64_t(maxJ) * maxJ + 255) / 256), h.LJ.nblk), 256, 0, st>>>(
       h.LJ.nb, h.LJ.nt, h.LJ.roff, h.LJ.foff, h.AJs.ptr, h.AJs.col, h.AJs.val64, E, ldE, h.LJ.L64);
   NS_LAUNCH_CHECK();
-  NS_HIP(hipStreamSynchronize(st));
 }
 
 template <class T>
