@@ -2,6 +2,8 @@
 // with a deterministic two-stage reduction, block updates Out = beta Out +
 // X M (+ X2 M2), column norms, dot products and the fused vector updates of
 // PCG with per-problem scalars and done flags.
+#include <type_traits>
+
 #include "ns_vec.h"
 
 namespace ns {
@@ -9,8 +11,6 @@ namespace {
 
 constexpr int CHUNK_MAX = 240;   // reduction chunks per segment (at most)
 constexpr int CHUNK_ROWS = 128;  // target rows per chunk
-constexpr int GRAM_RB = 16;      // rows staged per LDS batch
-constexpr int GRAM_MAXQ = 32;    // outputs per thread (1024 threads): up to 32768 entries
 
 // index p of the segment whose range [pre[p], pre[p + 1]) holds b
 __device__ __forceinline__ int seg_of(const int* __restrict__ pre, int n, int b) {
@@ -36,142 +36,78 @@ __device__ __forceinline__ int chunk_rows(const Seg& sg, int b, int64_t& r0, int
   return p;
 }
 
-template <class TA, class TB>
-__global__ __launch_bounds__(1024) void k_gram_partial(Seg sg, const TA* __restrict__ A, int64_t lda, int ra,
-                                                       const TB* __restrict__ B, int64_t ldb, int rb,
-                                                       double* __restrict__ part) {
-  extern __shared__ double sm[];
-  double* sA = sm;                 // GRAM_RB x ra
-  double* sB = sm + GRAM_RB * ra;  // GRAM_RB x rb
-  const int nout = ra * rb;
-  int64_t r0, r1;
-  chunk_rows(sg, blockIdx.x, r0, r1);
-  double acc[GRAM_MAXQ];
-#pragma unroll
-  for (int q = 0; q < GRAM_MAXQ; ++q) acc[q] = 0.0;
-  for (int64_t rs = r0; rs < r1; rs += GRAM_RB) {
-    const int nr = int(r1 - rs < GRAM_RB ? r1 - rs : GRAM_RB);
-    __syncthreads();
-    for (int e = threadIdx.x; e < GRAM_RB * ra; e += blockDim.x) {
-      const int rr = e / ra, c = e % ra;
-      sA[e] = rr < nr ? double(A[(rs + rr) * lda + c]) : 0.0;
-    }
-    for (int e = threadIdx.x; e < GRAM_RB * rb; e += blockDim.x) {
-      const int rr = e / rb, c = e % rb;
-      sB[e] = rr < nr ? double(B[(rs + rr) * ldb + c]) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < GRAM_MAXQ; ++q) {
-      const int o = threadIdx.x + q * 1024;
-      if (o < nout) {
-        const int a = o / rb, b = o % rb;
-        double s = acc[q];
-        for (int rr = 0; rr < GRAM_RB; ++rr) s += sA[rr * ra + a] * sB[rr * rb + b];
-        acc[q] = s;
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < GRAM_MAXQ; ++q) {
-    const int o = threadIdx.x + q * 1024;
-    if (o < nout) part[int64_t(blockIdx.x) * nout + o] = acc[q];
-  }
-}
-
-// The same partial Gram products on FP64 MFMA (16x16x4): the chunk's rows are staged in LDS as FP64 in
-// batches of GM_R rows (zero-padded to whole 16-column tiles), and each wave accumulates 16x16 output
-// tiles; lane l feeds A(r0 + l/16, a0 + l%16) and B(r0 + l/16, b0 + l%16) and holds output rows
-// a0 + 4v + l/16, column b0 + l%16 (v = 0..3).  The accumulation order is fixed per chunk.
 typedef double gv4d __attribute__((ext_vector_type(4)));
-constexpr int GM_R = 32;       // rows per LDS batch
-constexpr int GM_WAVES = 8;    // waves per workgroup
-constexpr int GM_MAXT = 8;     // output tiles per wave
-constexpr int GM_PRE = 16;     // prefetched values per thread: GM_R (wa + wb) <= GM_PRE * 64 GM_WAVES
+
+// Gram partials with more parallelism: workgroup (chunk, strip) computes the 16-row strip a0 = 16 strip of the
+// chunk's A^T B (all column tiles of B, at most GS_MAXT per launch column group); its four waves split the chunk's
+// rows in 4-row MFMA steps (wave w takes steps w, w + 4, ...), reading the operands straight from global memory
+// (the chunk is reused from cache by the strips), and the four partial strips are summed in a fixed order.
+constexpr int GS_MAXT = 5;
 template <class TA, class TB>
-__global__ __launch_bounds__(GM_WAVES * 64) void k_gram_mfma(Seg sg, const TA* __restrict__ A, int64_t lda, int ra,
-                                                          const TB* __restrict__ B, int64_t ldb, int rb,
-                                                          double* __restrict__ part) {
-  extern __shared__ double sm[];
-  const int wa = (ra + 15) & ~15, wb = (rb + 15) & ~15;
-  double* sA = sm;              // GM_R x wa
-  double* sB = sm + GM_R * wa;  // GM_R x wb
-  const int ta = wa / 16, tb = wb / 16, T = ta * tb;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__global__ __launch_bounds__(256) void k_gram_strip(Seg sg, const TA* __restrict__ A, int64_t lda, int ra,
+                                                    const TB* __restrict__ B, int64_t ldb, int rb,
+                                                    double* __restrict__ part, int sym) {
+  __shared__ double red[3][GS_MAXT][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  constexpr int NTH = GM_WAVES * 64;
-  const int na = (GM_R * wa + NTH - 1) / NTH, nb = (GM_R * wb + NTH - 1) / NTH;  // <= GM_PRE together
+  const int a0 = 16 * blockIdx.y;
+  const int bt0 = GS_MAXT * blockIdx.z;                 // first column tile of this group
+  // column tiles in this group; with sym (A = B) only those on or left of the diagonal, mirrored on output
+  const int tb = min(min(GS_MAXT, (rb + 15) / 16 - bt0), sym ? int(blockIdx.y) - bt0 + 1 : GS_MAXT);
+  if (tb <= 0) return;
   int64_t r0, r1;
   chunk_rows(sg, blockIdx.x, r0, r1);
-  gv4d acc[GM_MAXT];
+  gv4d acc[GS_MAXT];
 #pragma unroll
-  for (int q = 0; q < GM_MAXT; ++q) acc[q] = gv4d{0.0, 0.0, 0.0, 0.0};
-  // the next batch of rows is read into registers while the current one is multiplied
-  double pre[GM_PRE];
-  auto fetch = [&](int64_t rs) {
-    const int nr = int(r1 - rs < GM_R ? r1 - rs : GM_R);
+  for (int t = 0; t < GS_MAXT; ++t) acc[t] = gv4d{0.0, 0.0, 0.0, 0.0};
+  const int ac = a0 + li;                        // column of A this lane feeds
+  const bool aok = ac < ra;
+  const TA* Ap = A + (aok ? ac : 0);
+  int bc[GS_MAXT];
+  bool bok[GS_MAXT];
 #pragma unroll
-    for (int q = 0; q < GM_PRE; ++q) {
-      double v = 0.0;
-      if (q < na) {
-        const int e = threadIdx.x + q * NTH;
-        const int rr = e / wa, c = e - rr * wa;
-        if (e < GM_R * wa && rr < nr && c < ra) v = double(A[(rs + rr) * lda + c]);
-      } else if (q < na + nb) {
-        const int e = threadIdx.x + (q - na) * NTH;
-        const int rr = e / wb, c = e - rr * wb;
-        if (e < GM_R * wb && rr < nr && c < rb) v = double(B[(rs + rr) * ldb + c]);
-      }
-      pre[q] = v;
-    }
-  };
-  if (r0 < r1) fetch(r0);
-  for (int64_t rs = r0; rs < r1; rs += GM_R) {
-    const int nr = int(r1 - rs < GM_R ? r1 - rs : GM_R);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < GM_PRE; ++q) {
-      if (q < na) {
-        const int e = threadIdx.x + q * NTH;
-        if (e < GM_R * wa) sA[e] = pre[q];
-      } else if (q < na + nb) {
-        const int e = threadIdx.x + (q - na) * NTH;
-        if (e < GM_R * wb) sB[e] = pre[q];
-      }
-    }
-    if (rs + GM_R < r1) fetch(rs + GM_R);
-    __syncthreads();
-    const int kend = (nr + 3) & ~3;
-#pragma unroll
-    for (int q = 0; q < GM_MAXT; ++q) {
-      const int t = wave + q * GM_WAVES;
-      if (t < T) {
-        const int a0 = (t / tb) * 16, b0 = (t % tb) * 16;
-        gv4d c = acc[q];
-        for (int k = 0; k < kend; k += 4) {
-          const double x = sA[(k + lk) * wa + a0 + li];
-          const double y = sB[(k + lk) * wb + b0 + li];
-          c = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
-        }
-        acc[q] = c;
-      }
-    }
+  for (int t = 0; t < GS_MAXT; ++t) {
+    bc[t] = 16 * (bt0 + t) + li;
+    bok[t] = t < tb && bc[t] < rb;
+    if (!bok[t]) bc[t] = 0;
   }
+#pragma unroll 2
+  for (int64_t k = r0 + 4 * w; k < r1; k += 16) {
+    const int64_t r = k + lk;
+    const bool rok = r < r1;
+    const int64_t rr = rok ? r : r0;
+    const double x = (rok && aok) ? double(Ap[rr * lda]) : 0.0;
+#pragma unroll
+    for (int t = 0; t < GS_MAXT; ++t)
+      if (t < tb) {
+        const double y = (rok && bok[t]) ? double(B[rr * ldb + bc[t]]) : 0.0;
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[t], 0, 0, 0);
+      }
+  }
+  // fixed-order sum of the four waves' strips: waves 1..3 park theirs, wave 0 adds them in order
+  if (w > 0) {
+#pragma unroll
+    for (int t = 0; t < GS_MAXT; ++t)
+      if (t < tb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[w - 1][t][v][lane] = acc[t][v];
+  }
+  __syncthreads();
+  if (w != 0) return;
   const int nout = ra * rb;
   double* out = part + int64_t(blockIdx.x) * nout;
 #pragma unroll
-  for (int q = 0; q < GM_MAXT; ++q) {
-    const int t = wave + q * GM_WAVES;
-    if (t < T) {
-      const int a0 = (t / tb) * 16, b0 = (t % tb) * 16;
-      const int b = b0 + li;
+  for (int t = 0; t < GS_MAXT; ++t)
+    if (t < tb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int a = a0 + 4 * v + lk;
-        if (a < ra && b < rb) out[a * rb + b] = acc[q][v];
+        const double sum = ((acc[t][v] + red[0][t][v][lane]) + red[1][t][v][lane]) + red[2][t][v][lane];
+        const int a = a0 + 4 * v + lk, b = 16 * (bt0 + t) + li;
+        if (a < ra && b < rb) {
+          out[a * rb + b] = sum;
+          if (sym && bt0 + t != int(blockIdx.y)) out[b * rb + a] = sum;
+        }
       }
-    }
-  }
 }
 
 // G_p[o] = alpha * (sum of segment p's chunk partials of output o) + beta * G_p[o].  TX outputs per block;
@@ -211,72 +147,54 @@ void seg_final(const Seg& sg, int nout, const double* part, double* G, int64_t g
   NS_LAUNCH_CHECK();
 }
 
-// Out[r, c] = beta * Out[r, c] + gamma * (sum_m X[r, m] M_p[m, c] + sum_m X2[r, m] M2_p[m, c]) on 64-row tiles
-// that never straddle two segments, in FP64 on MFMA.  A workgroup computes a 64 x 64 output block (wave w:
-// rows 16 w .. 16 w + 15, four 16-column tiles); the reduction index runs over [X | X2] in batches of 32
-// staged through LDS, the next batch read into registers while the current one is multiplied.
+// Out[r, c] = beta * Out[r, c] + gamma * sum_m X[r, m] M_p[m, c] on 64-row tiles that never straddle two
+// segments, on FP64 MFMA 16x16x4 (FP32 blocks are widened, so the products and sums are those of FP64).  A
+// workgroup computes a 64 x 16 NTI output block (wave w: rows 16 w .. 16 w + 15, NTI column tiles); X and M are
+// staged through LDS in batches of TS_K rows of M.
 constexpr int TS_K = 32;
-template <class T>
+template <class T, int NTI>
 __global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* __restrict__ Out, int64_t ldo, double beta,
-                                                 double gamma, const T* __restrict__ X, int64_t ldx, int rm,
-                                                 const double* __restrict__ M, int64_t ldm, int64_t mstride,
-                                                 const T* __restrict__ X2, int64_t ldx2, int rm2,
-                                                 const double* __restrict__ M2, int64_t ldm2, int64_t m2stride) {
+                                                 double gamma, const T* __restrict__ X, int64_t ldx, int K,
+                                                 const double* __restrict__ M, int64_t ldm, int64_t mstride) {
+  constexpr int NC = 16 * NTI;
   __shared__ double sX[64 * (TS_K + 1)];
-  __shared__ double sM[TS_K * 65];
+  __shared__ double sM[TS_K * (NC + 1)];
   const int p = seg_of(sg.toff, sg.n, blockIdx.x);
   const int64_t rbase = sg.off[p] + int64_t(blockIdx.x - sg.toff[p]) * 64;
   const int64_t rend = sg.off[p + 1];
   const double* Mp = M + int64_t(p) * mstride;
-  const double* M2p = M2 ? M2 + int64_t(p) * m2stride : nullptr;
-  const int c0 = blockIdx.y * 64;
-  const int K = rm + rm2;
+  const int c0 = blockIdx.y * NC;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  gv4d acc[4];
+  gv4d acc[NTI];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = gv4d{0.0, 0.0, 0.0, 0.0};
-  double px[8], pm[8];
-  auto fetch = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {  // X batch: 64 rows x TS_K
-      const int e = threadIdx.x + 256 * q, r = e / TS_K, k = k0 + e % TS_K;
-      const int64_t row = rbase + r;
-      double v = 0.0;
-      if (row < rend && k < K) v = k < rm ? double(X[row * ldx + k]) : double(X2[row * ldx2 + (k - rm)]);
-      px[q] = v;
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {  // M batch: TS_K x 64
-      const int e = threadIdx.x + 256 * q, kk = e / 64, c = c0 + e % 64, k = k0 + kk;
-      double v = 0.0;
-      if (c < ncols && k < K) v = k < rm ? Mp[int64_t(k) * ldm + c] : M2p[int64_t(k - rm) * ldm2 + c];
-      pm[q] = v;
-    }
-  };
-  if (K > 0) fetch(0);
+  for (int t = 0; t < NTI; ++t) acc[t] = gv4d{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += TS_K) {
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = threadIdx.x + 256 * q;
-      sX[(e / TS_K) * (TS_K + 1) + e % TS_K] = px[q];
-      sM[(e / 64) * 65 + e % 64] = pm[q];
+    for (int e = threadIdx.x; e < 64 * TS_K; e += 256) {  // in-bounds addresses, zero outside
+      const int r = e / TS_K, kk = e % TS_K, k = k0 + kk;
+      const int64_t row = rbase + r;
+      const bool ok = row < rend && k < K;
+      const T v = X[(ok ? row : rbase) * ldx + (ok ? k : 0)];
+      sX[r * (TS_K + 1) + kk] = ok ? double(v) : 0.0;
     }
-    if (k0 + TS_K < K) fetch(k0 + TS_K);
+    for (int e = threadIdx.x; e < TS_K * NC; e += 256) {
+      const int kk = e / NC, cc = e % NC, c = c0 + cc, k = k0 + kk;
+      const bool ok = c < ncols && k < K;
+      const double v = Mp[int64_t(ok ? k : 0) * ldm + (ok ? c : 0)];
+      sM[kk * (NC + 1) + cc] = ok ? v : 0.0;
+    }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < TS_K; kk += 4) {
       const double a = sX[(16 * w + li) * (TS_K + 1) + kk + lk];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const double b = sM[(kk + lk) * 65 + 16 * t + li];
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-      }
+      for (int t = 0; t < NTI; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sM[(kk + lk) * (NC + 1) + 16 * t + li], acc[t], 0, 0, 0);
     }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < NTI; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t r = rbase + 16 * w + 4 * v + lk;
@@ -287,6 +205,30 @@ __global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* __restric
         Out[r * ldo + c] = T(y);
       }
     }
+}
+
+template <class T>
+void ts_launch(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, double gamma, const T* X, int64_t ldx,
+               int K, const double* M, int64_t ldm, int64_t mstride, hipStream_t st) {
+  const int tiles = (ncols + 15) / 16;
+  auto go = [&](auto nti) {
+    constexpr int N = decltype(nti)::value;
+    dim3 g(unsigned(sg.ntile), unsigned((tiles + N - 1) / N));
+    k_ts_mfma<T, N><<<g, 256, 0, st>>>(sg, ncols, Out, ldo, beta, gamma, X, ldx, K, M, ldm, mstride);
+  };
+  if (tiles <= 1)
+    go(std::integral_constant<int, 1>());
+  else if (tiles <= 2)
+    go(std::integral_constant<int, 2>());
+  else if (tiles <= 3)
+    go(std::integral_constant<int, 3>());
+  else if (tiles <= 4)
+    go(std::integral_constant<int, 4>());
+  else if (tiles <= 5)
+    go(std::integral_constant<int, 5>());
+  else
+    go(std::integral_constant<int, 8>());
+  NS_LAUNCH_CHECK();
 }
 
 template <class T, class U>
@@ -489,16 +431,11 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
           int64_t gstride, double alpha, double beta, double* work, hipStream_t st) {
   const int nout = ra * rb;
   if (nout == 0 || sg.n == 0) return;
-  if (nout > 1024 * GRAM_MAXQ) fail(INVALID_ARG, "Gram product too wide");
-  const int wa = (ra + 15) & ~15, wb = (rb + 15) & ~15;
-  const size_t lds_m = size_t(GM_R) * (wa + wb) * sizeof(double);
-  if ((wa / 16) * (wb / 16) <= GM_WAVES * GM_MAXT && GM_R * (wa + wb) <= GM_PRE * GM_WAVES * 64 &&
-      lds_m <= 64 * 1024) {
-    k_gram_mfma<TA, TB><<<sg.nchunk, GM_WAVES * 64, lds_m, st>>>(sg, A, lda, ra, B, ldb, rb, work);
-  } else {
-    const size_t lds = size_t(GRAM_RB) * (ra + rb) * sizeof(double);
-    k_gram_partial<TA, TB><<<sg.nchunk, 1024, lds, st>>>(sg, A, lda, ra, B, ldb, rb, work);
-  }
+  const int ta = (ra + 15) / 16, tbt = (rb + 15) / 16;
+  if (ta > 65535) fail(INVALID_ARG, "Gram product too wide");
+  dim3 g(unsigned(sg.nchunk), unsigned(ta), unsigned((tbt + GS_MAXT - 1) / GS_MAXT));
+  const int sym = (static_cast<const void*>(A) == static_cast<const void*>(B) && lda == ldb && ra == rb) ? 1 : 0;
+  k_gram_strip<TA, TB><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym);
   NS_LAUNCH_CHECK();
   seg_final(sg, nout, work, G, gstride, alpha, beta, st);
 }
@@ -510,10 +447,8 @@ void ts_update(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, doubl
                int rm, const double* M, int64_t ldm, int64_t mstride, const T* X2, int64_t ldx2, int rm2,
                const double* M2, int64_t ldm2, int64_t m2stride, hipStream_t st) {
   if (sg.rows == 0 || ncols == 0) return;
-  dim3 g(unsigned(sg.ntile), unsigned((ncols + 63) / 64));
-  k_ts_mfma<T><<<g, 256, 0, st>>>(sg, ncols, Out, ldo, beta, gamma, X, ldx, rm, M, ldm, mstride, X2, ldx2, rm2, M2,
-                                  ldm2, m2stride);
-  NS_LAUNCH_CHECK();
+  ts_launch<T>(sg, ncols, Out, ldo, beta, gamma, X, ldx, rm, M, ldm, mstride, st);
+  if (rm2 > 0) ts_launch<T>(sg, ncols, Out, ldo, 1.0, gamma, X2, ldx2, rm2, M2, ldm2, m2stride, st);
 }
 
 template <class T, class U>
