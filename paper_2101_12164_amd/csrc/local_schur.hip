@@ -148,7 +148,11 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restric
   using acc_t = typename MFL<T>::acc_t;
   constexpr int KC = 32;
   constexpr int AP = 64 + 1, BP = NC + 1;
-  constexpr int MW = NC == 64 ? 2 : 1;  // MFMA row blocks per wave
+  // wave layout: NC == 64: wave w owns rows [32*(w>>1), +32) x cols [32*(w&1), +32) (2 x 2 MFMA tiles)
+  //              NC == 16: wave w owns rows [16 w, +16) x cols [0, 16)
+  //              NC == 80: wave w owns rows [16 w, +16) x cols [0, 80) (1 x 5 tiles sharing the A operand)
+  constexpr int MR = NC == 64 ? 2 : 1;          // MFMA row tiles per wave
+  constexpr int MC = NC == 64 ? 2 : NC / 16;    // MFMA column tiles per wave
   __shared__ T sA[KC * AP];
   __shared__ T sB[KC * BP];
   const int j = blockIdx.z;
@@ -163,8 +167,6 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restric
   const int Nj = sym ? M : N;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rl = lane & 15, kq = lane >> 4;
-  // wave layout: NC == 64: wave w owns rows [32*(w>>1), +32) x cols [32*(w&1), +32)
-  //              NC == 16: wave w owns rows [16 w, +16) x cols [0, 16)
   const int wr = NC == 64 ? 32 * (w >> 1) : 16 * w;
   const int wc = NC == 64 ? 32 * (w & 1) : 0;
   // columns of A and B are zero above their first nonzero tile row: start K there
@@ -174,12 +176,12 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restric
     const int kb = g.kstart[j * g.kstride + (n0 >> 6)];
     kbeg = min(max(ka, kb) * 64, K);
   }
-  acc_t acc[MW][MW];
+  acc_t acc[MR][MC];
 #pragma unroll
-  for (int a = 0; a < MW; ++a)
+  for (int a = 0; a < MR; ++a)
 #pragma unroll
-    for (int b = 0; b < MW; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-  constexpr int PA = KC * 64 / 256, PB = KC * NC / 256;
+    for (int b = 0; b < MC; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  constexpr int PA = KC * 64 / 256, PB = (KC * NC + 255) / 256;
   T ra[PA], rb[PB];
   auto gload = [&](int k0) {
 #pragma unroll
@@ -190,7 +192,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restric
 #pragma unroll
     for (int q = 0; q < PB; ++q) {
       const int e = threadIdx.x + 256 * q, kk = e / NC, n = e % NC;
-      rb[q] = (k0 + kk < K && n0 + n < Nj) ? Bj[int64_t(k0 + kk) * ldb + n0 + n] : T(0);
+      rb[q] = (kk < KC && k0 + kk < K && n0 + n < Nj) ? Bj[int64_t(k0 + kk) * ldb + n0 + n] : T(0);
     }
   };
   if (kbeg < K) gload(kbeg);
@@ -204,30 +206,29 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restric
 #pragma unroll
     for (int q = 0; q < PB; ++q) {
       const int e = threadIdx.x + 256 * q;
-      sB[(e / NC) * BP + e % NC] = rb[q];
+      if (e < KC * NC) sB[(e / NC) * BP + e % NC] = rb[q];
     }
     if (k0 + KC < K) gload(k0 + KC);
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 4) {
-      T a[MW], b[MW];
+      T a[MR], b[MC];
 #pragma unroll
-      for (int q = 0; q < MW; ++q) {
-        a[q] = sA[(kk + kq) * AP + wr + 16 * q + rl];
-        b[q] = sB[(kk + kq) * BP + wc + 16 * q + rl];
-      }
+      for (int q = 0; q < MR; ++q) a[q] = sA[(kk + kq) * AP + wr + 16 * q + rl];
 #pragma unroll
-      for (int x = 0; x < MW; ++x)
+      for (int q = 0; q < MC; ++q) b[q] = sB[(kk + kq) * BP + wc + 16 * q + rl];
 #pragma unroll
-        for (int y = 0; y < MW; ++y) acc[x][y] = MFL<T>::mma(a[x], b[y], acc[x][y]);
+      for (int x = 0; x < MR; ++x)
+#pragma unroll
+        for (int y = 0; y < MC; ++y) acc[x][y] = MFL<T>::mma(a[x], b[y], acc[x][y]);
     }
   }
   T* Cj = C + g.coff[j] * g.cscale;
   const int64_t ldc = g.ldc ? g.ldc[j] : g.ldc_s;
 #pragma unroll
-  for (int x = 0; x < MW; ++x)
+  for (int x = 0; x < MR; ++x)
 #pragma unroll
-    for (int y = 0; y < MW; ++y)
+    for (int y = 0; y < MC; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = m0 + wr + 16 * x + MFL<T>::row(kq, v);
@@ -323,6 +324,9 @@ void launch_gemm(const LocalSchur& ls, const T* A, const T* B, T* C, int N, hipS
   if (N <= 16 && !sym) {
     dim3 grid(1, tilesM, nblk);
     k_gemm_tn<T, 16><<<grid, 256, 0, st>>>(g, A, B, C, N, 0);
+  } else if (N > 64 && N <= 80 && !sym) {
+    dim3 grid(1, tilesM, nblk);
+    k_gemm_tn<T, 80><<<grid, 256, 0, st>>>(g, A, B, C, N, 0);
   } else {
     const int tilesN = sym ? tilesM : (N + 63) / 64;
     dim3 grid(tilesN, tilesM, nblk);
@@ -357,6 +361,9 @@ void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStr
   if (ncols <= 16) {
     dim3 grid(1, tilesM, lv.nblk);
     k_gemm_tn<T, 16><<<grid, 256, 0, st>>>(g, A, B, C, ncols, 0);
+  } else if (ncols > 64 && ncols <= 80) {
+    dim3 grid(1, tilesM, lv.nblk);
+    k_gemm_tn<T, 80><<<grid, 256, 0, st>>>(g, A, B, C, ncols, 0);
   } else {
     dim3 grid((ncols + 63) / 64, tilesM, lv.nblk);
     k_gemm_tn<T, 64><<<grid, 256, 0, st>>>(g, A, B, C, ncols, 0);
