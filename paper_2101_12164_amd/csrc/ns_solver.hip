@@ -789,9 +789,16 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
 // Batch layout: part labels of every problem shifted into one numbering.
 __global__ void k_part_minmax(int64_t n, const int32_t* __restrict__ part, int* mm) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  atomicMax(&mm[0], part[i]);
-  atomicMin(&mm[1], part[i]);
+  int pmax = INT32_MIN, pmin = INT32_MAX;
+  if (i < n) pmax = pmin = part[i];
+  for (int o = 32; o > 0; o >>= 1) {  // one atomic per wave
+    pmax = max(pmax, __shfl_xor(pmax, o));
+    pmin = min(pmin, __shfl_xor(pmin, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (pmax != INT32_MIN) atomicMax(&mm[0], pmax);
+    if (pmin != INT32_MAX) atomicMin(&mm[1], pmin);
+  }
 }
 __global__ void k_concat(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ part, int64_t e0,
                          int64_t a, int sub0, int l20, int64_t* __restrict__ rpu, int32_t* __restrict__ partu) {

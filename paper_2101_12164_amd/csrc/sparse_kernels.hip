@@ -202,21 +202,31 @@ __global__ void k_validate(int64_t n, int64_t nnz, const int64_t* __restrict__ p
                            const double* __restrict__ val, const int32_t* __restrict__ part, int* flags,
                            int* minmax) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (i == 0 && (ptr[0] != 0 || ptr[n] != nnz)) flags[F_STRUCT] = 1;
-  const int64_t e0 = ptr[i], e1 = ptr[i + 1];
-  if (e1 < e0 || e0 < 0 || e1 > nnz) {
-    flags[F_STRUCT] = 1;
-    return;
+  int pmax = INT32_MIN, pmin = INT32_MAX;
+  if (i < n) {
+    if (i == 0 && (ptr[0] != 0 || ptr[n] != nnz)) flags[F_STRUCT] = 1;
+    const int64_t e0 = ptr[i], e1 = ptr[i + 1];
+    if (e1 < e0 || e0 < 0 || e1 > nnz) {
+      flags[F_STRUCT] = 1;
+    } else {
+      for (int64_t e = e0; e < e1; ++e) {
+        const int32_t j = col[e];
+        if (j < 0 || j >= n) flags[F_STRUCT] = 1;
+        const double v = val[e];
+        if (!(v == v) || v - v != 0.0) flags[F_NAN] = 1;
+      }
+    }
+    pmax = pmin = part[i];
   }
-  for (int64_t e = e0; e < e1; ++e) {
-    const int32_t j = col[e];
-    if (j < 0 || j >= n) flags[F_STRUCT] = 1;
-    const double v = val[e];
-    if (!(v == v) || v - v != 0.0) flags[F_NAN] = 1;
+  // label range: wave-wide max / min first, one atomic per wave (all lanes reach the shuffles)
+  for (int o = 32; o > 0; o >>= 1) {
+    pmax = max(pmax, __shfl_xor(pmax, o));
+    pmin = min(pmin, __shfl_xor(pmin, o));
   }
-  atomicMax(&minmax[0], part[i]);
-  atomicMin(&minmax[1], part[i]);
+  if ((threadIdx.x & 63) == 0) {
+    if (pmax != INT32_MIN) atomicMax(&minmax[0], pmax);
+    if (pmin != INT32_MAX) atomicMin(&minmax[1], pmin);
+  }
 }
 
 // Every stored (i, j, v) must have its mirror (j, i, v).
@@ -460,9 +470,10 @@ __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int3
     }
   }
   if (!FILL) {
+    // thousands of rows share a block's counter: only values above the one already stored need the atomic
     if (bw > 0) {
-      if (pi >= 0) atomicMax(o.bw1 + pi, bw);
-      if (pi <= -2) atomicMax(o.bw2 + (-2 - pi), bw);
+      if (pi >= 0 && bw > o.bw1[pi]) atomicMax(o.bw1 + pi, bw);
+      if (pi <= -2 && bw > o.bw2[-2 - pi]) atomicMax(o.bw2 + (-2 - pi), bw);
     }
     if (pi >= 0) {
       o.pIG[rowIG + 1] = nIG;
