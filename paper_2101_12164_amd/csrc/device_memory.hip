@@ -62,8 +62,10 @@ void release_idle(Cache& c, int dev) {
   (void)hipGetLastError();
 }
 
-// Pinned staging area of the calling thread for one stream.  Copies from base[0, used) may be in flight; ev is
-// recorded after the last of them.  Areas are allocated on first use and kept until the process ends.
+// Pinned staging areas of the calling thread.  An area serves one stream at a time: copies from
+// base[0, used) may be in flight on st, and ev is recorded after the last of them.  An area whose copies
+// have completed is handed to whichever stream asks next, so streams that come and go (one per handle)
+// share a few areas.  Areas are allocated on first use and kept until the process ends.
 struct Staging {
   hipStream_t st = nullptr;
   char* base = nullptr;
@@ -71,36 +73,71 @@ struct Staging {
   hipEvent_t ev = nullptr;
   bool pending = false;
 };
-constexpr int STAGE_STREAMS = 4;  // streams with an area of their own per thread
-thread_local Staging g_stage[STAGE_STREAMS];
+constexpr int STAGE_AREAS = 8;  // areas per thread
+thread_local Staging g_stage[STAGE_AREAS];
 thread_local int g_nstage = 0;
 thread_local bool g_stage_failed = false;
 constexpr size_t STAGE_BYTES = size_t(4) << 20;
 
-// The area of stream st (created on first use), or nullptr (then copies wait on the host).
-Staging* staging_for(hipStream_t st) {
+// true when every copy from area s has completed
+bool area_idle(Staging& s) {
+  if (!s.pending) return true;
+  const hipError_t e = hipEventQuery(s.ev);
+  if (e == hipSuccess) {
+    s.pending = false;
+    s.used = 0;
+    return true;
+  }
+  (void)hipGetLastError();  // not-ready is reported as an error code
+  return false;
+}
+
+// An area for `need` bytes of copies on stream st, or nullptr (then the copy waits on the host).
+Staging* staging_for(hipStream_t st, size_t need) {
+  // the stream's own area while it has room (its copies are ordered on st)
+  for (int i = 0; i < g_nstage; ++i) {
+    Staging& s = g_stage[i];
+    if (s.st != st) continue;
+    if (!s.pending) s.used = 0;
+    if (s.used + need <= s.cap) return &s;
+  }
+  // an area whose copies have all completed
   for (int i = 0; i < g_nstage; ++i)
-    if (g_stage[i].st == st) return &g_stage[i];
-  if (g_stage_failed || g_nstage == STAGE_STREAMS) return nullptr;
-  void* b = nullptr;
-  hipEvent_t e = nullptr;
-  if (hipHostMalloc(&b, STAGE_BYTES, hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    g_stage_failed = true;
-    return nullptr;
+    if (area_idle(g_stage[i])) {
+      g_stage[i].st = st;
+      return &g_stage[i];
+    }
+  if (!g_stage_failed && g_nstage < STAGE_AREAS) {
+    void* b = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipHostMalloc(&b, STAGE_BYTES, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      g_stage_failed = true;
+      return nullptr;
+    }
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipHostFree(b);
+      g_stage_failed = true;
+      return nullptr;
+    }
+    Staging& s = g_stage[g_nstage++];
+    s.st = st;
+    s.base = static_cast<char*>(b);
+    s.cap = STAGE_BYTES;
+    s.ev = e;
+    return &s;
   }
-  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-    (void)hipGetLastError();
-    (void)hipHostFree(b);
-    g_stage_failed = true;
-    return nullptr;
-  }
-  Staging& s = g_stage[g_nstage++];
-  s.st = st;
-  s.base = static_cast<char*>(b);
-  s.cap = STAGE_BYTES;
-  s.ev = e;
-  return &s;
+  if (g_nstage == 0) return nullptr;
+  // every area is busy: wait for the stream's own area (or the first one) to drain
+  Staging* s = &g_stage[0];
+  for (int i = 0; i < g_nstage; ++i)
+    if (g_stage[i].st == st) s = &g_stage[i];
+  if (s->pending) NS_HIP(hipEventSynchronize(s->ev));
+  s->pending = false;
+  s->used = 0;
+  s->st = st;
+  return s;
 }
 
 }  // namespace
@@ -167,18 +204,12 @@ void dev_free(void* p) {
 void upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
   if (bytes == 0) return;
   const size_t need = (bytes + 255) & ~size_t(255);
-  Staging* s = staging_for(st);
-  if (!s || need > s->cap) {
-    // no staging area, or too large for it: a copy the host waits for
+  Staging* s = need <= STAGE_BYTES ? staging_for(st, need) : nullptr;
+  if (!s) {
+    // no staging area, or too large for one: a copy the host waits for
     NS_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
     NS_HIP(hipStreamSynchronize(st));
     return;
-  }
-  if (s->pending && s->used + need > s->cap) {
-    // the area is full: wait for its last copy (the earlier ones precede it on the same stream)
-    NS_HIP(hipEventSynchronize(s->ev));
-    s->used = 0;
-    s->pending = false;
   }
   std::memcpy(s->base + s->used, src, bytes);
   NS_HIP(hipMemcpyAsync(dst, s->base + s->used, bytes, hipMemcpyHostToDevice, st));

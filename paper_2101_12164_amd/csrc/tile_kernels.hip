@@ -7,6 +7,7 @@
 // a direct method (section on Schur complement preconditioners); here every
 // block of every size is factorised in the same sequence of launches.
 #include <algorithm>
+#include <type_traits>
 
 #include "ns_internal.h"
 
@@ -67,73 +68,172 @@ __device__ __forceinline__ void store_tile_lds(T* __restrict__ g, const T* s) {
   }
 }
 
-// Cholesky factor and its inverse of the TILE x TILE SPD tile in s (LDS,
-// column-major, stride LDT; lower triangle used), computed by wave 0 alone:
-// lane r keeps row r in registers; each pivot is read from its lane, the
-// scaled column and (for the inverse) the factor's columns are LDS broadcasts,
-// so no workgroup barrier is needed between columns.  On return s holds L
-// (zeros above the diagonal) and x holds L^{-1}.  A pivot <= 0 records
-// (block, column) in err once and is replaced by 1 so the sweep finishes.
+constexpr int PB = 16;  // panel width of the tile factorisation
+
 __device__ __forceinline__ double lane_value(double v, int lane) {  // v of `lane` (lane uniform)
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
   return __hiloint2double(hi, lo);
 }
 
-// 1 / sqrt(d) for d > 0: hardware estimate refined by two Newton steps
-// (y <- y (3 - d y^2) / 2), each doubling the number of correct bits.
-__device__ __forceinline__ double rsqrt_refined(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-  y = y * fma(-0.5 * d * y, y, 1.5);
-  y = y * fma(-0.5 * d * y, y, 1.5);
-  return y;
+// Value of v in lane N of the calling lane's row of 16 lanes (DPP row broadcast, one VALU move).
+template <int N>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + N, 0xF, 0xF, false);
+}
+// f(integral_constant<int, I>) for I = B .. E - 1 in order (indices usable as template arguments)
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
 }
 
-__device__ void potrf_trtri_wave(double* s, double* x, double* colbuf, int blk, int jt, int* err) {
-  if (threadIdx.x >= 64) return;
-  const int r = threadIdx.x;
-  double a[TILE];
+// Inverse of the PB x PB lower triangular block L_kk (rows and columns k0 .. k0 + PB - 1 of s, stride
+// LDT) by one wave: every row of 16 lanes holds the block (lane m of a row holds row m), so the factor's
+// columns reach the lanes by row broadcasts.  Row m of X from X L = I, columns right to left:
+// x_mc = (delta_mc - sum_{i>c} x_mi l_ic) / l_cc, with 1 / l_cc taken from inv_d.  Written by lanes 0-15
+// to the same block of x (zeros above the diagonal).
+__device__ __forceinline__ void diag_block_inverse(const double* s, double* x, const double* inv_d, int k0,
+                                                   int lane) {
+  const int m = lane & 15;
+  double a[PB], xi[PB];
 #pragma unroll
-  for (int q = 0; q < TILE; ++q) a[q] = s[q * LDT + r];
-  int badc = -1;
-  // right-looking: column c is scaled by its pivot, then updates the columns to its right
+  for (int q = 0; q < PB; ++q) a[q] = s[(k0 + q) * LDT + k0 + m];
+  static_for<0, PB>([&](auto cc) {
+    constexpr int c = PB - 1 - decltype(cc)::value;
+    double acc0 = (m == c) ? 1.0 : 0.0, acc1 = 0.0;
+    static_for<c + 1, PB>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      const double lic = row_bcast<i>(a[c]);
+      if constexpr (i & 1)
+        acc1 = fma(-xi[i], lic, acc1);
+      else
+        acc0 = fma(-xi[i], lic, acc0);
+    });
+    xi[c] = (acc0 + acc1) * inv_d[k0 + c];
+    asm volatile("" : "+v"(xi[c]));  // keeps the row in registers as it is formed (not sunk into the store)
+  });
+  if (lane < PB) {
 #pragma unroll
-  for (int c = 0; c < TILE; ++c) {
-    double d = lane_value(a[c], c);
-    if (!(d > 0.0)) {
-      if (badc < 0) badc = c;
-      d = 1.0;
-    }
-    const double inv = rsqrt_refined(d);
-    const double l = a[c] * inv;
-    a[c] = (r == c) ? d * inv : l;
-    colbuf[TILE + c] = inv;  // 1 / l_cc for the inverse below
-    colbuf[r] = l;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the lanes' stores before the reads below
-#pragma unroll
-    for (int q = c + 1; q < TILE; ++q) a[q] = fma(-l, colbuf[q], a[q]);  // a_rq -= l_rc l_qc
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int q = 0; q < PB; ++q) x[(k0 + q) * LDT + k0 + lane] = xi[q];
   }
-  if (badc >= 0 && r == 0) {
+}
+
+// Cholesky factor and its inverse of the TILE x TILE SPD tile in s (LDS, column-major, stride LDT; lower
+// triangle used), computed by the whole 256-thread workgroup in four panels of PB = 16 columns:
+//  * wave 0 factors the panel below the current diagonal in registers (lane r holds row k0 + r; each
+//    column's multipliers reach the other lanes by readlane, and the next pivot is formed in its own
+//    lane, so no barrier or LDS round trip sits on the chain of pivots);
+//  * the four waves then apply the panel to the trailing lower blocks, A_ij -= L_ik L_jk^T, with FP64
+//    MFMA.
+// Each wave then inverts one 16 x 16 diagonal block, and the inverse is assembled block row by block row,
+// X_ij = -X_ii sum_{m=j}^{i-1} L_im X_mj, again on MFMA.
+// On return s holds L and x holds L^{-1} (zeros above the diagonal in both).  A pivot <= 0 records
+// (block, column) in err once and is replaced by 1 so the sweep finishes.
+__device__ __forceinline__ void potrf_trtri_tile(double* s, double* x, double* inv_d, int blk, int jt, int* err) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  // blocks above the diagonal: zero in both outputs
+  for (int e = t; e < TILE2; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    if ((r >> 4) < (c >> 4)) {
+      s[c * LDT + r] = 0.0;
+      x[c * LDT + r] = 0.0;
+    }
+  }
+  int badc = -1;  // first non-positive pivot (wave 0)
+  for (int kb = 0; kb < TILE / PB; ++kb) {
+    const int k0 = kb * PB;
+    if (w == 0) {
+      const int row = k0 + lane;
+      const bool act = row < TILE;
+      double a[PB], invd[PB];
+#pragma unroll
+      for (int q = 0; q < PB; ++q) a[q] = act ? s[(k0 + q) * LDT + row] : 0.0;
+      // right-looking over the panel: column c is scaled by its pivot, then updates the columns to its right
+      double d = lane_value(a[0], 0);
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        if (!(d > 0.0)) {
+          if (badc < 0) badc = k0 + c;
+          d = 1.0;
+        }
+        // 1 / sqrt(d): hardware estimate and two Newton steps y <- y (3 - d y^2) / 2; the last step's
+        // factor is applied to a_rc * y directly
+        const double nh = -0.5 * d;
+        double y = __builtin_amdgcn_rsq(d);
+        y = y * fma(nh * y, y, 1.5);
+        const double e = fma(nh * y, y, 1.5);
+        const double inv = y * e;
+        invd[c] = inv;  // 1 / l_cc
+        const double l = (a[c] * y) * e;
+        a[c] = (lane == c) ? d * inv : l;
+        // the next pivot from its own lane: a_{c+1,c+1} - l_{c+1,c}^2
+        if (c + 1 < PB) d = lane_value(fma(-l, l, a[c + 1]), c + 1);
+#pragma unroll
+        for (int q = c + 1; q < PB; ++q) a[q] = fma(-l, lane_value(l, q), a[q]);  // a_rq -= l_rc l_qc
+      }
+      if (act) {
+#pragma unroll
+        for (int q = 0; q < PB; ++q) s[(k0 + q) * LDT + row] = (lane >= q) ? a[q] : 0.0;
+      }
+      if (lane < PB) {
+        double v = invd[0];
+#pragma unroll
+        for (int c = 1; c < PB; ++c) v = (lane == c) ? invd[c] : v;
+        inv_d[k0 + lane] = v;
+      }
+    }
+    __syncthreads();
+    if (kb + 1 < TILE / PB) {
+      // trailing lower blocks (i, j), kb < j <= i, spread over the waves
+      int nb = 0;
+      for (int j = kb + 1; j < TILE / PB; ++j)
+        for (int i = j; i < TILE / PB; ++i, ++nb) {
+          if ((nb & 3) != w) continue;
+          v4d acc;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[v] = s[(PB * j + lr) * LDT + PB * i + 4 * v + lq];
+#pragma unroll
+          for (int st = 0; st < PB / 4; ++st) {
+            const int kc = (k0 + 4 * st + lq) * LDT;
+            acc = MF<double>::mma(-s[kc + PB * i + lr], s[kc + PB * j + lr], acc);
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) s[(PB * j + lr) * LDT + PB * i + 4 * v + lq] = acc[v];
+        }
+      __syncthreads();
+    }
+  }
+  diag_block_inverse(s, x, inv_d, PB * w, lane);  // wave w: the diagonal block w
+  __syncthreads();
+  // off-diagonal blocks of the inverse, block row i by wave j < i
+  for (int i = 1; i < TILE / PB; ++i) {
+    const int j = w;
+    if (j < i) {
+      v4d tacc = {0, 0, 0, 0};
+      for (int m = j; m < i; ++m)
+#pragma unroll
+        for (int st = 0; st < PB / 4; ++st)  // T += L_im X_mj
+          tacc = MF<double>::mma(s[(PB * m + 4 * st + lq) * LDT + PB * i + lr],
+                                 x[(PB * j + lr) * LDT + PB * m + 4 * st + lq], tacc);
+      v4d xacc = {0, 0, 0, 0};
+#pragma unroll
+      for (int st = 0; st < PB / 4; ++st)  // X_ij = -X_ii T (T's accumulator layout is the B operand layout)
+        xacc = MF<double>::mma(-x[(PB * i + 4 * st + lq) * LDT + PB * i + lr], tacc[st], xacc);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) x[(PB * j + lr) * LDT + PB * i + 4 * v + lq] = xacc[v];
+    }
+    __syncthreads();
+  }
+  if (t == 0 && badc >= 0) {
     if (atomicCAS(err, 0, 1) == 0) {
       err[1] = blk;
       err[2] = jt * TILE + badc;
     }
   }
-#pragma unroll
-  for (int q = 0; q < TILE; ++q) s[q * LDT + r] = (r >= q) ? a[q] : 0.0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  // row r of X = L^{-1} from X L = I, columns right to left:
-  // x_rc = (delta_rc - sum_{m>c} x_rm l_mc) / l_cc, the sum split over four chains
-#pragma unroll
-  for (int c = TILE - 1; c >= 0; --c) {
-    double acc[4] = {(r == c) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int m = c + 1; m < TILE; ++m) acc[m & 3] = fma(-a[m], s[c * LDT + m], acc[m & 3]);
-    a[c] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * colbuf[TILE + c];
-  }
-#pragma unroll
-  for (int q = 0; q < TILE; ++q) x[q * LDT + r] = a[q];
 }
 
 // Left-looking update of tile column j: C_ij = A_ij - sum_{l<j} L_il L_jl^T for
@@ -215,8 +315,8 @@ __global__ __launch_bounds__(256) void k_chol_update(int j, int nblk, const int*
     store_tile_lds(Tij, sA);
     return;
   }
-  __shared__ double colbuf[2 * TILE];
-  potrf_trtri_wave(sA, sB, colbuf, b, j, err);
+  __shared__ double inv_d[TILE];
+  potrf_trtri_tile(sA, sB, inv_d, b, j, err);
   __syncthreads();
   store_tile_lds(Tij, sA);
   store_tile_lds(Linv + ioff[b] + int64_t(j) * TILE2, sB);
