@@ -218,6 +218,14 @@ void upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
   s->pending = true;
 }
 
+void* pinned_scratch(size_t bytes) {
+  constexpr size_t CAP = 4096;
+  thread_local void* buf = nullptr;
+  if (bytes > CAP) fail(INVALID_ARG, "pinned scratch request too large");
+  if (!buf) NS_HIP(hipHostMalloc(&buf, CAP, hipHostMallocDefault));
+  return buf;
+}
+
 void stream_idle(hipStream_t st) {
   for (int i = 0; i < g_nstage; ++i)
     if (g_stage[i].st == st) {

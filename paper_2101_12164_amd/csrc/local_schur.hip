@@ -371,6 +371,20 @@ void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStr
   NS_LAUNCH_CHECK();
 }
 
+void tri_gram(const TileLevel& lv, const double* Y, double* C, int64_t ld, const int* kstart, int kstride,
+              double alg_flops, hipStream_t st) {
+  if (lv.nblk == 0) return;
+  // C_b = Y_b^T Y_b: block b at element offset inv_off[b] of both, every leading dimension ld
+  GemmBatch g{kstart, kstride, lv.npad_d, lv.npad_d, lv.inv_off, lv.inv_lda, lv.inv_off, 1, ld, lv.inv_off, 1,
+              lv.inv_lda, 0};
+  double sq = 0;
+  for (int b = 0; b < lv.nblk; ++b) sq += double(lv.h_nt[b]) * TILE * lv.h_nt[b] * TILE;
+  KScope ks(KF_INV64, st, 2.0 * sq * sizeof(double), alg_flops);
+  dim3 grid(lv.max_nt, lv.max_nt, lv.nblk);
+  k_gemm_tn<double, 64><<<grid, 256, 0, st>>>(g, Y, Y, C, 0, 1);
+  NS_LAUNCH_CHECK();
+}
+
 template void tile_apply_inverse<double>(const TileLevel&, const double*, double*, int, hipStream_t);
 template void tile_apply_inverse<float>(const TileLevel&, const float*, float*, int, hipStream_t);
 

@@ -50,6 +50,9 @@ void dev_free(void* p);         // back to the cache, ordered on alloc_stream()
 void upload(void* dst, const void* src, size_t bytes, hipStream_t st);
 // Tells the staging area that stream st has been synchronised.
 void stream_idle(hipStream_t st);
+// A small pinned host buffer of the calling thread (at most 4 KiB; allocated on first use and kept until the
+// process ends) for device-to-host copies the host waits for through an event.
+void* pinned_scratch(size_t bytes);
 
 // Owning device buffer.
 template <class T>
@@ -219,6 +222,11 @@ void tile_make_transposed(TileLevel& lv, hipStream_t st);
 void tile_solve1(const TileLevel& lv, double* B, int64_t ldb, hipStream_t st);
 // Explicit inverses (L L^T)^{-1} of every block of a level (FP64, optional FP32 copy).
 void tile_make_inverse(TileLevel& lv, bool fp32, hipStream_t st);
+// C_b = Y_b^T Y_b for the lower triangular Y_b of every block of lv (stacked at the offsets inv_off, leading
+// dimension ld; kstart[b * kstride + t]: first tile row holding a nonzero of column tile t): the tiles on
+// and below the diagonal are formed from that row on and mirrored.
+void tri_gram(const TileLevel& lv, const double* Y, double* C, int64_t ld, const int* kstart, int kstride,
+              double alg_flops, hipStream_t st);
 // C = A^{-1} B for every block with the explicit inverses; B, C padded rhs (ld ncols).
 template <class T>
 void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStream_t st);

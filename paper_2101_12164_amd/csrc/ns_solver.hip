@@ -586,15 +586,38 @@ void pcg_core(Handle& h, const double* b, double* x, double rtol, int maxit, std
         fail(HIP, std::string("PCG graph capture failed: ") + hipGetErrorString(e));
       }
     }
-    while (hc[0] < np && hc[1] < maxit) {
-      if (exec) {
+    if (exec && hc[0] < np && hc[1] < maxit) {
+      // One replay ahead: replay g + 1 is queued before the host reads the counters left by replay g, so
+      // the device never waits for the host's test.  Replays after convergence change nothing (finished
+      // problems are frozen, iterations past maxit are no-ops).
+      int* hp = static_cast<int*>(pinned_scratch(4 * sizeof(int)));
+      Event ev[2];
+      int64_t issued = hc[1];
+      auto issue = [&](int s) {
         NS_HIP(hipGraphLaunch(exec, st));
-      } else {
-        head(st);
-        read_back(h, hc, S.ndone, 2);
-        if (hc[0] >= np || hc[1] >= maxit) break;
-        tail(st);
+        NS_HIP(hipMemcpyAsync(hp + 2 * s, S.ndone, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        NS_HIP(hipEventRecord(ev[s].e, st));
+        issued += m;
+      };
+      int slot = 0;
+      issue(0);
+      for (;;) {
+        const bool more = issued < maxit;
+        if (more) issue(slot ^ 1);
+        NS_HIP(hipEventSynchronize(ev[slot].e));
+        hc[0] = hp[2 * slot];
+        hc[1] = hp[2 * slot + 1];
+        if (hc[0] >= np || hc[1] >= maxit || !more) break;
+        slot ^= 1;
       }
+      NS_HIP(hipStreamSynchronize(st));  // the replay queued ahead has finished too
+      stream_idle(st);
+    }
+    while (!exec && hc[0] < np && hc[1] < maxit) {
+      head(st);
+      read_back(h, hc, S.ndone, 2);
+      if (hc[0] >= np || hc[1] >= maxit) break;
+      tail(st);
       read_back(h, hc, S.ndone, 2);
     }
     if (exec) (void)hipGraphExecDestroy(exec);

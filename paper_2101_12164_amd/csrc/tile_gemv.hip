@@ -180,13 +180,8 @@ void tile_solve1(const TileLevel& lv, double* B, int64_t ldb, hipStream_t st) {
 
 void tile_make_inverse(TileLevel& lv, bool fp32, hipStream_t st) {
   if (lv.nblk == 0) return;
-  int maxpad = lv.max_nt * TILE;
+  const int maxpad = lv.max_nt * TILE;
   lv.inv_ld = maxpad;
-  lv.Ainv64.alloc(lv.nrows_pad * maxpad);
-  NS_HIP(hipMemsetAsync(lv.Ainv64.p, 0, lv.nrows_pad * maxpad * sizeof(double), st));
-  k_identity_blocks<<<dim3((maxpad + 255) / 256, lv.nblk), 256, 0, st>>>(lv.nt, lv.roff, lv.Ainv64, maxpad);
-  NS_LAUNCH_CHECK();
-  tile_solve<double>(lv, lv.Ainv64.p, maxpad, maxpad, 64, st);
   std::vector<int64_t> aoff(lv.nblk), lda(lv.nblk, maxpad);
   std::vector<int> np(lv.nblk);
   for (int b = 0; b < lv.nblk; ++b) {
@@ -199,6 +194,35 @@ void tile_make_inverse(TileLevel& lv, bool fp32, hipStream_t st) {
   upload(lv.inv_off.p, aoff.data(), lv.nblk * sizeof(int64_t), st);
   upload(lv.inv_lda.p, lda.data(), lv.nblk * sizeof(int64_t), st);
   upload(lv.npad_d.p, np.data(), lv.nblk * sizeof(int), st);
+  // Y_b = L_b^{-1}: forward sweep on the identity.  Column chunk c is zero above tile row c * cw / TILE
+  // and stays so, so its sweep starts there; narrower chunks when few blocks would leave the device idle.
+  int cw = 64;
+  while (cw > 16 && int64_t(lv.nblk) * ((maxpad + cw - 1) / cw) < 512) cw /= 2;
+  const int nchunk = (maxpad + cw - 1) / cw;
+  std::vector<int> ft(size_t(lv.nblk) * nchunk), kst(size_t(lv.nblk) * lv.max_nt);
+  double fl_fwd = 0, fl_gram = 0;
+  for (int b = 0; b < lv.nblk; ++b) {
+    for (int c = 0; c < nchunk; ++c) ft[size_t(b) * nchunk + c] = c * cw / TILE;
+    for (int t = 0; t < lv.max_nt; ++t) kst[size_t(b) * lv.max_nt + t] = t;
+    const double n = np[b];
+    fl_fwd += n * n * n / 3.0;   // column c of the identity: (n - c)^2 flops on a dense factor
+    fl_gram += n * n * n / 3.0;  // lower half of Y^T Y over the nonzero rows
+  }
+  DBuf<int> ftd, kstd;
+  ftd.alloc(ft.size());
+  kstd.alloc(kst.size());
+  upload(ftd.p, ft.data(), ft.size() * sizeof(int), st);
+  upload(kstd.p, kst.data(), kst.size() * sizeof(int), st);
+  DBuf<double> Y;
+  Y.alloc(lv.nrows_pad * maxpad);
+  NS_HIP(hipMemsetAsync(Y.p, 0, lv.nrows_pad * maxpad * sizeof(double), st));
+  k_identity_blocks<<<dim3((maxpad + 255) / 256, lv.nblk), 256, 0, st>>>(lv.nt, lv.roff, Y.p, maxpad);
+  NS_LAUNCH_CHECK();
+  tile_solve_fwd<double>(lv, Y.p, maxpad, maxpad, cw, st, lv.npad_d.p, ftd.p, fl_fwd);
+  // A_b^{-1} = L_b^{-T} L_b^{-1} = Y_b^T Y_b (lower tiles formed, mirrored)
+  lv.Ainv64.alloc(lv.nrows_pad * maxpad);
+  NS_HIP(hipMemsetAsync(lv.Ainv64.p, 0, lv.nrows_pad * maxpad * sizeof(double), st));
+  tri_gram(lv, Y.p, lv.Ainv64.p, maxpad, kstd.p, lv.max_nt, fl_gram, st);
   std::vector<int> dims(lv.nblk);
   for (int b = 0; b < lv.nblk; ++b) dims[b] = lv.h_nt[b] * TILE;
   sym_pack(lv.inv_sym, dims, lv.Ainv64.p, lv.inv_off.p, lv.inv_lda.p, lv.roff.p, st);
