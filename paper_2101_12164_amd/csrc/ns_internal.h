@@ -222,6 +222,10 @@ void tile_make_transposed(TileLevel& lv, hipStream_t st);
 void tile_solve1(const TileLevel& lv, double* B, int64_t ldb, hipStream_t st);
 // Explicit inverses (L L^T)^{-1} of every block of a level (FP64, optional FP32 copy).
 void tile_make_inverse(TileLevel& lv, bool fp32, hipStream_t st);
+// B = A^{-1} B (forward and backward sweeps, 64-column chunks) for a right-hand side whose chunk c of block b
+// is zero above tile row first_tile[b * chunks + c] (a value >= the block's tile count: the chunk is zero).
+void tile_solve_chunks(const TileLevel& lv, double* B, int64_t ldb, int ncols, const int* first_tile,
+                       hipStream_t st);
 // C_b = Y_b^T Y_b for the lower triangular Y_b of every block of lv (stacked at the offsets inv_off, leading
 // dimension ld; kstart[b * kstride + t]: first tile row holding a nonzero of column tile t): the tiles on
 // and below the diagonal are formed from that row on and mirrored.

@@ -352,16 +352,6 @@ __global__ void k_maps(int64_t n, NodeMaps m, int32_t* iperm, int32_t* icomp, in
 }
 
 // padded level-2 row -> first padded row of its piece's junction block (for the dense A_s^{-1} A_sJ)
-__global__ void k_l2_jbase(int nl2, const int* __restrict__ nt2, const int64_t* __restrict__ roff2,
-                           const int* __restrict__ l2first, int P, const int64_t* __restrict__ roffJ,
-                           int64_t* __restrict__ jbase) {
-  const int b = blockIdx.y;
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nt2[b] * TILE) return;
-  int q = 0;
-  while (q + 1 < P && l2first[q + 1] <= b) ++q;
-  jbase[roff2[b] + r] = roffJ[q];
-}
 
 
 struct Outs {
@@ -516,13 +506,29 @@ __global__ void k_junction_update(const int* __restrict__ nbJ, const int* __rest
   LJ[foffJ[q] + band_elem(ntJ[q], ntJ[q] - 1, ji, jj)] -= acc;
 }
 
-// E(row, c - jbase(row)) = A_sJ(row, c)
-__global__ void k_sj_to_dense(int64_t nrows, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                              const double* __restrict__ val, const int64_t* __restrict__ jbase,
-                              double* __restrict__ E, int64_t lde) {
-  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= nrows) return;
-  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) E[r * lde + (col[e] - jbase[r])] = val[e];
+// Row r of level-2 block b: E(roff2_b + r, c - roffJ_q) = A_sJ(roff2_b + r, c), q the problem of block b, and
+// ft[b * nchunk + chunk of the column] = the smallest tile row of block b holding a nonzero of that chunk.
+__global__ void k_sj_to_dense(int nl2, const int* __restrict__ nt2, const int64_t* __restrict__ roff2,
+                              const int* __restrict__ l2first, int P, const int64_t* __restrict__ roffJ,
+                              const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                              const double* __restrict__ val, double* __restrict__ E, int64_t lde, int nchunk,
+                              int* __restrict__ ft) {
+  const int b = blockIdx.y;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nt2[b] * TILE) return;
+  int q = 0;
+  while (q + 1 < P && l2first[q + 1] <= b) ++q;
+  const int64_t row = roff2[b] + r, jb = roffJ[q];
+  for (int64_t e = ptr[row]; e < ptr[row + 1]; ++e) {
+    const int64_t c = col[e] - jb;
+    E[row * lde + c] = val[e];
+    atomicMin(&ft[int64_t(b) * nchunk + c / TILE], r / TILE);
+  }
+}
+
+__global__ void k_fill_int(int64_t n, int v, int* __restrict__ a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
 }
 
 void pad_identity(TileLevel& lv, hipStream_t st) {
@@ -780,16 +786,20 @@ void assemble_junction(Handle& h) {
   int maxJ = 0;
   for (int q = 0; q < h.LJ.nblk; ++q) maxJ = std::max(maxJ, h.LJ.h_nb[q]);
   DBuf<double> E;
-  DBuf<int64_t> jbase;
+  DBuf<int> ft;
   E.alloc(n2pad * ldE);
-  jbase.alloc(n2pad);
+  const int nchunk = ldE / TILE;
+  const int64_t nft = int64_t(h.L2.nblk) * nchunk;
+  ft.alloc(nft);
   NS_HIP(hipMemsetAsync(E.p, 0, n2pad * ldE * sizeof(double), st));
-  k_l2_jbase<<<dim3((h.L2.max_nt * TILE + 255) / 256, h.L2.nblk), 256, 0, st>>>(
-      h.nl2, h.L2.nt, h.L2.roff, h.l2first, h.nprob, h.LJ.roff, jbase);
+  k_fill_int<<<unsigned((nft + 255) / 256), 256, 0, st>>>(nft, INT32_MAX, ft);  // no nonzero yet
   NS_LAUNCH_CHECK();
-  k_sj_to_dense<<<int((n2pad + 255) / 256), 256, 0, st>>>(n2pad, h.AsJ.ptr, h.AsJ.col, h.AsJ.val64, jbase, E, ldE);
+  k_sj_to_dense<<<dim3((h.L2.max_nt * TILE + 255) / 256, h.L2.nblk), 256, 0, st>>>(
+      h.nl2, h.L2.nt, h.L2.roff, h.l2first, h.nprob, h.LJ.roff, h.AsJ.ptr, h.AsJ.col, h.AsJ.val64, E, ldE, nchunk, ft);
   NS_LAUNCH_CHECK();
-  tile_solve<double>(h.L2, E.p, ldE, maxJ, 64, st);  // E = A_s^{-1} A_sJ
+  // E = A_s^{-1} A_sJ: a patch touches few junction nodes, so most column chunks of a block are zero and
+  // both sweeps skip them (the forward one also starts each chunk at its first nonzero tile row)
+  tile_solve_chunks(h.L2, E.p, ldE, maxJ, ft, st);
   k_junction_update<<<dim3(unsigned((int64_t(maxJ) * maxJ + 255) / 256), h.LJ.nblk), 256, 0, st>>>(
       h.LJ.nb, h.LJ.nt, h.LJ.roff, h.LJ.foff, h.AJs.ptr, h.AJs.col, h.AJs.val64, E, ldE, h.LJ.L64);
   NS_LAUNCH_CHECK();

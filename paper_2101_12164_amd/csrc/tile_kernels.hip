@@ -459,9 +459,11 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rl = lane & 15, kq = lane >> 4;
   TrsmStage<T, CW> s0, s1;
-  // forward sweeps whose right-hand side is zero above tile row `first` start there
-  const int first = (FWD && first_tile) ? min(first_tile[b * nchunk_all + chunk], nt) : 0;
-  for (int step = first; step < nt; ++step) {
+  // forward sweeps whose right-hand side is zero above tile row `first` start there; with first_tile the
+  // backward sweep only uses it to skip chunks that are entirely zero (first >= nt)
+  const int first = first_tile ? min(first_tile[b * nchunk_all + chunk], nt) : 0;
+  if (!FWD && first >= nt) return;  // a chunk that is zero on entry stays zero
+  for (int step = FWD ? first : 0; step < nt; ++step) {
     const int i = FWD ? step : nt - 1 - step;
     acc_t acc[NB];
 #pragma unroll
@@ -658,6 +660,27 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
     k_trsm<T, 64, true><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0, lv.ioff + b0,
                                               lv.roff + b0, L, Li, B, ldb, ncols, nc, ft, nchunk_all, row0);
   NS_LAUNCH_CHECK();
+}
+
+void tile_solve_chunks(const TileLevel& lv, double* B, int64_t ldb, int ncols, const int* first_tile,
+                       hipStream_t st) {
+  if (lv.nblk == 0 || ncols == 0) return;
+  const int nchunk = (ncols + TILE - 1) / TILE;
+  const int grid = (lv.nblk + 7) / 8 * 8 * nchunk;
+  const int fam = lv.role == 0 ? KF_TRSM_I64 : KF_TRSM_G64;
+  const double bytes = (lv.alg_tri + 2.0 * lv.alg_rows * ncols) * sizeof(double);
+  {
+    KScope ks(fam, st, bytes, lv.alg_sq * ncols);
+    k_trsm<double, TILE, true><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, lv.L64,
+                                                     lv.Linv64, B, ldb, ncols, nullptr, first_tile, nchunk);
+    NS_LAUNCH_CHECK();
+  }
+  {
+    KScope ks(fam, st, bytes, lv.alg_sq * ncols);
+    k_trsm<double, TILE, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, lv.L64,
+                                                      lv.Linv64, B, ldb, ncols, nullptr, first_tile, nchunk);
+    NS_LAUNCH_CHECK();
+  }
 }
 
 template void tile_solve_fwd<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t, const int*, const int*,
