@@ -388,22 +388,24 @@ void tri_gram(const TileLevel& lv, const double* Y, double* C, int64_t ld, const
 template void tile_apply_inverse<double>(const TileLevel&, const double*, double*, int, hipStream_t);
 template void tile_apply_inverse<float>(const TileLevel&, const float*, float*, int, hipStream_t);
 
-void local_schur_build(Handle& h) {
+void local_schur_plan(Handle& h) {
   hipStream_t st = h.stream;
   LocalSchur& ls = h.LS;
   const TileLevel& lv = h.L1;
   const int nb = lv.nblk;
-  const int64_t nG = h.nG, nIp = lv.nrows_pad;
+  const int64_t nIp = lv.nrows_pad;
   ls.nblk = nb;
   // row -> block map of the padded interior rows
-  DBuf<int32_t> rblk;
+  LocalSchurPlan& pl = ls.plan;
+  DBuf<int32_t>& rblk = pl.rblk;
   rblk.alloc(nIp);
   NS_HIP(hipMemsetAsync(rblk.p, 0xFF, nIp * sizeof(int32_t), st));
   k_row_block<<<dim3((lv.max_nt * TILE + 255) / 256, nb), 256, 0, st>>>(lv.nt, lv.roff, rblk);
   NS_LAUNCH_CHECK();
   // interface range of every block: its problem's interface rows
   std::vector<int64_t> gbase(nb), gcnt(nb);
-  int64_t ldf = 1;
+  int64_t& ldf = pl.ldf;
+  ldf = 1;
   for (int q = 0; q < h.nprob; ++q) {
     const int64_t g0 = h.h_goff[q], g1 = h.h_goff[q + 1];
     ldf = std::max(ldf, g1 - g0);
@@ -412,13 +414,14 @@ void local_schur_build(Handle& h) {
       gcnt[j] = g1 - g0;
     }
   }
-  DBuf<int64_t> gbase_d, gcnt_d;
+  DBuf<int64_t>& gbase_d = pl.gbase_d;
+  DBuf<int64_t> gcnt_d;
   gbase_d.alloc(nb);
   gcnt_d.alloc(nb);
   upload(gbase_d.p, gbase.data(), nb * sizeof(int64_t), st);
   upload(gcnt_d.p, gcnt.data(), nb * sizeof(int64_t), st);
   DBuf<int> flag, cnt;
-  DBuf<int32_t> cidx;
+  DBuf<int32_t>& cidx = pl.cidx;
   flag.alloc(int64_t(nb) * ldf);
   cnt.alloc(nb);
   cidx.alloc(int64_t(nb) * ldf);
@@ -432,7 +435,8 @@ void local_schur_build(Handle& h) {
   NS_HIP(hipStreamSynchronize(st));
   // stacked layouts: Gamma_j lists padded to 64 rows; S_j with ld = padded m_j
   std::vector<int64_t> goff(nb), soff(nb), sld(nb), wld(nb);
-  std::vector<int> Kv(nb);
+  std::vector<int>& Kv = pl.Kv;
+  Kv.assign(nb, 0);
   int64_t gp = 0, sp = 0;
   ls.max_m = 0;
   for (int j = 0; j < nb; ++j) {
@@ -448,6 +452,7 @@ void local_schur_build(Handle& h) {
   ls.npos = gp;
   ls.s_elems = sp;
   const int64_t ldw = std::max(ls.max_m, 1);
+  pl.ldw = ldw;
   for (int j = 0; j < nb; ++j) wld[j] = ldw;
   ls.goff.alloc(nb);
   upload(ls.goff.p, goff.data(), nb * sizeof(int64_t), st);
@@ -471,6 +476,21 @@ void local_schur_build(Handle& h) {
   up(ls.wld, wld);
   ls.S64.alloc(sp > 0 ? sp : 1);
   NS_HIP(hipMemsetAsync(ls.S64.p, 0, ls.S64.n * sizeof(double), st));
+}
+
+void local_schur_form(Handle& h) {
+  hipStream_t st = h.stream;
+  LocalSchur& ls = h.LS;
+  const TileLevel& lv = h.L1;
+  const int nb = lv.nblk;
+  const int64_t nG = h.nG;
+  LocalSchurPlan& pl = ls.plan;
+  const DBuf<int32_t>& rblk = pl.rblk;
+  const DBuf<int64_t>& gbase_d = pl.gbase_d;
+  const DBuf<int32_t>& cidx = pl.cidx;
+  const int64_t ldf = pl.ldf, ldw = pl.ldw;
+  const std::vector<int>& Kv = pl.Kv;
+  const int64_t gp = ls.npos;
   // W_j = L_j^{-1} B_j (forward sweep only), then S_j = W_j^T W_j, for groups of consecutive blocks whose
   // W fits a fixed budget (the groups only bound memory: every block is computed the same way)
   const int64_t budget = std::max<int64_t>(int64_t(1) << 30, int64_t(lv.max_nt) * TILE * ldw);
@@ -568,6 +588,9 @@ void local_schur_build(Handle& h) {
   }
   sym_pack(ls.sym, ls.h_m, ls.S64.p, ls.soff.p, ls.sld.p, ls.goff.p, st);
   ls.built = true;
+  pl.rblk.release();
+  pl.cidx.release();
+  pl.gbase_d.release();
 }
 
 template <class T>

@@ -9,8 +9,18 @@ namespace ns {
 
 // Explicit local Schur complements S_j = (L_j^{-1} B_j)^T (L_j^{-1} B_j), one
 // dense m_j x m_j block per subdomain (m_j = interface nodes coupled to it).
+// Structure of the local Schur formation handed from its symbolic pass (which reads sizes back to the host)
+// to its numeric pass.
+struct LocalSchurPlan {
+  DBuf<int32_t> rblk, cidx;  // padded interior row -> block; (block, interface index) -> column of B_j
+  DBuf<int64_t> gbase_d;     // first interface row of each block's problem
+  int64_t ldf = 1, ldw = 1;  // interface rows of the largest problem; columns of the stacked W
+  std::vector<int> Kv;       // padded rows of every block
+};
+
 struct LocalSchur {
   bool built = false;
+  LocalSchurPlan plan;
   int nblk = 0, max_m = 0;
   int64_t npos = 0, s_elems = 0;  // stacked (padded) interface rows, S elements
   std::vector<int> h_m;
@@ -137,7 +147,9 @@ struct Pieces {
 void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
                   const double* val, const int32_t* part, const Pieces* pieces = nullptr);
 void assemble_junction(Handle& h);
-void local_schur_build(Handle& h);
+// Symbolic pass (interface lists, layouts; waits for the device) and numeric pass (needs the interior factor).
+void local_schur_plan(Handle& h);
+void local_schur_form(Handle& h);
 
 // Generic row gather / scatter and CSR products (row-major blocks).
 template <class T>

@@ -730,8 +730,11 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
     }
     NS_HIP(hipEventRecord(join.e, h->stream));
   }
+  // the symbolic part of the local Schur formation reads sizes back: done before the interior factorisation is
+  // queued, so that wait finds the stream idle
+  if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_plan(*h);
   tile_cholesky(h->L1, h->dflags.p + CHOL_FLAGS, h->stream);
-  if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_build(*h);
+  if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_form(*h);
   if (trsv1_supported_size(h->L1)) tile_make_transposed(h->L1, h->stream);
   if (h->prec_inner && !h->LS.built) tile_make_fp32(h->L1, h->stream);
   NS_HIP(hipStreamWaitEvent(h->stream, join.e, 0));
