@@ -99,8 +99,8 @@ class DBBD:
 class Operators:
     """A_I^{-1}, A_Gamma^{-1}, the Schur operator S_Gamma and W.
 
-    A_I^{-1}: one Cholesky factor per diagonal block (the blocks are factorised
-    independently, "cheaply in parallel" in the paper's words).  A_Gamma^{-1}:
+    A_I^{-1}: one Cholesky factor per diagonal block (the blocks are independent
+    of each other, so each is factorised on its own).  A_Gamma^{-1}:
     exact, assumed available by eq. (S1).  ``factor='dense'`` uses LAPACK
     Cholesky on dense blocks; ``'sparse'`` uses SuperLU (same result up to
     rounding, for sizes where dense copies do not fit in host memory).

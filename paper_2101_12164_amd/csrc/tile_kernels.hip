@@ -1,11 +1,13 @@
-// Dense tile kernels for gfx950: batched left-looking Cholesky of the subdomain
-// blocks (diagonal tile factor + triangular inverse in LDS, off-diagonal
-// updates and panels on MFMA) and the batched forward/backward triangular
-// solves with many right-hand sides used by every Schur-operator application.
+// Dense tile kernels for gfx950: batched right-looking Cholesky of the subdomain
+// blocks (per tile column, one launch applies the previous column to the
+// trailing band tiles and factorises the diagonal tile; a second forms the
+// panel below it, all on FP64 MFMA) and the batched forward/backward
+// triangular solves with many right-hand sides used by every Schur-operator
+// application.
 //
-// The paper factorises the diagonal blocks of A_I "cheaply in parallel" with
-// a direct method (section on Schur complement preconditioners); here every
-// block of every size is factorised in the same sequence of launches.
+// The paper factorises the diagonal blocks of A_I independently of each other
+// with a direct method (section on Schur complement preconditioners); here
+// every block of every size is factorised in the same sequence of launches.
 #include <algorithm>
 #include <type_traits>
 
@@ -236,54 +238,54 @@ __device__ __forceinline__ void potrf_trtri_tile(double* s, double* x, double* i
   }
 }
 
-// Left-looking update of tile column j: C_ij = A_ij - sum_{l<j} L_il L_jl^T for
-// i >= j; the diagonal workgroup then factorises C_jj and inverts L_jj.
-// Workgroup ids map all tiles of one block to one XCD (ids are dispatched
-// round-robin over the 8 XCDs), so the shared row j tiles L_jl hit that L2.
-// The next (L_il, L_jl) pair is held in registers while the MFMAs consume the
-// pair staged in LDS.
-__global__ __launch_bounds__(256) void k_chol_update(int j, int nblk, const int* __restrict__ nt_arr,
-                                                     const int* __restrict__ nbt_arr,
-                                                     const int64_t* __restrict__ foff,
-                                                     const int64_t* __restrict__ ioff, double* __restrict__ L,
-                                                     double* __restrict__ Linv, int* err) {
+// Right-looking step j: every trailing tile (i, k), j <= k <= i, within the band of column j - 1 gets
+// A_ik -= L_{i,j-1} L_{k,j-1}^T (one tile product per workgroup, all of them in parallel); the workgroup of
+// the diagonal tile (j, j) then factorises it and inverts L_jj.  Pair p of a block numbers the tiles
+// (j + di, j + dk), p = di (di + 1) / 2 + dk, so pair 0 (the diagonal, the step's critical path) gets the
+// lowest workgroup ids of every block and is dispatched first.  Ids map all tiles of one block to one XCD.
+__global__ __launch_bounds__(256) void k_chol_step(int j, int nblk, const int* __restrict__ nt_arr,
+                                                   const int* __restrict__ nbt_arr, const int64_t* __restrict__ foff,
+                                                   const int64_t* __restrict__ ioff, double* __restrict__ L,
+                                                   double* __restrict__ Linv, int* err) {
   __shared__ double sA[TILE * LDT];
   __shared__ double sB[TILE * LDT];
+  __shared__ double inv_d[TILE];
   const int nbp8 = (nblk + 7) >> 3;
   const int g = blockIdx.x;
   const int slot = g >> 3;
   const int b = (g & 7) + 8 * (slot % nbp8);
-  const int i = j + slot / nbp8;
+  const int pair = slot / nbp8;
   if (b >= nblk) return;
+  int di = 0;
+  while ((di + 1) * (di + 2) / 2 <= pair) ++di;
+  const int dk = pair - di * (di + 1) / 2;
   const int nt = nt_arr[b], nbt = nbt_arr[b];
-  if (j >= nt || i >= nt || i - j > nbt) return;
+  const int i = j + di, k = j + dk, l = j - 1;
+  if (i >= nt) return;
+  const bool upd = l >= 0 && i - l <= nbt;  // L_il (and L_kl, k <= i) inside the band
+  if (!upd && di != 0) return;
   double* Lb = L + foff[b];
-  const int lbeg = max(0, i - nbt);  // L_il = 0 outside the band
+  double* Tik = Lb + band_tile_index(nt, nbt, i, k) * TILE2;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
-  v4d acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
-  constexpr int PT = TILE2 / 256;
-  double ra[PT], rb[PT];
-  auto gload = [&](int l) {
+  if (upd) {
+    constexpr int PT = TILE2 / 256;
+    double ra[PT], rb[PT];
     const double* ga = Lb + band_tile_index(nt, nbt, i, l) * TILE2;
-    const double* gb = Lb + band_tile_index(nt, nbt, j, l) * TILE2;
+    const double* gb = Lb + band_tile_index(nt, nbt, k, l) * TILE2;
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
       ra[q] = ga[threadIdx.x + 256 * q];
       rb[q] = gb[threadIdx.x + 256 * q];
     }
-  };
-  if (lbeg < j) gload(lbeg);
-  for (int l = lbeg; l < j; ++l) {
-    __syncthreads();
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
       const int e = threadIdx.x + 256 * q;
       sA[(e >> 6) * LDT + (e & 63)] = ra[q];
       sB[(e >> 6) * LDT + (e & 63)] = rb[q];
     }
-    if (l + 1 < j) gload(l + 1);
     __syncthreads();
+    const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+    v4d acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
 #pragma unroll 4
     for (int kk = 0; kk < TILE; kk += 4) {
       const int kr = (kk + (lane >> 4)) * LDT + (lane & 15);
@@ -294,12 +296,9 @@ __global__ __launch_bounds__(256) void k_chol_update(int j, int nblk, const int*
       acc10 = MF<double>::mma(a1, b0, acc10);
       acc11 = MF<double>::mma(a1, b1, acc11);
     }
-  }
-  __syncthreads();
-  double* Tij = Lb + band_tile_index(nt, nbt, i, j) * TILE2;
-  load_tile_lds(sA, Tij);
-  __syncthreads();
-  {
+    __syncthreads();
+    load_tile_lds(sA, Tik);
+    __syncthreads();
     const int cb = c0 + (lane & 15);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -309,16 +308,18 @@ __global__ __launch_bounds__(256) void k_chol_update(int j, int nblk, const int*
       sA[(cb)*LDT + rb + 16] -= acc10[v];
       sA[(cb + 16) * LDT + rb + 16] -= acc11[v];
     }
+    __syncthreads();
+    if (di != 0) {
+      store_tile_lds(Tik, sA);
+      return;
+    }
+  } else {
+    load_tile_lds(sA, Tik);
+    __syncthreads();
   }
-  __syncthreads();
-  if (i != j) {
-    store_tile_lds(Tij, sA);
-    return;
-  }
-  __shared__ double inv_d[TILE];
   potrf_trtri_tile(sA, sB, inv_d, b, j, err);
   __syncthreads();
-  store_tile_lds(Tij, sA);
+  store_tile_lds(Tik, sA);
   store_tile_lds(Linv + ioff[b] + int64_t(j) * TILE2, sB);
 }
 
@@ -569,14 +570,18 @@ void launch_trsm(const TileLevel& lv, T* B, int64_t ldb, int ncols, const T* L, 
 
 void tile_cholesky(TileLevel& lv, int* d_err, hipStream_t st) {
   if (lv.nblk == 0) return;
+  const int nbp8 = (lv.nblk + 7) / 8;
   for (int j = 0; j < lv.max_nt; ++j) {
     // tile rows j .. j + max_nbt of every block (rows outside a block's band exit at once)
     const int rows = std::min(lv.max_nt - j, lv.max_nbt + 1);
     {
+      // the work is attributed per tile column as in the left-looking order (the same total)
       KScope ks(KF_CHOL_UPDATE, st, lv.chol_bytes[j], lv.chol_upd_flops[j]);
-      const int nbp8 = (lv.nblk + 7) / 8;
-      k_chol_update<<<rows * nbp8 * 8, 256, 0, st>>>(j, lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.L64, lv.Linv64,
-                                                     d_err);
+      // trailing tiles of column j - 1: rows and columns j .. j - 1 + max_nbt
+      const int d = j == 0 ? 1 : std::max(1, std::min(lv.max_nbt, lv.max_nt - j));
+      const int pairs = d * (d + 1) / 2;
+      k_chol_step<<<pairs * nbp8 * 8, 256, 0, st>>>(j, lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.L64, lv.Linv64,
+                                                    d_err);
       NS_LAUNCH_CHECK();
     }
     if (rows > 1) {
