@@ -18,6 +18,13 @@ constexpr int NW = 16;  // waves per workgroup
 constexpr int NTH = NW * 64;
 constexpr int LDT = TILE + 1;
 
+// The sweeps walk the tile rows of a block in order; each step is a short chain of barriers, so the loads of
+// step i + 1 (the diagonal inverse and the band tiles of the next tile column, which do not depend on the
+// solution) are issued during step i and held in registers.  The nbt band tiles of a step are cut into
+// (tile, 16-column chunk) items, one per wave (rounds of NW items when nbt > NW / 4), so every wave loads
+// 16 + 4 values per step; partial sums are combined in a fixed order.
+constexpr int CH = TILE / 4;  // columns (rows) of a band tile per item
+
 // Forward: y = L^{-1} b (b, y in B with stride ldb, one column).
 __global__ __launch_bounds__(NTH) void k_trsv_fwd(const int* __restrict__ nt_arr, const int* __restrict__ nbt_arr,
                                                   const int64_t* __restrict__ foff,
@@ -33,14 +40,30 @@ __global__ __launch_bounds__(NTH) void k_trsv_fwd(const int* __restrict__ nt_arr
   const double* Lb = L + foff[b];
   const double* Ib = Linv + ioff[b];
   for (int e = threadIdx.x; e < nt * TILE; e += NTH) yv[e] = Bb[int64_t(e) * ldb];
+  // step i's operands of wave w: columns 4w .. 4w + 3 of Linv_ii (element (lane, c)) and item w of round 0:
+  // tile L_{i+1+w/4, i}, columns 16 (w % 4) .. + 15
+  double li[4], tt[CH];
+  auto load_step = [&](int i, double* l4, double* t16) {
+    const double* Li = Ib + int64_t(i) * TILE2;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) l4[c] = Li[(4 * w + c) * TILE + lane];
+    const int nl = min(nt - 1 - i, nbt);
+    if (w < 4 * nl) {
+      const double* T = Lb + (band_tile_index(nt, nbt, i, i) + 1 + (w >> 2)) * TILE2 + (CH * (w & 3)) * TILE;
+#pragma unroll
+      for (int c = 0; c < CH; ++c) t16[c] = T[c * TILE + lane];
+    }
+  };
+  if (nt > 0) load_step(0, li, tt);
   __syncthreads();
   for (int i = 0; i < nt; ++i) {
     // y_i = Linv_ii * acc_i: wave w sums columns [4w, 4w + 4)
-    const double* Li = Ib + int64_t(i) * TILE2;
     double p = 0.0;
 #pragma unroll
-    for (int c = 4 * w; c < 4 * w + 4; ++c) p += Li[c * TILE + lane] * yv[i * TILE + c];
+    for (int c = 0; c < 4; ++c) p += li[c] * yv[i * TILE + 4 * w + c];
     red[w * 64 + lane] = p;
+    double lin[4], ttn[CH];
+    if (i + 1 < nt) load_step(i + 1, lin, ttn);
     __syncthreads();
     if (threadIdx.x < 64) {
       double y = 0.0;
@@ -49,22 +72,46 @@ __global__ __launch_bounds__(NTH) void k_trsv_fwd(const int* __restrict__ nt_arr
       yv[i * TILE + threadIdx.x] = y;
     }
     __syncthreads();
-    // acc_l -= L_li y_i for i < l <= i + nbt (tiles of column i are contiguous)
-    const double* col = Lb + band_tile_index(nt, nbt, i, i) * TILE2;
-    const int lend = min(nt, i + nbt + 1);
-    for (int l = i + 1 + w; l < lend; l += NW) {
-      const double* T = col + int64_t(l - i) * TILE2;
+    // acc_l -= L_li y_i for i < l <= i + nbt, NW items (4 tiles) per round
+    const int nl = min(nt - 1 - i, nbt);
+    for (int r0 = 0; r0 < 4 * nl; r0 += NW) {
+      const int item = r0 + w;
       double s = 0.0;
-#pragma unroll 16
-      for (int c = 0; c < TILE; ++c) s += T[c * TILE + lane] * yv[i * TILE + c];
-      yv[l * TILE + lane] -= s;
+      if (item < 4 * nl) {
+        const double* yi = yv + i * TILE + CH * (item & 3);
+        if (r0 == 0) {
+#pragma unroll
+          for (int c = 0; c < CH; ++c) s += tt[c] * yi[c];
+        } else {
+          const double* T =
+              Lb + (band_tile_index(nt, nbt, i, i) + 1 + (item >> 2)) * TILE2 + (CH * (item & 3)) * TILE;
+#pragma unroll
+          for (int c = 0; c < CH; ++c) s += T[c * TILE + lane] * yi[c];
+        }
+      }
+      red[w * 64 + lane] = s;
+      __syncthreads();
+      if (threadIdx.x < 4 * 64) {
+        const int t = (r0 >> 2) + (threadIdx.x >> 6);
+        if (t < nl) {
+          const double* rq = red + (threadIdx.x >> 6) * 4 * 64 + lane;
+          yv[(i + 1 + t) * TILE + lane] -= (rq[0] + rq[64]) + (rq[128] + rq[192]);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    if (i + 1 < nt) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) li[c] = lin[c];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) tt[c] = ttn[c];
+    }
   }
   for (int e = threadIdx.x; e < nt * TILE; e += NTH) Bb[int64_t(e) * ldb] = yv[e];
 }
 
-// Backward: x = L^{-T} y, dot products with the transposed tiles LT.
+// Backward: x = L^{-T} y, dot products with the transposed tiles LT (row-major copies: element (r, c) of
+// L_li at r * TILE + c), items (tile, 16-row chunk); x_i = Linv_ii^T t with wave w summing rows 4w .. 4w + 3.
 __global__ __launch_bounds__(NTH) void k_trsv_bwd(const int* __restrict__ nt_arr, const int* __restrict__ nbt_arr,
                                                   const int64_t* __restrict__ foff,
                                                   const int64_t* __restrict__ ioff, const int64_t* __restrict__ roff,
@@ -72,7 +119,6 @@ __global__ __launch_bounds__(NTH) void k_trsv_bwd(const int* __restrict__ nt_arr
                                                   double* __restrict__ B, int64_t ldb) {
   extern __shared__ double yv[];
   __shared__ double red[NW * 64];
-  __shared__ double sI[TILE * LDT];
   __shared__ double tv[TILE];
   const int b = blockIdx.x;
   const int nt = nt_arr[b], nbt = nbt_arr[b];
@@ -81,32 +127,57 @@ __global__ __launch_bounds__(NTH) void k_trsv_bwd(const int* __restrict__ nt_arr
   const double* Lb = LT + foff[b];
   const double* Ib = Linv + ioff[b];
   for (int e = threadIdx.x; e < nt * TILE; e += NTH) yv[e] = Bb[int64_t(e) * ldb];
+  // step i's operands of wave w: Linv_ii(4w + k, lane) for k < 4 and item w of round 0: rows
+  // 16 (w % 4) .. + 15 of L_{i+1+w/4, i}
+  double li[4], tt[CH];
+  auto load_step = [&](int i, double* l4, double* t16) {
+    const double* Li = Ib + int64_t(i) * TILE2;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) l4[k] = Li[lane * TILE + 4 * w + k];
+    const int nl = min(nt - 1 - i, nbt);
+    if (w < 4 * nl) {
+      const double* T = Lb + (band_tile_index(nt, nbt, i, i) + 1 + (w >> 2)) * TILE2 + (CH * (w & 3)) * TILE;
+#pragma unroll
+      for (int r = 0; r < CH; ++r) t16[r] = T[r * TILE + lane];
+    }
+  };
+  if (nt > 0) load_step(nt - 1, li, tt);
   __syncthreads();
   for (int i = nt - 1; i >= 0; --i) {
-    // t = y_i - sum_{l>i} L_li^T x_l : lane c of wave w over tiles l = i+1+w, ...
-    const double* col = Lb + band_tile_index(nt, nbt, i, i) * TILE2;
-    const int lend = min(nt, i + nbt + 1);
-    double s = 0.0;
-    for (int l = i + 1 + w; l < lend; l += NW) {
-      const double* T = col + int64_t(l - i) * TILE2;  // row-major copy: element (r, c) at r * TILE + c
-#pragma unroll 16
-      for (int r = 0; r < TILE; ++r) s += T[r * TILE + lane] * yv[l * TILE + r];
-    }
-    red[w * 64 + lane] = s;
-    const double* Li = Ib + int64_t(i) * TILE2;
-    for (int e = threadIdx.x; e < TILE2; e += NTH) sI[(e >> 6) * LDT + (e & 63)] = Li[e];
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      double t = yv[i * TILE + threadIdx.x];
+    // t = y_i - sum_{l>i} L_li^T x_l, NW items per round, summed in item order by threads 0-63
+    const int nl = min(nt - 1 - i, nbt);
+    double lin[4], ttn[CH];
+    if (i > 0) load_step(i - 1, lin, ttn);
+    double tacc = 0.0;
+    for (int r0 = 0; r0 < 4 * nl; r0 += NW) {
+      const int item = r0 + w;
+      double s = 0.0;
+      if (item < 4 * nl) {
+        const double* xl = yv + (i + 1 + (item >> 2)) * TILE + CH * (item & 3);
+        if (r0 == 0) {
 #pragma unroll
-      for (int q = 0; q < NW; ++q) t -= red[q * 64 + threadIdx.x];
-      tv[threadIdx.x] = t;
+          for (int r = 0; r < CH; ++r) s += tt[r] * xl[r];
+        } else {
+          const double* T =
+              Lb + (band_tile_index(nt, nbt, i, i) + 1 + (item >> 2)) * TILE2 + (CH * (item & 3)) * TILE;
+#pragma unroll
+          for (int r = 0; r < CH; ++r) s += T[r * TILE + lane] * xl[r];
+        }
+      }
+      red[w * 64 + lane] = s;
+      __syncthreads();
+      if (threadIdx.x < 64) {
+#pragma unroll
+        for (int q = 0; q < NW; ++q) tacc += red[q * 64 + threadIdx.x];
+      }
+      __syncthreads();
     }
+    if (threadIdx.x < 64) tv[threadIdx.x] = yv[i * TILE + threadIdx.x] - tacc;
     __syncthreads();
-    // x_i = Linv_ii^T t : out[c] = sum_r Linv[r][c] t[r], wave w sums rows [4w, 4w+4)
+    // x_i = Linv_ii^T t : out[c] = sum_r Linv[r][c] t[r]
     double p = 0.0;
 #pragma unroll
-    for (int r = 4 * w; r < 4 * w + 4; ++r) p += sI[lane * LDT + r] * tv[r];
+    for (int k = 0; k < 4; ++k) p += li[k] * tv[4 * w + k];
     red[w * 64 + lane] = p;
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -116,6 +187,12 @@ __global__ __launch_bounds__(NTH) void k_trsv_bwd(const int* __restrict__ nt_arr
       yv[i * TILE + threadIdx.x] = x;
     }
     __syncthreads();
+    if (i > 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) li[k] = lin[k];
+#pragma unroll
+      for (int r = 0; r < CH; ++r) tt[r] = ttn[r];
+    }
   }
   for (int e = threadIdx.x; e < nt * TILE; e += NTH) Bb[int64_t(e) * ldb] = yv[e];
 }
