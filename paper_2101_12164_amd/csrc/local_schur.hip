@@ -524,16 +524,15 @@ void local_schur_form(Handle& h) {
     k_first_tiles<<<(nbs * ctiles + 255) / 256, 256, 0, st>>>(nbs, int(ldw), ctiles, first.p + int64_t(b0) * ldw,
                                                                ftile.p + int64_t(b0) * ctiles);
     NS_LAUNCH_CHECK();
-    // the sweep's algorithmic flops are added once all groups are queued (they need the first tiles)
-    tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p, ftile.p, 0.0, b0, b1, row0);  // W_j = L_j^{-1} B_j
+    // the formation's algorithmic flops are added once all groups are queued (they need the first rows)
+    tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p, ftile.p, 0.0, b0, b1, row0,
+                           KF_LS_FORM);  // W_j = L_j^{-1} B_j
     for (int j = b0; j < b1; ++j) hwo[j] = (lv.h_roff[j] - row0) * ldw;
     upload(woffg.p + b0, hwo.data() + b0, nbs * sizeof(int64_t), st);
     // B_j = W_j: offset woff[j] inside the group, common leading dimension ldw
     GemmBatch g{ftile.p + int64_t(b0) * ctiles, ctiles, ls.M.p + b0, ls.K.p + b0, woffg.p + b0, ls.wld.p + b0,
                 woffg.p + b0, 1, ldw, ls.soff.p + b0, 1, ls.sld.p + b0, 0};
-    double flg = 0;
-    for (int j = b0; j < b1; ++j) flg += 2.0 * Kv[j] * ls.h_m[j] * (ls.h_m[j] + 1) / 2;
-    KScope ks(KF_LS_FORM, st, double(rows) * ldw * 8.0, flg);
+    KScope ks(KF_LS_FORM, st, double(rows) * ldw * 8.0, 0.0);
     launch_gemm<double>(ls, W.p, W.p, ls.S64.p, 0, st, true, g, ls.max_m, nbs);
   }
   if (h.prec_inner) {
@@ -550,24 +549,31 @@ void local_schur_form(Handle& h) {
   NS_LAUNCH_CHECK();
   scan_inclusive(C.ptr.p + 1, nG, st);
   NS_HIP(hipMemcpyAsync(&C.nnz, C.ptr.p + nG, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  // algorithmic flops of the forward sweeps W_j = L_j^{-1} B_j: a column with first nonzero row r_c costs,
-  // over the rows below r_c, two flops per factor entry within the half-bandwidth bw_j, i.e.
-  // t(t-1) + 2 (rem - t) bw_j + rem with rem = n_b - r_c and t = min(rem, bw_j) (r_c approximated per
-  // 64-column tile by the tile's first row)
-  std::vector<int> hf(size_t(nb) * ctiles);
-  NS_HIP(hipMemcpyAsync(hf.data(), ftile.p, hf.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+  // Algorithmic flops of the formation, from the first nonzero row f_c of every column of B_j (exact per
+  // column): the forward sweep of a column costs, over the rem = n_b - f_c rows from f_c on, two flops per
+  // factor entry within the half-bandwidth bw_j plus the diagonal, t(t-1) + 2 (rem - t) bw_j + rem with
+  // t = min(rem, bw_j); the product W_j^T W_j forms the lower triangle, entry (a, b) over the rows from
+  // max(f_a, f_b) on, i.e. with f sorted ascending sum_k 2 k (n_b - f_(k)).
+  std::vector<int> hfc(size_t(nb) * ldw);
+  NS_HIP(hipMemcpyAsync(hfc.data(), first.p, hfc.size() * sizeof(int), hipMemcpyDeviceToHost, st));
   NS_HIP(hipStreamSynchronize(st));
   stream_idle(st);
   {
     double fl = 0.0;
-    for (int j = 0; j < nb; ++j)
-      for (int t = 0; t < ctiles; ++t) {
-        const int cols = std::max(0, std::min(64, ls.h_m[j] - 64 * t));
-        const double rem = std::max(0.0, double(lv.h_nb[j]) - 64.0 * std::min(hf[size_t(j) * ctiles + t], 1 << 20));
-        const double tb = std::min(rem, double(lv.h_bw[j]));
-        fl += (tb * (tb - 1.0) + 2.0 * (rem - tb) * lv.h_bw[j] + rem) * cols;
+    std::vector<int> fs;
+    for (int j = 0; j < nb; ++j) {
+      const int nbj = lv.h_nb[j], bw = lv.h_bw[j], m = ls.h_m[j];
+      fs.assign(hfc.begin() + size_t(j) * ldw, hfc.begin() + size_t(j) * ldw + m);
+      for (int& f : fs) f = std::min(f, nbj);
+      std::sort(fs.begin(), fs.end());
+      for (int k = 0; k < m; ++k) {
+        const double rem = double(nbj - fs[k]);
+        const double tb = std::min(rem, double(bw));
+        fl += tb * (tb - 1.0) + 2.0 * (rem - tb) * bw + rem;  // sweep of this column
+        fl += 2.0 * (k + 1) * rem;                           // its row of W_j^T W_j
       }
-    kscope_add_work(KF_TRSM_I64, 0.0, fl);
+    }
+    kscope_add_work(KF_LS_FORM, 0.0, fl);
   }
   C.col.alloc(C.nnz > 0 ? C.nnz : 1);
   C.val64.alloc(C.nnz > 0 ? C.nnz : 1);

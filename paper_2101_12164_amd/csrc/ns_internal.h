@@ -214,7 +214,7 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
 template <class T>
 void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st,
                     const int* ncols_blk = nullptr, const int* first_tile = nullptr, double alg_flops = -1.0,
-                    int b0 = 0, int b1 = -1, int64_t row0 = 0);
+                    int b0 = 0, int b1 = -1, int64_t row0 = 0, int family = -1);  // -1: by the level's role
 // Single right-hand side sweeps (FP64) with 16-wave workgroups; need LT64.
 bool trsv1_supported(const TileLevel& lv);
 bool trsv1_supported_size(const TileLevel& lv);  // the block size allows the single-column sweeps

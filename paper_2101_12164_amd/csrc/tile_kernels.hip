@@ -632,7 +632,8 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
 
 template <class T>
 void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st,
-                    const int* ncols_blk, const int* first_tile, double alg_flops, int b0, int b1, int64_t row0) {
+                    const int* ncols_blk, const int* first_tile, double alg_flops, int b0, int b1, int64_t row0,
+                    int family) {
   if (b1 < 0) b1 = lv.nblk;
   const int nblk = b1 - b0;
   if (nblk <= 0 || ncols == 0) return;
@@ -647,10 +648,21 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
   }
   if (cw != 16 && cw != 32) cw = 64;
   const int nbp8 = (nblk + 7) / 8;
-  const double bytes = (lv.alg_tri + 2.0 * lv.alg_rows * ncols) * sizeof(T);
-  const double flops = alg_flops >= 0 ? alg_flops : lv.alg_sq * ncols;
-  KScope ks(lv.role == 0 ? (sizeof(T) == 8 ? KF_TRSM_I64 : KF_TRSM_I32) : (sizeof(T) == 8 ? KF_TRSM_G64 : KF_TRSM_G32),
-            st, bytes, flops);
+  double tri = lv.alg_tri, rows = lv.alg_rows;
+  if (b0 != 0 || b1 != lv.nblk) {  // a range of the blocks: its band entries n (w + 1) - w (w + 1) / 2 and rows
+    tri = rows = 0;
+    for (int b = b0; b < b1; ++b) {
+      const double n = lv.h_nb[b], w = lv.h_bw[b];
+      tri += n * (w + 1) - w * (w + 1) / 2;
+      rows += n;
+    }
+  }
+  const double bytes = (tri + 2.0 * rows * ncols) * sizeof(T);
+  const double flops = alg_flops >= 0 ? alg_flops : (2.0 * tri - rows) * ncols;
+  const int fam = family >= 0 ? family
+                              : (lv.role == 0 ? (sizeof(T) == 8 ? KF_TRSM_I64 : KF_TRSM_I32)
+                                              : (sizeof(T) == 8 ? KF_TRSM_G64 : KF_TRSM_G32));
+  KScope ks(fam, st, bytes, flops);
   const int nchunk_all = (ncols + cw - 1) / cw;
   const int* nc = ncols_blk ? ncols_blk + b0 : nullptr;
   const int* ft = first_tile ? first_tile + int64_t(b0) * nchunk_all : nullptr;
@@ -689,7 +701,7 @@ void tile_solve_chunks(const TileLevel& lv, double* B, int64_t ldb, int ncols, c
 }
 
 template void tile_solve_fwd<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t, const int*, const int*,
-                                     double, int, int, int64_t);
+                                     double, int, int, int64_t, int);
 template void tile_solve<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t);
 template void tile_solve<float>(const TileLevel&, float*, int64_t, int, int, hipStream_t);
 
