@@ -140,11 +140,48 @@ struct GemmBatch {
   int64_t cscale;
   const int64_t* ldc;   // per block, or NULL: ldc_s
   int64_t ldc_s;
+  const int* perm = nullptr;  // optional [8][plen]: blocks whose tiles run on each XCD (-1: none)
+  int plen = 0;
 };
+
+// Blocks dealt to the 8 XCDs so that their work is balanced (largest first, each to the least loaded XCD):
+// [8][plen] block lists padded with -1.
+std::vector<int> xcd_lists(const std::vector<double>& work, int& plen) {
+  const int n = int(work.size());
+  std::vector<int> order(n);
+  for (int j = 0; j < n; ++j) order[j] = j;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  std::vector<std::vector<int>> lists(8);
+  double load[8] = {};
+  for (int j : order) {
+    int x = 0;
+    for (int y = 1; y < 8; ++y)
+      if (load[y] < load[x]) x = y;
+    lists[x].push_back(j);
+    load[x] += work[j];
+  }
+  plen = 0;
+  for (auto& l : lists) plen = std::max(plen, int(l.size()));
+  std::vector<int> flat(size_t(8) * std::max(plen, 1), -1);
+  for (int x = 0; x < 8; ++x)
+    for (size_t k = 0; k < lists[x].size(); ++k) flat[size_t(x) * plen + k] = lists[x][k];
+  return flat;
+}
+
+// One-dimensional launch of nb blocks x (gx x gy) output tiles.  Workgroup ids are dispatched round-robin
+// over the 8 XCDs; with 8 or more blocks, the ids of all tiles of a block are taken on one XCD (slot s of XCD
+// x: list entry s / tiles of x, tile s % tiles, row-major over (tm, tn)), so the tiles that share operand
+// columns share that XCD's L2.  The lists come from perm (work-balanced) or are x, x + 8, ...  With fewer
+// blocks the tiles of a block are spread over every XCD.
+inline unsigned gemm_grid(int gx, int gy, int nb, int plen = 0) {
+  const unsigned tiles = unsigned(gx) * unsigned(gy);
+  if (nb < 8) return unsigned(nb) * tiles;
+  return unsigned(8 * (plen > 0 ? plen : (nb + 7) / 8)) * tiles;
+}
 
 template <class T, int NC>
 __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restrict__ A, const T* __restrict__ B,
-                                                 T* __restrict__ C, int N, int sym) {
+                                                 T* __restrict__ C, int N, int sym, int gx, int gy, int nb) {
   using acc_t = typename MFL<T>::acc_t;
   constexpr int KC = 32;
   constexpr int AP = 64 + 1, BP = NC + 1;
@@ -155,9 +192,19 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restric
   constexpr int MC = NC == 64 ? 2 : NC / 16;    // MFMA column tiles per wave
   __shared__ T sA[KC * AP];
   __shared__ T sB[KC * BP];
-  const int j = blockIdx.z;
+  const int tiles = gx * gy;
+  int j, t;
+  if (nb < 8) {
+    j = int(blockIdx.x) / tiles;
+    t = int(blockIdx.x) % tiles;
+  } else {
+    const int slot = int(blockIdx.x >> 3), x = int(blockIdx.x & 7), lb = slot / tiles;
+    t = slot % tiles;
+    j = g.perm ? (lb < g.plen ? g.perm[x * g.plen + lb] : -1) : x + 8 * lb;
+  }
+  if (j < 0 || j >= nb) return;
+  const int tm = t / gx, tn = t % gx;
   const int M = g.M[j], K = g.K[j];
-  const int tm = blockIdx.y, tn = blockIdx.x;
   const int m0 = tm * 64, n0 = tn * NC;
   if (m0 >= M || n0 >= (sym ? M : N)) return;
   if (sym && tn * NC > tm * 64 + 63) return;  // strictly above the diagonal
@@ -322,15 +369,13 @@ void launch_gemm(const LocalSchur& ls, const T* A, const T* B, T* C, int N, hipS
   if (nblk == 0) return;
   const int tilesM = (maxM + 63) / 64;
   if (N <= 16 && !sym) {
-    dim3 grid(1, tilesM, nblk);
-    k_gemm_tn<T, 16><<<grid, 256, 0, st>>>(g, A, B, C, N, 0);
+    k_gemm_tn<T, 16><<<gemm_grid(1, tilesM, nblk, g.plen), 256, 0, st>>>(g, A, B, C, N, 0, 1, tilesM, nblk);
   } else if (N > 64 && N <= 80 && !sym) {
-    dim3 grid(1, tilesM, nblk);
-    k_gemm_tn<T, 80><<<grid, 256, 0, st>>>(g, A, B, C, N, 0);
+    k_gemm_tn<T, 80><<<gemm_grid(1, tilesM, nblk, g.plen), 256, 0, st>>>(g, A, B, C, N, 0, 1, tilesM, nblk);
   } else {
     const int tilesN = sym ? tilesM : (N + 63) / 64;
-    dim3 grid(tilesN, tilesM, nblk);
-    k_gemm_tn<T, 64><<<grid, 256, 0, st>>>(g, A, B, C, N, sym ? 1 : 0);
+    k_gemm_tn<T, 64><<<gemm_grid(tilesN, tilesM, nblk, g.plen), 256, 0, st>>>(g, A, B, C, N, sym ? 1 : 0, tilesN,
+                                                                               tilesM, nblk);
   }
   NS_LAUNCH_CHECK();
 }
@@ -359,14 +404,13 @@ void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStr
   KScope ks(sizeof(T) == 8 ? KF_INV64 : KF_INV32, st, (sq + 2.0 * lv.alg_rows * ncols) * sizeof(T), 2.0 * sq * ncols);
   const int tilesM = lv.max_nt;
   if (ncols <= 16) {
-    dim3 grid(1, tilesM, lv.nblk);
-    k_gemm_tn<T, 16><<<grid, 256, 0, st>>>(g, A, B, C, ncols, 0);
+    k_gemm_tn<T, 16><<<gemm_grid(1, tilesM, lv.nblk), 256, 0, st>>>(g, A, B, C, ncols, 0, 1, tilesM, lv.nblk);
   } else if (ncols > 64 && ncols <= 80) {
-    dim3 grid(1, tilesM, lv.nblk);
-    k_gemm_tn<T, 80><<<grid, 256, 0, st>>>(g, A, B, C, ncols, 0);
+    k_gemm_tn<T, 80><<<gemm_grid(1, tilesM, lv.nblk), 256, 0, st>>>(g, A, B, C, ncols, 0, 1, tilesM, lv.nblk);
   } else {
-    dim3 grid((ncols + 63) / 64, tilesM, lv.nblk);
-    k_gemm_tn<T, 64><<<grid, 256, 0, st>>>(g, A, B, C, ncols, 0);
+    const int tilesN = (ncols + 63) / 64;
+    k_gemm_tn<T, 64><<<gemm_grid(tilesN, tilesM, lv.nblk), 256, 0, st>>>(g, A, B, C, ncols, 0, tilesN, tilesM,
+                                                                          lv.nblk);
   }
   NS_LAUNCH_CHECK();
 }
@@ -380,8 +424,8 @@ void tri_gram(const TileLevel& lv, const double* Y, double* C, int64_t ld, const
   double sq = 0;
   for (int b = 0; b < lv.nblk; ++b) sq += double(lv.h_nt[b]) * TILE * lv.h_nt[b] * TILE;
   KScope ks(KF_INV64, st, 2.0 * sq * sizeof(double), alg_flops);
-  dim3 grid(lv.max_nt, lv.max_nt, lv.nblk);
-  k_gemm_tn<double, 64><<<grid, 256, 0, st>>>(g, Y, Y, C, 0, 1);
+  k_gemm_tn<double, 64><<<gemm_grid(lv.max_nt, lv.max_nt, lv.nblk), 256, 0, st>>>(g, Y, Y, C, 0, 1, lv.max_nt,
+                                                                                   lv.max_nt, lv.nblk);
   NS_LAUNCH_CHECK();
 }
 
@@ -451,6 +495,14 @@ void local_schur_plan(Handle& h) {
   }
   ls.npos = gp;
   ls.s_elems = sp;
+  {
+    // applies S_j^T X: blocks dealt to the XCDs by their work m_j^2
+    std::vector<double> wk(nb);
+    for (int j = 0; j < nb; ++j) wk[j] = double(ls.h_m[j]) * ls.h_m[j];
+    const std::vector<int> lists = xcd_lists(wk, ls.xplen);
+    ls.xperm.alloc(lists.size());
+    upload(ls.xperm.p, lists.data(), lists.size() * sizeof(int), st);
+  }
   const int64_t ldw = std::max(ls.max_m, 1);
   pl.ldw = ldw;
   for (int j = 0; j < nb; ++j) wld[j] = ldw;
@@ -512,6 +564,7 @@ void local_schur_form(Handle& h) {
   W.alloc(wmax > 0 ? wmax : 1);
   DBuf<int64_t> woffg;
   woffg.alloc(nb);
+  DBuf<int> gperm;
   std::vector<int64_t> hwo(nb);
   for (const auto& gr : groups) {
     const int b0 = gr.first, b1 = gr.second, nbs = b1 - b0;
@@ -532,6 +585,15 @@ void local_schur_form(Handle& h) {
     // B_j = W_j: offset woff[j] inside the group, common leading dimension ldw
     GemmBatch g{ftile.p + int64_t(b0) * ctiles, ctiles, ls.M.p + b0, ls.K.p + b0, woffg.p + b0, ls.wld.p + b0,
                 woffg.p + b0, 1, ldw, ls.soff.p + b0, 1, ls.sld.p + b0, 0};
+    // blocks of the group dealt to the XCDs by their work (m_j^2 K_j)
+    std::vector<double> wk(nbs);
+    for (int j = b0; j < b1; ++j) wk[j - b0] = double(ls.h_m[j]) * ls.h_m[j] * Kv[j];
+    int plen = 0;
+    const std::vector<int> lists = xcd_lists(wk, plen);
+    gperm.alloc(lists.size());
+    upload(gperm.p, lists.data(), lists.size() * sizeof(int), st);
+    g.perm = gperm.p;
+    g.plen = plen;
     KScope ks(KF_LS_FORM, st, double(rows) * ldw * 8.0, 0.0);
     launch_gemm<double>(ls, W.p, W.p, ls.S64.p, 0, st, true, g, ls.max_m, nbs);
   }
@@ -638,7 +700,8 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
     sym_gemv(ls.sym, reinterpret_cast<const double*>(Xg), reinterpret_cast<double*>(Yg), st);
   } else {
     // X_j / Y_j: stacked rows goff[j], leading dimension ncols
-    GemmBatch g{nullptr, 0, ls.M, ls.Kg, ls.soff, ls.sld, ls.goff, ncols, ncols, ls.goff, ncols, nullptr, ncols};
+    GemmBatch g{nullptr, 0, ls.M, ls.Kg, ls.soff, ls.sld, ls.goff, ncols, ncols, ls.goff, ncols, nullptr, ncols,
+                ls.xperm.p, ls.xplen};
     KScope ks(sizeof(T) == 8 ? KF_LS_APPLY64 : KF_LS_APPLY32, st,
               ls.alg_bytes * sizeof(T) + 2.0 * np * ncols * sizeof(T), ls.alg_flops * ncols);
     launch_gemm<T>(ls, S, Xg, Yg, ncols, st, false, g, ls.max_m);

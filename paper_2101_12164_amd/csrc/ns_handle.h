@@ -35,6 +35,8 @@ struct LocalSchur {
   int64_t ws_cols = 0;
   double alg_bytes = 0, alg_flops = 0;  // per apply and column: sum m_j^2 entries, 2 sum m_j^2 flops
   SymPacked sym;                         // S_j packed for single-column FP64 applies
+  DBuf<int> xperm;                       // [8][xplen] blocks of each XCD in the batched applies
+  int xplen = 0;
 };
 
 }  // namespace ns
