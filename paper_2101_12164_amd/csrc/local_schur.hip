@@ -38,14 +38,64 @@ struct MFL<float> {
 
 // Mark the interface columns touched by each block: flag[j * ldf + g - gbase_j] = 1, where block j's
 // interface columns lie in [gbase_j, gbase_j + ldf) (its problem's interface rows).
-__global__ void k_mark(int64_t nrows, const int32_t* __restrict__ rblk, const int64_t* __restrict__ ptr,
-                       const int32_t* __restrict__ col, const int64_t* __restrict__ gbase, int64_t ldf,
-                       int* __restrict__ flag) {
+// frow[j ldf + g] = first block-local row of block j coupled to interface node gbase_j + g (NO_ROW: none)
+constexpr int NO_ROW = 0x7F7F7F7F;
+__global__ void k_mark(int64_t nrows, const int32_t* __restrict__ rblk, const int64_t* __restrict__ roff,
+                       const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                       const int64_t* __restrict__ gbase, int64_t ldf, int* __restrict__ frow) {
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   const int j = rblk[r];
   if (j < 0) return;
-  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) flag[int64_t(j) * ldf + (col[e] - gbase[j])] = 1;
+  const int lr = int(r - roff[j]);
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) atomicMin(&frow[int64_t(j) * ldf + (col[e] - gbase[j])], lr);
+}
+
+// One workgroup per block: its interface list ordered by the first coupled row (ties by node), cidx
+// rewritten to the new positions.  Column c of W_j = L_j^{-1} A_{I_j Gamma_j} is zero above that row, so in
+// this order every 64-column tile of W_j starts close to its columns' own first rows and the forward sweep
+// and W_j^T W_j skip the zero rows of whole tiles.  Lists longer than SORT_MAX keep the node order.
+constexpr int SORT_MAX = 4096;
+__global__ __launch_bounds__(1024) void k_sort_lists(const int* __restrict__ cnt, const int64_t* __restrict__ gbase,
+                                                     int64_t ldf, const int* __restrict__ frow,
+                                                     const int64_t* __restrict__ goff, int32_t* __restrict__ cidx,
+                                                     int32_t* __restrict__ glist) {
+  __shared__ unsigned long long key[SORT_MAX];
+  const int j = blockIdx.x;
+  const int m = cnt[j];
+  if (m > SORT_MAX || m < 2) return;
+  int P = 2;
+  while (P < m) P <<= 1;
+  const int64_t gb = gbase[j];
+  int32_t* gl = glist + goff[j];
+  for (int i = threadIdx.x; i < P; i += 1024) {
+    if (i < m) {
+      const uint32_t g = uint32_t(gl[i] - gb);
+      key[i] = (uint64_t(uint32_t(frow[int64_t(j) * ldf + g])) << 32) | g;
+    } else {
+      key[i] = ~0ull;
+    }
+  }
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1)  // bitonic sort, ascending
+    for (int h = k >> 1; h > 0; h >>= 1) {
+      for (int i = threadIdx.x; i < P; i += 1024) {
+        const int o = i ^ h;
+        if (o > i) {
+          const unsigned long long a = key[i], b = key[o];
+          if ((a > b) == ((i & k) == 0)) {
+            key[i] = b;
+            key[o] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  for (int i = threadIdx.x; i < m; i += 1024) {
+    const uint32_t g = uint32_t(key[i] & 0xFFFFFFFFu);
+    gl[i] = int32_t(gb + g);
+    cidx[int64_t(j) * ldf + g] = i;
+  }
 }
 
 __global__ void k_row_block(const int* __restrict__ nt, const int64_t* __restrict__ roff, int32_t* __restrict__ rblk) {
@@ -69,7 +119,7 @@ __global__ __launch_bounds__(1024) void k_compact(const int64_t* __restrict__ gc
   __syncthreads();
   for (int64_t g0 = 0; g0 < nG; g0 += 1024) {
     const int64_t g = g0 + threadIdx.x;
-    const int v = g < nG ? f[g] : 0;
+    const int v = g < nG ? (f[g] != NO_ROW ? 1 : 0) : 0;
     s[threadIdx.x] = v;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -469,8 +519,8 @@ void local_schur_plan(Handle& h) {
   flag.alloc(int64_t(nb) * ldf);
   cnt.alloc(nb);
   cidx.alloc(int64_t(nb) * ldf);
-  NS_HIP(hipMemsetAsync(flag.p, 0, int64_t(nb) * ldf * sizeof(int), st));
-  k_mark<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, h.AIG.ptr, h.AIG.col, gbase_d, ldf, flag);
+  NS_HIP(hipMemsetAsync(flag.p, 0x7F, int64_t(nb) * ldf * sizeof(int), st));  // NO_ROW
+  k_mark<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, lv.roff, h.AIG.ptr, h.AIG.col, gbase_d, ldf, flag);
   NS_LAUNCH_CHECK();
   k_compact<<<nb, 1024, 0, st>>>(gcnt_d, gbase_d, ldf, flag, cnt, nullptr, nullptr, nullptr, 0);
   NS_LAUNCH_CHECK();
@@ -511,6 +561,8 @@ void local_schur_plan(Handle& h) {
   ls.glist.alloc(gp > 0 ? gp : 1);
   NS_HIP(hipMemsetAsync(ls.glist.p, 0xFF, ls.glist.n * sizeof(int32_t), st));
   k_compact<<<nb, 1024, 0, st>>>(gcnt_d, gbase_d, ldf, flag, cnt, ls.goff, cidx, ls.glist, 1);
+  NS_LAUNCH_CHECK();
+  k_sort_lists<<<nb, 1024, 0, st>>>(cnt, gbase_d, ldf, flag, ls.goff, cidx, ls.glist);
   NS_LAUNCH_CHECK();
   // per-block metadata for the batched GEMMs
   auto up = [&](DBuf<int64_t>& d, const std::vector<int64_t>& v) {
