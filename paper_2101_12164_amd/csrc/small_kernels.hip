@@ -54,9 +54,8 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Cyclic Jacobi: A (n x n, row stride ld, symmetric) is diagonalised in place;
 // V (stride ld) receives the eigenvectors in its columns.  cs: 2n doubles,
 // pr: n+2 ints.  Each round applies the n/2 disjoint rotations J of a
-// round-robin ordering at once, as A <- A J and V <- V J (columns p, q of every
-// row), then A <- J^T A (rows p, q of every column); consecutive threads take
-// consecutive rows or columns, so LDS accesses do not collide.
+// round-robin ordering at once: A <- J^T A J block by block (2 x 2 blocks of
+// two rotation pairs) and V <- V J (columns p, q of every row).
 __device__ __forceinline__ void jacobi(double* A, double* V, int n, int ld, double* cs, int* pr, double* red) {
   const int tid = threadIdx.x;
   for (int e = tid; e < n * n; e += NT) {
@@ -115,27 +114,33 @@ __device__ __forceinline__ void jacobi(double* A, double* V, int n, int ld, doub
         cs[2 * tid + 1] = s;
       }
       __syncthreads();
-      for (int t = tid; t < n * half; t += NT) {  // A <- A J, V <- V J
+      // A <- J^T A J, one thread per 2 x 2 block (rows of pair P, columns of pair Q): the columns are
+      // rotated first, then the rows, with the arithmetic of the two separate passes, but with no barrier
+      // between them since the blocks are disjoint
+      for (int t = tid; t < half * half; t += NT) {
+        const int P = t / half, Q = t - P * half;
+        const int p = pr[2 * P], q = pr[2 * P + 1], p2 = pr[2 * Q], q2 = pr[2 * Q + 1];
+        const bool hq = q < n, hq2 = q2 < n;  // q == n: the dummy partner of an odd n
+        const double c1 = cs[2 * P], s1 = cs[2 * P + 1], c2 = cs[2 * Q], s2 = cs[2 * Q + 1];
+        const double a = A[p * ld + p2], b = hq2 ? A[p * ld + q2] : 0.0;
+        const double c = hq ? A[q * ld + p2] : 0.0, d = (hq && hq2) ? A[q * ld + q2] : 0.0;
+        const double a1 = c2 * a - s2 * b, b1 = s2 * a + c2 * b;
+        const double c3 = c2 * c - s2 * d, d1 = s2 * c + c2 * d;
+        A[p * ld + p2] = c1 * a1 - s1 * c3;
+        if (hq2) A[p * ld + q2] = c1 * b1 - s1 * d1;
+        if (hq) {
+          A[q * ld + p2] = s1 * a1 + c1 * c3;
+          if (hq2) A[q * ld + q2] = s1 * b1 + c1 * d1;
+        }
+      }
+      for (int t = tid; t < n * half; t += NT) {  // V <- V J
         const int P = t / n, i = t - P * n;
         const int p = pr[2 * P], q = pr[2 * P + 1];
         if (q >= n) continue;
         const double c = cs[2 * P], s = cs[2 * P + 1];
-        const double ap = A[i * ld + p], aq = A[i * ld + q];
-        A[i * ld + p] = c * ap - s * aq;
-        A[i * ld + q] = s * ap + c * aq;
         const double vp = V[i * ld + p], vq = V[i * ld + q];
         V[i * ld + p] = c * vp - s * vq;
         V[i * ld + q] = s * vp + c * vq;
-      }
-      __syncthreads();
-      for (int t = tid; t < n * half; t += NT) {  // A <- J^T A
-        const int P = t / n, j = t - P * n;
-        const int p = pr[2 * P], q = pr[2 * P + 1];
-        if (q >= n) continue;
-        const double c = cs[2 * P], s = cs[2 * P + 1];
-        const double ap = A[p * ld + j], aq = A[q * ld + j];
-        A[p * ld + j] = c * ap - s * aq;
-        A[q * ld + j] = s * ap + c * aq;
       }
       __syncthreads();
     }
