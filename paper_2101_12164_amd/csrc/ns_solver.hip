@@ -446,8 +446,7 @@ void apply_prec(Handle& h, const double* r, int64_t ldr, double* z, int64_t ldz,
   op_gamma_solve<double>(h, r, ldr, z, ldz, ncols);  // t = A_Gamma^{-1} r
   if (h.k_eff == 0) return;
   if (h.apply_mode == NS_APPLY_M2) {
-    gram<double, double>(sg, h.Z.p, k, k, r, ldr, ncols, c1, cs, 1.0, 0.0, work, st);  // Z^T r
-    small_rowscale(np, k, ncols, h.Sigma.p, k, c1, ncols, cs, st);
+    gram<double, double>(sg, h.Z.p, k, k, r, ldr, ncols, c1, cs, 1.0, 0.0, work, st, h.Sigma.p, k);  // Sigma Z^T r
     ts_update<double>(sg, ncols, z, ldz, 1.0, 1.0, h.Z.p, k, k, c1, ncols, cs, nullptr, 0, 0, nullptr, 0, 0, st);
   } else {
     gram<double, double>(sg, h.Z.p, k, k, r, ldr, ncols, c1, cs, 1.0, 0.0, work, st);    // Z^T r
@@ -495,7 +494,7 @@ void pcg_core(Handle& h, const double* b, double* x, double rtol, int maxit, std
   DBuf<int> ist;
   bI.alloc(nIp);
   for (DBuf<double>* v : {&f, &w, &r, &z, &p, &q}) v->alloc(nG);
-  work.alloc(std::max<size_t>(gram_work_elems(sg, k), size_t(sg.nchunk) + 16));
+  work.alloc(std::max<size_t>(gram_work_elems(sg, k), 2 * size_t(sg.nchunk) + 32));
   c1.alloc(size_t(k) * np);
   c2.alloc(size_t(k) * np);
   tmp.alloc(std::max(n, nIp));  // gathers of the padded interior rows (n_I padded can exceed n)
@@ -534,15 +533,16 @@ void pcg_core(Handle& h, const double* b, double* x, double rtol, int maxit, std
   read_back(h, hc, S.ndone, 2);
   // One PCG iteration for every problem; the iteration index lives on the device, so the same launches
   // (recorded once into a graph) serve every iteration.
+  double* dpart = work.p + sg.nchunk + 16;  // chunk partials of p^T q and r^T z (work itself takes ||r||^2)
   auto head = [&](hipStream_t s) {
-    op_schur<double>(h, p.p, 1, q.p, 1, 1, false);  // q = S p
-    dot(sg, p.p, q.p, psd.p + PS_PQ, PS, work, s);  // p^T q
-    pcg_update_wr(sg, S, w.p, r.p, p.p, q.p, work, s);  // w, r, ||r||, stopping test
+    op_schur<double>(h, p.p, 1, q.p, 1, 1, false);            // q = S p
+    dot_partials(sg, p.p, q.p, dpart, s);                       // p^T q per chunk
+    pcg_update_wr(sg, S, w.p, r.p, p.p, q.p, dpart, work, s);  // alpha, w, r, ||r||, stopping test
   };
   auto tail = [&](hipStream_t s) {
-    apply_prec(h, r.p, 1, z.p, 1, 1, work, c1, c2, h.sws);        // z = M r
-    dot(sg, r.p, z.p, psd.p + PS_RHO_NEW, PS, work, s);  // rho_{j+1}
-    pcg_update_p(sg, S, z.p, p.p, s);
+    apply_prec(h, r.p, 1, z.p, 1, 1, work, c1, c2, h.sws);  // z = M r
+    dot_partials(sg, r.p, z.p, dpart, s);                    // r^T z per chunk
+    pcg_update_p(sg, S, z.p, p.p, dpart, s);                 // rho_{j+1}, p = z + beta p
     pcg_advance(np, S, s);
   };
   if (hc[0] < np && maxit > 0) {

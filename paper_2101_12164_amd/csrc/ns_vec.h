@@ -35,9 +35,11 @@ int seg_chunks(int64_t rows);
 
 // G_p (ra x rb, row-major, at G + p * gstride) = alpha * A_p^T B_p + beta * G_p for every segment p.
 // work: at least gram_work_elems(seg, max(ra, rb)) doubles.
+// With rscale, output row a of problem p is further scaled by rscale[p * rsstride + a].
 template <class TA, class TB>
 void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t ldb, int rb, double* G,
-          int64_t gstride, double alpha, double beta, double* work, hipStream_t st);
+          int64_t gstride, double alpha, double beta, double* work, hipStream_t st, const double* rscale = nullptr,
+          int64_t rsstride = 0);
 size_t gram_work_elems(const Seg& sg, int maxw);
 
 // Out_p = beta * Out_p + gamma * (X_p M_p + X2_p M2_p) on the rows of every segment p;
@@ -80,12 +82,16 @@ struct PcgState {
   double rtol;
   int maxit;
 };
-// w += alpha_p p, r -= alpha_p q for problems not done (alpha_p = rho_j / (p^T q)_p), then
-// ||r||^2 per problem, the stopping test, it and hist.
+// part[c] = x^T y over the rows of reduction chunk c (one value per chunk of every segment)
+void dot_partials(const Seg& sg, const double* x, const double* y, double* part, hipStream_t st);
+// w += alpha_p p, r -= alpha_p q for problems not done (alpha_p = rho_j / (p^T q)_p, (p^T q)_p summed from the
+// chunk partials pq_part of dot_partials), then ||r||^2 per problem (chunk partials in work), the stopping test,
+// it and hist.
 void pcg_update_wr(const Seg& sg, const PcgState& s, double* w, double* r, const double* p, const double* q,
-                   double* work, hipStream_t st);
-// p = z + beta_p p with beta_p = rho_{j+1} / rho_j.
-void pcg_update_p(const Seg& sg, const PcgState& s, const double* z, double* p, hipStream_t st);
+                   const double* pq_part, double* work, hipStream_t st);
+// p = z + beta_p p with beta_p = rho_{j+1} / rho_j, rho_{j+1} = (r^T z)_p summed from the chunk partials rz_part.
+void pcg_update_p(const Seg& sg, const PcgState& s, const double* z, double* p, const double* rz_part,
+                  hipStream_t st);
 // rho_j <- rho_{j+1} for every problem; j <- j + 1.
 void pcg_advance(int nseg, const PcgState& s, hipStream_t st);
 // hist[., 0] and done for the initial residual: rel = sqrt(rn2) / nf; j <- 0.
@@ -137,9 +143,6 @@ void small_cholqr(Batch bt, int s, const double* G, int64_t sG, const double* sh
 // (A Cholesky of C that certifies every eigenvalue above the threshold replaces the first EVD.)
 void small_nystrom(int nb, int s, int k, const double* C, const double* R, double eps_rel, double* Wk, double* Ek,
                    int* out, const SmallWs& ws, hipStream_t st);
-// c_b[i, j] *= sigma_b[i] for i < k, j < ncols (ld ldc; c_b = c + b * sc, sigma_b = sigma + b * ssig)
-void small_rowscale(int nb, int k, int ncols, const double* sigma, int64_t ssig, double* c, int64_t ldc, int64_t sc,
-                    hipStream_t st);
 // Symmetric EVD (descending) of an m x m matrix: W (m x m) eigenvectors in columns, E eigenvalues.
 void small_sym_evd(int m, const double* A, double* W, double* E, const SmallWs& ws, hipStream_t st);
 // Generalised symmetric EVD A c = lambda B c (B SPD), ascending: lam (k), C (k x k, C^T B C = I),

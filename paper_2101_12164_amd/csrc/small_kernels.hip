@@ -810,14 +810,6 @@ __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double
   }
 }
 
-__global__ void k_small_rowscale(int k, int ncols, const double* sigma, int64_t ssig, double* c, int64_t ldc,
-                                 int64_t sc) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int b = blockIdx.y;
-  if (idx >= k * ncols) return;
-  const int i = idx / ncols, j = idx % ncols;
-  c[b * sc + i * ldc + j] *= sigma[b * ssig + i];
-}
 
 template <int kLds>
 __global__ __launch_bounds__(NT) void k_small_sym_evd(int m, const double* Ain, double* W, double* E, double* gw) {
@@ -994,12 +986,6 @@ void small_nystrom(int nb, int s, int k, const double* C, const double* R, doubl
   NS_LAUNCH_CHECK();
 }
 
-void small_rowscale(int nb, int k, int ncols, const double* sigma, int64_t ssig, double* c, int64_t ldc, int64_t sc,
-                    hipStream_t st) {
-  if (k * ncols == 0 || nb == 0) return;
-  k_small_rowscale<<<dim3((k * ncols + 255) / 256, nb), 256, 0, st>>>(k, ncols, sigma, ssig, c, ldc, sc);
-  NS_LAUNCH_CHECK();
-}
 
 void small_gevd(int k, const double* A, const double* B, double* lam, double* C, double* Cl, int* flag, double* ws,
                 const SmallWs& sw, hipStream_t st) {

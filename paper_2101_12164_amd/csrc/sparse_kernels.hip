@@ -80,6 +80,26 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t nrows, const int32_t* _
   for (int c = lane; c < ncols; c += TPR) Out[int64_t(d) * ldo + c] = U(B[row * ldb + c]);
 }
 
+// Two scatters in one launch: rows [0, n1) of B1 through dst1, then rows [0, n2) of B2 through dst2
+template <class T, int TPR>
+__global__ __launch_bounds__(256) void k_scatter2(int64_t n1, const int32_t* __restrict__ dst1, const T* __restrict__ B1,
+                                                  int64_t n2, const int32_t* __restrict__ dst2, const T* __restrict__ B2,
+                                                  int64_t ldb, T* __restrict__ Out, int64_t ldo, int ncols) {
+  int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
+  const int lane = threadIdx.x % TPR;
+  const int32_t* dst = dst1;
+  const T* B = B1;
+  if (row >= n1) {
+    row -= n1;
+    if (row >= n2) return;
+    dst = dst2;
+    B = B2;
+  }
+  const int d = dst[row];
+  if (d < 0) return;
+  for (int c = lane; c < ncols; c += TPR) Out[int64_t(d) * ldo + c] = B[row * ldb + c];
+}
+
 template <int TPR>
 inline int grid_rows(int64_t nrows) {
   return int((nrows * TPR + 255) / 256);
@@ -911,7 +931,12 @@ void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int
       gather_sub<T>(n2pad, h.l2src, R, ldr, &h.AsJ, xj, ncols, Bp, ncols, ncols, st);
       xs = solve(h.L2, Bp, Bq);
     }
-    scatter<T, T>(nJpad, h.jsrc, xj, ncols, Out, ldo, ncols, st);
+    // both levels' results back into the interface rows in one launch
+    const int64_t n2 = n2pad ? n2pad : 0;
+    NS_TPR_DISPATCH(ncols, (k_scatter2<T, TPR><<<grid_rows<TPR>(nJpad + n2), 256, 0, st>>>(
+                               nJpad, h.jsrc, xj, n2, h.l2src, xs, ncols, Out, ldo, ncols)));
+    NS_LAUNCH_CHECK();
+    return;
   }
   if (n2pad) scatter<T, T>(n2pad, h.l2src, xs, ncols, Out, ldo, ncols, st);
 }

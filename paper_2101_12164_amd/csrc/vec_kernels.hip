@@ -115,7 +115,8 @@ __global__ __launch_bounds__(256) void k_gram_strip(Seg sg, const TA* __restrict
 template <int TX>
 __global__ __launch_bounds__(1024) void k_seg_final(Seg sg, int nout, const double* __restrict__ part,
                                                     double* __restrict__ G, int64_t gstride, double alpha,
-                                                    double beta) {
+                                                    double beta, const double* __restrict__ rscale = nullptr,
+                                                    int64_t rsstride = 0, int rb = 1) {
   constexpr int TY = 1024 / TX;
   __shared__ double red[1024];
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
@@ -133,16 +134,19 @@ __global__ __launch_bounds__(1024) void k_seg_final(Seg sg, int nout, const doub
   }
   if (ty == 0 && o < nout) {
     double* g = G + int64_t(p) * gstride + o;
-    *g = alpha * red[tx] + (beta != 0.0 ? beta * *g : 0.0);
+    const double a = rscale ? alpha * rscale[int64_t(p) * rsstride + o / rb] : alpha;  // output row o / rb
+    *g = a * red[tx] + (beta != 0.0 ? beta * *g : 0.0);
   }
 }
 
 void seg_final(const Seg& sg, int nout, const double* part, double* G, int64_t gstride, double alpha, double beta,
-               hipStream_t st) {
+               hipStream_t st, const double* rscale = nullptr, int64_t rsstride = 0, int rb = 1) {
   if (nout >= 16) {
-    k_seg_final<64><<<dim3((nout + 63) / 64, sg.n), 1024, 0, st>>>(sg, nout, part, G, gstride, alpha, beta);
+    k_seg_final<64><<<dim3((nout + 63) / 64, sg.n), 1024, 0, st>>>(sg, nout, part, G, gstride, alpha, beta, rscale,
+                                                                  rsstride, rb);
   } else {
-    k_seg_final<1><<<dim3(nout, sg.n), 1024, 0, st>>>(sg, nout, part, G, gstride, alpha, beta);
+    k_seg_final<1><<<dim3(nout, sg.n), 1024, 0, st>>>(sg, nout, part, G, gstride, alpha, beta, rscale, rsstride,
+                                                     rb);
   }
   NS_LAUNCH_CHECK();
 }
@@ -250,6 +254,22 @@ __device__ __forceinline__ double block_sum256(double s, double* red) {
   return red[0];
 }
 
+// Sum over the 256 threads in a fixed order: butterfly within each wave, then the four wave sums.
+__device__ __forceinline__ double block_sum256_w(double s, double* red4) {
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = s;
+  __syncthreads();
+  return (red4[0] + red4[1]) + (red4[2] + red4[3]);
+}
+
+// Sum of problem g's chunk partials part[coff[g] ..] (the same value in every block that asks).
+__device__ __forceinline__ double seg_total(const Seg& sg, int g, const double* __restrict__ part, double* red4) {
+  const int c0 = sg.coff[g], nch = sg.coff[g + 1] - c0;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < nch; c += 256) s += part[c0 + c];
+  return block_sum256_w(s, red4);
+}
+
 __global__ __launch_bounds__(256) void k_dot_partial(Seg sg, const double* __restrict__ x,
                                                      const double* __restrict__ y, double* __restrict__ part) {
   __shared__ double red[256];
@@ -261,17 +281,21 @@ __global__ __launch_bounds__(256) void k_dot_partial(Seg sg, const double* __res
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// PCG: w += alpha p, r -= alpha q on the chunk's rows unless its problem is done; partial ||r||^2.
+// PCG: (p^T q)_g from the chunk partials pq_part of problem g (formed again by every block of g, in one fixed
+// order), then w += alpha p, r -= alpha q on the chunk's rows unless its problem is done; partial ||r||^2.
 __global__ __launch_bounds__(256) void k_pcg_wr(Seg sg, PcgState S, double* __restrict__ w, double* __restrict__ r,
                                                 const double* __restrict__ p, const double* __restrict__ q,
-                                                double* __restrict__ part) {
+                                                const double* __restrict__ pq_part, double* __restrict__ part) {
   __shared__ double red[256];
+  __shared__ double red4[4];
   int64_t r0, r1;
   const int g = chunk_rows(sg, blockIdx.x, r0, r1);
+  const double pq = seg_total(sg, g, pq_part, red4);
   double s = 0.0;
   if (!S.done[g] && *S.j < S.maxit) {
-    const double* ps = S.ps + int64_t(g) * PS;
-    const double alpha = ps[PS_RHO] / ps[PS_PQ];
+    double* ps = S.ps + int64_t(g) * PS;
+    if (threadIdx.x == 0 && blockIdx.x == sg.coff[g]) ps[PS_PQ] = pq;
+    const double alpha = ps[PS_RHO] / pq;
     for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) {
       w[i] += alpha * p[i];
       const double ri = r[i] - alpha * q[i];
@@ -328,13 +352,18 @@ __global__ void k_pcg_init(int nseg, PcgState S) {
   }
 }
 
-// p = z + (rho_{j+1} / rho_j) p, per problem
-__global__ void k_pcg_p(Seg sg, PcgState S, const double* __restrict__ z, double* __restrict__ p) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= sg.rows) return;
-  const double* ps = S.ps + int64_t(sg.rseg[i]) * PS;
-  const double beta = ps[PS_RHO_NEW] / ps[PS_RHO];
-  p[i] = z[i] + beta * p[i];
+// rho_{j+1} = (r^T z)_g from the chunk partials (formed again by every block of g), then
+// p = z + (rho_{j+1} / rho_j) p on the chunk's rows; the problem's first block stores rho_{j+1}.
+__global__ __launch_bounds__(256) void k_pcg_p(Seg sg, PcgState S, const double* __restrict__ z, double* __restrict__ p,
+                                               const double* __restrict__ rz_part) {
+  __shared__ double red4[4];
+  int64_t r0, r1;
+  const int g = chunk_rows(sg, blockIdx.x, r0, r1);
+  const double rho_new = seg_total(sg, g, rz_part, red4);
+  double* ps = S.ps + int64_t(g) * PS;
+  const double beta = rho_new / ps[PS_RHO];
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) p[i] = z[i] + beta * p[i];
+  if (threadIdx.x == 0 && blockIdx.x == sg.coff[g]) ps[PS_RHO_NEW] = rho_new;
 }
 
 // one workgroup: rho_j <- rho_{j+1} for every problem, then j <- j + 1
@@ -428,7 +457,8 @@ void SegBuf::build(const std::vector<int64_t>& offsets, hipStream_t st) {
 
 template <class TA, class TB>
 void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t ldb, int rb, double* G,
-          int64_t gstride, double alpha, double beta, double* work, hipStream_t st) {
+          int64_t gstride, double alpha, double beta, double* work, hipStream_t st, const double* rscale,
+          int64_t rsstride) {
   const int nout = ra * rb;
   if (nout == 0 || sg.n == 0) return;
   const int ta = (ra + 15) / 16, tbt = (rb + 15) / 16;
@@ -437,7 +467,7 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
   const int sym = (static_cast<const void*>(A) == static_cast<const void*>(B) && lda == ldb && ra == rb) ? 1 : 0;
   k_gram_strip<TA, TB><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym);
   NS_LAUNCH_CHECK();
-  seg_final(sg, nout, work, G, gstride, alpha, beta, st);
+  seg_final(sg, nout, work, G, gstride, alpha, beta, st, rscale, rsstride, rb);
 }
 
 size_t gram_work_elems(const Seg& sg, int maxw) { return size_t(std::max(sg.nchunk, 1)) * maxw * maxw; }
@@ -475,16 +505,23 @@ void dot(const Seg& sg, const double* x, const double* y, double* out, int64_t o
   seg_final(sg, 1, work, out, ostride, 1.0, 0.0, st);
 }
 
+void dot_partials(const Seg& sg, const double* x, const double* y, double* part, hipStream_t st) {
+  if (sg.n == 0) return;
+  k_dot_partial<<<sg.nchunk, 256, 0, st>>>(sg, x, y, part);
+  NS_LAUNCH_CHECK();
+}
+
 void pcg_update_wr(const Seg& sg, const PcgState& s, double* w, double* r, const double* p, const double* q,
-                   double* work, hipStream_t st) {
-  k_pcg_wr<<<sg.nchunk, 256, 0, st>>>(sg, s, w, r, p, q, work);
+                   const double* pq_part, double* work, hipStream_t st) {
+  k_pcg_wr<<<sg.nchunk, 256, 0, st>>>(sg, s, w, r, p, q, pq_part, work);
   NS_LAUNCH_CHECK();
   k_pcg_check<<<sg.n, 256, 0, st>>>(sg, s, work);
   NS_LAUNCH_CHECK();
 }
 
-void pcg_update_p(const Seg& sg, const PcgState& s, const double* z, double* p, hipStream_t st) {
-  k_pcg_p<<<unsigned((sg.rows + 255) / 256), 256, 0, st>>>(sg, s, z, p);
+void pcg_update_p(const Seg& sg, const PcgState& s, const double* z, double* p, const double* rz_part,
+                  hipStream_t st) {
+  k_pcg_p<<<sg.nchunk, 256, 0, st>>>(sg, s, z, p, rz_part);
   NS_LAUNCH_CHECK();
 }
 
@@ -505,9 +542,9 @@ void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_
 }
 
 template void gram<double, double>(const Seg&, const double*, int64_t, int, const double*, int64_t, int, double*,
-                                   int64_t, double, double, double*, hipStream_t);
+                                   int64_t, double, double, double*, hipStream_t, const double*, int64_t);
 template void gram<float, float>(const Seg&, const float*, int64_t, int, const float*, int64_t, int, double*,
-                                 int64_t, double, double, double*, hipStream_t);
+                                 int64_t, double, double, double*, hipStream_t, const double*, int64_t);
 template void ts_update<double>(const Seg&, int, double*, int64_t, double, double, const double*, int64_t, int,
                                 const double*, int64_t, int64_t, const double*, int64_t, int, const double*, int64_t,
                                 int64_t, hipStream_t);
