@@ -433,7 +433,7 @@ void launch_gemm(const LocalSchur& ls, const T* A, const T* B, T* C, int N, hipS
 }  // namespace
 
 template <class T>
-void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStream_t st) {
+void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStream_t st, const int32_t* bidx) {
   if (lv.nblk == 0 || ncols == 0) return;
   const T* A;
   if constexpr (sizeof(T) == 8)
@@ -445,7 +445,7 @@ void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStr
   if constexpr (sizeof(T) == 8) {
     if (ncols == 1 && lv.inv_sym.built()) {  // packed symmetric tiles: every stored entry read once
       KScope ks(KF_INV64, st, lv.inv_sym.alg_bytes + 2.0 * lv.alg_rows * sizeof(T), lv.inv_sym.alg_flops);
-      sym_gemv(lv.inv_sym, B, C, st);
+      sym_gemv(lv.inv_sym, B, C, st, bidx);
       return;
     }
   }
@@ -479,8 +479,8 @@ void tri_gram(const TileLevel& lv, const double* Y, double* C, int64_t ld, const
   NS_LAUNCH_CHECK();
 }
 
-template void tile_apply_inverse<double>(const TileLevel&, const double*, double*, int, hipStream_t);
-template void tile_apply_inverse<float>(const TileLevel&, const float*, float*, int, hipStream_t);
+template void tile_apply_inverse<double>(const TileLevel&, const double*, double*, int, hipStream_t, const int32_t*);
+template void tile_apply_inverse<float>(const TileLevel&, const float*, float*, int, hipStream_t, const int32_t*);
 
 void local_schur_plan(Handle& h) {
   hipStream_t st = h.stream;
@@ -743,14 +743,14 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
       BODY;                             \
     }                                   \
   } while (0)
-  NS_TPR_DISPATCH_LS(ncols, (k_gather_ls<T, TPR><<<unsigned((np * TPR + 255) / 256), 256, 0, st>>>(
-                                 np, ls.glist, X, ldx, Xg, ncols, ncols)));
-  NS_LAUNCH_CHECK();
-  if (sizeof(T) == 8 && ncols == 1 && ls.sym.built()) {
-    // one column: the packed symmetric tiles (every stored entry of S_j read once)
+  if (sizeof(T) == 8 && ncols == 1 && ldx == 1 && ls.sym.built()) {
+    // one column: the packed symmetric tiles (every stored entry of S_j read once), x gathered through glist
     KScope ks(KF_LS_APPLY64, st, ls.sym.alg_bytes + 2.0 * np * sizeof(T), ls.sym.alg_flops);
-    sym_gemv(ls.sym, reinterpret_cast<const double*>(Xg), reinterpret_cast<double*>(Yg), st);
+    sym_gemv(ls.sym, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(Yg), st, ls.glist.p);
   } else {
+    NS_TPR_DISPATCH_LS(ncols, (k_gather_ls<T, TPR><<<unsigned((np * TPR + 255) / 256), 256, 0, st>>>(
+                                   np, ls.glist, X, ldx, Xg, ncols, ncols)));
+    NS_LAUNCH_CHECK();
     // X_j / Y_j: stacked rows goff[j], leading dimension ncols
     GemmBatch g{nullptr, 0, ls.M, ls.Kg, ls.soff, ls.sld, ls.goff, ncols, ncols, ls.goff, ncols, nullptr, ncols,
                 ls.xperm.p, ls.xplen};

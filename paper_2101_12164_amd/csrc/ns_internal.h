@@ -131,7 +131,8 @@ struct SymPacked {
 void sym_pack(SymPacked& sp, const std::vector<int>& dims, const double* src, const int64_t* src_off,
               const int64_t* src_ld, const int64_t* xoff, hipStream_t st);
 // y_b = A_b x_b for every block (one column).
-void sym_gemv(const SymPacked& sp, const double* x, double* y, hipStream_t st);
+// y = S x per block; block b's vector is x[xoff_b ..], or with xidx gathered as x[xidx[xoff_b + r]] (-1: 0).
+void sym_gemv(const SymPacked& sp, const double* x, double* y, hipStream_t st, const int32_t* xidx = nullptr);
 
 struct TileLevel {
   int role = 0;  // 0: interior blocks, 1: interface blocks (timing family)
@@ -233,7 +234,8 @@ void tri_gram(const TileLevel& lv, const double* Y, double* C, int64_t ld, const
               double alg_flops, hipStream_t st);
 // C = A^{-1} B for every block with the explicit inverses; B, C padded rhs (ld ncols).
 template <class T>
-void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStream_t st);
+void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStream_t st,
+                        const int32_t* bidx = nullptr);  // bidx: B gathered per row (one column, FP64 packed path)
 // Expand the factor of one block to a dense nb x nb column-major lower matrix.
 void tile_export(const TileLevel& lv, int block, double* out, hipStream_t st);
 

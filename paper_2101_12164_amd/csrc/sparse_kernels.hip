@@ -921,8 +921,14 @@ void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int
   };
   T* xs = nullptr;
   if (n2pad) {
-    gather_sub<T>(n2pad, h.l2src, R, ldr, nullptr, static_cast<const T*>(nullptr), 0, Bp, ncols, ncols, st);
-    xs = solve(h.L2, Bp, Bq);
+    if (sizeof(T) == 8 && ncols == 1 && ldr == 1 && h.L2.Ainv64.p && h.L2.inv_sym.built()) {
+      // one column: the packed product reads its input through l2src (no separate gather)
+      tile_apply_inverse<T>(h.L2, R, Bq, 1, st, h.l2src);
+      xs = Bq;
+    } else {
+      gather_sub<T>(n2pad, h.l2src, R, ldr, nullptr, static_cast<const T*>(nullptr), 0, Bp, ncols, ncols, st);
+      xs = solve(h.L2, Bp, Bq);
+    }
   }
   if (nJpad) {
     gather_sub<T>(nJpad, h.jsrc, R, ldr, n2pad ? &h.AJs : nullptr, xs, ncols, Gj, ncols, ncols, st);

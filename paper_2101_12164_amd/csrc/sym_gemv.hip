@@ -45,7 +45,8 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const int* __restrict__ mt, c
                                                    const int64_t* __restrict__ toff,
                                                    const int64_t* __restrict__ pboff,
                                                    const int64_t* __restrict__ xoff, const double* __restrict__ tiles,
-                                                   const double* __restrict__ x, double* __restrict__ part) {
+                                                   const double* __restrict__ x, const int32_t* __restrict__ xidx,
+                                                   double* __restrict__ part) {
   __shared__ double s[ST * (ST + 1)];
   __shared__ double xi[ST], xj[ST];
   const int b = blockIdx.y, u = blockIdx.x;
@@ -60,14 +61,18 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const int* __restrict__ mt, c
     const int e = threadIdx.x + 256 * q;
     s[(e / ST) * (ST + 1) + e % ST] = t[e];
   }
-  const double* xb = x + xoff[b];
-  if (threadIdx.x < ST) {
-    const int r = ST * ti + threadIdx.x;
-    xi[threadIdx.x] = r < n ? xb[r] : 0.0;
-  } else if (threadIdx.x < 2 * ST) {
-    const int c = ST * tj + threadIdx.x - ST;
-    xj[threadIdx.x - ST] = c < n ? xb[c] : 0.0;
-  }
+  // entry r of block b's vector: x[xoff_b + r], or x[xidx[xoff_b + r]] (-1: zero) when gathered by xidx
+  auto xval = [&](int r) {
+    if (r >= n) return 0.0;
+    const int64_t pos = xoff[b] + r;
+    if (!xidx) return x[pos];
+    const int32_t src = xidx[pos];
+    return src >= 0 ? x[src] : 0.0;
+  };
+  if (threadIdx.x < ST)
+    xi[threadIdx.x] = xval(ST * ti + threadIdx.x);
+  else if (threadIdx.x < 2 * ST)
+    xj[threadIdx.x - ST] = xval(ST * tj + threadIdx.x - ST);
   __syncthreads();
   double* pb = part + pboff[b];
   if (threadIdx.x < ST) {  // (A x_tj) rows of tile row ti
@@ -142,10 +147,10 @@ void sym_pack(SymPacked& sp, const std::vector<int>& dims, const double* src, co
   NS_LAUNCH_CHECK();
 }
 
-void sym_gemv(const SymPacked& sp, const double* x, double* y, hipStream_t st) {
+void sym_gemv(const SymPacked& sp, const double* x, double* y, hipStream_t st, const int32_t* xidx) {
   if (sp.nblk == 0 || sp.total_tiles == 0) return;
   k_sym_tiles<<<dim3(unsigned(sp.max_tiles), unsigned(sp.nblk)), 256, 0, st>>>(sp.mt, sp.dim, sp.toff, sp.pboff,
-                                                                               sp.xoff, sp.tiles, x, sp.part);
+                                                                               sp.xoff, sp.tiles, x, xidx, sp.part);
   NS_LAUNCH_CHECK();
   k_sym_reduce<<<dim3(unsigned((sp.max_mt * ST + 255) / 256), unsigned(sp.nblk)), 256, 0, st>>>(
       sp.mt, sp.dim, sp.pboff, sp.xoff, sp.part, y);
