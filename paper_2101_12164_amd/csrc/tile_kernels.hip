@@ -530,6 +530,168 @@ __global__ __launch_bounds__(256) void k_trsm(int nblk, const int* __restrict__ 
   }
 }
 
+// Forward sweep X = L^{-1} B (FP64) with the band's solved tiles held in
+// registers.  A workgroup takes 64 columns of one block; wave w owns columns
+// 16w .. 16w + 15 and all 64 rows of every tile row.  On gfx950 the FP64 MFMA
+// result layout of a 16 x 64 block column (element v of row block m on lane l
+// is row 16m + 4v + l/16, column l%16) is exactly the B operand layout of the
+// k-steps 16m + 4v, so each solved tile X_i stays in the wave's registers and
+// feeds the products L_{i',i} X_i of the next NBT tile rows directly: only the
+// factor tiles pass through LDS, staged once per workgroup in MFMA fragment
+// order, double-buffered with one barrier per tile.  Step i:
+//   R = B_i - sum_{l in band, l >= first} L_il X_l   (negated tiles, so the
+//       products accumulate onto B_i), then X_i = L_ii^{-1} R, whose
+//       fragments above the diagonal (all zero) are skipped.
+// Requires nbt <= NBT for every block of the launch.  (Skipping the factor's
+// zero fragments beyond the band with run-time tests measured slower: the
+// branches break the schedule of the unrolled products.)
+constexpr int FRAG = TILE2;  // one staged tile in fragment order
+// fragment position of tile element (r, c): k-step c/4, lane (c%4)*16 + r%16, row block r/16
+__device__ __forceinline__ int frag_pos(int r, int c) { return (((c >> 2) * 64 + (c & 3) * 16 + (r & 15)) << 2) + (r >> 4); }
+
+struct SweepTile {
+  double2 v[TILE2 / 512];  // 8 x 2 elements per thread
+  __device__ __forceinline__ void load(const double* __restrict__ g) {
+#pragma unroll
+    for (int q = 0; q < TILE2 / 512; ++q) v[q] = reinterpret_cast<const double2*>(g)[threadIdx.x + 256 * q];
+  }
+  __device__ __forceinline__ void store(double* s, bool neg) const {
+    const double sg = neg ? -1.0 : 1.0;
+#pragma unroll
+    for (int q = 0; q < TILE2 / 512; ++q) {
+      const int e = 2 * (threadIdx.x + 256 * q), c = e >> 6, r = e & 63;
+      s[frag_pos(r, c)] = sg * v[q].x;
+      s[frag_pos(r + 1, c)] = sg * v[q].y;
+    }
+  }
+};
+
+template <int NBT>
+__global__ __launch_bounds__(256) void k_trsm_fwd_reg(int nblk, const int* __restrict__ nt_arr,
+                                                      const int* __restrict__ nbt_arr,
+                                                      const int64_t* __restrict__ foff,
+                                                      const int64_t* __restrict__ ioff,
+                                                      const int64_t* __restrict__ roff, const double* __restrict__ L,
+                                                      const double* __restrict__ Linv, double* __restrict__ B,
+                                                      int64_t ldb, int ncols, const int* __restrict__ ncols_blk,
+                                                      const int* __restrict__ first_tile, int nchunk_all,
+                                                      int64_t row0) {
+  __shared__ __align__(16) double sF[2][FRAG];
+  int b, chunk;
+  map_block_chunk(nblk, b, chunk);
+  if (b >= nblk) return;
+  const int c0 = chunk * TILE;
+  if (c0 >= ncols) return;
+  if (ncols_blk && c0 >= ncols_blk[b]) return;
+  const int nt = nt_arr[b], nbt = nbt_arr[b];
+  const int first = first_tile ? min(first_tile[b * nchunk_all + chunk], nt) : 0;
+  if (first >= nt) return;
+  double* Bb = B + (roff[b] - row0) * ldb;
+  const double* Lb = L + foff[b];
+  const double* Ib = Linv + ioff[b];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int kq = lane >> 4, col = c0 + 16 * w + (lane & 15);
+  const bool cok = col < ncols;
+  auto nl_of = [&](int i) { return i - max(first, i - nbt); };
+  // first staged tile of step i: its farthest band tile, or the diagonal inverse when it has none
+  auto first_tile_of = [&](int i, bool& neg) -> const double* {
+    const int nl = nl_of(i);
+    neg = nl > 0;
+    return nl > 0 ? Lb + band_tile_index(nt, nbt, i, i - nl) * TILE2 : Ib + int64_t(i) * TILE2;
+  };
+  // the 16 values of this lane's column in tile row i, in MFMA result order (row block m, element v)
+  auto load_b = [&](int i, double* x) {
+    const double* g = Bb + int64_t(i) * TILE * ldb + col;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) x[4 * m + v] = cok ? g[int64_t(16 * m + 4 * v + kq) * ldb] : 0.0;
+  };
+  double xr[NBT][16];
+#pragma unroll
+  for (int s = 0; s < NBT; ++s)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) xr[s][e] = 0.0;
+  SweepTile pre;
+  {
+    bool neg;
+    pre.load(first_tile_of(first, neg));
+    pre.store(sF[0], neg);
+  }
+  double bcur[16];
+  load_b(first, bcur);
+  __syncthreads();
+  int buf = 0;
+  for (int i = first; i < nt; ++i) {
+    const int nl = nl_of(i);
+    v4d acc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[m] = v4d{bcur[4 * m], bcur[4 * m + 1], bcur[4 * m + 2], bcur[4 * m + 3]};
+    // band tiles, farthest first: slot s holds X_{i-1-s}
+#pragma unroll
+    for (int s = NBT - 1; s >= 0; --s) {
+      if (s < nl) {
+        const double* nx = s > 0 ? Lb + band_tile_index(nt, nbt, i, i - s) * TILE2 : Ib + int64_t(i) * TILE2;
+        pre.load(nx);
+        const double* f = sF[buf];
+#pragma unroll
+        for (int k4 = 0; k4 < 16; ++k4) {
+          const double2 a01 = reinterpret_cast<const double2*>(f + ((k4 * 64 + lane) << 2))[0];
+          const double2 a23 = reinterpret_cast<const double2*>(f + ((k4 * 64 + lane) << 2))[1];
+          const double bx = xr[s][k4];
+          acc[0] = MF<double>::mma(a01.x, bx, acc[0]);
+          acc[1] = MF<double>::mma(a01.y, bx, acc[1]);
+          acc[2] = MF<double>::mma(a23.x, bx, acc[2]);
+          acc[3] = MF<double>::mma(a23.y, bx, acc[3]);
+        }
+        pre.store(sF[buf ^ 1], s > 0);
+        __syncthreads();
+        buf ^= 1;
+      }
+    }
+    // diagonal inverse: X_i = L_ii^{-1} R, R (in acc) used as the B operand
+    const bool more = i + 1 < nt;
+    bool nneg = false;
+    if (more) {
+      pre.load(first_tile_of(i + 1, nneg));
+      load_b(i + 1, bcur);
+    }
+    v4d xn[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) xn[m] = v4d{0, 0, 0, 0};
+    {
+      const double* f = sF[buf];
+#pragma unroll
+      for (int k4 = 0; k4 < 16; ++k4) {
+        const double2 a01 = reinterpret_cast<const double2*>(f + ((k4 * 64 + lane) << 2))[0];
+        const double2 a23 = reinterpret_cast<const double2*>(f + ((k4 * 64 + lane) << 2))[1];
+        const double bx = acc[k4 >> 2][k4 & 3];
+        // L_ii^{-1} is lower triangular: fragment (m, k4) is zero for k4 >= 4m + 4
+        if (k4 < 4) xn[0] = MF<double>::mma(a01.x, bx, xn[0]);
+        if (k4 < 8) xn[1] = MF<double>::mma(a01.y, bx, xn[1]);
+        if (k4 < 12) xn[2] = MF<double>::mma(a23.x, bx, xn[2]);
+        xn[3] = MF<double>::mma(a23.y, bx, xn[3]);
+      }
+    }
+    if (cok) {
+      double* g = Bb + int64_t(i) * TILE * ldb + col;
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) g[int64_t(16 * m + 4 * v + kq) * ldb] = xn[m][v];
+    }
+#pragma unroll
+    for (int s = NBT - 1; s > 0; --s)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) xr[s][e] = xr[s - 1][e];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) xr[0][e] = xn[e >> 2][e & 3];
+    if (more) pre.store(sF[buf ^ 1], nneg);
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
 __global__ void k_tile_export(int nt, int nbt, int nb, const double* __restrict__ Lb, double* __restrict__ out) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(nb) * nb) return;
@@ -564,6 +726,14 @@ void launch_trsm(const TileLevel& lv, T* B, int64_t ldb, int ncols, const T* L, 
     k_trsm<T, CW, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L, Linv, B, ldb, ncols);
     NS_LAUNCH_CHECK();
   }
+}
+
+// the register-ring sweep holds REG_NBT solved tiles per wave
+constexpr int REG_NBT = 4;
+bool reg_sweep_ok(const TileLevel& lv, int b0, int b1) {
+  for (int b = b0; b < b1; ++b)
+    if (lv.h_nbt[b] > REG_NBT) return false;
+  return true;
 }
 
 }  // namespace
@@ -667,6 +837,14 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
   const int* nc = ncols_blk ? ncols_blk + b0 : nullptr;
   const int* ft = first_tile ? first_tile + int64_t(b0) * nchunk_all : nullptr;
   const int grid = nbp8 * 8 * nchunk_all;
+  if constexpr (sizeof(T) == 8) {
+    if (cw == 64 && reg_sweep_ok(lv, b0, b1)) {
+      k_trsm_fwd_reg<REG_NBT><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0, lv.ioff + b0,
+                                                    lv.roff + b0, L, Li, B, ldb, ncols, nc, ft, nchunk_all, row0);
+      NS_LAUNCH_CHECK();
+      return;
+    }
+  }
   if (cw == 16)
     k_trsm<T, 16, true><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0, lv.ioff + b0,
                                               lv.roff + b0, L, Li, B, ldb, ncols, nc, ft, nchunk_all, row0);
@@ -688,8 +866,12 @@ void tile_solve_chunks(const TileLevel& lv, double* B, int64_t ldb, int ncols, c
   const double bytes = (lv.alg_tri + 2.0 * lv.alg_rows * ncols) * sizeof(double);
   {
     KScope ks(fam, st, bytes, lv.alg_sq * ncols);
-    k_trsm<double, TILE, true><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, lv.L64,
-                                                     lv.Linv64, B, ldb, ncols, nullptr, first_tile, nchunk);
+    if (reg_sweep_ok(lv, 0, lv.nblk))
+      k_trsm_fwd_reg<REG_NBT><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, lv.L64,
+                                                    lv.Linv64, B, ldb, ncols, nullptr, first_tile, nchunk, 0);
+    else
+      k_trsm<double, TILE, true><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, lv.L64,
+                                                       lv.Linv64, B, ldb, ncols, nullptr, first_tile, nchunk);
     NS_LAUNCH_CHECK();
   }
   {
