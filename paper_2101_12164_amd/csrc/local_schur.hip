@@ -42,13 +42,19 @@ struct MFL<float> {
 constexpr int NO_ROW = 0x7F7F7F7F;
 __global__ void k_mark(int64_t nrows, const int32_t* __restrict__ rblk, const int64_t* __restrict__ roff,
                        const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                       const int64_t* __restrict__ gbase, int64_t ldf, int* __restrict__ frow) {
+                       const int64_t* __restrict__ gbase, int64_t ldf, int* __restrict__ frow,
+                       int* __restrict__ ccnt, int* __restrict__ over) {
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (r >= nrows) return;
   const int j = rblk[r];
   if (j < 0) return;
   const int lr = int(r - roff[j]);
-  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) atomicMin(&frow[int64_t(j) * ldf + (col[e] - gbase[j])], lr);
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) {
+    const int64_t q = int64_t(j) * ldf + (col[e] - gbase[j]);
+    atomicMin(&frow[q], lr);
+    // entries per column of A_{I_j Gamma_j}: only a count beyond the sparse cap is recorded
+    if (atomicAdd(&ccnt[q], 1) + 1 > SPARSE_RHS_CAP) atomicMax(over, 1);
+  }
 }
 
 // One workgroup per block: its interface list ordered by the first coupled row (ties by node), cidx
@@ -143,6 +149,32 @@ __global__ __launch_bounds__(1024) void k_compact(const int64_t* __restrict__ gc
 
 // B (rows row0 .. row0 + nrows of the padded interior rows, x ldb) = A_IGamma restricted to each block's
 // Gamma_j columns; first[j * ldb + c] = first block-local row with a nonzero in column c.
+// The sparse form of B_j = A_{I_j Gamma_j} (columns in the sorted order): per column its entries as
+// (local row, value) in a slot taken by an atomic counter (each entry has its own row, so the slot order
+// does not change any result), and the first nonzero row.
+__global__ void k_fill_sparse(int64_t nrows, int64_t row0, const int32_t* __restrict__ rblk,
+                              const int64_t* __restrict__ roff, const int64_t* __restrict__ ptr,
+                              const int32_t* __restrict__ col, const double* __restrict__ val,
+                              const int64_t* __restrict__ gbase, int64_t ldf, const int32_t* __restrict__ cidx,
+                              int64_t ldw, int* __restrict__ cnt, int* __restrict__ crow, double* __restrict__ cval,
+                              int* __restrict__ first) {
+  const int64_t rr = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (rr >= nrows) return;
+  const int64_t r = row0 + rr;
+  const int j = rblk[r];
+  if (j < 0) return;
+  const int lr = int(r - roff[j]);
+  for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) {
+    const int64_t q = int64_t(j) * ldw + cidx[int64_t(j) * ldf + (col[e] - gbase[j])];
+    const int slot = atomicAdd(&cnt[q], 1);
+    if (slot < SPARSE_RHS_CAP) {  // always: the counts were checked when the layout was planned
+      crow[q * SPARSE_RHS_CAP + slot] = lr;
+      cval[q * SPARSE_RHS_CAP + slot] = val[e];
+    }
+    atomicMin(&first[q], lr);
+  }
+}
+
 __global__ void k_fill_B(int64_t nrows, int64_t row0, const int32_t* __restrict__ rblk,
                          const int64_t* __restrict__ roff, const int64_t* __restrict__ ptr,
                          const int32_t* __restrict__ col, const double* __restrict__ val,
@@ -520,13 +552,21 @@ void local_schur_plan(Handle& h) {
   cnt.alloc(nb);
   cidx.alloc(int64_t(nb) * ldf);
   NS_HIP(hipMemsetAsync(flag.p, 0x7F, int64_t(nb) * ldf * sizeof(int), st));  // NO_ROW
-  k_mark<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, lv.roff, h.AIG.ptr, h.AIG.col, gbase_d, ldf, flag);
+  DBuf<int> ccnt;
+  ccnt.alloc(int64_t(nb) * ldf + 1);  // per (block, interface row) entry counts, then the overflow flag
+  NS_HIP(hipMemsetAsync(ccnt.p, 0, (int64_t(nb) * ldf + 1) * sizeof(int), st));
+  int* over = ccnt.p + int64_t(nb) * ldf;
+  k_mark<<<unsigned((nIp + 255) / 256), 256, 0, st>>>(nIp, rblk, lv.roff, h.AIG.ptr, h.AIG.col, gbase_d, ldf, flag,
+                                                      ccnt, over);
   NS_LAUNCH_CHECK();
   k_compact<<<nb, 1024, 0, st>>>(gcnt_d, gbase_d, ldf, flag, cnt, nullptr, nullptr, nullptr, 0);
   NS_LAUNCH_CHECK();
   ls.h_m.resize(nb);
+  int* h_over = static_cast<int*>(pinned_scratch(sizeof(int)));
   NS_HIP(hipMemcpyAsync(ls.h_m.data(), cnt.p, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipMemcpyAsync(h_over, over, sizeof(int), hipMemcpyDeviceToHost, st));
   NS_HIP(hipStreamSynchronize(st));
+  pl.sparse_rhs = *h_over == 0;
   // stacked layouts: Gamma_j lists padded to 64 rows; S_j with ld = padded m_j
   std::vector<int64_t> goff(nb), soff(nb), sld(nb), wld(nb);
   std::vector<int>& Kv = pl.Kv;
@@ -614,6 +654,17 @@ void local_schur_form(Handle& h) {
   }
   DBuf<double> W;
   W.alloc(wmax > 0 ? wmax : 1);
+  // sparse right-hand sides: the sweep builds each tile row of B_j from the column entries, so W is neither
+  // cleared nor filled (rows above a chunk's first tile are never read)
+  const bool sparse = pl.sparse_rhs && tile_sparse_rhs_ok(lv);
+  DBuf<int> scnt, srow;
+  DBuf<double> sval;
+  if (sparse) {
+    scnt.alloc(int64_t(nb) * ldw);
+    srow.alloc(int64_t(nb) * ldw * SPARSE_RHS_CAP);
+    sval.alloc(int64_t(nb) * ldw * SPARSE_RHS_CAP);
+    NS_HIP(hipMemsetAsync(scnt.p, 0, int64_t(nb) * ldw * sizeof(int), st));
+  }
   DBuf<int64_t> woffg;
   woffg.alloc(nb);
   DBuf<int> gperm;
@@ -622,16 +673,27 @@ void local_schur_form(Handle& h) {
     const int b0 = gr.first, b1 = gr.second, nbs = b1 - b0;
     const int64_t row0 = lv.h_roff[b0];
     const int64_t rows = lv.h_roff[b1 - 1] + int64_t(lv.h_nt[b1 - 1]) * TILE - row0;
-    NS_HIP(hipMemsetAsync(W.p, 0, rows * ldw * sizeof(double), st));
-    k_fill_B<<<unsigned((rows + 255) / 256), 256, 0, st>>>(rows, row0, rblk, lv.roff, h.AIG.ptr, h.AIG.col,
-                                                           h.AIG.val64, gbase_d, ldf, cidx, W, ldw, first);
+    if (sparse) {
+      k_fill_sparse<<<unsigned((rows + 255) / 256), 256, 0, st>>>(rows, row0, rblk, lv.roff, h.AIG.ptr, h.AIG.col,
+                                                                  h.AIG.val64, gbase_d, ldf, cidx, ldw, scnt, srow,
+                                                                  sval, first);
+    } else {
+      NS_HIP(hipMemsetAsync(W.p, 0, rows * ldw * sizeof(double), st));
+      k_fill_B<<<unsigned((rows + 255) / 256), 256, 0, st>>>(rows, row0, rblk, lv.roff, h.AIG.ptr, h.AIG.col,
+                                                             h.AIG.val64, gbase_d, ldf, cidx, W, ldw, first);
+    }
     NS_LAUNCH_CHECK();
     k_first_tiles<<<(nbs * ctiles + 255) / 256, 256, 0, st>>>(nbs, int(ldw), ctiles, first.p + int64_t(b0) * ldw,
                                                                ftile.p + int64_t(b0) * ctiles);
     NS_LAUNCH_CHECK();
     // the formation's algorithmic flops are added once all groups are queued (they need the first rows)
-    tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p, ftile.p, 0.0, b0, b1, row0,
-                           KF_LS_FORM);  // W_j = L_j^{-1} B_j
+    SparseRhs sr;
+    if (sparse) {
+      const int64_t q0 = int64_t(b0) * ldw;
+      sr = SparseRhs{scnt.p + q0, srow.p + q0 * SPARSE_RHS_CAP, sval.p + q0 * SPARSE_RHS_CAP, ldw};
+    }
+    tile_solve_fwd<double>(lv, W.p, ldw, int(ldw), 64, st, ls.M.p, ftile.p, 0.0, b0, b1, row0, KF_LS_FORM,
+                           sparse ? &sr : nullptr);  // W_j = L_j^{-1} B_j
     for (int j = b0; j < b1; ++j) hwo[j] = (lv.h_roff[j] - row0) * ldw;
     upload(woffg.p + b0, hwo.data() + b0, nbs * sizeof(int64_t), st);
     // B_j = W_j: offset woff[j] inside the group, common leading dimension ldw

@@ -16,6 +16,7 @@ struct LocalSchurPlan {
   DBuf<int64_t> gbase_d;     // first interface row of each block's problem
   int64_t ldf = 1, ldw = 1;  // interface rows of the largest problem; columns of the stacked W
   std::vector<int> Kv;       // padded rows of every block
+  bool sparse_rhs = false;   // every column of A_{I_j Gamma_j} has at most SPARSE_RHS_CAP entries
 };
 
 struct LocalSchur {

@@ -212,10 +212,24 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
 // first_tile: optional [block * nchunks + chunk] first tile row with a nonzero
 // right-hand side (rows above stay zero); alg_flops >= 0 overrides the timing work.
 // Blocks b0 .. b1-1 only (b1 < 0: all), with B holding the padded rows from row0 on.
+// A right-hand side given by columns of at most SPARSE_RHS_CAP entries: column c of block b (b counted from
+// b0, c < ld) has cnt[b * ld + c] entries, local row row[(b * ld + c) * CAP + e] and value val[...]; every
+// other entry is zero.  With it the sweep reads no right-hand side from B and writes every tile row from the
+// chunk's first tile on (rows above are left as they are: callers do not read them).
+constexpr int SPARSE_RHS_CAP = 4;
+struct SparseRhs {
+  const int* cnt = nullptr;
+  const int* row = nullptr;
+  const double* val = nullptr;
+  int64_t ld = 0;
+};
 template <class T>
 void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st,
                     const int* ncols_blk = nullptr, const int* first_tile = nullptr, double alg_flops = -1.0,
-                    int b0 = 0, int b1 = -1, int64_t row0 = 0, int family = -1);  // -1: by the level's role
+                    int b0 = 0, int b1 = -1, int64_t row0 = 0, int family = -1,  // -1: by the level's role
+                    const SparseRhs* sparse = nullptr);
+// The FP64 64-column forward sweep of every block of lv can take a SparseRhs (band of at most 4 tiles).
+bool tile_sparse_rhs_ok(const TileLevel& lv);
 // Single right-hand side sweeps (FP64) with 16-wave workgroups; need LT64.
 bool trsv1_supported(const TileLevel& lv);
 bool trsv1_supported_size(const TileLevel& lv);  // the block size allows the single-column sweeps

@@ -566,7 +566,7 @@ struct SweepTile {
   }
 };
 
-template <int NBT>
+template <int NBT, bool SPB>
 __global__ __launch_bounds__(256) void k_trsm_fwd_reg(int nblk, const int* __restrict__ nt_arr,
                                                       const int* __restrict__ nbt_arr,
                                                       const int64_t* __restrict__ foff,
@@ -575,7 +575,7 @@ __global__ __launch_bounds__(256) void k_trsm_fwd_reg(int nblk, const int* __res
                                                       const double* __restrict__ Linv, double* __restrict__ B,
                                                       int64_t ldb, int ncols, const int* __restrict__ ncols_blk,
                                                       const int* __restrict__ first_tile, int nchunk_all,
-                                                      int64_t row0) {
+                                                      int64_t row0, SparseRhs sp) {
   __shared__ __align__(16) double sF[2][FRAG];
   int b, chunk;
   map_block_chunk(nblk, b, chunk);
@@ -599,13 +599,50 @@ __global__ __launch_bounds__(256) void k_trsm_fwd_reg(int nblk, const int* __res
     neg = nl > 0;
     return nl > 0 ? Lb + band_tile_index(nt, nbt, i, i - nl) * TILE2 : Ib + int64_t(i) * TILE2;
   };
+  // SPB: this lane's column of the right-hand side as (local row, value) pairs (row -2^30: none)
+  constexpr int CAP = SPB ? SPARSE_RHS_CAP : 1;
+  int er[CAP];
+  double ev[CAP];
+#pragma unroll
+  for (int e = 0; e < CAP; ++e) {
+    er[e] = -(1 << 30);
+    ev[e] = 0.0;
+  }
+  if (SPB && cok) {
+    const int64_t q = int64_t(b) * sp.ld + col;
+    const int ne = min(sp.cnt[q], CAP);
+#pragma unroll
+    for (int e = 0; e < CAP; ++e)
+      if (e < ne) {
+        er[e] = sp.row[q * CAP + e];
+        ev[e] = sp.val[q * CAP + e];
+      }
+  }
   // the 16 values of this lane's column in tile row i, in MFMA result order (row block m, element v)
   auto load_b = [&](int i, double* x) {
-    const double* g = Bb + int64_t(i) * TILE * ldb + col;
+    if constexpr (SPB) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+      for (int t = 0; t < 16; ++t) x[t] = 0.0;
+      bool any = false;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) x[4 * m + v] = cok ? g[int64_t(16 * m + 4 * v + kq) * ldb] : 0.0;
+      for (int e = 0; e < CAP; ++e) any |= unsigned(er[e] - TILE * i) < unsigned(TILE);
+      if (__any(any)) {
+#pragma unroll
+        for (int e = 0; e < CAP; ++e) {
+          const int r = er[e] - TILE * i;  // row 16m + 4v + kq of the tile: slot 4m + v = r / 4
+          const bool hit = unsigned(r) < unsigned(TILE) && (r & 3) == kq;
+          const int sl = r >> 2;
+#pragma unroll
+          for (int t = 0; t < 16; ++t) x[t] = (hit && sl == t) ? ev[e] : x[t];
+        }
+      }
+    } else {
+      const double* g = Bb + int64_t(i) * TILE * ldb + col;
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[4 * m + v] = cok ? g[int64_t(16 * m + 4 * v + kq) * ldb] : 0.0;
+    }
   };
   double xr[NBT][16];
 #pragma unroll
@@ -738,6 +775,8 @@ bool reg_sweep_ok(const TileLevel& lv, int b0, int b1) {
 
 }  // namespace
 
+bool tile_sparse_rhs_ok(const TileLevel& lv) { return reg_sweep_ok(lv, 0, lv.nblk); }
+
 void tile_cholesky(TileLevel& lv, int* d_err, hipStream_t st) {
   if (lv.nblk == 0) return;
   const int nbp8 = (lv.nblk + 7) / 8;
@@ -803,7 +842,7 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
 template <class T>
 void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st,
                     const int* ncols_blk, const int* first_tile, double alg_flops, int b0, int b1, int64_t row0,
-                    int family) {
+                    int family, const SparseRhs* sparse) {
   if (b1 < 0) b1 = lv.nblk;
   const int nblk = b1 - b0;
   if (nblk <= 0 || ncols == 0) return;
@@ -839,12 +878,19 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
   const int grid = nbp8 * 8 * nchunk_all;
   if constexpr (sizeof(T) == 8) {
     if (cw == 64 && reg_sweep_ok(lv, b0, b1)) {
-      k_trsm_fwd_reg<REG_NBT><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0, lv.ioff + b0,
-                                                    lv.roff + b0, L, Li, B, ldb, ncols, nc, ft, nchunk_all, row0);
+      if (sparse)
+        k_trsm_fwd_reg<REG_NBT, true><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0,
+                                                            lv.ioff + b0, lv.roff + b0, L, Li, B, ldb, ncols, nc,
+                                                            ft, nchunk_all, row0, *sparse);
+      else
+        k_trsm_fwd_reg<REG_NBT, false><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0,
+                                                             lv.ioff + b0, lv.roff + b0, L, Li, B, ldb, ncols, nc,
+                                                             ft, nchunk_all, row0, SparseRhs{});
       NS_LAUNCH_CHECK();
       return;
     }
   }
+  if (sparse) fail(INVALID_ARG, "sparse right-hand side needs the 64-column FP64 register sweep");
   if (cw == 16)
     k_trsm<T, 16, true><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0, lv.ioff + b0,
                                               lv.roff + b0, L, Li, B, ldb, ncols, nc, ft, nchunk_all, row0);
@@ -867,8 +913,9 @@ void tile_solve_chunks(const TileLevel& lv, double* B, int64_t ldb, int ncols, c
   {
     KScope ks(fam, st, bytes, lv.alg_sq * ncols);
     if (reg_sweep_ok(lv, 0, lv.nblk))
-      k_trsm_fwd_reg<REG_NBT><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, lv.L64,
-                                                    lv.Linv64, B, ldb, ncols, nullptr, first_tile, nchunk, 0);
+      k_trsm_fwd_reg<REG_NBT, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff,
+                                                           lv.L64, lv.Linv64, B, ldb, ncols, nullptr, first_tile,
+                                                           nchunk, 0, SparseRhs{});
     else
       k_trsm<double, TILE, true><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, lv.L64,
                                                        lv.Linv64, B, ldb, ncols, nullptr, first_tile, nchunk);
@@ -883,7 +930,7 @@ void tile_solve_chunks(const TileLevel& lv, double* B, int64_t ldb, int ncols, c
 }
 
 template void tile_solve_fwd<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t, const int*, const int*,
-                                     double, int, int, int64_t, int);
+                                     double, int, int, int64_t, int, const SparseRhs*);
 template void tile_solve<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t);
 template void tile_solve<float>(const TileLevel&, float*, int64_t, int, int, hipStream_t);
 
