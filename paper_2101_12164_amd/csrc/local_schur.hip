@@ -369,6 +369,105 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restric
       }
 }
 
+// Symmetric product C_j = W_j^T W_j (FP64, the lower 64 x 64 tiles, each also
+// stored transposed) for the local Schur formation.  K runs in chunks of KC
+// rows from the later first nonzero tile row of the two column tiles; each
+// chunk of both operands is staged in LDS in MFMA fragment order (one 16-byte
+// read gives a wave both row blocks it needs for a k-step) with the next
+// chunk's global loads in flight in registers.  Wave w computes the 32 x 32
+// quarter (w >> 1, w & 1) of the tile as 2 x 2 MFMA blocks.
+__device__ __forceinline__ int syrk_frag(int r, int k) {  // operand element (row r of the tile, k) in fragment order
+  return (((k >> 2) * 64 + (k & 3) * 16 + (r & 15)) << 2) + (r >> 4);
+}
+template <int KC>
+__global__ __launch_bounds__(256) void k_syrk64(GemmBatch g, const double* __restrict__ W, double* __restrict__ C,
+                                                int gx, int nb) {
+  __shared__ __align__(16) double sA[KC * 64];
+  __shared__ __align__(16) double sB[KC * 64];
+  const int tiles = gx * gx;
+  int j, t;
+  if (nb < 8) {
+    j = int(blockIdx.x) / tiles;
+    t = int(blockIdx.x) % tiles;
+  } else {
+    const int slot = int(blockIdx.x >> 3), x = int(blockIdx.x & 7), lb = slot / tiles;
+    t = slot % tiles;
+    j = g.perm ? (lb < g.plen ? g.perm[x * g.plen + lb] : -1) : x + 8 * lb;
+  }
+  if (j < 0 || j >= nb) return;
+  const int tm = t / gx, tn = t % gx;
+  if (tn > tm) return;
+  const int M = g.M[j], K = g.K[j];
+  const int m0 = tm * 64, n0 = tn * 64;
+  if (m0 >= M) return;
+  const double* Wj = W + g.aoff[j];
+  const int64_t ld = g.lda[j];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int kq = lane >> 4, rl = lane & 15;
+  const int ha = w >> 1, hb = w & 1;  // row-block pair of A (rows 32 ha ..) and of B (columns 32 hb ..)
+  int kbeg = 0;
+  if (g.kstart) {
+    const int ka = g.kstart[j * g.kstride + tm], kb = g.kstart[j * g.kstride + tn];
+    kbeg = min(max(ka, kb) * 64, K);
+  }
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0, 0, 0, 0};
+  // thread's share of a chunk: element e = threadIdx.x + 256 q is row k = e / 64, column e % 64 (each wave
+  // reads whole 512-byte rows)
+  constexpr int PQ = KC * 64 / 256;
+  double ra[PQ], rb[PQ];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int e = threadIdx.x + 256 * q, k = k0 + (e >> 6), c = e & 63;
+      const bool kin = k < K;
+      const double* row = Wj + int64_t(k) * ld;
+      ra[q] = (kin && m0 + c < M) ? row[m0 + c] : 0.0;
+      rb[q] = (kin && n0 + c < M) ? row[n0 + c] : 0.0;
+    }
+  };
+  if (kbeg < K) gload(kbeg);
+  for (int k0 = kbeg; k0 < K; k0 += KC) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int pos = syrk_frag(e & 63, e >> 6);
+      sA[pos] = ra[q];
+      sB[pos] = rb[q];
+    }
+    if (k0 + KC < K) gload(k0 + KC);
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < KC / 4; ++k4) {
+      const double2 a = reinterpret_cast<const double2*>(sA + ((k4 * 64 + lane) << 2))[ha];
+      const double2 b = reinterpret_cast<const double2*>(sB + ((k4 * 64 + lane) << 2))[hb];
+      acc[0][0] = MFL<double>::mma(a.x, b.x, acc[0][0]);
+      acc[0][1] = MFL<double>::mma(a.x, b.y, acc[0][1]);
+      acc[1][0] = MFL<double>::mma(a.y, b.x, acc[1][0]);
+      acc[1][1] = MFL<double>::mma(a.y, b.y, acc[1][1]);
+    }
+  }
+  double* Cj = C + g.coff[j] * g.cscale;
+  const int64_t ldc = g.ldc ? g.ldc[j] : g.ldc_s;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + 32 * ha + 16 * x + MFL<double>::row(kq, v);
+        const int c = n0 + 32 * hb + 16 * y + rl;
+        if (r < M && c < M) {
+          Cj[int64_t(r) * ldc + c] = acc[x][y][v];
+          if (tm != tn) Cj[int64_t(c) * ldc + r] = acc[x][y][v];
+        }
+      }
+}
+
 // Contributor lists: for each interface row g the stacked positions p with
 // glist[p] == g, in ascending p (deterministic summation order).
 __global__ void k_contrib_count(int64_t npos, const int32_t* __restrict__ glist, int64_t* __restrict__ ptr1) {
@@ -709,7 +808,11 @@ void local_schur_form(Handle& h) {
     g.perm = gperm.p;
     g.plen = plen;
     KScope ks(KF_LS_FORM, st, double(rows) * ldw * 8.0, 0.0);
-    launch_gemm<double>(ls, W.p, W.p, ls.S64.p, 0, st, true, g, ls.max_m, nbs);
+    if (ls.max_m > 0) {
+      const int tilesM = (ls.max_m + 63) / 64;
+      k_syrk64<32><<<gemm_grid(tilesM, tilesM, nbs, g.plen), 256, 0, st>>>(g, W.p, ls.S64.p, tilesM, nbs);
+      NS_LAUNCH_CHECK();
+    }
   }
   if (h.prec_inner) {
     ls.S32.alloc(ls.S64.n);
