@@ -1,0 +1,152 @@
+"""Full-size runs in the launch configuration the benchmark times (FP32 inner block CG, FP64 outer PCG with the
+local Schur operator): the 64^3 lognormal problem (64 subdomains, k = 64, p = 16), the 2048^2 lognormal problem
+(1024 subdomains, k = 128, p = 32) and the batch of 256 anisotropic Q1 problems (k = 32, p = 8).
+
+The oracle cannot set these up whole in seconds, so the checks are outputs it computes one at a time -- sampled
+subdomain Cholesky factors and sampled rows of the Schur operator S_Gamma x, each from the subdomains the row
+touches -- and properties that hold at any size: the true residual of the returned solution in FP64 and the
+convergence report."""
+
+import concurrent.futures as cf
+import time
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import torch
+
+import paper_2101_12164_amd as ns
+from gpu_helpers import rel, to_dev
+from oracle import DBBD
+from workloads import config_c2, config_c3_problem, config_c5
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(f"[full-size] {msg}", flush=True)
+
+
+def csr(P):
+    return sp.csr_matrix((P.val, P.col, P.row_ptr), shape=(P.n, P.n))
+
+
+def true_relres(P, x):
+    b = P.b()
+    return float(np.linalg.norm(b - csr(P) @ x) / np.linalg.norm(b))
+
+
+def check_factors(handle, d, j_glob0, rng, count):
+    """Sampled subdomain factors L_j against the Cholesky factor of the oracle's block A_j."""
+    for j in rng.choice(d.n_sub, size=min(count, d.n_sub), replace=False):
+        Aj = d.block(int(j)).toarray()
+        L = ns.nystrom_schur_export_factor(handle, j_glob0 + int(j), Aj.shape[0]).cpu().numpy()
+        assert rel(L, sla.cholesky(Aj, lower=True)) < 1e-12, j
+
+
+def sampled_schur_rows(d, x, rows):
+    """(S_Gamma x)_g = (A_Gamma x)_g - A_{g,I} A_I^{-1} A_{I,Gamma} x for the sampled interface rows g: only
+    the subdomains that row g touches are solved, each with its own Cholesky factor."""
+    v = d.A_IG @ x
+    bp = d.block_ptr
+    blk = np.searchsorted(bp, np.arange(d.I.size), side="right") - 1
+    sols = {}
+    out, scale = [], []
+    for g in rows:
+        row = d.A_GI[g]
+        w = 0.0
+        for j in np.unique(blk[row.indices]):
+            a, b = int(bp[j]), int(bp[j + 1])
+            if j not in sols:
+                sols[j] = sla.cho_solve((sla.cholesky(d.block(int(j)).toarray(), lower=True), True), v[a:b])
+            w += float(row[:, a:b] @ sols[j])
+        ag = float(d.A_G[g] @ x)
+        out.append(ag - w)
+        scale.append(abs(ag) + abs(w))
+    return np.array(out), np.array(scale)
+
+
+SINGLE = {
+    "lognormal3d_64": config_c2,
+    "lognormal2d_2048": config_c5,
+}
+
+
+@pytest.mark.parametrize("name", list(SINGLE))
+def test_full_size_problem(name):
+    t0 = time.perf_counter()
+    P = SINGLE[name]()
+    log(f"{name}: n={P.n} k={P.k} p={P.p}, generated in {time.perf_counter() - t0:.1f} s")
+    dv = to_dev(P)
+    om = torch.as_tensor(np.ascontiguousarray(P.omega()), device="cuda")
+    t1 = time.perf_counter()
+    h = ns.NystromSchur(dv["row_ptr"], dv["col"], dv["val"], dv["part"], k=P.k, p=P.p, omega=om,
+                        tol_inner=P.tol_inner, prec_inner=ns.NS_FP32)
+    try:
+        x, info = h.solve(torch.as_tensor(P.b(), device="cuda"), rtol=P.tol_outer, maxit=2000)
+        torch.cuda.synchronize()
+        si = h.setup_info
+        log(f"{name}: setup + solve {time.perf_counter() - t1:.2f} s, it_SI={si['it_inner']} "
+            f"k_eff={si['k_eff']} it_PCG={info['it_pcg']} relres_true={info['relres_true']:.2e}")
+        assert info["converged"] == 1
+        assert info["relres_schur"] <= P.tol_outer
+        assert si["k_eff"] == P.k
+        xr = x.cpu().numpy()
+        r = true_relres(P, xr)
+        assert r <= 1e-7, r
+        assert abs(r - info["relres_true"]) <= 0.1 * r + 1e-12
+        d = DBBD(P.n, P.row_ptr, P.col, P.val, P.part)
+        assert h.sizes()["n_gamma"] == d.n_gamma and h.sizes()["n_sub"] == d.n_sub
+        rng = np.random.default_rng(11)
+        check_factors(h.handle, d, 0, rng, 2)
+        xg = rng.standard_normal(d.n_gamma)
+        Sx = ns.nystrom_schur_schur_apply(h.handle, torch.as_tensor(xg[:, None], device="cuda")).cpu().numpy()[:, 0]
+        rows = rng.choice(d.n_gamma, size=6, replace=False)
+        ref, scale = sampled_schur_rows(d, xg, rows)
+        assert np.all(np.abs(Sx[rows] - ref) <= 1e-11 * scale), (Sx[rows], ref)
+    finally:
+        h.close()
+
+
+def test_full_size_batch():
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(16) as ex:
+        Ps = list(ex.map(config_c3_problem, range(256)))
+    log(f"batch: 256 problems, {sum(P.n for P in Ps)} unknowns, generated in {time.perf_counter() - t0:.1f} s")
+
+    def T(a, dt):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+    probs = [(T(P.row_ptr, torch.int64), T(P.col, torch.int32), T(P.val, torch.float64), T(P.part, torch.int32))
+             for P in Ps]
+    oms = [T(P.omega(), torch.float64) for P in Ps]
+    bs = [T(P.b(), torch.float64) for P in Ps]
+    t1 = time.perf_counter()
+    h, infos = ns.nystrom_schur_setup_batched(probs, k=32, p=8, omegas=oms, tol_inner=0.1, prec_inner=ns.NS_FP32)
+    try:
+        xs, outs = ns.nystrom_schur_pcg_solve_batched(h, bs, rtol=1e-8, maxit=2000)
+        torch.cuda.synchronize()
+        log(f"batch: setup + solve {time.perf_counter() - t1:.2f} s, it_PCG "
+            f"{min(o['it_pcg'] for o in outs)}..{max(o['it_pcg'] for o in outs)}")
+        worst = 0.0
+        for P, x, o in zip(Ps, xs, outs):
+            assert o["converged"] == 1 and o["relres_schur"] <= 1e-8, P.name
+            worst = max(worst, true_relres(P, x.cpu().numpy()))
+        assert worst <= 1e-7, worst
+        # sampled problems: factors of two subdomains and rows of the Schur operator, at the problem's offsets
+        rng = np.random.default_rng(12)
+        qs = rng.choice(len(Ps), size=2, replace=False)
+        ds = {int(q): DBBD(Ps[q].n, Ps[q].row_ptr, Ps[q].col, Ps[q].val, Ps[q].part) for q in qs}
+        sub0 = np.concatenate([[0], np.cumsum([int(P.part.max()) + 1 for P in Ps])])
+        gam0 = np.concatenate([[0], np.cumsum([int(np.count_nonzero(P.part < 0)) for P in Ps])])
+        xg = rng.standard_normal(int(gam0[-1]))
+        Sx = ns.nystrom_schur_schur_apply(h, torch.as_tensor(xg[:, None], device="cuda")).cpu().numpy()[:, 0]
+        for q, d in ds.items():
+            check_factors(h, d, int(sub0[q]), rng, 2)
+            g0 = int(gam0[q])
+            rows = rng.choice(d.n_gamma, size=4, replace=False)
+            ref, scale = sampled_schur_rows(d, xg[g0:g0 + d.n_gamma], rows)
+            assert np.all(np.abs(Sx[g0 + rows] - ref) <= 1e-11 * scale), (q, Sx[g0 + rows], ref)
+    finally:
+        ns.nystrom_schur_destroy(h)
