@@ -429,8 +429,12 @@ __global__ __launch_bounds__(256) void k_syrk64(GemmBatch g, const double* __res
       rb[q] = (kin && n0 + c < M) ? row[n0 + c] : 0.0;
     }
   };
-  if (kbeg < K) gload(kbeg);
-  for (int k0 = kbeg; k0 < K; k0 += KC) {
+  // K is walked from the end down to kbeg: every tile of a block then starts on the same last rows of W_j and
+  // the tiles running together on an XCD read the same rows at about the same time (shared in its L2),
+  // while tiles with a later first row simply stop earlier
+  const int klast = kbeg < K ? kbeg + (K - 1 - kbeg) / KC * KC : kbeg;
+  if (kbeg < K) gload(klast);
+  for (int k0 = klast; k0 >= kbeg && kbeg < K; k0 -= KC) {
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PQ; ++q) {
@@ -439,7 +443,7 @@ __global__ __launch_bounds__(256) void k_syrk64(GemmBatch g, const double* __res
       sA[pos] = ra[q];
       sB[pos] = rb[q];
     }
-    if (k0 + KC < K) gload(k0 + KC);
+    if (k0 - KC >= kbeg) gload(k0 - KC);
     __syncthreads();
 #pragma unroll
     for (int k4 = 0; k4 < KC / 4; ++k4) {
