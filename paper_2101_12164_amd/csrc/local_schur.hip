@@ -369,6 +369,74 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restric
       }
 }
 
+// Products C_b = A_b^T B_b with few output tiles (the explicit inverse of a
+// single dense junction block applied to up to 80 columns): one workgroup per
+// 16-row strip of C, its eight waves taking every eighth k-step of the
+// reduction with the operands read straight from the cache, the eight partial
+// strips summed in LDS in a fixed order.  NQ 16-column MFMA tiles per strip.
+constexpr int KSPLIT_WAVES = 8;
+template <class T, int NQ>
+__global__ __launch_bounds__(64 * KSPLIT_WAVES) void k_gemm_tn_ksplit(GemmBatch g, const T* __restrict__ A,
+                                                                      const T* __restrict__ B, T* __restrict__ C,
+                                                                      int N, int strips, int nb) {
+  using acc_t = typename MFL<T>::acc_t;
+  __shared__ T red[KSPLIT_WAVES][NQ * 4][64];
+  const int j = int(blockIdx.x) / strips, tm = int(blockIdx.x) % strips;
+  if (j >= nb) return;
+  const int M = g.M[j], K = g.K[j];
+  const int m0 = 16 * tm;
+  if (m0 >= M) return;
+  const T* Aj = A + g.aoff[j];
+  const int64_t lda = g.lda[j];
+  const T* Bj = B + g.boff[j] * g.bscale;
+  const int64_t ldb = g.ldb;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rl = lane & 15, kq = lane >> 4;
+  acc_t acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = acc_t{0, 0, 0, 0};
+  // the loads of U k-steps are issued together (unconditional, from clamped indices; out-of-range values are
+  // replaced by zero) before their products, so they are in flight at the same time
+  constexpr int U = 4;
+  const int mc = min(m0 + rl, M - 1);
+  const bool mok = m0 + rl < M;
+  for (int kk = 4 * w; kk < K; kk += 4 * KSPLIT_WAVES * U) {
+    T av[U], bv[U][NQ];
+    bool kin[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = kk + 4 * KSPLIT_WAVES * u + kq;
+      kin[u] = k < K;
+      const int64_t kc = min(k, K - 1);
+      av[u] = Aj[kc * lda + mc];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) bv[u][q] = Bj[kc * ldb + min(16 * q + rl, N - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const T a = (kin[u] && mok) ? av[u] : T(0);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        acc[q] = MFL<T>::mma(a, (kin[u] && 16 * q + rl < N) ? bv[u][q] : T(0), acc[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[w][4 * q + v][lane] = acc[q][v];
+  __syncthreads();
+  T* Cj = C + g.coff[j] * g.cscale;
+  const int64_t ldc = g.ldc ? g.ldc[j] : g.ldc_s;
+  for (int e = threadIdx.x; e < NQ * 4 * 64; e += 64 * KSPLIT_WAVES) {
+    const int qv = e >> 6, ln = e & 63;
+    T sum = red[0][qv][ln];
+#pragma unroll
+    for (int x = 1; x < KSPLIT_WAVES; ++x) sum += red[x][qv][ln];
+    const int r = m0 + MFL<T>::row(ln >> 4, qv & 3), c = 16 * (qv >> 2) + (ln & 15);
+    if (r < M && c < N) Cj[int64_t(r) * ldc + c] = sum;
+  }
+}
+
 // Symmetric product C_j = W_j^T W_j (FP64, the lower 64 x 64 tiles, each also
 // stored transposed) for the local Schur formation.  K runs in chunks of KC
 // rows from the later first nonzero tile row of the two column tiles; each
@@ -588,7 +656,16 @@ void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStr
   for (int b = 0; b < lv.nblk; ++b) sq += double(lv.h_nb[b]) * lv.h_nb[b];
   KScope ks(sizeof(T) == 8 ? KF_INV64 : KF_INV32, st, (sq + 2.0 * lv.alg_rows * ncols) * sizeof(T), 2.0 * sq * ncols);
   const int tilesM = lv.max_nt;
-  if (ncols <= 16) {
+  if (ncols <= 80 && lv.nblk * tilesM < 128) {  // few output tiles: split the reduction over eight waves
+    const int strips = 4 * tilesM, grid = strips * lv.nblk;
+    switch ((ncols + 15) / 16) {
+      case 1: k_gemm_tn_ksplit<T, 1><<<grid, 64 * KSPLIT_WAVES, 0, st>>>(g, A, B, C, ncols, strips, lv.nblk); break;
+      case 2: k_gemm_tn_ksplit<T, 2><<<grid, 64 * KSPLIT_WAVES, 0, st>>>(g, A, B, C, ncols, strips, lv.nblk); break;
+      case 3: k_gemm_tn_ksplit<T, 3><<<grid, 64 * KSPLIT_WAVES, 0, st>>>(g, A, B, C, ncols, strips, lv.nblk); break;
+      case 4: k_gemm_tn_ksplit<T, 4><<<grid, 64 * KSPLIT_WAVES, 0, st>>>(g, A, B, C, ncols, strips, lv.nblk); break;
+      default: k_gemm_tn_ksplit<T, 5><<<grid, 64 * KSPLIT_WAVES, 0, st>>>(g, A, B, C, ncols, strips, lv.nblk); break;
+    }
+  } else if (ncols <= 16) {
     k_gemm_tn<T, 16><<<gemm_grid(1, tilesM, lv.nblk), 256, 0, st>>>(g, A, B, C, ncols, 0, 1, tilesM, lv.nblk);
   } else if (ncols > 64 && ncols <= 80) {
     k_gemm_tn<T, 80><<<gemm_grid(1, tilesM, lv.nblk), 256, 0, st>>>(g, A, B, C, ncols, 0, 1, tilesM, lv.nblk);
