@@ -43,7 +43,7 @@ typedef double gv4d __attribute__((ext_vector_type(4)));
 // rows in 4-row MFMA steps (wave w takes steps w, w + 4, ...), reading the operands straight from global memory
 // (the chunk is reused from cache by the strips), and the four partial strips are summed in a fixed order.
 constexpr int GS_MAXT = 5;
-template <class TA, class TB>
+template <class TA, class TB, int TMAX>
 __global__ __launch_bounds__(256) void k_gram_strip(Seg sg, const TA* __restrict__ A, int64_t lda, int ra,
                                                     const TB* __restrict__ B, int64_t ldb, int rb,
                                                     double* __restrict__ part, int sym) {
@@ -71,18 +71,28 @@ __global__ __launch_bounds__(256) void k_gram_strip(Seg sg, const TA* __restrict
     bok[t] = t < tb && bc[t] < rb;
     if (!bok[t]) bc[t] = 0;
   }
-#pragma unroll 2
-  for (int64_t k = r0 + 4 * w; k < r1; k += 16) {
-    const int64_t r = k + lk;
-    const bool rok = r < r1;
-    const int64_t rr = rok ? r : r0;
-    const double x = (rok && aok) ? double(Ap[rr * lda]) : 0.0;
+  // U k-steps per batch: all their loads are issued (unconditionally, from clamped in-bounds addresses) before
+  // the products, so they are in flight together; out-of-range values are replaced by zero afterwards
+  constexpr int U = 4;
+  for (int64_t k = r0 + 4 * w; k < r1; k += 16 * U) {
+    double xv[U], yv[U][GS_MAXT];
+    bool rok[U];
 #pragma unroll
-    for (int t = 0; t < GS_MAXT; ++t)
-      if (t < tb) {
-        const double y = (rok && bok[t]) ? double(B[rr * ldb + bc[t]]) : 0.0;
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[t], 0, 0, 0);
-      }
+    for (int u = 0; u < U; ++u) {
+      const int64_t r = k + 16 * u + lk;
+      rok[u] = r < r1;
+      const int64_t rr = rok[u] ? r : r0;
+      xv[u] = double(Ap[rr * lda]);
+#pragma unroll
+      for (int t = 0; t < TMAX; ++t) yv[u][t] = double(B[rr * ldb + bc[t]]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double x = (rok[u] && aok) ? xv[u] : 0.0;
+#pragma unroll
+      for (int t = 0; t < TMAX; ++t)
+        if (t < tb) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, (rok[u] && bok[t]) ? yv[u][t] : 0.0, acc[t], 0, 0, 0);
+    }
   }
   // fixed-order sum of the four waves' strips: waves 1..3 park theirs, wave 0 adds them in order
   if (w > 0) {
@@ -173,20 +183,36 @@ __global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* __restric
   gv4d acc[NTI];
 #pragma unroll
   for (int t = 0; t < NTI; ++t) acc[t] = gv4d{0.0, 0.0, 0.0, 0.0};
+  constexpr int PX = 64 * TS_K / 256, PM = (TS_K * NC + 255) / 256;
   for (int k0 = 0; k0 < K; k0 += TS_K) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * TS_K; e += 256) {  // in-bounds addresses, zero outside
-      const int r = e / TS_K, kk = e % TS_K, k = k0 + kk;
+    // every load of the batch is issued (in-bounds addresses) before the LDS stores, zero outside
+    T xv[PX];
+    double mv[PM];
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+      const int e = threadIdx.x + 256 * q, r = e / TS_K, k = k0 + e % TS_K;
       const int64_t row = rbase + r;
       const bool ok = row < rend && k < K;
-      const T v = X[(ok ? row : rbase) * ldx + (ok ? k : 0)];
-      sX[r * (TS_K + 1) + kk] = ok ? double(v) : 0.0;
+      xv[q] = X[(ok ? row : rbase) * ldx + (ok ? k : 0)];
     }
-    for (int e = threadIdx.x; e < TS_K * NC; e += 256) {
-      const int kk = e / NC, cc = e % NC, c = c0 + cc, k = k0 + kk;
-      const bool ok = c < ncols && k < K;
-      const double v = Mp[int64_t(ok ? k : 0) * ldm + (ok ? c : 0)];
-      sM[kk * (NC + 1) + cc] = ok ? v : 0.0;
+#pragma unroll
+    for (int q = 0; q < PM; ++q) {
+      const int e = threadIdx.x + 256 * q, c = c0 + e % NC, k = k0 + e / NC;
+      const bool ok = e < TS_K * NC && c < ncols && k < K;
+      mv[q] = Mp[int64_t(ok ? k : 0) * ldm + (ok ? c : 0)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+      const int e = threadIdx.x + 256 * q, r = e / TS_K, kk = e % TS_K;
+      const bool ok = rbase + r < rend && k0 + kk < K;
+      sX[r * (TS_K + 1) + kk] = ok ? double(xv[q]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PM; ++q) {
+      const int e = threadIdx.x + 256 * q, cc = e % NC, kk = e / NC;
+      const bool ok = c0 + cc < ncols && k0 + kk < K;
+      if (e < TS_K * NC) sM[kk * (NC + 1) + cc] = ok ? mv[q] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -465,7 +491,13 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
   if (ta > 65535) fail(INVALID_ARG, "Gram product too wide");
   dim3 g(unsigned(sg.nchunk), unsigned(ta), unsigned((tbt + GS_MAXT - 1) / GS_MAXT));
   const int sym = (static_cast<const void*>(A) == static_cast<const void*>(B) && lda == ldb && ra == rb) ? 1 : 0;
-  k_gram_strip<TA, TB><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym);
+  switch (std::min(tbt, GS_MAXT)) {  // column tiles per launch column group
+    case 1: k_gram_strip<TA, TB, 1><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym); break;
+    case 2: k_gram_strip<TA, TB, 2><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym); break;
+    case 3: k_gram_strip<TA, TB, 3><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym); break;
+    case 4: k_gram_strip<TA, TB, 4><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym); break;
+    default: k_gram_strip<TA, TB, GS_MAXT><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym); break;
+  }
   NS_LAUNCH_CHECK();
   seg_final(sg, nout, work, G, gstride, alpha, beta, st, rscale, rsstride, rb);
 }
