@@ -596,9 +596,8 @@ __global__ __launch_bounds__(256) void k_schur_epi_local(int64_t nrows, const in
   if (row >= nrows) return;
   for (int c = lane; c < ncols; c += TPR) {
     T a = T(0), w = T(0);
-    if (!w_only)
-      for (int64_t e = pG[row]; e < pG[row + 1]; ++e) a += vG[e] * X[int64_t(cG[e]) * ldx + c];
-    for (int64_t e = pC[row]; e < pC[row + 1]; ++e) w += Yg[int64_t(cC[e]) * ldy_g + c];
+    if (!w_only) csr_row_visit(pG[row], pG[row + 1], cG, vG, X, ldx, c, [&](T v, T x) { a += v * x; });
+    csr_row_visit(pC[row], pC[row + 1], cC, static_cast<const T*>(nullptr), Yg, ldy_g, c, [&](T, T x) { w += x; });
     Y[row * ldy + c] = w_only ? w : a - w;
   }
 }

@@ -82,6 +82,31 @@ struct DBuf {
 // full lower tile triangle) stores, tile column by tile column, the tiles
 // (j, j), (j + 1, j), ..., (min(nt - 1, j + nbt), j).  The Cholesky factor of
 // a band matrix keeps the band, so the factor lives in the same storage.
+// Visit the entries e0 .. e1-1 of a CSR row in index order as f(value, X[col[e] * ldx + c]) (value 1 when val
+// is null).  The index, value and X loads of four entries are issued together from clamped in-bounds positions
+// (a row's entries are otherwise a chain of dependent loads, each waiting for the last); entries past the row
+// end are loaded but not visited.
+template <class T, class F>
+__device__ __forceinline__ void csr_row_visit(int64_t e0, int64_t e1, const int32_t* __restrict__ col,
+                                              const T* __restrict__ val, const T* __restrict__ X, int64_t ldx, int c,
+                                              F&& f) {
+  for (int64_t e = e0; e < e1; e += 4) {
+    int j[4];
+    T v[4], x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t ek = e + k < e1 ? e + k : e;
+      j[k] = col[ek];
+      v[k] = val ? val[ek] : T(1);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = X[int64_t(j[k]) * ldx + c];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (e + k < e1) f(v[k], x[k]);
+  }
+}
+
 __host__ __device__ inline int64_t band_col_off(int nt, int nbt, int j) {
   const int a = nt - nbt;  // tile columns that hold nbt + 1 tiles
   if (j <= a) return int64_t(j) * (nbt + 1);

@@ -41,9 +41,8 @@ __global__ __launch_bounds__(256) void k_schur_epi(int64_t nrows, const int64_t*
   if (row >= nrows) return;
   for (int c = lane; c < ncols; c += TPR) {
     T a = T(0), w = T(0);
-    if (!w_only)
-      for (int64_t e = pG[row]; e < pG[row + 1]; ++e) a += vG[e] * X[int64_t(cG[e]) * ldx + c];
-    for (int64_t e = pI[row]; e < pI[row + 1]; ++e) w += vI[e] * Tb[int64_t(cI[e]) * ldt + c];
+    if (!w_only) csr_row_visit(pG[row], pG[row + 1], cG, vG, X, ldx, c, [&](T v, T x) { a += v * x; });
+    csr_row_visit(pI[row], pI[row + 1], cI, vI, Tb, ldt, c, [&](T v, T x) { w += v * x; });
     Y[row * ldy + c] = w_only ? w : a - w;
   }
 }
@@ -61,8 +60,7 @@ __global__ __launch_bounds__(256) void k_gather_sub(int64_t nrows, const int32_t
   const int s = src ? src[row] : int(row);
   for (int c = lane; c < ncols; c += TPR) {
     T acc = s >= 0 ? R[int64_t(s) * ldr + c] : T(0);
-    if (ptr)
-      for (int64_t e = ptr[row]; e < ptr[row + 1]; ++e) acc -= val[e] * X[int64_t(col[e]) * ldx + c];
+    if (ptr) csr_row_visit(ptr[row], ptr[row + 1], col, val, X, ldx, c, [&](T v, T x) { acc -= v * x; });
     Out[row * ldo + c] = acc;
   }
 }

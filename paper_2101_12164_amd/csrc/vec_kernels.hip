@@ -183,6 +183,19 @@ __global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* __restric
   gv4d acc[NTI];
 #pragma unroll
   for (int t = 0; t < NTI; ++t) acc[t] = gv4d{0.0, 0.0, 0.0, 0.0};
+  // the old output values (beta != 0) are loaded first, from clamped in-bounds addresses, so their loads are in
+  // flight during the products instead of one after another in the epilogue
+  T ov[NTI][4];
+  if (beta != 0.0) {
+#pragma unroll
+    for (int t = 0; t < NTI; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = min(rbase + 16 * w + 4 * v + lk, rend - 1);
+        const int c = min(c0 + 16 * t + li, ncols - 1);
+        ov[t][v] = Out[r * ldo + c];
+      }
+  }
   constexpr int PX = 64 * TS_K / 256, PM = (TS_K * NC + 255) / 256;
   for (int k0 = 0; k0 < K; k0 += TS_K) {
     // every load of the batch is issued (in-bounds addresses) before the LDS stores, zero outside
@@ -231,7 +244,7 @@ __global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* __restric
       const int c = c0 + 16 * t + li;
       if (r < rend && c < ncols) {
         double y = gamma * acc[t][v];
-        if (beta != 0.0) y += beta * double(Out[r * ldo + c]);
+        if (beta != 0.0) y += beta * double(ov[t][v]);
         Out[r * ldo + c] = T(y);
       }
     }
