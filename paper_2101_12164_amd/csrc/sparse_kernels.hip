@@ -380,7 +380,7 @@ struct Outs {
   double *L1, *L2, *LJ;
   const int *nt1, *nt2, *nbt1, *nbt2, *ntJ;
   const int64_t *foff1, *foff2, *foffJ;
-  int *bw1, *bw2;  // counting pass: element half-bandwidth of every diagonal block
+  int *bw1, *bw2;  // counting pass: element half-bandwidth of every padded row's block row (row r: largest r - c)
 };
 
 // One thread per row.  FILL = false: count entries per CSR row and find the
@@ -478,11 +478,9 @@ __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int3
     }
   }
   if (!FILL) {
-    // thousands of rows share a block's counter: only values above the one already stored need the atomic
-    if (bw > 0) {
-      if (pi >= 0 && bw > o.bw1[pi]) atomicMax(o.bw1 + pi, bw);
-      if (pi <= -2 && bw > o.bw2[-2 - pi]) atomicMax(o.bw2 + (-2 - pi), bw);
-    }
+    // per row (thousands of rows share a block: a per-block atomic maximum is a hot spot); k_block_max reduces
+    if (pi >= 0) o.bw1[rowIG] = bw;
+    if (pi <= -2) o.bw2[rowsJ] = bw;
     if (pi >= 0) {
       o.pIG[rowIG + 1] = nIG;
     } else {
@@ -492,6 +490,29 @@ __global__ void k_extract(int64_t n, const int64_t* __restrict__ ptr, const int3
       if (pi == -1) o.pJs[rowJs + 1] = nJs;
     }
   }
+}
+
+// Element half-bandwidth of every diagonal block of the two levels: the largest of its rows' values.
+__global__ __launch_bounds__(256) void k_block_max(int nb1, const int64_t* __restrict__ roff1,
+                                                   const int* __restrict__ rows1, const int* __restrict__ rbw1,
+                                                   const int64_t* __restrict__ roff2, const int* __restrict__ rows2,
+                                                   const int* __restrict__ rbw2, int* __restrict__ out) {
+  __shared__ int red[256];
+  const int b = blockIdx.x;
+  const bool l1 = b < nb1;
+  const int bb = l1 ? b : b - nb1;
+  const int64_t r0 = l1 ? roff1[bb] : roff2[bb];
+  const int cnt = l1 ? rows1[bb] : rows2[bb];
+  const int* src = l1 ? rbw1 : rbw2;
+  int m = 0;
+  for (int r = threadIdx.x; r < cnt; r += 256) m = max(m, src[r0 + r]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b] = red[0];
 }
 
 // Identity on the padded diagonal of every block.
@@ -721,13 +742,19 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
   o.pGG = h.AGG.ptr;
   o.psJ = h.AsJ.ptr;
   o.pJs = h.AJs.ptr;
-  DBuf<int> bwd;
+  DBuf<int> bwd, rbw;
   bwd.alloc(h.nsub + h.nl2 + 1);
+  rbw.alloc(nIpad + n2pad + 1);
   NS_HIP(hipMemsetAsync(bwd.p, 0, bwd.n * sizeof(int), st));
-  o.bw1 = bwd.p;
-  o.bw2 = bwd.p + h.nsub;
+  NS_HIP(hipMemsetAsync(rbw.p, 0, rbw.n * sizeof(int), st));
+  o.bw1 = rbw.p;
+  o.bw2 = rbw.p + nIpad;
   k_extract<false><<<gn, 256, 0, st>>>(n, row_ptr, col, val, m, o, flags);
   NS_LAUNCH_CHECK();
+  if (h.nsub + h.nl2 > 0) {
+    k_block_max<<<h.nsub + h.nl2, 256, 0, st>>>(h.nsub, h.L1.roff, h.L1.nb, o.bw1, h.L2.roff, h.L2.nb, o.bw2, bwd);
+    NS_LAUNCH_CHECK();
+  }
   std::vector<int> bwh(bwd.n);
   NS_HIP(hipMemcpyAsync(bwh.data(), bwd.p, bwd.n * sizeof(int), hipMemcpyDeviceToHost, st));
   NS_HIP(hipMemcpyAsync(h.hflags, flags, 8 * sizeof(int), hipMemcpyDeviceToHost, st));
