@@ -216,9 +216,11 @@ namespace {
 
 // ----------------------------------------------------------------- extraction
 
-__global__ void k_validate(int64_t n, int64_t nnz, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                           const double* __restrict__ val, const int32_t* __restrict__ part, int* flags,
-                           int* minmax) {
+__global__ __launch_bounds__(256) void k_validate(int64_t n, int64_t nnz, const int64_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                  const int32_t* __restrict__ part, int* flags,
+                                                  int* __restrict__ wg_minmax) {
+  __shared__ int smax[4], smin[4];
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   int pmax = INT32_MIN, pmin = INT32_MAX;
   if (i < n) {
@@ -227,25 +229,67 @@ __global__ void k_validate(int64_t n, int64_t nnz, const int64_t* __restrict__ p
     if (e1 < e0 || e0 < 0 || e1 > nnz) {
       flags[F_STRUCT] = 1;
     } else {
-      for (int64_t e = e0; e < e1; ++e) {
-        const int32_t j = col[e];
-        if (j < 0 || j >= n) flags[F_STRUCT] = 1;
-        const double v = val[e];
-        if (!(v == v) || v - v != 0.0) flags[F_NAN] = 1;
+      bool bad_idx = false, bad_val = false;
+      for (int64_t e = e0; e < e1; e += 4) {  // four entries' loads in flight together (clamped positions)
+        int32_t j[4];
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int64_t ek = e + k < e1 ? e + k : e;
+          j[k] = col[ek];
+          v[k] = val[ek];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          bad_idx |= j[k] < 0 || j[k] >= n;
+          bad_val |= !(v[k] == v[k]) || v[k] - v[k] != 0.0;
+        }
       }
+      if (bad_idx) flags[F_STRUCT] = 1;
+      if (bad_val) flags[F_NAN] = 1;
     }
     pmax = pmin = part[i];
   }
-  // label range: wave-wide max / min first, one atomic per wave (all lanes reach the shuffles)
+  // label range: wave-wide max / min, then the workgroup's, written per workgroup (k_minmax_final reduces)
   for (int o = 32; o > 0; o >>= 1) {
     pmax = max(pmax, __shfl_xor(pmax, o));
     pmin = min(pmin, __shfl_xor(pmin, o));
   }
   if ((threadIdx.x & 63) == 0) {
-    if (pmax != INT32_MIN) atomicMax(&minmax[0], pmax);
-    if (pmin != INT32_MAX) atomicMin(&minmax[1], pmin);
+    smax[threadIdx.x >> 6] = pmax;
+    smin[threadIdx.x >> 6] = pmin;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    wg_minmax[2 * blockIdx.x] = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
+    wg_minmax[2 * blockIdx.x + 1] = min(min(smin[0], smin[1]), min(smin[2], smin[3]));
   }
 }
+
+__global__ __launch_bounds__(1024) void k_minmax_final(int nwg, const int* __restrict__ wg_minmax,
+                                                       int* __restrict__ minmax) {
+  __shared__ int smax[1024], smin[1024];
+  int pmax = INT32_MIN, pmin = INT32_MAX;
+  for (int b = threadIdx.x; b < nwg; b += 1024) {
+    pmax = max(pmax, wg_minmax[2 * b]);
+    pmin = min(pmin, wg_minmax[2 * b + 1]);
+  }
+  smax[threadIdx.x] = pmax;
+  smin[threadIdx.x] = pmin;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + o]);
+      smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    minmax[0] = smax[0];
+    minmax[1] = smin[0];
+  }
+}
+
 
 // Every stored (i, j, v) must have its mirror (j, i, v).
 __global__ void k_symcheck(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
@@ -306,10 +350,17 @@ __global__ void k_chunk_offsets(int nchunk, int G, int32_t* __restrict__ cnt, in
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   int run = 0;
-  for (int c = 0; c < nchunk; ++c) {
-    const int v = cnt[int64_t(c) * G + g];
-    cnt[int64_t(c) * G + g] = run;
-    run += v;
+  constexpr int B = 16;  // chunks per batch: their loads are issued together
+  for (int c0 = 0; c0 < nchunk; c0 += B) {
+    int v[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) v[k] = cnt[int64_t(min(c0 + k, nchunk - 1)) * G + g];  // clamped, in bounds
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (c0 + k < nchunk) {
+        cnt[int64_t(c0 + k) * G + g] = run;
+        run += v[k];
+      }
   }
   const int d = g < nsub ? d0 + g : (g < nsub + nl2 ? d1 + g - nsub : d2);
   if (d >= 0) total[d] = run;
@@ -603,12 +654,12 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
   h.n = n;
   h.nnz = nnz;
   int* flags = h.dflags.p;
-  DBuf<int> minmax;
-  minmax.alloc(2);
-  const int hm[2] = {INT32_MIN, INT32_MAX};
-  upload(minmax.p, hm, sizeof(hm), st);
   const int gn = int((n + 255) / 256);
-  k_validate<<<gn, 256, 0, st>>>(n, nnz, row_ptr, col, val, part, flags, minmax);
+  DBuf<int> minmax;
+  minmax.alloc(2 + 2 * int64_t(gn));
+  k_validate<<<gn, 256, 0, st>>>(n, nnz, row_ptr, col, val, part, flags, minmax.p + 2);
+  NS_LAUNCH_CHECK();
+  k_minmax_final<<<1, 1024, 0, st>>>(gn, minmax.p + 2, minmax.p);
   NS_LAUNCH_CHECK();
   int mm[2];
   NS_HIP(hipMemcpyAsync(mm, minmax.p, sizeof(mm), hipMemcpyDeviceToHost, st));
