@@ -100,7 +100,15 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const int* __restrict__ mt, 
   const int m = mt[b];
   const double* p = part + pboff[b] + int64_t(i / ST) * m * ST + i % ST;
   double acc = 0.0;
-  for (int t = 0; t < m; ++t) acc += p[int64_t(t) * ST];
+  constexpr int U = 8;  // partials per batch: their loads are issued together (clamped), then summed in order
+  for (int t0 = 0; t0 < m; t0 += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = p[int64_t(min(t0 + u, m - 1)) * ST];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (t0 + u < m) acc += v[u];
+  }
   y[xoff[b] + i] = acc;
 }
 
