@@ -35,9 +35,17 @@ __global__ __launch_bounds__(256) void k_sym_pack(const int* __restrict__ mt, co
   const double* a = src + soff[b];
   const int64_t ld = sld[b];
   double* t = tiles + (toff[b] + u) * int64_t(ST * ST);
-  for (int e = threadIdx.x; e < ST * ST; e += 256) {
-    const int r = ST * ti + e / ST, c = ST * tj + e % ST;
-    t[e] = (r < n && c < n) ? a[int64_t(r) * ld + c] : 0.0;
+  // all sixteen loads of a thread in flight together (clamped in-bounds addresses, zero outside the block)
+  double v[ST * ST / 256];
+#pragma unroll
+  for (int q = 0; q < ST * ST / 256; ++q) {
+    const int e = threadIdx.x + 256 * q, r = ST * ti + e / ST, c = ST * tj + e % ST;
+    v[q] = a[int64_t(min(r, n - 1)) * ld + min(c, n - 1)];
+  }
+#pragma unroll
+  for (int q = 0; q < ST * ST / 256; ++q) {
+    const int e = threadIdx.x + 256 * q, r = ST * ti + e / ST, c = ST * tj + e % ST;
+    t[e] = (r < n && c < n) ? v[q] : 0.0;
   }
 }
 
