@@ -449,7 +449,8 @@ __device__ __forceinline__ int syrk_frag(int r, int k) {  // operand element (ro
 }
 template <int KC>
 __global__ __launch_bounds__(256) void k_syrk64(GemmBatch g, const double* __restrict__ W, double* __restrict__ C,
-                                                int gx, int nb) {
+                                                int gx, int nb, float* __restrict__ C32, double* __restrict__ P,
+                                                const int64_t* __restrict__ ptoff) {
   __shared__ __align__(16) double sA[KC * 64];
   __shared__ __align__(16) double sB[KC * 64];
   const int tiles = gx * gx;
@@ -523,7 +524,10 @@ __global__ __launch_bounds__(256) void k_syrk64(GemmBatch g, const double* __res
       acc[1][1] = MFL<double>::mma(a.y, b.y, acc[1][1]);
     }
   }
+  // outputs: C (both triangles), optionally its FP32 copy and the packed lower tile (row-major, zero beyond M)
   double* Cj = C + g.coff[j] * g.cscale;
+  float* Cj32 = C32 ? C32 + g.coff[j] * g.cscale : nullptr;
+  double* Pt = P ? P + (ptoff[j] + tm * (tm + 1) / 2 + tn) * int64_t(64 * 64) : nullptr;
   const int64_t ldc = g.ldc ? g.ldc[j] : g.ldc_s;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -531,12 +535,18 @@ __global__ __launch_bounds__(256) void k_syrk64(GemmBatch g, const double* __res
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = m0 + 32 * ha + 16 * x + MFL<double>::row(kq, v);
-        const int c = n0 + 32 * hb + 16 * y + rl;
-        if (r < M && c < M) {
+        const int rr = 32 * ha + 16 * x + MFL<double>::row(kq, v), cc = 32 * hb + 16 * y + rl;
+        const int r = m0 + rr, c = n0 + cc;
+        const bool in = r < M && c < M;
+        if (in) {
           Cj[int64_t(r) * ldc + c] = acc[x][y][v];
           if (tm != tn) Cj[int64_t(c) * ldc + r] = acc[x][y][v];
+          if (Cj32) {
+            Cj32[int64_t(r) * ldc + c] = float(acc[x][y][v]);
+            if (tm != tn) Cj32[int64_t(c) * ldc + r] = float(acc[x][y][v]);
+          }
         }
+        if (Pt) Pt[rr * 64 + cc] = in ? acc[x][y][v] : 0.0;
       }
 }
 
@@ -579,10 +589,6 @@ __global__ void k_contrib_sort(int64_t nG, const int64_t* __restrict__ ptr, int3
   }
 }
 
-__global__ void k_to_fp32_ls(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-    b[i] = float(a[i]);
-}
 
 template <class T, int TPR>
 __global__ __launch_bounds__(256) void k_schur_epi_local(int64_t nrows, const int64_t* __restrict__ pG,
@@ -833,6 +839,9 @@ void local_schur_form(Handle& h) {
   }
   DBuf<double> W;
   W.alloc(wmax > 0 ? wmax : 1);
+  // the product also writes the FP32 copy of S_j and the packed lower tiles of the single-column applies
+  if (h.prec_inner) ls.S32.alloc(ls.S64.n);
+  sym_layout(ls.sym, ls.h_m, ls.goff.p, st);
   // sparse right-hand sides: the sweep builds each tile row of B_j from the column entries, so W is neither
   // cleared nor filled (rows above a chunk's first tile are never read)
   const bool sparse = pl.sparse_rhs && tile_sparse_rhs_ok(lv);
@@ -890,14 +899,11 @@ void local_schur_form(Handle& h) {
     KScope ks(KF_LS_FORM, st, double(rows) * ldw * 8.0, 0.0);
     if (ls.max_m > 0) {
       const int tilesM = (ls.max_m + 63) / 64;
-      k_syrk64<32><<<gemm_grid(tilesM, tilesM, nbs, g.plen), 256, 0, st>>>(g, W.p, ls.S64.p, tilesM, nbs);
+      k_syrk64<32><<<gemm_grid(tilesM, tilesM, nbs, g.plen), 256, 0, st>>>(
+          g, W.p, ls.S64.p, tilesM, nbs, h.prec_inner ? ls.S32.p : nullptr, ls.sym.built() ? ls.sym.tiles.p : nullptr,
+          ls.sym.built() ? ls.sym.toff.p + b0 : nullptr);
       NS_LAUNCH_CHECK();
     }
-  }
-  if (h.prec_inner) {
-    ls.S32.alloc(ls.S64.n);
-    k_to_fp32_ls<<<2048, 256, 0, st>>>(ls.S64, ls.S32, ls.S64.n);
-    NS_LAUNCH_CHECK();
   }
   // contributor CSR (interface row -> stacked positions), values 1
   Csr& C = ls.contrib;
@@ -951,7 +957,6 @@ void local_schur_form(Handle& h) {
     ls.alg_bytes += double(ls.h_m[j]) * ls.h_m[j];
     ls.alg_flops += 2.0 * ls.h_m[j] * ls.h_m[j];
   }
-  sym_pack(ls.sym, ls.h_m, ls.S64.p, ls.soff.p, ls.sld.p, ls.goff.p, st);
   ls.built = true;
   pl.rblk.release();
   pl.cidx.release();

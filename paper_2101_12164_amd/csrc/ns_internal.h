@@ -155,6 +155,9 @@ struct SymPacked {
 // Pack block b of src (dim_b x dim_b at src + src_off[b], leading dimension src_ld[b]; device arrays).
 void sym_pack(SymPacked& sp, const std::vector<int>& dims, const double* src, const int64_t* src_off,
               const int64_t* src_ld, const int64_t* xoff, hipStream_t st);
+// The layout and storage of sym_pack without filling the tiles (a producer writes them: tile (ti, tj) of block b,
+// row-major, at tile index toff_b + ti (ti + 1) / 2 + tj, zero beyond dim_b).
+void sym_layout(SymPacked& sp, const std::vector<int>& dims, const int64_t* xoff, hipStream_t st);
 // y_b = A_b x_b for every block (one column).
 // y = S x per block; block b's vector is x[xoff_b ..], or with xidx gathered as x[xidx[xoff_b + r]] (-1: 0).
 void sym_gemv(const SymPacked& sp, const double* x, double* y, hipStream_t st, const int32_t* xidx = nullptr);

@@ -122,8 +122,7 @@ __global__ __launch_bounds__(256) void k_sym_reduce(const int* __restrict__ mt, 
 
 }  // namespace
 
-void sym_pack(SymPacked& sp, const std::vector<int>& dims, const double* src, const int64_t* src_off,
-              const int64_t* src_ld, const int64_t* xoff, hipStream_t st) {
+void sym_layout(SymPacked& sp, const std::vector<int>& dims, const int64_t* xoff, hipStream_t st) {
   const int nb = int(dims.size());
   sp.nblk = nb;
   sp.xoff = xoff;
@@ -158,8 +157,14 @@ void sym_pack(SymPacked& sp, const std::vector<int>& dims, const double* src, co
   upload(sp.pboff.p, hpb.data(), nb * sizeof(int64_t), st);
   sp.tiles.alloc(size_t(tt) * ST * ST);
   sp.part.alloc(size_t(pp));
-  k_sym_pack<<<dim3(unsigned(sp.max_tiles), unsigned(nb)), 256, 0, st>>>(sp.mt, sp.dim, sp.toff, src, src_off, src_ld,
-                                                                         sp.tiles);
+}
+
+void sym_pack(SymPacked& sp, const std::vector<int>& dims, const double* src, const int64_t* src_off,
+              const int64_t* src_ld, const int64_t* xoff, hipStream_t st) {
+  sym_layout(sp, dims, xoff, st);
+  if (sp.nblk == 0 || sp.total_tiles == 0) return;
+  k_sym_pack<<<dim3(unsigned(sp.max_tiles), unsigned(sp.nblk)), 256, 0, st>>>(sp.mt, sp.dim, sp.toff, src, src_off,
+                                                                              src_ld, sp.tiles);
   NS_LAUNCH_CHECK();
 }
 
