@@ -713,11 +713,19 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
   // interior factorisation and the local Schur formation: they run on a second stream, joined before the pivot
   // check, so the two latency-bound chains fill the device together.
   if (!h->aux) NS_HIP(hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking));
-  Event fork, join;
+  Event fork, join, l1done, planned;
   NS_HIP(hipEventRecord(fork.e, h->stream));
   NS_HIP(hipStreamWaitEvent(h->aux, fork.e, 0));
+  // the interior factorisation is queued first; the symbolic part of the local Schur formation (which reads
+  // sizes back) then runs on the second stream while the host waits and the device factorises, and the
+  // interface levels follow it there (they overlap the formation's start: measured faster overall than
+  // finishing them before the formation, whose event-timed launches then share the device)
+  tile_cholesky(h->L1, h->dflags.p + CHOL_FLAGS, h->stream);
+  NS_HIP(hipEventRecord(l1done.e, h->stream));
   {
     StreamSwap sw(*h, h->aux);
+    if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_plan(*h);
+    NS_HIP(hipEventRecord(planned.e, h->stream));
     tile_cholesky(h->L2, h->dflags.p + CHOL_FLAGS + 3, h->stream);
     assemble_junction(*h);
     tile_cholesky(h->LJ, h->dflags.p + CHOL_FLAGS + 6, h->stream);
@@ -730,13 +738,21 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
     }
     NS_HIP(hipEventRecord(join.e, h->stream));
   }
-  // the symbolic part of the local Schur formation reads sizes back: done before the interior factorisation is
-  // queued, so that wait finds the stream idle
-  if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_plan(*h);
-  tile_cholesky(h->L1, h->dflags.p + CHOL_FLAGS, h->stream);
+  NS_HIP(hipStreamWaitEvent(h->stream, planned.e, 0));  // the plan's last uploads and sorts
   if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_form(*h);
-  if (trsv1_supported_size(h->L1)) tile_make_transposed(h->L1, h->stream);
   if (h->prec_inner && !h->LS.built) tile_make_fp32(h->L1, h->stream);
+  // the tile-transposed interior factor is only read by the solve's single-column backward sweeps: it is made
+  // on the second stream while this one runs the inner solve (after the formation, so the two do not share the
+  // device), and joined at the end of the setup
+  Event formed, transposed;
+  NS_HIP(hipEventRecord(formed.e, h->stream));
+  {
+    StreamSwap sw(*h, h->aux);
+    NS_HIP(hipStreamWaitEvent(h->stream, l1done.e, 0));
+    NS_HIP(hipStreamWaitEvent(h->stream, formed.e, 0));
+    if (trsv1_supported_size(h->L1)) tile_make_transposed(h->L1, h->stream);
+    NS_HIP(hipEventRecord(transposed.e, h->stream));
+  }
   NS_HIP(hipStreamWaitEvent(h->stream, join.e, 0));
   check_chol(*h, info);
   ev.rec(2);
@@ -787,6 +803,7 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
     NS_HIP(hipMemsetAsync(h->keff_d.p, 0, np * sizeof(int), h->stream));
     ev.rec(3);
   }
+  NS_HIP(hipStreamWaitEvent(h->stream, transposed.e, 0));
   ev.rec(4);
   NS_HIP(hipStreamSynchronize(h->stream));
   if (info) {
