@@ -60,8 +60,8 @@ def sampled_schur_rows(d, x, rows):
             a, b = int(bp[j]), int(bp[j + 1])
             if j not in sols:
                 sols[j] = sla.cho_solve((sla.cholesky(d.block(int(j)).toarray(), lower=True), True), v[a:b])
-            w += float(row[:, a:b] @ sols[j])
-        ag = float(d.A_G[g] @ x)
+            w += float((row[:, a:b] @ sols[j])[0])
+        ag = float((d.A_G[g] @ x)[0])
         out.append(ag - w)
         scale.append(abs(ag) + abs(w))
     return np.array(out), np.array(scale)
