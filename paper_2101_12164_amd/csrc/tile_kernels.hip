@@ -567,7 +567,7 @@ struct SweepTile {
 };
 
 template <int NBT, bool SPB>
-__global__ __launch_bounds__(256) void k_trsm_fwd_reg(int nblk, const int* __restrict__ nt_arr,
+__device__ __forceinline__ void trsm_fwd_reg(int nblk, const int* __restrict__ nt_arr,
                                                       const int* __restrict__ nbt_arr,
                                                       const int64_t* __restrict__ foff,
                                                       const int64_t* __restrict__ ioff,
@@ -729,6 +729,35 @@ __global__ __launch_bounds__(256) void k_trsm_fwd_reg(int nblk, const int* __res
   }
 }
 
+template <int NBT, bool SPB>
+__global__ __launch_bounds__(256) void k_trsm_fwd_reg(int nblk, const int* __restrict__ nt_arr,
+                                                      const int* __restrict__ nbt_arr,
+                                                      const int64_t* __restrict__ foff,
+                                                      const int64_t* __restrict__ ioff,
+                                                      const int64_t* __restrict__ roff, const double* __restrict__ L,
+                                                      const double* __restrict__ Linv, double* __restrict__ B,
+                                                      int64_t ldb, int ncols, const int* __restrict__ ncols_blk,
+                                                      const int* __restrict__ first_tile, int nchunk_all,
+                                                      int64_t row0, SparseRhs sp) {
+  trsm_fwd_reg<NBT, SPB>(nblk, nt_arr, nbt_arr, foff, ioff, roff, L, Linv, B, ldb, ncols, ncols_blk, first_tile,
+                         nchunk_all, row0, sp);
+}
+// two-tile ring, compiled for two waves per SIMD (the narrow bands of two-dimensional subdomains)
+template <bool SPB>
+__global__ __launch_bounds__(256, 2) void k_trsm_fwd_reg2(int nblk, const int* __restrict__ nt_arr,
+                                                          const int* __restrict__ nbt_arr,
+                                                          const int64_t* __restrict__ foff,
+                                                          const int64_t* __restrict__ ioff,
+                                                          const int64_t* __restrict__ roff,
+                                                          const double* __restrict__ L,
+                                                          const double* __restrict__ Linv, double* __restrict__ B,
+                                                          int64_t ldb, int ncols, const int* __restrict__ ncols_blk,
+                                                          const int* __restrict__ first_tile, int nchunk_all,
+                                                          int64_t row0, SparseRhs sp) {
+  trsm_fwd_reg<2, SPB>(nblk, nt_arr, nbt_arr, foff, ioff, roff, L, Linv, B, ldb, ncols, ncols_blk, first_tile,
+                       nchunk_all, row0, sp);
+}
+
 __global__ void k_tile_export(int nt, int nbt, int nb, const double* __restrict__ Lb, double* __restrict__ out) {
   const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= int64_t(nb) * nb) return;
@@ -765,12 +794,25 @@ void launch_trsm(const TileLevel& lv, T* B, int64_t ldb, int ncols, const T* L, 
   }
 }
 
-// the register-ring sweep holds REG_NBT solved tiles per wave
+// the register-ring sweep holds REG_NBT solved tiles per wave (a ring of 2 when every band of the launch is
+// that narrow: fewer registers, two waves per SIMD)
 constexpr int REG_NBT = 4;
-bool reg_sweep_ok(const TileLevel& lv, int b0, int b1) {
-  for (int b = b0; b < b1; ++b)
-    if (lv.h_nbt[b] > REG_NBT) return false;
-  return true;
+int max_nbt_of(const TileLevel& lv, int b0, int b1) {
+  int m = 0;
+  for (int b = b0; b < b1; ++b) m = std::max(m, lv.h_nbt[b]);
+  return m;
+}
+bool reg_sweep_ok(const TileLevel& lv, int b0, int b1) { return max_nbt_of(lv, b0, b1) <= REG_NBT; }
+template <bool SPB>
+void launch_fwd_reg(int ring, int grid, hipStream_t st, int nblk, const int* nt, const int* nbt, const int64_t* foff,
+                    const int64_t* ioff, const int64_t* roff, const double* L, const double* Li, double* B,
+                    int64_t ldb, int ncols, const int* nc, const int* ft, int nchunk_all, int64_t row0, SparseRhs sp) {
+  if (ring <= 2)
+    k_trsm_fwd_reg2<SPB><<<grid, 256, 0, st>>>(nblk, nt, nbt, foff, ioff, roff, L, Li, B, ldb, ncols, nc, ft,
+                                               nchunk_all, row0, sp);
+  else
+    k_trsm_fwd_reg<REG_NBT, SPB><<<grid, 256, 0, st>>>(nblk, nt, nbt, foff, ioff, roff, L, Li, B, ldb, ncols, nc,
+                                                       ft, nchunk_all, row0, sp);
 }
 
 }  // namespace
@@ -878,14 +920,13 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
   const int grid = nbp8 * 8 * nchunk_all;
   if constexpr (sizeof(T) == 8) {
     if (cw == 64 && reg_sweep_ok(lv, b0, b1)) {
+      const int ring = max_nbt_of(lv, b0, b1);
       if (sparse)
-        k_trsm_fwd_reg<REG_NBT, true><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0,
-                                                            lv.ioff + b0, lv.roff + b0, L, Li, B, ldb, ncols, nc,
-                                                            ft, nchunk_all, row0, *sparse);
+        launch_fwd_reg<true>(ring, grid, st, nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0, lv.ioff + b0, lv.roff + b0,
+                             L, Li, B, ldb, ncols, nc, ft, nchunk_all, row0, *sparse);
       else
-        k_trsm_fwd_reg<REG_NBT, false><<<grid, 256, 0, st>>>(nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0,
-                                                             lv.ioff + b0, lv.roff + b0, L, Li, B, ldb, ncols, nc,
-                                                             ft, nchunk_all, row0, SparseRhs{});
+        launch_fwd_reg<false>(ring, grid, st, nblk, lv.nt + b0, lv.nbt + b0, lv.foff + b0, lv.ioff + b0,
+                              lv.roff + b0, L, Li, B, ldb, ncols, nc, ft, nchunk_all, row0, SparseRhs{});
       NS_LAUNCH_CHECK();
       return;
     }
@@ -913,9 +954,8 @@ void tile_solve_chunks(const TileLevel& lv, double* B, int64_t ldb, int ncols, c
   {
     KScope ks(fam, st, bytes, lv.alg_sq * ncols);
     if (reg_sweep_ok(lv, 0, lv.nblk))
-      k_trsm_fwd_reg<REG_NBT, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff,
-                                                           lv.L64, lv.Linv64, B, ldb, ncols, nullptr, first_tile,
-                                                           nchunk, 0, SparseRhs{});
+      launch_fwd_reg<false>(max_nbt_of(lv, 0, lv.nblk), grid, st, lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff,
+                            lv.L64, lv.Linv64, B, ldb, ncols, nullptr, first_tile, nchunk, 0, SparseRhs{});
     else
       k_trsm<double, TILE, true><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, lv.L64,
                                                        lv.Linv64, B, ldb, ncols, nullptr, first_tile, nchunk);
