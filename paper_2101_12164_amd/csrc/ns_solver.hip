@@ -143,9 +143,17 @@ __global__ void k_bcg_check(int np, int s, const double* __restrict__ colsq, con
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np || !active[p]) return;
   double m = 0.0;
-  for (int j = 0; j < s; ++j) {
-    const double f = nF2[p * s + j];
-    if (f > 0.0) m = fmax(m, sqrt(colsq[p * s + j] / f));
+  for (int j0 = 0; j0 < s; j0 += 8) {  // eight columns' loads in flight together (clamped, in bounds)
+    double f[8], c[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int j = min(j0 + k, s - 1);
+      f[k] = nF2[p * s + j];
+      c[k] = colsq[p * s + j];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (j0 + k < s && f[k] > 0.0) m = fmax(m, sqrt(c[k] / f[k]));
   }
   relres[p] = m;
   itp[p] = it;
