@@ -136,22 +136,27 @@ __global__ __launch_bounds__(256) void k_bgemm(int M, int N, int K, const uint16
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
   const int am = m0 + li;
+  // operands are loaded unconditionally from clamped in-bounds positions and zeroed afterwards, so the twenty
+  // loads of a k-step are in flight together (a load under a per-lane condition waits behind its own branch)
+  const int amc = min(am, M - 1);
   for (int k0 = kb; k0 < ke; k0 += 16) {
-    s4 a;
+    uint16_t av[4], bv[4][4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const int k = k0 + lk + t;
-      a[t] = (am < M && k < ke) ? short(A[int64_t(am) * sam + int64_t(k) * sak]) : short(0);
+      const int kc = min(k0 + lk + t, ke - 1);
+      av[t] = A[int64_t(amc) * sam + int64_t(kc) * sak];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[q][t] = B[int64_t(kc) * sbk + int64_t(min(n0 + 16 * q + li, N - 1)) * sbn];
     }
+    s4 a;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a[t] = (am < M && k0 + lk + t < ke) ? short(av[t]) : short(0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int bn = n0 + 16 * q + li;
       s4 b;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int k = k0 + lk + t;
-        b[t] = (bn < N && k < ke) ? short(B[int64_t(k) * sbk + int64_t(bn) * sbn]) : short(0);
-      }
+      for (int t = 0; t < 4; ++t) b[t] = (bn < N && k0 + lk + t < ke) ? short(bv[q][t]) : short(0);
       acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
     }
   }
