@@ -204,15 +204,28 @@ __global__ __launch_bounds__(256) void k_fgemm(int M, int N, int K, const TA* __
   f4 acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-  const int am = m0 + li;
-  for (int k0 = kb; k0 < ke; k0 += 4) {
-    const int k = k0 + lk;
-    const float a = (am < M && k < ke) ? ldf(A, int64_t(am) * sam + int64_t(k) * sak) : 0.f;
+  const int am = m0 + li, amc = min(am, M - 1);
+  // four k-steps per batch, every operand loaded unconditionally from a clamped in-bounds position (zeroed
+  // afterwards), so the twenty loads of a batch are in flight together
+  constexpr int U = 4;
+  for (int k0 = kb; k0 < ke; k0 += 4 * U) {
+    float av[U], bv[U][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int bn = n0 + 16 * q + li;
-      const float b = (bn < N && k < ke) ? ldf(B, int64_t(k) * sbk + int64_t(bn) * sbn) : 0.f;
-      acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
+    for (int u = 0; u < U; ++u) {
+      const int kc = min(k0 + 4 * u + lk, ke - 1);
+      av[u] = ldf(A, int64_t(amc) * sam + int64_t(kc) * sak);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) bv[u][q] = ldf(B, int64_t(kc) * sbk + int64_t(min(n0 + 16 * q + li, N - 1)) * sbn);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool kin = k0 + 4 * u + lk < ke;
+      const float a = (am < M && kin) ? av[u] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float b = (n0 + 16 * q + li < N && kin) ? bv[u][q] : 0.f;
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
