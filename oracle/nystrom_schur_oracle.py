@@ -203,7 +203,7 @@ def _col_relres(R, nF):
     return float(rel.max()) if rel.size else 0.0
 
 
-def bf_bpcg(Sop: Callable, Mop: Callable, F, tol: float, maxit: int, delta: float = 1e-8) -> BCGResult:
+def bf_bpcg(Sop: Callable, Mop: Callable, F, tol: float, maxit: int, delta: float = 1e-6) -> BCGResult:
     """Block PCG for S X = F with preconditioner M, from X_0 = 0.
 
     P_0 = orth(M R_0); per iteration Q = S P, Delta = P^T Q,

@@ -77,6 +77,29 @@ def pins_pass(m):
     # 6. full solve reaches the true residual
     sr = o.solve(Q.b(), tol=1e-8)
     ok.append(sr.relres_true <= 1e-8 and sr.relres_schur_true <= 2e-8)
+    # 7. adapted deflation: the start leaves a residual orthogonal to span(Z), and M S has the eigenvalue 1
+    #    k times plus the nonzero spectrum of the deflated operator in A_Gamma = R^T R coordinates
+    oa = m.NystromSchurOracle(Q.n, Q.row_ptr, Q.col, Q.val, Q.part, k=4, p=3, omega=Q.omega(), apply_mode="ADEF2")
+    oa.setup()
+    fa = oa.reduce_rhs(Q.b())
+    w0 = oa.initial_guess(fa)
+    ok.append(w0 is not None and np.linalg.norm(oa.Z.T @ (fa - oa.ops.S(w0))) <= 1e-11 * np.linalg.norm(oa.Z.T @ fa))
+    Rg = np.linalg.cholesky(d2.A_G.toarray()).T
+    Ah = np.linalg.inv(Rg).T @ S @ np.linalg.inv(Rg)
+    Zh = Rg @ oa.Z
+    PD = np.eye(ng) - Ah @ Zh @ np.linalg.solve(Zh.T @ Ah @ Zh, Zh.T)
+    mu = np.sort(np.linalg.eigvals(PD @ Ah).real)[4:]
+    ev = np.sort(np.linalg.eigvals(oa.apply(np.eye(ng)) @ S).real)
+    ok.append(np.allclose(ev, np.sort(np.concatenate([np.ones(4), mu])), rtol=1e-7, atol=1e-9))
+    # 8. Nystrom eigenvalues never exceed the exact eigenvalues of B = A_G (A^{-1})_GG A_G - A_G
+    Ainv2 = np.linalg.inv(Q.csr().toarray())
+    AG2 = d2.A_G.toarray()
+    Bx = AG2 @ Ainv2[np.ix_(d2.G, d2.G)] @ AG2 - AG2
+    sig = np.sort(np.linalg.eigvalsh(0.5 * (Bx + Bx.T)))[::-1]
+    ox = m.NystromSchurOracle(Q.n, Q.row_ptr, Q.col, Q.val, Q.part, k=4, p=3, omega=Q.omega(), tol_inner=1e-14)
+    sx = ox.setup()
+    ok.append(sx.Sigma.size == 4 and bool(np.all(sx.Sigma <= sig[:4] * (1 + 1e-9)))
+              and bool(np.all(sx.Sigma >= 0.5 * sig[:4])))
     return all(ok), ok
 
 
@@ -99,6 +122,11 @@ MUTATIONS = {
                     "return b[d.G] + d.A_GI @ self.ops.solve_I(b[d.I])"),
     "backsub_drop": ("xI = ops.solve_I(b[d.I] - d.A_IG @ w)", "xI = ops.solve_I(b[d.I])"),
     "interior_order": ("order = np.lexsort((interior, part[interior]))", "order = np.lexsort((part[interior], interior))"),
+    "adef2_start_zero": ("return self.Z @ sla.cho_solve(self.E_cf, self.Z.T @ f)", "return None"),
+    "adef2_coarse_sign": ("Z.T @ r - self.SZ.T @ t", "Z.T @ r + self.SZ.T @ t"),
+    "adef2_E_without_S": ("E = self.Z.T @ self.SZ", "E = self.Z.T @ self.Z"),
+    "shifted_rhs_uses_AG": ("F = ops.W(Om)", "F = d.A_G @ Om"),
+    "Y_without_AG": ("Y = d.A_G @ res.X", "Y = res.X"),
 }
 
 
