@@ -154,14 +154,20 @@ void* dev_alloc(size_t bytes) {
   auto& idle = c.idle[dev];
   for (auto it = idle.lower_bound(size); it != idle.end() && it->first <= limit; ++it) {
     Block& b = it->second;
-    if (b.st == st || hipEventQuery(b.ev) == hipSuccess) {
+    bool ready = b.st == st;
+    if (!ready) {
+      // not-ready (and, inside a stream capture, "not permitted") come back as error codes: clear each one
+      // here, before a later launch check could report it
+      ready = hipEventQuery(b.ev) == hipSuccess;
+      if (!ready) (void)hipGetLastError();
+    }
+    if (ready) {
       Block blk = b;
       idle.erase(it);
       c.live[blk.p] = blk;
       return blk.p;
     }
   }
-  (void)hipGetLastError();  // hipEventQuery reports not-ready as an error code
   Block blk;
   blk.size = size;
   blk.dev = dev;

@@ -37,7 +37,12 @@ void hip_check(hipError_t e, const char* what, const char* file, int line);
 hipStream_t& alloc_stream();  // thread-local; the null stream outside a call
 struct StreamScope {
   hipStream_t prev;
-  explicit StreamScope(hipStream_t s) : prev(alloc_stream()) { alloc_stream() = s; }
+  // Every library call opens one: an error code left by an earlier call whose result was deliberately
+  // ignored (an event query) is cleared so that the launch checks of this call report only its own launches.
+  explicit StreamScope(hipStream_t s) : prev(alloc_stream()) {
+    alloc_stream() = s;
+    (void)hipGetLastError();
+  }
   ~StreamScope() { alloc_stream() = prev; }
   StreamScope(const StreamScope&) = delete;
   StreamScope& operator=(const StreamScope&) = delete;
