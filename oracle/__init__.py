@@ -20,6 +20,8 @@ from .nystrom_schur_oracle import (  # noqa: F401
     bf_bpcg,
     nystrom_core,
     NystromSchurOracle,
+    GammaFactor,
+    level2_order,
     pcg,
     dense_schur,
     ideal_s2,

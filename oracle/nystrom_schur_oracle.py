@@ -171,6 +171,47 @@ class Operators:
 
 
 # ----------------------------------------------------------------------------
+# a factor R_Gamma with A_Gamma = R_Gamma^T R_Gamma  (eq. cholesky), for the variant M_1
+
+
+def level2_order(d: DBBD):
+    """Interface positions in the order of the level-2 split of A_Gamma: the nodes of each separator block
+    (label -2 - b for block b; blocks in label order, nodes by interface index), then the junction nodes
+    (label -1) by interface index.  Without level-2 labels this is the interface order itself."""
+    pg = d.part[d.G]
+    blk = np.where(pg <= -2, -2 - pg, np.iinfo(np.int64).max)
+    return np.lexsort((np.arange(d.n_gamma), blk))
+
+
+class GammaFactor:
+    """R_Gamma = L^T P: L the Cholesky factor of A_Gamma with rows and columns in the level-2 order
+    (P x = x[perm]), so that A_Gamma = R^T R.  Any R with R^T R = A_Gamma serves the derivation of M_1; this
+    one is the factor the level-2 block LDL^T of A_Gamma defines.  Dense (small interfaces only)."""
+
+    def __init__(self, d: DBBD, max_dense: int = 8000):
+        if d.n_gamma > max_dense:
+            raise ValueError("GammaFactor: interface too large for a dense factor")
+        self.perm = level2_order(d)
+        AG = d.A_G.toarray()
+        self.L = sla.cholesky(AG[np.ix_(self.perm, self.perm)], lower=True)
+
+    def mult(self, X):
+        """R X = L^T (P X)."""
+        return self.L.T @ np.asarray(X)[self.perm]
+
+    def solve(self, Y):
+        """R^{-1} Y: L^T u = Y, then x[perm] = u."""
+        u = sla.solve_triangular(self.L, np.asarray(Y), lower=True, trans="T")
+        out = np.empty_like(u)
+        out[self.perm] = u
+        return out
+
+    def solve_t(self, Y):
+        """R^{-T} Y = L^{-1} (P Y)."""
+        return sla.solve_triangular(self.L, np.asarray(Y)[self.perm], lower=True)
+
+
+# ----------------------------------------------------------------------------
 # breakdown-free block PCG  (block CG of O'Leary with the rank-revealing
 # orthonormalisation of Ji & Li, the inner solver of the numerical section)
 
@@ -356,17 +397,24 @@ class SolveResult:
 class NystromSchurOracle:
     """Algorithm alg:prec1 plus the block LDL^T solve of eq. A_LDLT.
 
-    ``apply_mode``: 'M2' (eq. left_prec_mat, the preconditioner of the
-    experiments) or 'ADEF2' (adapted deflation built from Z, eqs.
-    adapted_deflation_prec and deflation_comp_from_low_rank).
-    ``inner``: 'shifted' (S_Gamma D = W Omega, preconditioned by A_Gamma^{-1})
-    or 'formA' (S_I X = A_IGamma Omega, preconditioned by A_I^{-1}, the
-    literal step 3).  ``k = 0`` gives the first-level preconditioner S_1.
+    ``variant`` picks the matrix Nystrom approximates and how Z is formed:
+      'M2': B = A_GammaI S_I^{-1} A_IGamma (eq. internal_term_lr_approximation_1),
+            Z = A_Gamma^{-1} U (eq. left_prec_mat, the preconditioner of the experiments);
+      'M1': R_Gamma^{-T} B R_Gamma^{-1} (eq. lr_approximation_S-1_A-I), Z = R_Gamma^{-1} U (eq. prec1S);
+      'M3': S_I^{-1} on the interior space (eq. internal_term_lr_approximation_2; the sketch ``omega`` is
+            then n_I x (k+p) in interior order), Z = A_Gamma^{-1} A_GammaI U (eq. left_prec_mat2).
+    ``apply_mode``: 'M2' -- the additive low-rank form A_Gamma^{-1} + Z Sigma Z^T of the variant (M_1, M_2
+    or M_3) -- or 'ADEF2' -- the adapted deflation built from the variant's Z (eqs. adapted_deflation_prec,
+    deflation_comp_from_low_rank, our_two_level_preconditioner: M_1A-DEF, M_2A-DEF, M_3A-DEF).
+    ``inner``: 'shifted' (systems with S_Gamma, preconditioned by A_Gamma^{-1}) or 'formA' (S_I X = F,
+    preconditioned by A_I^{-1}, the literal step 3).
+    ``power``: q of eq. power -- the sketch is B^q Omega, orthonormalised (QR) after every product with B.
+    ``k = 0`` gives the first-level preconditioner S_1.
     """
 
     def __init__(self, n, row_ptr, col, val, part, *, k, p, omega, tol_inner=0.1, eps_rel=1e-10, delta=1e-6,
                  maxit_inner=500, factor="dense", apply_mode="M2", inner="shifted", gamma_factor=None,
-                 proposal=None, accept_tol=0.2):
+                 proposal=None, accept_tol=0.2, variant="M2", power=0):
         self.dbbd = DBBD(n, row_ptr, col, val, part)
         self.ops = Operators(self.dbbd, factor=factor, gamma_factor=gamma_factor)
         self.k, self.p = int(k), int(p)
@@ -379,7 +427,14 @@ class NystromSchurOracle:
         self.inner = inner
         self.proposal = np.asarray(proposal, dtype=np.float64) if proposal is not None else None
         self.accept_tol = accept_tol
+        if variant not in ("M1", "M2", "M3"):
+            raise ValueError(variant)
+        if inner not in ("shifted", "formA"):
+            raise ValueError(inner)
+        self.variant = variant
+        self.power = int(power)
         self.setup_result: Optional[SetupResult] = None
+        self.Rg = GammaFactor(self.dbbd) if variant == "M1" and self.k > 0 else None
 
     # -- Algorithm alg:prec1 ------------------------------------------------
     def setup(self) -> SetupResult:
@@ -409,23 +464,51 @@ class NystromSchurOracle:
                                                 np.zeros((ng, 0)), True, rho)
                 self._post_setup()
                 return self.setup_result
-        Om = self.omega
-        if self.inner == "shifted":
-            F = ops.W(Om)
-            res = bf_bpcg(ops.S, ops.solve_G, F, self.tol_inner, self.maxit_inner, self.delta)
-            Y = d.A_G @ res.X
-        elif self.inner == "formA":
-            F = d.A_IG @ Om
-            res = bf_bpcg(ops.S_I, ops.solve_I, F, self.tol_inner, self.maxit_inner, self.delta)
-            Y = d.A_GI @ res.X
+        # sketch G = B^q Omega (eq. power), orthonormalised after every product, then Y = B G
+        G = self.omega
+        Y, its, conv = self.apply_target(G)
+        for _ in range(self.power):
+            G = np.linalg.qr(Y)[0]
+            Y, it2, c2 = self.apply_target(G)
+            its += it2
+            conv = conv and c2
+        U, Sig, r = nystrom_core(Y, G, self.k, self.eps_rel)
+        if self.variant == "M2":
+            self.Z = ops.solve_G(U)
+        elif self.variant == "M1":
+            self.Z = self.Rg.solve(U)
         else:
-            raise ValueError(self.inner)
-        U, Sig, r = nystrom_core(Y, Om, self.k, self.eps_rel)
-        self.Z = ops.solve_G(U)
+            self.Z = ops.solve_G(d.A_GI @ U)
         self.Sigma = Sig
-        self.setup_result = SetupResult(res.iters, res.converged, U.shape[1], r, U, Sig, self.Z, Y, False, rho)
+        self.setup_result = SetupResult(its, conv, U.shape[1], r, U, Sig, self.Z, Y, False, rho)
         self._post_setup()
         return self.setup_result
+
+    def apply_target(self, G):
+        """B G for the variant's Nystrom target B, through the inner block solve (Algorithm alg:prec1
+        steps 2-4); returns (B G, inner iterations, converged)."""
+        ops, d = self.ops, self.dbbd
+        if self.variant == "M3":
+            # S_I^{-1} G.  formA: S_I X = G, preconditioned by A_I^{-1}.  shifted: by SMW,
+            # S_I^{-1} = A_I^{-1} + A_I^{-1} A_IGamma S_Gamma^{-1} A_GammaI A_I^{-1}, so
+            # X = A_I^{-1} (G + A_IGamma D) with S_Gamma D = A_GammaI A_I^{-1} G.
+            if self.inner == "formA":
+                res = bf_bpcg(ops.S_I, ops.solve_I, G, self.tol_inner, self.maxit_inner, self.delta)
+                return res.X, res.iters, res.converged
+            F = d.A_GI @ ops.solve_I(G)
+            res = bf_bpcg(ops.S, ops.solve_G, F, self.tol_inner, self.maxit_inner, self.delta)
+            return ops.solve_I(G + d.A_IG @ res.X), res.iters, res.converged
+        X = self.Rg.solve(G) if self.variant == "M1" else G
+        if self.inner == "shifted":
+            # S_Gamma D = W X preconditioned by A_Gamma^{-1}; B X = A_Gamma D (eq. S-1)
+            res = bf_bpcg(ops.S, ops.solve_G, ops.W(X), self.tol_inner, self.maxit_inner, self.delta)
+            BX = d.A_G @ res.X
+        else:
+            res = bf_bpcg(ops.S_I, ops.solve_I, d.A_IG @ X, self.tol_inner, self.maxit_inner, self.delta)
+            BX = d.A_GI @ res.X
+        if self.variant == "M1":
+            BX = self.Rg.solve_t(BX)
+        return BX, res.iters, res.converged
 
     def _post_setup(self):
         if self.apply_mode == "ADEF2" and self.Z.shape[1] > 0:

@@ -100,6 +100,40 @@ def pins_pass(m):
     sx = ox.setup()
     ok.append(sx.Sigma.size == 4 and bool(np.all(sx.Sigma <= sig[:4] * (1 + 1e-9)))
               and bool(np.all(sx.Sigma >= 0.5 * sig[:4])))
+    # 9. M_1 with an exact square sketch: the truncated EVD gives the ideal adapted spectrum
+    T = make_problem((12, 12), (2, 2), sigma=1.5, ell=3.0, k=4, p=3)
+    dT = m.DBBD(T.n, T.row_ptr, T.col, T.val, T.part)
+    ngT = dT.n_gamma
+    ST = m.dense_schur(dT)
+    _, lamT = m.ideal_s2(dT, 5)
+    o1 = m.NystromSchurOracle(T.n, T.row_ptr, T.col, T.val, T.part, k=5, p=ngT - 5,
+                              omega=np.random.default_rng(5).standard_normal((ngT, ngT)), tol_inner=1e-15,
+                              eps_rel=1e-14, variant="M1")
+    o1.setup()
+    ev1 = np.sort(np.linalg.eigvals(o1.apply(np.eye(ngT)) @ ST).real)
+    ok.append(np.allclose(ev1, np.sort(np.concatenate([np.ones(5), lamT[5:]])), rtol=1e-7, atol=1e-9))
+    # 10. M_3 of the whole interior space with an exact inner solve is S^{-1}
+    Rd = random_dbbd(4, sizes=(6, 5, 7), n_gamma=6)
+    dR = m.DBBD(Rd.n, Rd.row_ptr, Rd.col, Rd.val, Rd.part)
+    nIR = dR.I.size
+    o3 = m.NystromSchurOracle(Rd.n, Rd.row_ptr, Rd.col, Rd.val, Rd.part, k=nIR, p=0,
+                              omega=np.random.default_rng(2).standard_normal((nIR, nIR)), tol_inner=1e-15,
+                              eps_rel=1e-14, variant="M3")
+    o3.setup()
+    ok.append(np.allclose(o3.apply(np.eye(dR.n_gamma)) @ m.dense_schur(dR), np.eye(dR.n_gamma), atol=1e-8))
+    # 11. one power iteration: the Nystrom approximation with the sketch orth(B Omega), B formed densely
+    oq = m.NystromSchurOracle(T.n, T.row_ptr, T.col, T.val, T.part, k=4, p=3, omega=T.omega(), tol_inner=1e-14,
+                              eps_rel=1e-14, power=1)
+    sq = oq.setup()
+    AinvT = np.linalg.inv(T.csr().toarray())
+    AGT = dT.A_G.toarray()
+    BT = AGT @ AinvT[np.ix_(dT.G, dT.G)] @ AGT - AGT
+    BT = 0.5 * (BT + BT.T)
+    Gq = np.linalg.qr(BT @ T.omega())[0]
+    BGq = BT @ Gq
+    ref = BGq @ np.linalg.pinv(0.5 * (Gq.T @ BGq + BGq.T @ Gq)) @ BGq.T
+    Uq, Sq, _ = m.nystrom_core(sq.Y, Gq, 7, 1e-14)
+    ok.append(np.allclose(Uq @ np.diag(Sq) @ Uq.T, ref, atol=1e-9 * np.abs(ref).max()))
     return all(ok), ok
 
 
@@ -125,8 +159,14 @@ MUTATIONS = {
     "adef2_start_zero": ("return self.Z @ sla.cho_solve(self.E_cf, self.Z.T @ f)", "return None"),
     "adef2_coarse_sign": ("Z.T @ r - self.SZ.T @ t", "Z.T @ r + self.SZ.T @ t"),
     "adef2_E_without_S": ("E = self.Z.T @ self.SZ", "E = self.Z.T @ self.Z"),
-    "shifted_rhs_uses_AG": ("F = ops.W(Om)", "F = d.A_G @ Om"),
-    "Y_without_AG": ("Y = d.A_G @ res.X", "Y = res.X"),
+    "shifted_rhs_uses_AG": ("res = bf_bpcg(ops.S, ops.solve_G, ops.W(X),", "res = bf_bpcg(ops.S, ops.solve_G, d.A_G @ X,"),
+    "m1_Z_with_transpose": ("self.Z = self.Rg.solve(U)", "self.Z = self.Rg.solve_t(U)"),
+    "m1_target_without_Rt": ("BX = self.Rg.solve_t(BX)", "BX = BX"),
+    "m3_Z_without_coupling": ("self.Z = ops.solve_G(d.A_GI @ U)", "self.Z = d.A_GI @ U"),
+    "m3_shifted_drops_interior_term": ("return ops.solve_I(G + d.A_IG @ res.X), res.iters",
+                                       "return ops.solve_I(d.A_IG @ res.X), res.iters"),
+    "power_keeps_first_sketch": ("            G = np.linalg.qr(Y)[0]\n", "            pass\n"),
+    "Y_without_AG": ("BX = d.A_G @ res.X", "BX = res.X"),
 }
 
 
