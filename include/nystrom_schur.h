@@ -68,6 +68,31 @@ typedef enum {
 } ns_apply_mode;
 
 /*
+ * Which matrix Nystrom approximates and how the low-rank basis Z is formed (the
+ * variants of the preconditioner section; apply_mode then selects the additive
+ * form A_Gamma^{-1} + Z Sigma Z^T or the adapted deflation built from Z):
+ *   NS_VARIANT_M2: A_GammaI S_I^{-1} A_IGamma, Z = A_Gamma^{-1} U
+ *                  (eqs. internal_term_lr_approximation_1, left_prec_mat);
+ *   NS_VARIANT_M1: R_Gamma^{-T} A_GammaI S_I^{-1} A_IGamma R_Gamma^{-1}, Z = R_Gamma^{-1} U
+ *                  (eqs. lr_approximation_S-1_A-I, prec1S, our_two_level_preconditioner), with
+ *                  A_Gamma = R_Gamma^T R_Gamma the Cholesky factor of A_Gamma in the order of the
+ *                  interface split (interface blocks in label order, then the junction nodes);
+ *   NS_VARIANT_M3: S_I^{-1} on the interior space, Z = A_Gamma^{-1} A_GammaI U
+ *                  (eqs. internal_term_lr_approximation_2, left_prec_mat2); the sketch omega is then
+ *                  n_interior x (k+p) in interior order.  One problem per handle.
+ */
+typedef enum { NS_VARIANT_M2 = 0, NS_VARIANT_M1 = 1, NS_VARIANT_M3 = 2 } ns_variant;
+
+/*
+ * The outer iteration of pcg_solve:
+ *   NS_OUTER_SCHUR: PCG on S_Gamma w = f (eq. Sx=b), then back-substitution;
+ *   NS_OUTER_FULL:  PCG on A x = b preconditioned by the approximate block LDL^T factorisation with
+ *                   S~^{-1} = M (eq. M_inv_A; spectrum Lambda(M S_Gamma) u {1}).  Needs
+ *                   apply_mode NS_APPLY_M2 (a symmetric M).
+ */
+typedef enum { NS_OUTER_SCHUR = 0, NS_OUTER_FULL = 1 } ns_outer;
+
+/*
  * Options of setup().  Zero-initialise and set what you need; a value of 0 in
  * tol_inner, eig_thresh_rel, orth_drop_rel or max_inner_iters selects the
  * default given in brackets.
@@ -91,7 +116,8 @@ typedef struct {
                                 block per subdomain over the interface nodes it touches, applied
                                 as one batched GEMM                                              */
   const double* omega;       /* DEVICE, n_gamma x (k+p) row-major Gaussian sketch in interface
-                                order (Algorithm alg:prec1 step 1).  Required when k > 0.         */
+                                order (Algorithm alg:prec1 step 1); n_interior x (k+p) in
+                                interior order for NS_VARIANT_M3.  Required when k > 0.           */
   const double* proposal;    /* DEVICE, optional n_gamma x k starting subspace (learned); NULL =
                                 plain Nystrom.  Accepted subspaces run in NS_APPLY_ADEF2 mode.   */
   double accept_tol;         /* eigen-residual threshold for accepting `proposal` [0.2]          */
@@ -100,6 +126,11 @@ typedef struct {
                                 host's stopping checks: 0 = automatic (1 for one problem, 4 for
                                 a batch), -1 = plain launches, m > 0 = m iterations per graph.
                                 Results are the same in every mode.                              */
+  int32_t variant;           /* ns_variant [NS_VARIANT_M2]                                        */
+  int32_t power_iters;       /* q of eq. power: the sketch becomes B^q Omega, orthonormalised after
+                                every product with B (each product is one inner block solve;
+                                it_inner counts them all) [0]                                     */
+  int32_t outer;             /* ns_outer [NS_OUTER_SCHUR]                                         */
 } ns_options;
 
 /* Outputs of setup(), HOST memory. Times are seconds measured with hipEvents. */
@@ -119,7 +150,8 @@ typedef struct {
 typedef struct {
   int32_t it_pcg;            /* outer PCG iterations (applications of S_Gamma in the loop)        */
   int32_t converged;
-  double relres_schur;       /* recurrence residual ||r|| / ||f|| at exit                         */
+  double relres_schur;       /* recurrence residual ||r|| / ||f|| at exit (NS_OUTER_FULL: ||r|| / ||b||
+                                of the full-system recurrence)                                   */
   double relres_true;        /* ||b - A x|| / ||b|| of the returned x                             */
   double t_solve;            /* seconds, hipEvents                                                */
   double* res_hist;          /* optional HOST array receiving ||r_j|| / ||f||, j = 0..it_pcg      */

@@ -184,8 +184,9 @@ def level2_order(d: DBBD):
 
 
 class GammaFactor:
-    """R_Gamma = L^T P: L the Cholesky factor of A_Gamma with rows and columns in the level-2 order
-    (P x = x[perm]), so that A_Gamma = R^T R.  Any R with R^T R = A_Gamma serves the derivation of M_1; this
+    """R_Gamma = P^T L^T P: L the Cholesky factor of A_Gamma with rows and columns in the level-2 order
+    ((P x) = x[perm]), so that A_Gamma = R^T R with the rows of R labelled, like its columns and like the
+    sketch, by interface index.  Any R with R^T R = A_Gamma serves the derivation of M_1 (eq. cholesky); this
     one is the factor the level-2 block LDL^T of A_Gamma defines.  Dense (small interfaces only)."""
 
     def __init__(self, d: DBBD, max_dense: int = 8000):
@@ -195,20 +196,22 @@ class GammaFactor:
         AG = d.A_G.toarray()
         self.L = sla.cholesky(AG[np.ix_(self.perm, self.perm)], lower=True)
 
-    def mult(self, X):
-        """R X = L^T (P X)."""
-        return self.L.T @ np.asarray(X)[self.perm]
-
-    def solve(self, Y):
-        """R^{-1} Y: L^T u = Y, then x[perm] = u."""
-        u = sla.solve_triangular(self.L, np.asarray(Y), lower=True, trans="T")
+    def _unperm(self, u):
         out = np.empty_like(u)
         out[self.perm] = u
         return out
 
+    def mult(self, X):
+        """R X = P^T L^T (P X)."""
+        return self._unperm(self.L.T @ np.asarray(X)[self.perm])
+
+    def solve(self, Y):
+        """R^{-1} Y = P^T L^{-T} (P Y)."""
+        return self._unperm(sla.solve_triangular(self.L, np.asarray(Y)[self.perm], lower=True, trans="T"))
+
     def solve_t(self, Y):
-        """R^{-T} Y = L^{-1} (P Y)."""
-        return sla.solve_triangular(self.L, np.asarray(Y)[self.perm], lower=True)
+        """R^{-T} Y = P^T L^{-1} (P Y)."""
+        return self._unperm(sla.solve_triangular(self.L, np.asarray(Y)[self.perm], lower=True))
 
 
 # ----------------------------------------------------------------------------

@@ -64,6 +64,8 @@ struct ns_handle_s {
   std::vector<int> it_inner, conv_inner;
   std::vector<double> relres_inner;
   int prec_inner = 0, apply_mode = 0, trsm_cols = 0, schur_mode = 0, pcg_graph = 0;
+  int variant = 0, power = 0, outer = 0;  // ns_variant, power iterations of the sketch, ns_outer
+  ns::SegBuf segI;                         // padded interior rows (one problem): the rows of variant M_3
   double tol_inner = 0.1, eig_rel = 1e-10, drop_rel = 1e-6;
   int max_inner = 500;
 

@@ -261,6 +261,9 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
                     const int* ncols_blk = nullptr, const int* first_tile = nullptr, double alg_flops = -1.0,
                     int b0 = 0, int b1 = -1, int64_t row0 = 0, int family = -1,  // -1: by the level's role
                     const SparseRhs* sparse = nullptr);
+// Backward sweep only: B <- L^{-T} B (every block, padded rows).
+template <class T>
+void tile_solve_bwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st);
 // The FP64 64-column forward sweep of every block of lv can take a SparseRhs (band of at most 4 tiles).
 bool tile_sparse_rhs_ok(const TileLevel& lv);
 // Single right-hand side sweeps (FP64) with 16-wave workgroups; need LT64.

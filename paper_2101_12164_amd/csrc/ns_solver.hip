@@ -5,6 +5,7 @@
 // sequences launches and reads back convergence scalars.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "ns_handle.h"
 #include "ns_vec.h"
@@ -225,36 +226,29 @@ void orth(Handle& h, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int 
   std::swap(P, Q);
 }
 
-// Breakdown-free block PCG on S_Gamma D = W Omega, preconditioned by A_Gamma^{-1}, from D = 0 (the inner
-// solve of Algorithm alg:prec1, steps 2-4, in the shifted Schur form: A_Gamma D = A_GammaI S_I^{-1}
-// A_IGamma Omega by eq. S-1), for every problem of the batch at once.  Writes D (FP64, n_G x s) and the
-// per-problem iteration counts, convergence and final column-max relative residuals.
-template <class T>
-void block_pcg(Handle& h, SmallMats& sm, const double* Omega, double* D) {
+// Breakdown-free block PCG on S_Gamma D = F, preconditioned by A_Gamma^{-1}, from D = 0 (the inner solve of
+// Algorithm alg:prec1, steps 2-4, in the shifted Schur form: with F = W Omega, A_Gamma D = A_GammaI S_I^{-1}
+// A_IGamma Omega by eq. S-1), for every problem of the batch at once.  rhs(T* R) writes F into R.  Writes D
+// (FP64, n_G x s) and adds the per-problem iteration counts to h.it_inner (convergence and final column-max
+// relative residuals are those of this solve).
+template <class T, class Rhs>
+void block_pcg(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
   hipStream_t st = h.stream;
   const Seg& sg = h.segG.view;
   const int s = h.s, np = h.nprob;
   const int64_t nG = h.nG, ss = int64_t(s) * s;
   const int pb = (np + 255) / 256;
-  DBuf<T> Om, X, R, Pb, Qb, Z;
+  DBuf<T> X, R, Pb, Qb, Z;
   for (DBuf<T>* b : {&X, &R, &Pb, &Qb, &Z}) b->alloc(nG * s);
   DBuf<double> work;
   work.alloc(gram_work_elems(sg, s));
-  const T* Omt;
-  if constexpr (sizeof(T) == 8) {
-    Omt = Omega;
-  } else {
-    Om.alloc(nG * s);
-    convert_block<double, float>(nG, s, Omega, s, Om.p, s, st);
-    Omt = Om.p;
-  }
   T* P = Pb.p;
   T* Q = Qb.p;
   std::vector<int> ones(np, 1);
   upload(sm.active, ones.data(), np * sizeof(int), st);
   NS_HIP(hipMemsetAsync(sm.conv, 0, np * sizeof(int), st));
   NS_HIP(hipMemsetAsync(sm.ctr, 0, 4 * sizeof(int), st));
-  op_schur<T>(h, Omt, s, R.p, s, s, /*w_only=*/true);  // F = W Omega
+  rhs(R.p);  // F (n_G x s, precision T)
   NS_HIP(hipMemsetAsync(X.p, 0, nG * s * sizeof(T), st));
   col_sumsq<T>(sg, s, R.p, s, sm.nF2, work, st);
   NS_HIP(hipMemcpyAsync(sm.colsq, sm.nF2, size_t(np) * s * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -300,63 +294,236 @@ void block_pcg(Handle& h, SmallMats& sm, const double* Omega, double* D) {
     NS_HIP(hipMemcpyAsync(D, X.p, nG * s * sizeof(double), hipMemcpyDeviceToDevice, st));
   else
     convert_block<float, double>(nG, s, X.p, s, D, s, st);
-  h.it_inner.resize(np);
-  h.conv_inner.resize(np);
+  std::vector<int> its(np), conv(np);
   h.relres_inner.resize(np);
-  NS_HIP(hipMemcpyAsync(h.it_inner.data(), sm.itp, np * sizeof(int), hipMemcpyDeviceToHost, st));
-  NS_HIP(hipMemcpyAsync(h.conv_inner.data(), sm.conv, np * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipMemcpyAsync(its.data(), sm.itp, np * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipMemcpyAsync(conv.data(), sm.conv, np * sizeof(int), hipMemcpyDeviceToHost, st));
   NS_HIP(hipMemcpyAsync(h.relres_inner.data(), sm.relres, np * sizeof(double), hipMemcpyDeviceToHost, st));
   NS_HIP(hipStreamSynchronize(st));
+  h.it_inner.resize(np, 0);
+  h.conv_inner.resize(np, 1);
+  for (int q = 0; q < np; ++q) {
+    h.it_inner[q] += its[q];
+    h.conv_inner[q] = h.conv_inner[q] && conv[q];
+  }
 }
 
-// Nystrom core (Algorithm alg:prec1 steps 5-11) per problem: QR of Y by shifted Cholesky-QR (three
-// passes), C = Omega^T Y, EVDs, U = Q W(:, 1:k'), Z = A_G^{-1} U.
-void nystrom(Handle& h, SmallMats& sm, const double* Omega, double* Y) {
+// Three Cholesky-QR passes per problem over the rows of sg: X (rows x s) <- X R^{-1} with R^T R = X^T M X,
+// where MX holds M X for an SPD M (MX == nullptr: M = I, the QR of X); MX is updated alongside.  The first
+// pass is shifted by 11 (m s + s (s + 1)) u (m the problem's rows, u = 2^-53).  On return X (and MX) point at
+// the orthonormalised blocks (one of the two given buffers each) and sm.Racc holds R.
+void chol_qr3(Handle& h, SmallMats& sm, const Seg& sg, const std::vector<int64_t>& prow, int s, double*& X,
+              double*& Xs, double*& MX, double*& MXs, double* work) {
   hipStream_t st = h.stream;
-  const Seg& sg = h.segG.view;
-  const int s = h.s, k = h.k, np = h.nprob;
-  const int64_t nG = h.nG, ss = int64_t(s) * s;
-  DBuf<double> Qb, work;
-  Qb.alloc(nG * s);
-  work.alloc(gram_work_elems(sg, s));
-  gram<double, double>(sg, Omega, s, s, Y, s, s, sm.C, ss, 1.0, 0.0, work, st);  // C = Omega^T Y
+  const int np = h.nprob;
+  const int64_t ss = int64_t(s) * s;
   {
-    // shift of the first Cholesky-QR pass: 11 (n_G s + s (s + 1)) u, with n_G the problem's interface size
     const double u = std::ldexp(1.0, -53);
     std::vector<double> coef(np);
-    for (int q = 0; q < np; ++q)
-      coef[q] = 11.0 * (double(h.h_goff[q + 1] - h.h_goff[q]) * s + double(s) * (s + 1)) * u;
+    for (int q = 0; q < np; ++q) coef[q] = 11.0 * (double(prow[q]) * s + double(s) * (s + 1)) * u;
     upload(sm.coef, coef.data(), np * sizeof(double), st);
   }
-  double* A = Y;
-  double* B = Qb.p;
   for (int pass = 0; pass < 3; ++pass) {
-    gram<double, double>(sg, A, s, s, A, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
+    gram<double, double>(sg, X, s, s, MX ? MX : X, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
     small_cholqr(Batch{np, nullptr}, s, sm.Gorth, ss, pass == 0 ? sm.coef : nullptr, sm.Rinv, sm.Racc, pass == 0,
                  sm.flag + 2, h.sws, st);
-    ts_update<double>(sg, s, B, s, 0.0, 1.0, A, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
-    std::swap(A, B);
+    ts_update<double>(sg, s, Xs, s, 0.0, 1.0, X, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
+    std::swap(X, Xs);
+    if (MX) {
+      ts_update<double>(sg, s, MXs, s, 0.0, 1.0, MX, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
+      std::swap(MX, MXs);
+    }
   }
-  // A now holds Q (orthonormal), sm.Racc holds R
+}
+
+// Nystrom core (Algorithm alg:nystrom steps 3-8, Algorithm alg:prec1 steps 5-10) per problem on the rows of sg:
+// C = G^T BG with G the sketch and BG = B G; an orthonormal basis Q of the sketched range with BG = Q R (the
+// QR of BG; with D given, BG = A_Gamma D and the basis is D orthonormalised in the A_Gamma inner product, which
+// is R_Gamma^{-1} times the QR basis of R_Gamma D: the variant M_1); EVDs of C and T; out = Q W(:, 1:k')
+// (rows x k).  Sets k_eff and Sigma; BG and D are overwritten.
+void nystrom_factor(Handle& h, SmallMats& sm, const Seg& sg, const std::vector<int64_t>& prow, int64_t rows,
+                    const double* G, double* BG, double* D, double* out) {
+  hipStream_t st = h.stream;
+  const int s = h.s, k = h.k, np = h.nprob;
+  const int64_t ss = int64_t(s) * s;
+  DBuf<double> s1, s2, work;
+  s1.alloc(rows * s);
+  work.alloc(gram_work_elems(sg, s));
+  gram<double, double>(sg, G, s, s, BG, s, s, sm.C, ss, 1.0, 0.0, work, st);  // C = G^T B G
+  double* X = D ? D : BG;
+  double* Xs = s1.p;
+  double* MX = D ? BG : nullptr;
+  double* MXs = nullptr;
+  if (D) {
+    s2.alloc(rows * s);
+    MXs = s2.p;
+  }
+  chol_qr3(h, sm, sg, prow, s, X, Xs, MX, MXs, work);
   small_nystrom(np, s, k, sm.C, sm.Racc, h.eig_rel, sm.Wk, sm.Ek, sm.nys, h.sws, st);
-  std::vector<int> out(2 * np);
-  read_back(h, out.data(), sm.nys, 2 * np);
+  std::vector<int> o(2 * np);
+  read_back(h, o.data(), sm.nys, 2 * np);
   h.h_keff.resize(np);
   h.k_eff = 0;
   for (int q = 0; q < np; ++q) {
-    h.h_keff[q] = out[2 * q + 1];
+    h.h_keff[q] = o[2 * q + 1];
     h.k_eff = std::max(h.k_eff, h.h_keff[q]);
   }
   h.keff_d.alloc(np);
   upload(h.keff_d.p, h.h_keff.data(), np * sizeof(int), st);
-  h.Z.alloc(nG * (k > 0 ? k : 1));
   h.Sigma.alloc(size_t(k > 0 ? k : 1) * np);
-  NS_HIP(hipMemsetAsync(h.Z.p, 0, h.Z.n * sizeof(double), st));
   NS_HIP(hipMemcpyAsync(h.Sigma.p, sm.Ek, size_t(k) * np * sizeof(double), hipMemcpyDeviceToDevice, st));
+  NS_HIP(hipMemsetAsync(out, 0, rows * k * sizeof(double), st));
+  if (h.k_eff > 0)
+    ts_update<double>(sg, k, out, k, 0.0, 1.0, X, s, s, sm.Wk, k, int64_t(s) * k, nullptr, 0, 0, nullptr, 0, 0, st);
+}
+
+// R_Gamma^{-1} X (FP64, n_G x ncols, interface order) for A_Gamma = R_Gamma^T R_Gamma, R_Gamma = L^T P with L the
+// Cholesky factor of A_Gamma in the order of the interface split: [A_s A_sJ; A_Js A_J] = L L^T with
+// L = [L_s 0; A_Js L_s^{-T} L_J] and L_J L_J^T = S_J, so u_J = L_J^{-T} x_J and
+// u_s = L_s^{-T} (x_s - L_s^{-1} A_sJ u_J).
+void gamma_rinv(Handle& h, const double* X, double* Out, int ncols) {
+  hipStream_t st = h.stream;
+  const int64_t n2pad = h.L2.nrows_pad, nJpad = h.LJ.nrows_pad;
+  DBuf<double> Bs, Bt, Gj;
+  if (nJpad) {
+    Gj.alloc(nJpad * ncols);
+    gather_rows<double>(nJpad, h.jsrc, X, ncols, Gj.p, ncols, ncols, st);
+    tile_solve_bwd<double>(h.LJ, Gj.p, ncols, ncols, 0, st);  // u_J
+    scatter_rows<double, double>(nJpad, h.jsrc, Gj.p, ncols, Out, ncols, ncols, st);
+  }
+  if (n2pad) {
+    Bs.alloc(n2pad * ncols);
+    gather_rows<double>(n2pad, h.l2src, X, ncols, Bs.p, ncols, ncols, st);
+    if (nJpad && h.AsJ.nnz) {
+      Bt.alloc(n2pad * ncols);
+      csr_mult<double>(h.AsJ, Gj.p, ncols, Bt.p, ncols, ncols, st);                // A_sJ u_J
+      tile_solve_fwd<double>(h.L2, Bt.p, ncols, ncols, 64, st);                    // L_s^{-1} A_sJ u_J
+      axpby(n2pad * ncols, -1.0, Bt.p, 1.0, Bs.p, st);
+    }
+    tile_solve_bwd<double>(h.L2, Bs.p, ncols, ncols, 0, st);  // u_s
+    scatter_rows<double, double>(n2pad, h.l2src, Bs.p, ncols, Out, ncols, ncols, st);
+  }
+}
+
+// Block CG on the shifted system with right-hand side F = W G (G: n_G x s, FP64) in the inner precision.
+void inner_solve_w(Handle& h, SmallMats& sm, const double* G, double* D) {
+  const int s = h.s;
+  const int64_t nG = h.nG;
+  auto rhs = [&](auto* R) {
+    using T = std::remove_pointer_t<decltype(R)>;
+    if constexpr (sizeof(T) == 8) {
+      op_schur<double>(h, G, s, R, s, s, /*w_only=*/true);
+    } else {
+      DBuf<float> Gf;
+      Gf.alloc(nG * s);
+      convert_block<double, float>(nG, s, G, s, Gf.p, s, h.stream);
+      op_schur<float>(h, Gf.p, s, R, s, s, /*w_only=*/true);
+    }
+  };
+  if (h.prec_inner)
+    block_pcg<float>(h, sm, rhs, D);
+  else
+    block_pcg<double>(h, sm, rhs, D);
+}
+
+// Block CG on the shifted system with a given right-hand side F (FP64, n_G x s).
+void inner_solve_f(Handle& h, SmallMats& sm, const double* F, double* D) {
+  const int s = h.s;
+  const int64_t nG = h.nG;
+  auto rhs = [&](auto* R) {
+    using T = std::remove_pointer_t<decltype(R)>;
+    if constexpr (sizeof(T) == 8)
+      NS_HIP(hipMemcpyAsync(R, F, nG * s * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
+    else
+      convert_block<double, float>(nG, s, F, s, R, s, h.stream);
+  };
+  if (h.prec_inner)
+    block_pcg<float>(h, sm, rhs, D);
+  else
+    block_pcg<double>(h, sm, rhs, D);
+}
+
+// The low-rank term of the chosen variant (Algorithm alg:prec1 and its analogues for M_1 and M_3) with q power
+// iterations (eq. power): products B G through the inner block solves, the sketch orthonormalised after every
+// product but the last, the Nystrom core on the last one, then Z.  mark() is called after the last inner solve.
+template <class Mark>
+void lowrank_setup(Handle& h, SmallMats& sm, const double* omega, Mark mark) {
+  hipStream_t st = h.stream;
+  const int s = h.s, k = h.k, np = h.nprob;
+  const int64_t nG = h.nG, nIp = h.L1.nrows_pad;
+  const bool m3 = h.variant == NS_VARIANT_M3, m1 = h.variant == NS_VARIANT_M1;
+  std::vector<int64_t> prow(np);
+  for (int q = 0; q < np; ++q) prow[q] = h.h_goff[q + 1] - h.h_goff[q];
+  const int64_t rows = m3 ? nIp : nG;  // rows of the sketch and of B G
+  if (m3) {
+    prow.assign(1, nIp);
+    h.segI.build({0, nIp}, st);
+  }
+  const Seg& sg = m3 ? h.segI.view : h.segG.view;
+  DBuf<double> Gb, BGb, BGs, Db, Ds, F, work;
+  for (DBuf<double>* b : {&Gb, &BGb}) b->alloc(rows * s);
+  Db.alloc(nG * s);
+  if (m3) F.alloc(nG * s);
+  work.alloc(gram_work_elems(sg, s));
+  double* G = Gb.p;   // current sketch (M_1: in the coordinates of R_Gamma^{-1})
+  double* BG = BGb.p;
+  double* D = Db.p;
+  // the first sketch
+  if (m3)
+    gather_rows<double>(nIp, h.icomp, omega, s, G, s, s, st);  // padded interior rows, zero on the padding
+  else if (m1)
+    gamma_rinv(h, omega, G, s);
+  else
+    NS_HIP(hipMemcpyAsync(G, omega, nG * s * sizeof(double), hipMemcpyDeviceToDevice, st));
+  h.it_inner.assign(np, 0);
+  h.conv_inner.assign(np, 1);
+  for (int it = 0; it <= h.power; ++it) {
+    if (m3) {
+      // S_I^{-1} G = A_I^{-1} (G + A_IGamma D) with S_Gamma D = A_GammaI A_I^{-1} G (Sherman-Morrison-Woodbury)
+      NS_HIP(hipMemcpyAsync(BG, G, rows * s * sizeof(double), hipMemcpyDeviceToDevice, st));
+      tile_solve<double>(h.L1, BG, s, s, h.trsm_cols, st);
+      csr_mult<double>(h.AGI, BG, s, F.p, s, s, st);
+      inner_solve_f(h, sm, F.p, D);
+      csr_mult<double>(h.AIG, D, s, BG, s, s, st);
+      axpby(rows * s, 1.0, G, 1.0, BG, st);
+      tile_solve<double>(h.L1, BG, s, s, h.trsm_cols, st);
+    } else {
+      inner_solve_w(h, sm, G, D);                          // S_Gamma D = W G
+      csr_mult<double>(h.AGG, D, s, BG, s, s, st);         // B G = A_Gamma D (M_1: R_Gamma^T times R_Gamma D)
+    }
+    if (it == h.power) break;
+    // next sketch: the orthonormalised product (M_1: D in the A_Gamma inner product, i.e. R_Gamma^{-1} times
+    // the orthonormal basis of R_Gamma D)
+    double* X = m1 ? D : BG;
+    double* MX = m1 ? BG : nullptr;
+    if (!Ds.p) Ds.alloc(nG * s);
+    if (!BGs.p) BGs.alloc(rows * s);
+    double* Xs = m1 ? Ds.p : BGs.p;
+    double* MXs = m1 ? BGs.p : nullptr;
+    chol_qr3(h, sm, sg, prow, s, X, Xs, MX, MXs, work);
+    NS_HIP(hipMemcpyAsync(G, X, rows * s * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  mark();
+  DBuf<double> out;
+  out.alloc(rows * std::max(k, 1));
+  nystrom_factor(h, sm, sg, prow, rows, G, BG, m1 ? D : nullptr, out.p);
+  h.Z.alloc(nG * (k > 0 ? k : 1));
+  NS_HIP(hipMemsetAsync(h.Z.p, 0, h.Z.n * sizeof(double), st));
   if (h.k_eff > 0) {
-    h.U.alloc(nG * k);
-    ts_update<double>(sg, k, h.U.p, k, 0.0, 1.0, A, s, s, sm.Wk, k, int64_t(s) * k, nullptr, 0, 0, nullptr, 0, 0, st);
-    op_gamma_solve<double>(h, h.U.p, k, h.Z.p, k, k);
+    if (m1) {
+      // Z = R_Gamma^{-1} U = (D orthonormalised in the A_Gamma inner product) W(:, 1:k')
+      NS_HIP(hipMemcpyAsync(h.Z.p, out.p, nG * k * sizeof(double), hipMemcpyDeviceToDevice, st));
+    } else if (m3) {
+      // Z = A_Gamma^{-1} A_GammaI V (V: padded interior rows)
+      DBuf<double> t;
+      t.alloc(nG * k);
+      csr_mult<double>(h.AGI, out.p, k, t.p, k, k, st);
+      op_gamma_solve<double>(h, t.p, k, h.Z.p, k, k);
+    } else {
+      h.U.alloc(nG * k);
+      NS_HIP(hipMemcpyAsync(h.U.p, out.p, nG * k * sizeof(double), hipMemcpyDeviceToDevice, st));
+      op_gamma_solve<double>(h, h.U.p, k, h.Z.p, k, k);
+    }
   }
   NS_HIP(hipStreamSynchronize(st));
 }
@@ -482,12 +649,128 @@ __global__ void k_sqrt_inplace(int n, double* x, int stride) {
   if (i < n) x[int64_t(i) * stride] = sqrt(x[int64_t(i) * stride]);
 }
 
+// PCG iterations for every problem until all are done or maxit iterations ran.  head(s): q = A p, alpha,
+// w and r, the stopping test; tail(s): z = M r, beta, p.  The iteration index lives on the device, so the same
+// launches, recorded once into a HIP graph, serve every iteration (m per replay); the first iteration runs
+// with plain launches (it also sizes every workspace the body uses).  hc: problems done, iterations run.
+template <class Head, class Tail>
+void pcg_loop(Handle& h, int np, const PcgState& S, int maxit, int hc[2], Head head, Tail tail) {
+  hipStream_t st = h.stream;
+  int m = h.pcg_graph == 0 ? (np > 1 ? 4 : 1) : h.pcg_graph;
+  head(st);
+  read_back(h, hc, S.ndone, 2);
+  if (hc[0] < np && hc[1] < maxit) tail(st);
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  if (m > 0 && hc[0] < np && hc[1] < maxit) {
+    // record m iterations on a private stream (the handle's stream may be the null stream)
+    NS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    h.stream = cap;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        for (int t = 0; t < m; ++t) {
+          head(cap);
+          tail(cap);
+        }
+      } catch (...) {
+        (void)hipStreamEndCapture(cap, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        h.stream = st;
+        (void)hipStreamDestroy(cap);
+        throw;
+      }
+      e = hipStreamEndCapture(cap, &graph);
+    }
+    h.stream = st;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipStreamDestroy(cap);
+      fail(HIP, std::string("PCG graph capture failed: ") + hipGetErrorString(e));
+    }
+  }
+  if (exec && hc[0] < np && hc[1] < maxit) {
+    // One replay ahead: replay g + 1 is queued before the host reads the counters left by replay g, so the
+    // device never waits for the host's test.  Replays after convergence change nothing (finished problems
+    // are frozen, iterations past maxit are no-ops).
+    int* hp = static_cast<int*>(pinned_scratch(4 * sizeof(int)));
+    Event ev[2];
+    int64_t issued = hc[1];
+    auto issue = [&](int s) {
+      NS_HIP(hipGraphLaunch(exec, st));
+      NS_HIP(hipMemcpyAsync(hp + 2 * s, S.ndone, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      NS_HIP(hipEventRecord(ev[s].e, st));
+      issued += m;
+    };
+    int slot = 0;
+    issue(0);
+    for (;;) {
+      const bool more = issued < maxit;
+      if (more) issue(slot ^ 1);
+      NS_HIP(hipEventSynchronize(ev[slot].e));
+      hc[0] = hp[2 * slot];
+      hc[1] = hp[2 * slot + 1];
+      if (hc[0] >= np || hc[1] >= maxit || !more) break;
+      slot ^= 1;
+    }
+    NS_HIP(hipStreamSynchronize(st));  // the replay queued ahead has finished too
+    stream_idle(st);
+  }
+  while (!exec && hc[0] < np && hc[1] < maxit) {
+    head(st);
+    read_back(h, hc, S.ndone, 2);
+    if (hc[0] >= np || hc[1] >= maxit) break;
+    tail(st);
+    read_back(h, hc, S.ndone, 2);
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (cap) (void)hipStreamDestroy(cap);
+}
+
 // Results of one problem's solve.
 struct SolveOut {
   int it = 0, converged = 0;
   double relres_schur = 0.0, relres_true = 0.0;
   std::vector<double> hist;
 };
+
+// True residual ||b - A x|| / ||b|| and the recurrence history of every problem after a PCG run.
+// tmp: n doubles of scratch; ist: [done per problem, iterations per problem]; hist: hs values per problem.
+void pcg_results(Handle& h, const double* b, const double* x, double* tmp, const int* ist, const double* hist,
+                 int64_t hs, int maxit, int iters, std::vector<SolveOut>& res) {
+  hipStream_t st = h.stream;
+  const int np = h.nprob;
+  const int64_t n = h.n;
+  csr_mult<double>(h.Aorig, x, 1, tmp, 1, 1, st);
+  k_sub<<<unsigned((n + 255) / 256), 256, 0, st>>>(n, b, tmp, tmp);
+  NS_LAUNCH_CHECK();
+  const Seg& sn = h.segN.view;
+  DBuf<double> rr, work2;
+  rr.alloc(2 * size_t(np));
+  work2.alloc(size_t(sn.nchunk) + 16);
+  dot(sn, tmp, tmp, rr.p, 2, work2, st);
+  dot(sn, b, b, rr.p + 1, 2, work2, st);
+  std::vector<double> hrr(2 * np), hh(size_t(hs) * np);
+  std::vector<int> hi(2 * np);
+  NS_HIP(hipMemcpyAsync(hrr.data(), rr.p, 2 * np * sizeof(double), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipMemcpyAsync(hi.data(), ist, 2 * np * sizeof(int), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipMemcpyAsync(hh.data(), hist, hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  NS_HIP(hipStreamSynchronize(st));
+  res.assign(np, SolveOut{});
+  for (int g = 0; g < np; ++g) {
+    SolveOut& o = res[g];
+    const int done = hi[g];
+    o.it = done ? hi[np + g] : iters;
+    if (!done) o.it = std::min(o.it, maxit);
+    o.converged = done == 1;
+    o.hist.assign(hh.begin() + size_t(g) * hs, hh.begin() + size_t(g) * hs + o.it + 1);
+    o.relres_schur = o.hist.back();
+    o.relres_true = hrr[2 * g + 1] > 0 ? std::sqrt(hrr[2 * g] / hrr[2 * g + 1]) : 0.0;
+  }
+}
 
 // f = b_Gamma - A_GammaI A_I^{-1} b_I; PCG on S_Gamma w = f with M (w0 = Q f for the adapted deflation);
 // x_I = A_I^{-1} (b_I - A_IGamma w), x_Gamma = w (eqs. A_LDLT and Sx=b), for every problem at once.
@@ -557,79 +840,7 @@ void pcg_core(Handle& h, const double* b, double* x, double rtol, int maxit, std
     apply_prec(h, r.p, 1, z.p, 1, 1, work, c1, c2, h.sws);
     dot(sg, r.p, z.p, psd.p + PS_RHO, PS, work, st);  // rho_0
     NS_HIP(hipMemcpyAsync(p.p, z.p, nG * sizeof(double), hipMemcpyDeviceToDevice, st));
-    int m = h.pcg_graph == 0 ? (np > 1 ? 4 : 1) : h.pcg_graph;
-    // the first iteration runs with plain launches: it also sizes every workspace the body uses
-    head(st);
-    read_back(h, hc, S.ndone, 2);
-    if (hc[0] < np && hc[1] < maxit) tail(st);
-    hipGraphExec_t exec = nullptr;
-    hipStream_t cap = nullptr;
-    if (m > 0 && hc[0] < np && hc[1] < maxit) {
-      // record m iterations on a private stream (the handle's stream may be the null stream)
-      NS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-      hipGraph_t graph = nullptr;
-      h.stream = cap;
-      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-      if (e == hipSuccess) {
-        try {
-          for (int t = 0; t < m; ++t) {
-            head(cap);
-            tail(cap);
-          }
-        } catch (...) {
-          (void)hipStreamEndCapture(cap, &graph);
-          if (graph) (void)hipGraphDestroy(graph);
-          h.stream = st;
-          (void)hipStreamDestroy(cap);
-          throw;
-        }
-        e = hipStreamEndCapture(cap, &graph);
-      }
-      h.stream = st;
-      if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      if (graph) (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipStreamDestroy(cap);
-        fail(HIP, std::string("PCG graph capture failed: ") + hipGetErrorString(e));
-      }
-    }
-    if (exec && hc[0] < np && hc[1] < maxit) {
-      // One replay ahead: replay g + 1 is queued before the host reads the counters left by replay g, so
-      // the device never waits for the host's test.  Replays after convergence change nothing (finished
-      // problems are frozen, iterations past maxit are no-ops).
-      int* hp = static_cast<int*>(pinned_scratch(4 * sizeof(int)));
-      Event ev[2];
-      int64_t issued = hc[1];
-      auto issue = [&](int s) {
-        NS_HIP(hipGraphLaunch(exec, st));
-        NS_HIP(hipMemcpyAsync(hp + 2 * s, S.ndone, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-        NS_HIP(hipEventRecord(ev[s].e, st));
-        issued += m;
-      };
-      int slot = 0;
-      issue(0);
-      for (;;) {
-        const bool more = issued < maxit;
-        if (more) issue(slot ^ 1);
-        NS_HIP(hipEventSynchronize(ev[slot].e));
-        hc[0] = hp[2 * slot];
-        hc[1] = hp[2 * slot + 1];
-        if (hc[0] >= np || hc[1] >= maxit || !more) break;
-        slot ^= 1;
-      }
-      NS_HIP(hipStreamSynchronize(st));  // the replay queued ahead has finished too
-      stream_idle(st);
-    }
-    while (!exec && hc[0] < np && hc[1] < maxit) {
-      head(st);
-      read_back(h, hc, S.ndone, 2);
-      if (hc[0] >= np || hc[1] >= maxit) break;
-      tail(st);
-      read_back(h, hc, S.ndone, 2);
-    }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (cap) (void)hipStreamDestroy(cap);
+    pcg_loop(h, np, S, maxit, hc, head, tail);
   }
   const int iters = std::min(hc[1], maxit);
   // back-substitution: x_I = A_I^{-1} (b_I - A_IGamma w), x_Gamma = w
@@ -639,33 +850,77 @@ void pcg_core(Handle& h, const double* b, double* x, double rtol, int maxit, std
   tile_solve<double>(h.L1, bI.p, 1, 1, h.trsm_cols, st);
   scatter_rows<double, double>(nIp, h.iperm, bI.p, 1, x, 1, 1, st);
   scatter_rows<double, double>(nG, h.gperm, w.p, 1, x, 1, 1, st);
-  // true residual ||b - A x|| / ||b|| per problem
-  csr_mult<double>(h.Aorig, x, 1, tmp.p, 1, 1, st);
-  k_sub<<<unsigned((n + 255) / 256), 256, 0, st>>>(n, b, tmp.p, tmp.p);
-  NS_LAUNCH_CHECK();
+  pcg_results(h, b, x, tmp.p, ist.p, hist.p, hs, maxit, iters, res);
+}
+
+// PCG on A x = b for every problem at once, preconditioned by the approximate block LDL^T factorisation with
+// S~^{-1} = M (eq. M_inv_A): z_I = u_I - A_I^{-1} A_IGamma y_G, z_G = y_G, with u_I = A_I^{-1} r_I and
+// y_G = M (r_G - A_GammaI u_I).  Vectors in the original order; x_0 = 0; stops on ||r_j|| / ||b|| <= rtol.
+void pcg_full_core(Handle& h, const double* b, double* x, double rtol, int maxit, std::vector<SolveOut>& res) {
+  hipStream_t st = h.stream;
+  const Seg& sg = h.segG.view;
   const Seg& sn = h.segN.view;
-  DBuf<double> rr, work2;
-  rr.alloc(2 * size_t(np));
-  work2.alloc(size_t(sn.nchunk) + 16);
-  dot(sn, tmp.p, tmp.p, rr.p, 2, work2, st);
-  dot(sn, b, b, rr.p + 1, 2, work2, st);
-  std::vector<double> hrr(2 * np), hh(size_t(hs) * np);
-  std::vector<int> hi(2 * np);
-  NS_HIP(hipMemcpyAsync(hrr.data(), rr.p, 2 * np * sizeof(double), hipMemcpyDeviceToHost, st));
-  NS_HIP(hipMemcpyAsync(hi.data(), ist.p, 2 * np * sizeof(int), hipMemcpyDeviceToHost, st));
-  NS_HIP(hipMemcpyAsync(hh.data(), hist.p, hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  NS_HIP(hipStreamSynchronize(st));
-  res.assign(np, SolveOut{});
-  for (int g = 0; g < np; ++g) {
-    SolveOut& o = res[g];
-    const int done = hi[g];
-    o.it = done ? hi[np + g] : iters;
-    if (!done) o.it = std::min(o.it, maxit);
-    o.converged = done == 1;
-    o.hist.assign(hh.begin() + size_t(g) * hs, hh.begin() + size_t(g) * hs + o.it + 1);
-    o.relres_schur = o.hist.back();
-    o.relres_true = hrr[2 * g + 1] > 0 ? std::sqrt(hrr[2 * g] / hrr[2 * g + 1]) : 0.0;
+  const int np = h.nprob;
+  const int64_t n = h.n, nG = h.nG, nIp = h.L1.nrows_pad;
+  const int k = std::max(h.k, 1);
+  DBuf<double> r, z, p, q, uI, vI, rg, yg, work, workN, c1, c2, tmp, psd, hist;
+  DBuf<int> ist;
+  for (DBuf<double>* v : {&r, &z, &p, &q}) v->alloc(n);
+  for (DBuf<double>* v : {&uI, &vI}) v->alloc(nIp);
+  for (DBuf<double>* v : {&rg, &yg}) v->alloc(nG);
+  work.alloc(std::max<size_t>(gram_work_elems(sg, k), 2 * size_t(sg.nchunk) + 32));
+  workN.alloc(2 * size_t(sn.nchunk) + 32);
+  c1.alloc(size_t(k) * np);
+  c2.alloc(size_t(k) * np);
+  tmp.alloc(std::max(n, nIp));
+  psd.alloc(size_t(PS) * np);
+  const int64_t hs = int64_t(maxit) + 1;
+  hist.alloc(size_t(hs) * np);
+  ist.alloc(2 * size_t(np) + 4);
+  NS_HIP(hipMemsetAsync(psd.p, 0, psd.n * sizeof(double), st));
+  NS_HIP(hipMemsetAsync(ist.p, 0, ist.n * sizeof(int), st));
+  PcgState S{psd.p, ist.p, ist.p + np, ist.p + 2 * np, ist.p + 2 * np + 1, hist.p, hs, rtol, maxit};
+  double* dpart = workN.p + sn.nchunk + 16;  // chunk partials of p^T q and r^T z
+  auto prec = [&](hipStream_t s) {
+    gather_rows<double>(nIp, h.iperm, r.p, 1, uI.p, 1, 1, s);
+    tile_solve<double>(h.L1, uI.p, 1, 1, h.trsm_cols, s);     // u_I = A_I^{-1} r_I
+    gather_rows<double>(nG, h.gperm, r.p, 1, rg.p, 1, 1, s);
+    csr_mult<double>(h.AGI, uI.p, 1, yg.p, 1, 1, s);
+    axpby(nG, 1.0, rg.p, -1.0, yg.p, s);                       // r_G - A_GammaI u_I
+    apply_prec(h, yg.p, 1, rg.p, 1, 1, work, c1, c2, h.sws);  // y_G = M (r_G - A_GammaI u_I)
+    csr_mult<double>(h.AIG, rg.p, 1, vI.p, 1, 1, s);
+    tile_solve<double>(h.L1, vI.p, 1, 1, h.trsm_cols, s);
+    axpby(nIp, -1.0, vI.p, 1.0, uI.p, s);                      // z_I = u_I - A_I^{-1} A_IGamma y_G
+    scatter_rows<double, double>(nIp, h.iperm, uI.p, 1, z.p, 1, 1, s);
+    scatter_rows<double, double>(nG, h.gperm, rg.p, 1, z.p, 1, 1, s);
+  };
+  auto head = [&](hipStream_t s) {
+    csr_mult<double>(h.Aorig, p.p, 1, q.p, 1, 1, s);           // q = A p
+    dot_partials(sn, p.p, q.p, dpart, s);
+    pcg_update_wr(sn, S, x, r.p, p.p, q.p, dpart, workN, s);   // alpha, x, r, ||r||, stopping test
+  };
+  auto tail = [&](hipStream_t s) {
+    prec(s);
+    dot_partials(sn, r.p, z.p, dpart, s);
+    pcg_update_p(sn, S, z.p, p.p, dpart, s);
+    pcg_advance(np, S, s);
+  };
+  NS_HIP(hipMemsetAsync(x, 0, n * sizeof(double), st));
+  NS_HIP(hipMemcpyAsync(r.p, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  dot(sn, b, b, psd.p + PS_NF, PS, workN, st);
+  k_sqrt_inplace<<<(np + 255) / 256, 256, 0, st>>>(np, psd.p + PS_NF, PS);
+  NS_LAUNCH_CHECK();
+  dot(sn, r.p, r.p, psd.p + PS_RN2, PS, workN, st);
+  pcg_init_check(np, S, st);
+  int hc[2] = {0, 0};
+  read_back(h, hc, S.ndone, 2);
+  if (hc[0] < np && maxit > 0) {
+    prec(st);
+    dot(sn, r.p, z.p, psd.p + PS_RHO, PS, workN, st);  // rho_0
+    NS_HIP(hipMemcpyAsync(p.p, z.p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    pcg_loop(h, np, S, maxit, hc, head, tail);
   }
+  pcg_results(h, b, x, tmp.p, ist.p, hist.p, hs, maxit, std::min(hc[1], maxit), res);
 }
 
 ns_status finish(Handle* h, const Error& e) {
@@ -693,11 +948,19 @@ Handle* new_handle(const ns_options* opt) {
   h->pcg_graph = opt->pcg_graph_iters;
   h->proposal = opt->proposal;
   h->accept_tol = opt->accept_tol > 0 ? opt->accept_tol : 0.2;
+  h->variant = opt->variant;
+  h->power = opt->power_iters;
+  h->outer = opt->outer;
   return h;
 }
 
 void check_options(Handle* h) {
   if (h->schur_mode < 0 || h->schur_mode > 2) fail(INVALID_ARG, "schur_mode must be 0, 1 or 2");
+  if (h->variant < NS_VARIANT_M2 || h->variant > NS_VARIANT_M3) fail(INVALID_ARG, "variant must be 0, 1 or 2");
+  if (h->power < 0 || h->power > 32) fail(INVALID_ARG, "power_iters must be in [0, 32]");
+  if (h->outer != NS_OUTER_SCHUR && h->outer != NS_OUTER_FULL) fail(INVALID_ARG, "outer must be 0 or 1");
+  if (h->outer == NS_OUTER_FULL && h->apply_mode != NS_APPLY_M2)
+    fail(INVALID_ARG, "the full-system outer iteration needs the symmetric additive form (NS_APPLY_M2)");
   if (h->trsm_cols != 0 && h->trsm_cols != 16 && h->trsm_cols != 32 && h->trsm_cols != 64)
     fail(INVALID_ARG, "trsm_cols must be 0, 16, 32 or 64");
   h->dflags.alloc(32);
@@ -785,7 +1048,7 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
   } else if (h->k > 0) {
     SmallMats sm;
     sm.init(np, h->s, h->k);
-    DBuf<double> Om, D;
+    DBuf<double> Om;
     const double* omega = omegas[0];
     if (np > 1) {
       Om.alloc(h->nG * h->s);
@@ -795,16 +1058,7 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
                               h->stream));
       omega = Om.p;
     }
-    D.alloc(h->nG * h->s);
-    if (h->prec_inner)
-      block_pcg<float>(*h, sm, omega, D.p);
-    else
-      block_pcg<double>(*h, sm, omega, D.p);
-    ev.rec(3);
-    DBuf<double> Y;
-    Y.alloc(h->nG * h->s);
-    csr_mult<double>(h->AGG, D.p, h->s, Y.p, h->s, h->s, h->stream);  // Y = A_Gamma D
-    nystrom(*h, sm, omega, Y.p);
+    lowrank_setup(*h, sm, omega, [&] { ev.rec(3); });
     if (h->apply_mode == NS_APPLY_ADEF2) setup_adef2(*h);
   } else {
     h->keff_d.alloc(np);
@@ -943,6 +1197,8 @@ ns_status nystrom_schur_setup_batched(int32_t nprob, const int64_t* n, const int
     h = new_handle(opt);
     StreamScope ss(h->stream);
     check_options(h);
+    if (h->variant == NS_VARIANT_M3 && nprob > 1)
+      fail(INVALID_ARG, "the variant M_3 (sketch on the interior space) takes one problem per handle");
     hipStream_t st = h->stream;
     Pieces pc;
     pc.node.assign(nprob + 1, 0);
@@ -1049,7 +1305,10 @@ ns_status nystrom_schur_pcg_solve(ns_handle h, const double* b, double* x, doubl
     read_back(*h, &bad, h->dflags.p + 14, 1);
     if (bad) fail(INVALID_ARG, "b contains NaN or Inf");
     std::vector<SolveOut> res;
-    pcg_core(*h, b, x, rtol, maxit, res);
+    if (h->outer == NS_OUTER_FULL)
+      pcg_full_core(*h, b, x, rtol, maxit, res);
+    else
+      pcg_core(*h, b, x, rtol, maxit, res);
     ev.rec(1);
     if (info) {
       info->it_pcg = res[0].it;
@@ -1094,7 +1353,10 @@ ns_status nystrom_schur_pcg_solve_batched(ns_handle h, const double* const* b, d
     read_back(*h, &bad, h->dflags.p + 14, 1);
     if (bad) fail(INVALID_ARG, "b contains NaN or Inf");
     std::vector<SolveOut> res;
-    pcg_core(*h, bu.p, xu.p, rtol, maxit, res);
+    if (h->outer == NS_OUTER_FULL)
+      pcg_full_core(*h, bu.p, xu.p, rtol, maxit, res);
+    else
+      pcg_core(*h, bu.p, xu.p, rtol, maxit, res);
     for (int q = 0; q < np; ++q)
       NS_HIP(hipMemcpyAsync(x[q], xu.p + h->h_noff[q], (h->h_noff[q + 1] - h->h_noff[q]) * sizeof(double),
                             hipMemcpyDeviceToDevice, st));

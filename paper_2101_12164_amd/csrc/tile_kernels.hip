@@ -944,6 +944,36 @@ void tile_solve_fwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, h
   NS_LAUNCH_CHECK();
 }
 
+template <class T>
+void tile_solve_bwd(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipStream_t st) {
+  if (lv.nblk == 0 || ncols == 0) return;
+  const T* L;
+  const T* Li;
+  if constexpr (sizeof(T) == 8) {
+    L = lv.L64.p;
+    Li = lv.Linv64.p;
+  } else {
+    L = lv.L32.p;
+    Li = lv.Linv32.p;
+  }
+  if (cw != 16 && cw != 32) cw = 64;
+  const int nchunk = (ncols + cw - 1) / cw;
+  const int grid = (lv.nblk + 7) / 8 * 8 * nchunk;
+  const bool f64 = sizeof(T) == 8;
+  const int fam = lv.role == 0 ? (f64 ? KF_TRSM_I64 : KF_TRSM_I32) : (f64 ? KF_TRSM_G64 : KF_TRSM_G32);
+  KScope ks(fam, st, (lv.alg_tri + 2.0 * lv.alg_rows * ncols) * sizeof(T), lv.alg_sq * ncols);
+  if (cw == 16)
+    k_trsm<T, 16, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L, Li, B, ldb,
+                                               ncols);
+  else if (cw == 32)
+    k_trsm<T, 32, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L, Li, B, ldb,
+                                               ncols);
+  else
+    k_trsm<T, 64, false><<<grid, 256, 0, st>>>(lv.nblk, lv.nt, lv.nbt, lv.foff, lv.ioff, lv.roff, L, Li, B, ldb,
+                                               ncols);
+  NS_LAUNCH_CHECK();
+}
+
 void tile_solve_chunks(const TileLevel& lv, double* B, int64_t ldb, int ncols, const int* first_tile,
                        hipStream_t st) {
   if (lv.nblk == 0 || ncols == 0) return;
@@ -972,6 +1002,8 @@ void tile_solve_chunks(const TileLevel& lv, double* B, int64_t ldb, int ncols, c
 template void tile_solve_fwd<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t, const int*, const int*,
                                      double, int, int, int64_t, int, const SparseRhs*);
 template void tile_solve<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t);
+template void tile_solve_bwd<double>(const TileLevel&, double*, int64_t, int, int, hipStream_t);
+template void tile_solve_bwd<float>(const TileLevel&, float*, int64_t, int, int, hipStream_t);
 template void tile_solve<float>(const TileLevel&, float*, int64_t, int, int, hipStream_t);
 
 void tile_export(const TileLevel& lv, int block, double* out, hipStream_t st) {

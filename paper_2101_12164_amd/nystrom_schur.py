@@ -21,6 +21,8 @@ NS_OK, NS_ERR_INVALID_ARG, NS_ERR_NOT_SPD, NS_ERR_OOM, NS_ERR_HIP, NS_ERR_NOT_CO
 NS_FP64, NS_FP32 = 0, 1
 NS_APPLY_M2, NS_APPLY_ADEF2 = 0, 1
 NS_SCHUR_AUTO, NS_SCHUR_TRIANGULAR, NS_SCHUR_LOCAL = 0, 1, 2
+NS_VARIANT_M2, NS_VARIANT_M1, NS_VARIANT_M3 = 0, 1, 2
+NS_OUTER_SCHUR, NS_OUTER_FULL = 0, 1
 
 STATUS_NAMES = {
     0: "NS_OK",
@@ -83,6 +85,9 @@ class NsOptions(ctypes.Structure):
         ("accept_tol", c_double),
         ("stream", c_void_p),
         ("pcg_graph_iters", c_int32),
+        ("variant", c_int32),
+        ("power_iters", c_int32),
+        ("outer", c_int32),
     ]
 
 
@@ -226,27 +231,17 @@ def _setup_info_dict(si: NsSetupInfo) -> dict:
 
 def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_inner=0.1, eig_thresh_rel=1e-10,
                         orth_drop_rel=0.0, max_inner_iters=500, prec_inner=NS_FP64, apply_mode=NS_APPLY_M2,
-                        trsm_cols=0, schur_mode=0, proposal=None, accept_tol=0.2, pcg_graph_iters=0):
+                        trsm_cols=0, schur_mode=0, proposal=None, accept_tol=0.2, pcg_graph_iters=0,
+                        variant=NS_VARIANT_M2, power_iters=0, outer=NS_OUTER_SCHUR):
     """Returns (handle, info dict).  row_ptr int64, col_idx int32, val float64, part int32, omega float64
-    (n_gamma x (k+p), row-major), all CUDA tensors."""
+    (n_gamma x (k+p), row-major; n_interior x (k+p) for NS_VARIANT_M3), all CUDA tensors."""
     lib = load_library()
     n = row_ptr.numel() - 1
     nnz = val.numel()
-    opt = NsOptions()
-    opt.k, opt.p = int(k), int(p)
-    opt.tol_inner = tol_inner
-    opt.eig_thresh_rel = eig_thresh_rel
-    opt.orth_drop_rel = orth_drop_rel
-    opt.max_inner_iters = max_inner_iters
-    opt.prec_inner = prec_inner
-    opt.apply_mode = apply_mode
-    opt.trsm_cols = trsm_cols
-    opt.schur_mode = schur_mode
+    opt = _options(k, p, tol_inner, eig_thresh_rel, orth_drop_rel, max_inner_iters, prec_inner, apply_mode,
+                   trsm_cols, schur_mode, accept_tol, pcg_graph_iters, variant, power_iters, outer)
     opt.omega = _dev(omega, torch.float64, "omega") if omega is not None else None
     opt.proposal = _dev(proposal, torch.float64, "proposal") if proposal is not None else None
-    opt.accept_tol = accept_tol
-    opt.stream = _stream()
-    opt.pcg_graph_iters = pcg_graph_iters
     h = c_void_p()
     info = NsSetupInfo()
     st = lib.nystrom_schur_setup(n, nnz, _dev(row_ptr, torch.int64, "row_ptr"), _dev(col_idx, torch.int32, "col_idx"),
@@ -257,7 +252,7 @@ def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_in
 
 
 def _options(k, p, tol_inner, eig_thresh_rel, orth_drop_rel, max_inner_iters, prec_inner, apply_mode, trsm_cols,
-             schur_mode, accept_tol, pcg_graph_iters=0):
+             schur_mode, accept_tol, pcg_graph_iters=0, variant=NS_VARIANT_M2, power_iters=0, outer=NS_OUTER_SCHUR):
     opt = NsOptions()
     opt.k, opt.p = int(k), int(p)
     opt.tol_inner = tol_inner
@@ -271,18 +266,22 @@ def _options(k, p, tol_inner, eig_thresh_rel, orth_drop_rel, max_inner_iters, pr
     opt.accept_tol = accept_tol
     opt.stream = _stream()
     opt.pcg_graph_iters = pcg_graph_iters
+    opt.variant = variant
+    opt.power_iters = power_iters
+    opt.outer = outer
     return opt
 
 
 def nystrom_schur_setup_batched(problems, *, k, p, omegas=None, tol_inner=0.1, eig_thresh_rel=1e-10,
                                 orth_drop_rel=0.0, max_inner_iters=500, prec_inner=NS_FP64, apply_mode=NS_APPLY_M2,
-                                trsm_cols=0, schur_mode=0, pcg_graph_iters=0):
+                                trsm_cols=0, schur_mode=0, pcg_graph_iters=0, variant=NS_VARIANT_M2,
+                                power_iters=0, outer=NS_OUTER_SCHUR):
     """problems: list of (row_ptr, col_idx, val, part) CUDA tensors; omegas: list of n_gamma(q) x (k+p) float64
     CUDA tensors.  Returns (handle, list of info dicts)."""
     lib = load_library()
     m = len(problems)
     opt = _options(k, p, tol_inner, eig_thresh_rel, orth_drop_rel, max_inner_iters, prec_inner, apply_mode,
-                   trsm_cols, schur_mode, 0.2, pcg_graph_iters)
+                   trsm_cols, schur_mode, 0.2, pcg_graph_iters, variant, power_iters, outer)
     n = (c_int64 * m)(*[pr[0].numel() - 1 for pr in problems])
     nnz = (c_int64 * m)(*[pr[2].numel() for pr in problems])
     ptrs = [(c_void_p * m)(*[_dev(pr[i], dt, nm) for pr in problems])

@@ -68,13 +68,29 @@ def emulated_forward(p32, X):
     return Z0, q, (Xb, A1, H1, A2, H2)
 
 
-def test_forward_and_gradient_match_oracle():
+def c4_features():
+    """Features of the 48^3 lognormal family member 0 (sigma 1.5, 3^3 boxes): the learned layer's input at
+    full size, from the oracle's feature routine."""
+    from workloads import config_c4
+
+    P = config_c4(seed=0)
+    X = L.interface_features(P.n, P.row_ptr, P.col, P.val, P.part, grid_coords(P.shape))
+    return X.astype(np.float32)
+
+
+@pytest.mark.parametrize("case", ["small", "c4_full"])
+def test_forward_and_gradient_match_oracle(case):
     rng = np.random.default_rng(0)
-    n, d_in, h, k = 700, 16, 64, 8
+    if case == "small":
+        n, d_in, h, k = 700, 16, 64, 8
+        X = rng.standard_normal((n, d_in)).astype(np.float32)
+    else:
+        # the full-size configuration: 13 256 interface nodes, network 16 -> 256 -> 256 -> 48
+        X = c4_features()
+        n, d_in, h, k = X.shape[0], 16, 256, 48
     p = make_net(d_in, h, k, 11)
     flat = L.flatten(p).astype(np.float32)
     p32 = L.unflatten(flat.astype(np.float64), d_in, h, k)
-    X = rng.standard_normal((n, d_in)).astype(np.float32)
     U = np.linalg.qr(rng.standard_normal((n, k)))[0]
     m = ns.nystrom_schur_mlp_create(d_in, h, k, flat)
     try:
@@ -102,7 +118,11 @@ def test_forward_and_gradient_match_oracle():
             # the kernels compute exactly the BF16-rounded network; the distance to the FP64 network's
             # gradient is the BF16 rounding amplified by the conditioning of G = Z0^T Z0 at this random init
             assert ee <= 5e-3, name
-            assert eo <= 1e-1 and cos >= 0.99, name
+            # at full size the BF16 rounding of the features themselves (log-coefficients up to ~6 with an
+            # 8-bit significand) moves the first layer's gradient by about a third against the FP64 network
+            # (measured 0.34 for W1 and 0.31 for b1, cosines 0.94 and 0.95)
+            eo_max, cos_min = (1e-1, 0.99) if case == "small" or name not in ("W1", "b1") else (0.5, 0.9)
+            assert eo <= eo_max and cos >= cos_min, name
     finally:
         ns.nystrom_schur_mlp_destroy(m)
 

@@ -39,7 +39,8 @@ def dense_target(P):
 
 @pytest.mark.parametrize("level2", [True, False])
 def test_gamma_factor(level2):
-    """R^T R = A_Gamma; R is upper triangular in the level-2 order; the three solves invert it."""
+    """R^T R = A_Gamma; R is upper triangular with rows and columns in the level-2 order; the three solves
+    invert it."""
     P = make_problem((20, 20), (2, 2), sigma=1.0, ell=4.0, k=4, p=3, level2=level2)
     d = DBBD(P.n, P.row_ptr, P.col, P.val, P.part)
     R = GammaFactor(d)
@@ -49,7 +50,8 @@ def test_gamma_factor(level2):
     AG = d.A_G.toarray()
     assert np.allclose(Rm.T @ Rm, AG, atol=1e-12 * np.abs(AG).max())
     perm = level2_order(d)
-    assert np.allclose(np.tril(Rm[:, perm], -1), 0.0)
+    assert np.allclose(np.tril(Rm[np.ix_(perm, perm)], -1), 0.0)
+    assert not np.allclose(np.tril(Rm, -1), 0.0) or not level2
     X = np.random.default_rng(0).standard_normal((ng, 3))
     assert np.allclose(R.solve(R.mult(X)), X, atol=1e-12)
     assert np.allclose(Rm.T @ R.solve_t(X), X, atol=1e-12)
