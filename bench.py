@@ -38,9 +38,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--grid", type=int, default=64, help="grid side (64 = the benchmark workload)")
-    ap.add_argument("--boxes", type=int, default=4)
-    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32", help="inner block-CG precision")
+    ap.add_argument("--prec", choices=["fp32", "fp64"], default=None,
+                    help="inner block-CG precision of the timed steps (default: fp64 for the single systems, the "
+                         "other precision timed beside it; fp32 for the batched set)")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--trsm-cols", type=int, default=0)
@@ -48,15 +48,18 @@ def parse():
                     help="kernel families timed with HIP events in the measured steps")
     ap.add_argument("--pcg-graph", type=int, default=0,
                     help="PCG iterations per replayed HIP graph (0: library default, -1: plain launches)")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4"], default="c2",
-                    help="c2: the 64^3 lognormal system (default line); c3: the batched anisotropic set; "
-                         "c4: the learned proposal on the 48^3 lognormal family")
+    ap.add_argument("--workload", choices=["c5", "c2", "c3", "c4"], default="c5",
+                    help="c5: the 2048^2 lognormal system (default line); c2: the 64^3 lognormal system; "
+                         "c3: the batched anisotropic set; c4: the learned proposal on the 48^3 lognormal family")
     ap.add_argument("--nprob", type=int, default=256, help="problems of the batched workload")
     ap.add_argument("--ntrain", type=int, default=2000, help="c4: training instances (seeds 0..ntrain-1)")
     ap.add_argument("--nheld", type=int, default=32, help="c4: held-out instances (seeds 10000..)")
     ap.add_argument("--epochs", type=int, default=6, help="c4: passes over the training instances")
     ap.add_argument("--nval", type=int, default=16, help="c4: validation seeds (5000..) for the threshold")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.prec is None:
+        args.prec = "fp32" if args.workload == "c3" else "fp64"
+    return args
 
 
 def dominant_families(stats, scope="dominant"):
@@ -395,6 +398,19 @@ def bench_c3(args):
     print(json.dumps(line))
 
 
+SINGLE = {
+    # workload -> (generator, traffic-profile key, description)
+    "c5": ("config_c5", "lognormal2d_2048",
+           "2D 5-point lognormal diffusion sigma=2 ell=8, 2048^2 grid, 32^2 box subdomains (63^2 interiors), "
+           "k=128 p=32, eps_SI=0.1, rtol 1e-8"),
+    "c2": ("config_c2", "lognormal3d_64",
+           "3D 7-point lognormal diffusion sigma=2 ell=8, 64^3 grid, 4^3 box subdomains, k=64 p=16, eps_SI=0.1, "
+           "rtol 1e-8"),
+}
+BCG_FAMILIES = {"f64": ("local_schur_apply_f64", "interface_inverse_f64"),
+                "f32": ("local_schur_apply_f32", "interface_inverse_f32")}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -409,16 +425,26 @@ def main():
     if args.workload == "c4":
         bench_c4(args)
         return
+    bench_single(args)
+
+
+def bench_single(args):
+    """One system per step (c5 by default, or c2): setup + solve timed per step with plain FP64 inner work
+    (the value) and with the FP32 inner block CG (a sidecar)."""
+    import statistics
 
     import numpy as np
     import torch
 
     import paper_2101_12164_amd as ns
-    from workloads import config_c2
+    import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    gen, traffic_key, desc = SINGLE[args.workload]
+    t0 = time.perf_counter()
+    P = getattr(workloads, gen)()
+    print(f"generated {args.workload} (n={P.n}) in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     dev = "cuda"
-    P = config_c2(N=args.grid, nb=args.boxes)
 
     def T(a, dt):
         return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
@@ -434,16 +460,31 @@ def main():
     del cal
     torch.cuda.synchronize()
 
-    def step(prec):
+    def step(prec, solve=True):
         s = ns.NystromSchur(A["row_ptr"], A["col_idx"], A["val"], A["part"], k=P.k, p=P.p, omega=omega,
                             tol_inner=P.tol_inner, prec_inner=prec, trsm_cols=args.trsm_cols,
                             pcg_graph_iters=args.pcg_graph)
-        x, info = s.solve(b, rtol=P.tol_outer, maxit=2000)
+        info = None
+        if solve:
+            x, info = s.solve(b, rtol=P.tol_outer, maxit=4000)
         si = s.setup_info
         s.close()
         return si, info
 
-    main_prec = ns.NS_FP32 if args.prec == "fp32" else ns.NS_FP64
+    def timed_steps(prec, n):
+        out, secs = [], []
+        for i in range(n):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            out.append(step(prec))
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t1)
+            print(f"{'fp64' if prec == ns.NS_FP64 else 'fp32-inner'} step {i}: {secs[-1] * 1e3:.1f} ms",
+                  file=sys.stderr, flush=True)
+        return out, secs
+
+    main_prec = ns.NS_FP64 if args.prec == "fp64" else ns.NS_FP32
+    side_prec = ns.NS_FP32 if main_prec == ns.NS_FP64 else ns.NS_FP64
     # warmup with every kernel family timed: it names the dominant family, the only one timed in the
     # measured steps (events around every launch would perturb the measured throughput)
     ns.nystrom_schur_kernel_timing(True)
@@ -455,59 +496,47 @@ def main():
     ns.nystrom_schur_kernel_timing_families(timed)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    runs = []
-    for i in range(args.steps):
-        runs.append(step(main_prec))
-        print(f"step {i} done", file=sys.stderr, flush=True)
+    runs, secs = timed_steps(main_prec, args.steps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    t_region = time.perf_counter() - t0
     stats = {f: ns.nystrom_schur_kernel_stats(f) for f in ns.KERNEL_FAMILIES}
     ns.nystrom_schur_kernel_timing(False)
-    sec = (t1 - t0) / args.steps
+    sec = statistics.median(secs)
     si, info = runs[-1]
 
-    # factor bytes streamed per Schur apply (forward + backward sweep, algorithmic)
-    bp = np.bincount(P.part[P.part >= 0])
-    tri = float(np.sum(bp * (bp + 1) / 2))
+    # the other inner precision, timed the same way after the measured region
+    side = None
+    if not args.no_fp64_compare:
+        step(side_prec)
+        side_runs, side_secs = timed_steps(side_prec, max(1, args.steps))
+        ssi, sinfo = side_runs[-1]
+        side = {"sec_per_step_median": statistics.median(side_secs), "sec_per_step": side_secs,
+                "it_SI": ssi["it_inner"], "it_PCG": sinfo["it_pcg"], "relres_true": sinfo["relres_true"],
+                "t_setup_s": ssi["t_total"], "t_solve_s": sinfo["t_solve"], "t_inner_s": ssi["t_inner"]}
 
-    def bcg_gbs(si_, prec):
-        napply = si_["it_inner"] + 1
-        by = napply * 2.0 * tri * (4 if prec == ns.NS_FP32 else 8)
-        return by / si_["t_inner"] / 1e9 if si_["t_inner"] > 0 else None
+    # Schur-BCG HBM GB/s: bytes the inner block CG's operator applications move (the explicit local Schur
+    # blocks, the interface-level inverses and the block vectors they read and write, each once per apply)
+    # over the HIP-event time of those launches, from one setup (no solve) per inner precision
+    def bcg_gbs(prec):
+        key = "f64" if prec == ns.NS_FP64 else "f32"
+        ns.nystrom_schur_kernel_timing_families(list(BCG_FAMILIES[key]))
+        step(prec, solve=False)
+        st_ = [ns.nystrom_schur_kernel_stats(f) for f in BCG_FAMILIES[key]]
+        ns.nystrom_schur_kernel_timing(False)
+        by = sum(x["bytes"] for x in st_)
+        ms = sum(x["ms"] for x in st_)
+        return {"gbs": by / (ms * 1e-3) / 1e9 if ms else None, "bytes": by, "ms": ms,
+                "launches": int(sum(x["launches"] for x in st_)), "families": list(BCG_FAMILIES[key])}
 
-    out_extra = {
-        "it_SI": si["it_inner"],
-        "it_PCG": info["it_pcg"],
-        "relres_true": info["relres_true"],
-        "relres_schur": info["relres_schur"],
-        "k_eff": si["k_eff"],
-        "t_setup_s": si["t_total"],
-        "t_solve_s": info["t_solve"],
-        "t_phases_s": {k: si[k] for k in ("t_extract", "t_factor", "t_inner", "t_nystrom")},
-        "schur_bcg_gbs": bcg_gbs(si, main_prec),
-    }
-    if not args.no_fp64_compare and main_prec != ns.NS_FP64:
-        t2 = time.perf_counter()
-        si64, info64 = step(ns.NS_FP64)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        print("fp64 comparison step done", file=sys.stderr, flush=True)
-        out_extra["plain_fp64"] = {
-            "sec_per_step": t3 - t2,
-            "it_SI": si64["it_inner"],
-            "it_PCG": info64["it_pcg"],
-            "relres_true": info64["relres_true"],
-            "t_inner_s": si64["t_inner"],
-            "schur_bcg_gbs": bcg_gbs(si64, ns.NS_FP64),
-        }
+    gbs_main = bcg_gbs(main_prec)
+    gbs_side = bcg_gbs(side_prec) if side is not None else None
 
-    # dominant kernel family in the timed region -> roofline
     kern = {f: {"ms_total": v["ms"], "launches": v["launches"],
                 "gbs": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] else None,
                 "tflops": v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] else None}
             for f, v in stats.items() if v["launches"]}
-    roof = roofline(stats, args.steps, workload=f"lognormal3d_{args.grid}" if args.boxes == 4 else None)
-
+    roof = roofline(stats, args.steps, workload=traffic_key)
+    prec_name = "fp64" if main_prec == ns.NS_FP64 else "fp32"
     line = {
         "metric": METRIC,
         "value": sec,
@@ -516,59 +545,133 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": sec * 1e3,
+        "mean_ms_per_step": t_region / args.steps * 1e3,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 (inner block CG f32)" if main_prec == ns.NS_FP32 else "f64",
+        "dtype": "f64" if main_prec == ns.NS_FP64 else "f64 (inner block CG f32)",
         "data": "synthetic",
-        "config": {"workload": f"3D 7-point lognormal diffusion sigma=2 ell=8, {args.grid}^3 grid, "
-                               f"{args.boxes}^3 box subdomains, k={P.k} p={P.p}, eps_SI=0.1, rtol 1e-8",
-                   "n": P.n, "n_gamma": P.n_gamma, "inner_prec": args.prec},
+        "config": {"workload": desc, "n": P.n, "n_gamma": P.n_gamma, "inner_prec": prec_name},
         "roofline": roof,
         "kernels": kern,
+        "it_SI": si["it_inner"],
+        "it_PCG": info["it_pcg"],
+        "relres_true": info["relres_true"],
+        "relres_schur": info["relres_schur"],
+        "k_eff": si["k_eff"],
+        "t_setup_s": si["t_total"],
+        "t_solve_s": info["t_solve"],
+        "t_phases_s": {k: si[k] for k in ("t_extract", "t_factor", "t_inner", "t_nystrom")},
+        "schur_bcg_gbs": gbs_main["gbs"],
+        "schur_bcg": {prec_name: gbs_main},
     }
-    line.update(out_extra)
-
+    if side is not None:
+        side_name = "fp32" if side_prec == ns.NS_FP32 else "fp64"
+        side["schur_bcg_gbs"] = gbs_side["gbs"] if gbs_side else None
+        line["fp32_inner" if side_prec == ns.NS_FP32 else "plain_fp64"] = side
+        line["schur_bcg"][side_name] = gbs_side
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(P, si["it_inner"], info["it_pcg"])
     print(json.dumps(line))
 
 
-def cpu_baseline(P, it_si, it_pcg):
-    """FP64 oracle timed on the host on a bounded sample of the same workload.
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    Sample: the oracle's factorisation (dense LAPACK Cholesky of every interior
-    block, sparse factorisation of A_Gamma), one Schur-operator application
-    with k+p columns and one outer PCG iteration (S apply + A_Gamma solve).
-    Scaled to one full step: the block-CG applications x (it_SI + 1), the PCG
-    iteration x it_PCG (the iteration counts measured on the GPU).
+
+def cpu_baseline(P, it_si, it_pcg):
+    """The FP64 oracle timed on the host cores on a bounded sample of the same workload, scaled to one step.
+
+    Timed whole: the DBBD split and the factorisation of every interior block and of A_Gamma; the Nystrom core
+    and Z = A_Gamma^{-1} U; the reduction of b and the back-substitution.  Sampled: the block CG's first
+    iteration (with the right-hand side W Omega and the first orthonormalisation) and one later iteration
+    (S_Gamma and A_Gamma^{-1} on k+p columns, the Gram products, the block update, the orthonormalisation),
+    scaled by it_SI; three outer PCG iterations, scaled by it_PCG (the iteration counts the GPU measured; the
+    oracle reaches the same counts within one where it runs whole).  Interior factors are dense LAPACK
+    Cholesky blocks up to 4096 unknowns per block times 64 blocks, SuperLU factors otherwise (same result to
+    rounding); A_Gamma is factorised by SuperLU.
     """
     import numpy as np
+    import scipy.linalg as sla
 
-    from oracle import DBBD, Operators
+    from oracle import DBBD, Operators, bf_bpcg, nystrom_core, orth, pcg
+
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_info = threadpool_limits = None
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1]) if threadpool_info else 0
 
     t = {}
     t0 = time.perf_counter()
     d = DBBD(P.n, P.row_ptr, P.col, P.val, P.part)
-    ops = Operators(d, factor="dense", gamma_factor="sparse")
+    nb = np.diff(d.block_ptr)
+    factor = "dense" if d.n_sub <= 64 and nb.max() <= 4096 else "sparse"
+    ops = Operators(d, factor=factor, gamma_factor="sparse")
     t["extract_factor"] = time.perf_counter() - t0
     s = P.k + P.p
-    X = np.random.default_rng(0).standard_normal((d.n_gamma, s))
+    Om = P.omega()
     t0 = time.perf_counter()
-    ops.S(X)
-    ops.solve_G(X)
-    t["bcg_apply"] = time.perf_counter() - t0
-    r = np.random.default_rng(1).standard_normal(d.n_gamma)
+    F = ops.W(Om)
+    first = bf_bpcg(ops.S, ops.solve_G, F, 0.0, 1, 1e-6)
+    t["bcg_first_iteration"] = time.perf_counter() - t0
+
+    def bcg_iteration():
+        Pm = orth(ops.solve_G(F), 1e-6)
+        Q = ops.S(Pm)
+        Delta = Pm.T @ Q
+        cf = sla.cho_factor(0.5 * (Delta + Delta.T), lower=True)
+        alpha = sla.cho_solve(cf, Pm.T @ F)
+        X = Pm @ alpha
+        R = F - Q @ alpha
+        Z = ops.solve_G(R)
+        beta = -sla.cho_solve(cf, Q.T @ Z)
+        return X, orth(Z + Pm @ beta, 1e-6)
+
     t0 = time.perf_counter()
-    ops.S(r)
-    ops.solve_G(r)
-    t["pcg_iter"] = time.perf_counter() - t0
-    est = t["extract_factor"] + (it_si + 1) * t["bcg_apply"] + it_pcg * t["pcg_iter"]
-    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    return {"value": est, "unit": "s", "cores": int(threads), "kind": "oracle",
-            "sample": f"oracle DBBD split + factorisation of all {d.n_sub} blocks and A_Gamma (x1), one block-CG "
-                      f"application S and A_Gamma^-1 on {s} columns (x{it_si + 1}), one PCG iteration (x{it_pcg}); "
-                      f"seconds {json.dumps({k: round(v, 3) for k, v in t.items()})}"}
+    bcg_iteration()
+    t["bcg_iteration"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Y = d.A_G @ first.X
+    U, Sig, _ = nystrom_core(Y, Om, P.k)
+    Zl = ops.solve_G(U)
+    t["nystrom"] = time.perf_counter() - t0
+    b = P.b()
+    t0 = time.perf_counter()
+    f = b[d.G] - d.A_GI @ ops.solve_I(b[d.I])
+    t["reduce_rhs"] = time.perf_counter() - t0
+
+    def M(r):
+        return ops.solve_G(r) + Zl @ (Sig * (Zl.T @ r))
+
+    t0 = time.perf_counter()
+    res = pcg(ops.S, M, f, 0.0, 3)
+    t["pcg_3_iterations"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ops.solve_I(b[d.I] - d.A_IG @ res.w)
+    t["back_substitution"] = time.perf_counter() - t0
+    est = (t["extract_factor"] + t["bcg_first_iteration"] + max(it_si - 1, 0) * t["bcg_iteration"] + t["nystrom"]
+           + t["reduce_rhs"] + it_pcg * t["pcg_3_iterations"] / 3.0 + t["back_substitution"])
+    one = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            bcg_iteration()
+            one = time.perf_counter() - t0
+    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle", "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(), "factor": factor,
+            "bcg_iteration_s": t["bcg_iteration"], "bcg_iteration_1thread_s": one,
+            "sample": f"oracle on the full system: split + {factor} factorisation of all {d.n_sub} blocks and of "
+                      f"A_Gamma, Nystrom core, reduction and back-substitution timed whole; block CG first "
+                      f"iteration + one iteration on {s} columns (x{max(it_si - 1, 0)}), 3 PCG iterations "
+                      f"(x{it_pcg}/3); seconds {json.dumps({k: round(v, 3) for k, v in t.items()})}"}
 
 
 if __name__ == "__main__":

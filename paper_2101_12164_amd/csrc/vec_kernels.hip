@@ -250,6 +250,90 @@ __global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* __restric
     }
 }
 
+// The same product for wide blocks (more than 80 columns): one workgroup computes all NTI column tiles of its
+// 64 rows, so X is read once and no column tile is computed twice; K is staged in batches of 16 rows of M,
+// double-buffered in LDS with the next batch's global loads in flight during the current batch's products (one
+// barrier per batch).  The sums over K run in the same order as in k_ts_mfma (same bits).
+constexpr int TW_K = 16;
+template <class T, int NTI>
+__global__ __launch_bounds__(256, 2) void k_ts_wide(Seg sg, int ncols, T* __restrict__ Out, int64_t ldo, double beta,
+                                                 double gamma, const T* __restrict__ X, int64_t ldx, int K,
+                                                 const double* __restrict__ M, int64_t ldm, int64_t mstride) {
+  constexpr int NC = 16 * NTI;
+  constexpr int XS = TW_K + 1, MS = NC + 1;
+  __shared__ double sX[2][64 * XS];
+  __shared__ double sM[2][TW_K * MS];
+  const int p = seg_of(sg.toff, sg.n, blockIdx.x);
+  const int64_t rbase = sg.off[p] + int64_t(blockIdx.x - sg.toff[p]) * 64;
+  const int64_t rend = sg.off[p + 1];
+  const double* Mp = M + int64_t(p) * mstride;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  gv4d acc[NTI];
+#pragma unroll
+  for (int t = 0; t < NTI; ++t) acc[t] = gv4d{0.0, 0.0, 0.0, 0.0};
+  constexpr int PX = 64 * TW_K / 256, PM = (TW_K * NC + 255) / 256;
+  T xv[PX];
+  double mv[PM];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+      const int e = threadIdx.x + 256 * q, r = e / TW_K, k = k0 + e % TW_K;
+      const int64_t row = rbase + r;
+      const bool ok = row < rend && k < K;
+      xv[q] = X[(ok ? row : rbase) * ldx + (ok ? k : 0)];
+    }
+#pragma unroll
+    for (int q = 0; q < PM; ++q) {
+      const int e = threadIdx.x + 256 * q, c = e % NC, k = k0 + e / NC;
+      const bool ok = e < TW_K * NC && c < ncols && k < K;
+      mv[q] = Mp[int64_t(ok ? k : 0) * ldm + (ok ? c : 0)];
+    }
+  };
+  auto store = [&](int k0, int buf) {
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+      const int e = threadIdx.x + 256 * q, r = e / TW_K, kk = e % TW_K;
+      const bool ok = rbase + r < rend && k0 + kk < K;
+      sX[buf][r * XS + kk] = ok ? double(xv[q]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PM; ++q) {
+      const int e = threadIdx.x + 256 * q, cc = e % NC, kk = e / NC;
+      const bool ok = cc < ncols && k0 + kk < K;
+      if (e < TW_K * NC) sM[buf][kk * MS + cc] = ok ? mv[q] : 0.0;
+    }
+  };
+  load(0);
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += TW_K, buf ^= 1) {
+    store(k0, buf);
+    __syncthreads();
+    if (k0 + TW_K < K) load(k0 + TW_K);
+    const double* xs = sX[buf];
+    const double* ms = sM[buf];
+#pragma unroll
+    for (int kk = 0; kk < TW_K; kk += 4) {
+      const double a = xs[(16 * w + li) * XS + kk + lk];
+#pragma unroll
+      for (int t = 0; t < NTI; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ms[(kk + lk) * MS + 16 * t + li], acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NTI; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = rbase + 16 * w + 4 * v + lk;
+      const int c = 16 * t + li;
+      if (r < rend && c < ncols) {
+        double y = gamma * acc[t][v];
+        if (beta != 0.0) y += beta * double(Out[r * ldo + c]);
+        Out[r * ldo + c] = T(y);
+      }
+    }
+}
+
 template <class T>
 void ts_launch(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, double gamma, const T* X, int64_t ldx,
                int K, const double* M, int64_t ldm, int64_t mstride, hipStream_t st) {
@@ -259,6 +343,27 @@ void ts_launch(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, doubl
     dim3 g(unsigned(sg.ntile), unsigned((tiles + N - 1) / N));
     k_ts_mfma<T, N><<<g, 256, 0, st>>>(sg, ncols, Out, ldo, beta, gamma, X, ldx, K, M, ldm, mstride);
   };
+  auto wide = [&](auto nti) {
+    constexpr int N = decltype(nti)::value;
+    k_ts_wide<T, N><<<unsigned(sg.ntile), 256, 0, st>>>(sg, ncols, Out, ldo, beta, gamma, X, ldx, K, M, ldm, mstride);
+  };
+  if (tiles > 5 && tiles <= 16) {
+    switch (tiles) {
+      case 6: wide(std::integral_constant<int, 6>()); break;
+      case 7: wide(std::integral_constant<int, 7>()); break;
+      case 8: wide(std::integral_constant<int, 8>()); break;
+      case 9: wide(std::integral_constant<int, 9>()); break;
+      case 10: wide(std::integral_constant<int, 10>()); break;
+      case 11: wide(std::integral_constant<int, 11>()); break;
+      case 12: wide(std::integral_constant<int, 12>()); break;
+      case 13: wide(std::integral_constant<int, 13>()); break;
+      case 14: wide(std::integral_constant<int, 14>()); break;
+      case 15: wide(std::integral_constant<int, 15>()); break;
+      default: wide(std::integral_constant<int, 16>()); break;
+    }
+    NS_LAUNCH_CHECK();
+    return;
+  }
   if (tiles <= 1)
     go(std::integral_constant<int, 1>());
   else if (tiles <= 2)
