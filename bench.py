@@ -7,15 +7,17 @@ block CG on the shifted Schur system (k+p sketch columns, eps_SI = 0.1), the
 Nystrom core, and the PCG solve of A x = b to relative residual 1e-8 with the
 block LDL^T back-substitution.
 
-Workload (default): 3D 7-point lognormal diffusion (sigma 2, correlation 8
-cells) on a 64^3 grid, 4x4x4 box subdomains, k = 64, p = 16; inner block CG
-in FP32 (FP32 factors and block vectors, MFMA), everything else FP64.  A plain
-FP64 step is timed beside it for the "vs plain FP64" part of the metric.
+Workload (default): 2D 5-point lognormal diffusion (sigma 2, correlation 8
+cells) on a 2048^2 grid, 32x32 box subdomains (63^2 interiors), k = 128,
+p = 32, everything FP64 (the value).  The same step with the inner block CG in
+FP32 and with BF16 operator operands is timed beside it, each with its counts
+and its preconditioner's distance to the FP64 one.  --workload c2 runs the
+64^3 lognormal system, c3 the batched anisotropic set, c4 the learned proposal.
 
-Prints ONE JSON line.  `value` = seconds per step (setup + solve); lower is
-better.  `roofline` is computed live from HIP events bracketing every launch
-of the dominant kernel family inside the timed region; `cpu_baseline` times
-the FP64 oracle on the host on a bounded sample of the same workload.
+Prints ONE JSON line.  `value` = median seconds per step (setup + solve);
+lower is better.  `roofline` is computed live from HIP events bracketing every
+launch of the dominant kernel family inside the timed region; `cpu_baseline`
+times the FP64 oracle on the host on a bounded sample of the same workload.
 """
 
 import argparse
@@ -38,7 +40,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", choices=["fp32", "fp64"], default=None,
+    ap.add_argument("--prec", choices=["fp32", "fp64", "bf16"], default=None,
                     help="inner block-CG precision of the timed steps (default: fp64 for the single systems, the "
                          "other precision timed beside it; fp32 for the batched set)")
     ap.add_argument("--no-fp64-compare", action="store_true")
@@ -69,7 +71,8 @@ def dominant_families(stats, scope="dominant"):
         return []
     if scope == "all":
         return list(stats)
-    dom = max(stats, key=lambda f: stats[f]["ms"])
+    work = {f: v for f, v in stats.items() if v["bytes"] > 0 or v["flops"] > 0}
+    dom = max(work or stats, key=lambda f: stats[f]["ms"])
     return ["chol_update", "chol_panel"] if dom.startswith("chol") else [dom]
 
 
@@ -99,7 +102,12 @@ def measured_traffic(family, workload):
 
 def roofline(stats, steps, workload=None):
     """Roofline of the dominant kernel family from the live HIP-event totals."""
-    dom = max(stats, key=lambda f: stats[f]["ms"])
+    # the dominant family among those with algorithmic work (the one-workgroup s x s kernels carry none:
+    # they are latency-bound and have no roofline of their own)
+    work = {f: v for f, v in stats.items() if v["bytes"] > 0 or v["flops"] > 0}
+    if not work:
+        return None
+    dom = max(work, key=lambda f: work[f]["ms"])
     d = stats[dom]
     if not d["launches"]:
         return None
@@ -408,7 +416,8 @@ SINGLE = {
            "rtol 1e-8"),
 }
 BCG_FAMILIES = {"f64": ("local_schur_apply_f64", "interface_inverse_f64"),
-                "f32": ("local_schur_apply_f32", "interface_inverse_f32")}
+                "f32": ("local_schur_apply_f32", "interface_inverse_f32"),
+                "bf16": ("local_schur_apply_bf16", "interface_inverse_bf16")}
 
 
 def main():
@@ -479,12 +488,11 @@ def bench_single(args):
             out.append(step(prec))
             torch.cuda.synchronize()
             secs.append(time.perf_counter() - t1)
-            print(f"{'fp64' if prec == ns.NS_FP64 else 'fp32-inner'} step {i}: {secs[-1] * 1e3:.1f} ms",
+            print(f"{['fp64', 'fp32-inner', 'bf16-inner'][prec]} step {i}: {secs[-1] * 1e3:.1f} ms",
                   file=sys.stderr, flush=True)
         return out, secs
 
-    main_prec = ns.NS_FP64 if args.prec == "fp64" else ns.NS_FP32
-    side_prec = ns.NS_FP32 if main_prec == ns.NS_FP64 else ns.NS_FP64
+    main_prec = {"fp64": ns.NS_FP64, "fp32": ns.NS_FP32, "bf16": ns.NS_BF16}[args.prec]
     # warmup with every kernel family timed: it names the dominant family, the only one timed in the
     # measured steps (events around every launch would perturb the measured throughput)
     ns.nystrom_schur_kernel_timing(True)
@@ -504,21 +512,38 @@ def bench_single(args):
     sec = statistics.median(secs)
     si, info = runs[-1]
 
-    # the other inner precision, timed the same way after the measured region
-    side = None
+    # the other inner precisions, timed the same way after the measured region; each result also reports
+    # ||M^mixed r - M^fp64 r|| / ||M^fp64 r|| for four random interface vectors
+    R = torch.as_tensor(np.random.default_rng(77).standard_normal((P.n_gamma, 4)), device=dev)
+
+    def apply_of(prec):
+        s = ns.NystromSchur(A["row_ptr"], A["col_idx"], A["val"], A["part"], k=P.k, p=P.p, omega=omega,
+                            tol_inner=P.tol_inner, prec_inner=prec)
+        z = s.apply(R)
+        s.close()
+        return z
+
+    sides = {}
     if not args.no_fp64_compare:
-        step(side_prec)
-        side_runs, side_secs = timed_steps(side_prec, max(1, args.steps))
-        ssi, sinfo = side_runs[-1]
-        side = {"sec_per_step_median": statistics.median(side_secs), "sec_per_step": side_secs,
-                "it_SI": ssi["it_inner"], "it_PCG": sinfo["it_pcg"], "relres_true": sinfo["relres_true"],
-                "t_setup_s": ssi["t_total"], "t_solve_s": sinfo["t_solve"], "t_inner_s": ssi["t_inner"]}
+        ref = apply_of(ns.NS_FP64)
+        others = [ns.NS_FP32, ns.NS_BF16] if main_prec == ns.NS_FP64 else [ns.NS_FP64]
+        for sp in others:
+            step(sp)
+            side_runs, side_secs = timed_steps(sp, max(1, args.steps))
+            ssi, sinfo = side_runs[-1]
+            name = {ns.NS_FP64: "plain_fp64", ns.NS_FP32: "fp32_inner", ns.NS_BF16: "bf16_inner"}[sp]
+            sides[name] = {"sec_per_step_median": statistics.median(side_secs), "sec_per_step": side_secs,
+                           "it_SI": ssi["it_inner"], "it_PCG": sinfo["it_pcg"], "relres_true": sinfo["relres_true"],
+                           "t_setup_s": ssi["t_total"], "t_solve_s": sinfo["t_solve"],
+                           "t_inner_s": ssi["t_inner"], "inner_bf16_schur": ssi.get("inner_bf16_schur"),
+                           "apply_rel_err_vs_fp64": float(torch.linalg.norm(apply_of(sp) - ref) /
+                                                          torch.linalg.norm(ref))}
 
     # Schur-BCG HBM GB/s: bytes the inner block CG's operator applications move (the explicit local Schur
     # blocks, the interface-level inverses and the block vectors they read and write, each once per apply)
     # over the HIP-event time of those launches, from one setup (no solve) per inner precision
     def bcg_gbs(prec):
-        key = "f64" if prec == ns.NS_FP64 else "f32"
+        key = {ns.NS_FP64: "f64", ns.NS_FP32: "f32", ns.NS_BF16: "bf16"}[prec]
         ns.nystrom_schur_kernel_timing_families(list(BCG_FAMILIES[key]))
         step(prec, solve=False)
         st_ = [ns.nystrom_schur_kernel_stats(f) for f in BCG_FAMILIES[key]]
@@ -529,14 +554,13 @@ def bench_single(args):
                 "launches": int(sum(x["launches"] for x in st_)), "families": list(BCG_FAMILIES[key])}
 
     gbs_main = bcg_gbs(main_prec)
-    gbs_side = bcg_gbs(side_prec) if side is not None else None
 
     kern = {f: {"ms_total": v["ms"], "launches": v["launches"],
                 "gbs": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] else None,
                 "tflops": v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] else None}
             for f, v in stats.items() if v["launches"]}
     roof = roofline(stats, args.steps, workload=traffic_key)
-    prec_name = "fp64" if main_prec == ns.NS_FP64 else "fp32"
+    prec_name = ["fp64", "fp32", "bf16"][main_prec]
     line = {
         "metric": METRIC,
         "value": sec,
@@ -549,7 +573,7 @@ def bench_single(args):
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if main_prec == ns.NS_FP64 else "f64 (inner block CG f32)",
+        "dtype": ["f64", "f64 (inner block CG f32)", "f64 (inner block CG f32, bf16 operator operands)"][main_prec],
         "data": "synthetic",
         "config": {"workload": desc, "n": P.n, "n_gamma": P.n_gamma, "inner_prec": prec_name},
         "roofline": roof,
@@ -565,11 +589,12 @@ def bench_single(args):
         "schur_bcg_gbs": gbs_main["gbs"],
         "schur_bcg": {prec_name: gbs_main},
     }
-    if side is not None:
-        side_name = "fp32" if side_prec == ns.NS_FP32 else "fp64"
-        side["schur_bcg_gbs"] = gbs_side["gbs"] if gbs_side else None
-        line["fp32_inner" if side_prec == ns.NS_FP32 else "plain_fp64"] = side
-        line["schur_bcg"][side_name] = gbs_side
+    for name, side in sides.items():
+        sp = {"plain_fp64": ns.NS_FP64, "fp32_inner": ns.NS_FP32, "bf16_inner": ns.NS_BF16}[name]
+        g_ = bcg_gbs(sp)
+        side["schur_bcg_gbs"] = g_["gbs"]
+        line[name] = side
+        line["schur_bcg"][{"plain_fp64": "fp64", "fp32_inner": "fp32", "bf16_inner": "bf16"}[name]] = g_
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(P, si["it_inner"], info["it_pcg"])
     print(json.dumps(line))

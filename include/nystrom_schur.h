@@ -58,7 +58,18 @@ typedef enum {
   NS_ERR_BREAKDOWN = 6      /* block CG lost every search direction / zero curvature          */
 } ns_status;
 
-typedef enum { NS_FP64 = 0, NS_FP32 = 1 } ns_prec;
+/*
+ * Precision of the inner block CG (the loose-tolerance solve of Algorithm alg:prec1 step 3):
+ *   NS_FP64: everything FP64;
+ *   NS_FP32: FP32 factors, local Schur blocks, interface inverses and block vectors, MFMA f32;
+ *   NS_BF16: FP32 block vectors; the local Schur blocks and the interface-level inverses are applied as
+ *            BF16 operands (round to nearest even) of 16x16x32 BF16 MFMA with FP32 accumulation (needs the
+ *            local Schur operator and explicit interface inverses; otherwise those applications run in FP32).
+ *            If the block CG breaks down on the BF16 Schur operator, it is run again with FP32 Schur operands
+ *            (ns_setup_info.inner_bf16_schur says which ran).
+ * The Nystrom core, the coarse deflation solve and the outer PCG (operator and residual) stay FP64.
+ */
+typedef enum { NS_FP64 = 0, NS_FP32 = 1, NS_BF16 = 2 } ns_prec;
 
 typedef enum {
   NS_APPLY_M2 = 0,    /* z = A_Gamma^{-1} r + Z (Sigma o Z^T r)            eq. (left_prec_mat)  */
@@ -144,6 +155,10 @@ typedef struct {
   int32_t bad_block, bad_col;/* location of a non-positive pivot (NS_ERR_NOT_SPD), else -1        */
   double inner_relres;       /* final max column relative residual of block CG                    */
   double t_extract, t_factor, t_inner, t_nystrom, t_total;
+  int32_t inner_bf16_schur;  /* NS_BF16: 1 if the Schur operator of the inner block CG ran on BF16 operands
+                                to the end; 0 if the block CG broke down with them (P^T S P not positive
+                                definite: S_Gamma's small eigenvalues below BF16 resolution) and was run again
+                                with FP32 Schur operands (the preconditioner keeps its BF16 operands)      */
 } ns_setup_info;
 
 /* Outputs of pcg_solve(), HOST memory. */
@@ -338,7 +353,8 @@ void nystrom_schur_kernel_timing_families(uint32_t mask);
  * "trsm_interface_f32" (forward and backward sweeps), "schur_epi", "spmm",
  * "local_schur_form", "local_schur_apply_f64", "local_schur_apply_f32",
  * "interface_inverse_f64", "interface_inverse_f32", "mlp_forward_bf16",
- * "mlp_backward_f32".
+ * "mlp_backward_f32", "local_schur_apply_bf16", "interface_inverse_bf16", "gram" (block-vector Gram
+ * products), "block_update" (block updates X M), "small_dense" (the one-workgroup s x s kernels).
  * Waits for the recorded events.  All outputs are HOST pointers (may be NULL).
  * NS_ERR_INVALID_ARG for an unknown family. */
 ns_status nystrom_schur_kernel_stats(const char* family, double* total_ms, int64_t* launches, double* bytes,

@@ -619,6 +619,118 @@ __global__ __launch_bounds__(256) void k_gather_ls(int64_t nrows, const int32_t*
   for (int c = lane; c < ncols; c += TPR) Out[row * ldo + c] = s >= 0 ? R[int64_t(s) * ldr + c] : T(0);
 }
 
+// C_j = S_j B_j with S_j symmetric and stored as BF16 (so S_j^T = S_j: rows of S_j are read with their K
+// entries contiguous), B_j FP32, C_j FP32: 16x16x32 BF16 MFMA with FP32 accumulation.  A workgroup computes a
+// 64 x 64 tile of C_j (four waves in 2 x 2, each 32 x 32 = 2 x 2 MFMA tiles); K is staged by 64 through LDS,
+// both operands with K contiguous (B converted to BF16, round to nearest even, and transposed on the way in),
+// so each lane reads its eight K values of an operand in one 16-byte LDS load.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint16_t f32_to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return uint16_t((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+constexpr int BKB = 64, BSP = BKB + 8;  // K per batch, LDS row stride (uint16)
+__global__ __launch_bounds__(256) void k_gemm_bf16_sym(GemmBatch g, const uint16_t* __restrict__ A,
+                                                       const float* __restrict__ B, float* __restrict__ C, int N,
+                                                       int gx, int gy, int nb) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[64 * BSP];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[64 * BSP];
+  const int tiles = gx * gy;
+  int j, t;
+  if (nb < 8) {
+    j = int(blockIdx.x) / tiles;
+    t = int(blockIdx.x) % tiles;
+  } else {
+    const int slot = int(blockIdx.x >> 3), x = int(blockIdx.x & 7), lb = slot / tiles;
+    t = slot % tiles;
+    j = g.perm ? (lb < g.plen ? g.perm[x * g.plen + lb] : -1) : x + 8 * lb;
+  }
+  if (j < 0 || j >= nb) return;
+  const int tm = t / gx, tn = t % gx;
+  const int M = g.M[j], K = g.K[j];
+  const int m0 = tm * 64, n0 = tn * 64;
+  if (m0 >= M || n0 >= N) return;
+  const uint16_t* Aj = A + g.aoff[j];
+  const float* Bj = B + g.boff[j] * g.bscale;
+  const int64_t lda = g.lda[j], ldb = g.ldb;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // per batch: thread e loads 16 K entries of row e / 4 of S_j (two 8-wide pieces) and 16 entries of B_j
+  // (K row e / 4, four 4-wide pieces of N); out-of-range entries are zero
+  const int ar = threadIdx.x >> 2, ak = 16 * (threadIdx.x & 3);
+  uint16_t va[16];
+  float vb[16];
+  auto gload = [&](int k0) {
+    const int m = m0 + ar;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int k = k0 + ak + e;
+      va[e] = (m < M && k < K) ? Aj[int64_t(m) * lda + k] : uint16_t(0);
+    }
+    const int kb = k0 + ar;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int n = n0 + ak + e;
+      vb[e] = (kb < K && n < N) ? Bj[int64_t(kb) * ldb + n] : 0.f;
+    }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += BKB) {
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sA[ar * BSP + ak + e] = va[e];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sB[(ak + e) * BSP + ar] = f32_to_bf16(vb[e]);
+    __syncthreads();
+    if (k0 + BKB < K) gload(k0 + BKB);
+#pragma unroll
+    for (int kk = 0; kk < BKB; kk += 32) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) a[x] = *reinterpret_cast<const bf16x8*>(&sA[(wr + 16 * x + li) * BSP + kk + 8 * lg]);
+#pragma unroll
+      for (int y = 0; y < 2; ++y) b[y] = *reinterpret_cast<const bf16x8*>(&sB[(wc + 16 * y + li) * BSP + kk + 8 * lg]);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+  }
+  float* Cj = C + g.coff[j] * g.cscale;
+  const int64_t ldc = g.ldc ? g.ldc[j] : g.ldc_s;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = m0 + wr + 16 * x + 4 * lg + v, c = n0 + wc + 16 * y + li;
+        if (r < M && c < N) Cj[int64_t(r) * ldc + c] = acc[x][y][v];
+      }
+}
+
+void launch_gemm_bf16(const GemmBatch& g, const uint16_t* A, const float* B, float* C, int N, int maxM, int nblk,
+                      hipStream_t st) {
+  if (maxM == 0 || nblk == 0 || N == 0) return;
+  const int tilesM = (maxM + 63) / 64, tilesN = (N + 63) / 64;
+  k_gemm_bf16_sym<<<gemm_grid(tilesN, tilesM, nblk, g.plen), 256, 0, st>>>(g, A, B, C, N, tilesN, tilesM, nblk);
+  NS_LAUNCH_CHECK();
+}
+
+__global__ void k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    y[i] = f32_to_bf16(x[i]);
+}
+
 template <class T>
 void launch_gemm(const LocalSchur& ls, const T* A, const T* B, T* C, int N, hipStream_t st, bool sym,
                  const GemmBatch& g, int maxM, int nblk = -1) {
@@ -641,8 +753,20 @@ void launch_gemm(const LocalSchur& ls, const T* A, const T* B, T* C, int N, hipS
 }  // namespace
 
 template <class T>
-void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStream_t st, const int32_t* bidx) {
+void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStream_t st, const int32_t* bidx,
+                        bool bf16) {
   if (lv.nblk == 0 || ncols == 0) return;
+  if constexpr (sizeof(T) == 4) {
+    if (bf16 && lv.Ainv16.p) {  // BF16 operands of the symmetric inverses, FP32 accumulation
+      GemmBatch g{nullptr, 0, lv.npad_d, lv.npad_d, lv.inv_off, lv.inv_lda, lv.roff, ncols, ncols, lv.roff, ncols,
+                  nullptr, ncols};
+      double sq = 0;
+      for (int b = 0; b < lv.nblk; ++b) sq += double(lv.h_nb[b]) * lv.h_nb[b];
+      KScope ks(KF_INV16, st, sq * 2.0 + 2.0 * lv.alg_rows * ncols * sizeof(float), 2.0 * sq * ncols);
+      launch_gemm_bf16(g, lv.Ainv16.p, B, C, ncols, lv.max_nt * TILE, lv.nblk, st);
+      return;
+    }
+  }
   const T* A;
   if constexpr (sizeof(T) == 8)
     A = lv.Ainv64.p;
@@ -696,8 +820,25 @@ void tri_gram(const TileLevel& lv, const double* Y, double* C, int64_t ld, const
   NS_LAUNCH_CHECK();
 }
 
-template void tile_apply_inverse<double>(const TileLevel&, const double*, double*, int, hipStream_t, const int32_t*);
-template void tile_apply_inverse<float>(const TileLevel&, const float*, float*, int, hipStream_t, const int32_t*);
+template void tile_apply_inverse<double>(const TileLevel&, const double*, double*, int, hipStream_t, const int32_t*,
+                                         bool);
+template void tile_apply_inverse<float>(const TileLevel&, const float*, float*, int, hipStream_t, const int32_t*,
+                                        bool);
+
+void tile_make_bf16_inverse(TileLevel& lv, hipStream_t st) {
+  if (!lv.Ainv32.p) return;
+  lv.Ainv16.alloc(lv.Ainv32.n);
+  k_to_bf16<<<2048, 256, 0, st>>>(lv.Ainv32.p, lv.Ainv16.p, int64_t(lv.Ainv32.n));
+  NS_LAUNCH_CHECK();
+}
+
+void local_schur_make_bf16(Handle& h) {
+  LocalSchur& ls = h.LS;
+  if (!ls.built || !ls.S32.p) return;
+  ls.S16.alloc(ls.S32.n);
+  k_to_bf16<<<2048, 256, 0, h.stream>>>(ls.S32.p, ls.S16.p, int64_t(ls.S32.n));
+  NS_LAUNCH_CHECK();
+}
 
 void local_schur_plan(Handle& h) {
   hipStream_t st = h.stream;
@@ -1004,9 +1145,19 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
     // X_j / Y_j: stacked rows goff[j], leading dimension ncols
     GemmBatch g{nullptr, 0, ls.M, ls.Kg, ls.soff, ls.sld, ls.goff, ncols, ncols, ls.goff, ncols, nullptr, ncols,
                 ls.xperm.p, ls.xplen};
-    KScope ks(sizeof(T) == 8 ? KF_LS_APPLY64 : KF_LS_APPLY32, st,
-              ls.alg_bytes * sizeof(T) + 2.0 * np * ncols * sizeof(T), ls.alg_flops * ncols);
-    launch_gemm<T>(ls, S, Xg, Yg, ncols, st, false, g, ls.max_m);
+    bool done = false;
+    if constexpr (sizeof(T) == 4) {
+      if (h.op_bf16 && h.bf16_schur && ls.S16.p) {  // BF16 operands of the symmetric S_j, FP32 accumulation
+        KScope ks(KF_LS_APPLY16, st, ls.alg_bytes * 2.0 + 2.0 * np * ncols * sizeof(float), ls.alg_flops * ncols);
+        launch_gemm_bf16(g, ls.S16.p, Xg, Yg, ncols, ls.max_m, ls.nblk, st);
+        done = true;
+      }
+    }
+    if (!done) {
+      KScope ks(sizeof(T) == 8 ? KF_LS_APPLY64 : KF_LS_APPLY32, st,
+                ls.alg_bytes * sizeof(T) + 2.0 * np * ncols * sizeof(T), ls.alg_flops * ncols);
+      launch_gemm<T>(ls, S, Xg, Yg, ncols, st, false, g, ls.max_m);
+    }
   }
   const T* vG;
   if constexpr (sizeof(T) == 8)

@@ -30,6 +30,7 @@ struct LocalSchur {
   DBuf<int32_t> glist;                         // stacked position -> interface index (-1 pad)
   DBuf<double> S64;
   DBuf<float> S32;
+  DBuf<uint16_t> S16;  // BF16 copy (NS_BF16 inner operators)
   Csr contrib;  // interface row -> stacked positions (values 1)
   DBuf<double> wsX64, wsY64;
   DBuf<float> wsX32, wsY32;
@@ -65,6 +66,9 @@ struct ns_handle_s {
   std::vector<double> relres_inner;
   int prec_inner = 0, apply_mode = 0, trsm_cols = 0, schur_mode = 0, pcg_graph = 0;
   int variant = 0, power = 0, outer = 0;  // ns_variant, power iterations of the sketch, ns_outer
+  int bf16 = 0;     // NS_BF16 inner operators built (BF16 copies of S_j and of the interface inverses)
+  int op_bf16 = 0;  // FP32 operator applications currently use the BF16 copies
+  int bf16_schur = 1;  // the BF16 copies of S_j are used (cleared after a block-CG breakdown on them)
   ns::SegBuf segI;                         // padded interior rows (one problem): the rows of variant M_3
   double tol_inner = 0.1, eig_rel = 1e-10, drop_rel = 1e-6;
   int max_inner = 500;
@@ -155,6 +159,7 @@ void assemble_junction(Handle& h);
 // Symbolic pass (interface lists, layouts; waits for the device) and numeric pass (needs the interior factor).
 void local_schur_plan(Handle& h);
 void local_schur_form(Handle& h);
+void local_schur_make_bf16(Handle& h);  // BF16 copy of the FP32 local Schur blocks
 
 // Generic row gather / scatter and CSR products (row-major blocks).
 template <class T>

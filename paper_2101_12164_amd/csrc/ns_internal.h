@@ -182,6 +182,7 @@ struct TileLevel {
   // explicit inverses of the (small) blocks: rows nrows_pad x inv_ld, block b at row roff_b
   DBuf<double> Ainv64;
   DBuf<float> Ainv32;
+  DBuf<uint16_t> Ainv16;  // BF16 copy (NS_BF16 inner operators)
   DBuf<int64_t> inv_off, inv_lda;
   DBuf<int> npad_d;
   int64_t inv_ld = 0;
@@ -214,6 +215,11 @@ enum KFamily {
   KF_INV32,
   KF_MLP_FWD,  // learned proposal: network forward GEMMs (BF16 MFMA)
   KF_MLP_BWD,  // learned proposal: backward GEMMs (FP32 MFMA)
+  KF_LS_APPLY16,  // local Schur blocks applied with BF16 operands (FP32 accumulation)
+  KF_INV16,       // interface-block inverses applied with BF16 operands
+  KF_GRAM,        // Gram products A^T B of block vectors (block CG, Nystrom)
+  KF_BLOCK_UPDATE,  // block updates Out = beta Out + gamma X M (block CG, Nystrom)
+  KF_SMALL,       // one-workgroup dense kernels on the s x s matrices
   KF_COUNT
 };
 // Brackets one launch when timing is on; bytes / flops are the algorithmic
@@ -285,7 +291,10 @@ void tri_gram(const TileLevel& lv, const double* Y, double* C, int64_t ld, const
 // C = A^{-1} B for every block with the explicit inverses; B, C padded rhs (ld ncols).
 template <class T>
 void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStream_t st,
-                        const int32_t* bidx = nullptr);  // bidx: B gathered per row (one column, FP64 packed path)
+                        const int32_t* bidx = nullptr,  // bidx: B gathered per row (one column, FP64 packed path)
+                        bool bf16 = false);             // FP32 data: BF16 operands of the inverses (Ainv16)
+// BF16 copy of the FP32 inverses (round to nearest even), for the BF16 inner operators.
+void tile_make_bf16_inverse(TileLevel& lv, hipStream_t st);
 // Expand the factor of one block to a dense nb x nb column-major lower matrix.
 void tile_export(const TileLevel& lv, int block, double* out, hipStream_t st);
 

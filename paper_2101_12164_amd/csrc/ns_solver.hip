@@ -308,6 +308,14 @@ void block_pcg(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
   }
 }
 
+// While alive, FP32 operator applications of the handle use the BF16 operand copies (NS_BF16).
+struct BF16Scope {
+  Handle& h;
+  int prev;
+  explicit BF16Scope(Handle& hh, bool on = true) : h(hh), prev(hh.op_bf16) { h.op_bf16 = on && h.bf16; }
+  ~BF16Scope() { h.op_bf16 = prev; }
+};
+
 // Three Cholesky-QR passes per problem over the rows of sg: X (rows x s) <- X R^{-1} with R^T R = X^T M X,
 // where MX holds M X for an SPD M (MX == nullptr: M = I, the QR of X); MX is updated alongside.  The first
 // pass is shifted by 11 (m s + s (s + 1)) u (m the problem's rows, u = 2^-53).  On return X (and MX) point at
@@ -405,6 +413,30 @@ void gamma_rinv(Handle& h, const double* X, double* Out, int ncols) {
   }
 }
 
+// The block CG in the inner precision.  NS_BF16: the operators on BF16 operands; a breakdown there (P^T S P
+// not positive definite: the BF16 rounding of S_j is larger than S_Gamma's small eigenvalues) is the measured
+// gate -- the solve is run again with FP32 Schur operands, the preconditioner keeping its BF16 operands.
+template <class Rhs>
+void run_inner(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
+  if (!h.prec_inner) {
+    block_pcg<double>(h, sm, rhs, D);
+    return;
+  }
+  BF16Scope b16(h);
+  if (h.bf16 && h.bf16_schur) {
+    try {
+      block_pcg<float>(h, sm, rhs, D);
+      return;
+    } catch (const Error& e) {
+      if (e.status != BREAKDOWN) throw;
+      (void)hipGetLastError();
+      NS_HIP(hipMemsetAsync(sm.flag, 0, 4 * sizeof(int), h.stream));
+      h.bf16_schur = 0;
+    }
+  }
+  block_pcg<float>(h, sm, rhs, D);
+}
+
 // Block CG on the shifted system with right-hand side F = W G (G: n_G x s, FP64) in the inner precision.
 void inner_solve_w(Handle& h, SmallMats& sm, const double* G, double* D) {
   const int s = h.s;
@@ -420,10 +452,7 @@ void inner_solve_w(Handle& h, SmallMats& sm, const double* G, double* D) {
       op_schur<float>(h, Gf.p, s, R, s, s, /*w_only=*/true);
     }
   };
-  if (h.prec_inner)
-    block_pcg<float>(h, sm, rhs, D);
-  else
-    block_pcg<double>(h, sm, rhs, D);
+  run_inner(h, sm, rhs, D);
 }
 
 // Block CG on the shifted system with a given right-hand side F (FP64, n_G x s).
@@ -437,10 +466,7 @@ void inner_solve_f(Handle& h, SmallMats& sm, const double* F, double* D) {
     else
       convert_block<double, float>(nG, s, F, s, R, s, h.stream);
   };
-  if (h.prec_inner)
-    block_pcg<float>(h, sm, rhs, D);
-  else
-    block_pcg<double>(h, sm, rhs, D);
+  run_inner(h, sm, rhs, D);
 }
 
 // The low-rank term of the chosen variant (Algorithm alg:prec1 and its analogues for M_1 and M_3) with q power
@@ -939,7 +965,9 @@ Handle* new_handle(const ns_options* opt) {
   h->s = opt->k + opt->p;
   h->tol_inner = opt->tol_inner > 0 ? opt->tol_inner : 0.1;
   h->eig_rel = opt->eig_thresh_rel > 0 ? opt->eig_thresh_rel : 1e-10;
-  h->prec_inner = opt->prec_inner == NS_FP32 ? 1 : 0;
+  if (opt->prec_inner < NS_FP64 || opt->prec_inner > NS_BF16) fail(INVALID_ARG, "prec_inner must be 0, 1 or 2");
+  h->prec_inner = opt->prec_inner == NS_FP64 ? 0 : 1;  // FP32 block vectors for NS_FP32 and NS_BF16
+  h->bf16 = opt->prec_inner == NS_BF16 ? 1 : 0;
   h->drop_rel = opt->orth_drop_rel > 0 ? opt->orth_drop_rel : (h->prec_inner ? 1e-5 : 1e-6);
   h->max_inner = opt->max_inner_iters > 0 ? opt->max_inner_iters : 500;
   h->apply_mode = opt->apply_mode == NS_APPLY_ADEF2 ? 1 : 0;
@@ -1007,10 +1035,15 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
       tile_make_fp32(h->L2, h->stream);
       tile_make_fp32(h->LJ, h->stream);
     }
+    if (h->bf16) {
+      tile_make_bf16_inverse(h->L2, h->stream);
+      tile_make_bf16_inverse(h->LJ, h->stream);
+    }
     NS_HIP(hipEventRecord(join.e, h->stream));
   }
   NS_HIP(hipStreamWaitEvent(h->stream, planned.e, 0));  // the plan's last uploads and sorts
   if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_form(*h);
+  if (h->bf16) local_schur_make_bf16(*h);
   if (h->prec_inner && !h->LS.built) tile_make_fp32(h->L1, h->stream);
   // the tile-transposed interior factor is only read by the solve's single-column backward sweeps: it is made
   // on the second stream while this one runs the inner solve (after the formation, so the two do not share the
@@ -1087,6 +1120,7 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
       o.t_inner = ev.sec(2, 3);
       o.t_nystrom = ev.sec(3, 4);
       o.t_total = ev.sec(0, 4);
+      o.inner_bf16_schur = h->bf16 && h->bf16_schur ? 1 : 0;
     }
   }
 }
@@ -1388,8 +1422,10 @@ ns_status nystrom_schur_schur_apply(ns_handle h, const double* X, double* Y, int
   try {
     StreamScope ss(h->stream);
     if (ncols < 1 || ncols > 1024 || !X || !Y) fail(INVALID_ARG, "bad arguments");
-    if (prec == NS_FP32) {
-      if (!h->prec_inner) fail(INVALID_ARG, "FP32 operators exist only with prec_inner = NS_FP32");
+    if (prec == NS_FP32 || prec == NS_BF16) {
+      if (!h->prec_inner) fail(INVALID_ARG, "FP32 operators exist only with prec_inner = NS_FP32 or NS_BF16");
+      if (prec == NS_BF16 && !h->bf16) fail(INVALID_ARG, "BF16 operators exist only with prec_inner = NS_BF16");
+      BF16Scope b16(*h, prec == NS_BF16);
       DBuf<float> x32, y32;
       x32.alloc(h->nG * ncols);
       y32.alloc(h->nG * ncols);
@@ -1412,8 +1448,10 @@ ns_status nystrom_schur_interface_solve(ns_handle h, const double* X, double* Y,
   try {
     StreamScope ss(h->stream);
     if (ncols < 1 || ncols > 1024 || !X || !Y) fail(INVALID_ARG, "bad arguments");
-    if (prec == NS_FP32) {
-      if (!h->prec_inner) fail(INVALID_ARG, "FP32 operators exist only with prec_inner = NS_FP32");
+    if (prec == NS_FP32 || prec == NS_BF16) {
+      if (!h->prec_inner) fail(INVALID_ARG, "FP32 operators exist only with prec_inner = NS_FP32 or NS_BF16");
+      if (prec == NS_BF16 && !h->bf16) fail(INVALID_ARG, "BF16 operators exist only with prec_inner = NS_BF16");
+      BF16Scope b16(*h, prec == NS_BF16);
       DBuf<float> x32, y32;
       x32.alloc(h->nG * ncols);
       y32.alloc(h->nG * ncols);
@@ -1436,7 +1474,7 @@ ns_status nystrom_schur_interior_solve(ns_handle h, const double* X, double* Y, 
     StreamScope ss(h->stream);
     if (ncols < 1 || ncols > 1024 || !X || !Y) fail(INVALID_ARG, "bad arguments");
     if (prec == NS_FP32) {
-      if (!h->prec_inner) fail(INVALID_ARG, "FP32 operators exist only with prec_inner = NS_FP32");
+      if (!h->prec_inner) fail(INVALID_ARG, "FP32 operators exist only with prec_inner = NS_FP32 or NS_BF16");
       DBuf<float> x32, y32;
       x32.alloc(h->nI * ncols);
       y32.alloc(h->nI * ncols);

@@ -610,10 +610,49 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
     fro += x * x;
   }
   if (ok) {
-    // lambda_min(G) >= 1 / ||L^{-1}||_F^2 and lambda_max(G) <= trace(G): certify that no
-    // singular value ratio of the block is at or below the drop tolerance
+    // certify that no singular value ratio of the block is at or below the drop tolerance, from guaranteed
+    // bounds: lambda_min(G) = 1 / ||L^{-1}||_2^2 >= 1 / min(||L^{-1}||_F^2, ||L^{-1}||_1 ||L^{-1}||_inf) (Hoelder)
+    // and lambda_max(G) <= min(trace(G), ||G||_inf); the norms of L^{-1} from its rows and columns in X
     const double f = block_sum(fro, red);
-    if (threadIdx.x == 0) ok[b] = (sinfo == 0 && 1.0 / f > certify * tr) ? 1 : 0;
+    double rmax = 0.0, cmax = 0.0, gmax = 0.0;
+    for (int i = threadIdx.x; i < n; i += NT) {
+      double rs = 0.0, cs = 0.0, gs = 0.0;
+      for (int j = 0; j < n; ++j) {
+        rs += fabs(X[i * ld + j]);   // row i of L^{-1}
+        cs += fabs(X[j * ld + i]);   // column i of L^{-1}
+        gs += fabs(0.5 * (G[i * s + j] + G[j * s + i]));
+      }
+      rmax = fmax(rmax, rs);
+      cmax = fmax(cmax, cs);
+      gmax = fmax(gmax, gs);
+    }
+    red[threadIdx.x] = rmax;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+      __syncthreads();
+    }
+    rmax = red[0];
+    __syncthreads();
+    red[threadIdx.x] = cmax;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+      __syncthreads();
+    }
+    cmax = red[0];
+    __syncthreads();
+    red[threadIdx.x] = gmax;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+      __syncthreads();
+    }
+    gmax = red[0];
+    __syncthreads();
+    const double lmin = 1.0 / fmin(f, rmax * cmax);
+    const double lmax = fmin(tr, gmax);
+    if (threadIdx.x == 0) ok[b] = (sinfo == 0 && lmin > certify * lmax) ? 1 : 0;
   }
   __syncthreads();
   if (init) {
@@ -919,6 +958,7 @@ SmallWs small_ws(DBuf<double>& buf, int nb, int n, int c) {
 void small_chol_solve(Batch bt, int r, double* D, int64_t sD, const double* B, int64_t ldb, int64_t sB, double* X,
                       int64_t ldx, int64_t sX, int s, int s0, double alpha, int* flag, const SmallWs& ws,
                       hipStream_t st) {
+  KScope ks_small(KF_SMALL, st);
   if (bt.nb <= 0 || (r <= 0 && s0 <= 0)) return;  // s == 0: factor only
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
   const size_t el = chol_ws(r, s);
@@ -935,6 +975,7 @@ void small_chol_solve(Batch bt, int r, double* D, int64_t sD, const double* B, i
 void small_chol_apply(Batch bt, int r, const double* L, int64_t sL, const double* B, int64_t ldb, int64_t sB,
                       double* X, int64_t ldx, int64_t sX, int s, int s0, double alpha, const SmallWs& ws,
                       hipStream_t st) {
+  KScope ks_small(KF_SMALL, st);
   if (bt.nb <= 0 || (r <= 0 && s0 <= 0) || s <= 0) return;
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
   const size_t el = chol_ws(r, s);
@@ -950,6 +991,7 @@ void small_chol_apply(Batch bt, int r, const double* L, int64_t sL, const double
 
 void small_svqb(int nb, int s, const double* G, int64_t sG, double drop2, double* T, int64_t sT, int* out,
                 const int* skip, const SmallWs& ws, hipStream_t st) {
+  KScope ks_small(KF_SMALL, st);
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
   const size_t el = evd_elems(s);
   const int mode = ws_mode(ws, el, s, s);
@@ -962,6 +1004,7 @@ void small_svqb(int nb, int s, const double* G, int64_t sG, double drop2, double
 
 void small_cholqr(Batch bt, int s, const double* G, int64_t sG, const double* shift, double* Rinv, double* Racc,
                   int init, int* flag, const SmallWs& ws, hipStream_t st, double certify, int* ok) {
+  KScope ks_small(KF_SMALL, st);
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
   const size_t el = chol_ws(s, s);
   const int mode = ws_mode(ws, el, s, s);
@@ -976,6 +1019,7 @@ void small_cholqr(Batch bt, int s, const double* G, int64_t sG, const double* sh
 
 void small_nystrom(int nb, int s, int k, const double* C, const double* R, double eps_rel, double* Wk, double* Ek,
                    int* out, const SmallWs& ws, hipStream_t st) {
+  KScope ks_small(KF_SMALL, st);
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
   const size_t el = chol_ws(s, s);
   const int mode = ws_mode(ws, el, s, s);
@@ -989,6 +1033,7 @@ void small_nystrom(int nb, int s, int k, const double* C, const double* R, doubl
 
 void small_gevd(int k, const double* A, const double* B, double* lam, double* C, double* Cl, int* flag, double* ws,
                 const SmallWs& sw, hipStream_t st) {
+  KScope ks_small(KF_SMALL, st);
   if (k > SMAX) fail(INVALID_ARG, "matrix too large for the small dense kernels (limit 256)");
   double* L = ws;
   double* Linv = ws + size_t(k) * k;
@@ -1003,6 +1048,7 @@ void small_gevd(int k, const double* A, const double* B, double* lam, double* C,
 }
 
 void small_sym_evd(int m, const double* A, double* W, double* E, const SmallWs& ws, hipStream_t st) {
+  KScope ks_small(KF_SMALL, st);
   if (m > SMAX) fail(INVALID_ARG, "matrix too large for the small dense kernels (limit 256)");
   const size_t el = evd_elems(m);
   const int mode = ws_mode(ws, el, m, m);

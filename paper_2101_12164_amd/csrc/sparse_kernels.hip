@@ -989,7 +989,7 @@ void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int
   // interface blocks: explicit inverses when built, else the two triangular sweeps (in place)
   auto solve = [&](const TileLevel& lv, T* in, T* out) -> T* {
     if (lv.Ainv64.p && (sizeof(T) == 8 || lv.Ainv32.p)) {
-      tile_apply_inverse<T>(lv, in, out, ncols, st);
+      tile_apply_inverse<T>(lv, in, out, ncols, st, nullptr, h.op_bf16 != 0);
       return out;
     }
     tile_solve<T>(lv, in, ncols, ncols, h.trsm_cols, st);

@@ -609,6 +609,11 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
   if (ta > 65535) fail(INVALID_ARG, "Gram product too wide");
   dim3 g(unsigned(sg.nchunk), unsigned(ta), unsigned((tbt + GS_MAXT - 1) / GS_MAXT));
   const int sym = (static_cast<const void*>(A) == static_cast<const void*>(B) && lda == ldb && ra == rb) ? 1 : 0;
+  // algorithmic work: A and B read once (once in all when they are the same block), the products of the
+  // output entries (the lower triangle and the diagonal when symmetric)
+  const double rows = double(sg.rows);
+  KScope ks(KF_GRAM, st, rows * (double(ra) * sizeof(TA) + (sym ? 0.0 : double(rb) * sizeof(TB))),
+            sym ? rows * ra * (ra + 1.0) : 2.0 * rows * ra * rb);
   switch (std::min(tbt, GS_MAXT)) {  // column tiles per launch column group
     case 1: k_gram_strip<TA, TB, 1><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym); break;
     case 2: k_gram_strip<TA, TB, 2><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym); break;
@@ -627,6 +632,11 @@ void ts_update(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, doubl
                int rm, const double* M, int64_t ldm, int64_t mstride, const T* X2, int64_t ldx2, int rm2,
                const double* M2, int64_t ldm2, int64_t m2stride, hipStream_t st) {
   if (sg.rows == 0 || ncols == 0) return;
+  // algorithmic work: X (and X2) read once, Out read (beta != 0) and written once, 2 rm ncols flops per row
+  const double rows = double(sg.rows);
+  KScope ks(KF_BLOCK_UPDATE, st,
+            rows * sizeof(T) * (double(rm) + rm2 + ncols * (beta != 0.0 ? 2.0 : 1.0)),
+            2.0 * rows * ncols * (double(rm) + rm2));
   ts_launch<T>(sg, ncols, Out, ldo, beta, gamma, X, ldx, rm, M, ldm, mstride, st);
   if (rm2 > 0) ts_launch<T>(sg, ncols, Out, ldo, 1.0, gamma, X2, ldx2, rm2, M2, ldm2, m2stride, st);
 }

@@ -18,7 +18,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnystrom
 _lib = None
 
 NS_OK, NS_ERR_INVALID_ARG, NS_ERR_NOT_SPD, NS_ERR_OOM, NS_ERR_HIP, NS_ERR_NOT_CONVERGED, NS_ERR_BREAKDOWN = range(7)
-NS_FP64, NS_FP32 = 0, 1
+NS_FP64, NS_FP32, NS_BF16 = 0, 1, 2
 NS_APPLY_M2, NS_APPLY_ADEF2 = 0, 1
 NS_SCHUR_AUTO, NS_SCHUR_TRIANGULAR, NS_SCHUR_LOCAL = 0, 1, 2
 NS_VARIANT_M2, NS_VARIANT_M1, NS_VARIANT_M3 = 0, 1, 2
@@ -65,7 +65,8 @@ EXPORTED = [
 KERNEL_FAMILIES = ["chol_update", "chol_panel", "trsm_interior_f64", "trsm_interior_f32", "trsm_interface_f64",
                    "trsm_interface_f32", "schur_epi", "spmm", "local_schur_form", "local_schur_apply_f64",
                    "local_schur_apply_f32", "interface_inverse_f64", "interface_inverse_f32", "mlp_forward_bf16",
-                   "mlp_backward_f32"]
+                   "mlp_backward_f32", "local_schur_apply_bf16", "interface_inverse_bf16", "gram", "block_update",
+                   "small_dense"]
 
 
 class NsOptions(ctypes.Structure):
@@ -111,6 +112,7 @@ class NsSetupInfo(ctypes.Structure):
         ("t_inner", c_double),
         ("t_nystrom", c_double),
         ("t_total", c_double),
+        ("inner_bf16_schur", c_int32),
     ]
 
 
