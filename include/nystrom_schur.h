@@ -211,6 +211,19 @@ ns_status nystrom_schur_setup(int64_t n, int64_t nnz, const int64_t* row_ptr, co
 ns_status nystrom_schur_apply(ns_handle h, const double* r_gamma, double* z_gamma, int32_t ncols);
 
 /*
+ * nystrom_schur_apply without any device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments and results as
+ * nystrom_schur_apply; its scratch (Gram partials, coefficient blocks, small dense workspace) is a
+ * file-scope device array of 4 MiB that every GPU the library runs on holds until the process ends, and the
+ * handle's own operator workspaces (sized at setup for k + p columns) are used as they are.
+ * NS_ERR_INVALID_ARG when the call would need more than the 4 MiB (its need grows with k x ncols x the
+ * number of reduction chunks, about n_gamma / 128 up to 240 per problem) or more columns than the handle's
+ * workspaces hold.  Calls on one GPU share the array: calls that overlap on one GPU (two streams, two
+ * threads) race and must not be made.
+ */
+ns_status nystrom_schur_apply_noalloc(ns_handle h, const double* r_gamma, double* z_gamma, int32_t ncols);
+
+/*
  * Solve A x = b (eq. A_LDLT): f = b_Gamma - A_GammaI A_I^{-1} b_I; PCG with M on
  * S_Gamma w = f until ||r_j|| / ||f|| <= rtol (eq. Sx=b); x_I = A_I^{-1}(b_I -
  * A_IGamma w), x_Gamma = w.  b, x: DEVICE, length n, ORIGINAL node order; they

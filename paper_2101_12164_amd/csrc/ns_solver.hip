@@ -5,6 +5,7 @@
 // sequences launches and reads back convergence scalars.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "ns_handle.h"
@@ -1162,6 +1163,42 @@ __global__ void k_shift_cols(int64_t m, const int32_t* __restrict__ c, int64_t a
 }  // namespace
 }  // namespace ns
 
+// ---------------------------------------------------------------------------------------------------------
+// Allocation-free apply.  Its scratch -- the Gram partials of Z^T r (and of (S Z)^T t), the k x ncols
+// coefficient blocks and the small dense kernels' workspace -- is this file-scope device array, of which every
+// GPU the library runs on holds one copy until the process ends.  Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in symbol): the device address is looked up once per device, with
+// that device current, and used from then on.
+constexpr size_t kScratchDoubles = size_t(1) << 19;  // 4 MiB per device
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace ns {
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxScratchDevices] = {};
+
+double* scratch_address() {
+  int dev = 0;
+  NS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) fail(HIP, "device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      fail(HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    }
+    g_scratch[dev] = static_cast<double*>(p);
+  }
+  return g_scratch[dev];
+}
+
+size_t round256(size_t n) { return (n + 31) / 32 * 32; }  // doubles, keeping 256-byte alignment
+}  // namespace
+}  // namespace ns
+
 using namespace ns;
 
 namespace ns {
@@ -1314,6 +1351,43 @@ ns_status nystrom_schur_apply(ns_handle h, const double* r_gamma, double* z_gamm
     c2.alloc(size_t(std::max(h->k, 1)) * ncols * h->nprob);
     DBuf<double> gs;
     const SmallWs ws = small_ws(gs, h->nprob, std::max(h->s, 1), ncols);
+    apply_prec(*h, r_gamma, ncols, z_gamma, ncols, ncols, work, c1, c2, ws);
+    NS_HIP(hipStreamSynchronize(h->stream));
+    return NS_OK;
+  } catch (const Error& e) {
+    return finish(h, e);
+  }
+}
+
+ns_status nystrom_schur_apply_noalloc(ns_handle h, const double* r_gamma, double* z_gamma, int32_t ncols) {
+  if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
+  try {
+    StreamScope ss(h->stream);
+    if (ncols < 1 || ncols > 1024 || !r_gamma || !z_gamma) fail(INVALID_ARG, "bad apply arguments");
+    // the operator workspaces of the handle (made at setup for k + p columns, or by an earlier apply) must
+    // already hold ncols columns: growing them would allocate
+    if (ncols > h->ws_cols)
+      fail(INVALID_ARG, "nystrom_schur_apply_noalloc: " + std::to_string(ncols) +
+                            " columns exceed the handle's workspaces (" + std::to_string(h->ws_cols) + ")");
+    const Seg& sg = h->segG.view;
+    const int k = std::max(h->k, 1), np = h->nprob;
+    const size_t nwork = round256(std::max<size_t>(size_t(sg.nchunk) * size_t(k) * size_t(ncols), 2 * sg.nchunk + 32));
+    const size_t ncoef = round256(size_t(k) * ncols * np);
+    const size_t stride = h->apply_mode == NS_APPLY_ADEF2 ? small_chol_scratch_elems(k, ncols) : 0;
+    const size_t need = nwork + 2 * ncoef + round256(stride * size_t(np));
+    if (need > kScratchDoubles)
+      fail(INVALID_ARG, "nystrom_schur_apply_noalloc: needs " + std::to_string(need * sizeof(double)) +
+                            " bytes of scratch, the limit is " + std::to_string(kScratchDoubles * sizeof(double)) +
+                            " per device (fewer columns, or nystrom_schur_apply)");
+    double* base = scratch_address();
+    double* work = base;
+    double* c1 = work + nwork;
+    double* c2 = c1 + ncoef;
+    SmallWs ws;
+    ws.n = k;
+    ws.c = ncols;
+    ws.stride = int64_t(stride);
+    ws.p = stride ? c2 + ncoef : nullptr;
     apply_prec(*h, r_gamma, ncols, z_gamma, ncols, ncols, work, c1, c2, ws);
     NS_HIP(hipStreamSynchronize(h->stream));
     return NS_OK;

@@ -114,6 +114,8 @@ struct SmallWs {
 };
 // doubles per problem for dimensions <= n and column counts <= c (0 when everything fits in LDS)
 size_t small_scratch_elems(int n, int c);
+// doubles per problem of the Cholesky solve / apply kernels for an r x r factor and c columns (0: in LDS)
+size_t small_chol_scratch_elems(int r, int c);
 // a scratch for nb problems (buf is allocated only when needed)
 SmallWs small_ws(DBuf<double>& buf, int nb, int n, int c);
 

@@ -943,6 +943,11 @@ size_t small_scratch_elems(int n, int c) {
   return e * sizeof(double) <= LDS_LIMIT ? 0 : e;
 }
 
+size_t small_chol_scratch_elems(int r, int c) {
+  const size_t e = chol_ws(r, c);
+  return e * sizeof(double) <= LDS_LIMIT ? 0 : e;
+}
+
 SmallWs small_ws(DBuf<double>& buf, int nb, int n, int c) {
   SmallWs w;
   w.n = n;

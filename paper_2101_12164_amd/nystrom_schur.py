@@ -37,6 +37,7 @@ STATUS_NAMES = {
 EXPORTED = [
     "nystrom_schur_setup",
     "nystrom_schur_apply",
+    "nystrom_schur_apply_noalloc",
     "nystrom_schur_pcg_solve",
     "nystrom_schur_setup_batched",
     "nystrom_schur_pcg_solve_batched",
@@ -180,6 +181,8 @@ def load_library() -> ctypes.CDLL:
     lib.nystrom_schur_mlp_last_error.restype = c_char_p
     lib.nystrom_schur_apply.argtypes = [H, c_void_p, c_void_p, c_int32]
     lib.nystrom_schur_apply.restype = c_int32
+    lib.nystrom_schur_apply_noalloc.argtypes = [H, c_void_p, c_void_p, c_int32]
+    lib.nystrom_schur_apply_noalloc.restype = c_int32
     lib.nystrom_schur_pcg_solve.argtypes = [H, c_void_p, c_void_p, c_double, c_int32, POINTER(NsSolveInfo)]
     lib.nystrom_schur_pcg_solve.restype = c_int32
     for name in ("nystrom_schur_schur_apply", "nystrom_schur_interface_solve", "nystrom_schur_interior_solve"):
@@ -326,6 +329,15 @@ def nystrom_schur_pcg_solve_batched(handle, bs, xs=None, rtol=1e-8, maxit=1000, 
         return xs, out
     _check(st, handle, out)
     return xs, out
+
+
+def nystrom_schur_apply_noalloc(handle, r: torch.Tensor, z: torch.Tensor):
+    """z = M r through the allocation-free entry point (z must be given: nothing is allocated)."""
+    lib = load_library()
+    ncols = 1 if r.dim() == 1 else r.shape[1]
+    st = lib.nystrom_schur_apply_noalloc(handle, _dev(r, torch.float64, "r"), _dev(z, torch.float64, "z"), ncols)
+    _check(st, handle)
+    return z
 
 
 def nystrom_schur_apply(handle, r: torch.Tensor, z: torch.Tensor = None):
