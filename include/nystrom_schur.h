@@ -142,6 +142,9 @@ typedef struct {
                                 every product with B (each product is one inner block solve;
                                 it_inner counts them all) [0]                                     */
   int32_t outer;             /* ns_outer [NS_OUTER_SCHUR]                                         */
+  int32_t bcg_graph_iters;   /* block-CG iterations recorded per HIP graph and replayed between the
+                                host's stopping checks (rounded up to an even count): 0 = automatic
+                                (2), -1 = plain launches.  Results are the same in every mode.   */
 } ns_options;
 
 /* Outputs of setup(), HOST memory. Times are seconds measured with hipEvents. */

@@ -66,6 +66,7 @@ struct ns_handle_s {
   std::vector<double> relres_inner;
   int prec_inner = 0, apply_mode = 0, trsm_cols = 0, schur_mode = 0, pcg_graph = 0;
   int variant = 0, power = 0, outer = 0;  // ns_variant, power iterations of the sketch, ns_outer
+  int bcg_graph = 0;                       // block-CG iterations per replayed graph (0 auto, -1 plain)
   int bf16 = 0;     // NS_BF16 inner operators built (BF16 copies of S_j and of the interface inverses)
   int op_bf16 = 0;  // FP32 operator applications currently use the BF16 copies
   int bf16_schur = 1;  // the BF16 copies of S_j are used (cleared after a block-CG breakdown on them)

@@ -140,10 +140,15 @@ void check_chol(Handle& h, ns_setup_info* info) {
 // ------------------------------------------------------------------ inner-solve control (per problem)
 // Stopping test of block CG: rel_p = max_j ||R_p(:, j)|| / ||F_p(:, j)||; an active problem with
 // rel_p <= tol stops (converged) at iteration it.
+__global__ void k_iter(int* it) { *it += 1; }
+
+// it: the iteration index, or, with itd != nullptr, read from the device (graph-replayed iterations)
 __global__ void k_bcg_check(int np, int s, const double* __restrict__ colsq, const double* __restrict__ nF2,
-                            double tol, int it, int* active, int* itp, int* conv, double* relres, int* ndone) {
+                            double tol, int it, int* active, int* itp, int* conv, double* relres, int* ndone,
+                            const int* itd) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= np || !active[p]) return;
+  if (itd) it = *itd;
   double m = 0.0;
   for (int j0 = 0; j0 < s; j0 += 8) {  // eight columns' loads in flight together (clamped, in bounds)
     double f[8], c[8];
@@ -179,8 +184,9 @@ __global__ void k_svqb_mask(int np, const int* active, const int* ok, int* skip)
 // (copied into Rinv); rank: s, the number of directions kept, or 0 when inactive.  An active problem
 // left without directions stops (not converged).
 __global__ void k_orth_select(int np, int s, int* active, const int* ok, const int* svr, const double* Torth,
-                              double* Rinv, int* rank, int it, int* itp, int* ndone) {
+                              double* Rinv, int* rank, int it, int* itp, int* ndone, const int* itd) {
   const int p = blockIdx.x;
+  if (itd) it = *itd;
   const bool use_svqb = active[p] && !ok[p];
   if (use_svqb)
     for (int e = threadIdx.x; e < s * s; e += blockDim.x) Rinv[int64_t(p) * s * s + e] = Torth[int64_t(p) * s * s + e];
@@ -202,7 +208,8 @@ __global__ void k_orth_select(int np, int s, int* active, const int* ok, const i
 // eigenpairs above drop^2 * lambda_max) followed by one Cholesky-QR pass.  Inactive problems get zero
 // columns; dropped directions are zero columns at the end.  Q is scratch.
 template <class T>
-void orth(Handle& h, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int s, int it) {
+void orth(Handle& h, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int s, int it,
+          const int* itd = nullptr) {
   hipStream_t st = h.stream;
   const Seg& sg = h.segG.view;
   const int np = h.nprob;
@@ -218,7 +225,7 @@ void orth(Handle& h, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int 
   NS_LAUNCH_CHECK();
   small_svqb(np, s, sm.Gorth, ss, drop2, sm.Torth, ss, sm.svr, sm.skip, h.sws, st);
   k_orth_select<<<np, 256, 0, st>>>(np, s, sm.active, sm.ok, sm.svr, sm.Torth, sm.Rinv, sm.rank, it, sm.itp,
-                                    sm.ctr);
+                                    sm.ctr, itd);
   NS_LAUNCH_CHECK();
   ts_update<T>(sg, s, P, s, 0.0, 1.0, V, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
   gram<T, T>(sg, P, s, s, P, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
@@ -254,42 +261,103 @@ void block_pcg(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
   col_sumsq<T>(sg, s, R.p, s, sm.nF2, work, st);
   NS_HIP(hipMemcpyAsync(sm.colsq, sm.nF2, size_t(np) * s * sizeof(double), hipMemcpyDeviceToDevice, st));
   k_bcg_check<<<pb, 256, 0, st>>>(np, s, sm.colsq, sm.nF2, h.tol_inner, 0, sm.active, sm.itp, sm.conv, sm.relres,
-                                  sm.ctr);
+                                  sm.ctr, nullptr);
   NS_LAUNCH_CHECK();
   int hc[2] = {0, 0};
   read_back(h, hc, sm.ctr, 1);
-  int it = 0;
   if (hc[0] < np) {
-    op_gamma_solve<T>(h, R.p, s, Z.p, s, s);
-    orth<T>(h, sm, work, Z.p, P, Q, s, 0);
-    while (it < h.max_inner) {
-      ++it;
-      op_schur<T>(h, P, s, Q, s, s, false);                                     // Q = S P
-      gram<T, T>(sg, P, s, s, Q, s, s, sm.Delta, ss, 1.0, 0.0, work, st);      // Delta = P^T Q
-      gram<T, T>(sg, P, s, s, R.p, s, s, sm.G1, ss, 1.0, 0.0, work, st);       // P^T R
-      k_dims<<<pb, 256, 0, st>>>(np, s, sm.active, sm.rank, sm.dimA);
+    // the iteration index lives on the device, so that the same launches, recorded once into a HIP graph, serve
+    // every iteration: k_iter advances it, the stopping test and the orthonormalisation read it
+    DBuf<int> itd;
+    itd.alloc(1);
+    NS_HIP(hipMemsetAsync(itd.p, 0, sizeof(int), st));
+    // first half: Q = S P, alpha, X and R, the stopping test; second half: Z = M R, beta, P = orth(Z + P beta)
+    auto half1 = [&](hipStream_t q) {
+      k_iter<<<1, 1, 0, q>>>(itd.p);
+      op_schur<T>(h, P, s, Q, s, s, false);                                   // Q = S P
+      gram<T, T>(sg, P, s, s, Q, s, s, sm.Delta, ss, 1.0, 0.0, work, q);      // Delta = P^T Q
+      gram<T, T>(sg, P, s, s, R.p, s, s, sm.G1, ss, 1.0, 0.0, work, q);       // P^T R
+      k_dims<<<pb, 256, 0, q>>>(np, s, sm.active, sm.rank, sm.dimA);
       NS_LAUNCH_CHECK();
       small_chol_solve(Batch{np, sm.dimA}, s, sm.Delta, ss, sm.G1, s, ss, sm.alpha, s, ss, s, s, 1.0, sm.flag,
-                       h.sws, st);  // alpha
-      ts_update<T>(sg, s, X.p, s, 1.0, 1.0, P, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
-      ts_update<T>(sg, s, R.p, s, 1.0, -1.0, Q, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
-      col_sumsq<T>(sg, s, R.p, s, sm.colsq, work, st);
-      k_bcg_check<<<pb, 256, 0, st>>>(np, s, sm.colsq, sm.nF2, h.tol_inner, it, sm.active, sm.itp, sm.conv,
-                                      sm.relres, sm.ctr);
+                       h.sws, q);  // alpha
+      ts_update<T>(sg, s, X.p, s, 1.0, 1.0, P, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, q);
+      ts_update<T>(sg, s, R.p, s, 1.0, -1.0, Q, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, q);
+      col_sumsq<T>(sg, s, R.p, s, sm.colsq, work, q);
+      k_bcg_check<<<pb, 256, 0, q>>>(np, s, sm.colsq, sm.nF2, h.tol_inner, 0, sm.active, sm.itp, sm.conv,
+                                     sm.relres, sm.ctr, itd.p);
       NS_LAUNCH_CHECK();
+    };
+    auto half2 = [&](hipStream_t q) {
+      op_gamma_solve<T>(h, R.p, s, Z.p, s, s);                                // Z = A_G^{-1} R
+      gram<T, T>(sg, Q, s, s, Z.p, s, s, sm.G2, ss, 1.0, 0.0, work, q);       // Q^T Z
+      k_dims<<<pb, 256, 0, q>>>(np, s, sm.active, sm.rank, sm.dimA);
+      NS_LAUNCH_CHECK();
+      small_chol_apply(Batch{np, sm.dimA}, s, sm.Delta, ss, sm.G2, s, ss, sm.beta, s, ss, s, s, -1.0, h.sws,
+                       q);  // beta
+      ts_update<T>(sg, s, Z.p, s, 1.0, 1.0, P, s, s, sm.beta, s, ss, nullptr, 0, 0, nullptr, 0, 0, q);  // Z + P beta
+      orth<T>(h, sm, work, Z.p, P, Q, s, 0, itd.p);
+    };
+    auto done = [&]() {  // breakdown flag and problems finished, from the device
       NS_HIP(hipMemcpyAsync(hc + 1, sm.flag, sizeof(int), hipMemcpyDeviceToHost, st));
       read_back(h, hc, sm.ctr, 1);
       if (hc[1]) fail(BREAKDOWN, "block CG: P^T S P is not positive definite");
-      if (hc[0] >= np) break;
-      op_gamma_solve<T>(h, R.p, s, Z.p, s, s);                                 // Z = A_G^{-1} R
-      gram<T, T>(sg, Q, s, s, Z.p, s, s, sm.G2, ss, 1.0, 0.0, work, st);       // Q^T Z
-      k_dims<<<pb, 256, 0, st>>>(np, s, sm.active, sm.rank, sm.dimA);
-      NS_LAUNCH_CHECK();
-      small_chol_apply(Batch{np, sm.dimA}, s, sm.Delta, ss, sm.G2, s, ss, sm.beta, s, ss, s, s, -1.0, h.sws,
-                       st);  // beta
-      ts_update<T>(sg, s, Z.p, s, 1.0, 1.0, P, s, s, sm.beta, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);  // Z + P beta
-      orth<T>(h, sm, work, Z.p, P, Q, s, it);
+      return hc[0] >= np;
+    };
+    op_gamma_solve<T>(h, R.p, s, Z.p, s, s);
+    orth<T>(h, sm, work, Z.p, P, Q, s, 0, itd.p);
+    int it = 1;
+    half1(st);  // the first iteration runs with plain launches: it also sizes every workspace the body uses
+    bool fin = done();
+    if (!fin && it < h.max_inner) half2(st);
+    // m iterations per graph (an even count, so that the two search-direction buffers P and Q, which swap
+    // roles every iteration, are where the recording found them at every replay); iterations a replay runs
+    // after every problem has finished change nothing (finished problems are frozen)
+    const int m = h.bcg_graph == 0 ? 2 : (h.bcg_graph < 0 ? 0 : 2 * ((h.bcg_graph + 1) / 2));
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    if (!fin && m > 0 && it + m <= h.max_inner) {
+      NS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipGraph_t graph = nullptr;
+      h.stream = cap;
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        try {
+          for (int t = 0; t < m; ++t) {
+            half1(cap);
+            half2(cap);
+          }
+        } catch (...) {
+          (void)hipStreamEndCapture(cap, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          h.stream = st;
+          (void)hipStreamDestroy(cap);
+          throw;
+        }
+        e = hipStreamEndCapture(cap, &graph);
+      }
+      h.stream = st;
+      if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamDestroy(cap);
+        fail(HIP, std::string("block-CG graph capture failed: ") + hipGetErrorString(e));
+      }
+      while (!fin && it + m <= h.max_inner) {
+        NS_HIP(hipGraphLaunch(exec, st));
+        it += m;
+        fin = done();
+      }
     }
+    while (!fin && it < h.max_inner) {  // plain launches (no graph, or the last iterations before the cap)
+      ++it;
+      half1(st);
+      fin = done();
+      if (!fin && it < h.max_inner) half2(st);
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (cap) (void)hipStreamDestroy(cap);
   }
   if constexpr (sizeof(T) == 8)
     NS_HIP(hipMemcpyAsync(D, X.p, nG * s * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -975,6 +1043,7 @@ Handle* new_handle(const ns_options* opt) {
   h->trsm_cols = opt->trsm_cols;
   h->schur_mode = opt->schur_mode;
   h->pcg_graph = opt->pcg_graph_iters;
+  h->bcg_graph = opt->bcg_graph_iters;
   h->proposal = opt->proposal;
   h->accept_tol = opt->accept_tol > 0 ? opt->accept_tol : 0.2;
   h->variant = opt->variant;

@@ -90,6 +90,7 @@ class NsOptions(ctypes.Structure):
         ("variant", c_int32),
         ("power_iters", c_int32),
         ("outer", c_int32),
+        ("bcg_graph_iters", c_int32),
     ]
 
 
@@ -237,14 +238,14 @@ def _setup_info_dict(si: NsSetupInfo) -> dict:
 def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_inner=0.1, eig_thresh_rel=1e-10,
                         orth_drop_rel=0.0, max_inner_iters=500, prec_inner=NS_FP64, apply_mode=NS_APPLY_M2,
                         trsm_cols=0, schur_mode=0, proposal=None, accept_tol=0.2, pcg_graph_iters=0,
-                        variant=NS_VARIANT_M2, power_iters=0, outer=NS_OUTER_SCHUR):
+                        variant=NS_VARIANT_M2, power_iters=0, outer=NS_OUTER_SCHUR, bcg_graph_iters=0):
     """Returns (handle, info dict).  row_ptr int64, col_idx int32, val float64, part int32, omega float64
     (n_gamma x (k+p), row-major; n_interior x (k+p) for NS_VARIANT_M3), all CUDA tensors."""
     lib = load_library()
     n = row_ptr.numel() - 1
     nnz = val.numel()
     opt = _options(k, p, tol_inner, eig_thresh_rel, orth_drop_rel, max_inner_iters, prec_inner, apply_mode,
-                   trsm_cols, schur_mode, accept_tol, pcg_graph_iters, variant, power_iters, outer)
+                   trsm_cols, schur_mode, accept_tol, pcg_graph_iters, variant, power_iters, outer, bcg_graph_iters)
     opt.omega = _dev(omega, torch.float64, "omega") if omega is not None else None
     opt.proposal = _dev(proposal, torch.float64, "proposal") if proposal is not None else None
     h = c_void_p()
@@ -257,7 +258,8 @@ def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_in
 
 
 def _options(k, p, tol_inner, eig_thresh_rel, orth_drop_rel, max_inner_iters, prec_inner, apply_mode, trsm_cols,
-             schur_mode, accept_tol, pcg_graph_iters=0, variant=NS_VARIANT_M2, power_iters=0, outer=NS_OUTER_SCHUR):
+             schur_mode, accept_tol, pcg_graph_iters=0, variant=NS_VARIANT_M2, power_iters=0, outer=NS_OUTER_SCHUR,
+             bcg_graph_iters=0):
     opt = NsOptions()
     opt.k, opt.p = int(k), int(p)
     opt.tol_inner = tol_inner
@@ -274,19 +276,20 @@ def _options(k, p, tol_inner, eig_thresh_rel, orth_drop_rel, max_inner_iters, pr
     opt.variant = variant
     opt.power_iters = power_iters
     opt.outer = outer
+    opt.bcg_graph_iters = bcg_graph_iters
     return opt
 
 
 def nystrom_schur_setup_batched(problems, *, k, p, omegas=None, tol_inner=0.1, eig_thresh_rel=1e-10,
                                 orth_drop_rel=0.0, max_inner_iters=500, prec_inner=NS_FP64, apply_mode=NS_APPLY_M2,
                                 trsm_cols=0, schur_mode=0, pcg_graph_iters=0, variant=NS_VARIANT_M2,
-                                power_iters=0, outer=NS_OUTER_SCHUR):
+                                power_iters=0, outer=NS_OUTER_SCHUR, bcg_graph_iters=0):
     """problems: list of (row_ptr, col_idx, val, part) CUDA tensors; omegas: list of n_gamma(q) x (k+p) float64
     CUDA tensors.  Returns (handle, list of info dicts)."""
     lib = load_library()
     m = len(problems)
     opt = _options(k, p, tol_inner, eig_thresh_rel, orth_drop_rel, max_inner_iters, prec_inner, apply_mode,
-                   trsm_cols, schur_mode, 0.2, pcg_graph_iters, variant, power_iters, outer)
+                   trsm_cols, schur_mode, 0.2, pcg_graph_iters, variant, power_iters, outer, bcg_graph_iters)
     n = (c_int64 * m)(*[pr[0].numel() - 1 for pr in problems])
     nnz = (c_int64 * m)(*[pr[2].numel() for pr in problems])
     ptrs = [(c_void_p * m)(*[_dev(pr[i], dt, nm) for pr in problems])
