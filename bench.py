@@ -469,6 +469,8 @@ def bench_single(args):
     del cal
     torch.cuda.synchronize()
 
+    tuning = {}
+
     def step(prec, solve=True):
         s = ns.NystromSchur(A["row_ptr"], A["col_idx"], A["val"], A["part"], k=P.k, p=P.p, omega=omega,
                             tol_inner=P.tol_inner, prec_inner=prec, trsm_cols=args.trsm_cols,
@@ -477,6 +479,7 @@ def bench_single(args):
         if solve:
             x, info = s.solve(b, rtol=P.tol_outer, maxit=4000)
         si = s.setup_info
+        tuning[["fp64", "fp32", "bf16"][prec]] = ns.nystrom_schur_get_tuning(s.handle)
         s.close()
         return si, info
 
@@ -588,6 +591,7 @@ def bench_single(args):
         "t_phases_s": {k: si[k] for k in ("t_extract", "t_factor", "t_inner", "t_nystrom")},
         "schur_bcg_gbs": gbs_main["gbs"],
         "schur_bcg": {prec_name: gbs_main},
+        "tuning": {"table_entries": ns.nystrom_schur_tuning_info()[0], "applied": tuning},
     }
     for name, side in sides.items():
         sp = {"plain_fp64": ns.NS_FP64, "fp32_inner": ns.NS_FP32, "bf16_inner": ns.NS_BF16}[name]

@@ -376,6 +376,22 @@ void nystrom_schur_kernel_timing_families(uint32_t mask);
 ns_status nystrom_schur_kernel_stats(const char* family, double* total_ms, int64_t* launches, double* bytes,
                                      double* flops);
 
+/* Automatic settings.  The library takes the automatic choices below from a table written by the project's
+ * autotuner (paper_2101_12164_amd/autotune.py: it times the candidates on the device and keeps the fastest),
+ * shipped beside the shared library as tuning_<arch>.tsv and keyed by architecture, kernel, precision and
+ * size class; explicit ns_options values take precedence.  get_tuning reports, for a handle, the values
+ * that apply to its sizes: out[0] columns per workgroup of the multi-column triangular sweeps (k + p
+ * columns), out[1] PCG iterations per graph, out[2] block-CG iterations per graph, out[3] output columns per
+ * workgroup of the local Schur products for 65-80 columns (64 or 80).  HOST array of 4.  tuning_info returns
+ * the number of table entries loaded for the current device and copies the table's path into `path` (HOST,
+ * capacity `cap`, may be NULL). */
+ns_status nystrom_schur_get_tuning(ns_handle h, int32_t* out);
+int32_t nystrom_schur_tuning_info(char* path, int32_t cap);
+/* Process-wide value of one automatic setting ("trsm_cols", "pcg_graph_iters", "bcg_graph_iters",
+ * "ls_gemm_cols") that takes precedence over the table until removed (value 0); the autotuner times its
+ * candidates with it.  Returns 0, or -1 for a NULL name. */
+int32_t nystrom_schur_tuning_override(const char* kernel, int32_t value);
+
 /* Release everything the handle owns.  Idempotent on NULL. */
 void nystrom_schur_destroy(ns_handle h);
 

@@ -16,7 +16,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnystrom_schur.so")
 SOURCES = [
     "tile_kernels.hip", "sparse_kernels.hip", "vec_kernels.hip", "small_kernels.hip", "ns_solver.hip", "ktimer.hip",
-    "local_schur.hip", "tile_gemv.hip", "learned.hip", "device_memory.hip", "sym_gemv.hip"
+    "local_schur.hip", "tile_gemv.hip", "learned.hip", "device_memory.hip", "sym_gemv.hip", "tuning.hip"
 ]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -53,7 +53,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
             if err.strip():
                 print(o, err, file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-ldl"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

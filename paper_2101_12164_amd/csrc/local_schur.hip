@@ -740,7 +740,7 @@ void launch_gemm(const LocalSchur& ls, const T* A, const T* B, T* C, int N, hipS
   const int tilesM = (maxM + 63) / 64;
   if (N <= 16 && !sym) {
     k_gemm_tn<T, 16><<<gemm_grid(1, tilesM, nblk, g.plen), 256, 0, st>>>(g, A, B, C, N, 0, 1, tilesM, nblk);
-  } else if (N > 64 && N <= 80 && !sym) {
+  } else if (N > 64 && N <= 80 && !sym && tuned("ls_gemm_cols", sizeof(T) == 8 ? "f64" : "f32", N, 80) == 80) {
     k_gemm_tn<T, 80><<<gemm_grid(1, tilesM, nblk, g.plen), 256, 0, st>>>(g, A, B, C, N, 0, 1, tilesM, nblk);
   } else {
     const int tilesN = sym ? tilesM : (N + 63) / 64;

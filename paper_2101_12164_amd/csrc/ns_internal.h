@@ -196,6 +196,11 @@ struct TileLevel {
   void layout_band(const std::vector<int>& bw);  // host: band, factor storage (allocates L64, Linv64)
 };
 
+// ---------------------------------------------------------------- tuned settings
+// The tuned value of an automatic setting (kernel: "trsm_cols", "pcg_graph_iters", "bcg_graph_iters",
+// "ls_gemm_cols"; prec: "f64", "f32", "bf16") for a size, from the table beside the library, else fallback.
+int tuned(const char* kernel, const char* prec, int64_t size, int fallback);
+
 // ---------------------------------------------------------------- kernel timing
 // Families of launches that can be timed with HIP events (opt-in, ABI
 // nystrom_schur_kernel_timing / nystrom_schur_kernel_stats).

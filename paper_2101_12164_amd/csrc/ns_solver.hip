@@ -313,7 +313,10 @@ void block_pcg(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
     // m iterations per graph (an even count, so that the two search-direction buffers P and Q, which swap
     // roles every iteration, are where the recording found them at every replay); iterations a replay runs
     // after every problem has finished change nothing (finished problems are frozen)
-    const int m = h.bcg_graph == 0 ? 2 : (h.bcg_graph < 0 ? 0 : 2 * ((h.bcg_graph + 1) / 2));
+    const int mb = h.bcg_graph == 0 ? tuned("bcg_graph_iters", h.bf16 ? "bf16" : (sizeof(T) == 8 ? "f64" : "f32"),
+                                            h.nG, 2)
+                                    : h.bcg_graph;
+    const int m = mb <= 0 ? 0 : 2 * ((mb + 1) / 2);
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
     if (!fin && m > 0 && it + m <= h.max_inner) {
@@ -751,7 +754,7 @@ __global__ void k_sqrt_inplace(int n, double* x, int stride) {
 template <class Head, class Tail>
 void pcg_loop(Handle& h, int np, const PcgState& S, int maxit, int hc[2], Head head, Tail tail) {
   hipStream_t st = h.stream;
-  int m = h.pcg_graph == 0 ? (np > 1 ? 4 : 1) : h.pcg_graph;
+  int m = h.pcg_graph == 0 ? tuned("pcg_graph_iters", "f64", h.nG, np > 1 ? 4 : 1) : h.pcg_graph;
   head(st);
   read_back(h, hc, S.ndone, 2);
   if (hc[0] < np && hc[1] < maxit) tail(st);
@@ -1422,6 +1425,23 @@ ns_status nystrom_schur_apply(ns_handle h, const double* r_gamma, double* z_gamm
     const SmallWs ws = small_ws(gs, h->nprob, std::max(h->s, 1), ncols);
     apply_prec(*h, r_gamma, ncols, z_gamma, ncols, ncols, work, c1, c2, ws);
     NS_HIP(hipStreamSynchronize(h->stream));
+    return NS_OK;
+  } catch (const Error& e) {
+    return finish(h, e);
+  }
+}
+
+ns_status nystrom_schur_get_tuning(ns_handle h, int32_t* out) {
+  if (!h) return finish(nullptr, Error{INVALID_ARG, "NULL handle"});
+  try {
+    StreamScope ss(h->stream);
+    if (!out) fail(INVALID_ARG, "out must not be NULL");
+    const char* pi = h->bf16 ? "bf16" : (h->prec_inner ? "f32" : "f64");
+    const int s = std::max(h->s, 1);
+    out[0] = h->trsm_cols ? h->trsm_cols : tuned("trsm_cols", h->prec_inner ? "f32" : "f64", s, s <= 16 ? 16 : 32);
+    out[1] = h->pcg_graph ? h->pcg_graph : tuned("pcg_graph_iters", "f64", h->nG, h->nprob > 1 ? 4 : 1);
+    out[2] = h->bcg_graph ? h->bcg_graph : tuned("bcg_graph_iters", pi, h->nG, 2);
+    out[3] = tuned("ls_gemm_cols", h->prec_inner ? "f32" : "f64", s, 80);
     return NS_OK;
   } catch (const Error& e) {
     return finish(h, e);

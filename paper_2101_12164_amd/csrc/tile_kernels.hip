@@ -872,7 +872,8 @@ void tile_solve(const TileLevel& lv, T* B, int64_t ldb, int ncols, int cw, hipSt
     L = lv.L32.p;
     Li = lv.Linv32.p;
   }
-  if (cw <= 0) cw = ncols <= 16 ? 16 : 32;
+  if (cw <= 0) cw = tuned("trsm_cols", sizeof(T) == 8 ? "f64" : "f32", ncols, ncols <= 16 ? 16 : 32);
+  if (cw != 16 && cw != 32 && cw != 64) cw = 32;
   if (cw == 16)
     launch_trsm<T, 16>(lv, B, ldb, ncols, L, Li, st);
   else if (cw == 32)

@@ -59,6 +59,9 @@ EXPORTED = [
     "nystrom_schur_kernel_timing",
     "nystrom_schur_kernel_timing_families",
     "nystrom_schur_kernel_stats",
+    "nystrom_schur_get_tuning",
+    "nystrom_schur_tuning_info",
+    "nystrom_schur_tuning_override",
     "nystrom_schur_destroy",
     "nystrom_schur_last_error",
 ]
@@ -184,6 +187,12 @@ def load_library() -> ctypes.CDLL:
     lib.nystrom_schur_apply.restype = c_int32
     lib.nystrom_schur_apply_noalloc.argtypes = [H, c_void_p, c_void_p, c_int32]
     lib.nystrom_schur_apply_noalloc.restype = c_int32
+    lib.nystrom_schur_get_tuning.argtypes = [H, POINTER(c_int32)]
+    lib.nystrom_schur_get_tuning.restype = c_int32
+    lib.nystrom_schur_tuning_info.argtypes = [c_char_p, c_int32]
+    lib.nystrom_schur_tuning_info.restype = c_int32
+    lib.nystrom_schur_tuning_override.argtypes = [c_char_p, c_int32]
+    lib.nystrom_schur_tuning_override.restype = c_int32
     lib.nystrom_schur_pcg_solve.argtypes = [H, c_void_p, c_void_p, c_double, c_int32, POINTER(NsSolveInfo)]
     lib.nystrom_schur_pcg_solve.restype = c_int32
     for name in ("nystrom_schur_schur_apply", "nystrom_schur_interface_solve", "nystrom_schur_interior_solve"):
@@ -406,6 +415,27 @@ def nystrom_schur_export_factor(handle, block: int, nb: int, device="cuda"):
     L = torch.empty((nb, nb), dtype=torch.float64, device=device)
     _check(lib.nystrom_schur_export_factor(handle, block, _dev(L, torch.float64, "L")), handle)
     return L.t()  # stored column-major
+
+
+def nystrom_schur_get_tuning(handle):
+    """The automatic settings that apply to a handle's sizes (see the header)."""
+    lib = load_library()
+    out = (c_int32 * 4)()
+    _check(lib.nystrom_schur_get_tuning(handle, out), handle)
+    return {"trsm_cols": out[0], "pcg_graph_iters": out[1], "bcg_graph_iters": out[2], "ls_gemm_cols": out[3]}
+
+
+def nystrom_schur_tuning_info():
+    """(number of table entries loaded for the current device, the table's path)."""
+    lib = load_library()
+    buf = ctypes.create_string_buffer(4096)
+    n = lib.nystrom_schur_tuning_info(buf, 4096)
+    return n, buf.value.decode()
+
+
+def nystrom_schur_tuning_override(kernel, value):
+    """Process-wide value of an automatic setting (0 removes it), over the table."""
+    return load_library().nystrom_schur_tuning_override(kernel.encode(), int(value))
 
 
 def nystrom_schur_get_lowrank(handle, device="cuda"):
