@@ -10,7 +10,8 @@ Preconditioner for Sparse Symmetric Positive Definite Matrices" (arXiv
 LDL^T factorisation (eq. A_LDLT), the Schur complement (eq. schur_complement),
 the Sherman-Morrison-Woodbury form (eq. S-1), Nystrom's method (Algorithm
 alg:nystrom), the construction of M_2 (Algorithm alg:prec1, eq. left_prec_mat)
-and PCG on S_Gamma w = f (eq. Sx=b).
+and PCG on S_Gamma w = f (eq. Sx=b), and the recursive construction the
+conclusions name as future work (A_Gamma preconditioned one level down).
 """
 
 from .nystrom_schur_oracle import (  # noqa: F401
@@ -22,6 +23,8 @@ from .nystrom_schur_oracle import (  # noqa: F401
     NystromSchurOracle,
     GammaFactor,
     level2_order,
+    level2_part,
+    RecursiveGamma,
     pcg,
     dense_schur,
     ideal_s2,

@@ -106,9 +106,11 @@ class Operators:
     rounding, for sizes where dense copies do not fit in host memory).
     """
 
-    def __init__(self, dbbd: DBBD, factor: str = "dense", gamma_factor: Optional[str] = None):
+    def __init__(self, dbbd: DBBD, factor: str = "dense", gamma_factor: Optional[str] = None,
+                 gamma_solve: Optional[Callable] = None):
         self.d = dbbd
         self.factor = factor
+        self._gamma_solve = gamma_solve  # an approximate A_Gamma^{-1} (the recursive level), else exact
         self._blk = []
         for j in range(dbbd.n_sub):
             Aj = dbbd.block(j)
@@ -118,7 +120,9 @@ class Operators:
             else:
                 self._blk.append(("sparse", spla.splu(Aj.tocsc())))
         gf = gamma_factor or ("dense" if dbbd.n_gamma <= 6000 else "sparse")
-        if dbbd.n_gamma == 0:
+        if gamma_solve is not None:
+            self._g = ("given", None)
+        elif dbbd.n_gamma == 0:
             self._g = ("none", None)
         elif gf == "dense":
             self._g = ("dense", sla.cholesky(dbbd.A_G.toarray(), lower=True))
@@ -148,6 +152,8 @@ class Operators:
         """A_Gamma^{-1} X (the first-level preconditioner of eq. S1)."""
         X = np.asarray(X, dtype=np.float64)
         kind, F = self._g
+        if kind == "given":
+            return self._gamma_solve(X)
         if kind == "none":
             return X.copy()
         if kind == "dense":
@@ -212,6 +218,58 @@ class GammaFactor:
     def solve_t(self, Y):
         """R^{-T} Y = P^T L^{-1} (P Y)."""
         return self._unperm(sla.solve_triangular(self.L, np.asarray(Y)[self.perm], lower=True))
+
+
+# ----------------------------------------------------------------------------
+# the recursive (multilevel) construction: A_Gamma^{-1} replaced by a Nystrom-Schur preconditioner one level down
+
+
+def level2_part(d: DBBD):
+    """Labels that make A_Gamma a DBBD matrix of its own: separator block b (label -2 - b) -> subdomain b, junction
+    node (label -1) -> interface.  Rows and columns of A_Gamma keep the interface order."""
+    pg = d.part[d.G]
+    return np.where(pg <= -2, -2 - pg, -1).astype(np.int32)
+
+
+class RecursiveGamma:
+    """Approximate A_Gamma^{-1} of the recursive construction the conclusions name as future work (with the
+    reading of the design notes): A_Gamma, split by the level-2 labels (separator blocks = its interior s,
+    junction nodes = its interface J), is preconditioned exactly as A is -- the block LDL^T solve of eq. A_LDLT
+    with the inverse of its Schur complement S_J = A_J - A_Js A_s^{-1} A_sJ replaced by the Nystrom-Schur
+    preconditioner M_J of S_J (eq. left_prec_mat one level down: sketch ``omega`` of n_J x (k + p), inner
+    block solve preconditioned by A_J^{-1}):
+
+        u_s = A_s^{-1} r_s,   y_J = M_J (r_J - A_Js u_s),   z_s = A_s^{-1} (r_s - A_sJ y_J),   z_J = y_J,
+
+    the preconditioner M^{-1} of the Schur-complement section applied to A_Gamma.  Only the separator blocks and
+    A_J are factorised.  ``k = 0`` gives M_J = A_J^{-1}."""
+
+    def __init__(self, d: DBBD, *, k, p, omega, tol_inner=0.1, eps_rel=1e-10, delta=1e-6, maxit_inner=500,
+                 factor="dense"):
+        part2 = level2_part(d)
+        if not np.any(part2 == -1):
+            raise ValueError("RecursiveGamma: the level-2 split has no junction nodes")
+        if not np.any(part2 >= 0):
+            raise ValueError("RecursiveGamma: the level-2 split has no separator blocks")
+        AG = sp.csr_matrix(d.A_G)
+        AG.sort_indices()
+        self.inner = NystromSchurOracle(d.n_gamma, AG.indptr, AG.indices, AG.data, part2, k=k, p=p, omega=omega,
+                                        tol_inner=tol_inner, eps_rel=eps_rel, delta=delta, maxit_inner=maxit_inner,
+                                        factor=factor)
+        self.setup_result = self.inner.setup()
+
+    def solve(self, R):
+        """Approximate A_Gamma^{-1} R (interface order, one vector or a block of columns)."""
+        sub = self.inner
+        sd, so = sub.dbbd, sub.ops
+        R = np.asarray(R, dtype=np.float64)
+        uI = so.solve_I(R[sd.I])
+        yG = sub.apply(R[sd.G] - sd.A_GI @ uI)
+        zI = so.solve_I(R[sd.I] - sd.A_IG @ yG)
+        out = np.empty_like(R)
+        out[sd.I] = zI
+        out[sd.G] = yG
+        return out
 
 
 # ----------------------------------------------------------------------------
@@ -413,13 +471,24 @@ class NystromSchurOracle:
     preconditioned by A_I^{-1}, the literal step 3).
     ``power``: q of eq. power -- the sketch is B^q Omega, orthonormalised (QR) after every product with B.
     ``k = 0`` gives the first-level preconditioner S_1.
+    ``level2``: None -- A_Gamma^{-1} exact (eq. S1) -- or dict(k=, p=, omega=, tol_inner=) -- every solve with
+    A_Gamma uses the recursive approximation of ``RecursiveGamma`` built with those parameters (its tolerance
+    defaults to ``tol_inner``); not with 'M1', which needs an exact factor of A_Gamma.
     """
 
     def __init__(self, n, row_ptr, col, val, part, *, k, p, omega, tol_inner=0.1, eps_rel=1e-10, delta=1e-6,
                  maxit_inner=500, factor="dense", apply_mode="M2", inner="shifted", gamma_factor=None,
-                 proposal=None, accept_tol=0.2, variant="M2", power=0):
+                 proposal=None, accept_tol=0.2, variant="M2", power=0, level2=None):
         self.dbbd = DBBD(n, row_ptr, col, val, part)
-        self.ops = Operators(self.dbbd, factor=factor, gamma_factor=gamma_factor)
+        self.level2 = None
+        if level2 is not None:
+            if variant == "M1":
+                raise ValueError("variant M1 needs an exact factor of A_Gamma (no recursive level)")
+            l2 = dict(level2)
+            l2.setdefault("tol_inner", tol_inner)
+            self.level2 = RecursiveGamma(self.dbbd, factor=factor, eps_rel=eps_rel, delta=delta, **l2)
+        self.ops = Operators(self.dbbd, factor=factor, gamma_factor=gamma_factor,
+                             gamma_solve=self.level2.solve if self.level2 is not None else None)
         self.k, self.p = int(k), int(p)
         self.omega = np.asarray(omega, dtype=np.float64) if omega is not None else None
         self.tol_inner = tol_inner

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from oracle import NystromSchurOracle  # noqa: E402
-from workloads import config_c1  # noqa: E402
+from workloads import config_c1, config_c2  # noqa: E402
 
 
 def c1_record(seed=0):
@@ -32,8 +32,25 @@ def c1_record(seed=0):
                 **out)
 
 
+def c2_record():
+    """The 64^3 lognormal system end to end (dense per-block factors: a few minutes on 8 cores)."""
+    P = config_c2()
+    o = NystromSchurOracle(P.n, P.row_ptr, P.col, P.val, P.part, k=P.k, p=P.p, omega=P.omega(),
+                           tol_inner=P.tol_inner, factor="dense")
+    s = o.setup()
+    r = o.solve(P.b(), tol=P.tol_outer)
+    return dict(config="c2: 3D 7-point lognormal sigma=2 ell=8 on 64^3, 4x4x4 boxes, k=64, p=16, eps_SI=0.1, "
+                       "tol 1e-8, seed %d" % P.seed,
+                M2=dict(it_inner=s.it_inner, k_eff=s.k_eff, it_pcg=r.it_pcg, relres_schur=r.relres_schur,
+                        relres_true=r.relres_true))
+
+
 if __name__ == "__main__":
-    path = os.path.join(ROOT, "tests", "golden", "c1_oracle.json")
-    with open(path, "w") as fh:
-        json.dump(c1_record(0), fh, indent=2)
-    print("wrote", path)
+    which = sys.argv[1:] or ["c1", "c2"]
+    for name, rec in (("c1", lambda: c1_record(0)), ("c2", c2_record)):
+        if name not in which:
+            continue
+        path = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.json")
+        with open(path, "w") as fh:
+            json.dump(rec(), fh, indent=2)
+        print("wrote", path)

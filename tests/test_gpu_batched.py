@@ -75,7 +75,7 @@ def test_batched_equals_alone(mode):
         np.testing.assert_allclose(outs[q]["res_hist"], o1["res_hist"], rtol=1e-10, atol=0)
         d = (xs[q] - x1).norm().item() / x1.norm().item()
         assert d <= 1e-13, (P.name, d)
-        assert outs[q]["relres_true"] <= 1e-7
+        assert outs[q]["relres_true"] <= 1e-8
 
 
 def test_batched_single_problem_is_bitwise_alone():

@@ -174,7 +174,7 @@ def test_exact_proposal_is_accepted():
     so = o.solve(P.b())
     assert o.setup_result.proposal_accepted
     assert abs(out["it_pcg"] - so.it_pcg) <= 1
-    assert out["relres_true"] <= 1e-7
+    assert out["relres_true"] <= 1e-8
 
 
 def test_rejected_proposal_falls_back_bitwise():
@@ -241,7 +241,7 @@ def test_trained_network_gain_on_held_out_problems():
                 print(P.name, "accepted", a, "rho", round(rho, 3), "it_pcg learned/plain", ol["it_pcg"],
                       op["it_pcg"], "setup s", round(hl.setup_info["t_total"], 4), round(hp.setup_info["t_total"], 4),
                       flush=True)
-                assert ol["relres_true"] <= 1e-7 and op["relres_true"] <= 1e-7
+                assert ol["relres_true"] <= 1e-8 and op["relres_true"] <= 1e-8
                 if not a:
                     assert ol["it_pcg"] == op["it_pcg"]
             finally:

@@ -134,6 +134,25 @@ def pins_pass(m):
     ref = BGq @ np.linalg.pinv(0.5 * (Gq.T @ BGq + BGq.T @ Gq)) @ BGq.T
     Uq, Sq, _ = m.nystrom_core(sq.Y, Gq, 7, 1e-14)
     ok.append(np.allclose(Uq @ np.diag(Sq) @ Uq.T, ref, atol=1e-9 * np.abs(ref).max()))
+    # 12. recursive level: a full-rank level-2 sketch gives the exact A_Gamma^{-1}; a low-rank one keeps the block
+    #     LDL^T spectrum identity Lambda(A~^{-1} A_Gamma) = Lambda(M_J S_J) u {1}
+    V = make_problem((8, 8, 8), (2, 2, 2), sigma=1.5, ell=3.0, k=4, p=2)
+    dV = m.DBBD(V.n, V.row_ptr, V.col, V.val, V.part)
+    nJ = int(np.count_nonzero(m.level2_part(dV) == -1))
+    AGV = dV.A_G.toarray()
+    rf = m.RecursiveGamma(dV, k=nJ, p=0, omega=np.random.default_rng(3).standard_normal((nJ, nJ)), tol_inner=1e-14,
+                          eps_rel=1e-14)
+    XV = np.random.default_rng(1).standard_normal((dV.n_gamma, 2))
+    ok.append(np.allclose(rf.solve(XV), np.linalg.solve(AGV, XV), rtol=1e-9, atol=1e-11))
+    rl = m.RecursiveGamma(dV, k=5, p=2, omega=np.random.default_rng(4).standard_normal((nJ, 7)))
+    Mt = rl.solve(np.eye(dV.n_gamma))
+    Lc = np.linalg.cholesky(0.5 * (Mt + Mt.T))
+    ev = np.sort(np.linalg.eigvalsh(Lc.T @ AGV @ Lc))
+    MJ = rl.inner.apply(np.eye(nJ))
+    LJ = np.linalg.cholesky(0.5 * (MJ + MJ.T))
+    evJ = np.sort(np.linalg.eigvalsh(LJ.T @ m.dense_schur(rl.inner.dbbd) @ LJ))
+    ok.append(np.allclose(Mt, Mt.T, atol=1e-13 * np.abs(Mt).max())
+              and np.allclose(ev, np.sort(np.concatenate([evJ, np.ones(dV.n_gamma - nJ)])), atol=1e-10))
     return all(ok), ok
 
 
@@ -167,6 +186,10 @@ MUTATIONS = {
                                        "return ops.solve_I(d.A_IG @ res.X), res.iters"),
     "power_keeps_first_sketch": ("            G = np.linalg.qr(Y)[0]\n", "            pass\n"),
     "Y_without_AG": ("BX = d.A_G @ res.X", "BX = res.X"),
+    "rec_drops_coupling": ("yG = sub.apply(R[sd.G] - sd.A_GI @ uI)", "yG = sub.apply(R[sd.G])"),
+    "rec_backsub_sign": ("zI = so.solve_I(R[sd.I] - sd.A_IG @ yG)", "zI = so.solve_I(R[sd.I] + sd.A_IG @ yG)"),
+    "rec_without_low_rank": ("yG = sub.apply(R[sd.G] - sd.A_GI @ uI)", "yG = so.solve_G(R[sd.G] - sd.A_GI @ uI)"),
+    "rec_backsub_from_first_solve": ("zI = so.solve_I(R[sd.I] - sd.A_IG @ yG)", "zI = uI"),
 }
 
 
