@@ -104,6 +104,23 @@ typedef enum { NS_VARIANT_M2 = 0, NS_VARIANT_M1 = 1, NS_VARIANT_M3 = 2 } ns_vari
 typedef enum { NS_OUTER_SCHUR = 0, NS_OUTER_FULL = 1 } ns_outer;
 
 /*
+ * How every solve with A_Gamma is made (the first level of M, the inner block CG's preconditioner, Z):
+ *   NS_LEVEL2_EXACT:    exactly, through the interface split given by the labels (interface blocks, then
+ *                       the junction Schur complement S_J = A_J - A_Js A_s^{-1} A_sJ, factorised);
+ *   NS_LEVEL2_NYSTROM:  the recursive construction the conclusions name as future work: A_Gamma, taken as
+ *                       a DBBD matrix of its own (interface blocks = its interior, junction nodes = its
+ *                       interface), is preconditioned by its block LDL^T (eq. A_LDLT, the preconditioner
+ *                       M^{-1} of the Schur-complement section) with S_J^{-1} replaced by the
+ *                       Nystrom-Schur preconditioner M_J = A_J^{-1} + Z_J Sigma_J Z_J^T of S_J (Algorithm
+ *                       alg:prec1 one level down, rank level2_k, sketch level2_omega, tolerance
+ *                       level2_tol_inner, preconditioned by A_J^{-1}).  Only the interface blocks and A_J
+ *                       are factorised.  One problem per handle; FP64 inner work; not with
+ *                       NS_VARIANT_M1 (which needs an exact factor of A_Gamma) or a learned proposal;
+ *                       the labels must give at least one interface block and one junction node.
+ */
+typedef enum { NS_LEVEL2_EXACT = 0, NS_LEVEL2_NYSTROM = 1 } ns_level2;
+
+/*
  * Options of setup().  Zero-initialise and set what you need; a value of 0 in
  * tol_inner, eig_thresh_rel, orth_drop_rel or max_inner_iters selects the
  * default given in brackets.
@@ -145,6 +162,12 @@ typedef struct {
   int32_t bcg_graph_iters;   /* block-CG iterations recorded per HIP graph and replayed between the
                                 host's stopping checks (rounded up to an even count): 0 = automatic
                                 (2), -1 = plain launches.  Results are the same in every mode.   */
+  int32_t level2;            /* ns_level2 [NS_LEVEL2_EXACT]                                       */
+  int32_t level2_k;          /* NS_LEVEL2_NYSTROM: rank k_2 of M_J, 0 <= k_2 (0: M_J = A_J^{-1})  */
+  int32_t level2_p;          /* NS_LEVEL2_NYSTROM: oversampling p_2, k_2 + p_2 <= n_junction      */
+  double level2_tol_inner;   /* NS_LEVEL2_NYSTROM: block-CG tolerance of level 2 [tol_inner]      */
+  const double* level2_omega;/* NS_LEVEL2_NYSTROM: DEVICE, n_junction x (k_2 + p_2) row-major
+                                sketch, junction nodes in interface order.  Required when k_2 > 0. */
 } ns_options;
 
 /* Outputs of setup(), HOST memory. Times are seconds measured with hipEvents. */
@@ -162,6 +185,8 @@ typedef struct {
                                 to the end; 0 if the block CG broke down with them (P^T S P not positive
                                 definite: S_Gamma's small eigenvalues below BF16 resolution) and was run again
                                 with FP32 Schur operands (the preconditioner keeps its BF16 operands)      */
+  int32_t level2_it_inner;   /* NS_LEVEL2_NYSTROM: block-CG iterations of level 2, else 0         */
+  int32_t level2_k_eff;      /* NS_LEVEL2_NYSTROM: rank kept by M_J, else 0                       */
 } ns_setup_info;
 
 /* Outputs of pcg_solve(), HOST memory. */
@@ -221,7 +246,7 @@ ns_status nystrom_schur_apply(ns_handle h, const double* r_gamma, double* z_gamm
  * handle's own operator workspaces (sized at setup for k + p columns) are used as they are.
  * NS_ERR_INVALID_ARG when the call would need more than the 4 MiB (its need grows with k x ncols x the
  * number of reduction chunks, about n_gamma / 128 up to 240 per problem) or more columns than the handle's
- * workspaces hold.  Calls on one GPU share the array: calls that overlap on one GPU (two streams, two
+ * workspaces hold, and for handles built with NS_LEVEL2_NYSTROM.  Calls on one GPU share the array: calls that overlap on one GPU (two streams, two
  * threads) race and must not be made.
  */
 ns_status nystrom_schur_apply_noalloc(ns_handle h, const double* r_gamma, double* z_gamma, int32_t ncols);
@@ -254,7 +279,8 @@ ns_status nystrom_schur_pcg_solve(ns_handle h, const double* b, double* x, doubl
  *     entries (times are those of the whole batch), may be NULL.
  * The handle serves nystrom_schur_pcg_solve_batched and nystrom_schur_apply
  * (on the problems' interface vectors stacked in problem order).
- * Errors as nystrom_schur_setup; a failure in any problem fails the batch.
+ * Errors as nystrom_schur_setup; a failure in any problem fails the batch; opt->level2 must be
+ * NS_LEVEL2_EXACT.
  */
 ns_status nystrom_schur_setup_batched(int32_t nprob, const int64_t* n, const int64_t* nnz,
                                       const int64_t* const* row_ptr, const int32_t* const* col_idx,
@@ -282,7 +308,8 @@ ns_status nystrom_schur_pcg_solve_batched(ns_handle h, const double* const* b, d
  * the FP32 one used inside the inner block CG (inputs/outputs stay double). */
 ns_status nystrom_schur_schur_apply(ns_handle h, const double* X, double* Y, int32_t ncols, int32_t prec);
 
-/* Y = A_Gamma^{-1} X (the first-level preconditioner of eq. S1); interface order. */
+/* Y = A_Gamma^{-1} X (the first-level preconditioner of eq. S1); interface order.  With NS_LEVEL2_NYSTROM,
+ * the recursive approximation of A_Gamma^{-1} that the handle uses (FP64 only). */
 ns_status nystrom_schur_interface_solve(ns_handle h, const double* X, double* Y, int32_t ncols, int32_t prec);
 
 /* Y = A_I^{-1} X; X, Y: n_interior x ncols in interior order. */

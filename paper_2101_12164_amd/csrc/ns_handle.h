@@ -71,6 +71,16 @@ struct ns_handle_s {
   int op_bf16 = 0;  // FP32 operator applications currently use the BF16 copies
   int bf16_schur = 1;  // the BF16 copies of S_j are used (cleared after a block-CG breakdown on them)
   ns::SegBuf segI;                         // padded interior rows (one problem): the rows of variant M_3
+  // recursive level (NS_LEVEL2_NYSTROM): A_Gamma as a DBBD matrix of its own, preconditioned by a handle of
+  // its own (interior = interface blocks, interface = junction nodes), which this handle owns
+  int level2 = 0, level2_k = 0, level2_p = 0;
+  double level2_tol = 0.0;
+  const double* level2_omega = nullptr;
+  ns_handle_s* sub = nullptr;
+  ns::DBuf<double> recU, recT, recY;  // workspaces of the recursive A_Gamma solve (sized by columns)
+  int64_t rec_cols = 0;
+  ns::DBuf<double> subW, subC1, subC2;  // workspaces of the low-rank term when this handle is the level below
+  int64_t sub_cols = 0;
   double tol_inner = 0.1, eig_rel = 1e-10, drop_rel = 1e-6;
   int max_inner = 500;
 
@@ -145,6 +155,10 @@ template <class T>
 void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int ncols);
 template <class T>
 void op_interior_solve(Handle& h, const T* X, T* Y, int ncols);  // X, Y: n_I x ncols interior order
+// The preconditioner of a level-below handle g on its interface rows: z = M_g r (FP64, row-major, ncols
+// columns; its workspaces grow on first use and are reused afterwards, so calls inside a captured graph
+// allocate nothing once a call of the same width has run).
+void sub_apply(Handle& g, const double* r, int64_t ldr, double* z, int64_t ldz, int ncols);
 
 // Setup pieces.
 // Problems of a batch laid side by side in one matrix: piece q owns nodes [node[q], node[q + 1]),

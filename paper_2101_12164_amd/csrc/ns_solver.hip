@@ -1052,6 +1052,11 @@ Handle* new_handle(const ns_options* opt) {
   h->variant = opt->variant;
   h->power = opt->power_iters;
   h->outer = opt->outer;
+  h->level2 = opt->level2;
+  h->level2_k = opt->level2_k;
+  h->level2_p = opt->level2_p;
+  h->level2_tol = opt->level2_tol_inner;
+  h->level2_omega = opt->level2_omega;
   return h;
 }
 
@@ -1064,9 +1069,19 @@ void check_options(Handle* h) {
     fail(INVALID_ARG, "the full-system outer iteration needs the symmetric additive form (NS_APPLY_M2)");
   if (h->trsm_cols != 0 && h->trsm_cols != 16 && h->trsm_cols != 32 && h->trsm_cols != 64)
     fail(INVALID_ARG, "trsm_cols must be 0, 16, 32 or 64");
+  if (h->level2 != NS_LEVEL2_EXACT && h->level2 != NS_LEVEL2_NYSTROM) fail(INVALID_ARG, "level2 must be 0 or 1");
+  if (h->level2 == NS_LEVEL2_NYSTROM) {
+    if (h->prec_inner || h->bf16) fail(INVALID_ARG, "the recursive level runs with FP64 inner work only");
+    if (h->variant == NS_VARIANT_M1) fail(INVALID_ARG, "variant M1 needs an exact factor of A_Gamma");
+    if (h->proposal) fail(INVALID_ARG, "a learned proposal is not combined with the recursive level");
+    if (h->level2_k < 0 || h->level2_p < 0) fail(INVALID_ARG, "level2_k and level2_p must be >= 0");
+    if (h->level2_k > 0 && !h->level2_omega) fail(INVALID_ARG, "level2_omega is required when level2_k > 0");
+  }
   h->dflags.alloc(32);
   NS_HIP(hipMemsetAsync(h->dflags.p, 0, 32 * sizeof(int), h->stream));
 }
+
+void build_recursive_level(Handle* h, const int32_t* part);
 
 // Setup after the matrix is in place: extraction, factorisations, inner solve, Nystrom.
 // omega: n_G x s row-major (the problems' sketches stacked in interface order).
@@ -1098,19 +1113,23 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
     StreamSwap sw(*h, h->aux);
     if (h->schur_mode != SCHUR_TRIANGULAR) local_schur_plan(*h);
     NS_HIP(hipEventRecord(planned.e, h->stream));
-    tile_cholesky(h->L2, h->dflags.p + CHOL_FLAGS + 3, h->stream);
-    assemble_junction(*h);
-    tile_cholesky(h->LJ, h->dflags.p + CHOL_FLAGS + 6, h->stream);
-    for (ns::TileLevel* lv : {&h->L2, &h->LJ})
-      if (lv->nblk && lv->max_nt * TILE <= 4096 && lv->nrows_pad * lv->max_nt * TILE <= (int64_t(1) << 28))
-        tile_make_inverse(*lv, h->prec_inner != 0, h->stream);
-    if (h->prec_inner) {
-      tile_make_fp32(h->L2, h->stream);
-      tile_make_fp32(h->LJ, h->stream);
-    }
-    if (h->bf16) {
-      tile_make_bf16_inverse(h->L2, h->stream);
-      tile_make_bf16_inverse(h->LJ, h->stream);
+    if (h->level2 == NS_LEVEL2_NYSTROM) {
+      build_recursive_level(h, part);  // A_Gamma preconditioned one level down instead of factorised
+    } else {
+      tile_cholesky(h->L2, h->dflags.p + CHOL_FLAGS + 3, h->stream);
+      assemble_junction(*h);
+      tile_cholesky(h->LJ, h->dflags.p + CHOL_FLAGS + 6, h->stream);
+      for (ns::TileLevel* lv : {&h->L2, &h->LJ})
+        if (lv->nblk && lv->max_nt * TILE <= 4096 && lv->nrows_pad * lv->max_nt * TILE <= (int64_t(1) << 28))
+          tile_make_inverse(*lv, h->prec_inner != 0, h->stream);
+      if (h->prec_inner) {
+        tile_make_fp32(h->L2, h->stream);
+        tile_make_fp32(h->LJ, h->stream);
+      }
+      if (h->bf16) {
+        tile_make_bf16_inverse(h->L2, h->stream);
+        tile_make_bf16_inverse(h->LJ, h->stream);
+      }
     }
     NS_HIP(hipEventRecord(join.e, h->stream));
   }
@@ -1194,8 +1213,53 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
       o.t_nystrom = ev.sec(3, 4);
       o.t_total = ev.sec(0, 4);
       o.inner_bf16_schur = h->bf16 && h->bf16_schur ? 1 : 0;
+      o.level2_it_inner = h->sub ? h->sub->it_inner[0] : 0;
+      o.level2_k_eff = h->sub ? h->sub->h_keff[0] : 0;
     }
   }
+}
+
+__global__ void k_level2_labels(int64_t nG, const int32_t* __restrict__ gperm, const int32_t* __restrict__ part,
+                                int32_t* __restrict__ out) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= nG) return;
+  const int lab = part[gperm[g]];
+  out[g] = lab <= -2 ? -2 - lab : -1;
+}
+
+// The level below of the recursive construction: A_Gamma (this handle's interface rows and their couplings,
+// in interface order) set up as a problem of its own, with the interface blocks as its subdomains and the
+// junction nodes as its interface, on this handle's current stream.  The handle owns it from then on.
+void build_recursive_level(Handle* h, const int32_t* part) {
+  if (h->nprob != 1) fail(INVALID_ARG, "the recursive level applies to one problem (not a batch)");
+  if (h->nl2 == 0 || h->nJ == 0)
+    fail(INVALID_ARG, "the recursive level needs at least one interface block and one junction node");
+  if (h->level2_k > 0 && int64_t(h->level2_k) + h->level2_p > h->nJ)
+    fail(INVALID_ARG, "level2_k + level2_p exceeds the number of junction nodes");
+  DBuf<int32_t> part2;
+  part2.alloc(h->nG);
+  k_level2_labels<<<unsigned((h->nG + 255) / 256), 256, 0, h->stream>>>(h->nG, h->gperm, part, part2);
+  NS_LAUNCH_CHECK();
+  ns_options o{};
+  o.k = h->level2_k;
+  o.p = h->level2_k > 0 ? h->level2_p : 0;
+  o.tol_inner = h->level2_tol > 0 ? h->level2_tol : h->tol_inner;
+  o.eig_thresh_rel = h->eig_rel;
+  o.orth_drop_rel = h->drop_rel;
+  o.max_inner_iters = h->max_inner;
+  o.prec_inner = NS_FP64;
+  o.apply_mode = NS_APPLY_M2;
+  o.trsm_cols = h->trsm_cols;
+  o.schur_mode = h->schur_mode;
+  o.omega = h->level2_omega;
+  o.stream = h->stream;
+  o.pcg_graph_iters = -1;
+  o.bcg_graph_iters = h->bcg_graph;
+  Handle* g = new_handle(&o);
+  h->sub = g;  // freed with h, also when its setup fails
+  check_options(g);
+  const double* om = h->level2_k > 0 ? h->level2_omega : nullptr;
+  setup_core(g, h->nG, h->AGG.nnz, h->AGG.ptr.p, h->AGG.col.p, h->AGG.val64.p, part2.p, nullptr, &om, nullptr);
 }
 
 // Batch layout: part labels of every problem shifted into one numbering.
@@ -1233,6 +1297,18 @@ __global__ void k_shift_cols(int64_t m, const int32_t* __restrict__ c, int64_t a
 }
 
 }  // namespace
+
+void sub_apply(Handle& g, const double* r, int64_t ldr, double* z, int64_t ldz, int ncols) {
+  const int k = std::max(g.k, 1);
+  if (ncols > g.sub_cols) {
+    g.subW.alloc(gram_work_elems(g.segG.view, std::max(k, ncols)));
+    g.subC1.alloc(size_t(k) * ncols * g.nprob);
+    g.subC2.alloc(size_t(k) * ncols * g.nprob);
+    g.sub_cols = ncols;
+  }
+  apply_prec(g, r, ldr, z, ldz, ncols, g.subW.p, g.subC1.p, g.subC2.p, g.sws);
+}
+
 }  // namespace ns
 
 // ---------------------------------------------------------------------------------------------------------
@@ -1278,6 +1354,11 @@ namespace {
 // Frees the handle's buffers in order behind the work queued on its stream.
 void destroy_handle(Handle* h) {
   if (!h) return;
+  if (h->sub) {
+    h->sub->stream = h->stream;  // the level below may still name a stream a graph capture used
+    destroy_handle(h->sub);
+    h->sub = nullptr;
+  }
   if (h->aux) (void)hipStreamSynchronize(h->aux);  // a failed setup may leave work queued there
   {
     StreamScope ss(h->stream);
@@ -1339,6 +1420,7 @@ ns_status nystrom_schur_setup_batched(int32_t nprob, const int64_t* n, const int
       }
     h = new_handle(opt);
     StreamScope ss(h->stream);
+    if (h->level2 != NS_LEVEL2_EXACT) fail(INVALID_ARG, "the recursive level applies to one problem (not a batch)");
     check_options(h);
     if (h->variant == NS_VARIANT_M3 && nprob > 1)
       fail(INVALID_ARG, "the variant M_3 (sketch on the interior space) takes one problem per handle");
@@ -1453,6 +1535,7 @@ ns_status nystrom_schur_apply_noalloc(ns_handle h, const double* r_gamma, double
   try {
     StreamScope ss(h->stream);
     if (ncols < 1 || ncols > 1024 || !r_gamma || !z_gamma) fail(INVALID_ARG, "bad apply arguments");
+    if (h->sub) fail(INVALID_ARG, "nystrom_schur_apply_noalloc: not available with the recursive level");
     // the operator workspaces of the handle (made at setup for k + p columns, or by an earlier apply) must
     // already hold ncols columns: growing them would allocate
     if (ncols > h->ws_cols)

@@ -977,9 +977,47 @@ void op_schur_tri(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int nco
   NS_LAUNCH_CHECK();
 }
 
+// Approximate A_Gamma^{-1} R of the recursive construction: the block LDL^T solve of A_Gamma split by the
+// level-2 labels (its interior s = the interface blocks, its interface J = the junction nodes), handled by the
+// level-below handle g whose "original" rows are this handle's interface rows, with M_J = g's preconditioner
+// in place of S_J^{-1}:
+//   u_s = A_s^{-1} r_s,  y_J = M_J (r_J - A_Js u_s),  z_s = A_s^{-1} (r_s - A_sJ y_J),  z_J = y_J.
+void gamma_solve_recursive(Handle& h, const double* R, int64_t ldr, double* Out, int64_t ldo, int ncols) {
+  hipStream_t st = h.stream;
+  Handle& g = *h.sub;
+  g.stream = st;  // the level below follows this handle's stream (which a graph capture swaps)
+  const int64_t nIp = g.L1.nrows_pad, nJ = g.nG;
+  if (ncols > h.rec_cols) {
+    h.recU.alloc(size_t(std::max<int64_t>(nIp, 1)) * ncols);
+    h.recT.alloc(size_t(std::max<int64_t>(nJ, 1)) * ncols);
+    h.recY.alloc(size_t(std::max<int64_t>(nJ, 1)) * ncols);
+    h.rec_cols = ncols;
+  }
+  double* u = h.recU.p;
+  double* t = h.recT.p;
+  double* y = h.recY.p;
+  gather_sub<double>(nIp, g.iperm, R, ldr, nullptr, static_cast<const double*>(nullptr), 0, u, ncols, ncols, st);
+  tile_solve<double>(g.L1, u, ncols, ncols, h.trsm_cols, st);                   // u_s = A_s^{-1} r_s
+  gather_sub<double>(nJ, g.gperm, R, ldr, &g.AGI, u, ncols, t, ncols, ncols, st);  // r_J - A_Js u_s
+  sub_apply(g, t, ncols, y, ncols, ncols);                                        // y_J = M_J (...)
+  gather_sub<double>(nIp, g.iperm, R, ldr, &g.AIG, y, ncols, u, ncols, ncols, st);  // r_s - A_sJ y_J
+  tile_solve<double>(g.L1, u, ncols, ncols, h.trsm_cols, st);                   // z_s
+  NS_TPR_DISPATCH(ncols, (k_scatter2<double, TPR><<<grid_rows<TPR>(nJ + nIp), 256, 0, st>>>(
+                             nJ, g.gperm, y, nIp, g.iperm, u, ncols, Out, ldo, ncols)));
+  NS_LAUNCH_CHECK();
+}
+
 template <class T>
 void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int ncols) {
   hipStream_t st = h.stream;
+  if (h.sub) {
+    if constexpr (sizeof(T) == 8) {
+      gamma_solve_recursive(h, R, ldr, Out, ldo, ncols);
+      return;
+    } else {
+      fail(INVALID_ARG, "the recursive A_Gamma solve runs in FP64 only");
+    }
+  }
   ensure_workspace(h, ncols);
   T* Bp = ws_ptr<T>(h.wsB64, h.wsB32);
   T* Bq = ws_ptr<T>(h.wsB64b, h.wsB32b);

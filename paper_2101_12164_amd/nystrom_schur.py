@@ -23,6 +23,7 @@ NS_APPLY_M2, NS_APPLY_ADEF2 = 0, 1
 NS_SCHUR_AUTO, NS_SCHUR_TRIANGULAR, NS_SCHUR_LOCAL = 0, 1, 2
 NS_VARIANT_M2, NS_VARIANT_M1, NS_VARIANT_M3 = 0, 1, 2
 NS_OUTER_SCHUR, NS_OUTER_FULL = 0, 1
+NS_LEVEL2_EXACT, NS_LEVEL2_NYSTROM = 0, 1
 
 STATUS_NAMES = {
     0: "NS_OK",
@@ -94,6 +95,11 @@ class NsOptions(ctypes.Structure):
         ("power_iters", c_int32),
         ("outer", c_int32),
         ("bcg_graph_iters", c_int32),
+        ("level2", c_int32),
+        ("level2_k", c_int32),
+        ("level2_p", c_int32),
+        ("level2_tol_inner", c_double),
+        ("level2_omega", c_void_p),
     ]
 
 
@@ -118,6 +124,8 @@ class NsSetupInfo(ctypes.Structure):
         ("t_nystrom", c_double),
         ("t_total", c_double),
         ("inner_bf16_schur", c_int32),
+        ("level2_it_inner", c_int32),
+        ("level2_k_eff", c_int32),
     ]
 
 
@@ -247,9 +255,11 @@ def _setup_info_dict(si: NsSetupInfo) -> dict:
 def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_inner=0.1, eig_thresh_rel=1e-10,
                         orth_drop_rel=0.0, max_inner_iters=500, prec_inner=NS_FP64, apply_mode=NS_APPLY_M2,
                         trsm_cols=0, schur_mode=0, proposal=None, accept_tol=0.2, pcg_graph_iters=0,
-                        variant=NS_VARIANT_M2, power_iters=0, outer=NS_OUTER_SCHUR, bcg_graph_iters=0):
+                        variant=NS_VARIANT_M2, power_iters=0, outer=NS_OUTER_SCHUR, bcg_graph_iters=0,
+                        level2=NS_LEVEL2_EXACT, level2_k=0, level2_p=0, level2_tol_inner=0.0, level2_omega=None):
     """Returns (handle, info dict).  row_ptr int64, col_idx int32, val float64, part int32, omega float64
-    (n_gamma x (k+p), row-major; n_interior x (k+p) for NS_VARIANT_M3), all CUDA tensors."""
+    (n_gamma x (k+p), row-major; n_interior x (k+p) for NS_VARIANT_M3), level2_omega float64 (n_junction x
+    (level2_k + level2_p), junction nodes in interface order), all CUDA tensors."""
     lib = load_library()
     n = row_ptr.numel() - 1
     nnz = val.numel()
@@ -257,6 +267,10 @@ def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_in
                    trsm_cols, schur_mode, accept_tol, pcg_graph_iters, variant, power_iters, outer, bcg_graph_iters)
     opt.omega = _dev(omega, torch.float64, "omega") if omega is not None else None
     opt.proposal = _dev(proposal, torch.float64, "proposal") if proposal is not None else None
+    opt.level2 = int(level2)
+    opt.level2_k, opt.level2_p = int(level2_k), int(level2_p)
+    opt.level2_tol_inner = float(level2_tol_inner)
+    opt.level2_omega = _dev(level2_omega, torch.float64, "level2_omega") if level2_omega is not None else None
     h = c_void_p()
     info = NsSetupInfo()
     st = lib.nystrom_schur_setup(n, nnz, _dev(row_ptr, torch.int64, "row_ptr"), _dev(col_idx, torch.int32, "col_idx"),
