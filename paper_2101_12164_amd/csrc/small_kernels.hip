@@ -926,6 +926,361 @@ __global__ void k_gevd_back(int k, const double* Linv, const double* W, const do
   for (int j = threadIdx.x; j < k; j += blockDim.x) lam[j] = E[k - 1 - j];
 }
 
+// ---------------------------------------------------------------- packed tiles (s up to 160 past the LDS limit)
+// When the dense workspaces above exceed the LDS, the Cholesky kernels keep only the lower 16 x 16 tiles of the
+// factor, packed in LDS: tile (i, j), i >= j, at index i (i + 1) / 2 + j, rows of PTL = 17 doubles (bank
+// spread).  The triangular solves then run one 16-column chunk per wave with the whole chunk in registers: the
+// FP64 MFMA accumulator layout (element v of lane l is row 4 v + l / 16, column l % 16) is also the B-operand
+// layout of the k-steps 4 v .. 4 v + 3 of the same tile, so each solved tile feeds the next tile rows'
+// products directly and only the factor is read from LDS.  No workgroup barrier inside a sweep.
+constexpr int NTP = 512;         // threads of the packed kernels: 2 waves per SIMD leave 256 VGPRs for a chunk
+constexpr int NWP = NTP / 64;
+constexpr int PTL = NB + 1;
+constexpr int PTS = NB * PTL;
+constexpr int PNT = 10;           // tile rows of the largest packed factor
+constexpr int PSMAX = PNT * NB;   // 160
+__host__ __device__ inline int ptile_count(int nt) { return nt * (nt + 1) / 2; }
+__host__ __device__ inline size_t ptiles_elems(int nt) {
+  return size_t(ptile_count(nt)) * PTS + size_t(nt) * NB * NBL;  // tiles + diagonal-tile inverses
+}
+__device__ __forceinline__ double* ptile(double* pt, int i, int j) { return pt + (i * (i + 1) / 2 + j) * PTS; }
+__device__ __forceinline__ const double* ptile(const double* pt, int i, int j) {
+  return pt + (i * (i + 1) / 2 + j) * PTS;
+}
+__device__ __forceinline__ int tri_row(int u) {  // row of the u-th entry of a row-wise packed lower triangle
+  int t = 0;
+  while ((t + 1) * (t + 2) / 2 <= u) ++t;
+  return t;
+}
+
+// Lower tiles of an n x n matrix, padded with the identity to nt tiles: val(i, j) for i, j < n.
+template <class F>
+__device__ __forceinline__ void ptiles_fill(double* pt, int n, int nt, F val) {
+  const int ne = ptile_count(nt) * NB * NB;
+  for (int e = threadIdx.x; e < ne; e += NTP) {
+    const int t = e >> 8, w = e & 255, a = w >> 4, c = w & 15;
+    const int ti = tri_row(t), tj = t - ti * (ti + 1) / 2;
+    const int i = ti * NB + a, j = tj * NB + c;
+    pt[t * PTS + a * PTL + c] = (i < n && j < n) ? val(i, j) : (i == j ? 1.0 : 0.0);
+  }
+}
+
+// Right-looking Cholesky on the packed tiles (lower parts of the diagonal tiles and the tiles below are the
+// factor on return; Dinv: inverses of the diagonal tiles).  Returns 0 or the 1-based first pivot <= 0.
+__device__ __forceinline__ int chol_ptiles(double* pt, int nt, double* Dinv, int* sinfo) {
+  const int wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) *sinfo = 0;
+  __syncthreads();
+  for (int j = 0; j < nt; ++j) {
+    double* Di = Dinv + j * (NB * NBL);
+    if (wave == 0) {
+      const int bad = diag_factor_wave(ptile(pt, j, j), PTL, 0, NB, Di);
+      if (bad && (threadIdx.x & 63) == 0 && *sinfo == 0) *sinfo = j * NB + bad;
+    }
+    __syncthreads();
+    for (int i = j + 1 + wave; i < nt; i += NWP) {  // L_ij = A_ij L_jj^{-T}
+      double* T = ptile(pt, i, j);
+      sv4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(acc, T, PTL, 1, Di, 1, NBL, NB);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[tile_row(v) * PTL + tile_col()] = acc[v];
+    }
+    __syncthreads();
+    const int mt = nt - j - 1;
+    for (int u = wave; u < ptile_count(mt); u += NWP) {  // A_iq -= L_ij L_qj^T, j < q <= i
+      const int ti = tri_row(u), tq = u - ti * (ti + 1) / 2;
+      const int i = j + 1 + ti, q = j + 1 + tq;
+      sv4d acc = {0.0, 0.0, 0.0, 0.0};
+      acc = mma16(acc, ptile(pt, i, j), PTL, 1, ptile(pt, q, j), 1, PTL, NB);
+      double* T = ptile(pt, i, q);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[tile_row(v) * PTL + tile_col()] -= acc[v];
+    }
+    __syncthreads();
+  }
+  const int info = *sinfo;
+  __syncthreads();
+  return info;
+}
+
+// Inverses of the diagonal tiles of an existing packed factor, one wave per tile.
+__device__ __forceinline__ void ptiles_diag_inverses(const double* pt, int nt, double* Dinv) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int bk = wave; bk < nt; bk += NWP) {
+    const double* T = ptile(pt, bk, bk);
+    double x[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      double acc = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+      for (int t = 0; t < i; ++t) acc -= T[i * PTL + t] * x[t];
+      x[i] = acc / T[i * PTL + i];
+    }
+    if (lane < NB) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) Dinv[bk * (NB * NBL) + i * NBL + lane] = x[i];
+    }
+  }
+  __syncthreads();
+}
+
+// One wave, one 16-column chunk in registers: X <- L^{-1} X (tiles before i0 are zero and stay zero).
+__device__ __forceinline__ void wave_fwd(const double* pt, const double* Dinv, int nt, int i0, sv4d (&X)[PNT]) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int i = 0; i < PNT; ++i) {
+    if (i < i0 || i >= nt) continue;
+    sv4d sum = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < PNT; ++k) {
+      if (k >= i0 && k < i) {
+        const double* T = ptile(pt, i, k) + li * PTL + lk;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sum = __builtin_amdgcn_mfma_f64_16x16x4f64(T[4 * v], X[k][v], sum, 0, 0, 0);
+      }
+    }
+    const sv4d t = X[i] - sum;
+    const double* Di = Dinv + i * (NB * NBL) + li * NBL + lk;
+    sv4d y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) y = __builtin_amdgcn_mfma_f64_16x16x4f64(Di[4 * v], t[v], y, 0, 0, 0);
+    X[i] = y;
+  }
+}
+
+// One wave, one chunk in registers: X <- L^{-T} X.
+__device__ __forceinline__ void wave_bwd(const double* pt, const double* Dinv, int nt, sv4d (&X)[PNT]) {
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int i = PNT - 1; i >= 0; --i) {
+    if (i >= nt) continue;
+    sv4d sum = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < PNT; ++k) {
+      if (k > i && k < nt) {
+        const double* T = ptile(pt, k, i) + lk * PTL + li;  // (L_ki)^T (li, 4 v + lk) = L_ki (4 v + lk, li)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          sum = __builtin_amdgcn_mfma_f64_16x16x4f64(T[4 * v * PTL], X[k][v], sum, 0, 0, 0);
+      }
+    }
+    const sv4d t = X[i] - sum;
+    const double* Di = Dinv + i * (NB * NBL) + lk * NBL + li;
+    sv4d y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) y = __builtin_amdgcn_mfma_f64_16x16x4f64(Di[4 * v * NBL], t[v], y, 0, 0, 0);
+    X[i] = y;
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+// Workgroup sum / max through one value per wave (red: NWP doubles); every thread gets the result.
+__device__ __forceinline__ double group_sum(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < NWP; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ double group_max(double v, double* red) {
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int w = 1; w < NWP; ++w) r = fmax(r, red[w]);
+  __syncthreads();
+  return r;
+}
+
+// k_small_chol_solve for factors of 17..160 rows whose dense workspace exceeds the LDS: same arguments and
+// results; the factor is packed in LDS and each wave solves 16-column chunks of the right-hand sides.
+__global__ __launch_bounds__(NTP) void k_small_chol_solve_p(int r0, const int* __restrict__ dims, double* D,
+                                                           int64_t sD, const double* B, int64_t ldb, int64_t sB,
+                                                           double* X, int64_t ldx, int64_t sX, int s, int s0,
+                                                           double alpha, int* flag, int factor) {
+  extern __shared__ double sm[];
+  __shared__ int sinfo;
+  const int b = blockIdx.x;
+  const int r = dims ? dims[b] : r0;
+  D += b * sD;
+  B += b * sB;
+  X += b * sX;
+  for (int e = threadIdx.x; e < (s0 - r) * s; e += NTP) X[(r + e / s) * ldx + e % s] = 0.0;
+  if (r == 0) return;
+  const int nt = (r + NB - 1) / NB;
+  double* pt = sm;
+  double* Dinv = sm + size_t(ptile_count(nt)) * PTS;
+  ptiles_fill(pt, r, nt, [&](int i, int j) { return D[i * r0 + j]; });
+  __syncthreads();
+  if (factor) {
+    if (chol_ptiles(pt, nt, Dinv, &sinfo) && threadIdx.x == 0) flag[0] = 1;
+    for (int e = threadIdx.x; e < r * r; e += NTP) {
+      const int i = e / r, j = e - i * r;
+      D[i * r0 + j] = j <= i ? ptile(pt, i / NB, j / NB)[(i % NB) * PTL + j % NB] : 0.0;
+    }
+  } else {
+    ptiles_diag_inverses(pt, nt, Dinv);
+  }
+  if (s == 0) return;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  for (int c0 = wave * NB; c0 < s; c0 += NWP * NB) {
+    const int col = c0 + li;
+    const bool cin = col < s;
+    sv4d Xr[PNT];
+#pragma unroll
+    for (int i = 0; i < PNT; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = NB * i + 4 * v + lk;
+        Xr[i][v] = (i < nt && row < r && cin) ? B[row * ldb + col] : 0.0;
+      }
+    wave_fwd(pt, Dinv, nt, 0, Xr);
+    wave_bwd(pt, Dinv, nt, Xr);
+#pragma unroll
+    for (int i = 0; i < PNT; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = NB * i + 4 * v + lk;
+        if (i < nt && row < r && cin) X[row * ldx + col] = alpha * Xr[i][v];
+      }
+  }
+}
+
+// k_small_cholqr for 17..160 columns whose dense workspace exceeds the LDS: same arguments and results.  The
+// factor is packed in LDS; each wave forms block columns of L^{-1} in registers (writing Rinv and the norms of
+// the certificate from them); R Racc is staged through the caller's global scratch gw (s x s per problem).
+__global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __restrict__ dims, const double* G,
+                                                       int64_t sG, const double* shift_coef, double* Rinv,
+                                                       double* Racc, int init, int* flag, double* gw, int64_t gws,
+                                                       double certify, int* ok) {
+  extern __shared__ double sm[];
+  __shared__ int sinfo;
+  __shared__ double red[NWP];
+  __shared__ double rowsum[PSMAX];
+  const int b = blockIdx.x;
+  const int n = dims ? dims[b] : s;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  G += b * sG;
+  Rinv += b * int64_t(s) * s;
+  Racc += b * int64_t(s) * s;
+  if (n == 0) {
+    for (int e = threadIdx.x; e < s * s; e += NTP) Rinv[e] = Racc[e] = 0.0;
+    if (ok && threadIdx.x == 0) ok[b] = 0;
+    return;
+  }
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < n; i += NTP) tr += G[i * s + i];
+  tr = group_sum(tr, red);
+  const double shift = (shift_coef ? shift_coef[b] : 0.0) * tr;
+  const int nt = (n + NB - 1) / NB, np = nt * NB;
+  double* pt = sm;
+  double* Dinv = sm + size_t(ptile_count(nt)) * PTS;
+  ptiles_fill(pt, n, nt, [&](int i, int j) { return 0.5 * (G[i * s + j] + G[j * s + i]) + (i == j ? shift : 0.0); });
+  for (int i = threadIdx.x; i < PSMAX; i += NTP) rowsum[i] = 0.0;
+  __syncthreads();
+  if (chol_ptiles(pt, nt, Dinv, &sinfo) && threadIdx.x == 0) flag[0] = 1;
+  for (int e = threadIdx.x; e < nt * NB * NB; e += NTP) {  // the factorisation leaves values above the diagonal
+    const int j = e >> 8, a = (e >> 4) & 15, c = e & 15;
+    if (c > a) ptile(pt, j, j)[a * PTL + c] = 0.0;
+  }
+  __syncthreads();
+  // Rinv = (L^{-1})^T in the leading n x n block, zero elsewhere; Frobenius, column and row sums of |L^{-1}|
+  double fro = 0.0, cmax = 0.0;
+  for (int j = wave; j < nt; j += NWP) {
+    sv4d Xr[PNT];
+#pragma unroll
+    for (int i = 0; i < PNT; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Xr[i][v] = (i == j && 4 * v + lk == li) ? 1.0 : 0.0;
+    wave_fwd(pt, Dinv, nt, j, Xr);
+    const int col = NB * j + li;
+    double csum = 0.0;
+#pragma unroll
+    for (int i = 0; i < PNT; ++i) {
+      if (i >= nt) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = NB * i + 4 * v + lk;
+        const double x = (row < n && col < n) ? Xr[i][v] : 0.0;
+        if (row < s && col < s) Rinv[col * s + row] = x;
+        fro += x * x;
+        csum += fabs(x);
+        if (row < n && x != 0.0) atomicAdd(&rowsum[row], fabs(x));
+      }
+    }
+    csum += __shfl_xor(csum, 16);
+    csum += __shfl_xor(csum, 32);
+    cmax = fmax(cmax, csum);
+  }
+  for (int e = threadIdx.x; e < s * s; e += NTP) {  // rows and columns past the tiles
+    const int i = e / s, j = e - i * s;
+    if (i >= np || j >= np) Rinv[e] = 0.0;
+  }
+  fro = group_sum(fro, red);
+  cmax = group_max(cmax, red);
+  if (ok) {
+    double rmax = 0.0, gmax = 0.0;
+    for (int i = threadIdx.x; i < n; i += NTP) {
+      double gs = 0.0;
+      for (int j = 0; j < n; ++j) gs += fabs(0.5 * (G[i * s + j] + G[j * s + i]));
+      rmax = fmax(rmax, rowsum[i]);
+      gmax = fmax(gmax, gs);
+    }
+    rmax = group_max(rmax, red);
+    gmax = group_max(gmax, red);
+    const double lmin = 1.0 / fmin(fro, rmax * cmax);
+    const double lmax = fmin(tr, gmax);
+    if (threadIdx.x == 0) ok[b] = (sinfo == 0 && lmin > certify * lmax) ? 1 : 0;
+  }
+  if (init) {
+    for (int e = threadIdx.x; e < s * s; e += NTP) {
+      const int i = e / s, j = e - i * s;
+      Racc[e] = (i < n && j < n && j >= i) ? ptile(pt, j / NB, i / NB)[(j % NB) * PTL + i % NB] : 0.0;
+    }
+    return;
+  }
+  // Racc <- R Racc, R = L^T upper: output tile (ti, tj), ti <= tj, sums over the tiles m = ti .. tj
+  double* Ra = gw + b * gws;
+  for (int e = threadIdx.x; e < np * np; e += NTP) {
+    const int i = e / np, j = e - i * np;
+    Ra[e] = (i < n && j < n) ? Racc[i * s + j] : 0.0;
+  }
+  __syncthreads();
+  for (int u = wave; u < nt * nt; u += NWP) {
+    const int ti = u / nt, tj = u - ti * nt;
+    sv4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int m = ti; m <= tj; ++m) {
+      const double* T = ptile(pt, m, ti) + lk * PTL + li;  // R(ti, m) (li, 4 v + lk) = L(m, ti) (4 v + lk, li)
+      const double* Q = Ra + (NB * m + lk) * np + NB * tj + li;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[4 * v * PTL], Q[4 * v * np], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = NB * ti + tile_row(v), j = NB * tj + tile_col();
+      if (i < s && j < s) Racc[i * s + j] = (i < n && j < n && j >= i) ? acc[v] : 0.0;
+    }
+  }
+  for (int e = threadIdx.x; e < s * s; e += NTP) {
+    const int i = e / s, j = e % s;
+    if (i >= np || j >= np) Racc[e] = 0.0;
+  }
+}
+
 // Where a launch's workspace lives: LDS when it fits, else the caller's global scratch (checked).
 int ws_mode(const SmallWs& ws, size_t elems, int r, int c) {
   if (elems * sizeof(double) <= LDS_LIMIT) return 1;
@@ -935,6 +1290,11 @@ int ws_mode(const SmallWs& ws, size_t elems, int r, int c) {
   return 0;
 }
 size_t dyn_lds(int mode, size_t elems) { return mode ? elems * sizeof(double) : 0; }
+// The packed-tile Cholesky kernels serve factors of up to 160 rows whose dense workspace does not fit in LDS.
+bool packed_chol(size_t dense_elems, int r) {
+  return dense_elems * sizeof(double) > LDS_LIMIT && r >= 1 && r <= PSMAX;
+}
+size_t packed_lds(int r) { return ptiles_elems((r + NB - 1) / NB) * sizeof(double); }
 
 }  // namespace
 
@@ -967,6 +1327,12 @@ void small_chol_solve(Batch bt, int r, double* D, int64_t sD, const double* B, i
   if (bt.nb <= 0 || (r <= 0 && s0 <= 0)) return;  // s == 0: factor only
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
   const size_t el = chol_ws(r, s);
+  if (packed_chol(el, r)) {
+    k_small_chol_solve_p<<<bt.nb, NTP, packed_lds(r), st>>>(r, bt.dims, D, sD, B, ldb, sB, X, ldx, sX, s, s0, alpha,
+                                                           flag, 1);
+    NS_LAUNCH_CHECK();
+    return;
+  }
   const int mode = ws_mode(ws, el, r, s);
   if (mode)
     k_small_chol_solve<1><<<bt.nb, NT, dyn_lds(mode, el), st>>>(r, bt.dims, D, sD, B, ldb, sB, X, ldx, sX, s, s0,
@@ -984,6 +1350,12 @@ void small_chol_apply(Batch bt, int r, const double* L, int64_t sL, const double
   if (bt.nb <= 0 || (r <= 0 && s0 <= 0) || s <= 0) return;
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
   const size_t el = chol_ws(r, s);
+  if (packed_chol(el, r)) {
+    k_small_chol_solve_p<<<bt.nb, NTP, packed_lds(r), st>>>(r, bt.dims, const_cast<double*>(L), sL, B, ldb, sB, X,
+                                                           ldx, sX, s, s0, alpha, nullptr, 0);
+    NS_LAUNCH_CHECK();
+    return;
+  }
   const int mode = ws_mode(ws, el, r, s);
   if (mode)
     k_small_chol_solve<1><<<bt.nb, NT, dyn_lds(mode, el), st>>>(r, bt.dims, const_cast<double*>(L), sL, B, ldb, sB,
@@ -1013,6 +1385,12 @@ void small_cholqr(Batch bt, int s, const double* G, int64_t sG, const double* sh
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
   const size_t el = chol_ws(s, s);
   const int mode = ws_mode(ws, el, s, s);
+  if (packed_chol(el, s)) {  // (its R Racc staging uses the global scratch that ws_mode checked)
+    k_small_cholqr_p<<<bt.nb, NTP, packed_lds(s), st>>>(s, bt.dims, G, sG, shift, Rinv, Racc, init, flag, ws.p,
+                                                       ws.stride, certify, ok);
+    NS_LAUNCH_CHECK();
+    return;
+  }
   if (mode)
     k_small_cholqr<1><<<bt.nb, NT, dyn_lds(mode, el), st>>>(s, bt.dims, G, sG, shift, Rinv, Racc, init, flag, ws.p,
                                                             ws.stride, certify, ok);
