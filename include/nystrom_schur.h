@@ -380,7 +380,10 @@ const char* nystrom_schur_mlp_last_error(ns_mlp m);
 /* Opt-in kernel timing for performance measurement (callers: benchmarks).
  * enable != 0 brackets every launch of the main kernel families with HIP
  * events on the launching stream (adds a few microseconds per launch);
- * calling it also resets the accumulated totals.  Process-wide. */
+ * calling it also resets the accumulated totals.  Process-wide.  While a
+ * timed family runs inside the block-CG or PCG iterations, those iterations
+ * use plain launches instead of replayed graphs (launches recorded into a
+ * graph cannot be timed one by one); results are the same. */
 void nystrom_schur_kernel_timing(int32_t enable);
 
 /* As nystrom_schur_kernel_timing, for the families whose bit is set in mask

@@ -92,6 +92,15 @@ KScope::~KScope() {
   if (hipEventRecord(b, st) == hipSuccess) t.pending.push_back(Rec{a, b, fam, bytes, flops});
 }
 
+bool kernel_timing_in_loops() {
+  KTimer& t = timer();
+  std::lock_guard<std::mutex> g(t.mu);
+  // families that run only in the setup's factorisation and formation, or in the learned layer
+  constexpr uint32_t setup_only = (1u << KF_CHOL_UPDATE) | (1u << KF_CHOL_PANEL) | (1u << KF_LS_FORM) |
+                                  (1u << KF_MLP_FWD) | (1u << KF_MLP_BWD);
+  return t.on && (t.mask & ~setup_only) != 0;
+}
+
 void kscope_add_work(int fam, double bytes, double flops) {
   KTimer& t = timer();
   std::lock_guard<std::mutex> g(t.mu);

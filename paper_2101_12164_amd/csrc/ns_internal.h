@@ -229,6 +229,9 @@ enum KFamily {
 };
 // Brackets one launch when timing is on; bytes / flops are the algorithmic
 // work of the launch (what the method must move / compute, no padding).
+// True while kernel timing covers a family that runs inside the block-CG or PCG iterations: those loops then
+// use plain launches (launches recorded into a graph cannot be timed one by one).
+bool kernel_timing_in_loops();
 struct KScope {
   int fam;
   hipStream_t st;

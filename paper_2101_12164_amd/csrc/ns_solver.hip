@@ -52,7 +52,7 @@ struct SmallMats {
   DBuf<int> ibuf;
   int* flag;   // [4] breakdown / factorisation flags
   int* ctr;    // [4] ctr[0]: problems no longer active in the inner solve
-  int *active, *rank, *ok, *skip, *svr, *dimA, *itp, *conv, *nys;  // per problem (nys: 2 per problem)
+  int *active, *rank, *ok, *skip, *svr, *dimA, *itp, *conv, *single, *dimB, *nys;  // per problem (nys: 2)
   int np = 0;
   void init(int nprob, int s, int k) {
     np = nprob;
@@ -74,12 +74,12 @@ struct SmallMats {
     coef = p;
     p += np;
     relres = p;
-    ibuf.alloc(8 + 10 * size_t(np));
+    ibuf.alloc(8 + 12 * size_t(np));
     NS_HIP(hipMemsetAsync(ibuf.p, 0, ibuf.n * sizeof(int), alloc_stream()));
     flag = ibuf.p;
     ctr = ibuf.p + 4;
     int* q = ibuf.p + 8;
-    for (int** d : {&active, &rank, &ok, &skip, &svr, &dimA, &itp, &conv}) {
+    for (int** d : {&active, &rank, &ok, &skip, &svr, &dimA, &itp, &conv, &single, &dimB}) {
       *d = q;
       q += np;
     }
@@ -176,6 +176,11 @@ __global__ void k_dims(int np, int s, const int* active, const int* rank, int* d
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < np) dims[p] = active[p] ? (rank ? rank[p] : s) : 0;
 }
+// dims of the second Cholesky-QR pass: 0 where the first pass was certified to suffice
+__global__ void k_dims2(int np, const int* rank, const int* single, int* dims) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < np) dims[p] = single[p] ? 0 : rank[p];
+}
 __global__ void k_svqb_mask(int np, const int* active, const int* ok, int* skip) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < np) skip[p] = !(active[p] && !ok[p]);
@@ -219,8 +224,13 @@ void orth(Handle& h, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int 
   gram<T, T>(sg, V, s, s, V, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
   k_dims<<<pb, 256, 0, st>>>(np, s, sm.active, nullptr, sm.dimA);
   NS_LAUNCH_CHECK();
+  // FP64 blocks: when the bounds certify that the column-equilibrated Gram matrix has a condition number below
+  // 1e6, the first pass already leaves an orthonormality error of order 1e6 times its rounding (1e-9 or less),
+  // and the second pass is passed over on the device (its block update becomes a copy, so the result lands
+  // where the graph expects it); FP32 blocks always take both passes
+  int* single = sizeof(T) == 8 ? sm.single : nullptr;
   small_cholqr(Batch{np, sm.dimA}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.sws, st, drop2,
-               sm.ok);
+               sm.ok, 1e-6, single);
   k_svqb_mask<<<pb, 256, 0, st>>>(np, sm.active, sm.ok, sm.skip);
   NS_LAUNCH_CHECK();
   small_svqb(np, s, sm.Gorth, ss, drop2, sm.Torth, ss, sm.svr, sm.skip, h.sws, st);
@@ -228,9 +238,17 @@ void orth(Handle& h, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int 
                                     sm.ctr, itd);
   NS_LAUNCH_CHECK();
   ts_update<T>(sg, s, P, s, 0.0, 1.0, V, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
-  gram<T, T>(sg, P, s, s, P, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
-  small_cholqr(Batch{np, sm.rank}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.sws, st);
-  ts_update<T>(sg, s, Q, s, 0.0, 1.0, P, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
+  Seg sg2 = sg;
+  const int* dims2 = sm.rank;
+  if (single) {
+    sg2.skip = single;
+    k_dims2<<<pb, 256, 0, st>>>(np, sm.rank, single, sm.dimB);
+    NS_LAUNCH_CHECK();
+    dims2 = sm.dimB;
+  }
+  gram<T, T>(sg2, P, s, s, P, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
+  small_cholqr(Batch{np, dims2}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.sws, st);
+  ts_update<T>(sg2, s, Q, s, 0.0, 1.0, P, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
   std::swap(P, Q);
 }
 
@@ -316,7 +334,7 @@ void block_pcg(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
     const int mb = h.bcg_graph == 0 ? tuned("bcg_graph_iters", h.bf16 ? "bf16" : (sizeof(T) == 8 ? "f64" : "f32"),
                                             h.nG, 2)
                                     : h.bcg_graph;
-    const int m = mb <= 0 ? 0 : 2 * ((mb + 1) / 2);
+    const int m = mb <= 0 || kernel_timing_in_loops() ? 0 : 2 * ((mb + 1) / 2);
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
     if (!fin && m > 0 && it + m <= h.max_inner) {
@@ -755,6 +773,7 @@ template <class Head, class Tail>
 void pcg_loop(Handle& h, int np, const PcgState& S, int maxit, int hc[2], Head head, Tail tail) {
   hipStream_t st = h.stream;
   int m = h.pcg_graph == 0 ? tuned("pcg_graph_iters", "f64", h.nG, np > 1 ? 4 : 1) : h.pcg_graph;
+  if (kernel_timing_in_loops()) m = 0;  // every launch timed
   head(st);
   read_back(h, hc, S.ndone, 2);
   if (hc[0] < np && hc[1] < maxit) tail(st);
@@ -1094,7 +1113,7 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
     if (h->s > h->h_goff[q + 1] - h->h_goff[q]) fail(INVALID_ARG, "k + p exceeds the interface size n_gamma");
   h->segG.build(h->h_goff, h->stream);
   h->segN.build(h->h_noff, h->stream);
-  h->sws = small_ws(h->small, h->nprob, h->s, h->s);
+  h->sws = small_ws(h->small, h->nprob, h->s, h->s, true);
   ev.rec(1);
   // The interface levels (patch factorisation, junction complement, explicit inverses) do not depend on the
   // interior factorisation and the local Schur formation: they run on a second stream, joined before the pivot

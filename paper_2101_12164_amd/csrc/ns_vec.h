@@ -21,6 +21,9 @@ struct Seg {
   const int* toff = nullptr;     // [n + 1] prefix of 64-row tiles per segment
   const int* rseg = nullptr;     // [rows] segment of each row
   int nchunk = 0, ntile = 0;     // totals
+  // [n] optional device flags: a segment flagged nonzero is passed over -- the Gram products leave its G_p as
+  // it is, and the block updates copy X into Out (the orthonormalisation pass the flag makes unnecessary)
+  const int* skip = nullptr;
 };
 // Owner of a segment description.
 struct SegBuf {
@@ -111,13 +114,19 @@ struct SmallWs {
   double* p = nullptr;
   int64_t stride = 0;
   int n = 0, c = 0;
+  // eigen-decompositions of n x n matrices past the LDS limit: per problem, a rotation log of jstride doubles
+  // and a status word (nullptr when not needed or not provided)
+  double* jlog = nullptr;
+  int64_t jstride = 0;
+  int* jstat = nullptr;
 };
 // doubles per problem for dimensions <= n and column counts <= c (0 when everything fits in LDS)
 size_t small_scratch_elems(int n, int c);
 // doubles per problem of the Cholesky solve / apply kernels for an r x r factor and c columns (0: in LDS)
 size_t small_chol_scratch_elems(int r, int c);
-// a scratch for nb problems (buf is allocated only when needed)
-SmallWs small_ws(DBuf<double>& buf, int nb, int n, int c);
+// a scratch for nb problems (buf is allocated only when needed); evd: also the rotation logs of the
+// eigen-decompositions (the setup's Nystrom core and block-CG orthonormalisation)
+SmallWs small_ws(DBuf<double>& buf, int nb, int n, int c, bool evd = false);
 
 // L (in place of D, lower) = chol(D) for an r x r SPD D; X = alpha * D^{-1} B (B: r x s, ld ldb; X ld ldx).
 // Rows r..s0-1 of X are set to zero (s0 = rows of the stacked X, pass r when unused).  s = 0: factor only.
@@ -136,10 +145,13 @@ void small_svqb(int nb, int s, const double* G, int64_t sG, double drop2, double
                 const int* skip, const SmallWs& ws, hipStream_t st);
 // R = chol(G + shift_b * trace(G) * I)^T (upper) on the leading dim_b block (zero elsewhere);
 // Rinv = R^{-1}; Racc <- R * Racc (or R when init).  shift_b = shift[b] when shift != nullptr.
-// With ok != nullptr: ok[b] = 1 when the Cholesky succeeded and 1/||R^{-1}||_F^2 > certify * trace(G),
-// which proves lambda_min(G) / lambda_max(G) > certify (no direction falls below that ratio).
+// With ok != nullptr: ok[b] = 1 when the Cholesky succeeded and a guaranteed lower bound of lambda_min(G)
+// exceeds certify times an upper bound of lambda_max(G) (no direction falls below that ratio); single[b] = 1
+// when the same bounds for the column-equilibrated D G D (unit diagonal) certify a condition number below
+// 1 / single_thr, small enough for one Cholesky-QR pass (its rounding depends on that scaled condition).
 void small_cholqr(Batch bt, int s, const double* G, int64_t sG, const double* shift, double* Rinv, double* Racc,
-                  int init, int* flag, const SmallWs& ws, hipStream_t st, double certify = 0.0, int* ok = nullptr);
+                  int init, int* flag, const SmallWs& ws, hipStream_t st, double certify = 0.0, int* ok = nullptr,
+                  double single_thr = 0.0, int* single = nullptr);
 // Nystrom core: EVD of sym(C), keep eigenvalues >= eps_rel * max; T = (R V1) D1^{-1} (R V1)^T;
 // EVD of T descending; Wk = first k' eigenvectors (s x k, ld k), Ek = eigenvalues; out[2b..] = {r, k'}.
 // (A Cholesky of C that certifies every eigenvalue above the threshold replaces the first EVD.)

@@ -566,7 +566,7 @@ template <int kLds>
 __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restrict__ dims, const double* G, int64_t sG,
                                                      const double* shift_coef, double* Rinv, double* Racc, int init,
                                                      int* flag, double* gw, int64_t gws, double certify,
-                                                     int* ok) {
+                                                     int* ok, double single_thr, int* single) {
   extern __shared__ double sm[];
   __shared__ int sinfo;
   __shared__ double red[NT];
@@ -579,6 +579,7 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
   if (n == 0) {
     for (int e = threadIdx.x; e < s * s; e += NT) Rinv[e] = Racc[e] = 0.0;
     if (ok && threadIdx.x == 0) ok[b] = 0;
+    if (single && threadIdx.x == 0) single[b] = 0;
     return;
   }
   double tr = 0.0;
@@ -602,13 +603,17 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
     if (j > i) A[i * ld + j] = 0.0;
   }
   // Rinv = (L^{-1})^T (upper) in the leading block, zero elsewhere; R = L^T
-  double fro = 0.0;
+  // fsc: ||L^{-1} D^{-1}||_F^2 with D^{-2} = diag(G + shift I), the same bound for the column-equilibrated
+  // Gram matrix D (G + shift I) D, whose trace is n
+  double fro = 0.0, fsc = 0.0;
   for (int e = threadIdx.x; e < s * s; e += NT) {
     const int i = e / s, j = e % s;
     const double x = (i < n && j < n) ? X[j * ld + i] : 0.0;
     Rinv[e] = x;
     fro += x * x;
+    if (single && i < n) fsc += x * x * (G[i * s + i] + shift);
   }
+  if (single) fsc = block_sum(fsc, red);
   if (ok) {
     // certify that no singular value ratio of the block is at or below the drop tolerance, from guaranteed
     // bounds: lambda_min(G) = 1 / ||L^{-1}||_2^2 >= 1 / min(||L^{-1}||_F^2, ||L^{-1}||_1 ||L^{-1}||_inf) (Hoelder)
@@ -652,7 +657,10 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
     __syncthreads();
     const double lmin = 1.0 / fmin(f, rmax * cmax);
     const double lmax = fmin(tr, gmax);
-    if (threadIdx.x == 0) ok[b] = (sinfo == 0 && lmin > certify * lmax) ? 1 : 0;
+    if (threadIdx.x == 0) {
+      ok[b] = (sinfo == 0 && lmin > certify * lmax) ? 1 : 0;
+      if (single) single[b] = (sinfo == 0 && fsc > 0.0 && 1.0 / fsc > single_thr * n) ? 1 : 0;
+    }
   }
   __syncthreads();
   if (init) {
@@ -693,7 +701,8 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
 // T = R C^{-1} R^T = H^T H with H = L^{-1} R^T: the EVD of C is skipped.
 template <int kLds>
 __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double* C, const double* R, double eps_rel,
-                                                      double* Wk, double* Ek, int* out, double* gw, int64_t gws) {
+                                                      double* Wk, double* Ek, int* out, double* gw, int64_t gws,
+                                                      const int* run_if) {
   extern __shared__ double sm[];
   __shared__ double red[NT];
   __shared__ double sd[3 * SMAX];
@@ -702,6 +711,7 @@ __global__ __launch_bounds__(NT) void k_small_nystrom(int s, int k, const double
   __shared__ int ikeep[SMAX];
   __shared__ int nkeep, sinfo;
   const int b = blockIdx.x;
+  if (run_if && run_if[b] != 1) return;  // (the packed kernels served this problem)
   const int wave = threadIdx.x >> 6;
   C += b * int64_t(s) * s;
   R += b * int64_t(s) * s;
@@ -953,15 +963,30 @@ __device__ __forceinline__ int tri_row(int u) {  // row of the u-th entry of a r
   return t;
 }
 
-// Lower tiles of an n x n matrix, padded with the identity to nt tiles: val(i, j) for i, j < n.
+// Lower tiles of an n x n matrix, padded with the identity to nt tiles: val(i, j) for i, j < n.  Eight values
+// per thread are loaded (from clamped, in-bounds positions) before the first is stored.
 template <class F>
 __device__ __forceinline__ void ptiles_fill(double* pt, int n, int nt, F val) {
   const int ne = ptile_count(nt) * NB * NB;
-  for (int e = threadIdx.x; e < ne; e += NTP) {
-    const int t = e >> 8, w = e & 255, a = w >> 4, c = w & 15;
-    const int ti = tri_row(t), tj = t - ti * (ti + 1) / 2;
-    const int i = ti * NB + a, j = tj * NB + c;
-    pt[t * PTS + a * PTL + c] = (i < n && j < n) ? val(i, j) : (i == j ? 1.0 : 0.0);
+  for (int e0 = threadIdx.x; e0 < ne; e0 += 8 * NTP) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = min(e0 + u * NTP, ne - 1);
+      const int t = e >> 8, a = (e >> 4) & 15, c = e & 15;
+      const int ti = tri_row(t), tj = t - ti * (ti + 1) / 2;
+      v[u] = val(min(ti * NB + a, n - 1), min(tj * NB + c, n - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NTP;
+      if (e < ne) {
+        const int t = e >> 8, a = (e >> 4) & 15, c = e & 15;
+        const int ti = tri_row(t), tj = t - ti * (ti + 1) / 2;
+        const int i = ti * NB + a, j = tj * NB + c;
+        pt[t * PTS + a * PTL + c] = (i < n && j < n) ? v[u] : (i == j ? 1.0 : 0.0);
+      }
+    }
   }
 }
 
@@ -1045,6 +1070,7 @@ __device__ __forceinline__ void wave_fwd(const double* pt, const double* Dinv, i
 #pragma unroll
     for (int v = 0; v < 4; ++v) y = __builtin_amdgcn_mfma_f64_16x16x4f64(Di[4 * v], t[v], y, 0, 0, 0);
     X[i] = y;
+    __builtin_amdgcn_sched_barrier(0);  // one tile row's operand loads at a time (register pressure)
   }
 }
 
@@ -1070,6 +1096,7 @@ __device__ __forceinline__ void wave_bwd(const double* pt, const double* Dinv, i
 #pragma unroll
     for (int v = 0; v < 4; ++v) y = __builtin_amdgcn_mfma_f64_16x16x4f64(Di[4 * v * NBL], t[v], y, 0, 0, 0);
     X[i] = y;
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -1139,13 +1166,25 @@ __global__ __launch_bounds__(NTP) void k_small_chol_solve_p(int r0, const int* _
   for (int c0 = wave * NB; c0 < s; c0 += NWP * NB) {
     const int col = c0 + li;
     const bool cin = col < s;
+    const int cc = min(col, s - 1), ldb32 = int(ldb);
     sv4d Xr[PNT];
+    // loads from clamped, in-bounds rows (32-bit offsets from the problem's base), half the tiles at a time;
+    // out-of-range values zeroed afterwards
+#pragma unroll
+    for (int i = 0; i < PNT / 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Xr[i][v] = B[min(NB * i + 4 * v + lk, r - 1) * ldb32 + cc];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = PNT / 2; i < PNT; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Xr[i][v] = B[min(NB * i + 4 * v + lk, r - 1) * ldb32 + cc];
 #pragma unroll
     for (int i = 0; i < PNT; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = NB * i + 4 * v + lk;
-        Xr[i][v] = (i < nt && row < r && cin) ? B[row * ldb + col] : 0.0;
+        if (!(i < nt && row < r && cin)) Xr[i][v] = 0.0;
       }
     wave_fwd(pt, Dinv, nt, 0, Xr);
     wave_bwd(pt, Dinv, nt, Xr);
@@ -1165,7 +1204,7 @@ __global__ __launch_bounds__(NTP) void k_small_chol_solve_p(int r0, const int* _
 __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __restrict__ dims, const double* G,
                                                        int64_t sG, const double* shift_coef, double* Rinv,
                                                        double* Racc, int init, int* flag, double* gw, int64_t gws,
-                                                       double certify, int* ok) {
+                                                       double certify, int* ok, double single_thr, int* single) {
   extern __shared__ double sm[];
   __shared__ int sinfo;
   __shared__ double red[NWP];
@@ -1179,6 +1218,7 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
   if (n == 0) {
     for (int e = threadIdx.x; e < s * s; e += NTP) Rinv[e] = Racc[e] = 0.0;
     if (ok && threadIdx.x == 0) ok[b] = 0;
+    if (single && threadIdx.x == 0) single[b] = 0;
     return;
   }
   double tr = 0.0;
@@ -1191,6 +1231,27 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
   ptiles_fill(pt, n, nt, [&](int i, int j) { return 0.5 * (G[i * s + j] + G[j * s + i]) + (i == j ? shift : 0.0); });
   for (int i = threadIdx.x; i < PSMAX; i += NTP) rowsum[i] = 0.0;
   __syncthreads();
+  // ||sym(G)||_inf from the tiles (unshifted), before the factorisation overwrites them
+  double gmax = 0.0;
+  if (ok) {
+    for (int i = threadIdx.x; i < n; i += NTP) {
+      const int ti = i / NB, a = i % NB;
+      double gs = 0.0;
+      for (int tj = 0; tj < nt; ++tj) {
+        double x[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c)  // row i of tile (ti, tj), or column i of tile (tj, ti) above the diagonal
+          x[c] = tj <= ti ? ptile(pt, ti, tj)[a * PTL + c] : ptile(pt, tj, ti)[c * PTL + a];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          const int j = tj * NB + c;
+          if (j < n) gs += fabs(j == i ? x[c] - shift : x[c]);
+        }
+      }
+      gmax = fmax(gmax, gs);
+    }
+  }
+  __syncthreads();
   if (chol_ptiles(pt, nt, Dinv, &sinfo) && threadIdx.x == 0) flag[0] = 1;
   for (int e = threadIdx.x; e < nt * NB * NB; e += NTP) {  // the factorisation leaves values above the diagonal
     const int j = e >> 8, a = (e >> 4) & 15, c = e & 15;
@@ -1198,7 +1259,7 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
   }
   __syncthreads();
   // Rinv = (L^{-1})^T in the leading n x n block, zero elsewhere; Frobenius, column and row sums of |L^{-1}|
-  double fro = 0.0, cmax = 0.0;
+  double fro = 0.0, fsc = 0.0, cmax = 0.0;  // fsc: as fro for the column-equilibrated Gram matrix
   for (int j = wave; j < nt; j += NWP) {
     sv4d Xr[PNT];
 #pragma unroll
@@ -1207,7 +1268,8 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
       for (int v = 0; v < 4; ++v) Xr[i][v] = (i == j && 4 * v + lk == li) ? 1.0 : 0.0;
     wave_fwd(pt, Dinv, nt, j, Xr);
     const int col = NB * j + li;
-    double csum = 0.0;
+    const double gcc = G[min(col, n - 1) * s + min(col, n - 1)] + shift;
+    double csum = 0.0, cf = 0.0;
 #pragma unroll
     for (int i = 0; i < PNT; ++i) {
       if (i >= nt) continue;
@@ -1216,11 +1278,13 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
         const int row = NB * i + 4 * v + lk;
         const double x = (row < n && col < n) ? Xr[i][v] : 0.0;
         if (row < s && col < s) Rinv[col * s + row] = x;
-        fro += x * x;
+        cf += x * x;
         csum += fabs(x);
         if (row < n && x != 0.0) atomicAdd(&rowsum[row], fabs(x));
       }
     }
+    fro += cf;
+    fsc += cf * gcc;
     csum += __shfl_xor(csum, 16);
     csum += __shfl_xor(csum, 32);
     cmax = fmax(cmax, csum);
@@ -1230,20 +1294,19 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
     if (i >= np || j >= np) Rinv[e] = 0.0;
   }
   fro = group_sum(fro, red);
+  fsc = group_sum(fsc, red);
   cmax = group_max(cmax, red);
   if (ok) {
-    double rmax = 0.0, gmax = 0.0;
-    for (int i = threadIdx.x; i < n; i += NTP) {
-      double gs = 0.0;
-      for (int j = 0; j < n; ++j) gs += fabs(0.5 * (G[i * s + j] + G[j * s + i]));
-      rmax = fmax(rmax, rowsum[i]);
-      gmax = fmax(gmax, gs);
-    }
+    double rmax = 0.0;
+    for (int i = threadIdx.x; i < n; i += NTP) rmax = fmax(rmax, rowsum[i]);
     rmax = group_max(rmax, red);
     gmax = group_max(gmax, red);
     const double lmin = 1.0 / fmin(fro, rmax * cmax);
     const double lmax = fmin(tr, gmax);
-    if (threadIdx.x == 0) ok[b] = (sinfo == 0 && lmin > certify * lmax) ? 1 : 0;
+    if (threadIdx.x == 0) {
+      ok[b] = (sinfo == 0 && lmin > certify * lmax) ? 1 : 0;
+      if (single) single[b] = (sinfo == 0 && fsc > 0.0 && 1.0 / fsc > single_thr * n) ? 1 : 0;
+    }
   }
   if (init) {
     for (int e = threadIdx.x; e < s * s; e += NTP) {
@@ -1254,20 +1317,41 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
   }
   // Racc <- R Racc, R = L^T upper: output tile (ti, tj), ti <= tj, sums over the tiles m = ti .. tj
   double* Ra = gw + b * gws;
-  for (int e = threadIdx.x; e < np * np; e += NTP) {
-    const int i = e / np, j = e - i * np;
-    Ra[e] = (i < n && j < n) ? Racc[i * s + j] : 0.0;
+  for (int e0 = threadIdx.x; e0 < np * np; e0 += 8 * NTP) {
+    double v8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = min(e0 + u * NTP, np * np - 1);
+      const int i = e / np, j = e - i * np;
+      v8[u] = Racc[min(i, n - 1) * s + min(j, n - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * NTP;
+      if (e < np * np) {
+        const int i = e / np, j = e - i * np;
+        Ra[e] = (i < n && j < n) ? v8[u] : 0.0;
+      }
+    }
   }
   __syncthreads();
   for (int u = wave; u < nt * nt; u += NWP) {
     const int ti = u / nt, tj = u - ti * nt;
-    sv4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int m = ti; m <= tj; ++m) {
-      const double* T = ptile(pt, m, ti) + lk * PTL + li;  // R(ti, m) (li, 4 v + lk) = L(m, ti) (4 v + lk, li)
-      const double* Q = Ra + (NB * m + lk) * np + NB * tj + li;
+    double q[PNT][4];  // the B operands of every k-step, loaded together
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[4 * v * PTL], Q[4 * v * np], acc, 0, 0, 0);
+    for (int m = 0; m < PNT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int mm = min(max(m, ti), tj);
+        q[m][v] = Ra[int64_t(NB * mm + 4 * v + lk) * np + NB * tj + li];
+      }
+    sv4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < PNT; ++m) {
+      if (m < ti || m > tj) continue;
+      const double* T = ptile(pt, m, ti) + lk * PTL + li;  // R(ti, m) (li, 4 v + lk) = L(m, ti) (4 v + lk, li)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[4 * v * PTL], q[m][v], acc, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1278,6 +1362,320 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
   for (int e = threadIdx.x; e < s * s; e += NTP) {
     const int i = e / s, j = e % s;
     if (i >= np || j >= np) Racc[e] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- packed Jacobi (n up to 160 past the LDS limit)
+// The eigen-decompositions keep the lower triangle of the symmetric matrix packed by rows in LDS (element
+// (i, j), i >= j, at i (i + 1) / 2 + j: 103 KB at n = 160) and write each round's rotations (c, s) to a log in
+// global memory instead of applying them to V; k_jacobi_rows then forms rows of V = J_1 J_2 ... (the
+// identity's rows with every logged round applied in order), one wave per row, in parallel over the rows.
+// Rounds follow the same round-robin ordering and rotation formulas as jacobi() above.
+constexpr int JSWEEPS_P = 40;  // sweep limit of the packed Jacobi (bounds the log)
+__host__ __device__ inline int64_t jlog_stride(int n) {  // header (rounds, kept), order, scales, rotations
+  const int m = n + (n & 1);
+  return int64_t(2 + 2 * n + 1) / 2 * 2 + int64_t(JSWEEPS_P) * (m - 1) * m;
+}
+__device__ __forceinline__ int pidx(int i, int j) {
+  return i >= j ? ((i * (i + 1)) >> 1) + j : ((j * (j + 1)) >> 1) + i;
+}
+__device__ __forceinline__ int tri_row_fast(int e) {
+  int i = int((sqrt(8.0 * double(e) + 1.0) - 1.0) * 0.5);
+  while (((i + 1) * (i + 2)) / 2 <= e) ++i;
+  while ((i * (i + 1)) / 2 > e) --i;
+  return i;
+}
+__device__ __forceinline__ int rr_pos(int x, int round, int m) { return x == 0 ? 0 : 1 + (x - 1 + round) % (m - 1); }
+
+// Cyclic Jacobi on the packed lower triangle A (n x n); rotations logged at rot[round * m + 2 t + {0, 1}].
+// Returns the number of rounds run (stops at the rounding floor, after JSWEEPS_P sweeps at most).
+__device__ int jacobi_packed(double* A, int n, double* cs, int* pr, double* red, double* rot) {
+  const int tid = threadIdx.x;
+  if (n < 2) return 0;
+  const int m = n + (n & 1), half = m / 2, nblk = half * (half + 1) / 2, ne = n * (n + 1) / 2;
+  int rounds = 0;
+  for (int sweep = 0; sweep < JSWEEPS_P; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < ne; e += NT) {
+      const int i = tri_row_fast(e), j = e - ((i * (i + 1)) >> 1);
+      const double v = A[e] * A[e];
+      tot += i == j ? v : 2.0 * v;
+      if (i != j) off += 2.0 * v;
+    }
+    off = block_sum(off, red);
+    tot = block_sum(tot, red);
+    if (!(off > 2e-31 * double(n) * double(n) * tot)) break;
+    for (int round = 0; round < m - 1; ++round) {
+      if (tid < half) {
+        int p = rr_pos(tid, round, m), q = rr_pos(m - 1 - tid, round, m);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[pidx(q, p)];
+          const double app = A[pidx(p, p)], aqq = A[pidx(q, q)];
+          if (apq * apq > 1e-36 * fabs(app * aqq) && fabs(apq) > 1e-300) {
+            const double tau = (aqq - app) * rcp_nr(2.0 * apq);
+            const double at = fabs(tau);
+            double tf;
+            if (at > 1e15) {
+              tf = 0.5 * rcp_nr(at);
+            } else {
+              const double u = 1.0 + at * at;
+              tf = rcp_nr(at + u * rsqrt_nr(u));
+            }
+            const double t = tau >= 0.0 ? tf : -tf;
+            c = rsqrt_nr(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        pr[2 * tid] = p;
+        pr[2 * tid + 1] = q;
+        cs[2 * tid] = c;
+        cs[2 * tid + 1] = s;
+        rot[int64_t(rounds + round) * m + 2 * tid] = c;
+        rot[int64_t(rounds + round) * m + 2 * tid + 1] = s;
+      }
+      __syncthreads();
+      // A <- J^T A J on the stored 2 x 2 blocks (pair P rows, pair Q columns, P >= Q): as jacobi(), the
+      // columns rotated first, then the rows
+      for (int t = tid; t < nblk; t += NT) {
+        const int P = tri_row_fast(t), Q = t - ((P * (P + 1)) >> 1);
+        const int p = pr[2 * P], q = pr[2 * P + 1];
+        const bool hq = q < n;
+        const double c1 = cs[2 * P], s1 = cs[2 * P + 1];
+        if (P == Q) {
+          const double a = A[pidx(p, p)], b = hq ? A[pidx(q, p)] : 0.0, d = hq ? A[pidx(q, q)] : 0.0;
+          const double a1 = c1 * a - s1 * b, b1 = s1 * a + c1 * b;
+          const double c3 = c1 * b - s1 * d, d1 = s1 * b + c1 * d;
+          A[pidx(p, p)] = c1 * a1 - s1 * c3;
+          if (hq) {
+            A[pidx(q, p)] = 0.5 * ((c1 * b1 - s1 * d1) + (s1 * a1 + c1 * c3));
+            A[pidx(q, q)] = s1 * b1 + c1 * d1;
+          }
+        } else {
+          const int p2 = pr[2 * Q], q2 = pr[2 * Q + 1];
+          const bool hq2 = q2 < n;
+          const double c2 = cs[2 * Q], s2 = cs[2 * Q + 1];
+          const double a = A[pidx(p, p2)], b = hq2 ? A[pidx(p, q2)] : 0.0;
+          const double c = hq ? A[pidx(q, p2)] : 0.0, d = (hq && hq2) ? A[pidx(q, q2)] : 0.0;
+          const double a1 = c2 * a - s2 * b, b1 = s2 * a + c2 * b;
+          const double c3 = c2 * c - s2 * d, d1 = s2 * c + c2 * d;
+          A[pidx(p, p2)] = c1 * a1 - s1 * c3;
+          if (hq2) A[pidx(p, q2)] = c1 * b1 - s1 * d1;
+          if (hq) {
+            A[pidx(q, p2)] = s1 * a1 + c1 * c3;
+            if (hq2) A[pidx(q, q2)] = s1 * b1 + c1 * d1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    rounds += m - 1;
+  }
+  return rounds;
+}
+
+// Eigen-decomposition of sym(M) (n x n, problem b at M + b sM) on the packed triangle.  mode 0 (Nystrom core):
+// eigenvalues descending, kept = min(k, n), E[c] = lambda_c for c < kept (zero up to k), out[2 b] = n,
+// out[2 b + 1] = kept.  mode 1 (orthonormalisation): kept = leading eigenvalues > 0 and > drop2 lambda_max,
+// scale_c = 1 / sqrt(lambda_c), out[b] = kept.  The log receives the rounds, kept, order and scales for
+// k_jacobi_rows.  Problems with skip[b] == 1 are left alone.
+__global__ __launch_bounds__(NT) void k_jacobi_p(int n, const double* M, int64_t sM, int mode, int k, double drop2,
+                                                 double* E, int* out, const int* skip, double* jlog, int64_t jls) {
+  extern __shared__ double sm[];
+  __shared__ double red[NT];
+  __shared__ double cs[PSMAX], d[PSMAX];
+  __shared__ int pr[PSMAX], ord[PSMAX];
+  const int b = blockIdx.x;
+  if (skip && skip[b] == 1) return;
+  M += b * sM;
+  double* jl = jlog + b * jls;
+  const int ne = n * (n + 1) / 2;
+  for (int e = threadIdx.x; e < ne; e += NT) {
+    const int i = tri_row_fast(e), j = e - ((i * (i + 1)) >> 1);
+    sm[e] = i == j ? M[i * n + i] : 0.5 * (M[i * n + j] + M[j * n + i]);
+  }
+  __syncthreads();
+  const int hdr = int(jlog_stride(n) - int64_t(JSWEEPS_P) * ((n + (n & 1)) - 1) * (n + (n & 1)));
+  const int rounds = jacobi_packed(sm, n, cs, pr, red, jl + hdr);
+  for (int i = threadIdx.x; i < n; i += NT) d[i] = sm[pidx(i, i)];
+  __syncthreads();
+  sort_desc(d, n, ord);
+  int kept;
+  if (mode == 0) {
+    kept = k < n ? k : n;
+  } else {
+    const double lmax = d[ord[0]];
+    kept = 0;
+    while (kept < n && d[ord[kept]] > 0.0 && d[ord[kept]] > drop2 * lmax) ++kept;
+  }
+  for (int c = threadIdx.x; c < n; c += NT) {
+    jl[2 + c] = double(ord[c]);
+    jl[2 + n + c] = (mode == 1 && c < kept) ? 1.0 / sqrt(d[ord[c]]) : 1.0;
+  }
+  if (threadIdx.x == 0) {
+    jl[0] = double(rounds);
+    jl[1] = double(kept);
+    if (mode == 0) {
+      out[2 * b] = n;
+      out[2 * b + 1] = kept;
+    } else {
+      out[b] = kept;
+    }
+  }
+  if (mode == 0)
+    for (int c = threadIdx.x; c < k; c += NT) E[int64_t(b) * k + c] = c < kept ? d[ord[c]] : 0.0;
+}
+
+// Rows of the eigenvector matrix from the rotation log: row i of V is e_i^T J_1 J_2 ... (V <- V J per round, as
+// jacobi()); out[i][c] = V[i][order[c]] scale_c for c < kept, zero for kept <= c < ncol.  Four rows (waves) per
+// workgroup, each row in LDS; the log passes through LDS in chunks of JCH rounds shared by the four waves.
+constexpr int JCH = 32;
+__global__ __launch_bounds__(256) void k_jacobi_rows(int n, const double* jlog, int64_t jls, double* out, int64_t ldo,
+                                                     int64_t so, int ncol, const int* skip) {
+  __shared__ double rowv[4][PSMAX];
+  __shared__ double chunk[JCH * PSMAX];
+  const int b = blockIdx.y;
+  if (skip && skip[b] == 1) return;
+  const double* jl = jlog + b * jls;
+  const int m = n + (n & 1), half = m / 2;
+  const int hdr = int(jlog_stride(n) - int64_t(JSWEEPS_P) * (m - 1) * m);
+  const double* rot = jl + hdr;
+  const int rounds = int(jl[0]), kept = int(jl[1]);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wave;
+  const bool valid = i < n;
+  double* rv = rowv[wave];
+  for (int j = lane; j < n; j += 64) rv[j] = j == i ? 1.0 : 0.0;
+  for (int r0 = 0; r0 < rounds; r0 += JCH) {
+    const int nr = rounds - r0 < JCH ? rounds - r0 : JCH;
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * m; e += 256) chunk[e] = rot[int64_t(r0) * m + e];
+    __syncthreads();
+    if (valid) {
+      for (int rr = 0; rr < nr; ++rr) {
+        const int round = (r0 + rr) % (m - 1);
+        for (int t = lane; t < half; t += 64) {
+          int p = rr_pos(t, round, m), q = rr_pos(m - 1 - t, round, m);
+          if (p > q) {
+            const int x = p;
+            p = q;
+            q = x;
+          }
+          if (q < n) {
+            const double c = chunk[rr * m + 2 * t], s = chunk[rr * m + 2 * t + 1];
+            const double vp = rv[p], vq = rv[q];
+            rv[p] = c * vp - s * vq;
+            rv[q] = s * vp + c * vq;
+          }
+        }
+        // the next round's pairs read what other lanes of this wave wrote
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
+  }
+  if (!valid) return;
+  for (int c = lane; c < ncol; c += 64)
+    out[b * so + int64_t(i) * ldo + c] = c < kept ? rv[int(jl[2 + c])] * jl[2 + n + c] : 0.0;
+}
+
+// Nystrom core, certified path, for 17..160 columns past the LDS limit: C = L L^T (packed tiles), the
+// certificate 1 / ||L^{-1}||_F^2 >= eps_rel trace(C), H = L^{-1} R^T (register sweeps; to gw), T = H^T H (to gw
+// after H).  stat[b] = 0: T is ready for the packed Jacobi; 1: not certified (the dense kernel then runs).
+__global__ __launch_bounds__(NTP) void k_nys_prep_p(int s, const double* C, const double* R, double eps_rel,
+                                                    double* gw, int64_t gws, int* stat) {
+  extern __shared__ double sm[];
+  __shared__ int sinfo;
+  __shared__ double red[NWP];
+  const int b = blockIdx.x;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  C += b * int64_t(s) * s;
+  R += b * int64_t(s) * s;
+  const int nt = (s + NB - 1) / NB, np = nt * NB;
+  double* H = gw + b * gws;
+  double* T = H + int64_t(np) * np;
+  double* pt = sm;
+  double* Dinv = sm + size_t(ptile_count(nt)) * PTS;
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < s; i += NTP) tr += C[i * s + i];
+  tr = group_sum(tr, red);
+  ptiles_fill(pt, s, nt, [&](int i, int j) { return 0.5 * (C[i * s + j] + C[j * s + i]); });
+  __syncthreads();
+  const int info = chol_ptiles(pt, nt, Dinv, &sinfo);
+  double fro = 0.0;
+  if (info == 0) {
+    for (int j = wave; j < nt; j += NWP) {
+      sv4d Xr[PNT];
+#pragma unroll
+      for (int i = 0; i < PNT; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Xr[i][v] = (i == j && 4 * v + lk == li) ? 1.0 : 0.0;
+      wave_fwd(pt, Dinv, nt, j, Xr);
+      const int col = NB * j + li;
+#pragma unroll
+      for (int i = 0; i < PNT; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = NB * i + 4 * v + lk;
+          const double x = (i < nt && row < s && col < s) ? Xr[i][v] : 0.0;
+          fro += x * x;
+        }
+    }
+  }
+  fro = group_sum(fro, red);
+  const bool certified = info == 0 && tr > 0.0 && 1.0 / fro >= eps_rel * tr;
+  if (threadIdx.x == 0) stat[b] = certified ? 0 : 1;
+  if (!certified) return;
+  // H = L^{-1} R^T by 16-column chunks (R upper: R^T (i, c) = R[c][i]); rows and columns past s are zero
+  for (int c0 = wave * NB; c0 < np; c0 += NWP * NB) {
+    const int col = c0 + li;
+    const int cb = min(col, s - 1) * s;
+    sv4d Xr[PNT];
+#pragma unroll
+    for (int i = 0; i < PNT / 2; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Xr[i][v] = R[cb + min(NB * i + 4 * v + lk, s - 1)];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = PNT / 2; i < PNT; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Xr[i][v] = R[cb + min(NB * i + 4 * v + lk, s - 1)];
+#pragma unroll
+    for (int i = 0; i < PNT; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = NB * i + 4 * v + lk;
+        if (!(i < nt && row < s && col < s)) Xr[i][v] = 0.0;
+      }
+    wave_fwd(pt, Dinv, nt, 0, Xr);
+#pragma unroll
+    for (int i = 0; i < PNT; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = NB * i + 4 * v + lk;
+        if (i < nt) H[int64_t(row) * np + col] = (row < s && col < s) ? Xr[i][v] : 0.0;
+      }
+  }
+  __syncthreads();
+  // T = H^T H, all s x s tiles (the Jacobi kernel symmetrises on load)
+  for (int u = wave; u < nt * nt; u += NWP) {
+    const int ti = u / nt, tj = u - ti * nt;
+    const double* A0 = H + int64_t(lk) * np + NB * ti + li;  // H^T (li, 4 v + lk) = H (4 v + lk, li)
+    const double* B0 = H + int64_t(lk) * np + NB * tj + li;
+    sv4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < np; kk += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A0[int64_t(kk) * np], B0[int64_t(kk) * np], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = NB * ti + tile_row(v), j = NB * tj + tile_col();
+      if (i < s && j < s) T[int64_t(i) * s + j] = acc[v];
+    }
   }
 }
 
@@ -1308,14 +1706,22 @@ size_t small_chol_scratch_elems(int r, int c) {
   return e * sizeof(double) <= LDS_LIMIT ? 0 : e;
 }
 
-SmallWs small_ws(DBuf<double>& buf, int nb, int n, int c) {
+SmallWs small_ws(DBuf<double>& buf, int nb, int n, int c, bool evd) {
   SmallWs w;
   w.n = n;
   w.c = c;
   w.stride = int64_t(small_scratch_elems(n, c));
-  if (w.stride > 0) {
-    buf.alloc(size_t(w.stride) * std::max(nb, 1));
-    w.p = buf.p;
+  const bool logs = evd && w.stride > 0 && evd_elems(n) * sizeof(double) > LDS_LIMIT && n <= PSMAX;
+  w.jstride = logs ? jlog_stride(n) : 0;
+  const size_t nbs = size_t(std::max(nb, 1));
+  const size_t total = size_t(w.stride) * nbs + size_t(w.jstride) * nbs + (logs ? (nbs + 1) / 2 + 1 : 0);
+  if (total > 0) {
+    buf.alloc(total);
+    w.p = w.stride > 0 ? buf.p : nullptr;
+    if (logs) {
+      w.jlog = buf.p + size_t(w.stride) * nbs;
+      w.jstat = reinterpret_cast<int*>(w.jlog + size_t(w.jstride) * nbs);
+    }
   }
   return w;
 }
@@ -1372,31 +1778,39 @@ void small_svqb(int nb, int s, const double* G, int64_t sG, double drop2, double
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
   const size_t el = evd_elems(s);
   const int mode = ws_mode(ws, el, s, s);
-  if (mode)
+  if (mode) {
     k_small_svqb<1><<<nb, NT, dyn_lds(mode, el), st>>>(s, G, sG, drop2, T, sT, out, skip, ws.p, ws.stride);
-  else
+  } else if (s <= PSMAX && ws.jlog) {
+    k_jacobi_p<<<nb, NT, size_t(s) * (s + 1) / 2 * sizeof(double), st>>>(s, G, sG, 1, 0, drop2, nullptr, out, skip,
+                                                                        ws.jlog, ws.jstride);
+    NS_LAUNCH_CHECK();
+    k_jacobi_rows<<<dim3(unsigned((s + 3) / 4), unsigned(nb)), 256, 0, st>>>(s, ws.jlog, ws.jstride, T, s, sT, s,
+                                                                            skip);
+  } else {
     k_small_svqb<0><<<nb, NT, 0, st>>>(s, G, sG, drop2, T, sT, out, skip, ws.p, ws.stride);
+  }
   NS_LAUNCH_CHECK();
 }
 
 void small_cholqr(Batch bt, int s, const double* G, int64_t sG, const double* shift, double* Rinv, double* Racc,
-                  int init, int* flag, const SmallWs& ws, hipStream_t st, double certify, int* ok) {
+                  int init, int* flag, const SmallWs& ws, hipStream_t st, double certify, int* ok, double single_thr,
+                  int* single) {
   KScope ks_small(KF_SMALL, st);
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
   const size_t el = chol_ws(s, s);
   const int mode = ws_mode(ws, el, s, s);
   if (packed_chol(el, s)) {  // (its R Racc staging uses the global scratch that ws_mode checked)
     k_small_cholqr_p<<<bt.nb, NTP, packed_lds(s), st>>>(s, bt.dims, G, sG, shift, Rinv, Racc, init, flag, ws.p,
-                                                       ws.stride, certify, ok);
+                                                        ws.stride, certify, ok, single_thr, single);
     NS_LAUNCH_CHECK();
     return;
   }
   if (mode)
     k_small_cholqr<1><<<bt.nb, NT, dyn_lds(mode, el), st>>>(s, bt.dims, G, sG, shift, Rinv, Racc, init, flag, ws.p,
-                                                            ws.stride, certify, ok);
+                                                            ws.stride, certify, ok, single_thr, single);
   else
     k_small_cholqr<0><<<bt.nb, NT, 0, st>>>(s, bt.dims, G, sG, shift, Rinv, Racc, init, flag, ws.p, ws.stride, certify,
-                                           ok);
+                                           ok, single_thr, single);
   NS_LAUNCH_CHECK();
 }
 
@@ -1406,10 +1820,23 @@ void small_nystrom(int nb, int s, int k, const double* C, const double* R, doubl
   if (s > SMAX) fail(INVALID_ARG, "k + p too large for the small dense kernels (limit 256)");
   const size_t el = chol_ws(s, s);
   const int mode = ws_mode(ws, el, s, s);
-  if (mode)
-    k_small_nystrom<1><<<nb, NT, dyn_lds(mode, el), st>>>(s, k, C, R, eps_rel, Wk, Ek, out, ws.p, ws.stride);
-  else
-    k_small_nystrom<0><<<nb, NT, 0, st>>>(s, k, C, R, eps_rel, Wk, Ek, out, ws.p, ws.stride);
+  if (mode) {
+    k_small_nystrom<1><<<nb, NT, dyn_lds(mode, el), st>>>(s, k, C, R, eps_rel, Wk, Ek, out, ws.p, ws.stride, nullptr);
+  } else if (s <= PSMAX && ws.jlog) {
+    // packed kernels for the certified problems (jstat 0), the dense kernel in global memory for the others
+    const int np = pad16(s);
+    k_nys_prep_p<<<nb, NTP, packed_lds(s), st>>>(s, C, R, eps_rel, ws.p, ws.stride, ws.jstat);
+    NS_LAUNCH_CHECK();
+    k_jacobi_p<<<nb, NT, size_t(s) * (s + 1) / 2 * sizeof(double), st>>>(
+        s, ws.p + int64_t(np) * np, ws.stride, 0, k, 0.0, Ek, out, ws.jstat, ws.jlog, ws.jstride);
+    NS_LAUNCH_CHECK();
+    k_jacobi_rows<<<dim3(unsigned((s + 3) / 4), unsigned(nb)), 256, 0, st>>>(s, ws.jlog, ws.jstride, Wk, k,
+                                                                            int64_t(s) * k, k, ws.jstat);
+    NS_LAUNCH_CHECK();
+    k_small_nystrom<0><<<nb, NT, 0, st>>>(s, k, C, R, eps_rel, Wk, Ek, out, ws.p, ws.stride, ws.jstat);
+  } else {
+    k_small_nystrom<0><<<nb, NT, 0, st>>>(s, k, C, R, eps_rel, Wk, Ek, out, ws.p, ws.stride, nullptr);
+  }
   NS_LAUNCH_CHECK();
 }
 

@@ -56,7 +56,8 @@ __global__ __launch_bounds__(256) void k_gram_strip(Seg sg, const TA* __restrict
   const int tb = min(min(GS_MAXT, (rb + 15) / 16 - bt0), sym ? int(blockIdx.y) - bt0 + 1 : GS_MAXT);
   if (tb <= 0) return;
   int64_t r0, r1;
-  chunk_rows(sg, blockIdx.x, r0, r1);
+  const int pseg = chunk_rows(sg, blockIdx.x, r0, r1);
+  if (sg.skip && sg.skip[pseg]) return;
   gv4d acc[GS_MAXT];
 #pragma unroll
   for (int t = 0; t < GS_MAXT; ++t) acc[t] = gv4d{0.0, 0.0, 0.0, 0.0};
@@ -120,6 +121,113 @@ __global__ __launch_bounds__(256) void k_gram_strip(Seg sg, const TA* __restrict
       }
 }
 
+// Gram partials of wide blocks (32..160 columns each side), one workgroup per reduction chunk: every output
+// tile of the chunk's A^T B (with A = B only the lower ones and the diagonal, mirrored on output) is owned by one
+// of the 8 waves, and the chunk's rows pass through LDS GC_K at a time, double-buffered with the next stage's
+// loads in flight during the products, so each chunk of A and B is read from memory once (the strip kernel
+// above reads B once per output strip).  Each tile sums the chunk's rows in row order.
+constexpr int GC_MAXC = 160;
+constexpr int GC_K = 16;
+constexpr int GC_LD = GC_MAXC + 4;  // LDS row stride (bank spread between the four rows of a k-step)
+constexpr int GC_NT = 512;          // 8 waves, 2 per SIMD: 256 registers each for 13 accumulator tiles
+constexpr int GC_MT = 13;           // output tiles per wave (100 tiles over 8 waves)
+constexpr int GC_PL = (GC_K * GC_MAXC + GC_NT - 1) / GC_NT;
+template <class TA, class TB>
+__global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restrict__ A, int64_t lda, int ra,
+                                                     const TB* __restrict__ B, int64_t ldb, int rb,
+                                                     double* __restrict__ part, int sym) {
+  __shared__ double sA[2][GC_K * GC_LD];
+  __shared__ double sB[2][GC_K * GC_LD];
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int li = lane & 15, lk = lane >> 4;
+  int64_t r0, r1;
+  const int pseg = chunk_rows(sg, blockIdx.x, r0, r1);
+  if (sg.skip && sg.skip[pseg]) return;
+  if (r0 >= r1) {  // a chunk without rows contributes zeros
+    for (int o = threadIdx.x; o < ra * rb; o += GC_NT) part[int64_t(blockIdx.x) * ra * rb + o] = 0.0;
+    return;
+  }
+  const int ta = (ra + 15) / 16, tbn = (rb + 15) / 16;
+  const int ntile = sym ? ta * (ta + 1) / 2 : ta * tbn;
+  const int wa = 16 * ta, wb = 16 * tbn;  // staged columns (zero past ra, rb)
+  int tA[GC_MT], tB[GC_MT];
+  bool has[GC_MT];
+#pragma unroll
+  for (int m = 0; m < GC_MT; ++m) {
+    const int t = w + 8 * m;
+    has[m] = t < ntile;
+    int i = 0, j = 0;
+    if (has[m]) {
+      if (sym) {
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        j = t - i * (i + 1) / 2;
+      } else {
+        i = t / tbn;
+        j = t - i * tbn;
+      }
+    }
+    tA[m] = i;
+    tB[m] = j;
+  }
+  gv4d acc[GC_MT];
+#pragma unroll
+  for (int m = 0; m < GC_MT; ++m) acc[m] = gv4d{0.0, 0.0, 0.0, 0.0};
+  double xa[GC_PL], xb[GC_PL];
+  auto load = [&](int64_t k0) {  // clamped, in-bounds addresses; out-of-range values are zeroed in store
+#pragma unroll
+    for (int q = 0; q < GC_PL; ++q) {
+      const int e = threadIdx.x + GC_NT * q;
+      const int ea = min(e, GC_K * wa - 1), eb = min(e, GC_K * wb - 1);
+      const int64_t rowa = min(k0 + ea / wa, r1 - 1), rowb = min(k0 + eb / wb, r1 - 1);
+      xa[q] = double(A[rowa * lda + min(ea % wa, ra - 1)]);
+      if (!sym) xb[q] = double(B[rowb * ldb + min(eb % wb, rb - 1)]);
+    }
+  };
+  auto store = [&](int64_t k0, int buf) {
+#pragma unroll
+    for (int q = 0; q < GC_PL; ++q) {
+      const int e = threadIdx.x + GC_NT * q;
+      if (e < GC_K * wa) {
+        const int r = e / wa, c = e % wa;
+        sA[buf][r * GC_LD + c] = (k0 + r < r1 && c < ra) ? xa[q] : 0.0;
+      }
+      if (!sym && e < GC_K * wb) {
+        const int r = e / wb, c = e % wb;
+        sB[buf][r * GC_LD + c] = (k0 + r < r1 && c < rb) ? xb[q] : 0.0;
+      }
+    }
+  };
+  load(r0);
+  int buf = 0;
+  for (int64_t k0 = r0; k0 < r1; k0 += GC_K, buf ^= 1) {
+    store(k0, buf);
+    __syncthreads();
+    if (k0 + GC_K < r1) load(k0 + GC_K);
+    const double* a_ = sA[buf];
+    const double* b_ = sym ? sA[buf] : sB[buf];
+#pragma unroll
+    for (int kk = 0; kk < GC_K; kk += 4) {
+      const int ro = (kk + lk) * GC_LD + li;
+#pragma unroll
+      for (int m = 0; m < GC_MT; ++m)
+        if (has[m]) acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_[ro + 16 * tA[m]], b_[ro + 16 * tB[m]], acc[m], 0, 0, 0);
+    }
+  }
+  const int nout = ra * rb;
+  double* out = part + int64_t(blockIdx.x) * nout;
+#pragma unroll
+  for (int m = 0; m < GC_MT; ++m)
+    if (has[m])
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * tA[m] + 4 * v + lk, b = 16 * tB[m] + li;
+        if (a < ra && b < rb) {
+          out[a * rb + b] = acc[m][v];
+          if (sym && tA[m] != tB[m]) out[b * rb + a] = acc[m][v];
+        }
+      }
+}
+
 // G_p[o] = alpha * (sum of segment p's chunk partials of output o) + beta * G_p[o].  TX outputs per block;
 // the TY = 1024 / TX threads of an output take the chunks c = ty, ty + TY, ... and a fixed tree combines them.
 template <int TX>
@@ -132,6 +240,7 @@ __global__ __launch_bounds__(1024) void k_seg_final(Seg sg, int nout, const doub
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   const int o = blockIdx.x * TX + tx;
   const int p = blockIdx.y;
+  if (sg.skip && sg.skip[p]) return;
   const int c0 = sg.coff[p], nch = sg.coff[p + 1] - c0;
   double s = 0.0;
   if (o < nout)
@@ -166,6 +275,21 @@ void seg_final(const Seg& sg, int nout, const double* part, double* G, int64_t g
 // workgroup computes a 64 x 16 NTI output block (wave w: rows 16 w .. 16 w + 15, NTI column tiles); X and M are
 // staged through LDS in batches of TS_K rows of M.
 constexpr int TS_K = 32;
+// Out[r][c] = X[r][c] for the rows [rbase, min(rbase + 64, rend)) and columns [c0, c1) (a skipped segment of a
+// block update), 256 threads.
+template <class T>
+__device__ __forceinline__ void ts_copy_tile(int64_t rbase, int64_t rend, int c0, int c1, T* __restrict__ Out,
+                                             int64_t ldo, const T* __restrict__ X, int64_t ldx) {
+  const int nc = c1 - c0;
+  if (nc <= 0) return;
+  const int64_t nr = rend - rbase < 64 ? rend - rbase : 64;
+  for (int e = threadIdx.x; e < nr * nc; e += 256) {
+    const int64_t r = rbase + e / nc;
+    const int c = c0 + e % nc;
+    Out[r * ldo + c] = X[r * ldx + c];
+  }
+}
+
 template <class T, int NTI>
 __global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* __restrict__ Out, int64_t ldo, double beta,
                                                  double gamma, const T* __restrict__ X, int64_t ldx, int K,
@@ -178,6 +302,10 @@ __global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* __restric
   const int64_t rend = sg.off[p + 1];
   const double* Mp = M + int64_t(p) * mstride;
   const int c0 = blockIdx.y * NC;
+  if (sg.skip && sg.skip[p]) {  // Out = X on this tile's rows and column group
+    ts_copy_tile(rbase, rend, c0, min(c0 + NC, ncols), Out, ldo, X, ldx);
+    return;
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   gv4d acc[NTI];
@@ -267,6 +395,10 @@ __global__ __launch_bounds__(256, 2) void k_ts_wide(Seg sg, int ncols, T* __rest
   const int64_t rbase = sg.off[p] + int64_t(blockIdx.x - sg.toff[p]) * 64;
   const int64_t rend = sg.off[p + 1];
   const double* Mp = M + int64_t(p) * mstride;
+  if (sg.skip && sg.skip[p]) {  // Out = X on this tile's rows
+    ts_copy_tile(rbase, rend, 0, ncols, Out, ldo, X, ldx);
+    return;
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   gv4d acc[NTI];
@@ -614,6 +746,13 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
   const double rows = double(sg.rows);
   KScope ks(KF_GRAM, st, rows * (double(ra) * sizeof(TA) + (sym ? 0.0 : double(rb) * sizeof(TB))),
             sym ? rows * ra * (ra + 1.0) : 2.0 * rows * ra * rb);
+  // wide FP64 blocks: one workgroup per chunk (FP32 blocks stay on the strip kernel, faster for them)
+  if (sizeof(TA) == 8 && sizeof(TB) == 8 && ra >= 32 && rb >= 32 && ra <= GC_MAXC && rb <= GC_MAXC) {
+    k_gram_chunk<TA, TB><<<unsigned(sg.nchunk), GC_NT, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym);
+    NS_LAUNCH_CHECK();
+    seg_final(sg, nout, work, G, gstride, alpha, beta, st, rscale, rsstride, rb);
+    return;
+  }
   switch (std::min(tbt, GS_MAXT)) {  // column tiles per launch column group
     case 1: k_gram_strip<TA, TB, 1><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym); break;
     case 2: k_gram_strip<TA, TB, 2><<<g, 256, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym); break;
