@@ -21,6 +21,7 @@ struct Seg {
   const int* toff = nullptr;     // [n + 1] prefix of 64-row tiles per segment
   const int* rseg = nullptr;     // [rows] segment of each row
   int nchunk = 0, ntile = 0;     // totals
+  int64_t first = 0;             // host copy of off[0]
   // [n] optional device flags: a segment flagged nonzero is passed over -- the Gram products leave its G_p as
   // it is, and the block updates copy X into Out (the orthonormalisation pass the flag makes unnecessary)
   const int* skip = nullptr;

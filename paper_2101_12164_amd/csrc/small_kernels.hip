@@ -568,7 +568,8 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
                                                      int* flag, double* gw, int64_t gws, double certify,
                                                      int* ok, double single_thr, int* single) {
   extern __shared__ double sm[];
-  __shared__ int sinfo;
+  __shared__ int sinfo, refine;
+  double lmax_c = 0.0;
   __shared__ double red[NT];
   const int b = blockIdx.x;
   const int n = dims ? dims[b] : s;
@@ -584,6 +585,7 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
   }
   double tr = 0.0;
   for (int i = threadIdx.x; i < n; i += NT) tr += G[i * s + i];
+  if (threadIdx.x == 0) refine = 0;
   tr = block_sum(tr, red);
   const double shift = (shift_coef ? shift_coef[b] : 0.0) * tr;
   CholWs w = chol_carve(kLds ? sm : gw + b * gws, n, n);
@@ -656,18 +658,38 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
     gmax = red[0];
     __syncthreads();
     const double lmin = 1.0 / fmin(f, rmax * cmax);
-    const double lmax = fmin(tr, gmax);
+    lmax_c = fmin(tr, gmax);
     if (threadIdx.x == 0) {
-      ok[b] = (sinfo == 0 && lmin > certify * lmax) ? 1 : 0;
+      const int okb = (sinfo == 0 && lmin > certify * lmax_c) ? 1 : 0;
+      ok[b] = okb;
+      refine = sinfo == 0 && !okb;
       if (single) single[b] = (sinfo == 0 && fsc > 0.0 && 1.0 / fsc > single_thr * n) ? 1 : 0;
     }
   }
   __syncthreads();
+  // the norm bounds above are loose by up to a factor of about n each: where they fail, the Cholesky of
+  // G + shift I - tau I with tau = certify * lambda_max bound + its backward-error bound decides; success proves
+  // lambda_min > certify * lambda_max (the factor in A is no longer needed once Rinv and Racc are out)
+  auto refine_certificate = [&]() {
+    if (!ok || !refine) return;
+    const double g = double(n + 1) * 0x1p-53 / (1.0 - double(n + 1) * 0x1p-53);
+    const double tau = certify * lmax_c + 1.01 * g * (tr + double(n) * shift);
+    __syncthreads();
+    for (int e = threadIdx.x; e < np * np; e += NT) {
+      const int i = e / np, j = e - i * np;
+      A[i * ld + j] = (i < n && j < n) ? 0.5 * (G[i * s + j] + G[j * s + i]) + (i == j ? shift - tau : 0.0)
+                                       : (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    const int info2 = chol_blocked(A, np, ld, w.Dinv, w.Pn, &sinfo);
+    if (threadIdx.x == 0) ok[b] = info2 == 0 ? 1 : 0;
+  };
   if (init) {
     for (int e = threadIdx.x; e < s * s; e += NT) {
       const int i = e / s, j = e % s;
       Racc[e] = (i < n && j < n && j >= i) ? A[j * ld + i] : 0.0;
     }
+    refine_certificate();
     return;
   }
   // Racc <- R * Racc (R = L^T), with Racc staged in X (zero-padded)
@@ -692,6 +714,7 @@ __global__ __launch_bounds__(NT) void k_small_cholqr(int s, const int* __restric
     const int i = e / s, j = e % s;
     if (i >= np || j >= np) Racc[e] = 0.0;
   }
+  refine_certificate();
 }
 
 // Nystrom core of one problem.  C = Omega^T Y (s x s) and the Cholesky-QR factor R of Y give
@@ -1206,9 +1229,10 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
                                                        double* Racc, int init, int* flag, double* gw, int64_t gws,
                                                        double certify, int* ok, double single_thr, int* single) {
   extern __shared__ double sm[];
-  __shared__ int sinfo;
+  __shared__ int sinfo, refine;
   __shared__ double red[NWP];
   __shared__ double rowsum[PSMAX];
+  double lmax_c = 0.0;
   const int b = blockIdx.x;
   const int n = dims ? dims[b] : s;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
@@ -1223,6 +1247,7 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
   }
   double tr = 0.0;
   for (int i = threadIdx.x; i < n; i += NTP) tr += G[i * s + i];
+  if (threadIdx.x == 0) refine = 0;
   tr = group_sum(tr, red);
   const double shift = (shift_coef ? shift_coef[b] : 0.0) * tr;
   const int nt = (n + NB - 1) / NB, np = nt * NB;
@@ -1302,17 +1327,34 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
     rmax = group_max(rmax, red);
     gmax = group_max(gmax, red);
     const double lmin = 1.0 / fmin(fro, rmax * cmax);
-    const double lmax = fmin(tr, gmax);
+    lmax_c = fmin(tr, gmax);
     if (threadIdx.x == 0) {
-      ok[b] = (sinfo == 0 && lmin > certify * lmax) ? 1 : 0;
+      const int okb = (sinfo == 0 && lmin > certify * lmax_c) ? 1 : 0;
+      ok[b] = okb;
+      refine = sinfo == 0 && !okb;
       if (single) single[b] = (sinfo == 0 && fsc > 0.0 && 1.0 / fsc > single_thr * n) ? 1 : 0;
     }
   }
+  __syncthreads();
+  // where the norm bounds fail, the Cholesky of G + shift I - tau I decides (as in k_small_cholqr)
+  auto refine_certificate = [&]() {
+    if (!ok || !refine) return;
+    const double g = double(n + 1) * 0x1p-53 / (1.0 - double(n + 1) * 0x1p-53);
+    const double tau = certify * lmax_c + 1.01 * g * (tr + double(n) * shift);
+    __syncthreads();
+    ptiles_fill(pt, n, nt, [&](int i, int j) {
+      return 0.5 * (G[i * s + j] + G[j * s + i]) + (i == j ? shift - tau : 0.0);
+    });
+    __syncthreads();
+    const int info2 = chol_ptiles(pt, nt, Dinv, &sinfo);
+    if (threadIdx.x == 0) ok[b] = info2 == 0 ? 1 : 0;
+  };
   if (init) {
     for (int e = threadIdx.x; e < s * s; e += NTP) {
       const int i = e / s, j = e - i * s;
       Racc[e] = (i < n && j < n && j >= i) ? ptile(pt, j / NB, i / NB)[(j % NB) * PTL + i % NB] : 0.0;
     }
+    refine_certificate();
     return;
   }
   // Racc <- R Racc, R = L^T upper: output tile (ti, tj), ti <= tj, sums over the tiles m = ti .. tj
@@ -1363,6 +1405,7 @@ __global__ __launch_bounds__(NTP) void k_small_cholqr_p(int s, const int* __rest
     const int i = e / s, j = e % s;
     if (i >= np || j >= np) Racc[e] = 0.0;
   }
+  refine_certificate();
 }
 
 // ---------------------------------------------------------------- packed Jacobi (n up to 160 past the LDS limit)

@@ -466,6 +466,104 @@ __global__ __launch_bounds__(256, 2) void k_ts_wide(Seg sg, int ncols, T* __rest
     }
 }
 
+// Block updates of one problem's wide FP64 blocks (6..10 column tiles): 256-row workgroups of 8 waves, each wave
+// two 16-row tiles across every column tile (80 accumulators); X and M pass through LDS TB_K values of K at a
+// time, double-buffered with the next stage's loads in flight, so each M stage serves 256 rows (four times the
+// rows of k_ts_wide) and each SIMD has two waves of products to cover the loads.  The sums over K run in the
+// same order as in k_ts_mfma (same bits).
+constexpr int TB_R = 256, TB_NT = 512, TB_K = 16;
+template <int NTI>
+__global__ __launch_bounds__(TB_NT) void k_ts_big(int64_t r0, int64_t rend, const int* skip, int ncols,
+                                                  double* __restrict__ Out, int64_t ldo, double beta, double gamma,
+                                                  const double* __restrict__ X, int64_t ldx, int K,
+                                                  const double* __restrict__ M, int64_t ldm) {
+  constexpr int NC = 16 * NTI;
+  constexpr int XS = TB_K + 1, MS = NC + 1;
+  __shared__ double sX[2][TB_R * XS];
+  __shared__ double sM[2][TB_K * MS];
+  const int64_t rbase = r0 + int64_t(blockIdx.x) * TB_R;
+  if (skip && skip[0]) {  // Out = X on this workgroup's rows (a skipped segment)
+    const int64_t nr = rend - rbase < TB_R ? rend - rbase : TB_R;
+    for (int64_t e = threadIdx.x; e < nr * ncols; e += TB_NT) {
+      const int64_t r = rbase + e / ncols;
+      const int c = int(e % ncols);
+      Out[r * ldo + c] = X[r * ldx + c];
+    }
+    return;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  gv4d acc[2][NTI];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int t = 0; t < NTI; ++t) acc[h][t] = gv4d{0.0, 0.0, 0.0, 0.0};
+  constexpr int PX = TB_R * TB_K / TB_NT, PM = (TB_K * NC + TB_NT - 1) / TB_NT;
+  double xv[PX], mv[PM];
+  // 32-bit offsets from the workgroup's first row (its 256 rows span less than 2^31 elements)
+  const double* Xw = X + rbase * ldx;
+  const int rlast = int(min(int64_t(TB_R), rend - rbase)) - 1, ldx32 = int(ldx), ldm32 = int(ldm);
+  auto load = [&](int k0) {  // clamped, in-bounds addresses; out-of-range values zeroed in store
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+      const int e = threadIdx.x + TB_NT * q, r = min(e / TB_K, rlast), k = min(k0 + e % TB_K, K - 1);
+      xv[q] = Xw[r * ldx32 + k];
+    }
+#pragma unroll
+    for (int q = 0; q < PM; ++q) {
+      const int e = min(threadIdx.x + TB_NT * q, TB_K * NC - 1), c = min(e % NC, ncols - 1);
+      const int k = min(k0 + e / NC, K - 1);
+      mv[q] = M[k * ldm32 + c];
+    }
+  };
+  auto store = [&](int k0, int buf) {
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+      const int e = threadIdx.x + TB_NT * q, r = e / TB_K, kk = e % TB_K;
+      sX[buf][r * XS + kk] = (rbase + r < rend && k0 + kk < K) ? xv[q] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PM; ++q) {
+      const int e = threadIdx.x + TB_NT * q, c = e % NC, kk = e / NC;
+      if (e < TB_K * NC) sM[buf][kk * MS + c] = (c < ncols && k0 + kk < K) ? mv[q] : 0.0;
+    }
+  };
+  load(0);
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += TB_K, buf ^= 1) {
+    store(k0, buf);
+    __syncthreads();
+    if (k0 + TB_K < K) load(k0 + TB_K);
+    const double* xs = sX[buf];
+    const double* ms = sM[buf];
+#pragma unroll
+    for (int kk = 0; kk < TB_K; kk += 4) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double a = xs[(32 * w + 16 * h + li) * XS + kk + lk];
+#pragma unroll
+        for (int t = 0; t < NTI; ++t)
+          acc[h][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ms[(kk + lk) * MS + 16 * t + li], acc[h][t], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // one k-step's operands at a time (80 accumulators stay in registers)
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int t = 0; t < NTI; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = rbase + 32 * w + 16 * h + 4 * v + lk;
+        const int c = 16 * t + li;
+        if (r < rend && c < ncols) {
+          double y = gamma * acc[h][t][v];
+          if (beta != 0.0) y += beta * Out[r * ldo + c];
+          Out[r * ldo + c] = y;
+        }
+      }
+}
+
 template <class T>
 void ts_launch(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, double gamma, const T* X, int64_t ldx,
                int K, const double* M, int64_t ldm, int64_t mstride, hipStream_t st) {
@@ -479,6 +577,24 @@ void ts_launch(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, doubl
     constexpr int N = decltype(nti)::value;
     k_ts_wide<T, N><<<unsigned(sg.ntile), 256, 0, st>>>(sg, ncols, Out, ldo, beta, gamma, X, ldx, K, M, ldm, mstride);
   };
+  if constexpr (sizeof(T) == 8) {
+    if (sg.n == 1 && tiles > 5 && tiles <= 10 && sg.rows > sg.first) {  // one problem's wide FP64 block
+      auto big = [&](auto nti) {
+        constexpr int N = decltype(nti)::value;
+        k_ts_big<N><<<unsigned((sg.rows - sg.first + TB_R - 1) / TB_R), TB_NT, 0, st>>>(
+            sg.first, sg.rows, sg.skip, ncols, Out, ldo, beta, gamma, X, ldx, K, M, ldm);
+      };
+      switch (tiles) {
+        case 6: big(std::integral_constant<int, 6>()); break;
+        case 7: big(std::integral_constant<int, 7>()); break;
+        case 8: big(std::integral_constant<int, 8>()); break;
+        case 9: big(std::integral_constant<int, 9>()); break;
+        default: big(std::integral_constant<int, 10>()); break;
+      }
+      NS_LAUNCH_CHECK();
+      return;
+    }
+  }
   if (tiles > 5 && tiles <= 16) {
     switch (tiles) {
       case 6: wide(std::integral_constant<int, 6>()); break;
@@ -723,6 +839,7 @@ void SegBuf::build(const std::vector<int64_t>& offsets, hipStream_t st) {
   }
   view.n = n;
   view.rows = rows;
+  view.first = offsets[0];
   view.off = off.p;
   view.coff = coff.p;
   view.toff = toff.p;
