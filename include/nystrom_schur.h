@@ -357,9 +357,12 @@ ns_status nystrom_schur_features(int64_t n, int64_t nnz, const int64_t* row_ptr,
                                  int64_t* n_gamma, void* stream);
 
 /* The network: d_in -> hidden -> hidden -> d_out, ReLU hidden layers, linear
- * output; BF16 operands on MFMA with FP32 accumulation; FP32 master weights.
- * params: HOST float array, in order W1 (d_in x hidden, row-major in x out), b1,
- * W2 (hidden x hidden), b2, W3 (hidden x d_out), b3; the library copies it. */
+ * output; BF16 operands on 16x16x32 MFMA with FP32 accumulation; FP32 master
+ * weights.  params: HOST float array, in order W1 (d_in x hidden, row-major in x
+ * out), b1, W2 (hidden x hidden), b2, W3 (hidden x d_out), b3; the library copies
+ * it.  Every call is ordered on its stream and after the network's previous call
+ * (whatever its stream); create, get_params and destroy use the network's own
+ * stream and synchronise only that (no device-wide synchronisation). */
 typedef struct ns_mlp_s* ns_mlp;
 ns_status nystrom_schur_mlp_create(int32_t d_in, int32_t hidden, int32_t d_out, const float* params, ns_mlp* out);
 /* HOST copies of the parameters and of the last gradient (either may be NULL). */

@@ -119,9 +119,16 @@ __global__ void k_feat_out(int64_t ng, const double* __restrict__ F, const doubl
 // ------------------------------------------------------------------ BF16 GEMM on MFMA
 // C(m, n) = sum_k A(m, k) B(k, n), A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn] (BF16).
 // One workgroup: 64 x 64 output tile, wave w rows [16 w, 16 w + 16), four 16 x 16 MFMA blocks.
-// MFMA 16x16x16 BF16 operands: lane l holds A(l % 16, 4 (l / 16) + t) and B(4 (l / 16) + t, l % 16),
-// t = 0..3; the FP32 result element v of lane l is C(4 (l / 16) + v, l % 16).
+// gfx950 MFMA 16x16x32 BF16 operands: lane l holds A(l % 16, 8 (l / 16) + t) and B(8 (l / 16) + t, l % 16),
+// t = 0..7; the FP32 result element v of lane l is C(4 (l / 16) + v, l % 16).
 // OUT 0: BF16 out = act(acc + bias); OUT 2: FP64 out = acc + bias.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ bf16x8 bf16x8_of(const uint16_t (&u)[8]) {
+  bf16x8 r;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) r[t] = __builtin_bit_cast(__bf16, u[t]);
+  return r;
+}
 template <int OUT>
 __global__ __launch_bounds__(256) void k_bgemm(int M, int N, int K, const uint16_t* __restrict__ A, int64_t sam,
                                                int64_t sak, const uint16_t* __restrict__ B, int64_t sbk,
@@ -131,33 +138,34 @@ __global__ __launch_bounds__(256) void k_bgemm(int M, int N, int K, const uint16
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = blockIdx.y * 64 + 16 * w, n0 = blockIdx.x * 64;
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
-  const int li = lane & 15, lk = 4 * (lane >> 4);
+  const int li = lane & 15, lk = 8 * (lane >> 4), lr = 4 * (lane >> 4);
   f4 acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
   const int am = m0 + li;
-  // operands are loaded unconditionally from clamped in-bounds positions and zeroed afterwards, so the twenty
+  // operands are loaded unconditionally from clamped in-bounds positions and zeroed afterwards, so the forty
   // loads of a k-step are in flight together (a load under a per-lane condition waits behind its own branch)
   const int amc = min(am, M - 1);
-  for (int k0 = kb; k0 < ke; k0 += 16) {
-    uint16_t av[4], bv[4][4];
+  for (int k0 = kb; k0 < ke; k0 += 32) {
+    uint16_t av[8], bv[4][8];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < 8; ++t) {
       const int kc = min(k0 + lk + t, ke - 1);
       av[t] = A[int64_t(amc) * sam + int64_t(kc) * sak];
 #pragma unroll
       for (int q = 0; q < 4; ++q) bv[q][t] = B[int64_t(kc) * sbk + int64_t(min(n0 + 16 * q + li, N - 1)) * sbn];
     }
-    s4 a;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) a[t] = (am < M && k0 + lk + t < ke) ? short(av[t]) : short(0);
+    for (int t = 0; t < 8; ++t)
+      if (!(am < M && k0 + lk + t < ke)) av[t] = 0;
+    const bf16x8 a = bf16x8_of(av);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int bn = n0 + 16 * q + li;
-      s4 b;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) b[t] = (bn < N && k0 + lk + t < ke) ? short(bv[q][t]) : short(0);
-      acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[q], 0, 0, 0);
+      for (int t = 0; t < 8; ++t)
+        if (!(bn < N && k0 + lk + t < ke)) bv[q][t] = 0;
+      acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bf16x8_of(bv[q]), acc[q], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -166,7 +174,7 @@ __global__ __launch_bounds__(256) void k_bgemm(int M, int N, int K, const uint16
     if (cn >= N) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int cm = m0 + lk + v;
+      const int cm = m0 + lr + v;
       if (cm >= M) continue;
       float x = acc[q][v];
       if constexpr (OUT == 0) {
@@ -342,6 +350,7 @@ struct ns_mlp_s {
   std::string last_error;
   hipEvent_t ev = nullptr;       // recorded at the end of every call
   hipStream_t last = nullptr;    // stream of the previous call
+  hipStream_t own = nullptr;     // the network's own stream (initialisation, parameter copies)
 };
 
 namespace ns {
@@ -531,18 +540,24 @@ ns_status nystrom_schur_mlp_create(int32_t d_in, int32_t hidden, int32_t d_out, 
     m->h = hidden;
     m->k = d_out;
     mlp_layout(*m);
+    // initialisation on a private stream, synchronised alone (no device-wide synchronisation); later calls on
+    // any stream wait for it through the network's event
+    NS_HIP(hipStreamCreateWithFlags(&m->own, hipStreamNonBlocking));
+    StreamScope ss(m->own);
     m->p.alloc(m->np);
     m->g.alloc(m->np);
     m->m1.alloc(m->np);
     m->m2.alloc(m->np);
     m->wb.alloc(m->np);
     NS_HIP(hipEventCreateWithFlags(&m->ev, hipEventDisableTiming));
-    NS_HIP(hipMemcpy(m->p.p, params, m->np * sizeof(float), hipMemcpyHostToDevice));
-    NS_HIP(hipMemset(m->g.p, 0, m->np * sizeof(float)));
-    NS_HIP(hipMemset(m->m1.p, 0, m->np * sizeof(float)));
-    NS_HIP(hipMemset(m->m2.p, 0, m->np * sizeof(float)));
-    mlp_refresh_bf(*m, nullptr);
-    NS_HIP(hipDeviceSynchronize());
+    NS_HIP(hipMemcpyAsync(m->p.p, params, m->np * sizeof(float), hipMemcpyHostToDevice, m->own));
+    NS_HIP(hipMemsetAsync(m->g.p, 0, m->np * sizeof(float), m->own));
+    NS_HIP(hipMemsetAsync(m->m1.p, 0, m->np * sizeof(float), m->own));
+    NS_HIP(hipMemsetAsync(m->m2.p, 0, m->np * sizeof(float), m->own));
+    mlp_refresh_bf(*m, m->own);
+    NS_HIP(hipEventRecord(m->ev, m->own));
+    m->last = m->own;
+    NS_HIP(hipStreamSynchronize(m->own));
     *out = m;
     return NS_OK;
   } catch (const Error& e) {
@@ -555,9 +570,11 @@ ns_status nystrom_schur_mlp_create(int32_t d_in, int32_t hidden, int32_t d_out, 
 ns_status nystrom_schur_mlp_get_params(ns_mlp m, float* params, float* grad) {
   if (!m) return mlp_fail(nullptr, Error{INVALID_ARG, "NULL network"});
   try {
-    NS_HIP(hipDeviceSynchronize());
-    if (params) NS_HIP(hipMemcpy(params, m->p.p, m->np * sizeof(float), hipMemcpyDeviceToHost));
-    if (grad) NS_HIP(hipMemcpy(grad, m->g.p, m->np * sizeof(float), hipMemcpyDeviceToHost));
+    // after the network's last call (its event), on the network's own stream
+    NS_HIP(hipStreamWaitEvent(m->own, m->ev, 0));
+    if (params) NS_HIP(hipMemcpyAsync(params, m->p.p, m->np * sizeof(float), hipMemcpyDeviceToHost, m->own));
+    if (grad) NS_HIP(hipMemcpyAsync(grad, m->g.p, m->np * sizeof(float), hipMemcpyDeviceToHost, m->own));
+    NS_HIP(hipStreamSynchronize(m->own));
     return NS_OK;
   } catch (const Error& e) {
     return mlp_fail(m, e);
@@ -646,9 +663,17 @@ ns_status nystrom_schur_mlp_adam_step(ns_mlp m, double lr, void* stream) {
 
 void nystrom_schur_mlp_destroy(ns_mlp m) {
   if (!m) return;
-  (void)hipDeviceSynchronize();  // calls may have used several streams: free after all of them
-  if (m->ev) (void)hipEventDestroy(m->ev);
-  delete m;
+  // every call waits for the previous one (the network's event), so the last event covers them all
+  if (m->ev) (void)hipEventSynchronize(m->ev);
+  if (m->own) (void)hipStreamSynchronize(m->own);
+  {
+    StreamScope ss(m->own);
+    hipStream_t own = m->own;
+    hipEvent_t ev = m->ev;
+    delete m;  // buffers return to the allocator behind the completed work
+    if (ev) (void)hipEventDestroy(ev);
+    if (own) (void)hipStreamDestroy(own);
+  }
 }
 
 const char* nystrom_schur_mlp_last_error(ns_mlp m) { return m ? m->last_error.c_str() : g_mlp_error.c_str(); }
