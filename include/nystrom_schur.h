@@ -121,6 +121,16 @@ typedef enum { NS_OUTER_SCHUR = 0, NS_OUTER_FULL = 1 } ns_outer;
 typedef enum { NS_LEVEL2_EXACT = 0, NS_LEVEL2_NYSTROM = 1 } ns_level2;
 
 /*
+ * The inner system of the construction:
+ *   NS_INNER_SHIFTED: S_Gamma D = W G preconditioned by A_Gamma^{-1}, then B G = A_Gamma D (by eq. S-1 the
+ *                     product of Algorithm alg:prec1 steps 2-4; n_gamma rows);
+ *   NS_INNER_FORM_A:  the steps as printed: S_I X = A_IGamma G preconditioned by A_I^{-1} (eq. SI), then
+ *                     B G = A_GammaI X (NS_VARIANT_M3: S_I X = G, B G = X); block vectors of n_interior rows.
+ *                     One problem per handle; FP64 inner work; NS_VARIANT_M2 or NS_VARIANT_M3.
+ */
+typedef enum { NS_INNER_SHIFTED = 0, NS_INNER_FORM_A = 1 } ns_inner_form;
+
+/*
  * Options of setup().  Zero-initialise and set what you need; a value of 0 in
  * tol_inner, eig_thresh_rel, orth_drop_rel or max_inner_iters selects the
  * default given in brackets.
@@ -168,6 +178,7 @@ typedef struct {
   double level2_tol_inner;   /* NS_LEVEL2_NYSTROM: block-CG tolerance of level 2 [tol_inner]      */
   const double* level2_omega;/* NS_LEVEL2_NYSTROM: DEVICE, n_junction x (k_2 + p_2) row-major
                                 sketch, junction nodes in interface order.  Required when k_2 > 0. */
+  int32_t inner_form;        /* ns_inner_form [NS_INNER_SHIFTED]                                  */
 } ns_options;
 
 /* Outputs of setup(), HOST memory. Times are seconds measured with hipEvents. */
@@ -402,8 +413,10 @@ void nystrom_schur_kernel_timing_families(uint32_t mask);
  * "trsm_interface_f32" (forward and backward sweeps), "schur_epi", "spmm",
  * "local_schur_form", "local_schur_apply_f64", "local_schur_apply_f32",
  * "interface_inverse_f64", "interface_inverse_f32", "mlp_forward_bf16",
- * "mlp_backward_f32", "local_schur_apply_bf16", "interface_inverse_bf16", "gram" (block-vector Gram
- * products), "block_update" (block updates X M), "small_dense" (the one-workgroup s x s kernels).
+ * "mlp_backward_f32", "local_schur_apply_bf16", "interface_inverse_bf16", "gram" (Gram products
+ * of block vectors, both wider than 16 columns), "block_update" (block updates X M of more than 16
+ * columns), "small_dense" (the one-workgroup s x s kernels), "gram_narrow" and
+ * "block_update_narrow" (the same with at most 16 columns on one side, e.g. Z^T r and Z c).
  * Waits for the recorded events.  All outputs are HOST pointers (may be NULL).
  * NS_ERR_INVALID_ARG for an unknown family. */
 ns_status nystrom_schur_kernel_stats(const char* family, double* total_ms, int64_t* launches, double* bytes,

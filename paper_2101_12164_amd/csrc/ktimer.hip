@@ -16,7 +16,7 @@ const char* kFamilyNames[KF_COUNT] = {"chol_update",        "chol_panel",       
                                       "local_schur_apply_f64", "local_schur_apply_f32",
                                       "interface_inverse_f64", "interface_inverse_f32", "mlp_forward_bf16", "mlp_backward_f32",
                                       "local_schur_apply_bf16", "interface_inverse_bf16", "gram", "block_update",
-                                      "small_dense"};
+                                      "small_dense", "gram_narrow", "block_update_narrow"};
 
 struct Rec {
   hipEvent_t a, b;
@@ -92,13 +92,15 @@ KScope::~KScope() {
   if (hipEventRecord(b, st) == hipSuccess) t.pending.push_back(Rec{a, b, fam, bytes, flops});
 }
 
-bool kernel_timing_in_loops() {
+bool kernel_timing_in_loops(bool pcg) {
   KTimer& t = timer();
   std::lock_guard<std::mutex> g(t.mu);
-  // families that run only in the setup's factorisation and formation, or in the learned layer
+  // families that run only in the setup's factorisation and formation, or in the learned layer; the PCG
+  // iterations apply single columns, so the wide Gram products and block updates are not in them
   constexpr uint32_t setup_only = (1u << KF_CHOL_UPDATE) | (1u << KF_CHOL_PANEL) | (1u << KF_LS_FORM) |
                                   (1u << KF_MLP_FWD) | (1u << KF_MLP_BWD);
-  return t.on && (t.mask & ~setup_only) != 0;
+  const uint32_t outside = setup_only | (pcg ? (1u << KF_GRAM) | (1u << KF_BLOCK_UPDATE) : 0u);
+  return t.on && (t.mask & ~outside) != 0;
 }
 
 void kscope_add_work(int fam, double bytes, double flops) {

@@ -73,6 +73,7 @@ struct ns_handle_s {
   ns::SegBuf segI;                         // padded interior rows (one problem): the rows of variant M_3
   // recursive level (NS_LEVEL2_NYSTROM): A_Gamma as a DBBD matrix of its own, preconditioned by a handle of
   // its own (interior = interface blocks, interface = junction nodes), which this handle owns
+  int inner_form = 0;  // ns_inner_form
   int level2 = 0, level2_k = 0, level2_p = 0;
   double level2_tol = 0.0;
   const double* level2_omega = nullptr;

@@ -222,16 +222,18 @@ enum KFamily {
   KF_MLP_BWD,  // learned proposal: backward GEMMs (FP32 MFMA)
   KF_LS_APPLY16,  // local Schur blocks applied with BF16 operands (FP32 accumulation)
   KF_INV16,       // interface-block inverses applied with BF16 operands
-  KF_GRAM,        // Gram products A^T B of block vectors (block CG, Nystrom)
-  KF_BLOCK_UPDATE,  // block updates Out = beta Out + gamma X M (block CG, Nystrom)
+  KF_GRAM,        // Gram products A^T B of block vectors, both sides wider than 16 columns (block CG, Nystrom)
+  KF_BLOCK_UPDATE,  // block updates Out = beta Out + gamma X M of more than 16 columns (block CG, Nystrom)
   KF_SMALL,       // one-workgroup dense kernels on the s x s matrices
+  KF_GRAM_NARROW,          // Gram products with one side of at most 16 columns (Z^T r of the PCG apply)
+  KF_BLOCK_UPDATE_NARROW,  // block updates of at most 16 output columns (Z c of the PCG apply)
   KF_COUNT
 };
 // Brackets one launch when timing is on; bytes / flops are the algorithmic
 // work of the launch (what the method must move / compute, no padding).
-// True while kernel timing covers a family that runs inside the block-CG or PCG iterations: those loops then
-// use plain launches (launches recorded into a graph cannot be timed one by one).
-bool kernel_timing_in_loops();
+// True while kernel timing covers a family that runs inside the block-CG (pcg false) or the PCG (pcg true)
+// iterations: that loop then uses plain launches (launches recorded into a graph cannot be timed one by one).
+bool kernel_timing_in_loops(bool pcg);
 struct KScope {
   int fam;
   hipStream_t st;

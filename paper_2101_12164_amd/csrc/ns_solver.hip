@@ -213,10 +213,9 @@ __global__ void k_orth_select(int np, int s, int* active, const int* ok, const i
 // eigenpairs above drop^2 * lambda_max) followed by one Cholesky-QR pass.  Inactive problems get zero
 // columns; dropped directions are zero columns at the end.  Q is scratch.
 template <class T>
-void orth(Handle& h, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int s, int it,
+void orth(Handle& h, const Seg& sg, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int s, int it,
           const int* itd = nullptr) {
   hipStream_t st = h.stream;
-  const Seg& sg = h.segG.view;
   const int np = h.nprob;
   const int64_t ss = int64_t(s) * s;
   const double drop2 = h.drop_rel * h.drop_rel;
@@ -257,12 +256,22 @@ void orth(Handle& h, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int 
 // A_IGamma Omega by eq. S-1), for every problem of the batch at once.  rhs(T* R) writes F into R.  Writes D
 // (FP64, n_G x s) and adds the per-problem iteration counts to h.it_inner (convergence and final column-max
 // relative residuals are those of this solve).
-template <class T, class Rhs>
-void block_pcg(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
+// The operators of the shifted form: rows = interface rows, S = S_Gamma, preconditioner A_Gamma^{-1}.
+template <class T>
+struct SchurOps {
+  Handle& h;
+  const Seg& seg() const { return h.segG.view; }
+  int64_t rows() const { return h.nG; }
+  void S(const T* P, T* Q) { op_schur<T>(h, P, h.s, Q, h.s, h.s, false); }
+  void M(const T* R, T* Z) { op_gamma_solve<T>(h, R, h.s, Z, h.s, h.s); }
+};
+
+template <class T, class Ops, class Rhs>
+void block_pcg(Handle& h, SmallMats& sm, Ops& ops, Rhs rhs, double* D) {
   hipStream_t st = h.stream;
-  const Seg& sg = h.segG.view;
+  const Seg& sg = ops.seg();
   const int s = h.s, np = h.nprob;
-  const int64_t nG = h.nG, ss = int64_t(s) * s;
+  const int64_t nG = ops.rows(), ss = int64_t(s) * s;
   const int pb = (np + 255) / 256;
   DBuf<T> X, R, Pb, Qb, Z;
   for (DBuf<T>* b : {&X, &R, &Pb, &Qb, &Z}) b->alloc(nG * s);
@@ -292,7 +301,7 @@ void block_pcg(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
     // first half: Q = S P, alpha, X and R, the stopping test; second half: Z = M R, beta, P = orth(Z + P beta)
     auto half1 = [&](hipStream_t q) {
       k_iter<<<1, 1, 0, q>>>(itd.p);
-      op_schur<T>(h, P, s, Q, s, s, false);                                   // Q = S P
+      ops.S(P, Q);                                                            // Q = S P
       gram<T, T>(sg, P, s, s, Q, s, s, sm.Delta, ss, 1.0, 0.0, work, q);      // Delta = P^T Q
       gram<T, T>(sg, P, s, s, R.p, s, s, sm.G1, ss, 1.0, 0.0, work, q);       // P^T R
       k_dims<<<pb, 256, 0, q>>>(np, s, sm.active, sm.rank, sm.dimA);
@@ -307,14 +316,14 @@ void block_pcg(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
       NS_LAUNCH_CHECK();
     };
     auto half2 = [&](hipStream_t q) {
-      op_gamma_solve<T>(h, R.p, s, Z.p, s, s);                                // Z = A_G^{-1} R
+      ops.M(R.p, Z.p);                                                        // Z = M R
       gram<T, T>(sg, Q, s, s, Z.p, s, s, sm.G2, ss, 1.0, 0.0, work, q);       // Q^T Z
       k_dims<<<pb, 256, 0, q>>>(np, s, sm.active, sm.rank, sm.dimA);
       NS_LAUNCH_CHECK();
       small_chol_apply(Batch{np, sm.dimA}, s, sm.Delta, ss, sm.G2, s, ss, sm.beta, s, ss, s, s, -1.0, h.sws,
                        q);  // beta
       ts_update<T>(sg, s, Z.p, s, 1.0, 1.0, P, s, s, sm.beta, s, ss, nullptr, 0, 0, nullptr, 0, 0, q);  // Z + P beta
-      orth<T>(h, sm, work, Z.p, P, Q, s, 0, itd.p);
+      orth<T>(h, sg, sm, work, Z.p, P, Q, s, 0, itd.p);
     };
     auto done = [&]() {  // breakdown flag and problems finished, from the device
       NS_HIP(hipMemcpyAsync(hc + 1, sm.flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -322,8 +331,8 @@ void block_pcg(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
       if (hc[1]) fail(BREAKDOWN, "block CG: P^T S P is not positive definite");
       return hc[0] >= np;
     };
-    op_gamma_solve<T>(h, R.p, s, Z.p, s, s);
-    orth<T>(h, sm, work, Z.p, P, Q, s, 0, itd.p);
+    ops.M(R.p, Z.p);
+    orth<T>(h, sg, sm, work, Z.p, P, Q, s, 0, itd.p);
     int it = 1;
     half1(st);  // the first iteration runs with plain launches: it also sizes every workspace the body uses
     bool fin = done();
@@ -332,9 +341,9 @@ void block_pcg(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
     // roles every iteration, are where the recording found them at every replay); iterations a replay runs
     // after every problem has finished change nothing (finished problems are frozen)
     const int mb = h.bcg_graph == 0 ? tuned("bcg_graph_iters", h.bf16 ? "bf16" : (sizeof(T) == 8 ? "f64" : "f32"),
-                                            h.nG, 2)
+                                            nG, 2)
                                     : h.bcg_graph;
-    const int m = mb <= 0 || kernel_timing_in_loops() ? 0 : 2 * ((mb + 1) / 2);
+    const int m = mb <= 0 || kernel_timing_in_loops(false) ? 0 : 2 * ((mb + 1) / 2);
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
     if (!fin && m > 0 && it + m <= h.max_inner) {
@@ -509,13 +518,15 @@ void gamma_rinv(Handle& h, const double* X, double* Out, int ncols) {
 template <class Rhs>
 void run_inner(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
   if (!h.prec_inner) {
-    block_pcg<double>(h, sm, rhs, D);
+    SchurOps<double> ops{h};
+    block_pcg<double>(h, sm, ops, rhs, D);
     return;
   }
   BF16Scope b16(h);
+  SchurOps<float> ops{h};
   if (h.bf16 && h.bf16_schur) {
     try {
-      block_pcg<float>(h, sm, rhs, D);
+      block_pcg<float>(h, sm, ops, rhs, D);
       return;
     } catch (const Error& e) {
       if (e.status != BREAKDOWN) throw;
@@ -524,7 +535,50 @@ void run_inner(Handle& h, SmallMats& sm, Rhs rhs, double* D) {
       h.bf16_schur = 0;
     }
   }
-  block_pcg<float>(h, sm, rhs, D);
+  block_pcg<float>(h, sm, ops, rhs, D);
+}
+
+// The operators of the inner system exactly as Algorithm alg:prec1 step 3 prints it: rows = padded interior rows
+// (zero on the padding), S = S_I = A_I - A_IGamma A_Gamma^{-1} A_GammaI (eq. SI), preconditioner A_I^{-1}.  A_I P
+// is the interior part of A [P; 0] (the original matrix times P with the interface rows zero).  FP64, one problem.
+struct FormAOps {
+  Handle& h;
+  DBuf<double> full, fullA, g1, g2, tI;
+  explicit FormAOps(Handle& hh) : h(hh) {
+    const int64_t s = h.s;
+    full.alloc(h.n * s);
+    fullA.alloc(h.n * s);
+    g1.alloc(h.nG * s);
+    g2.alloc(h.nG * s);
+    tI.alloc(h.L1.nrows_pad * s);
+    NS_HIP(hipMemsetAsync(full.p, 0, h.n * s * sizeof(double), h.stream));  // its interface rows stay zero
+  }
+  const Seg& seg() const { return h.segI.view; }
+  int64_t rows() const { return h.L1.nrows_pad; }
+  void S(const double* P, double* Q) {
+    hipStream_t st = h.stream;
+    const int s = h.s;
+    const int64_t nIp = h.L1.nrows_pad;
+    scatter_rows<double, double>(nIp, h.iperm, P, s, full.p, s, s, st);  // [P; 0] in the original order
+    csr_mult<double>(h.Aorig, full.p, s, fullA.p, s, s, st);              // A [P; 0]
+    gather_rows<double>(nIp, h.iperm, fullA.p, s, Q, s, s, st);           // A_I P (zero on the padding)
+    csr_mult<double>(h.AGI, P, s, g1.p, s, s, st);                        // A_GammaI P
+    op_gamma_solve<double>(h, g1.p, s, g2.p, s, s);                       // A_Gamma^{-1} A_GammaI P
+    csr_mult<double>(h.AIG, g2.p, s, tI.p, s, s, st);                     // A_IGamma (...)
+    axpby(nIp * s, -1.0, tI.p, 1.0, Q, st);                                // S_I P
+  }
+  void M(const double* R, double* Z) {
+    NS_HIP(hipMemcpyAsync(Z, R, h.L1.nrows_pad * h.s * sizeof(double), hipMemcpyDeviceToDevice, h.stream));
+    tile_solve<double>(h.L1, Z, h.s, h.s, h.trsm_cols, h.stream);        // A_I^{-1} R
+  }
+};
+
+// Block CG on S_I X = F (F, X: padded interior rows x s, FP64), preconditioned by A_I^{-1}.
+void inner_solve_forma(Handle& h, SmallMats& sm, const double* F, double* X) {
+  FormAOps ops(h);
+  const int64_t n = h.L1.nrows_pad * h.s;
+  auto rhs = [&](double* R) { NS_HIP(hipMemcpyAsync(R, F, n * sizeof(double), hipMemcpyDeviceToDevice, h.stream)); };
+  block_pcg<double>(h, sm, ops, rhs, X);
 }
 
 // Block CG on the shifted system with right-hand side F = W G (G: n_G x s, FP64) in the inner precision.
@@ -568,12 +622,16 @@ void lowrank_setup(Handle& h, SmallMats& sm, const double* omega, Mark mark) {
   const int s = h.s, k = h.k, np = h.nprob;
   const int64_t nG = h.nG, nIp = h.L1.nrows_pad;
   const bool m3 = h.variant == NS_VARIANT_M3, m1 = h.variant == NS_VARIANT_M1;
+  const bool forma = h.inner_form == NS_INNER_FORM_A;
   std::vector<int64_t> prow(np);
   for (int q = 0; q < np; ++q) prow[q] = h.h_goff[q + 1] - h.h_goff[q];
   const int64_t rows = m3 ? nIp : nG;  // rows of the sketch and of B G
-  if (m3) {
-    prow.assign(1, nIp);
-    h.segI.build({0, nIp}, st);
+  if (m3 || forma) h.segI.build({0, nIp}, st);
+  if (m3) prow.assign(1, nIp);
+  DBuf<double> FI, XI;  // form A: right-hand side and solution on the padded interior rows
+  if (forma && !m3) {
+    FI.alloc(nIp * s);
+    XI.alloc(nIp * s);
   }
   const Seg& sg = m3 ? h.segI.view : h.segG.view;
   DBuf<double> Gb, BGb, BGs, Db, Ds, F, work;
@@ -594,7 +652,13 @@ void lowrank_setup(Handle& h, SmallMats& sm, const double* omega, Mark mark) {
   h.it_inner.assign(np, 0);
   h.conv_inner.assign(np, 1);
   for (int it = 0; it <= h.power; ++it) {
-    if (m3) {
+    if (forma && m3) {
+      inner_solve_forma(h, sm, G, BG);                    // S_I^{-1} G, the literal inner system
+    } else if (forma) {
+      csr_mult<double>(h.AIG, G, s, FI.p, s, s, st);      // F = A_IGamma G
+      inner_solve_forma(h, sm, FI.p, XI.p);               // S_I X = F
+      csr_mult<double>(h.AGI, XI.p, s, BG, s, s, st);     // B G = A_GammaI X
+    } else if (m3) {
       // S_I^{-1} G = A_I^{-1} (G + A_IGamma D) with S_Gamma D = A_GammaI A_I^{-1} G (Sherman-Morrison-Woodbury)
       NS_HIP(hipMemcpyAsync(BG, G, rows * s * sizeof(double), hipMemcpyDeviceToDevice, st));
       tile_solve<double>(h.L1, BG, s, s, h.trsm_cols, st);
@@ -773,7 +837,7 @@ template <class Head, class Tail>
 void pcg_loop(Handle& h, int np, const PcgState& S, int maxit, int hc[2], Head head, Tail tail) {
   hipStream_t st = h.stream;
   int m = h.pcg_graph == 0 ? tuned("pcg_graph_iters", "f64", h.nG, np > 1 ? 4 : 1) : h.pcg_graph;
-  if (kernel_timing_in_loops()) m = 0;  // every launch timed
+  if (kernel_timing_in_loops(true)) m = 0;  // every launch timed
   head(st);
   read_back(h, hc, S.ndone, 2);
   if (hc[0] < np && hc[1] < maxit) tail(st);
@@ -1071,6 +1135,7 @@ Handle* new_handle(const ns_options* opt) {
   h->variant = opt->variant;
   h->power = opt->power_iters;
   h->outer = opt->outer;
+  h->inner_form = opt->inner_form;
   h->level2 = opt->level2;
   h->level2_k = opt->level2_k;
   h->level2_p = opt->level2_p;
@@ -1088,6 +1153,11 @@ void check_options(Handle* h) {
     fail(INVALID_ARG, "the full-system outer iteration needs the symmetric additive form (NS_APPLY_M2)");
   if (h->trsm_cols != 0 && h->trsm_cols != 16 && h->trsm_cols != 32 && h->trsm_cols != 64)
     fail(INVALID_ARG, "trsm_cols must be 0, 16, 32 or 64");
+  if (h->inner_form != NS_INNER_SHIFTED && h->inner_form != NS_INNER_FORM_A) fail(INVALID_ARG, "inner_form must be 0 or 1");
+  if (h->inner_form == NS_INNER_FORM_A) {
+    if (h->prec_inner || h->bf16) fail(INVALID_ARG, "the literal inner form runs with FP64 inner work only");
+    if (h->variant == NS_VARIANT_M1) fail(INVALID_ARG, "the literal inner form serves the variants M_2 and M_3");
+  }
   if (h->level2 != NS_LEVEL2_EXACT && h->level2 != NS_LEVEL2_NYSTROM) fail(INVALID_ARG, "level2 must be 0 or 1");
   if (h->level2 == NS_LEVEL2_NYSTROM) {
     if (h->prec_inner || h->bf16) fail(INVALID_ARG, "the recursive level runs with FP64 inner work only");
@@ -1439,6 +1509,7 @@ ns_status nystrom_schur_setup_batched(int32_t nprob, const int64_t* n, const int
       }
     h = new_handle(opt);
     StreamScope ss(h->stream);
+    if (h->inner_form != NS_INNER_SHIFTED) fail(INVALID_ARG, "the literal inner form applies to one problem (not a batch)");
     if (h->level2 != NS_LEVEL2_EXACT) fail(INVALID_ARG, "the recursive level applies to one problem (not a batch)");
     check_options(h);
     if (h->variant == NS_VARIANT_M3 && nprob > 1)

@@ -861,7 +861,8 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
   // algorithmic work: A and B read once (once in all when they are the same block), the products of the
   // output entries (the lower triangle and the diagonal when symmetric)
   const double rows = double(sg.rows);
-  KScope ks(KF_GRAM, st, rows * (double(ra) * sizeof(TA) + (sym ? 0.0 : double(rb) * sizeof(TB))),
+  KScope ks(ra > 16 && rb > 16 ? KF_GRAM : KF_GRAM_NARROW, st,
+            rows * (double(ra) * sizeof(TA) + (sym ? 0.0 : double(rb) * sizeof(TB))),
             sym ? rows * ra * (ra + 1.0) : 2.0 * rows * ra * rb);
   // wide FP64 blocks: one workgroup per chunk (FP32 blocks stay on the strip kernel, faster for them)
   if (sizeof(TA) == 8 && sizeof(TB) == 8 && ra >= 32 && rb >= 32 && ra <= GC_MAXC && rb <= GC_MAXC) {
@@ -890,7 +891,7 @@ void ts_update(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, doubl
   if (sg.rows == 0 || ncols == 0) return;
   // algorithmic work: X (and X2) read once, Out read (beta != 0) and written once, 2 rm ncols flops per row
   const double rows = double(sg.rows);
-  KScope ks(KF_BLOCK_UPDATE, st,
+  KScope ks(ncols > 16 ? KF_BLOCK_UPDATE : KF_BLOCK_UPDATE_NARROW, st,
             rows * sizeof(T) * (double(rm) + rm2 + ncols * (beta != 0.0 ? 2.0 : 1.0)),
             2.0 * rows * ncols * (double(rm) + rm2));
   ts_launch<T>(sg, ncols, Out, ldo, beta, gamma, X, ldx, rm, M, ldm, mstride, st);

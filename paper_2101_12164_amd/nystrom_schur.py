@@ -24,6 +24,7 @@ NS_SCHUR_AUTO, NS_SCHUR_TRIANGULAR, NS_SCHUR_LOCAL = 0, 1, 2
 NS_VARIANT_M2, NS_VARIANT_M1, NS_VARIANT_M3 = 0, 1, 2
 NS_OUTER_SCHUR, NS_OUTER_FULL = 0, 1
 NS_LEVEL2_EXACT, NS_LEVEL2_NYSTROM = 0, 1
+NS_INNER_SHIFTED, NS_INNER_FORM_A = 0, 1
 
 STATUS_NAMES = {
     0: "NS_OK",
@@ -71,7 +72,7 @@ KERNEL_FAMILIES = ["chol_update", "chol_panel", "trsm_interior_f64", "trsm_inter
                    "trsm_interface_f32", "schur_epi", "spmm", "local_schur_form", "local_schur_apply_f64",
                    "local_schur_apply_f32", "interface_inverse_f64", "interface_inverse_f32", "mlp_forward_bf16",
                    "mlp_backward_f32", "local_schur_apply_bf16", "interface_inverse_bf16", "gram", "block_update",
-                   "small_dense"]
+                   "small_dense", "gram_narrow", "block_update_narrow"]
 
 
 class NsOptions(ctypes.Structure):
@@ -100,6 +101,7 @@ class NsOptions(ctypes.Structure):
         ("level2_p", c_int32),
         ("level2_tol_inner", c_double),
         ("level2_omega", c_void_p),
+        ("inner_form", c_int32),
     ]
 
 
@@ -256,7 +258,8 @@ def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_in
                         orth_drop_rel=0.0, max_inner_iters=500, prec_inner=NS_FP64, apply_mode=NS_APPLY_M2,
                         trsm_cols=0, schur_mode=0, proposal=None, accept_tol=0.2, pcg_graph_iters=0,
                         variant=NS_VARIANT_M2, power_iters=0, outer=NS_OUTER_SCHUR, bcg_graph_iters=0,
-                        level2=NS_LEVEL2_EXACT, level2_k=0, level2_p=0, level2_tol_inner=0.0, level2_omega=None):
+                        level2=NS_LEVEL2_EXACT, level2_k=0, level2_p=0, level2_tol_inner=0.0, level2_omega=None,
+                        inner_form=NS_INNER_SHIFTED):
     """Returns (handle, info dict).  row_ptr int64, col_idx int32, val float64, part int32, omega float64
     (n_gamma x (k+p), row-major; n_interior x (k+p) for NS_VARIANT_M3), level2_omega float64 (n_junction x
     (level2_k + level2_p), junction nodes in interface order), all CUDA tensors."""
@@ -271,6 +274,7 @@ def nystrom_schur_setup(row_ptr, col_idx, val, part, *, k, p, omega=None, tol_in
     opt.level2_k, opt.level2_p = int(level2_k), int(level2_p)
     opt.level2_tol_inner = float(level2_tol_inner)
     opt.level2_omega = _dev(level2_omega, torch.float64, "level2_omega") if level2_omega is not None else None
+    opt.inner_form = int(inner_form)
     h = c_void_p()
     info = NsSetupInfo()
     st = lib.nystrom_schur_setup(n, nnz, _dev(row_ptr, torch.int64, "row_ptr"), _dev(col_idx, torch.int32, "col_idx"),
