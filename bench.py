@@ -427,8 +427,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only "
-                                   "(see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the solver runs on one GPU; sharding by subdomain across GPUs is not "
+                                   "implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     if args.workload == "c3":
