@@ -608,6 +608,77 @@ __global__ __launch_bounds__(256) void k_schur_epi_local(int64_t nrows, const in
   }
 }
 
+// The same epilogue for 17..256 columns: one row per wave, lane l owns the columns l + 64 g (g < CPL), and each
+// batch of four entries of both lists issues its index loads, then all 4 x CPL data loads of each list, before
+// the first sum (a handful of dependent memory round trips per row instead of a few per column group).  The
+// sums run in list order per column, as in k_schur_epi_local (same bits).
+template <class T, int CPL>
+__global__ __launch_bounds__(256) void k_schur_epi_wide(int64_t nrows, const int64_t* __restrict__ pG,
+                                                        const int32_t* __restrict__ cG, const T* __restrict__ vG,
+                                                        const T* __restrict__ X, int64_t ldx,
+                                                        const int64_t* __restrict__ pC, const int32_t* __restrict__ cC,
+                                                        const T* __restrict__ Yg, int64_t ldy_g, T* __restrict__ Y,
+                                                        int64_t ldy, int ncols, int w_only) {
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;  // uniform over the wave
+  const int lane = threadIdx.x & 63;
+  if (row >= nrows) return;
+  int cc[CPL];
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) cc[g] = min(lane + 64 * g, ncols - 1);
+  T a[CPL], w[CPL];
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) a[g] = w[g] = T(0);
+  const int64_t ga = w_only ? 0 : pG[row], gb = w_only ? 0 : pG[row + 1], ca = pC[row], cb = pC[row + 1];
+  for (int64_t e = ga, f = ca; e < gb || f < cb; e += 4, f += 4) {
+    const bool ha = e < gb, hc = f < cb;  // wave-uniform
+    int ja[4], jc[4];
+    T va[4], xa[4][CPL], xc[4][CPL];
+    if (ha) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t ek = e + k < gb ? e + k : e;
+        ja[k] = cG[ek];
+        va[k] = vG[ek];
+      }
+    }
+    if (hc) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) jc[k] = cC[f + k < cb ? f + k : f];
+    }
+    if (ha) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int g = 0; g < CPL; ++g) xa[k][g] = X[int64_t(ja[k]) * ldx + cc[g]];
+    }
+    if (hc) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int g = 0; g < CPL; ++g) xc[k][g] = Yg[int64_t(jc[k]) * ldy_g + cc[g]];
+    }
+    if (ha) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (e + k < gb)
+#pragma unroll
+          for (int g = 0; g < CPL; ++g) a[g] += va[k] * xa[k][g];
+    }
+    if (hc) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (f + k < cb)
+#pragma unroll
+          for (int g = 0; g < CPL; ++g) w[g] += xc[k][g];
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) {
+    const int c = lane + 64 * g;
+    if (c < ncols) Y[row * ldy + c] = w_only ? w[g] : a[g] - w[g];
+  }
+}
+
 template <class T, int TPR>
 __global__ __launch_bounds__(256) void k_gather_ls(int64_t nrows, const int32_t* __restrict__ src,
                                                    const T* __restrict__ R, int64_t ldr, T* __restrict__ Out,
@@ -1164,9 +1235,24 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
     vG = h.AGG.val64.p;
   else
     vG = h.AGG.val32.p;
-  NS_TPR_DISPATCH_LS(ncols, (k_schur_epi_local<T, TPR><<<unsigned((h.nG * TPR + 255) / 256), 256, 0, st>>>(
-                                 h.nG, h.AGG.ptr, h.AGG.col, vG, X, ldx, ls.contrib.ptr, ls.contrib.col, Yg, ncols,
-                                 Y, ldy, ncols, w_only ? 1 : 0)));
+  if (ncols > 16 && ncols <= 256) {
+    auto wide = [&](auto cpl) {
+      constexpr int CPL = decltype(cpl)::value;
+      k_schur_epi_wide<T, CPL><<<unsigned((h.nG * 64 + 255) / 256), 256, 0, st>>>(
+          h.nG, h.AGG.ptr, h.AGG.col, vG, X, ldx, ls.contrib.ptr, ls.contrib.col, Yg, ncols, Y, ldy, ncols,
+          w_only ? 1 : 0);
+    };
+    switch ((ncols + 63) / 64) {
+      case 1: wide(std::integral_constant<int, 1>()); break;
+      case 2: wide(std::integral_constant<int, 2>()); break;
+      case 3: wide(std::integral_constant<int, 3>()); break;
+      default: wide(std::integral_constant<int, 4>()); break;
+    }
+  } else {
+    NS_TPR_DISPATCH_LS(ncols, (k_schur_epi_local<T, TPR><<<unsigned((h.nG * TPR + 255) / 256), 256, 0, st>>>(
+                                   h.nG, h.AGG.ptr, h.AGG.col, vG, X, ldx, ls.contrib.ptr, ls.contrib.col, Yg,
+                                   ncols, Y, ldy, ncols, w_only ? 1 : 0)));
+  }
   NS_LAUNCH_CHECK();
 #undef NS_TPR_DISPATCH_LS
 }

@@ -65,6 +65,59 @@ __global__ __launch_bounds__(256) void k_gather_sub(int64_t nrows, const int32_t
   }
 }
 
+// The same for 17..256 columns: one row per wave, lane l owns the columns l + 64 g (g < CPL); the row of R and
+// each batch of four CSR entries issue all their loads before the first use.  Same sums in the same order.
+template <class T, int CPL>
+__global__ __launch_bounds__(256) void k_gather_sub_wide(int64_t nrows, const int32_t* __restrict__ src,
+                                                         const T* __restrict__ R, int64_t ldr,
+                                                         const int64_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ col, const T* __restrict__ val,
+                                                         const T* __restrict__ X, int64_t ldx, T* __restrict__ Out,
+                                                         int64_t ldo, int ncols) {
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;  // uniform over the wave
+  const int lane = threadIdx.x & 63;
+  if (row >= nrows) return;
+  int cc[CPL];
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) cc[g] = min(lane + 64 * g, ncols - 1);
+  const int s = src ? src[row] : int(row);
+  T acc[CPL];
+  if (s >= 0) {
+#pragma unroll
+    for (int g = 0; g < CPL; ++g) acc[g] = R[int64_t(s) * ldr + cc[g]];
+  } else {
+#pragma unroll
+    for (int g = 0; g < CPL; ++g) acc[g] = T(0);
+  }
+  if (ptr) {
+    const int64_t e0 = ptr[row], e1 = ptr[row + 1];
+    for (int64_t e = e0; e < e1; e += 4) {
+      int j[4];
+      T v[4], x[4][CPL];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t ek = e + k < e1 ? e + k : e;
+        j[k] = col[ek];
+        v[k] = val[ek];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int g = 0; g < CPL; ++g) x[k][g] = X[int64_t(j[k]) * ldx + cc[g]];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (e + k < e1)
+#pragma unroll
+          for (int g = 0; g < CPL; ++g) acc[g] -= v[k] * x[k][g];
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) {
+    const int c = lane + 64 * g;
+    if (c < ncols) Out[row * ldo + c] = acc[g];
+  }
+}
+
 // Out[dst[r]] = B[r] for dst[r] >= 0
 template <class T, class U, int TPR>
 __global__ __launch_bounds__(256) void k_scatter(int64_t nrows, const int32_t* __restrict__ dst,
@@ -144,8 +197,22 @@ void gather_sub(int64_t nrows, const int32_t* src, const T* R, int64_t ldr, cons
   const int64_t* p = A && A->nnz ? A->ptr.p : nullptr;
   const int32_t* c = A ? A->col.p : nullptr;
   const T* v = A ? csr_vals<T>(*A) : nullptr;
-  NS_TPR_DISPATCH(ncols, (k_gather_sub<T, TPR><<<grid_rows<TPR>(nrows), 256, 0, st>>>(nrows, src, R, ldr, p, c, v,
-                                                                                          X, ldx, Out, ldo, ncols)));
+  if (ncols > 16 && ncols <= 256) {
+    auto wide = [&](auto cpl) {
+      constexpr int CPL = decltype(cpl)::value;
+      k_gather_sub_wide<T, CPL><<<grid_rows<64>(nrows), 256, 0, st>>>(nrows, src, R, ldr, p, c, v, X, ldx, Out, ldo,
+                                                                      ncols);
+    };
+    switch ((ncols + 63) / 64) {
+      case 1: wide(std::integral_constant<int, 1>()); break;
+      case 2: wide(std::integral_constant<int, 2>()); break;
+      case 3: wide(std::integral_constant<int, 3>()); break;
+      default: wide(std::integral_constant<int, 4>()); break;
+    }
+  } else {
+    NS_TPR_DISPATCH(ncols, (k_gather_sub<T, TPR><<<grid_rows<TPR>(nrows), 256, 0, st>>>(
+                                nrows, src, R, ldr, p, c, v, X, ldx, Out, ldo, ncols)));
+  }
   NS_LAUNCH_CHECK();
 }
 

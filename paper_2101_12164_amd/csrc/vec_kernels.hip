@@ -9,7 +9,7 @@
 namespace ns {
 namespace {
 
-constexpr int CHUNK_MAX = 240;   // reduction chunks per segment (at most)
+constexpr int CHUNK_MAX = 256;   // reduction chunks per segment (at most): one per compute unit
 constexpr int CHUNK_ROWS = 128;  // target rows per chunk
 
 // index p of the segment whose range [pre[p], pre[p + 1]) holds b
@@ -230,18 +230,19 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
 
 // G_p[o] = alpha * (sum of segment p's chunk partials of output o) + beta * G_p[o].  TX outputs per block;
 // the TY = 1024 / TX threads of an output take the chunks c = ty, ty + TY, ... and a fixed tree combines them.
+// With split > 1 every chunk c left split consecutive partials (chunk c's rows in split parts).
 template <int TX>
 __global__ __launch_bounds__(1024) void k_seg_final(Seg sg, int nout, const double* __restrict__ part,
                                                     double* __restrict__ G, int64_t gstride, double alpha,
                                                     double beta, const double* __restrict__ rscale = nullptr,
-                                                    int64_t rsstride = 0, int rb = 1) {
+                                                    int64_t rsstride = 0, int rb = 1, int split = 1) {
   constexpr int TY = 1024 / TX;
   __shared__ double red[1024];
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   const int o = blockIdx.x * TX + tx;
   const int p = blockIdx.y;
   if (sg.skip && sg.skip[p]) return;
-  const int c0 = sg.coff[p], nch = sg.coff[p + 1] - c0;
+  const int c0 = sg.coff[p] * split, nch = (sg.coff[p + 1] - sg.coff[p]) * split;
   double s = 0.0;
   if (o < nout)
     for (int c = ty; c < nch; c += TY) s += part[int64_t(c0 + c) * nout + o];
@@ -259,13 +260,13 @@ __global__ __launch_bounds__(1024) void k_seg_final(Seg sg, int nout, const doub
 }
 
 void seg_final(const Seg& sg, int nout, const double* part, double* G, int64_t gstride, double alpha, double beta,
-               hipStream_t st, const double* rscale = nullptr, int64_t rsstride = 0, int rb = 1) {
+               hipStream_t st, const double* rscale = nullptr, int64_t rsstride = 0, int rb = 1, int split = 1) {
   if (nout >= 16) {
     k_seg_final<64><<<dim3((nout + 63) / 64, sg.n), 1024, 0, st>>>(sg, nout, part, G, gstride, alpha, beta, rscale,
-                                                                  rsstride, rb);
+                                                                  rsstride, rb, split);
   } else {
     k_seg_final<1><<<dim3(nout, sg.n), 1024, 0, st>>>(sg, nout, part, G, gstride, alpha, beta, rscale, rsstride,
-                                                     rb);
+                                                     rb, split);
   }
   NS_LAUNCH_CHECK();
 }
@@ -772,26 +773,53 @@ __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, doubl
     y[i] = a * x[i] + (b != 0.0 ? b * y[i] : 0.0);
 }
 
-// Column sums of squares of the chunk's rows: 64 columns x 4 row lanes per pass.
+// Column sums of squares: workgroup b takes part b % split of chunk b / split (contiguous rows).  Lane l of a
+// wave owns the columns l, l + 64, ... of a group of CG column blocks (one pass over the rows per group); wave w
+// takes the rows w, w + 4, ... of the part, CQ_U of them per batch with every load of the batch issued (from
+// clamped in-bounds addresses) before the first product, and the four waves' sums are combined in a fixed
+// order.  Partial b * ncols + c.
+constexpr int CQ_U = 4, CQ_CG = 3;
 template <class T>
 __global__ __launch_bounds__(256) void k_colsq_partial(Seg sg, int ncols, const T* __restrict__ X, int64_t ldx,
-                                                       double* __restrict__ part) {
-  __shared__ double red[256];
-  int64_t r0, r1;
-  chunk_rows(sg, blockIdx.x, r0, r1);
-  for (int c0 = 0; c0 < ncols; c0 += 64) {
-    const int c = c0 + (threadIdx.x & 63);
-    double s = 0.0;
-    if (c < ncols)
-      for (int64_t r = r0 + (threadIdx.x >> 6); r < r1; r += 4) {
-        const double v = double(X[r * ldx + c]);
-        s += v * v;
+                                                       double* __restrict__ part, int split) {
+  __shared__ double red[3][CQ_CG][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t c0, c1;
+  chunk_rows(sg, blockIdx.x / split, c0, c1);
+  const int q = blockIdx.x % split;
+  const int64_t per = (c1 - c0 + split - 1) / split;
+  const int64_t r0 = c0 + q * per < c1 ? c0 + q * per : c1, r1 = r0 + per < c1 ? r0 + per : c1;
+  for (int g0 = 0; g0 < ncols; g0 += 64 * CQ_CG) {
+    int col[CQ_CG];
+#pragma unroll
+    for (int g = 0; g < CQ_CG; ++g) col[g] = min(g0 + 64 * g + lane, ncols - 1);
+    double s[CQ_CG];
+#pragma unroll
+    for (int g = 0; g < CQ_CG; ++g) s[g] = 0.0;
+    for (int64_t r = r0 + w; r < r1; r += 4 * CQ_U) {
+      double v[CQ_U][CQ_CG];
+#pragma unroll
+      for (int u = 0; u < CQ_U; ++u) {
+        const int64_t rr = r + 4 * u < r1 ? r + 4 * u : r;
+#pragma unroll
+        for (int g = 0; g < CQ_CG; ++g) v[u][g] = double(X[rr * ldx + col[g]]);
       }
-    red[threadIdx.x] = s;
+#pragma unroll
+      for (int u = 0; u < CQ_U; ++u)
+#pragma unroll
+        for (int g = 0; g < CQ_CG; ++g) s[g] += r + 4 * u < r1 ? v[u][g] * v[u][g] : 0.0;
+    }
+    if (w > 0)
+#pragma unroll
+      for (int g = 0; g < CQ_CG; ++g) red[w - 1][g][lane] = s[g];
     __syncthreads();
-    if (threadIdx.x < 64 && c < ncols)
-      part[int64_t(blockIdx.x) * ncols + c] =
-          (red[threadIdx.x] + red[threadIdx.x + 64]) + (red[threadIdx.x + 128] + red[threadIdx.x + 192]);
+    if (w == 0)
+#pragma unroll
+      for (int g = 0; g < CQ_CG; ++g) {
+        const int c = g0 + 64 * g + lane;
+        if (c < ncols)
+          part[int64_t(blockIdx.x) * ncols + c] = ((s[g] + red[0][g][lane]) + red[1][g][lane]) + red[2][g][lane];
+      }
     __syncthreads();
   }
 }
@@ -909,9 +937,11 @@ void convert_block(int64_t n, int ncols, const T* X, int64_t ldx, U* Y, int64_t 
 template <class T>
 void col_sumsq(const Seg& sg, int ncols, const T* X, int64_t ldx, double* out, double* work, hipStream_t st) {
   if (ncols == 0 || sg.n == 0) return;
-  k_colsq_partial<T><<<sg.nchunk, 256, 0, st>>>(sg, ncols, X, ldx, work);
+  // the caller's workspace holds nchunk * ncols * ncols partials: up to four parts per chunk fit
+  const int split = ncols < 4 ? ncols : 4;
+  k_colsq_partial<T><<<unsigned(sg.nchunk * split), 256, 0, st>>>(sg, ncols, X, ldx, work, split);
   NS_LAUNCH_CHECK();
-  seg_final(sg, ncols, work, out, ncols, 1.0, 0.0, st);
+  seg_final(sg, ncols, work, out, ncols, 1.0, 0.0, st, nullptr, 0, 1, split);
 }
 
 void dot(const Seg& sg, const double* x, const double* y, double* out, int64_t ostride, double* work,
