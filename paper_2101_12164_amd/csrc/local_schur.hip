@@ -373,15 +373,17 @@ __global__ __launch_bounds__(256) void k_gemm_tn(GemmBatch g, const T* __restric
 // single dense junction block applied to up to 80 columns): one workgroup per
 // 16-row strip of C, its eight waves taking every eighth k-step of the
 // reduction with the operands read straight from the cache, the eight partial
-// strips summed in LDS in a fixed order.  NQ 16-column MFMA tiles per strip.
+// strips summed in LDS in a fixed order.  NQ 16-column MFMA tiles per strip; with ncg > 1 column groups of
+// 16 NQ columns each take a workgroup of their own.
 constexpr int KSPLIT_WAVES = 8;
 template <class T, int NQ>
 __global__ __launch_bounds__(64 * KSPLIT_WAVES) void k_gemm_tn_ksplit(GemmBatch g, const T* __restrict__ A,
                                                                       const T* __restrict__ B, T* __restrict__ C,
-                                                                      int N, int strips, int nb) {
+                                                                      int N, int strips, int nb, int ncg = 1) {
   using acc_t = typename MFL<T>::acc_t;
   __shared__ T red[KSPLIT_WAVES][NQ * 4][64];
-  const int j = int(blockIdx.x) / strips, tm = int(blockIdx.x) % strips;
+  const int n0 = 16 * NQ * (int(blockIdx.x) % ncg), wg = int(blockIdx.x) / ncg;
+  const int j = wg / strips, tm = wg % strips;
   if (j >= nb) return;
   const int M = g.M[j], K = g.K[j];
   const int m0 = 16 * tm;
@@ -410,14 +412,14 @@ __global__ __launch_bounds__(64 * KSPLIT_WAVES) void k_gemm_tn_ksplit(GemmBatch 
       const int64_t kc = min(k, K - 1);
       av[u] = Aj[kc * lda + mc];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) bv[u][q] = Bj[kc * ldb + min(16 * q + rl, N - 1)];
+      for (int q = 0; q < NQ; ++q) bv[u][q] = Bj[kc * ldb + min(n0 + 16 * q + rl, N - 1)];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const T a = (kin[u] && mok) ? av[u] : T(0);
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        acc[q] = MFL<T>::mma(a, (kin[u] && 16 * q + rl < N) ? bv[u][q] : T(0), acc[q]);
+        acc[q] = MFL<T>::mma(a, (kin[u] && n0 + 16 * q + rl < N) ? bv[u][q] : T(0), acc[q]);
     }
   }
 #pragma unroll
@@ -432,7 +434,7 @@ __global__ __launch_bounds__(64 * KSPLIT_WAVES) void k_gemm_tn_ksplit(GemmBatch 
     T sum = red[0][qv][ln];
 #pragma unroll
     for (int x = 1; x < KSPLIT_WAVES; ++x) sum += red[x][qv][ln];
-    const int r = m0 + MFL<T>::row(ln >> 4, qv & 3), c = 16 * (qv >> 2) + (ln & 15);
+    const int r = m0 + MFL<T>::row(ln >> 4, qv & 3), c = n0 + 16 * (qv >> 2) + (ln & 15);
     if (r < M && c < N) Cj[int64_t(r) * ldc + c] = sum;
   }
 }
@@ -690,6 +692,30 @@ __global__ __launch_bounds__(256) void k_gather_ls(int64_t nrows, const int32_t*
   for (int c = lane; c < ncols; c += TPR) Out[row * ldo + c] = s >= 0 ? R[int64_t(s) * ldr + c] : T(0);
 }
 
+// The same for 17..256 columns: one row per wave, the CPL loads of a lane issued together.
+template <class T, int CPL>
+__global__ __launch_bounds__(256) void k_gather_ls_wide(int64_t nrows, const int32_t* __restrict__ src,
+                                                        const T* __restrict__ R, int64_t ldr, T* __restrict__ Out,
+                                                        int64_t ldo, int ncols) {
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;  // uniform over the wave
+  const int lane = threadIdx.x & 63;
+  if (row >= nrows) return;
+  const int s = src[row];
+  T v[CPL];
+  if (s >= 0) {
+#pragma unroll
+    for (int g = 0; g < CPL; ++g) v[g] = R[int64_t(s) * ldr + min(lane + 64 * g, ncols - 1)];
+  } else {
+#pragma unroll
+    for (int g = 0; g < CPL; ++g) v[g] = T(0);
+  }
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) {
+    const int c = lane + 64 * g;
+    if (c < ncols) Out[row * ldo + c] = v[g];
+  }
+}
+
 // C_j = S_j B_j with S_j symmetric and stored as BF16 (so S_j^T = S_j: rows of S_j are read with their K
 // entries contiguous), B_j FP32, C_j FP32: 16x16x32 BF16 MFMA with FP32 accumulation.  A workgroup computes a
 // 64 x 64 tile of C_j (four waves in 2 x 2, each 32 x 32 = 2 x 2 MFMA tiles); K is staged by 64 through LDS,
@@ -802,6 +828,10 @@ __global__ void k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y,
     y[i] = f32_to_bf16(x[i]);
 }
 
+// Output tiles of 80 columns instead of 64 where they pad the columns less (160 columns: two tiles of 80 instead
+// of three of 64, the last half empty).  Either width sums each output in the same order (same bits).
+inline bool cols80(int N) { return N > 80 && 80 * ((N + 79) / 80) < 64 * ((N + 63) / 64); }
+
 template <class T>
 void launch_gemm(const LocalSchur& ls, const T* A, const T* B, T* C, int N, hipStream_t st, bool sym,
                  const GemmBatch& g, int maxM, int nblk = -1) {
@@ -813,6 +843,10 @@ void launch_gemm(const LocalSchur& ls, const T* A, const T* B, T* C, int N, hipS
     k_gemm_tn<T, 16><<<gemm_grid(1, tilesM, nblk, g.plen), 256, 0, st>>>(g, A, B, C, N, 0, 1, tilesM, nblk);
   } else if (N > 64 && N <= 80 && !sym && tuned("ls_gemm_cols", sizeof(T) == 8 ? "f64" : "f32", N, 80) == 80) {
     k_gemm_tn<T, 80><<<gemm_grid(1, tilesM, nblk, g.plen), 256, 0, st>>>(g, A, B, C, N, 0, 1, tilesM, nblk);
+  } else if (!sym && !g.kstart && cols80(N)) {  // first-nonzero tile starts are kept per 64 columns
+    const int tilesN = (N + 79) / 80;
+    k_gemm_tn<T, 80><<<gemm_grid(tilesN, tilesM, nblk, g.plen), 256, 0, st>>>(g, A, B, C, N, 0, tilesN, tilesM,
+                                                                               nblk);
   } else {
     const int tilesN = sym ? tilesM : (N + 63) / 64;
     k_gemm_tn<T, 64><<<gemm_grid(tilesN, tilesM, nblk, g.plen), 256, 0, st>>>(g, A, B, C, N, sym ? 1 : 0, tilesN,
@@ -856,14 +890,16 @@ void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStr
   for (int b = 0; b < lv.nblk; ++b) sq += double(lv.h_nb[b]) * lv.h_nb[b];
   KScope ks(sizeof(T) == 8 ? KF_INV64 : KF_INV32, st, (sq + 2.0 * lv.alg_rows * ncols) * sizeof(T), 2.0 * sq * ncols);
   const int tilesM = lv.max_nt;
-  if (ncols <= 80 && lv.nblk * tilesM < 128) {  // few output tiles: split the reduction over eight waves
-    const int strips = 4 * tilesM, grid = strips * lv.nblk;
-    switch ((ncols + 15) / 16) {
+  if (ncols <= 160 && lv.nblk * tilesM < 128) {  // few output tiles: split the reduction over eight waves
+    const int strips = 4 * tilesM, ncg = (ncols + 79) / 80, grid = strips * lv.nblk * ncg;
+    switch (ncg > 1 ? 5 : (ncols + 15) / 16) {
       case 1: k_gemm_tn_ksplit<T, 1><<<grid, 64 * KSPLIT_WAVES, 0, st>>>(g, A, B, C, ncols, strips, lv.nblk); break;
       case 2: k_gemm_tn_ksplit<T, 2><<<grid, 64 * KSPLIT_WAVES, 0, st>>>(g, A, B, C, ncols, strips, lv.nblk); break;
       case 3: k_gemm_tn_ksplit<T, 3><<<grid, 64 * KSPLIT_WAVES, 0, st>>>(g, A, B, C, ncols, strips, lv.nblk); break;
       case 4: k_gemm_tn_ksplit<T, 4><<<grid, 64 * KSPLIT_WAVES, 0, st>>>(g, A, B, C, ncols, strips, lv.nblk); break;
-      default: k_gemm_tn_ksplit<T, 5><<<grid, 64 * KSPLIT_WAVES, 0, st>>>(g, A, B, C, ncols, strips, lv.nblk); break;
+      default:
+        k_gemm_tn_ksplit<T, 5><<<grid, 64 * KSPLIT_WAVES, 0, st>>>(g, A, B, C, ncols, strips, lv.nblk, ncg);
+        break;
     }
   } else if (ncols <= 16) {
     k_gemm_tn<T, 16><<<gemm_grid(1, tilesM, lv.nblk), 256, 0, st>>>(g, A, B, C, ncols, 0, 1, tilesM, lv.nblk);
@@ -1210,8 +1246,22 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
     KScope ks(KF_LS_APPLY64, st, ls.sym.alg_bytes + 2.0 * np * sizeof(T), ls.sym.alg_flops);
     sym_gemv(ls.sym, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(Yg), st, ls.glist.p);
   } else {
-    NS_TPR_DISPATCH_LS(ncols, (k_gather_ls<T, TPR><<<unsigned((np * TPR + 255) / 256), 256, 0, st>>>(
-                                   np, ls.glist, X, ldx, Xg, ncols, ncols)));
+    if (ncols > 16 && ncols <= 256) {
+      auto wide = [&](auto cpl) {
+        constexpr int CPL = decltype(cpl)::value;
+        k_gather_ls_wide<T, CPL><<<unsigned((np * 64 + 255) / 256), 256, 0, st>>>(np, ls.glist, X, ldx, Xg, ncols,
+                                                                                  ncols);
+      };
+      switch ((ncols + 63) / 64) {
+        case 1: wide(std::integral_constant<int, 1>()); break;
+        case 2: wide(std::integral_constant<int, 2>()); break;
+        case 3: wide(std::integral_constant<int, 3>()); break;
+        default: wide(std::integral_constant<int, 4>()); break;
+      }
+    } else {
+      NS_TPR_DISPATCH_LS(ncols, (k_gather_ls<T, TPR><<<unsigned((np * TPR + 255) / 256), 256, 0, st>>>(
+                                     np, ls.glist, X, ldx, Xg, ncols, ncols)));
+    }
     NS_LAUNCH_CHECK();
     // X_j / Y_j: stacked rows goff[j], leading dimension ncols
     GemmBatch g{nullptr, 0, ls.M, ls.Kg, ls.soff, ls.sld, ls.goff, ncols, ncols, ls.goff, ncols, nullptr, ncols,

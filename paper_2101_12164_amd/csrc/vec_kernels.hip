@@ -126,6 +126,53 @@ __global__ __launch_bounds__(256) void k_gram_strip(Seg sg, const TA* __restrict
 // of the 8 waves, and the chunk's rows pass through LDS GC_K at a time, double-buffered with the next stage's
 // loads in flight during the products, so each chunk of A and B is read from memory once (the strip kernel
 // above reads B once per output strip).  Each tile sums the chunk's rows in row order.
+// A^T b for one column b (FP64): part[chunk][a].  1024-thread workgroups, one per reduction chunk; lane l of a
+// wave owns the columns l + 64 g (g < CPL) of A and wave w the rows w, w + 16, ... of the chunk, GV_U of them
+// per batch with all their loads issued (from clamped in-bounds rows) before the first product; the sixteen
+// waves' sums are added in a fixed order.
+constexpr int GV_NT = 1024, GV_U = 4;
+template <int CPL>
+__global__ __launch_bounds__(GV_NT) void k_gram_col(Seg sg, const double* __restrict__ A, int64_t lda, int ra,
+                                                    const double* __restrict__ B, int64_t ldb,
+                                                    double* __restrict__ part) {
+  __shared__ double red[GV_NT / 64][64 * CPL];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t r0, r1;
+  const int pseg = chunk_rows(sg, blockIdx.x, r0, r1);
+  if (sg.skip && sg.skip[pseg]) return;
+  int cc[CPL];
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) cc[g] = min(lane + 64 * g, ra - 1);
+  double acc[CPL];
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) acc[g] = 0.0;
+  for (int64_t r = r0 + w; r < r1; r += (GV_NT / 64) * GV_U) {
+    double av[GV_U][CPL], bv[GV_U];
+#pragma unroll
+    for (int u = 0; u < GV_U; ++u) {
+      const int64_t rr = r + (GV_NT / 64) * u < r1 ? r + (GV_NT / 64) * u : r;
+      bv[u] = B[rr * ldb];
+#pragma unroll
+      for (int g = 0; g < CPL; ++g) av[u][g] = A[rr * lda + cc[g]];
+    }
+#pragma unroll
+    for (int u = 0; u < GV_U; ++u)
+      if (r + (GV_NT / 64) * u < r1)  // uniform over the wave
+#pragma unroll
+        for (int g = 0; g < CPL; ++g) acc[g] += av[u][g] * bv[u];
+  }
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) red[w][64 * g + lane] = acc[g];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * CPL; e += GV_NT) {
+    if (e >= ra) continue;
+    double sum = red[0][e];
+#pragma unroll
+    for (int x = 1; x < GV_NT / 64; ++x) sum += red[x][e];
+    part[int64_t(blockIdx.x) * ra + e] = sum;
+  }
+}
+
 constexpr int GC_MAXC = 160;
 constexpr int GC_K = 16;
 constexpr int GC_LD = GC_MAXC + 4;  // LDS row stride (bank spread between the four rows of a k-step)
@@ -565,6 +612,58 @@ __global__ __launch_bounds__(TB_NT) void k_ts_big(int64_t r0, int64_t rend, cons
       }
 }
 
+// One output column, FP64: Out[r] = beta Out[r] + gamma sum_m X[r, m] M_p[m] for K <= 16 KPL.  A workgroup
+// takes a 64-row tile (never straddling two segments); sixteen lanes share a row, lane l holding the columns
+// l + 16 i of it (a 128-byte run per i over the sixteen lanes), and all 4 KPL row loads of a lane are issued
+// before the products; the sixteen partial sums meet in a butterfly.
+template <int KPL>
+__global__ __launch_bounds__(256) void k_ts_gemv(Seg sg, double* __restrict__ Out, int64_t ldo, double beta,
+                                                 double gamma, const double* __restrict__ X, int64_t ldx, int K,
+                                                 const double* __restrict__ M, int64_t ldm, int64_t mstride) {
+  const int p = seg_of(sg.toff, sg.n, blockIdx.x);
+  const int64_t rbase = sg.off[p] + int64_t(blockIdx.x - sg.toff[p]) * 64, rend = sg.off[p + 1];
+  const int l16 = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  if (sg.skip && sg.skip[p]) {  // Out = X on this tile's rows (a skipped segment)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t r = rbase + 16 * u + grp;
+      if (l16 == 0 && r < rend) Out[r * ldo] = X[r * ldx];
+    }
+    return;
+  }
+  const double* Mp = M + int64_t(p) * mstride;
+  double mv[KPL];
+#pragma unroll
+  for (int i = 0; i < KPL; ++i) {
+    const int k = l16 + 16 * i;
+    const double m = Mp[int64_t(min(k, K - 1)) * ldm];
+    mv[i] = k < K ? m : 0.0;  // the clamped duplicate columns below meet a zero
+  }
+  double xv[4][KPL];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = rbase + 16 * u + grp, rr = r < rend ? r : rbase;
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) xv[u][i] = X[rr * ldx + min(l16 + 16 * i, K - 1)];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) s += xv[u][i] * mv[i];
+    s += __shfl_xor(s, 8, 16);
+    s += __shfl_xor(s, 4, 16);
+    s += __shfl_xor(s, 2, 16);
+    s += __shfl_xor(s, 1, 16);
+    const int64_t r = rbase + 16 * u + grp;
+    if (l16 == 0 && r < rend) {
+      double y = gamma * s;
+      if (beta != 0.0) y += beta * Out[r * ldo];
+      Out[r * ldo] = y;
+    }
+  }
+}
+
 template <class T>
 void ts_launch(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, double gamma, const T* X, int64_t ldx,
                int K, const double* M, int64_t ldm, int64_t mstride, hipStream_t st) {
@@ -579,6 +678,24 @@ void ts_launch(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, doubl
     k_ts_wide<T, N><<<unsigned(sg.ntile), 256, 0, st>>>(sg, ncols, Out, ldo, beta, gamma, X, ldx, K, M, ldm, mstride);
   };
   if constexpr (sizeof(T) == 8) {
+    if (ncols == 1 && K >= 16 && K <= 256) {  // one column (the deflation product Z c of the outer iteration)
+      auto gemv = [&](auto kpl) {
+        constexpr int KPL = decltype(kpl)::value;
+        k_ts_gemv<KPL><<<unsigned(sg.ntile), 256, 0, st>>>(sg, Out, ldo, beta, gamma, X, ldx, K, M, ldm, mstride);
+      };
+      switch ((K + 31) / 32) {
+        case 1: gemv(std::integral_constant<int, 2>()); break;
+        case 2: gemv(std::integral_constant<int, 4>()); break;
+        case 3: gemv(std::integral_constant<int, 6>()); break;
+        case 4: gemv(std::integral_constant<int, 8>()); break;
+        case 5: gemv(std::integral_constant<int, 10>()); break;
+        case 6: gemv(std::integral_constant<int, 12>()); break;
+        case 7: gemv(std::integral_constant<int, 14>()); break;
+        default: gemv(std::integral_constant<int, 16>()); break;
+      }
+      NS_LAUNCH_CHECK();
+      return;
+    }
     if (sg.n == 1 && tiles > 5 && tiles <= 10 && sg.rows > sg.first) {  // one problem's wide FP64 block
       auto big = [&](auto nti) {
         constexpr int N = decltype(nti)::value;
@@ -892,6 +1009,25 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
   KScope ks(ra > 16 && rb > 16 ? KF_GRAM : KF_GRAM_NARROW, st,
             rows * (double(ra) * sizeof(TA) + (sym ? 0.0 : double(rb) * sizeof(TB))),
             sym ? rows * ra * (ra + 1.0) : 2.0 * rows * ra * rb);
+  // one FP64 column against a block of 16..256 columns (the deflation products Z^T r of the outer iteration)
+  if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8) {
+    if (rb == 1 && !sym && ra >= 16 && ra <= 256) {
+      auto col = [&](auto cpl) {
+        constexpr int CPL = decltype(cpl)::value;
+        k_gram_col<CPL><<<unsigned(sg.nchunk), GV_NT, 0, st>>>(sg, reinterpret_cast<const double*>(A), lda, ra,
+                                                                reinterpret_cast<const double*>(B), ldb, work);
+      };
+      switch ((ra + 63) / 64) {
+        case 1: col(std::integral_constant<int, 1>()); break;
+        case 2: col(std::integral_constant<int, 2>()); break;
+        case 3: col(std::integral_constant<int, 3>()); break;
+        default: col(std::integral_constant<int, 4>()); break;
+      }
+      NS_LAUNCH_CHECK();
+      seg_final(sg, nout, work, G, gstride, alpha, beta, st, rscale, rsstride, rb);
+      return;
+    }
+  }
   // wide FP64 blocks: one workgroup per chunk (FP32 blocks stay on the strip kernel, faster for them)
   if (sizeof(TA) == 8 && sizeof(TB) == 8 && ra >= 32 && rb >= 32 && ra <= GC_MAXC && rb <= GC_MAXC) {
     k_gram_chunk<TA, TB><<<unsigned(sg.nchunk), GC_NT, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym);
