@@ -416,7 +416,10 @@ void nystrom_schur_kernel_timing_families(uint32_t mask);
  * "mlp_backward_f32", "local_schur_apply_bf16", "interface_inverse_bf16", "gram" (Gram products
  * of block vectors, both wider than 16 columns), "block_update" (block updates X M of more than 16
  * columns), "small_dense" (the one-workgroup s x s kernels), "gram_narrow" and
- * "block_update_narrow" (the same with at most 16 columns on one side, e.g. Z^T r and Z c).
+ * "block_update_narrow" (the same with at most 16 columns on one side, e.g. Z^T r and Z c),
+ * "local_schur_apply_narrow_f64" and "interface_inverse_narrow_f64" (the FP64 applies to at most 16
+ * columns, e.g. the outer iteration's S_Gamma p and A_Gamma^{-1} r; the families without "narrow" then
+ * hold the wider applies).
  * Waits for the recorded events.  All outputs are HOST pointers (may be NULL).
  * NS_ERR_INVALID_ARG for an unknown family. */
 ns_status nystrom_schur_kernel_stats(const char* family, double* total_ms, int64_t* launches, double* bytes,

@@ -16,7 +16,8 @@ const char* kFamilyNames[KF_COUNT] = {"chol_update",        "chol_panel",       
                                       "local_schur_apply_f64", "local_schur_apply_f32",
                                       "interface_inverse_f64", "interface_inverse_f32", "mlp_forward_bf16", "mlp_backward_f32",
                                       "local_schur_apply_bf16", "interface_inverse_bf16", "gram", "block_update",
-                                      "small_dense", "gram_narrow", "block_update_narrow"};
+                                      "small_dense", "gram_narrow", "block_update_narrow",
+                                      "local_schur_apply_narrow_f64", "interface_inverse_narrow_f64"};
 
 struct Rec {
   hipEvent_t a, b;
@@ -99,7 +100,8 @@ bool kernel_timing_in_loops(bool pcg) {
   // iterations apply single columns, so the wide Gram products and block updates are not in them
   constexpr uint32_t setup_only = (1u << KF_CHOL_UPDATE) | (1u << KF_CHOL_PANEL) | (1u << KF_LS_FORM) |
                                   (1u << KF_MLP_FWD) | (1u << KF_MLP_BWD);
-  const uint32_t outside = setup_only | (pcg ? (1u << KF_GRAM) | (1u << KF_BLOCK_UPDATE) : 0u);
+  const uint32_t outside =
+      setup_only | (pcg ? (1u << KF_GRAM) | (1u << KF_BLOCK_UPDATE) | (1u << KF_LS_APPLY64) | (1u << KF_INV64) : 0u);
   return t.on && (t.mask & ~outside) != 0;
 }
 

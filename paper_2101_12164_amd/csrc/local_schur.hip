@@ -881,14 +881,15 @@ void tile_apply_inverse(const TileLevel& lv, const T* B, T* C, int ncols, hipStr
               ncols};
   if constexpr (sizeof(T) == 8) {
     if (ncols == 1 && lv.inv_sym.built()) {  // packed symmetric tiles: every stored entry read once
-      KScope ks(KF_INV64, st, lv.inv_sym.alg_bytes + 2.0 * lv.alg_rows * sizeof(T), lv.inv_sym.alg_flops);
+      KScope ks(KF_INV64_NARROW, st, lv.inv_sym.alg_bytes + 2.0 * lv.alg_rows * sizeof(T), lv.inv_sym.alg_flops);
       sym_gemv(lv.inv_sym, B, C, st, bidx);
       return;
     }
   }
   double sq = 0;
   for (int b = 0; b < lv.nblk; ++b) sq += double(lv.h_nb[b]) * lv.h_nb[b];
-  KScope ks(sizeof(T) == 8 ? KF_INV64 : KF_INV32, st, (sq + 2.0 * lv.alg_rows * ncols) * sizeof(T), 2.0 * sq * ncols);
+  KScope ks(sizeof(T) == 8 ? (ncols <= 16 ? KF_INV64_NARROW : KF_INV64) : KF_INV32, st,
+            (sq + 2.0 * lv.alg_rows * ncols) * sizeof(T), 2.0 * sq * ncols);
   const int tilesM = lv.max_nt;
   if (ncols <= 160 && lv.nblk * tilesM < 128) {  // few output tiles: split the reduction over eight waves
     const int strips = 4 * tilesM, ncg = (ncols + 79) / 80, grid = strips * lv.nblk * ncg;
@@ -1243,7 +1244,7 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
   } while (0)
   if (sizeof(T) == 8 && ncols == 1 && ldx == 1 && ls.sym.built()) {
     // one column: the packed symmetric tiles (every stored entry of S_j read once), x gathered through glist
-    KScope ks(KF_LS_APPLY64, st, ls.sym.alg_bytes + 2.0 * np * sizeof(T), ls.sym.alg_flops);
+    KScope ks(KF_LS_APPLY64_NARROW, st, ls.sym.alg_bytes + 2.0 * np * sizeof(T), ls.sym.alg_flops);
     sym_gemv(ls.sym, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(Yg), st, ls.glist.p);
   } else {
     if (ncols > 16 && ncols <= 256) {
@@ -1275,7 +1276,7 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
       }
     }
     if (!done) {
-      KScope ks(sizeof(T) == 8 ? KF_LS_APPLY64 : KF_LS_APPLY32, st,
+      KScope ks(sizeof(T) == 8 ? (ncols <= 16 ? KF_LS_APPLY64_NARROW : KF_LS_APPLY64) : KF_LS_APPLY32, st,
                 ls.alg_bytes * sizeof(T) + 2.0 * np * ncols * sizeof(T), ls.alg_flops * ncols);
       launch_gemm<T>(ls, S, Xg, Yg, ncols, st, false, g, ls.max_m);
     }

@@ -227,6 +227,8 @@ enum KFamily {
   KF_SMALL,       // one-workgroup dense kernels on the s x s matrices
   KF_GRAM_NARROW,          // Gram products with one side of at most 16 columns (Z^T r of the PCG apply)
   KF_BLOCK_UPDATE_NARROW,  // block updates of at most 16 output columns (Z c of the PCG apply)
+  KF_LS_APPLY64_NARROW,    // local Schur blocks applied to at most 16 FP64 columns (the PCG's S_Gamma p)
+  KF_INV64_NARROW,         // interface-block inverses applied to at most 16 FP64 columns (the PCG's M r)
   KF_COUNT
 };
 // Brackets one launch when timing is on; bytes / flops are the algorithmic

@@ -52,7 +52,7 @@ struct SmallMats {
   DBuf<int> ibuf;
   int* flag;   // [4] breakdown / factorisation flags
   int* ctr;    // [4] ctr[0]: problems no longer active in the inner solve
-  int *active, *rank, *ok, *skip, *svr, *dimA, *itp, *conv, *single, *dimB, *nys;  // per problem (nys: 2)
+  int *active, *rank, *ok, *skip, *svr, *dimA, *itp, *conv, *single, *dimB, *skip2, *dimC, *nys;  // (nys: 2)
   int np = 0;
   void init(int nprob, int s, int k) {
     np = nprob;
@@ -74,12 +74,12 @@ struct SmallMats {
     coef = p;
     p += np;
     relres = p;
-    ibuf.alloc(8 + 12 * size_t(np));
+    ibuf.alloc(8 + 14 * size_t(np));
     NS_HIP(hipMemsetAsync(ibuf.p, 0, ibuf.n * sizeof(int), alloc_stream()));
     flag = ibuf.p;
     ctr = ibuf.p + 4;
     int* q = ibuf.p + 8;
-    for (int** d : {&active, &rank, &ok, &skip, &svr, &dimA, &itp, &conv, &single, &dimB}) {
+    for (int** d : {&active, &rank, &ok, &skip, &svr, &dimA, &itp, &conv, &single, &dimB, &skip2, &dimC}) {
       *d = q;
       q += np;
     }
@@ -143,31 +143,37 @@ void check_chol(Handle& h, ns_setup_info* info) {
 __global__ void k_iter(int* it) { *it += 1; }
 
 // it: the iteration index, or, with itd != nullptr, read from the device (graph-replayed iterations)
-__global__ void k_bcg_check(int np, int s, const double* __restrict__ colsq, const double* __restrict__ nF2,
-                            double tol, int it, int* active, int* itp, int* conv, double* relres, int* ndone,
-                            const int* itd) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np || !active[p]) return;
+// One wave per problem: the largest relative column residual sqrt(colsq / nF2) over the s columns, lanes over
+// columns (four per lane in flight together, from clamped positions), a butterfly for the maximum.
+__global__ __launch_bounds__(64) void k_bcg_check(int np, int s, const double* __restrict__ colsq,
+                                                  const double* __restrict__ nF2, double tol, int it, int* active,
+                                                  int* itp, int* conv, double* relres, int* ndone, const int* itd) {
+  const int p = blockIdx.x, lane = threadIdx.x;
+  if (p >= np || !active[p]) return;  // uniform over the wave
   if (itd) it = *itd;
   double m = 0.0;
-  for (int j0 = 0; j0 < s; j0 += 8) {  // eight columns' loads in flight together (clamped, in bounds)
-    double f[8], c[8];
+  for (int j0 = 0; j0 < s; j0 += 4 * 64) {
+    double f[4], c[4];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int j = min(j0 + k, s - 1);
-      f[k] = nF2[p * s + j];
-      c[k] = colsq[p * s + j];
+    for (int k = 0; k < 4; ++k) {
+      const int j = min(j0 + 64 * k + lane, s - 1);
+      f[k] = nF2[int64_t(p) * s + j];
+      c[k] = colsq[int64_t(p) * s + j];
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (j0 + k < s && f[k] > 0.0) m = fmax(m, sqrt(c[k] / f[k]));
+    for (int k = 0; k < 4; ++k)
+      if (j0 + 64 * k + lane < s && f[k] > 0.0) m = fmax(m, sqrt(c[k] / f[k]));
   }
-  relres[p] = m;
-  itp[p] = it;
-  if (m <= tol) {
-    conv[p] = 1;
-    active[p] = 0;
-    atomicAdd(ndone, 1);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (lane == 0) {
+    relres[p] = m;
+    itp[p] = it;
+    if (m <= tol) {
+      conv[p] = 1;
+      active[p] = 0;
+      atomicAdd(ndone, 1);
+    }
   }
 }
 
@@ -181,6 +187,40 @@ __global__ void k_dims2(int np, const int* rank, const int* single, int* dims) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < np) dims[p] = single[p] ? 0 : rank[p];
 }
+// The second Cholesky-QR pass measured before it runs: skip2[p] = 1 where it has nothing to do (dims 0) or where
+// the Gram matrix G of the first pass's basis is already within eta of the identity in the Frobenius norm over
+// its leading dims x dims block (the basis then has condition number at most sqrt((1 + eta) / (1 - eta)));
+// dimC[p] = skip2[p] ? 0 : dims[p].  One workgroup per problem.
+__global__ __launch_bounds__(256) void k_near_identity(int np, int s, const int* dims, const double* G, int64_t sG,
+                                                       double eta, int* skip2, int* dimC) {
+  __shared__ double red[4];
+  const int p = blockIdx.x;
+  const int n = dims[p];
+  const double* Gp = G + int64_t(p) * sG;
+  double e2 = 0.0;
+  for (int e0 = threadIdx.x; e0 < n * n; e0 += 4 * 256) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = min(e0 + 256 * u, n * n - 1), i = e / n, j = e - i * n;
+      v[u] = Gp[int64_t(i) * s + j] - (i == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e0 + 256 * u < n * n) e2 += v[u] * v[u];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double f2 = (red[0] + red[1]) + (red[2] + red[3]);
+    const int sk = (n == 0 || f2 <= eta * eta) ? 1 : 0;
+    skip2[p] = sk;
+    dimC[p] = sk ? 0 : n;
+  }
+}
+
 __global__ void k_svqb_mask(int np, const int* active, const int* ok, int* skip) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < np) skip[p] = !(active[p] && !ok[p]);
@@ -210,8 +250,12 @@ __global__ void k_orth_select(int np, int s, int* active, const int* ok, const i
 // directions with singular value <= drop * sigma_max.  When a Cholesky of the Gram matrix certifies
 // that every singular value ratio exceeds the drop tolerance, nothing is dropped and Cholesky-QR2
 // yields a basis of the same span; otherwise the Gram matrix is eigen-decomposed (SVQB: keep the
-// eigenpairs above drop^2 * lambda_max) followed by one Cholesky-QR pass.  Inactive problems get zero
-// columns; dropped directions are zero columns at the end.  Q is scratch.
+// eigenpairs above drop^2 * lambda_max) followed by one Cholesky-QR pass.  The second pass runs in place,
+// and only where the first pass's basis B is measurably short of orthonormal: ||B^T B - I||_F > ORTH_ETA (a
+// basis within ORTH_ETA has condition number below 1 + ORTH_ETA, and the block CG's recurrences only need a
+// well-conditioned basis of the span).  Inactive problems get zero columns; dropped directions are zero
+// columns at the end.  P and Q trade places (the old P is scratch).
+constexpr double ORTH_ETA = 1e-4;
 template <class T>
 void orth(Handle& h, const Seg& sg, SmallMats& sm, double* work, const T* V, T*& P, T*& Q, int s, int it,
           const int* itd = nullptr) {
@@ -236,7 +280,7 @@ void orth(Handle& h, const Seg& sg, SmallMats& sm, double* work, const T* V, T*&
   k_orth_select<<<np, 256, 0, st>>>(np, s, sm.active, sm.ok, sm.svr, sm.Torth, sm.Rinv, sm.rank, it, sm.itp,
                                     sm.ctr, itd);
   NS_LAUNCH_CHECK();
-  ts_update<T>(sg, s, P, s, 0.0, 1.0, V, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
+  ts_update<T>(sg, s, Q, s, 0.0, 1.0, V, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
   Seg sg2 = sg;
   const int* dims2 = sm.rank;
   if (single) {
@@ -245,9 +289,12 @@ void orth(Handle& h, const Seg& sg, SmallMats& sm, double* work, const T* V, T*&
     NS_LAUNCH_CHECK();
     dims2 = sm.dimB;
   }
-  gram<T, T>(sg2, P, s, s, P, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
-  small_cholqr(Batch{np, dims2}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.sws, st);
-  ts_update<T>(sg2, s, Q, s, 0.0, 1.0, P, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
+  gram<T, T>(sg2, Q, s, s, Q, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
+  k_near_identity<<<np, 256, 0, st>>>(np, s, dims2, sm.Gorth, ss, ORTH_ETA, sm.skip2, sm.dimC);
+  NS_LAUNCH_CHECK();
+  sg2.skip = sm.skip2;
+  small_cholqr(Batch{np, sm.dimC}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.sws, st);
+  ts_update<T>(sg2, s, Q, s, 0.0, 1.0, Q, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);  // in place
   std::swap(P, Q);
 }
 
@@ -287,7 +334,7 @@ void block_pcg(Handle& h, SmallMats& sm, Ops& ops, Rhs rhs, double* D) {
   NS_HIP(hipMemsetAsync(X.p, 0, nG * s * sizeof(T), st));
   col_sumsq<T>(sg, s, R.p, s, sm.nF2, work, st);
   NS_HIP(hipMemcpyAsync(sm.colsq, sm.nF2, size_t(np) * s * sizeof(double), hipMemcpyDeviceToDevice, st));
-  k_bcg_check<<<pb, 256, 0, st>>>(np, s, sm.colsq, sm.nF2, h.tol_inner, 0, sm.active, sm.itp, sm.conv, sm.relres,
+  k_bcg_check<<<np, 64, 0, st>>>(np, s, sm.colsq, sm.nF2, h.tol_inner, 0, sm.active, sm.itp, sm.conv, sm.relres,
                                   sm.ctr, nullptr);
   NS_LAUNCH_CHECK();
   int hc[2] = {0, 0};
@@ -311,7 +358,7 @@ void block_pcg(Handle& h, SmallMats& sm, Ops& ops, Rhs rhs, double* D) {
       ts_update<T>(sg, s, X.p, s, 1.0, 1.0, P, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, q);
       ts_update<T>(sg, s, R.p, s, 1.0, -1.0, Q, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, q);
       col_sumsq<T>(sg, s, R.p, s, sm.colsq, work, q);
-      k_bcg_check<<<pb, 256, 0, q>>>(np, s, sm.colsq, sm.nF2, h.tol_inner, 0, sm.active, sm.itp, sm.conv,
+      k_bcg_check<<<np, 64, 0, q>>>(np, s, sm.colsq, sm.nF2, h.tol_inner, 0, sm.active, sm.itp, sm.conv,
                                      sm.relres, sm.ctr, itd.p);
       NS_LAUNCH_CHECK();
     };

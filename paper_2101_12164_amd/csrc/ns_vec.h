@@ -47,7 +47,9 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
 size_t gram_work_elems(const Seg& sg, int maxw);
 
 // Out_p = beta * Out_p + gamma * (X_p M_p + X2_p M2_p) on the rows of every segment p;
-// M_p: rm x ncols (ld ldm) at M + p * mstride, FP64; X2 optional (rm2 = 0).
+// M_p: rm x ncols (ld ldm) at M + p * mstride, FP64; X2 optional (rm2 = 0).  A skipped segment (sg.skip) gets
+// Out = X.  Out may be X itself (same leading dimension, at most 256 columns, no X2): every workgroup reads
+// only the rows it writes, all of them before its first store, and a skipped segment is left as it is.
 template <class T>
 void ts_update(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, double gamma, const T* X, int64_t ldx,
                int rm, const double* M, int64_t ldm, int64_t mstride, const T* X2 = nullptr, int64_t ldx2 = 0,

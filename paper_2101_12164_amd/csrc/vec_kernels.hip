@@ -326,10 +326,10 @@ constexpr int TS_K = 32;
 // Out[r][c] = X[r][c] for the rows [rbase, min(rbase + 64, rend)) and columns [c0, c1) (a skipped segment of a
 // block update), 256 threads.
 template <class T>
-__device__ __forceinline__ void ts_copy_tile(int64_t rbase, int64_t rend, int c0, int c1, T* __restrict__ Out,
-                                             int64_t ldo, const T* __restrict__ X, int64_t ldx) {
+__device__ __forceinline__ void ts_copy_tile(int64_t rbase, int64_t rend, int c0, int c1, T* Out, int64_t ldo,
+                                             const T* X, int64_t ldx) {
   const int nc = c1 - c0;
-  if (nc <= 0) return;
+  if (nc <= 0 || (static_cast<const T*>(Out) == X && ldo == ldx)) return;  // in place: nothing to copy
   const int64_t nr = rend - rbase < 64 ? rend - rbase : 64;
   for (int e = threadIdx.x; e < nr * nc; e += 256) {
     const int64_t r = rbase + e / nc;
@@ -339,8 +339,8 @@ __device__ __forceinline__ void ts_copy_tile(int64_t rbase, int64_t rend, int c0
 }
 
 template <class T, int NTI>
-__global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* __restrict__ Out, int64_t ldo, double beta,
-                                                 double gamma, const T* __restrict__ X, int64_t ldx, int K,
+__global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* Out, int64_t ldo, double beta,
+                                                 double gamma, const T* X, int64_t ldx, int K,
                                                  const double* __restrict__ M, int64_t ldm, int64_t mstride) {
   constexpr int NC = 16 * NTI;
   __shared__ double sX[64 * (TS_K + 1)];
@@ -432,8 +432,8 @@ __global__ __launch_bounds__(256) void k_ts_mfma(Seg sg, int ncols, T* __restric
 // barrier per batch).  The sums over K run in the same order as in k_ts_mfma (same bits).
 constexpr int TW_K = 16;
 template <class T, int NTI>
-__global__ __launch_bounds__(256, 2) void k_ts_wide(Seg sg, int ncols, T* __restrict__ Out, int64_t ldo, double beta,
-                                                 double gamma, const T* __restrict__ X, int64_t ldx, int K,
+__global__ __launch_bounds__(256, 2) void k_ts_wide(Seg sg, int ncols, T* Out, int64_t ldo, double beta,
+                                                 double gamma, const T* X, int64_t ldx, int K,
                                                  const double* __restrict__ M, int64_t ldm, int64_t mstride) {
   constexpr int NC = 16 * NTI;
   constexpr int XS = TW_K + 1, MS = NC + 1;
@@ -522,15 +522,16 @@ __global__ __launch_bounds__(256, 2) void k_ts_wide(Seg sg, int ncols, T* __rest
 constexpr int TB_R = 256, TB_NT = 512, TB_K = 16;
 template <int NTI>
 __global__ __launch_bounds__(TB_NT) void k_ts_big(int64_t r0, int64_t rend, const int* skip, int ncols,
-                                                  double* __restrict__ Out, int64_t ldo, double beta, double gamma,
-                                                  const double* __restrict__ X, int64_t ldx, int K,
+                                                  double* Out, int64_t ldo, double beta, double gamma,
+                                                  const double* X, int64_t ldx, int K,
                                                   const double* __restrict__ M, int64_t ldm) {
   constexpr int NC = 16 * NTI;
   constexpr int XS = TB_K + 1, MS = NC + 1;
   __shared__ double sX[2][TB_R * XS];
   __shared__ double sM[2][TB_K * MS];
   const int64_t rbase = r0 + int64_t(blockIdx.x) * TB_R;
-  if (skip && skip[0]) {  // Out = X on this workgroup's rows (a skipped segment)
+  if (skip && skip[0]) {  // Out = X on this workgroup's rows (a skipped segment; nothing to do in place)
+    if (static_cast<const double*>(Out) == X && ldo == ldx) return;
     const int64_t nr = rend - rbase < TB_R ? rend - rbase : TB_R;
     for (int64_t e = threadIdx.x; e < nr * ncols; e += TB_NT) {
       const int64_t r = rbase + e / ncols;
@@ -617,8 +618,8 @@ __global__ __launch_bounds__(TB_NT) void k_ts_big(int64_t r0, int64_t rend, cons
 // l + 16 i of it (a 128-byte run per i over the sixteen lanes), and all 4 KPL row loads of a lane are issued
 // before the products; the sixteen partial sums meet in a butterfly.
 template <int KPL>
-__global__ __launch_bounds__(256) void k_ts_gemv(Seg sg, double* __restrict__ Out, int64_t ldo, double beta,
-                                                 double gamma, const double* __restrict__ X, int64_t ldx, int K,
+__global__ __launch_bounds__(256) void k_ts_gemv(Seg sg, double* Out, int64_t ldo, double beta,
+                                                 double gamma, const double* X, int64_t ldx, int K,
                                                  const double* __restrict__ M, int64_t ldm, int64_t mstride) {
   const int p = seg_of(sg.toff, sg.n, blockIdx.x);
   const int64_t rbase = sg.off[p] + int64_t(blockIdx.x - sg.toff[p]) * 64, rend = sg.off[p + 1];
@@ -730,6 +731,8 @@ void ts_launch(const Seg& sg, int ncols, T* Out, int64_t ldo, double beta, doubl
     NS_LAUNCH_CHECK();
     return;
   }
+  if (tiles > 16 && static_cast<const T*>(Out) == X)
+    fail(INVALID_ARG, "block update in place wider than 256 columns");  // column groups would race
   if (tiles <= 1)
     go(std::integral_constant<int, 1>());
   else if (tiles <= 2)
@@ -890,22 +893,18 @@ __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, doubl
     y[i] = a * x[i] + (b != 0.0 ? b * y[i] : 0.0);
 }
 
-// Column sums of squares: workgroup b takes part b % split of chunk b / split (contiguous rows).  Lane l of a
-// wave owns the columns l, l + 64, ... of a group of CG column blocks (one pass over the rows per group); wave w
-// takes the rows w, w + 4, ... of the part, CQ_U of them per batch with every load of the batch issued (from
-// clamped in-bounds addresses) before the first product, and the four waves' sums are combined in a fixed
-// order.  Partial b * ncols + c.
-constexpr int CQ_U = 4, CQ_CG = 3;
+// Column sums of squares of each chunk's rows: 1024-thread workgroups, one per chunk.  Lane l of a wave owns
+// the columns l, l + 64, ... of a group of CQ_CG column blocks (one pass over the rows per group); wave w takes
+// the rows w, w + 16, ..., CQ_U of them per batch with every load of the batch issued (from clamped in-bounds
+// rows) before the first product, and the sixteen waves' sums are combined in a fixed order.
+constexpr int CQ_NT = 1024, CQ_W = CQ_NT / 64, CQ_U = 4, CQ_CG = 3;
 template <class T>
-__global__ __launch_bounds__(256) void k_colsq_partial(Seg sg, int ncols, const T* __restrict__ X, int64_t ldx,
-                                                       double* __restrict__ part, int split) {
-  __shared__ double red[3][CQ_CG][64];
+__global__ __launch_bounds__(CQ_NT) void k_colsq_partial(Seg sg, int ncols, const T* __restrict__ X, int64_t ldx,
+                                                         double* __restrict__ part) {
+  __shared__ double red[CQ_W - 1][CQ_CG][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int64_t c0, c1;
-  chunk_rows(sg, blockIdx.x / split, c0, c1);
-  const int q = blockIdx.x % split;
-  const int64_t per = (c1 - c0 + split - 1) / split;
-  const int64_t r0 = c0 + q * per < c1 ? c0 + q * per : c1, r1 = r0 + per < c1 ? r0 + per : c1;
+  int64_t r0, r1;
+  chunk_rows(sg, blockIdx.x, r0, r1);
   for (int g0 = 0; g0 < ncols; g0 += 64 * CQ_CG) {
     int col[CQ_CG];
 #pragma unroll
@@ -913,18 +912,19 @@ __global__ __launch_bounds__(256) void k_colsq_partial(Seg sg, int ncols, const 
     double s[CQ_CG];
 #pragma unroll
     for (int g = 0; g < CQ_CG; ++g) s[g] = 0.0;
-    for (int64_t r = r0 + w; r < r1; r += 4 * CQ_U) {
+    for (int64_t r = r0 + w; r < r1; r += CQ_W * CQ_U) {
       double v[CQ_U][CQ_CG];
 #pragma unroll
       for (int u = 0; u < CQ_U; ++u) {
-        const int64_t rr = r + 4 * u < r1 ? r + 4 * u : r;
+        const int64_t rr = r + CQ_W * u < r1 ? r + CQ_W * u : r;
 #pragma unroll
         for (int g = 0; g < CQ_CG; ++g) v[u][g] = double(X[rr * ldx + col[g]]);
       }
 #pragma unroll
       for (int u = 0; u < CQ_U; ++u)
+        if (r + CQ_W * u < r1)  // uniform over the wave
 #pragma unroll
-        for (int g = 0; g < CQ_CG; ++g) s[g] += r + 4 * u < r1 ? v[u][g] * v[u][g] : 0.0;
+          for (int g = 0; g < CQ_CG; ++g) s[g] += v[u][g] * v[u][g];
     }
     if (w > 0)
 #pragma unroll
@@ -934,8 +934,10 @@ __global__ __launch_bounds__(256) void k_colsq_partial(Seg sg, int ncols, const 
 #pragma unroll
       for (int g = 0; g < CQ_CG; ++g) {
         const int c = g0 + 64 * g + lane;
-        if (c < ncols)
-          part[int64_t(blockIdx.x) * ncols + c] = ((s[g] + red[0][g][lane]) + red[1][g][lane]) + red[2][g][lane];
+        double t = s[g];
+#pragma unroll
+        for (int x = 0; x < CQ_W - 1; ++x) t += red[x][g][lane];
+        if (c < ncols) part[int64_t(blockIdx.x) * ncols + c] = t;
       }
     __syncthreads();
   }
@@ -1073,11 +1075,9 @@ void convert_block(int64_t n, int ncols, const T* X, int64_t ldx, U* Y, int64_t 
 template <class T>
 void col_sumsq(const Seg& sg, int ncols, const T* X, int64_t ldx, double* out, double* work, hipStream_t st) {
   if (ncols == 0 || sg.n == 0) return;
-  // the caller's workspace holds nchunk * ncols * ncols partials: up to four parts per chunk fit
-  const int split = ncols < 4 ? ncols : 4;
-  k_colsq_partial<T><<<unsigned(sg.nchunk * split), 256, 0, st>>>(sg, ncols, X, ldx, work, split);
+  k_colsq_partial<T><<<unsigned(sg.nchunk), CQ_NT, 0, st>>>(sg, ncols, X, ldx, work);
   NS_LAUNCH_CHECK();
-  seg_final(sg, ncols, work, out, ncols, 1.0, 0.0, st, nullptr, 0, 1, split);
+  seg_final(sg, ncols, work, out, ncols, 1.0, 0.0, st);
 }
 
 void dot(const Seg& sg, const double* x, const double* y, double* out, int64_t ostride, double* work,

@@ -72,7 +72,8 @@ KERNEL_FAMILIES = ["chol_update", "chol_panel", "trsm_interior_f64", "trsm_inter
                    "trsm_interface_f32", "schur_epi", "spmm", "local_schur_form", "local_schur_apply_f64",
                    "local_schur_apply_f32", "interface_inverse_f64", "interface_inverse_f32", "mlp_forward_bf16",
                    "mlp_backward_f32", "local_schur_apply_bf16", "interface_inverse_bf16", "gram", "block_update",
-                   "small_dense", "gram_narrow", "block_update_narrow"]
+                   "small_dense", "gram_narrow", "block_update_narrow", "local_schur_apply_narrow_f64",
+                   "interface_inverse_narrow_f64"]
 
 
 class NsOptions(ctypes.Structure):

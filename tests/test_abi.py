@@ -78,3 +78,18 @@ def test_package_exposes_every_entry_point():
 
     for name in ns.EXPORTED:
         assert callable(getattr(ns, name, None)), name
+
+
+def test_kernel_family_names_match_the_library():
+    """Every timing family the binding names is one the library knows (statistics of an untimed run: zeros)."""
+    from paper_2101_12164_amd import library_path
+    from paper_2101_12164_amd.nystrom_schur import KERNEL_FAMILIES, nystrom_schur_kernel_stats
+
+    if not os.path.exists(library_path()):
+        pytest.skip("library not built")
+    assert len(KERNEL_FAMILIES) == len(set(KERNEL_FAMILIES)) <= 32
+    for f in KERNEL_FAMILIES:
+        st = nystrom_schur_kernel_stats(f)
+        assert st["launches"] == 0 and st["ms"] == 0.0
+    with pytest.raises(Exception):
+        nystrom_schur_kernel_stats("no_such_family")
