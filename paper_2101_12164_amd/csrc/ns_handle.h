@@ -105,6 +105,15 @@ struct ns_handle_s {
   ns::Csr AsJ;  // rows: padded level-2 rows;  cols: junction rows
   ns::Csr AJs;  // rows: padded junction rows; cols: padded level-2 rows
   ns::TileLevel L2, LJ;
+  // level-2 rows coupled to junction nodes (the rows of A_sJ with entries), listed block by block: the second
+  // level-2 solve of an A_Gamma solve only changes by A_s^{-1} restricted to these columns (see
+  // op_gamma_solve); l2c_n = 0 turns that path off
+  ns::DBuf<int32_t> l2c_rows, l2c_off, l2c_blk;  // row list, per-block offsets (nblk + 1), padded row -> block
+  int64_t l2c_n = 0;
+  int l2c_w = 0;                   // most listed rows of one block
+  ns::DBuf<int32_t> l2c_rinf;      // per padded level-2 row: first listed row of its block, their count
+  ns::DBuf<double> l2c_coef64;     // per padded level-2 row r: (A_b^{-1})(k, r) for the listed rows k of its block
+  ns::DBuf<float> l2c_coef32;
 
   // low-rank term (FP64): Z n_G x k (ld = k; columns >= k_eff of a problem are zero), Sigma k per problem
   ns::DBuf<double> Z, Sigma;
@@ -125,6 +134,8 @@ struct ns_handle_s {
   // workspaces (sized at setup)
   ns::DBuf<double> wsT64, wsB64, wsJ64, wsB64b, wsJ64b;  // interior rhs, level-2 rhs, junction rhs, outputs
   ns::DBuf<float> wsT32, wsB32, wsJ32, wsB32b, wsJ32b;
+  ns::DBuf<double> wsC64;  // A_sJ y_J on the listed level-2 rows
+  ns::DBuf<float> wsC32;
   ns::DBuf<double> red;    // reduction partials
   ns::DBuf<double> small;  // small dense scratch (per problem), described by sws
   ns::SmallWs sws;
@@ -172,6 +183,8 @@ struct Pieces {
 void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
                   const double* val, const int32_t* part, const Pieces* pieces = nullptr);
 void assemble_junction(Handle& h);
+// the second level-2 solve's coefficients from the explicit level-2 inverses (after they are made)
+void make_l2_coefs(Handle& h);
 // Symbolic pass (interface lists, layouts; waits for the device) and numeric pass (needs the interior factor).
 void local_schur_plan(Handle& h);
 void local_schur_form(Handle& h);

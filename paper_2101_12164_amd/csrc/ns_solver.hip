@@ -1262,6 +1262,7 @@ void setup_core(Handle* h, int64_t n, int64_t nnz, const int64_t* row_ptr, const
         tile_make_fp32(h->L2, h->stream);
         tile_make_fp32(h->LJ, h->stream);
       }
+      make_l2_coefs(*h);
       if (h->bf16) {
         tile_make_bf16_inverse(h->L2, h->stream);
         tile_make_bf16_inverse(h->LJ, h->stream);

@@ -151,6 +151,109 @@ __global__ __launch_bounds__(256) void k_scatter2(int64_t n1, const int32_t* __r
   for (int c = lane; c < ncols; c += TPR) Out[int64_t(d) * ldo + c] = B[row * ldb + c];
 }
 
+// C[q] = (A_sJ Y)[rows[q]] on the listed level-2 rows; TPR lanes per row, lane l holding the columns l + TPR g.
+template <class T, int TPR, int CPL>
+__global__ __launch_bounds__(256) void k_l2c_rows(int64_t nq, const int32_t* __restrict__ rows,
+                                                  const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                  const T* __restrict__ val, const T* __restrict__ Y, int64_t ldy,
+                                                  T* __restrict__ C, int ncols) {
+  const int64_t q = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
+  const int lane = threadIdx.x % TPR;
+  if (q >= nq) return;
+  int cc[CPL];
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) cc[g] = min(lane + TPR * g, ncols - 1);
+  T acc[CPL];
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) acc[g] = T(0);
+  const int r = rows[q];
+  for (int64_t e = ptr[r], e1 = ptr[r + 1]; e < e1; ++e) {
+    const int64_t j = col[e];
+    const T v = val[e];
+#pragma unroll
+    for (int g = 0; g < CPL; ++g) acc[g] += v * Y[j * ldy + cc[g]];
+  }
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) {
+    const int c = lane + TPR * g;
+    if (c < ncols) C[q * ncols + c] = acc[g];
+  }
+}
+
+// The last step of an A_Gamma solve: Out[jsrc[i]] = yJ[i] on the junction rows and, on the level-2 rows,
+// Out[l2src[r]] = xs[r] - sum over the listed rows k of r's block b of (A_b^{-1})(k, r) C[k], where xs is
+// A_s^{-1} applied to the level-2 right-hand side alone and C = A_sJ y_J on the listed rows: by linearity
+// A_s^{-1} (r_s - A_sJ y_J), with A_s^{-1} A_sJ y_J reduced to the few columns of A_s^{-1} that A_sJ reaches.
+// The coefficients of row r sit at coef[r w + u] (k_l2c_coef), rinf[r] = (first listed row, count).  TPR lanes
+// per row, lane l holding the columns l + TPR g; four listed rows at a time, their loads issued together.
+template <class T, int TPR, int CPL>
+__global__ __launch_bounds__(256) void k_scatter_l2c(int64_t nJ, const int32_t* __restrict__ jsrc,
+                                                     const T* __restrict__ yJ, int64_t n2,
+                                                     const int32_t* __restrict__ l2src, const T* __restrict__ xs,
+                                                     const int2* __restrict__ rinf, const T* __restrict__ coef, int w,
+                                                     const T* __restrict__ C, T* __restrict__ Out, int64_t ldo,
+                                                     int ncols) {
+  int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
+  const int lane = threadIdx.x % TPR;
+  int cc[CPL];
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) cc[g] = min(lane + TPR * g, ncols - 1);
+  T v[CPL];
+  int d;
+  if (row < nJ) {
+    d = jsrc[row];
+#pragma unroll
+    for (int g = 0; g < CPL; ++g) v[g] = yJ[row * ncols + cc[g]];
+    if (d < 0) return;
+  } else {
+    row -= nJ;
+    if (row >= n2) return;
+    d = l2src[row];
+    const int2 ri = rinf[row];
+#pragma unroll
+    for (int g = 0; g < CPL; ++g) v[g] = xs[row * ncols + cc[g]];
+    if (d < 0) return;
+    const T* cr = coef + row * w;
+    for (int u = 0; u < ri.y; u += 4) {
+      T a[4], cv[4][CPL];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int uk = u + k < ri.y ? u + k : u;
+        a[k] = cr[uk];
+#pragma unroll
+        for (int g = 0; g < CPL; ++g) cv[k][g] = C[int64_t(ri.x + uk) * ncols + cc[g]];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (u + k < ri.y)
+#pragma unroll
+          for (int g = 0; g < CPL; ++g) v[g] -= a[k] * cv[k][g];
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < CPL; ++g) {
+    const int c = lane + TPR * g;
+    if (c < ncols) Out[int64_t(d) * ldo + c] = v[g];
+  }
+}
+
+// coef[r w + u] = (A_b^{-1})(k_u, r) for the listed rows k_u of the block b of padded level-2 row r (zero past
+// their count), rinf[r] = (first listed row of b, count) when rinf is given.
+template <class T>
+__global__ void k_l2c_coef(int64_t n2, const int32_t* __restrict__ blk, const int64_t* __restrict__ roff,
+                           const int64_t* __restrict__ inv_off, const int64_t* __restrict__ inv_lda,
+                           const T* __restrict__ Ainv, const int32_t* __restrict__ off,
+                           const int32_t* __restrict__ rows, int w, T* __restrict__ coef, int2* __restrict__ rinf) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= n2) return;
+  const int b = blk[r];
+  const int64_t r0 = roff[b], m = r - r0;
+  const int q0 = off[b], nq = off[b + 1] - q0;
+  if (rinf) rinf[r] = make_int2(q0, nq);
+  for (int u = 0; u < w; ++u)
+    coef[r * w + u] = u < nq ? Ainv[inv_off[b] + (int64_t(rows[q0 + u]) - r0) * inv_lda[b] + m] : T(0);
+}
+
 template <int TPR>
 inline int grid_rows(int64_t nrows) {
   return int((nrows * TPR + 255) / 256);
@@ -701,6 +804,63 @@ void alloc_csr(Csr& A, int64_t nrows) {
   NS_HIP(hipMemsetAsync(A.ptr.p, 0, (nrows + 1) * sizeof(int64_t), alloc_stream()));
 }
 
+// The level-2 rows with entries in A_sJ, block by block, and the padded row -> block map.  Kept only when every
+// block has at most L2C_MAX such rows (box interfaces in two dimensions: the two ends of a separator segment);
+// otherwise l2c_n stays 0 and the second level-2 solve runs in full.
+constexpr int L2C_MAX = 16;
+void build_l2_coupled_rows(Handle& h, const std::vector<int64_t>& ptr) {
+  const TileLevel& lv = h.L2;
+  h.l2c_n = 0;
+  h.l2c_w = 0;
+  if (lv.nblk == 0) return;
+  std::vector<int32_t> rows, off(lv.nblk + 1, 0), blk(lv.nrows_pad, 0);
+  for (int b = 0; b < lv.nblk; ++b) {
+    const int64_t r0 = lv.h_roff[b], r1 = r0 + int64_t(lv.h_nt[b]) * TILE;
+    for (int64_t r = r0; r < r1; ++r) {
+      blk[r] = b;
+      if (ptr[r + 1] > ptr[r]) rows.push_back(int32_t(r));
+    }
+    off[b + 1] = int32_t(rows.size());
+    if (off[b + 1] - off[b] > L2C_MAX) return;
+    h.l2c_w = std::max(h.l2c_w, off[b + 1] - off[b]);
+  }
+  if (rows.empty()) return;
+  hipStream_t st = alloc_stream();
+  h.l2c_rows.alloc(rows.size());
+  h.l2c_off.alloc(off.size());
+  h.l2c_blk.alloc(blk.size());
+  upload(h.l2c_rows.p, rows.data(), rows.size() * sizeof(int32_t), st);
+  upload(h.l2c_off.p, off.data(), off.size() * sizeof(int32_t), st);
+  upload(h.l2c_blk.p, blk.data(), blk.size() * sizeof(int32_t), st);
+  h.l2c_n = int64_t(rows.size());
+}
+
+}  // namespace
+
+// The coefficients of the second level-2 solve (k_l2c_coef) from the explicit inverses of the level-2 blocks,
+// FP64 and, when the FP32 inverses exist, FP32; without explicit inverses the path stays off.
+void make_l2_coefs(Handle& h) {
+  const TileLevel& lv = h.L2;
+  if (!h.l2c_n || !lv.Ainv64.p) return;
+  hipStream_t st = h.stream;
+  const int64_t n2 = lv.nrows_pad;
+  const unsigned grid = unsigned((n2 + 255) / 256);
+  h.l2c_rinf.alloc(2 * n2);
+  h.l2c_coef64.alloc(n2 * h.l2c_w);
+  k_l2c_coef<double><<<grid, 256, 0, st>>>(n2, h.l2c_blk, lv.roff, lv.inv_off, lv.inv_lda, lv.Ainv64.p, h.l2c_off,
+                                           h.l2c_rows, h.l2c_w, h.l2c_coef64.p,
+                                           reinterpret_cast<int2*>(h.l2c_rinf.p));
+  NS_LAUNCH_CHECK();
+  if (lv.Ainv32.p) {
+    h.l2c_coef32.alloc(n2 * h.l2c_w);
+    k_l2c_coef<float><<<grid, 256, 0, st>>>(n2, h.l2c_blk, lv.roff, lv.inv_off, lv.inv_lda, lv.Ainv32.p, h.l2c_off,
+                                            h.l2c_rows, h.l2c_w, h.l2c_coef32.p, nullptr);
+    NS_LAUNCH_CHECK();
+  }
+}
+
+namespace {
+
 void finish_csr(Csr& A, hipStream_t st) {
   if (A.nrows == 0) return;
   scan_inclusive(A.ptr.p + 1, A.nrows, st);
@@ -900,7 +1060,16 @@ void extract_dbbd(Handle& h, int64_t n, int64_t nnz, const int64_t* row_ptr, con
   finish_csr(h.AGI, st);
   finish_csr(h.AGG, st);
   finish_csr(h.AsJ, st);
+  std::vector<int64_t> sjp;
+  if (n2pad > 0 && nJpad > 0) {  // read once the junction coupling of finish_csr(AJs) has synchronised
+    sjp.resize(n2pad + 1);
+    NS_HIP(hipMemcpyAsync(sjp.data(), h.AsJ.ptr.p, (n2pad + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  }
   finish_csr(h.AJs, st);
+  if (!sjp.empty()) {
+    NS_HIP(hipStreamSynchronize(st));
+    build_l2_coupled_rows(h, sjp);
+  }
   // fill pass
   if (h.L1.f_elems) NS_HIP(hipMemsetAsync(h.L1.L64.p, 0, h.L1.f_elems * sizeof(double), st));
   if (h.L2.f_elems) NS_HIP(hipMemsetAsync(h.L2.L64.p, 0, h.L2.f_elems * sizeof(double), st));
@@ -982,11 +1151,13 @@ void ensure_workspace(Handle& h, int64_t ncols) {
   auto grow = [&](auto& buf, int64_t rows) { buf.alloc(rows > 0 ? rows * c : 1); };
   grow(h.wsB64, h.L2.nrows_pad);
   grow(h.wsJ64, h.LJ.nrows_pad);
+  grow(h.wsC64, h.l2c_n);
   grow(h.wsB64b, h.L2.nrows_pad);
   grow(h.wsJ64b, h.LJ.nrows_pad);
   if (h.prec_inner) {
     grow(h.wsB32, h.L2.nrows_pad);
     grow(h.wsJ32, h.LJ.nrows_pad);
+    grow(h.wsC32, h.l2c_n);
     grow(h.wsB32b, h.L2.nrows_pad);
     grow(h.wsJ32b, h.LJ.nrows_pad);
   }
@@ -1114,6 +1285,36 @@ void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int
   if (nJpad) {
     gather_sub<T>(nJpad, h.jsrc, R, ldr, n2pad ? &h.AJs : nullptr, xs, ncols, Gj, ncols, ncols, st);
     T* xj = solve(h.LJ, Gj, Gk);
+    // the second level-2 solve through the few columns of the explicit inverses that A_sJ reaches
+    const T* coef = ws_ptr<T>(h.l2c_coef64, h.l2c_coef32);
+    if (n2pad && h.l2c_n && coef && !h.op_bf16 && ncols <= 256) {
+      T* C = ws_ptr<T>(h.wsC64, h.wsC32);
+      const T* vsJ = ws_ptr<T>(h.AsJ.val64, h.AsJ.val32);
+      auto run = [&](auto tpr, auto cpl) {
+        constexpr int TPR = decltype(tpr)::value, CPL = decltype(cpl)::value;
+        k_l2c_rows<T, TPR, CPL><<<grid_rows<TPR>(h.l2c_n), 256, 0, st>>>(h.l2c_n, h.l2c_rows, h.AsJ.ptr, h.AsJ.col,
+                                                                         vsJ, xj, ncols, C, ncols);
+        NS_LAUNCH_CHECK();
+        k_scatter_l2c<T, TPR, CPL><<<grid_rows<TPR>(nJpad + n2pad), 256, 0, st>>>(
+            nJpad, h.jsrc, xj, n2pad, h.l2src, xs, reinterpret_cast<const int2*>(h.l2c_rinf.p), coef, h.l2c_w, C,
+            Out, ldo, ncols);
+        NS_LAUNCH_CHECK();
+      };
+      using I = std::integral_constant<int, 1>;
+      if (ncols == 1)
+        run(I(), I());
+      else if (ncols <= 16)
+        run(std::integral_constant<int, 16>(), I());
+      else if (ncols <= 64)
+        run(std::integral_constant<int, 64>(), I());
+      else if (ncols <= 128)
+        run(std::integral_constant<int, 64>(), std::integral_constant<int, 2>());
+      else if (ncols <= 192)
+        run(std::integral_constant<int, 64>(), std::integral_constant<int, 3>());
+      else
+        run(std::integral_constant<int, 64>(), std::integral_constant<int, 4>());
+      return;
+    }
     if (n2pad) {
       gather_sub<T>(n2pad, h.l2src, R, ldr, &h.AsJ, xj, ncols, Bp, ncols, ncols, st);
       xs = solve(h.L2, Bp, Bq);
