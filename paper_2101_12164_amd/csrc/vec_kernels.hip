@@ -500,18 +500,34 @@ __global__ __launch_bounds__(256, 2) void k_ts_wide(Seg sg, int ncols, T* Out, i
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ms[(kk + lk) * MS + 16 * t + li], acc[t], 0, 0, 0);
     }
   }
+  // epilogue four column tiles at a time: their old outputs (beta != 0) loaded together from clamped in-bounds
+  // positions before the first store
 #pragma unroll
-  for (int t = 0; t < NTI; ++t)
+  for (int t0 = 0; t0 < NTI; t0 += 4) {
+    T o[4][4];
+    if (beta != 0.0) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = rbase + 16 * w + 4 * v + lk;
-      const int c = 16 * t + li;
-      if (r < rend && c < ncols) {
-        double y = gamma * acc[t][v];
-        if (beta != 0.0) y += beta * double(Out[r * ldo + c]);
-        Out[r * ldo + c] = T(y);
-      }
+      for (int t = t0; t < t0 + 4 && t < NTI; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t r = rbase + 16 * w + 4 * v + lk;
+          const int c = 16 * t + li;
+          o[t - t0][v] = Out[(r < rend ? r : rend - 1) * ldo + (c < ncols ? c : ncols - 1)];
+        }
     }
+#pragma unroll
+    for (int t = t0; t < t0 + 4 && t < NTI; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = rbase + 16 * w + 4 * v + lk;
+        const int c = 16 * t + li;
+        if (r < rend && c < ncols) {
+          double y = gamma * acc[t][v];
+          if (beta != 0.0) y += beta * double(o[t - t0][v]);
+          Out[r * ldo + c] = T(y);
+        }
+      }
+  }
 }
 
 // Block updates of one problem's wide FP64 blocks (6..10 column tiles): 256-row workgroups of 8 waves, each wave
@@ -597,20 +613,38 @@ __global__ __launch_bounds__(TB_NT) void k_ts_big(int64_t r0, int64_t rend, cons
       __builtin_amdgcn_sched_barrier(0);  // one k-step's operands at a time (80 accumulators stay in registers)
     }
   }
+  // epilogue two column tiles at a time: their sixteen old outputs (beta != 0) are loaded together, from clamped
+  // in-bounds positions, before the first store (one memory round trip per pair instead of one per value)
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int t0 = 0; t0 < NTI; t0 += 2) {
+    double o[2][2][4];
+    if (beta != 0.0) {
 #pragma unroll
-    for (int t = 0; t < NTI; ++t)
+      for (int t = t0; t < t0 + 2 && t < NTI; ++t)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = rbase + 32 * w + 16 * h + 4 * v + lk;
-        const int c = 16 * t + li;
-        if (r < rend && c < ncols) {
-          double y = gamma * acc[h][t][v];
-          if (beta != 0.0) y += beta * Out[r * ldo + c];
-          Out[r * ldo + c] = y;
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t r = rbase + 32 * w + 16 * h + 4 * v + lk;
+            const int c = 16 * t + li;
+            o[t - t0][h][v] = Out[(r < rend ? r : rend - 1) * ldo + (c < ncols ? c : ncols - 1)];
+          }
+    }
+#pragma unroll
+    for (int t = t0; t < t0 + 2 && t < NTI; ++t)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t r = rbase + 32 * w + 16 * h + 4 * v + lk;
+          const int c = 16 * t + li;
+          if (r < rend && c < ncols) {
+            double y = gamma * acc[h][t][v];
+            if (beta != 0.0) y += beta * o[t - t0][h][v];
+            Out[r * ldo + c] = y;
+          }
         }
-      }
+  }
 }
 
 // One output column, FP64: Out[r] = beta Out[r] + gamma sum_m X[r, m] M_p[m] for K <= 16 KPL.  A workgroup
