@@ -349,7 +349,7 @@ void block_pcg(Handle& h, SmallMats& sm, Ops& ops, Rhs rhs, double* D) {
     auto half1 = [&](hipStream_t q) {
       k_iter<<<1, 1, 0, q>>>(itd.p);
       ops.S(P, Q);                                                            // Q = S P
-      gram<T, T>(sg, P, s, s, Q, s, s, sm.Delta, ss, 1.0, 0.0, work, q);      // Delta = P^T Q
+      gram<T, T>(sg, P, s, s, Q, s, s, sm.Delta, ss, 1.0, 0.0, work, q, nullptr, 0, true);  // Delta = P^T S P
       gram<T, T>(sg, P, s, s, R.p, s, s, sm.G1, ss, 1.0, 0.0, work, q);       // P^T R
       k_dims<<<pb, 256, 0, q>>>(np, s, sm.active, sm.rank, sm.dimA);
       NS_LAUNCH_CHECK();

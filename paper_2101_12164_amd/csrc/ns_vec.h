@@ -39,11 +39,13 @@ int seg_chunks(int64_t rows);
 
 // G_p (ra x rb, row-major, at G + p * gstride) = alpha * A_p^T B_p + beta * G_p for every segment p.
 // work: at least gram_work_elems(seg, max(ra, rb)) doubles.
-// With rscale, output row a of problem p is further scaled by rscale[p * rsstride + a].
+// With rscale, output row a of problem p is further scaled by rscale[p * rsstride + a].  symmetric: the caller
+// knows A_p^T B_p to be symmetric (ra = rb, e.g. P^T S P): FP64 blocks then form its lower tiles only and mirror
+// them (the result is exactly symmetric).
 template <class TA, class TB>
 void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t ldb, int rb, double* G,
           int64_t gstride, double alpha, double beta, double* work, hipStream_t st, const double* rscale = nullptr,
-          int64_t rsstride = 0);
+          int64_t rsstride = 0, bool symmetric = false);
 size_t gram_work_elems(const Seg& sg, int maxw);
 
 // Out_p = beta * Out_p + gamma * (X_p M_p + X2_p M2_p) on the rows of every segment p;

@@ -182,7 +182,10 @@ constexpr int GC_PL = (GC_K * GC_MAXC + GC_NT - 1) / GC_NT;
 template <class TA, class TB>
 __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restrict__ A, int64_t lda, int ra,
                                                      const TB* __restrict__ B, int64_t ldb, int rb,
-                                                     double* __restrict__ part, int sym) {
+                                                     double* __restrict__ part, int mode) {
+  // mode 0: every tile of A^T B; 1: A = B, the lower tiles, mirrored; 2: the lower tiles of A^T B, mirrored
+  // (a product known to be symmetric)
+  const bool same = mode == 1, lower = mode != 0;
   __shared__ double sA[2][GC_K * GC_LD];
   __shared__ double sB[2][GC_K * GC_LD];
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
     return;
   }
   const int ta = (ra + 15) / 16, tbn = (rb + 15) / 16;
-  const int ntile = sym ? ta * (ta + 1) / 2 : ta * tbn;
+  const int ntile = lower ? ta * (ta + 1) / 2 : ta * tbn;
   const int wa = 16 * ta, wb = 16 * tbn;  // staged columns (zero past ra, rb)
   int tA[GC_MT], tB[GC_MT];
   bool has[GC_MT];
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
     has[m] = t < ntile;
     int i = 0, j = 0;
     if (has[m]) {
-      if (sym) {
+      if (lower) {
         while ((i + 1) * (i + 2) / 2 <= t) ++i;
         j = t - i * (i + 1) / 2;
       } else {
@@ -227,7 +230,7 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
       const int ea = min(e, GC_K * wa - 1), eb = min(e, GC_K * wb - 1);
       const int64_t rowa = min(k0 + ea / wa, r1 - 1), rowb = min(k0 + eb / wb, r1 - 1);
       xa[q] = double(A[rowa * lda + min(ea % wa, ra - 1)]);
-      if (!sym) xb[q] = double(B[rowb * ldb + min(eb % wb, rb - 1)]);
+      if (!same) xb[q] = double(B[rowb * ldb + min(eb % wb, rb - 1)]);
     }
   };
   auto store = [&](int64_t k0, int buf) {
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
         const int r = e / wa, c = e % wa;
         sA[buf][r * GC_LD + c] = (k0 + r < r1 && c < ra) ? xa[q] : 0.0;
       }
-      if (!sym && e < GC_K * wb) {
+      if (!same && e < GC_K * wb) {
         const int r = e / wb, c = e % wb;
         sB[buf][r * GC_LD + c] = (k0 + r < r1 && c < rb) ? xb[q] : 0.0;
       }
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
     __syncthreads();
     if (k0 + GC_K < r1) load(k0 + GC_K);
     const double* a_ = sA[buf];
-    const double* b_ = sym ? sA[buf] : sB[buf];
+    const double* b_ = same ? sA[buf] : sB[buf];
 #pragma unroll
     for (int kk = 0; kk < GC_K; kk += 4) {
       const int ro = (kk + lk) * GC_LD + li;
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
         const int a = 16 * tA[m] + 4 * v + lk, b = 16 * tB[m] + li;
         if (a < ra && b < rb) {
           out[a * rb + b] = acc[m][v];
-          if (sym && tA[m] != tB[m]) out[b * rb + a] = acc[m][v];
+          if (lower && tA[m] != tB[m]) out[b * rb + a] = acc[m][v];
         }
       }
 }
@@ -1032,7 +1035,7 @@ void SegBuf::build(const std::vector<int64_t>& offsets, hipStream_t st) {
 template <class TA, class TB>
 void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t ldb, int rb, double* G,
           int64_t gstride, double alpha, double beta, double* work, hipStream_t st, const double* rscale,
-          int64_t rsstride) {
+          int64_t rsstride, bool symmetric) {
   const int nout = ra * rb;
   if (nout == 0 || sg.n == 0) return;
   const int ta = (ra + 15) / 16, tbt = (rb + 15) / 16;
@@ -1044,7 +1047,7 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
   const double rows = double(sg.rows);
   KScope ks(ra > 16 && rb > 16 ? KF_GRAM : KF_GRAM_NARROW, st,
             rows * (double(ra) * sizeof(TA) + (sym ? 0.0 : double(rb) * sizeof(TB))),
-            sym ? rows * ra * (ra + 1.0) : 2.0 * rows * ra * rb);
+            sym || (symmetric && ra == rb) ? rows * ra * (ra + 1.0) : 2.0 * rows * ra * rb);
   // one FP64 column against a block of 16..256 columns (the deflation products Z^T r of the outer iteration)
   if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8) {
     if (rb == 1 && !sym && ra >= 16 && ra <= 256) {
@@ -1066,7 +1069,8 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
   }
   // wide FP64 blocks: one workgroup per chunk (FP32 blocks stay on the strip kernel, faster for them)
   if (sizeof(TA) == 8 && sizeof(TB) == 8 && ra >= 32 && rb >= 32 && ra <= GC_MAXC && rb <= GC_MAXC) {
-    k_gram_chunk<TA, TB><<<unsigned(sg.nchunk), GC_NT, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, sym);
+    const int mode = sym ? 1 : (symmetric && ra == rb ? 2 : 0);
+    k_gram_chunk<TA, TB><<<unsigned(sg.nchunk), GC_NT, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, mode);
     NS_LAUNCH_CHECK();
     seg_final(sg, nout, work, G, gstride, alpha, beta, st, rscale, rsstride, rb);
     return;
@@ -1159,9 +1163,9 @@ void axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_
 }
 
 template void gram<double, double>(const Seg&, const double*, int64_t, int, const double*, int64_t, int, double*,
-                                   int64_t, double, double, double*, hipStream_t, const double*, int64_t);
+                                   int64_t, double, double, double*, hipStream_t, const double*, int64_t, bool);
 template void gram<float, float>(const Seg&, const float*, int64_t, int, const float*, int64_t, int, double*,
-                                 int64_t, double, double, double*, hipStream_t, const double*, int64_t);
+                                 int64_t, double, double, double*, hipStream_t, const double*, int64_t, bool);
 template void ts_update<double>(const Seg&, int, double*, int64_t, double, double, const double*, int64_t, int,
                                 const double*, int64_t, int64_t, const double*, int64_t, int, const double*, int64_t,
                                 int64_t, hipStream_t);
