@@ -1221,6 +1221,66 @@ __global__ __launch_bounds__(NTP) void k_small_chol_solve_p(int r0, const int* _
   }
 }
 
+// The triangular solves of k_small_chol_solve_p with an existing factor (D holds L, zero above the diagonal),
+// one 16-column chunk of the right-hand sides per workgroup (grid: chunks x problems), so that the chunks run
+// on as many compute units instead of two rounds on one: every workgroup packs the factor into LDS and inverts
+// its diagonal tiles, then its first wave sweeps its chunk forward and backward in registers.
+__global__ __launch_bounds__(NTP) void k_small_chol_apply_p(int r0, const int* __restrict__ dims, const double* D,
+                                                           int64_t sD, const double* B, int64_t ldb, int64_t sB,
+                                                           double* X, int64_t ldx, int64_t sX, int s, int s0,
+                                                           double alpha) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.y;
+  const int r = dims ? dims[b] : r0;
+  const int c0 = blockIdx.x * NB;
+  D += b * sD;
+  B += b * sB;
+  X += b * sX;
+  for (int e = threadIdx.x; e < (s0 - r) * NB; e += NTP) {  // rows past the problem's dimension: zero
+    const int col = c0 + e % NB;
+    if (col < s) X[(r + e / NB) * ldx + col] = 0.0;
+  }
+  if (r == 0) return;
+  const int nt = (r + NB - 1) / NB;
+  double* pt = sm;
+  double* Dinv = sm + size_t(ptile_count(nt)) * PTS;
+  ptiles_fill(pt, r, nt, [&](int i, int j) { return D[i * r0 + j]; });
+  __syncthreads();
+  ptiles_diag_inverses(pt, nt, Dinv);
+  if ((threadIdx.x >> 6) != 0) return;
+  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+  const int col = c0 + li;
+  const bool cin = col < s;
+  const int cc = min(col, s - 1), ldb32 = int(ldb);
+  sv4d Xr[PNT];
+  // loads from clamped, in-bounds rows, half the tiles at a time; out-of-range values zeroed afterwards
+#pragma unroll
+  for (int i = 0; i < PNT / 2; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xr[i][v] = B[min(NB * i + 4 * v + lk, r - 1) * ldb32 + cc];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = PNT / 2; i < PNT; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xr[i][v] = B[min(NB * i + 4 * v + lk, r - 1) * ldb32 + cc];
+#pragma unroll
+  for (int i = 0; i < PNT; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = NB * i + 4 * v + lk;
+      if (!(i < nt && row < r && cin)) Xr[i][v] = 0.0;
+    }
+  wave_fwd(pt, Dinv, nt, 0, Xr);
+  wave_bwd(pt, Dinv, nt, Xr);
+#pragma unroll
+  for (int i = 0; i < PNT; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = NB * i + 4 * v + lk;
+      if (i < nt && row < r && cin) X[row * ldx + col] = alpha * Xr[i][v];
+    }
+}
+
 // k_small_cholqr for 17..160 columns whose dense workspace exceeds the LDS: same arguments and results.  The
 // factor is packed in LDS; each wave forms block columns of L^{-1} in registers (writing Rinv and the norms of
 // the certificate from them); R Racc is staged through the caller's global scratch gw (s x s per problem).
@@ -1776,10 +1836,15 @@ void small_chol_solve(Batch bt, int r, double* D, int64_t sD, const double* B, i
   if (bt.nb <= 0 || (r <= 0 && s0 <= 0)) return;  // s == 0: factor only
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
   const size_t el = chol_ws(r, s);
-  if (packed_chol(el, r)) {
-    k_small_chol_solve_p<<<bt.nb, NTP, packed_lds(r), st>>>(r, bt.dims, D, sD, B, ldb, sB, X, ldx, sX, s, s0, alpha,
+  if (packed_chol(el, r)) {  // the factorisation on one workgroup, then the chunks of the solve side by side
+    k_small_chol_solve_p<<<bt.nb, NTP, packed_lds(r), st>>>(r, bt.dims, D, sD, B, ldb, sB, X, ldx, sX, 0, s0, alpha,
                                                            flag, 1);
     NS_LAUNCH_CHECK();
+    if (s > 0) {
+      k_small_chol_apply_p<<<dim3(unsigned((s + NB - 1) / NB), unsigned(bt.nb)), NTP, packed_lds(r), st>>>(
+          r, bt.dims, D, sD, B, ldb, sB, X, ldx, sX, s, s0, alpha);
+      NS_LAUNCH_CHECK();
+    }
     return;
   }
   const int mode = ws_mode(ws, el, r, s);
@@ -1800,8 +1865,8 @@ void small_chol_apply(Batch bt, int r, const double* L, int64_t sL, const double
   if (r > SMAX || s > 4 * SMAX) fail(INVALID_ARG, "small Cholesky solve too large");
   const size_t el = chol_ws(r, s);
   if (packed_chol(el, r)) {
-    k_small_chol_solve_p<<<bt.nb, NTP, packed_lds(r), st>>>(r, bt.dims, const_cast<double*>(L), sL, B, ldb, sB, X,
-                                                           ldx, sX, s, s0, alpha, nullptr, 0);
+    k_small_chol_apply_p<<<dim3(unsigned((s + NB - 1) / NB), unsigned(bt.nb)), NTP, packed_lds(r), st>>>(
+        r, bt.dims, L, sL, B, ldb, sB, X, ldx, sX, s, s0, alpha);
     NS_LAUNCH_CHECK();
     return;
   }
