@@ -191,30 +191,32 @@ __global__ void k_dims2(int np, const int* rank, const int* single, int* dims) {
 // the Gram matrix G of the first pass's basis is already within eta of the identity in the Frobenius norm over
 // its leading dims x dims block (the basis then has condition number at most sqrt((1 + eta) / (1 - eta)));
 // dimC[p] = skip2[p] ? 0 : dims[p].  One workgroup per problem.
-__global__ __launch_bounds__(256) void k_near_identity(int np, int s, const int* dims, const double* G, int64_t sG,
-                                                       double eta, int* skip2, int* dimC) {
-  __shared__ double red[4];
+__global__ __launch_bounds__(1024) void k_near_identity(int np, int s, const int* dims, const double* G, int64_t sG,
+                                                        double eta, int* skip2, int* dimC) {
+  __shared__ double red[16];
   const int p = blockIdx.x;
   const int n = dims[p];
   const double* Gp = G + int64_t(p) * sG;
   double e2 = 0.0;
-  for (int e0 = threadIdx.x; e0 < n * n; e0 += 4 * 256) {
+  for (int e0 = threadIdx.x; e0 < n * n; e0 += 4 * 1024) {
     double v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = min(e0 + 256 * u, n * n - 1), i = e / n, j = e - i * n;
+      const int e = min(e0 + 1024 * u, n * n - 1), i = e / n, j = e - i * n;
       v[u] = Gp[int64_t(i) * s + j] - (i == j ? 1.0 : 0.0);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (e0 + 256 * u < n * n) e2 += v[u] * v[u];
+      if (e0 + 1024 * u < n * n) e2 += v[u] * v[u];
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e2;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double f2 = (red[0] + red[1]) + (red[2] + red[3]);
+    double f2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) f2 += red[w];
     const int sk = (n == 0 || f2 <= eta * eta) ? 1 : 0;
     skip2[p] = sk;
     dimC[p] = sk ? 0 : n;
@@ -290,7 +292,7 @@ void orth(Handle& h, const Seg& sg, SmallMats& sm, double* work, const T* V, T*&
     dims2 = sm.dimB;
   }
   gram<T, T>(sg2, Q, s, s, Q, s, s, sm.Gorth, ss, 1.0, 0.0, work, st);
-  k_near_identity<<<np, 256, 0, st>>>(np, s, dims2, sm.Gorth, ss, ORTH_ETA, sm.skip2, sm.dimC);
+  k_near_identity<<<np, 1024, 0, st>>>(np, s, dims2, sm.Gorth, ss, ORTH_ETA, sm.skip2, sm.dimC);
   NS_LAUNCH_CHECK();
   sg2.skip = sm.skip2;
   small_cholqr(Batch{np, sm.dimC}, s, sm.Gorth, ss, nullptr, sm.Rinv, sm.Racc, 1, sm.flag + 1, h.sws, st);
