@@ -64,23 +64,33 @@ __global__ __launch_bounds__(256) void k_sym_tiles(const int* __restrict__ mt, c
   tile_of(u, ti, tj);
   const int n = dim[b];
   const double* t = tiles + (toff[b] + u) * int64_t(ST * ST);
+  // entry r of block b's vector: x[xoff_b + r], or x[xidx[xoff_b + r]] (-1: zero) when gathered by xidx.  The
+  // gather index is requested before the tile and the value after it, so the three memory round trips overlap.
+  const int tid = threadIdx.x;
+  const int xr = tid < ST ? ST * ti + tid : ST * tj + (tid - ST);  // threads below 2 ST: x_ti, then x_tj
+  const bool xin = tid < 2 * ST && xr < n;
+  const int64_t xpos = xoff[b] + min(xr, n - 1);
+  int32_t src = -1;
+  if (xidx && xin) src = xidx[xpos];
+  double v[ST * ST / 256];
+#pragma unroll
+  for (int q = 0; q < ST * ST / 256; ++q) v[q] = t[tid + 256 * q];
+  double xv = 0.0;
+  if (xin) {
+    if (!xidx)
+      xv = x[xpos];
+    else if (src >= 0)
+      xv = x[src];
+  }
 #pragma unroll
   for (int q = 0; q < ST * ST / 256; ++q) {
-    const int e = threadIdx.x + 256 * q;
-    s[(e / ST) * (ST + 1) + e % ST] = t[e];
+    const int e = tid + 256 * q;
+    s[(e / ST) * (ST + 1) + e % ST] = v[q];
   }
-  // entry r of block b's vector: x[xoff_b + r], or x[xidx[xoff_b + r]] (-1: zero) when gathered by xidx
-  auto xval = [&](int r) {
-    if (r >= n) return 0.0;
-    const int64_t pos = xoff[b] + r;
-    if (!xidx) return x[pos];
-    const int32_t src = xidx[pos];
-    return src >= 0 ? x[src] : 0.0;
-  };
-  if (threadIdx.x < ST)
-    xi[threadIdx.x] = xval(ST * ti + threadIdx.x);
-  else if (threadIdx.x < 2 * ST)
-    xj[threadIdx.x - ST] = xval(ST * tj + threadIdx.x - ST);
+  if (tid < ST)
+    xi[tid] = xv;
+  else if (tid < 2 * ST)
+    xj[tid - ST] = xv;
   __syncthreads();
   double* pb = part + pboff[b];
   if (threadIdx.x < ST) {  // (A x_tj) rows of tile row ti

@@ -176,16 +176,19 @@ __global__ __launch_bounds__(GV_NT) void k_gram_col(Seg sg, const double* __rest
 constexpr int GC_MAXC = 160;
 constexpr int GC_K = 16;
 constexpr int GC_LD = GC_MAXC + 4;  // LDS row stride (bank spread between the four rows of a k-step)
-constexpr int GC_NT = 512;          // 8 waves, 2 per SIMD: 256 registers each for 13 accumulator tiles
-constexpr int GC_MT = 13;           // output tiles per wave (100 tiles over 8 waves)
-constexpr int GC_PL = (GC_K * GC_MAXC + GC_NT - 1) / GC_NT;
-template <class TA, class TB>
-__global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restrict__ A, int64_t lda, int ra,
+// NT threads, MT output tiles per wave: 512 threads with 13 tiles (256 registers a wave) for every tile of a
+// product of up to 10 x 10 tiles, 1024 threads (4 waves per SIMD: while one waits for its fragments the others
+// multiply) with 2 or 4 tiles for the lower triangles (55 tiles at 160 columns).  The products run
+// unconditionally (a wave's spare slots multiply tile (0, 0) and are not stored): a per-tile branch would make
+// every product wait for its own fragment reads.
+template <class TA, class TB, int MT, int NT>
+__global__ __launch_bounds__(NT) void k_gram_chunk(Seg sg, const TA* __restrict__ A, int64_t lda, int ra,
                                                      const TB* __restrict__ B, int64_t ldb, int rb,
                                                      double* __restrict__ part, int mode) {
   // mode 0: every tile of A^T B; 1: A = B, the lower tiles, mirrored; 2: the lower tiles of A^T B, mirrored
   // (a product known to be symmetric)
   const bool same = mode == 1, lower = mode != 0;
+  constexpr int PL = (GC_K * GC_MAXC + NT - 1) / NT;  // staged values per thread and matrix
   __shared__ double sA[2][GC_K * GC_LD];
   __shared__ double sB[2][GC_K * GC_LD];
   const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -194,17 +197,17 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
   const int pseg = chunk_rows(sg, blockIdx.x, r0, r1);
   if (sg.skip && sg.skip[pseg]) return;
   if (r0 >= r1) {  // a chunk without rows contributes zeros
-    for (int o = threadIdx.x; o < ra * rb; o += GC_NT) part[int64_t(blockIdx.x) * ra * rb + o] = 0.0;
+    for (int o = threadIdx.x; o < ra * rb; o += NT) part[int64_t(blockIdx.x) * ra * rb + o] = 0.0;
     return;
   }
   const int ta = (ra + 15) / 16, tbn = (rb + 15) / 16;
   const int ntile = lower ? ta * (ta + 1) / 2 : ta * tbn;
   const int wa = 16 * ta, wb = 16 * tbn;  // staged columns (zero past ra, rb)
-  int tA[GC_MT], tB[GC_MT];
-  bool has[GC_MT];
+  int tA[MT], tB[MT];
+  bool has[MT];
 #pragma unroll
-  for (int m = 0; m < GC_MT; ++m) {
-    const int t = w + 8 * m;
+  for (int m = 0; m < MT; ++m) {
+    const int t = w + (NT / 64) * m;
     has[m] = t < ntile;
     int i = 0, j = 0;
     if (has[m]) {
@@ -219,14 +222,14 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
     tA[m] = i;
     tB[m] = j;
   }
-  gv4d acc[GC_MT];
+  gv4d acc[MT];
 #pragma unroll
-  for (int m = 0; m < GC_MT; ++m) acc[m] = gv4d{0.0, 0.0, 0.0, 0.0};
-  double xa[GC_PL], xb[GC_PL];
+  for (int m = 0; m < MT; ++m) acc[m] = gv4d{0.0, 0.0, 0.0, 0.0};
+  double xa[PL], xb[PL];
   auto load = [&](int64_t k0) {  // clamped, in-bounds addresses; out-of-range values are zeroed in store
 #pragma unroll
-    for (int q = 0; q < GC_PL; ++q) {
-      const int e = threadIdx.x + GC_NT * q;
+    for (int q = 0; q < PL; ++q) {
+      const int e = threadIdx.x + NT * q;
       const int ea = min(e, GC_K * wa - 1), eb = min(e, GC_K * wb - 1);
       const int64_t rowa = min(k0 + ea / wa, r1 - 1), rowb = min(k0 + eb / wb, r1 - 1);
       xa[q] = double(A[rowa * lda + min(ea % wa, ra - 1)]);
@@ -235,8 +238,8 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
   };
   auto store = [&](int64_t k0, int buf) {
 #pragma unroll
-    for (int q = 0; q < GC_PL; ++q) {
-      const int e = threadIdx.x + GC_NT * q;
+    for (int q = 0; q < PL; ++q) {
+      const int e = threadIdx.x + NT * q;
       if (e < GC_K * wa) {
         const int r = e / wa, c = e % wa;
         sA[buf][r * GC_LD + c] = (k0 + r < r1 && c < ra) ? xa[q] : 0.0;
@@ -259,14 +262,14 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
     for (int kk = 0; kk < GC_K; kk += 4) {
       const int ro = (kk + lk) * GC_LD + li;
 #pragma unroll
-      for (int m = 0; m < GC_MT; ++m)
-        if (has[m]) acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_[ro + 16 * tA[m]], b_[ro + 16 * tB[m]], acc[m], 0, 0, 0);
+      for (int m = 0; m < MT; ++m)
+        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_[ro + 16 * tA[m]], b_[ro + 16 * tB[m]], acc[m], 0, 0, 0);
     }
   }
   const int nout = ra * rb;
   double* out = part + int64_t(blockIdx.x) * nout;
 #pragma unroll
-  for (int m = 0; m < GC_MT; ++m)
+  for (int m = 0; m < MT; ++m)
     if (has[m])
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -275,6 +278,103 @@ __global__ __launch_bounds__(GC_NT) void k_gram_chunk(Seg sg, const TA* __restri
           out[a * rb + b] = acc[m][v];
           if (lower && tA[m] != tB[m]) out[b * rb + a] = acc[m][v];
         }
+      }
+}
+
+// The same products for FP64 blocks of exactly W = 16 TW columns stored with leading dimension W (the block-CG
+// vectors): a GC_K-row stage of each operand is one contiguous run (loads without index arithmetic; rows past
+// the chunk are zeroed when staged), and the fragment offsets within a stage are compile-time.
+// NT = 1024 threads, MT tiles per wave, tile t = w + 16 m as in k_gram_chunk.
+template <int TW, int MT>
+__global__ __launch_bounds__(1024) void k_gram_tw(Seg sg, const double* __restrict__ A,
+                                                 const double* __restrict__ B, double* __restrict__ part, int mode) {
+  constexpr int NT = 1024, NW = NT / 64, W = 16 * TW, SE = GC_K * W, PL = (SE + NT - 1) / NT;
+  constexpr int LD = W + 4;  // LDS row stride (W is a multiple of the bank count: the four rows of a fragment
+                             // read would share banks)
+  const bool same = mode == 1, lower = mode != 0;
+  __shared__ double sA[2][GC_K * LD];
+  __shared__ double sB[2][GC_K * LD];
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+  const int li = lane & 15, lk = lane >> 4;
+  int64_t r0, r1;
+  const int pseg = chunk_rows(sg, blockIdx.x, r0, r1);
+  if (sg.skip && sg.skip[pseg]) return;
+  if (r0 >= r1) {  // a chunk without rows contributes zeros
+    for (int o = threadIdx.x; o < W * W; o += NT) part[int64_t(blockIdx.x) * W * W + o] = 0.0;
+    return;
+  }
+  const int ntile = lower ? TW * (TW + 1) / 2 : TW * TW;
+  int tA[MT], tB[MT];
+  bool has[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int t = w + NW * m;
+    has[m] = t < ntile;
+    int i = 0, j = 0;
+    if (has[m]) {
+      if (lower) {
+        while ((i + 1) * (i + 2) / 2 <= t) ++i;
+        j = t - i * (i + 1) / 2;
+      } else {
+        i = t / TW;
+        j = t - i * TW;
+      }
+    }
+    tA[m] = 16 * i;
+    tB[m] = 16 * j;
+  }
+  gv4d acc[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) acc[m] = gv4d{0.0, 0.0, 0.0, 0.0};
+  double xa[PL], xb[PL];
+  auto load = [&](int64_t k0) {  // elements past the chunk's last row read that row's last element (in bounds)
+    const int lim = int(min(int64_t(GC_K), r1 - k0)) * W - 1;
+    const double* a = A + k0 * W;
+    const double* b = B + k0 * W;
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      const int e = min(int(threadIdx.x) + NT * q, lim);
+      xa[q] = a[e];
+      if (!same) xb[q] = b[e];
+    }
+  };
+  auto store = [&](int64_t k0, int buf) {
+    const int lim = int(min(int64_t(GC_K), r1 - k0)) * W;
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      const int e = threadIdx.x + NT * q;
+      if (SE % NT == 0 || e < SE) {
+        const int o = (e / W) * LD + e % W;
+        sA[buf][o] = e < lim ? xa[q] : 0.0;
+        if (!same) sB[buf][o] = e < lim ? xb[q] : 0.0;
+      }
+    }
+  };
+  load(r0);
+  int buf = 0;
+  for (int64_t k0 = r0; k0 < r1; k0 += GC_K, buf ^= 1) {
+    store(k0, buf);
+    __syncthreads();
+    if (k0 + GC_K < r1) load(k0 + GC_K);
+    const double* a_ = sA[buf] + lk * LD + li;
+    const double* b_ = (same ? sA[buf] : sB[buf]) + lk * LD + li;
+#pragma unroll
+    for (int kk = 0; kk < GC_K; kk += 4) {
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_[kk * LD + tA[m]], b_[kk * LD + tB[m]], acc[m], 0, 0, 0);
+      if constexpr (MT > 4) __builtin_amdgcn_sched_barrier(0);  // one K step's fragments live at a time
+    }
+  }
+  double* out = part + int64_t(blockIdx.x) * W * W;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+    if (has[m])
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = tA[m] + 4 * v + lk, b = tB[m] + li;
+        out[a * W + b] = acc[m][v];
+        if (lower && tA[m] != tB[m]) out[b * W + a] = acc[m][v];
       }
 }
 
@@ -1070,7 +1170,29 @@ void gram(const Seg& sg, const TA* A, int64_t lda, int ra, const TB* B, int64_t 
   // wide FP64 blocks: one workgroup per chunk (FP32 blocks stay on the strip kernel, faster for them)
   if (sizeof(TA) == 8 && sizeof(TB) == 8 && ra >= 32 && rb >= 32 && ra <= GC_MAXC && rb <= GC_MAXC) {
     const int mode = sym ? 1 : (symmetric && ra == rb ? 2 : 0);
-    k_gram_chunk<TA, TB><<<unsigned(sg.nchunk), GC_NT, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, mode);
+    if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8) {
+      // every tile of a product of contiguous 80- or 160-column blocks (the lower-triangle products are faster
+      // on the general kernel's 16-wave form)
+      if (mode == 0 && ra == rb && lda == ra && ldb == rb && (ra == 80 || ra == 160)) {
+        const double* Ad = reinterpret_cast<const double*>(A);
+        const double* Bd = reinterpret_cast<const double*>(B);
+        if (ra == 80)
+          k_gram_tw<5, 2><<<unsigned(sg.nchunk), 1024, 0, st>>>(sg, Ad, Bd, work, mode);
+        else
+          k_gram_tw<10, 7><<<unsigned(sg.nchunk), 1024, 0, st>>>(sg, Ad, Bd, work, mode);
+        NS_LAUNCH_CHECK();
+        seg_final(sg, nout, work, G, gstride, alpha, beta, st, rscale, rsstride, rb);
+        return;
+      }
+    }
+    const int ntile = mode ? ta * (ta + 1) / 2 : ta * tbt;
+    const dim3 grid(unsigned(sg.nchunk));
+    if (ntile <= 16 * 2)
+      k_gram_chunk<TA, TB, 2, 1024><<<grid, 1024, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, mode);
+    else if (ntile <= 16 * 4)
+      k_gram_chunk<TA, TB, 4, 1024><<<grid, 1024, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, mode);
+    else
+      k_gram_chunk<TA, TB, 13, 512><<<grid, 512, 0, st>>>(sg, A, lda, ra, B, ldb, rb, work, mode);
     NS_LAUNCH_CHECK();
     seg_final(sg, nout, work, G, gstride, alpha, beta, st, rscale, rsstride, rb);
     return;
