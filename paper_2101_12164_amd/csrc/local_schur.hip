@@ -614,25 +614,26 @@ __global__ __launch_bounds__(256) void k_schur_epi_local(int64_t nrows, const in
 // batch of four entries of both lists issues its index loads, then all 4 x CPL data loads of each list, before
 // the first sum (a handful of dependent memory round trips per row instead of a few per column group).  The
 // sums run in list order per column, as in k_schur_epi_local (same bits).
-template <class T, int CPL>
+template <class T, int CPL, int TPR = 64>
 __global__ __launch_bounds__(256) void k_schur_epi_wide(int64_t nrows, const int64_t* __restrict__ pG,
                                                         const int32_t* __restrict__ cG, const T* __restrict__ vG,
                                                         const T* __restrict__ X, int64_t ldx,
                                                         const int64_t* __restrict__ pC, const int32_t* __restrict__ cC,
                                                         const T* __restrict__ Yg, int64_t ldy_g, T* __restrict__ Y,
                                                         int64_t ldy, int ncols, int w_only) {
-  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;  // uniform over the wave
-  const int lane = threadIdx.x & 63;
+  // TPR threads per row (64 / TPR rows per wave: their chains of dependent loads overlap)
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
+  const int lane = threadIdx.x % TPR;
   if (row >= nrows) return;
   int cc[CPL];
 #pragma unroll
-  for (int g = 0; g < CPL; ++g) cc[g] = min(lane + 64 * g, ncols - 1);
+  for (int g = 0; g < CPL; ++g) cc[g] = min(lane + TPR * g, ncols - 1);
   T a[CPL], w[CPL];
 #pragma unroll
   for (int g = 0; g < CPL; ++g) a[g] = w[g] = T(0);
   const int64_t ga = w_only ? 0 : pG[row], gb = w_only ? 0 : pG[row + 1], ca = pC[row], cb = pC[row + 1];
   for (int64_t e = ga, f = ca; e < gb || f < cb; e += 4, f += 4) {
-    const bool ha = e < gb, hc = f < cb;  // wave-uniform
+    const bool ha = e < gb, hc = f < cb;  // uniform over the row's threads
     int ja[4], jc[4];
     T va[4], xa[4][CPL], xc[4][CPL];
     if (ha) {
@@ -676,7 +677,7 @@ __global__ __launch_bounds__(256) void k_schur_epi_wide(int64_t nrows, const int
   }
 #pragma unroll
   for (int g = 0; g < CPL; ++g) {
-    const int c = lane + 64 * g;
+    const int c = lane + TPR * g;
     if (c < ncols) Y[row * ldy + c] = w_only ? w[g] : a[g] - w[g];
   }
 }
@@ -693,25 +694,25 @@ __global__ __launch_bounds__(256) void k_gather_ls(int64_t nrows, const int32_t*
 }
 
 // The same for 17..256 columns: one row per wave, the CPL loads of a lane issued together.
-template <class T, int CPL>
+template <class T, int CPL, int TPR = 64>
 __global__ __launch_bounds__(256) void k_gather_ls_wide(int64_t nrows, const int32_t* __restrict__ src,
                                                         const T* __restrict__ R, int64_t ldr, T* __restrict__ Out,
                                                         int64_t ldo, int ncols) {
-  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;  // uniform over the wave
-  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;  // TPR threads per row
+  const int lane = threadIdx.x % TPR;
   if (row >= nrows) return;
   const int s = src[row];
   T v[CPL];
   if (s >= 0) {
 #pragma unroll
-    for (int g = 0; g < CPL; ++g) v[g] = R[int64_t(s) * ldr + min(lane + 64 * g, ncols - 1)];
+    for (int g = 0; g < CPL; ++g) v[g] = R[int64_t(s) * ldr + min(lane + TPR * g, ncols - 1)];
   } else {
 #pragma unroll
     for (int g = 0; g < CPL; ++g) v[g] = T(0);
   }
 #pragma unroll
   for (int g = 0; g < CPL; ++g) {
-    const int c = lane + 64 * g;
+    const int c = lane + TPR * g;
     if (c < ncols) Out[row * ldo + c] = v[g];
   }
 }
@@ -1248,17 +1249,21 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
     sym_gemv(ls.sym, reinterpret_cast<const double*>(X), reinterpret_cast<double*>(Yg), st, ls.glist.p);
   } else {
     if (ncols > 16 && ncols <= 256) {
-      auto wide = [&](auto cpl) {
-        constexpr int CPL = decltype(cpl)::value;
-        k_gather_ls_wide<T, CPL><<<unsigned((np * 64 + 255) / 256), 256, 0, st>>>(np, ls.glist, X, ldx, Xg, ncols,
-                                                                                  ncols);
+      auto wide = [&](auto cpl, auto tpr) {
+        constexpr int CPL = decltype(cpl)::value, TPR = decltype(tpr)::value;
+        k_gather_ls_wide<T, CPL, TPR><<<unsigned((np * TPR + 255) / 256), 256, 0, st>>>(np, ls.glist, X, ldx, Xg,
+                                                                                        ncols, ncols);
       };
-      switch ((ncols + 63) / 64) {
-        case 1: wide(std::integral_constant<int, 1>()); break;
-        case 2: wide(std::integral_constant<int, 2>()); break;
-        case 3: wide(std::integral_constant<int, 3>()); break;
-        default: wide(std::integral_constant<int, 4>()); break;
-      }
+      using T64 = std::integral_constant<int, 64>;
+      using T16 = std::integral_constant<int, 16>;
+      if (ncols <= 80)  // four rows per wave
+        wide(std::integral_constant<int, 5>(), T16());
+      else if (ncols <= 160)
+        wide(std::integral_constant<int, 10>(), T16());
+      else if (ncols <= 192)
+        wide(std::integral_constant<int, 3>(), T64());
+      else
+        wide(std::integral_constant<int, 4>(), T64());
     } else {
       NS_TPR_DISPATCH_LS(ncols, (k_gather_ls<T, TPR><<<unsigned((np * TPR + 255) / 256), 256, 0, st>>>(
                                      np, ls.glist, X, ldx, Xg, ncols, ncols)));
@@ -1287,18 +1292,22 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
   else
     vG = h.AGG.val32.p;
   if (ncols > 16 && ncols <= 256) {
-    auto wide = [&](auto cpl) {
-      constexpr int CPL = decltype(cpl)::value;
-      k_schur_epi_wide<T, CPL><<<unsigned((h.nG * 64 + 255) / 256), 256, 0, st>>>(
+    auto wide = [&](auto cpl, auto tpr) {
+      constexpr int CPL = decltype(cpl)::value, TPR = decltype(tpr)::value;
+      k_schur_epi_wide<T, CPL, TPR><<<unsigned((h.nG * TPR + 255) / 256), 256, 0, st>>>(
           h.nG, h.AGG.ptr, h.AGG.col, vG, X, ldx, ls.contrib.ptr, ls.contrib.col, Yg, ncols, Y, ldy, ncols,
           w_only ? 1 : 0);
     };
-    switch ((ncols + 63) / 64) {
-      case 1: wide(std::integral_constant<int, 1>()); break;
-      case 2: wide(std::integral_constant<int, 2>()); break;
-      case 3: wide(std::integral_constant<int, 3>()); break;
-      default: wide(std::integral_constant<int, 4>()); break;
-    }
+    using T64 = std::integral_constant<int, 64>;
+    using T16 = std::integral_constant<int, 16>;
+    if (ncols <= 80)  // four rows per wave
+      wide(std::integral_constant<int, 5>(), T16());
+    else if (ncols <= 160)
+      wide(std::integral_constant<int, 10>(), T16());
+    else if (ncols <= 192)
+      wide(std::integral_constant<int, 3>(), T64());
+    else
+      wide(std::integral_constant<int, 4>(), T64());
   } else {
     NS_TPR_DISPATCH_LS(ncols, (k_schur_epi_local<T, TPR><<<unsigned((h.nG * TPR + 255) / 256), 256, 0, st>>>(
                                    h.nG, h.AGG.ptr, h.AGG.col, vG, X, ldx, ls.contrib.ptr, ls.contrib.col, Yg,

@@ -67,19 +67,20 @@ __global__ __launch_bounds__(256) void k_gather_sub(int64_t nrows, const int32_t
 
 // The same for 17..256 columns: one row per wave, lane l owns the columns l + 64 g (g < CPL); the row of R and
 // each batch of four CSR entries issue all their loads before the first use.  Same sums in the same order.
-template <class T, int CPL>
+template <class T, int CPL, int TPR = 64>
 __global__ __launch_bounds__(256) void k_gather_sub_wide(int64_t nrows, const int32_t* __restrict__ src,
                                                          const T* __restrict__ R, int64_t ldr,
                                                          const int64_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ col, const T* __restrict__ val,
                                                          const T* __restrict__ X, int64_t ldx, T* __restrict__ Out,
                                                          int64_t ldo, int ncols) {
-  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;  // uniform over the wave
-  const int lane = threadIdx.x & 63;
+  // TPR threads per row (64 / TPR rows per wave: their chains of dependent loads overlap)
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
+  const int lane = threadIdx.x % TPR;
   if (row >= nrows) return;
   int cc[CPL];
 #pragma unroll
-  for (int g = 0; g < CPL; ++g) cc[g] = min(lane + 64 * g, ncols - 1);
+  for (int g = 0; g < CPL; ++g) cc[g] = min(lane + TPR * g, ncols - 1);
   const int s = src ? src[row] : int(row);
   T acc[CPL];
   if (s >= 0) {
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(256) void k_gather_sub_wide(int64_t nrows, const in
   }
 #pragma unroll
   for (int g = 0; g < CPL; ++g) {
-    const int c = lane + 64 * g;
+    const int c = lane + TPR * g;
     if (c < ncols) Out[row * ldo + c] = acc[g];
   }
 }
@@ -301,17 +302,26 @@ void gather_sub(int64_t nrows, const int32_t* src, const T* R, int64_t ldr, cons
   const int32_t* c = A ? A->col.p : nullptr;
   const T* v = A ? csr_vals<T>(*A) : nullptr;
   if (ncols > 16 && ncols <= 256) {
-    auto wide = [&](auto cpl) {
-      constexpr int CPL = decltype(cpl)::value;
-      k_gather_sub_wide<T, CPL><<<grid_rows<64>(nrows), 256, 0, st>>>(nrows, src, R, ldr, p, c, v, X, ldx, Out, ldo,
-                                                                      ncols);
+    auto wide = [&](auto cpl, auto tpr) {
+      constexpr int CPL = decltype(cpl)::value, TPR = decltype(tpr)::value;
+      k_gather_sub_wide<T, CPL, TPR><<<grid_rows<TPR>(nrows), 256, 0, st>>>(nrows, src, R, ldr, p, c, v, X, ldx,
+                                                                            Out, ldo, ncols);
     };
-    switch ((ncols + 63) / 64) {
-      case 1: wide(std::integral_constant<int, 1>()); break;
-      case 2: wide(std::integral_constant<int, 2>()); break;
-      case 3: wide(std::integral_constant<int, 3>()); break;
-      default: wide(std::integral_constant<int, 4>()); break;
-    }
+    using T64 = std::integral_constant<int, 64>;
+    using T16 = std::integral_constant<int, 16>;
+    const bool many = nrows >= 16384;  // four rows per wave (a few thousand rows keep one per wave)
+    if (many && ncols <= 80)
+      wide(std::integral_constant<int, 5>(), T16());
+    else if (many && ncols <= 160)
+      wide(std::integral_constant<int, 10>(), T16());
+    else if (ncols <= 64)
+      wide(std::integral_constant<int, 1>(), T64());
+    else if (ncols <= 128)
+      wide(std::integral_constant<int, 2>(), T64());
+    else if (ncols <= 192)
+      wide(std::integral_constant<int, 3>(), T64());
+    else
+      wide(std::integral_constant<int, 4>(), T64());
   } else {
     NS_TPR_DISPATCH(ncols, (k_gather_sub<T, TPR><<<grid_rows<TPR>(nrows), 256, 0, st>>>(
                                 nrows, src, R, ldr, p, c, v, X, ldx, Out, ldo, ncols)));
@@ -1307,8 +1317,12 @@ void op_gamma_solve(Handle& h, const T* R, int64_t ldr, T* Out, int64_t ldo, int
         run(std::integral_constant<int, 16>(), I());
       else if (ncols <= 64)
         run(std::integral_constant<int, 64>(), I());
+      else if (ncols <= 80)  // four rows per wave: their dependent loads overlap
+        run(std::integral_constant<int, 16>(), std::integral_constant<int, 5>());
       else if (ncols <= 128)
         run(std::integral_constant<int, 64>(), std::integral_constant<int, 2>());
+      else if (ncols <= 160)
+        run(std::integral_constant<int, 16>(), std::integral_constant<int, 10>());
       else if (ncols <= 192)
         run(std::integral_constant<int, 64>(), std::integral_constant<int, 3>());
       else
