@@ -614,7 +614,7 @@ __global__ __launch_bounds__(256) void k_schur_epi_local(int64_t nrows, const in
 // batch of four entries of both lists issues its index loads, then all 4 x CPL data loads of each list, before
 // the first sum (a handful of dependent memory round trips per row instead of a few per column group).  The
 // sums run in list order per column, as in k_schur_epi_local (same bits).
-template <class T, int CPL, int TPR = 64>
+template <class T, int CPL, int TPR = 64, bool EXACT = false, int BC = 4>
 __global__ __launch_bounds__(256) void k_schur_epi_wide(int64_t nrows, const int64_t* __restrict__ pG,
                                                         const int32_t* __restrict__ cG, const T* __restrict__ vG,
                                                         const T* __restrict__ X, int64_t ldx,
@@ -625,17 +625,20 @@ __global__ __launch_bounds__(256) void k_schur_epi_wide(int64_t nrows, const int
   const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / TPR;
   const int lane = threadIdx.x % TPR;
   if (row >= nrows) return;
+  // EXACT: ncols = CPL TPR, so no column is clamped and the loads of a row share one address (immediate offsets)
   int cc[CPL];
 #pragma unroll
-  for (int g = 0; g < CPL; ++g) cc[g] = min(lane + TPR * g, ncols - 1);
+  for (int g = 0; g < CPL; ++g) cc[g] = EXACT ? lane + TPR * g : min(lane + TPR * g, ncols - 1);
   T a[CPL], w[CPL];
 #pragma unroll
   for (int g = 0; g < CPL; ++g) a[g] = w[g] = T(0);
   const int64_t ga = w_only ? 0 : pG[row], gb = w_only ? 0 : pG[row + 1], ca = pC[row], cb = pC[row + 1];
-  for (int64_t e = ga, f = ca; e < gb || f < cb; e += 4, f += 4) {
+  // batches of 4 A_Gamma entries and BC contributors (an interface row of a two-dimensional box partition has
+  // three entries and two contributors, or five and four at a cross point)
+  for (int64_t e = ga, f = ca; e < gb || f < cb; e += 4, f += BC) {
     const bool ha = e < gb, hc = f < cb;  // uniform over the row's threads
-    int ja[4], jc[4];
-    T va[4], xa[4][CPL], xc[4][CPL];
+    int ja[4], jc[BC];
+    T va[4], xa[4][CPL], xc[BC][CPL];
     if (ha) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -646,7 +649,7 @@ __global__ __launch_bounds__(256) void k_schur_epi_wide(int64_t nrows, const int
     }
     if (hc) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) jc[k] = cC[f + k < cb ? f + k : f];
+      for (int k = 0; k < BC; ++k) jc[k] = cC[f + k < cb ? f + k : f];
     }
     if (ha) {
 #pragma unroll
@@ -656,7 +659,7 @@ __global__ __launch_bounds__(256) void k_schur_epi_wide(int64_t nrows, const int
     }
     if (hc) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < BC; ++k)
 #pragma unroll
         for (int g = 0; g < CPL; ++g) xc[k][g] = Yg[int64_t(jc[k]) * ldy_g + cc[g]];
     }
@@ -669,7 +672,7 @@ __global__ __launch_bounds__(256) void k_schur_epi_wide(int64_t nrows, const int
     }
     if (hc) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < BC; ++k)
         if (f + k < cb)
 #pragma unroll
           for (int g = 0; g < CPL; ++g) w[g] += xc[k][g];
@@ -1294,16 +1297,26 @@ void op_schur_local(Handle& h, const T* X, int64_t ldx, T* Y, int64_t ldy, int n
   if (ncols > 16 && ncols <= 256) {
     auto wide = [&](auto cpl, auto tpr) {
       constexpr int CPL = decltype(cpl)::value, TPR = decltype(tpr)::value;
-      k_schur_epi_wide<T, CPL, TPR><<<unsigned((h.nG * TPR + 255) / 256), 256, 0, st>>>(
-          h.nG, h.AGG.ptr, h.AGG.col, vG, X, ldx, ls.contrib.ptr, ls.contrib.col, Yg, ncols, Y, ldy, ncols,
-          w_only ? 1 : 0);
+      if (ncols == CPL * TPR)
+        k_schur_epi_wide<T, CPL, TPR, true, 2><<<unsigned((h.nG * TPR + 255) / 256), 256, 0, st>>>(
+            h.nG, h.AGG.ptr, h.AGG.col, vG, X, ldx, ls.contrib.ptr, ls.contrib.col, Yg, ncols, Y, ldy, ncols,
+            w_only ? 1 : 0);
+      else
+        k_schur_epi_wide<T, CPL, TPR><<<unsigned((h.nG * TPR + 255) / 256), 256, 0, st>>>(
+            h.nG, h.AGG.ptr, h.AGG.col, vG, X, ldx, ls.contrib.ptr, ls.contrib.col, Yg, ncols, Y, ldy, ncols,
+            w_only ? 1 : 0);
     };
     using T64 = std::integral_constant<int, 64>;
+    using T32 = std::integral_constant<int, 32>;
     using T16 = std::integral_constant<int, 16>;
-    if (ncols <= 80)  // four rows per wave
+    // two rows per wave up to 160 columns (four would hold 80 operand values a lane: one wave per SIMD); 80
+    // columns four rows per wave
+    if (ncols == 80)
       wide(std::integral_constant<int, 5>(), T16());
+    else if (ncols <= 96)
+      wide(std::integral_constant<int, 3>(), T32());
     else if (ncols <= 160)
-      wide(std::integral_constant<int, 10>(), T16());
+      wide(std::integral_constant<int, 5>(), T32());
     else if (ncols <= 192)
       wide(std::integral_constant<int, 3>(), T64());
     else
