@@ -1019,13 +1019,25 @@ __device__ __forceinline__ int chol_ptiles(double* pt, int nt, double* Dinv, int
   const int wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) *sinfo = 0;
   __syncthreads();
+  // one step of look-ahead: wave 0 updates the next diagonal tile first and factors it while the other waves
+  // update the rest of the trailing tiles (the serial 16x16 factor no longer waits for the whole update)
+  auto diag = [&](int j) {
+    const int bad = diag_factor_wave(ptile(pt, j, j), PTL, 0, NB, Dinv + j * (NB * NBL));
+    if (bad && (threadIdx.x & 63) == 0 && *sinfo == 0) *sinfo = j * NB + bad;
+  };
+  auto update = [&](int j, int u) {  // A_iq -= L_ij L_qj^T for the u-th lower tile of the trailing matrix
+    const int ti = tri_row(u), tq = u - ti * (ti + 1) / 2;
+    const int i = j + 1 + ti, q = j + 1 + tq;
+    sv4d acc = {0.0, 0.0, 0.0, 0.0};
+    acc = mma16(acc, ptile(pt, i, j), PTL, 1, ptile(pt, q, j), 1, PTL, NB);
+    double* T = ptile(pt, i, q);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) T[tile_row(v) * PTL + tile_col()] -= acc[v];
+  };
+  if (wave == 0) diag(0);
+  __syncthreads();
   for (int j = 0; j < nt; ++j) {
-    double* Di = Dinv + j * (NB * NBL);
-    if (wave == 0) {
-      const int bad = diag_factor_wave(ptile(pt, j, j), PTL, 0, NB, Di);
-      if (bad && (threadIdx.x & 63) == 0 && *sinfo == 0) *sinfo = j * NB + bad;
-    }
-    __syncthreads();
+    const double* Di = Dinv + j * (NB * NBL);
     for (int i = j + 1 + wave; i < nt; i += NWP) {  // L_ij = A_ij L_jj^{-T}
       double* T = ptile(pt, i, j);
       sv4d acc = {0.0, 0.0, 0.0, 0.0};
@@ -1035,14 +1047,13 @@ __device__ __forceinline__ int chol_ptiles(double* pt, int nt, double* Dinv, int
     }
     __syncthreads();
     const int mt = nt - j - 1;
-    for (int u = wave; u < ptile_count(mt); u += NWP) {  // A_iq -= L_ij L_qj^T, j < q <= i
-      const int ti = tri_row(u), tq = u - ti * (ti + 1) / 2;
-      const int i = j + 1 + ti, q = j + 1 + tq;
-      sv4d acc = {0.0, 0.0, 0.0, 0.0};
-      acc = mma16(acc, ptile(pt, i, j), PTL, 1, ptile(pt, q, j), 1, PTL, NB);
-      double* T = ptile(pt, i, q);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) T[tile_row(v) * PTL + tile_col()] -= acc[v];
+    if (mt > 0) {
+      if (wave == 0) {  // tile (j + 1, j + 1), then its factor (LDS accesses of one wave complete in order)
+        update(j, 0);
+        diag(j + 1);
+      } else {
+        for (int u = wave; u < ptile_count(mt); u += NWP - 1) update(j, u);
+      }
     }
     __syncthreads();
   }
