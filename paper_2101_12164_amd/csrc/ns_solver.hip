@@ -145,9 +145,11 @@ __global__ void k_iter(int* it) { *it += 1; }
 // it: the iteration index, or, with itd != nullptr, read from the device (graph-replayed iterations)
 // One wave per problem: the largest relative column residual sqrt(colsq / nF2) over the s columns, lanes over
 // columns (four per lane in flight together, from clamped positions), a butterfly for the maximum.
+// A problem that converges here also gets dims[p] = 0 (the dimension the small solves take, active ? rank : 0).
 __global__ __launch_bounds__(64) void k_bcg_check(int np, int s, const double* __restrict__ colsq,
                                                   const double* __restrict__ nF2, double tol, int it, int* active,
-                                                  int* itp, int* conv, double* relres, int* ndone, const int* itd) {
+                                                  int* itp, int* conv, double* relres, int* ndone, const int* itd,
+                                                  int* dims) {
   const int p = blockIdx.x, lane = threadIdx.x;
   if (p >= np || !active[p]) return;  // uniform over the wave
   if (itd) it = *itd;
@@ -172,6 +174,7 @@ __global__ __launch_bounds__(64) void k_bcg_check(int np, int s, const double* _
     if (m <= tol) {
       conv[p] = 1;
       active[p] = 0;
+      dims[p] = 0;
       atomicAdd(ndone, 1);
     }
   }
@@ -229,9 +232,10 @@ __global__ void k_svqb_mask(int np, const int* active, const int* ok, int* skip)
 }
 // Transform per problem: the Cholesky-QR inverse when certified, else the eigen-decomposition based one
 // (copied into Rinv); rank: s, the number of directions kept, or 0 when inactive.  An active problem
-// left without directions stops (not converged).
+// left without directions stops (not converged).  dims[p] = active ? rank : 0 afterwards (the dimension of the
+// next small solves).
 __global__ void k_orth_select(int np, int s, int* active, const int* ok, const int* svr, const double* Torth,
-                              double* Rinv, int* rank, int it, int* itp, int* ndone, const int* itd) {
+                              double* Rinv, int* rank, int it, int* itp, int* ndone, const int* itd, int* dims) {
   const int p = blockIdx.x;
   if (itd) it = *itd;
   const bool use_svqb = active[p] && !ok[p];
@@ -245,6 +249,7 @@ __global__ void k_orth_select(int np, int s, int* active, const int* ok, const i
       itp[p] = it;
       atomicAdd(ndone, 1);
     }
+    dims[p] = active[p] ? r : 0;
   }
 }
 
@@ -280,7 +285,7 @@ void orth(Handle& h, const Seg& sg, SmallMats& sm, double* work, const T* V, T*&
   NS_LAUNCH_CHECK();
   small_svqb(np, s, sm.Gorth, ss, drop2, sm.Torth, ss, sm.svr, sm.skip, h.sws, st);
   k_orth_select<<<np, 256, 0, st>>>(np, s, sm.active, sm.ok, sm.svr, sm.Torth, sm.Rinv, sm.rank, it, sm.itp,
-                                    sm.ctr, itd);
+                                    sm.ctr, itd, sm.dimA);
   NS_LAUNCH_CHECK();
   ts_update<T>(sg, s, Q, s, 0.0, 1.0, V, s, s, sm.Rinv, s, ss, nullptr, 0, 0, nullptr, 0, 0, st);
   Seg sg2 = sg;
@@ -321,7 +326,6 @@ void block_pcg(Handle& h, SmallMats& sm, Ops& ops, Rhs rhs, double* D) {
   const Seg& sg = ops.seg();
   const int s = h.s, np = h.nprob;
   const int64_t nG = ops.rows(), ss = int64_t(s) * s;
-  const int pb = (np + 255) / 256;
   DBuf<T> X, R, Pb, Qb, Z;
   for (DBuf<T>* b : {&X, &R, &Pb, &Qb, &Z}) b->alloc(nG * s);
   DBuf<double> work;
@@ -337,7 +341,7 @@ void block_pcg(Handle& h, SmallMats& sm, Ops& ops, Rhs rhs, double* D) {
   col_sumsq<T>(sg, s, R.p, s, sm.nF2, work, st);
   NS_HIP(hipMemcpyAsync(sm.colsq, sm.nF2, size_t(np) * s * sizeof(double), hipMemcpyDeviceToDevice, st));
   k_bcg_check<<<np, 64, 0, st>>>(np, s, sm.colsq, sm.nF2, h.tol_inner, 0, sm.active, sm.itp, sm.conv, sm.relres,
-                                  sm.ctr, nullptr);
+                                  sm.ctr, nullptr, sm.dimA);
   NS_LAUNCH_CHECK();
   int hc[2] = {0, 0};
   read_back(h, hc, sm.ctr, 1);
@@ -353,22 +357,19 @@ void block_pcg(Handle& h, SmallMats& sm, Ops& ops, Rhs rhs, double* D) {
       ops.S(P, Q);                                                            // Q = S P
       gram<T, T>(sg, P, s, s, Q, s, s, sm.Delta, ss, 1.0, 0.0, work, q, nullptr, 0, true);  // Delta = P^T S P
       gram<T, T>(sg, P, s, s, R.p, s, s, sm.G1, ss, 1.0, 0.0, work, q);       // P^T R
-      k_dims<<<pb, 256, 0, q>>>(np, s, sm.active, sm.rank, sm.dimA);
-      NS_LAUNCH_CHECK();
+      // sm.dimA = active ? rank : 0, kept by the orthonormalisation's selection and the stopping test
       small_chol_solve(Batch{np, sm.dimA}, s, sm.Delta, ss, sm.G1, s, ss, sm.alpha, s, ss, s, s, 1.0, sm.flag,
                        h.sws, q);  // alpha
       ts_update<T>(sg, s, X.p, s, 1.0, 1.0, P, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, q);
       ts_update<T>(sg, s, R.p, s, 1.0, -1.0, Q, s, s, sm.alpha, s, ss, nullptr, 0, 0, nullptr, 0, 0, q);
       col_sumsq<T>(sg, s, R.p, s, sm.colsq, work, q);
       k_bcg_check<<<np, 64, 0, q>>>(np, s, sm.colsq, sm.nF2, h.tol_inner, 0, sm.active, sm.itp, sm.conv,
-                                     sm.relres, sm.ctr, itd.p);
+                                     sm.relres, sm.ctr, itd.p, sm.dimA);
       NS_LAUNCH_CHECK();
     };
     auto half2 = [&](hipStream_t q) {
       ops.M(R.p, Z.p);                                                        // Z = M R
       gram<T, T>(sg, Q, s, s, Z.p, s, s, sm.G2, ss, 1.0, 0.0, work, q);       // Q^T Z
-      k_dims<<<pb, 256, 0, q>>>(np, s, sm.active, sm.rank, sm.dimA);
-      NS_LAUNCH_CHECK();
       small_chol_apply(Batch{np, sm.dimA}, s, sm.Delta, ss, sm.G2, s, ss, sm.beta, s, ss, s, s, -1.0, h.sws,
                        q);  // beta
       ts_update<T>(sg, s, Z.p, s, 1.0, 1.0, P, s, s, sm.beta, s, ss, nullptr, 0, 0, nullptr, 0, 0, q);  // Z + P beta
